@@ -1,0 +1,251 @@
+"""Plain FP64 CPU oracle for fast randomized SVT (arXiv:1509.00296).
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, ``__graft_entry__.smoke()``
+and the CPU-baseline leg of ``bench.py`` may import this package.  It wraps
+``frsvt_oracle.c`` (plain C, no BLAS) through ctypes and shares no code with
+the GPU library; the two never import each other.
+
+Every function takes and returns numpy float64 arrays; matrices cross the
+ctypes boundary in column-major (Fortran) order.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "frsvt_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+_i64 = ctypes.c_int64
+_dp = ctypes.POINTER(ctypes.c_double)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain -O2, single thread)."""
+    if force or not os.path.exists(_LIB_PATH) or \
+            os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp,
+                               _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+_libs: dict = {}
+_active = [None]
+
+
+def _bind(path: str):
+    if path not in _libs:
+        lib = ctypes.CDLL(path)
+        lib.orc_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
+        lib.orc_uniform53.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
+        lib.orc_uniform53.restype = ctypes.c_double
+        lib.orc_gaussian_matrix.argtypes = [ctypes.c_uint64, ctypes.c_uint64, _i64, _i64, _dp, _i64]
+        lib.orc_qr.argtypes = [_i64, _i64, _dp, _i64, _dp, _i64, _dp, _i64]
+        lib.orc_qrcp_basis.argtypes = [_i64, _i64, _dp, _i64, _dp, _i64]
+        lib.orc_qrcp_basis.restype = _i64
+        lib.orc_svd.argtypes = [_i64, _i64, _dp, _i64, _dp, _i64, _dp, _dp, _i64]
+        lib.orc_svt.argtypes = [_i64, _i64, _dp, _i64, ctypes.c_double, _dp, _i64, _i64p]
+        lib.orc_wsvt.argtypes = [_i64, _i64, _dp, _i64, _dp, _dp, _i64, _i64p]
+        lib.orc_frsvt.argtypes = [_i64, _i64, _dp, _i64, ctypes.c_double, ctypes.c_int,
+                                  _dp, _i64, _i64, _dp, _i64, _i64, _dp, _i64, _dp, _i64,
+                                  _i64p, _dp, _i64p]
+        lib.orc_rpca_ialm.argtypes = [_i64, _i64, _dp, _i64, ctypes.c_double, ctypes.c_int,
+                                      _i64, ctypes.c_int, ctypes.c_uint64, ctypes.c_double,
+                                      ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, _dp, _i64, _dp, _i64, _i64p, _dp,
+                                      ctypes.POINTER(ctypes.c_int)]
+        lib.orc_svt_vjp.argtypes = [_i64, _i64, _dp, _i64, ctypes.c_double, _dp, _i64, _dp,
+                                    _i64, _dp]
+        _libs[path] = lib
+    return _libs[path]
+
+
+def _L():
+    if _active[0] is None:
+        override = os.environ.get("FRSVT_ORACLE_LIB")
+        if override:
+            _active[0] = override
+        else:
+            if not os.path.exists(_LIB_PATH):
+                build()
+            _active[0] = _LIB_PATH
+    return _bind(_active[0])
+
+
+class use_library:
+    """Context manager: route every call in this module to another build of
+    the oracle source (the mutation tests compile deliberately broken copies
+    on the CPU and check that the pins reject them)."""
+
+    def __init__(self, path: str):
+        self.path = path
+
+    def __enter__(self):
+        self.prev = _active[0]
+        _bind(self.path)
+        _active[0] = self.path
+        return self
+
+    def __exit__(self, *exc):
+        _active[0] = self.prev
+        return False
+
+
+def _f(a) -> np.ndarray:
+    return np.asfortranarray(np.asarray(a, dtype=np.float64))
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(_dp)
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _check(rc: int, name: str):
+    if rc < 0:
+        raise OracleError(f"{name}: argument {-rc} invalid")
+
+
+# ---------------------------------------------------------------- random numbers
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    c = (ctypes.c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])
+    o = (ctypes.c_uint32 * 4)()
+    _L().orc_philox4x32_10(c, k, o)
+    return np.array(list(o), dtype=np.uint32)
+
+
+def uniform53(a: int, b: int) -> float:
+    return float(_L().orc_uniform53(a, b))
+
+
+def gaussian_matrix(seed: int, counter: int, rows: int, cols: int) -> np.ndarray:
+    om = np.zeros((rows, cols), dtype=np.float64, order="F")
+    _L().orc_gaussian_matrix(seed, counter, rows, cols, _p(om), max(rows, 1))
+    return om
+
+
+# ---------------------------------------------------------------- factorizations
+
+def qr(A):
+    A = _f(A)
+    m, n = A.shape
+    Q = np.zeros((m, n), order="F")
+    R = np.zeros((n, n), order="F")
+    _check(_L().orc_qr(m, n, _p(A), max(m, 1), _p(Q), max(m, 1), _p(R), max(n, 1)), "qr")
+    return Q, R
+
+
+def qrcp_basis(A):
+    A = _f(A)
+    m, n = A.shape
+    Q = np.zeros((m, min(m, n)), order="F")
+    s = _L().orc_qrcp_basis(m, n, _p(A), m, _p(Q), m)
+    return np.asfortranarray(Q[:, :s])
+
+
+def svd(A):
+    """Thin SVD by one-sided Jacobi: returns U, S, V, sweeps (A = U diag(S) V^T)."""
+    A = _f(A)
+    m, n = A.shape
+    k = min(m, n)
+    U = np.zeros((m, k), order="F")
+    S = np.zeros(k)
+    V = np.zeros((n, k), order="F")
+    rc = _L().orc_svd(m, n, _p(A), m, _p(U), m, _p(S), _p(V), n)
+    _check(rc, "svd")
+    return U, S, V, rc
+
+
+# ---------------------------------------------------------------- operators
+
+def svt(A, tau: float):
+    A = _f(A)
+    m, n = A.shape
+    X = np.zeros((m, n), order="F")
+    r = _i64()
+    _check(_L().orc_svt(m, n, _p(A), m, tau, _p(X), m, ctypes.byref(r)), "svt")
+    return X, int(r.value)
+
+
+def wsvt(A, w):
+    A = _f(A)
+    m, n = A.shape
+    w = np.ascontiguousarray(np.asarray(w, dtype=np.float64))
+    assert w.shape[0] >= min(m, n)
+    X = np.zeros((m, n), order="F")
+    r = _i64()
+    _check(_L().orc_wsvt(m, n, _p(A), m, _p(w), _p(X), m, ctypes.byref(r)), "wsvt")
+    return X, int(r.value)
+
+
+def frsvt(A, tau: float, q: int, Omega, Qprev=None):
+    """FRSVT (Alg. 1) with an explicit Gaussian matrix.
+
+    Omega is nhat x l (fresh) or nhat x p (range propagation with Qprev,
+    mhat x r_prev).  Returns X, Q~ (mhat x r), r, sigma (length s), s.
+    """
+    A = _f(A)
+    m, n = A.shape
+    mh, nh = min(m, n), max(m, n)
+    Om = _f(Omega)
+    assert Om.shape[0] == nh
+    nomega = Om.shape[1]
+    X = np.zeros((m, n), order="F")
+    Qout = np.zeros((mh, mh), order="F")
+    sigma = np.zeros(mh)
+    r = _i64()
+    s = _i64()
+    if Qprev is None:
+        qp, rp, ldq = None, 0, mh
+    else:
+        Qp = _f(Qprev)
+        qp, rp, ldq = _p(Qp), Qp.shape[1], mh
+    rc = _L().orc_frsvt(m, n, _p(A), m, tau, q, _p(Om), nh, nomega, qp, ldq, rp,
+                        _p(X), m, _p(Qout), mh, ctypes.byref(r), _p(sigma), ctypes.byref(s))
+    _check(rc, "frsvt")
+    rr, ss = int(r.value), int(s.value)
+    return X, np.asfortranarray(Qout[:, :rr]), rr, sigma[:ss].copy(), ss
+
+
+def rpca_ialm(O, lam: float, mode: str = "frsvt", p: int = 5, q: int = 1, seed: int = 0,
+              tol: float = 1e-7, max_iter: int = 60, mu0: float = 0.0, rho: float = 1.5,
+              mu_bar_factor: float = 1e7):
+    """Inexact-ALM RPCA; mode 'exact' (SVT by full SVD) or 'frsvt' (FRSVT + RP).
+
+    Returns dict(L, S, ranks, resid, iters, converged)."""
+    O = _f(O)
+    m, n = O.shape
+    L = np.zeros((m, n), order="F")
+    S = np.zeros((m, n), order="F")
+    ranks = np.zeros(max_iter, dtype=np.int64)
+    resid = np.zeros(max_iter)
+    it = ctypes.c_int()
+    rc = _L().orc_rpca_ialm(m, n, _p(O), m, lam, 0 if mode == "exact" else 1, p, q, seed,
+                            tol, max_iter, mu0, rho, mu_bar_factor, _p(L), m, _p(S), m,
+                            ranks.ctypes.data_as(_i64p), _p(resid), ctypes.byref(it))
+    _check(rc, "rpca_ialm")
+    k = int(it.value)
+    return dict(L=L, S=S, ranks=ranks[:k], resid=resid[:k], iters=k, converged=(rc == 0))
+
+
+def svt_vjp(A, tau: float, Xbar):
+    A = _f(A)
+    Xb = _f(Xbar)
+    m, n = A.shape
+    Ab = np.zeros((m, n), order="F")
+    tb = ctypes.c_double()
+    _check(_L().orc_svt_vjp(m, n, _p(A), m, tau, _p(Xb), m, _p(Ab), m, ctypes.byref(tb)),
+           "svt_vjp")
+    return Ab, float(tb.value)

@@ -1,0 +1,56 @@
+"""Plant plausible mistakes in copies of the oracle source (on the CPU) and
+check that the oracle's pin tests reject every one of them."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "frsvt_oracle.c")
+PIN_FILES = ["tests/test_oracle_rng.py", "tests/test_oracle_linalg.py",
+             "tests/test_oracle_svt.py", "tests/test_oracle_frsvt.py",
+             "tests/test_oracle_rpca_grad.py"]
+
+# (name, original text, planted mistake)
+MUTANTS = [
+    ("philox_multiplier", "0xD2511F53u * (uint64_t)c0", "0xD2511F55u * (uint64_t)c0"),
+    ("philox_key_bump", "k1 += 0xBB67AE85u;", "k1 += 0xBB67AE84u;"),
+    ("uniform_bits", "double lo = (double)(b >> 6);", "double lo = (double)(b >> 7);"),
+    ("box_muller_radius", "sqrt(-2.0 * log(u1))", "sqrt(-1.0 * log(u1))"),
+    ("householder_beta_sign", "*beta = -v0 / alpha;", "*beta = v0 / alpha;"),
+    ("qrcp_no_pivot", "if (nc > best_norm) {", "if (nc > best_norm && c == j) {"),
+    ("jacobi_rotation_sign", "gq[i] = s * a + c * b;", "gq[i] = -s * a + c * b;"),
+    ("jacobi_v_not_rotated", "vq[i] = s * a + c * b;", "vq[i] = b;"),
+    ("soft_threshold_half", "double a = fabs(x) - tau;", "double a = fabs(x) - 0.5 * tau;"),
+    ("frsvt_swapped_factors", "mat_mul(nh, s, s, H, nh, UC, s, HWV, nh);",
+     "mat_mul(nh, s, s, H, nh, VC, s, HWV, nh);"),
+    ("frsvt_one_power_step_short", "for (int it = 0; it < q; ++it) {",
+     "for (int it = 1; it < q; ++it) {"),
+    ("rp_no_partial_orthogonalisation", "for (int pass = 0; pass < 2; ++pass)\n            for (int64_t c = 0; c < have + j; ++c) {",
+     "for (int pass = 0; pass < 0; ++pass)\n            for (int64_t c = 0; c < have + j; ++c) {"),
+    ("frsvt_rank_off_by_one", "if (D[i] > tau) ++r;", "if (D[i] > tau && i > 0) ++r;"),
+    ("ialm_dual_sign", "AT(Y, m, i, j) += mu * z;", "AT(Y, m, i, j) -= mu * z;"),
+    ("ialm_shrink_lambda", "lambda / mu);", "lambda * mu);"),
+    ("vjp_antisymmetric_term", "(f[i] + f[j]) / (sg[i] + sg[j])", "(f[i] - f[j]) / (sg[i] + sg[j])"),
+    ("vjp_missing_complement", "AT(UPb, m, i, j) + AT(T, m, i, j) - AT(M2, m, i, j);",
+     "AT(UPb, m, i, j);"),
+]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,orig,bad", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_reject_planted_mistake(tmp_path, name, orig, bad):
+    src = open(SRC).read()
+    assert src.count(orig) == 1, f"mutation anchor for {name} not unique"
+    mutated = tmp_path / "frsvt_oracle.c"
+    mutated.write_text(src.replace(orig, bad))
+    (tmp_path / "frsvt_oracle.h").write_text(open(SRC[:-2] + ".h").read())
+    lib = tmp_path / "liboracle_mutant.so"
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", str(lib),
+                           str(mutated), "-lm"])
+    env = dict(os.environ, FRSVT_ORACLE_LIB=str(lib))
+    proc = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                           "--timeout", "120", *PIN_FILES], cwd=ROOT, env=env,
+                          capture_output=True, text=True, timeout=900)
+    assert proc.returncode != 0, f"mutant {name} survived the pin tests:\n{proc.stdout[-2000:]}"
