@@ -1,0 +1,232 @@
+/*
+ * frsvt.h -- C ABI of the MI355X (gfx950) library for fast randomized
+ * singular value thresholding (FRSVT) and its hosts.
+ *
+ * Method: T.-H. Oh, Y. Matsushita, Y.-W. Tai, I.S. Kweon, "Fast Randomized
+ * Singular Value Thresholding for Low-rank Optimization", arXiv:1509.00296.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Matrices are DEVICE pointers, column-major, with a leading dimension
+ *   (element (i,j) of an m x n matrix M with leading dimension ld is at
+ *   M[i + j*ld], ld >= max(1, m)).  A row-major tensor is passed as the
+ *   column-major view of its transpose.
+ * - The element type of every matrix argument is fixed by `prec`:
+ *     FRSVT_F64        double everywhere;
+ *     FRSVT_F32        float storage and float GEMMs, FP64 Gram/Cholesky and
+ *                      small SVD;
+ *     FRSVT_MIXED_BF16 float storage; the sketch and power-iteration products
+ *                      run on a bfloat16 copy of A with float accumulation,
+ *                      the projection and the reconstruction in float, the
+ *                      Gram/Cholesky steps and the small SVD in double.
+ * - Orientation (Sec. 2.5 of the paper): the method works on Ahat = A when
+ *   m <= n and on Ahat = A^T when m > n, with mhat = min(m,n) rows and
+ *   nhat = max(m,n) columns, so that the power iteration acts on the short
+ *   side.  The sketch Omega is nhat x l; the propagated basis Q~ is mhat x r.
+ * - Ownership: the caller owns every input and output buffer.  The library
+ *   owns only its workspace, held in the handle, grown on demand and freed by
+ *   frsvt_destroy.  All work is enqueued on the handle's HIP stream in order;
+ *   an entry point blocks the host only when it writes a HOST output pointer
+ *   (ranks, statistics), which it documents.
+ * - Status codes (LAPACK-like `info`): 0 success; -i the i-th argument is
+ *   invalid (nothing is launched); FRSVT_NOT_CONVERGED (+1) a Jacobi sweep
+ *   limit was reached (the result is still written); FRSVT_MAX_ITER (+2) RPCA
+ *   stopped at max_iter; FRSVT_ERR_* below for runtime failures.  No C++
+ *   exception crosses this interface.
+ */
+#ifndef FRSVT_H
+#define FRSVT_H
+
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define FRSVT_API __attribute__((visibility("default")))
+#else
+#define FRSVT_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct frsvt_context *frsvt_handle;
+
+typedef enum {
+    FRSVT_F64 = 0,
+    FRSVT_F32 = 1,
+    FRSVT_MIXED_BF16 = 2
+} frsvt_precision;
+
+#define FRSVT_OK 0
+#define FRSVT_NOT_CONVERGED 1
+#define FRSVT_MAX_ITER 2
+#define FRSVT_ERR_HIP (-100)
+#define FRSVT_ERR_OOM (-101)
+#define FRSVT_ERR_NONFINITE (-102)
+#define FRSVT_ERR_UNSUPPORTED (-104)
+#define FRSVT_ERR_HANDLE (-105)
+
+/* ------------------------------------------------------------------ handle */
+
+/* Create a handle bound to HIP device `device` and the HIP stream
+ * `hip_stream` (a hipStream_t; NULL selects the null stream).  The device
+ * must be a gfx950 GPU; returns FRSVT_ERR_UNSUPPORTED otherwise. */
+FRSVT_API int frsvt_create(frsvt_handle *handle, int device, void *hip_stream);
+
+/* Release the workspace and the handle.  Waits for the handle's stream. */
+FRSVT_API int frsvt_destroy(frsvt_handle handle);
+
+/* Rebind the handle to another stream of the same device. */
+FRSVT_API int frsvt_set_stream(frsvt_handle handle, void *hip_stream);
+
+/* Human-readable text of a status code (static storage). */
+FRSVT_API const char *frsvt_status_string(int status);
+
+/* Text of the last runtime error seen by this handle (static per handle). */
+FRSVT_API const char *frsvt_last_error(frsvt_handle handle);
+
+/* Device bytes currently held by the handle's workspace. */
+FRSVT_API int64_t frsvt_workspace_bytes(frsvt_handle handle);
+
+/* ---------------------------------------------------------- exact operator */
+
+/*
+ * svt: exact singular value thresholding, Def. 1 / Eq. (3) of the paper,
+ *   X = U S_tau(Sigma) V^T,  S_tau(x) = sgn(x) max(|x| - tau, 0),
+ * the minimiser of Problem (2): tau ||X||_* + 1/2 ||X - A||_F^2.
+ *   A     [in]  m x n, leading dimension lda >= m.
+ *   tau   [in]  threshold, tau >= 0.
+ *   X     [out] m x n, leading dimension ldx >= m; must not alias A.
+ *   rank  [out, HOST, optional] #{sigma_i > tau}; when non-NULL the call
+ *         waits for the stream.
+ * The full singular value decomposition is taken of the mhat x mhat Gram
+ * matrix Ahat Ahat^T through its Cholesky factor and a one-sided Jacobi SVD.
+ */
+FRSVT_API int svt(frsvt_handle handle, frsvt_precision prec, int64_t m, int64_t n, const void *A,
+        int64_t lda, double tau, void *X, int64_t ldx, int32_t *rank);
+
+/* --------------------------------------------------------------- FRSVT */
+
+/*
+ * frsvt: fast randomized SVT, Alg. 1 of the paper.
+ *   A, lda, tau  as for svt (tau >= 0; tau = 0 returns the projection P_Q A).
+ *   k, p         target rank and oversampling (Table 1); l = k + p > 0.
+ *   q            number of power iterations (eta in the paper), q >= 0.
+ *   Q_prev       [in, optional] range propagation (Alg. 1 lines 8-11):
+ *                mhat x r_prev orthonormal columns, leading dimension
+ *                ldq_prev >= mhat.  When given, only p new Gaussian samples
+ *                are drawn and l = r_prev + p; k is ignored.  NULL (or
+ *                r_prev = 0) selects the fresh sketch of lines 4-6.
+ *   seed, counter  key and call counter of the Philox4x32-10 stream from
+ *                which Omega(k, 2j+e) is drawn (e-th Box-Muller output of
+ *                counter {k, j, counter lo, counter hi}); the same
+ *                (seed, counter) always gives the same Omega.
+ *   X            [out] m x n, ldx >= m; must not alias A or Q_prev.
+ *   Q_out        [out, optional] Q~ = (Q V)_{:,1:r} of line 21, mhat x r,
+ *                leading dimension ldq_out >= mhat, capacity l columns; may
+ *                alias Q_prev (it is written after Q_prev is consumed).
+ *   r_out        [out, HOST, optional] r = #{sigma_i > tau}; non-NULL makes
+ *                the call wait for the stream.
+ * l is clamped to mhat; at l = mhat the result equals exact SVT.
+ */
+FRSVT_API int frsvt(frsvt_handle handle, frsvt_precision prec, int64_t m, int64_t n, const void *A,
+          int64_t lda, double tau, int32_t k, int32_t p, int32_t q, const void *Q_prev,
+          int32_t r_prev, int64_t ldq_prev, uint64_t seed, uint64_t counter, void *X,
+          int64_t ldx, void *Q_out, int64_t ldq_out, int32_t *r_out);
+
+/* --------------------------------------------------------------- WSVT */
+
+/*
+ * wsvt: weighted SVT (the WSVT of weighted nuclear norm minimisation, named
+ * in Sec. 1 and footnote 1 of the paper):
+ *   X = U diag(max(sigma_i - w_i, 0)) V^T,
+ * with w indexed by DESCENDING sigma.  It minimises
+ * sum_i w_i sigma_i(X) + 1/2 ||X - A||_F^2 when w is non-descending; other
+ * weights are applied as given.
+ *   w     [in] DEVICE array of min(m,n) doubles.
+ *   rank  [out, HOST, optional] #{sigma_i > w_i}.
+ */
+FRSVT_API int wsvt(frsvt_handle handle, frsvt_precision prec, int64_t m, int64_t n, const void *A,
+         int64_t lda, const double *w, void *X, int64_t ldx, int32_t *rank);
+
+/* Weight rule of a batched WSVT call.  With c > 0 the weights follow the
+ * patch-group denoising rule w_i = c sqrt(cols) / (sigma_hat_i + eps),
+ * sigma_hat_i = sqrt(max(sigma_i^2 - cols * noise_var, 0)).  With c <= 0 the
+ * thresholds are the constant `tau` for every singular value (plain SVT). */
+typedef struct {
+    double c;
+    double noise_var;
+    double eps;
+    double tau;
+} frsvt_wsvt_rule;
+
+/*
+ * wsvt_batched: weighted SVT of `count` independent small matrices of
+ * uneven shapes in one persistent launch.
+ *   rows, cols   [in] DEVICE int32 arrays (count); 1 <= rows, cols <= 128,
+ *                min(rows, cols) <= 96.
+ *   offsets      [in] DEVICE int64 array (count): element offset of matrix
+ *                j inside A_packed / X_packed; each matrix is column-major
+ *                with leading dimension rows[j].
+ *   A_packed     [in]  float, DEVICE.
+ *   X_packed     [out] float, DEVICE; must not alias A_packed.
+ *   ranks        [out, DEVICE, optional] int32 per matrix, #{sigma > w}.
+ * The small SVD runs in double precision in the local data share.
+ */
+FRSVT_API int wsvt_batched(frsvt_handle handle, int64_t count, const int32_t *rows,
+                 const int32_t *cols, const int64_t *offsets, const float *A_packed,
+                 float *X_packed, const frsvt_wsvt_rule *rule, int32_t *ranks);
+
+/* ---------------------------------------------------------- RPCA host */
+
+typedef struct {
+    double tol;            /* stop when ||O - L - S||_F / ||O||_F < tol (1e-7) */
+    int32_t max_iter;      /* iteration limit (60) */
+    double mu0;            /* initial penalty; <= 0 selects 1.25 / ||O||_2 */
+    double rho;            /* penalty growth (1.5) */
+    double mu_bar_factor;  /* mu never exceeds mu0 * mu_bar_factor (1e7) */
+    int32_t use_frsvt;     /* 1: FRSVT with range propagation; 0: exact svt */
+    int32_t p;             /* oversampling of the propagated sketch (5) */
+    int32_t q;             /* power iterations (1) */
+    int32_t l0;            /* first sketch width; <= 0 selects ceil(0.1 mhat) */
+    uint64_t seed;         /* Philox key; iteration i uses counter i */
+} frsvt_rpca_opts;
+
+typedef struct {
+    int32_t iters;         /* iterations run */
+    int32_t converged;     /* 1 when the tolerance was met */
+    double residual;       /* final ||O - L - S||_F / ||O||_F */
+    double norm2;          /* ||O||_2 used for mu0 */
+    double seconds;        /* wall time of the iteration loop */
+    int32_t ranks[64];     /* r_i of the first 64 iterations */
+    double residuals[64];  /* residual of the first 64 iterations */
+} frsvt_rpca_stats;
+
+/* Fill `opts` with the defaults listed above. */
+FRSVT_API void frsvt_rpca_default_opts(frsvt_rpca_opts *opts);
+
+/*
+ * rpca_ialm: robust PCA, min ||L||_* + lambda ||S||_1 s.t. O = L + S, by the
+ * inexact augmented Lagrange multiplier method used in Sec. 4.1 of the paper
+ * (lambda = 1/sqrt(max(m,n)) there).  Each iteration:
+ *   L = SVT_{1/mu}(O - S + Y/mu)  (FRSVT + range propagation, or exact svt),
+ *   S = shrink_{lambda/mu}(O - L + Y/mu),  Y += mu (O - L - S),
+ *   mu = min(rho mu, mu_bar),
+ * starting from S = 0, Y = O / max(||O||_2, ||O||_inf / lambda).
+ *   O      [in]  m x n, ldo >= m.
+ *   L, S   [out] m x n, leading dimensions ldl, lds >= m.
+ *   opts   [in, optional] NULL selects frsvt_rpca_default_opts.
+ *   stats  [out, HOST, optional].
+ * The host reads one 16-byte status word per iteration (rank and residual)
+ * to size the next sketch and test convergence; the call returns after the
+ * last iteration has finished.  Returns FRSVT_MAX_ITER when max_iter was
+ * reached before tol.
+ */
+FRSVT_API int rpca_ialm(frsvt_handle handle, frsvt_precision prec, int64_t m, int64_t n, const void *O,
+              int64_t ldo, double lambda, const frsvt_rpca_opts *opts, void *L, int64_t ldl,
+              void *S, int64_t lds, frsvt_rpca_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FRSVT_H */

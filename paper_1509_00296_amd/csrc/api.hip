@@ -1,0 +1,995 @@
+// api.hip -- host orchestration behind the C ABI declared in include/frsvt.h.
+//
+// Argument validation, the handle and its workspace, and the order of the
+// kernel launches for Alg. 1 (FRSVT), exact SVT, weighted SVT and the
+// inexact-ALM RPCA loop of arXiv:1509.00296.
+#include "frsvt.h"
+#include "internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+using namespace frk;
+
+struct frsvt_context {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int num_cu = 256;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    int *dstatus = nullptr;      // small device status area (ints)
+    double *dscalars = nullptr;  // small device scalar area (doubles)
+    void *pinned = nullptr;      // host pinned status area
+    char last_error[256] = {0};
+};
+
+namespace {
+
+constexpr double kU = 1.1102230246251565e-16;
+constexpr size_t kStatusInts = 1024;
+constexpr size_t kScalarDoubles = 8192;
+
+int fail(frsvt_context *h, hipError_t e, const char *what)
+{
+    if (h) snprintf(h->last_error, sizeof(h->last_error), "%s: %s", what, hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? FRSVT_ERR_OOM : FRSVT_ERR_HIP;
+}
+
+#define CK(expr)                                                   \
+    do {                                                           \
+        hipError_t e_ = (expr);                                    \
+        if (e_ != hipSuccess) return fail(h, e_, #expr);           \
+    } while (0)
+
+// Bump allocator over the handle's workspace; sizes are computed first with
+// a dry run (base == nullptr), then the workspace is grown to fit.
+struct Carver {
+    char *base;
+    size_t off = 0;
+    explicit Carver(void *b) : base((char *)b) {}
+    template <typename T>
+    T *take(size_t count)
+    {
+        off = (off + 255) & ~(size_t)255;
+        T *p = base ? (T *)(base + off) : nullptr;
+        off += std::max<size_t>(count, 1) * sizeof(T);
+        return p;
+    }
+};
+
+int ensure_ws(frsvt_context *h, size_t bytes)
+{
+    if (bytes <= h->ws_bytes) return FRSVT_OK;
+    if (h->ws) {
+        hipError_t e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return fail(h, e, "hipStreamSynchronize");
+        (void)hipFree(h->ws);
+        h->ws = nullptr;
+        h->ws_bytes = 0;
+    }
+    size_t grow = std::max(bytes, (size_t)(h->ws_bytes * 3 / 2));
+    hipError_t e = hipMalloc(&h->ws, grow);
+    if (e != hipSuccess) {
+        h->ws = nullptr;
+        return fail(h, e, "hipMalloc(workspace)");
+    }
+    h->ws_bytes = grow;
+    return FRSVT_OK;
+}
+
+template <typename T>
+struct Prec;
+template <>
+struct Prec<double> {
+    static constexpr int bytes = 8;
+};
+template <>
+struct Prec<float> {
+    static constexpr int bytes = 4;
+};
+
+// Strides of Ahat(i, k) = A[i * si + k * sk].
+struct Orient {
+    bool trans;
+    int mh;
+    int64_t nh;
+    int64_t si, sk;
+};
+Orient orient(int64_t m, int64_t n, int64_t lda)
+{
+    Orient o;
+    o.trans = m > n;
+    o.mh = (int)(o.trans ? n : m);
+    o.nh = o.trans ? m : n;
+    o.si = o.trans ? lda : 1;
+    o.sk = o.trans ? 1 : lda;
+    return o;
+}
+
+int gemm_splitk(int64_t M, int64_t N, int64_t K, int num_cu)
+{
+    const int64_t tiles = ((M + 63) / 64) * ((N + 63) / 64);
+    int64_t want = (2 * num_cu + tiles - 1) / std::max<int64_t>(tiles, 1);
+    want = std::min<int64_t>(want, std::max<int64_t>(1, K / 256));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(want, 128));
+}
+
+// ---------------------------------------------------------------------------
+// The FRSVT core: basis Q, projection B^T, the small SVD and the factors of
+// the reconstruction X = (Q Mm) B, all in the workspace.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Core {
+    // inputs
+    const T *A;
+    int64_t lda;
+    Orient o;
+    double tau;
+    const double *w;     // device weights (WSVT) or nullptr
+    int q;
+    const T *Qt;         // propagated basis (mh x rp) or nullptr
+    int64_t ldqt;
+    int rp;
+    int cnew;            // new Gaussian samples
+    uint64_t seed, counter;
+    T *Qout;             // mh x l (ld ldqo); may alias Qt
+    int64_t ldqo;
+    // results (workspace)
+    int l;
+    T *Q, *Bt, *QM;
+    double *G, *U, *Mm, *sigma;
+    int *status;         // device: [0] r, [1] sweeps, [2] converged, [4..] orth flags
+};
+
+template <typename T>
+struct CoreBuffers {
+    T *Ypart, *Y, *Q, *Bt, *QM, *Om, *Z, *gpart_t, *Qtmp;
+    double *Gpart, *G, *U, *Mm, *sigma, *R, *gpart_d, *jwork;
+    int *nullc;
+};
+
+template <typename T>
+size_t carve_core(Carver &cv, const Orient &o, int l, int cnew, int num_cu, CoreBuffers<T> &b)
+{
+    const int mh = o.mh;
+    const int64_t nh = o.nh;
+    const int grid = 2 * num_cu;
+    const int cmax = std::max(l, 1);
+    b.Ypart = cv.take<T>((size_t)grid * mh * cmax);
+    b.Y = cv.take<T>((size_t)mh * cmax);
+    b.Q = cv.take<T>((size_t)mh * cmax);
+    b.Qtmp = cv.take<T>((size_t)mh * cmax);
+    b.Bt = cv.take<T>((size_t)nh * cmax);
+    b.QM = cv.take<T>((size_t)mh * cmax);
+    b.Gpart = cv.take<double>((size_t)grid * cmax * cmax);
+    b.G = cv.take<double>((size_t)cmax * cmax);
+    b.U = cv.take<double>((size_t)cmax * cmax);
+    b.Mm = cv.take<double>((size_t)cmax * cmax);
+    b.sigma = cv.take<double>((size_t)cmax);
+    b.R = cv.take<double>((size_t)cmax * cmax);
+    b.nullc = cv.take<int>((size_t)cmax);
+    b.jwork = cv.take<double>((size_t)cmax * cmax);
+    const bool big = !(long_path_ok(mh, std::max(l, 1)) && small_orth_ok(mh, l));
+    if (big) {
+        b.Om = cv.take<T>((size_t)nh * std::max(cnew, 1));
+        b.Z = cv.take<T>((size_t)nh * cmax);
+        // GEMM split-K partials: the largest of Y = Ahat V and Gram products
+        const size_t p1 = (size_t)128 * mh * cmax;
+        b.gpart_t = cv.take<T>(p1);
+        b.gpart_d = cv.take<double>((size_t)std::max<int64_t>(128 * (int64_t)cmax * cmax, (int64_t)mh * cmax * 4));
+    } else {
+        b.Om = b.Z = b.gpart_t = nullptr;
+        b.gpart_d = nullptr;
+    }
+    return cv.off;
+}
+
+// Ahat(mh x nh) times a tall matrix V (nh x c, ld ldv): Y (mh x c, ld mh).
+template <typename T>
+int ahat_times(frsvt_context *h, const Core<T> &c, const T *V, int64_t ldv, int cols, T *Y,
+               T *part)
+{
+    const Orient &o = c.o;
+    const int sk = gemm_splitk(o.mh, cols, o.nh, h->num_cu);
+    CK((launch_gemm<T, T, T>(o.mh, cols, o.nh, c.A, o.si, o.sk, V, 1, ldv, Y, 1, o.mh, sk, part,
+                             h->stream)));
+    return FRSVT_OK;
+}
+
+// Ahat^T (nh x mh) times Q (mh x c): Z (nh x c, ld nh).
+template <typename T>
+int ahat_t_times(frsvt_context *h, const Core<T> &c, const T *Qm, int64_t ldq, int cols, T *Z,
+                 T *part)
+{
+    const Orient &o = c.o;
+    CK((launch_gemm<T, T, T>(o.nh, cols, o.mh, c.A, o.sk, o.si, Qm, 1, ldq, Z, 1, o.nh, 1, part,
+                             h->stream)));
+    return FRSVT_OK;
+}
+
+// Gram G = Y^T Y (l x l, double) of a tall rows x l matrix.
+template <typename T>
+int gram(frsvt_context *h, int64_t rows, int l, const T *Y, int64_t ldy, double *G, double *part)
+{
+    const int sk = gemm_splitk(l, l, rows, h->num_cu);
+    if (std::is_same<T, double>::value) {
+        CK((launch_gemm<double, double, double>(l, l, rows, (const double *)Y, ldy, 1,
+                                                (const double *)Y, 1, ldy, G, 1, l, sk, part,
+                                                h->stream)));
+    } else {
+        CK((launch_gemm<float, double, double>(l, l, rows, (const float *)Y, ldy, 1,
+                                               (const float *)Y, 1, ldy, G, 1, l, sk, part,
+                                               h->stream)));
+    }
+    return FRSVT_OK;
+}
+
+// Large-path orthonormalisation of Y (rows x l) in place: column
+// equilibration, shifted CholeskyQR, CholeskyQR with null refill, a final
+// CholeskyQR pass.  No host synchronisation.
+template <typename T>
+int big_orth(frsvt_context *h, int64_t rows, int l, T *Y, int64_t ldy, CoreBuffers<T> &b,
+             uint64_t seed, uint64_t counter, int *flags)
+{
+    int rc;
+    if ((rc = gram(h, rows, l, Y, ldy, b.G, b.gpart_d))) return rc;
+    CK(launch_col_scale<T>(rows, l, Y, ldy, b.G, h->stream));
+    const double shift = 11.0 * ((double)rows * l + (double)l * (l + 1)) * kU;
+    if ((rc = gram(h, rows, l, Y, ldy, b.G, b.gpart_d))) return rc;
+    CK(launch_chol(l, b.G, shift, 0.0, b.R, nullptr, flags, h->stream));
+    CK(launch_trsm<T>(rows, l, Y, ldy, b.R, h->stream));
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        if ((rc = gram(h, rows, l, Y, ldy, b.G, b.gpart_d))) return rc;
+        CK(launch_chol(l, b.G, 0.0, 16.0 * l * kU, b.R, b.nullc, flags, h->stream));
+        CK(launch_refill<T>(rows, l, Y, ldy, b.nullc, seed, counter, attempt, h->stream));
+    }
+    if ((rc = gram(h, rows, l, Y, ldy, b.G, b.gpart_d))) return rc;
+    CK(launch_chol(l, b.G, 0.0, 16.0 * l * kU, b.R, b.nullc, flags, h->stream));
+    CK(launch_trsm<T>(rows, l, Y, ldy, b.R, h->stream));
+    if ((rc = gram(h, rows, l, Y, ldy, b.G, b.gpart_d))) return rc;
+    CK(launch_chol(l, b.G, 0.0, 0.0, b.R, nullptr, flags, h->stream));
+    CK(launch_trsm<T>(rows, l, Y, ldy, b.R, h->stream));
+    return FRSVT_OK;
+}
+
+template <typename T>
+int run_core(frsvt_context *h, Core<T> &c, CoreBuffers<T> &b)
+{
+    const Orient &o = c.o;
+    const int mh = o.mh;
+    const int l = c.rp + c.cnew;
+    c.l = l;
+    c.Q = b.Q;
+    c.Bt = b.Bt;
+    c.QM = b.QM;
+    c.G = b.G;
+    c.U = b.U;
+    c.Mm = b.Mm;
+    c.sigma = b.sigma;
+    const bool small = long_path_ok(mh, l) && small_orth_ok(mh, l);
+    int *oflags = c.status + 4;
+    hipStream_t s = h->stream;
+    int rc;
+
+    LongArgs<T> la{};
+    la.A = c.A;
+    la.lda = c.lda;
+    la.trans = o.trans ? 1 : 0;
+    la.mh = mh;
+    la.nh = o.nh;
+    la.seed = c.seed;
+    la.counter = c.counter;
+
+    // Alg. 1 lines 3-12: sketch and initial basis
+    if (small) {
+        if (c.cnew > 0) {
+            LongPlan p = long_plan(mh, o.nh, c.cnew, Prec<T>::bytes, kSketch, h->num_cu);
+            la.c = c.cnew;
+            la.Ypart = b.Ypart;
+            CK(launch_long<T>(p, kSketch, la, s));
+            CK(launch_reduce<T>(b.Ypart, (int64_t)mh * c.cnew, p.grid, b.Y, s));
+        }
+        CK(launch_small_orth<T>(mh, c.Qt, c.ldqt, c.rp, b.Y, mh, c.cnew, b.Q, mh, c.seed,
+                                c.counter, oflags, s));
+    } else {
+        if (c.rp > 0)
+            CK(hipMemcpy2DAsync(b.Q, mh * sizeof(T), c.Qt, c.ldqt * sizeof(T), mh * sizeof(T),
+                                c.rp, hipMemcpyDeviceToDevice, s));
+        if (c.cnew > 0) {
+            CK(launch_omega<T>(o.nh, c.cnew, c.seed, c.counter, b.Om, o.nh, s));
+            if ((rc = ahat_times<T>(h, c, b.Om, o.nh, c.cnew, b.Q + (size_t)c.rp * mh, b.gpart_t)))
+                return rc;
+        }
+        if ((rc = big_orth<T>(h, mh, l, b.Q, mh, b, c.seed, c.counter, oflags))) return rc;
+    }
+
+    // Alg. 1 lines 13-15: power iterations Q = QR(Ahat Ahat^T Q)
+    for (int it = 0; it < c.q; ++it) {
+        const uint64_t ctr2 = c.counter ^ (0x5bd1e995ull << 32) ^ (uint64_t)(it + 1) << 56;
+        if (small) {
+            LongPlan p = long_plan(mh, o.nh, l, Prec<T>::bytes, kPower, h->num_cu);
+            la.c = l;
+            la.Q = b.Q;
+            la.ldq = mh;
+            la.Ypart = b.Ypart;
+            CK(launch_long<T>(p, kPower, la, s));
+            CK(launch_reduce<T>(b.Ypart, (int64_t)mh * l, p.grid, b.Y, s));
+            CK(launch_small_orth<T>(mh, (const T *)nullptr, mh, 0, b.Y, mh, l, b.Q, mh, c.seed,
+                                    ctr2, oflags, s));
+        } else {
+            if ((rc = ahat_t_times<T>(h, c, b.Q, mh, l, b.Z, b.gpart_t))) return rc;
+            if ((rc = ahat_times<T>(h, c, b.Z, o.nh, l, b.Q, b.gpart_t))) return rc;
+            if ((rc = big_orth<T>(h, mh, l, b.Q, mh, b, c.seed, ctr2, oflags))) return rc;
+        }
+    }
+
+    // Alg. 1 line 16: B^T = Ahat^T Q and its Gram B B^T
+    if (long_path_ok(mh, l)) {
+        LongPlan p = long_plan(mh, o.nh, l, Prec<T>::bytes, kProject, h->num_cu);
+        la.c = l;
+        la.Q = b.Q;
+        la.ldq = mh;
+        la.Z = b.Bt;
+        la.ldz = o.nh;
+        la.Gpart = b.Gpart;
+        CK(launch_long<T>(p, kProject, la, s));
+        CK(launch_reduce<double>(b.Gpart, (int64_t)l * l, p.grid, b.G, s));
+    } else {
+        if ((rc = ahat_t_times<T>(h, c, b.Q, mh, l, b.Bt, b.gpart_t))) return rc;
+        if ((rc = gram<T>(h, o.nh, l, b.Bt, o.nh, b.G, b.gpart_d))) return rc;
+    }
+
+    // Alg. 1 lines 17-19: small SVD, thresholds, reconstruction factors
+    SmallSvdOut so{b.sigma, b.U, b.Mm, c.status};
+    const int fuse = small_svd_fuse_q_ok(mh, l) ? 1 : 0;
+    CK(launch_small_svd<T>(l, b.G, c.tau, c.w, b.Q, mh, mh, b.QM, mh, c.Qout, c.ldqo, so, b.jwork,
+                           fuse, s));
+    if (!fuse) {
+        // QM = Q Mm, Qout = Q U (double small factors cast through a copy)
+        T *Mt = b.Qtmp;  // reuse: l x l in storage precision needs l*l <= mh*l
+        CK(launch_cast<T>(l, l, b.Mm, 1, l, Mt, l, s));
+        CK((launch_gemm<T, T, T>(mh, l, l, b.Q, 1, mh, Mt, 1, l, b.QM, 1, mh, 1, b.gpart_t, s)));
+        if (c.Qout) {
+            CK(launch_cast<T>(l, l, b.U, 1, l, Mt, l, s));
+            CK((launch_gemm<T, T, T>(mh, l, l, b.Q, 1, mh, Mt, 1, l, c.Qout, 1, c.ldqo, 1,
+                                     b.gpart_t, s)));
+        }
+    }
+    return FRSVT_OK;
+}
+
+// X (physical m x n, ldx) = (QM) B.
+template <typename T>
+int write_x(frsvt_context *h, const Core<T> &c, T *X, int64_t ldx, T *part)
+{
+    const Orient &o = c.o;
+    if (recon_ok(c.l)) {
+        ReconArgs<T> ra{};
+        ra.c = c.l;
+        if (o.trans) {
+            ra.rows = o.nh;
+            ra.cols = o.mh;
+            ra.FR = c.Bt;
+            ra.ldfr = o.nh;
+            ra.FC = c.QM;
+            ra.ldfc = o.mh;
+        } else {
+            ra.rows = o.mh;
+            ra.cols = o.nh;
+            ra.FR = c.QM;
+            ra.ldfr = o.mh;
+            ra.FC = c.Bt;
+            ra.ldfc = o.nh;
+        }
+        ra.X = X;
+        ra.ldx = ldx;
+        CK(launch_recon<T>(kRecon, ra, nullptr, h->stream));
+    } else {
+        const int64_t scm = o.trans ? ldx : 1, scn = o.trans ? 1 : ldx;
+        CK((launch_gemm<T, T, T>(o.mh, o.nh, c.l, c.QM, 1, o.mh, c.Bt, o.nh, 1, X, scm, scn, 1,
+                                 part, h->stream)));
+    }
+    return FRSVT_OK;
+}
+
+// Exact SVT / WSVT: G = Ahat Ahat^T, small SVD of size mh, X = Mm Ahat.
+template <typename T>
+int exact_factors(frsvt_context *h, const T *A, int64_t lda, const Orient &o, double tau,
+                  const double *w, Carver &cv, double **Mm_out, T **Mt_out)
+{
+    const int mh = o.mh;
+    const int sk = gemm_splitk(mh, mh, o.nh, h->num_cu);
+    double *G = cv.take<double>((size_t)mh * mh);
+    double *gp = cv.take<double>((size_t)sk * mh * mh);
+    double *U = cv.take<double>((size_t)mh * mh);
+    double *Mm = cv.take<double>((size_t)mh * mh);
+    double *sig = cv.take<double>((size_t)mh);
+    double *jw = cv.take<double>((size_t)mh * mh);
+    T *Mt = cv.take<T>((size_t)mh * mh);
+    if (!cv.base) return FRSVT_OK;
+    if (std::is_same<T, double>::value) {
+        CK((launch_gemm<double, double, double>(mh, mh, o.nh, (const double *)A, o.si, o.sk,
+                                                (const double *)A, o.sk, o.si, G, 1, mh, sk, gp,
+                                                h->stream)));
+    } else {
+        CK((launch_gemm<float, double, double>(mh, mh, o.nh, (const float *)A, o.si, o.sk,
+                                               (const float *)A, o.sk, o.si, G, 1, mh, sk, gp,
+                                               h->stream)));
+    }
+    SmallSvdOut so{sig, U, Mm, h->dstatus};
+    CK(launch_small_svd<T>(mh, G, tau, w, (const T *)nullptr, 0, mh, (T *)nullptr, 0,
+                           (T *)nullptr, 0, so, jw, 0, h->stream));
+    CK(launch_cast<T>(mh, mh, Mm, 1, mh, Mt, mh, h->stream));
+    *Mm_out = Mm;
+    *Mt_out = Mt;
+    return FRSVT_OK;
+}
+
+template <typename T>
+int exact_svt_impl(frsvt_context *h, int64_t m, int64_t n, const T *A, int64_t lda, double tau,
+                   const double *w, T *X, int64_t ldx, int32_t *rank)
+{
+    const Orient o = orient(m, n, lda);
+    Carver dry(nullptr);
+    double *Mm;
+    T *Mt;
+    exact_factors<T>(h, A, lda, o, tau, w, dry, &Mm, &Mt);
+    int rc = ensure_ws(h, dry.off);
+    if (rc) return rc;
+    Carver cv(h->ws);
+    if ((rc = exact_factors<T>(h, A, lda, o, tau, w, cv, &Mm, &Mt))) return rc;
+    const int64_t scm = o.trans ? ldx : 1, scn = o.trans ? 1 : ldx;
+    CK((launch_gemm<T, T, T>(o.mh, o.nh, o.mh, Mt, 1, o.mh, A, o.si, o.sk, X, scm, scn, 1,
+                             (T *)nullptr, h->stream)));
+    if (rank) {
+        CK(hipMemcpyAsync(h->pinned, h->dstatus, 4 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+        CK(hipStreamSynchronize(h->stream));
+        *rank = ((int *)h->pinned)[0];
+        if (((int *)h->pinned)[2] == 0) return FRSVT_NOT_CONVERGED;
+    }
+    return FRSVT_OK;
+}
+
+template <typename T>
+int frsvt_impl(frsvt_context *h, int64_t m, int64_t n, const T *A, int64_t lda, double tau,
+               int k, int p, int q, const T *Qprev, int r_prev, int64_t ldqp, uint64_t seed,
+               uint64_t counter, T *X, int64_t ldx, T *Qout, int64_t ldqo, int32_t *r_out)
+{
+    const Orient o = orient(m, n, lda);
+    Core<T> c{};
+    c.A = A;
+    c.lda = lda;
+    c.o = o;
+    c.tau = tau;
+    c.w = nullptr;
+    c.q = q;
+    c.seed = seed;
+    c.counter = counter;
+    if (Qprev && r_prev > 0) {
+        c.Qt = Qprev;
+        c.ldqt = ldqp;
+        c.rp = std::min(r_prev, o.mh);
+        c.cnew = std::max(0, std::min(p, o.mh - c.rp));
+    } else {
+        c.Qt = nullptr;
+        c.ldqt = o.mh;
+        c.rp = 0;
+        c.cnew = std::max(1, std::min(k + p, o.mh));
+    }
+    c.Qout = Qout;
+    c.ldqo = ldqo;
+    c.status = h->dstatus;
+    const int l = c.rp + c.cnew;
+    CoreBuffers<T> b{};
+    Carver dry(nullptr);
+    carve_core<T>(dry, o, l, c.cnew, h->num_cu, b);
+    int rc = ensure_ws(h, dry.off);
+    if (rc) return rc;
+    Carver cv(h->ws);
+    carve_core<T>(cv, o, l, c.cnew, h->num_cu, b);
+    if ((rc = run_core<T>(h, c, b))) return rc;
+    if ((rc = write_x<T>(h, c, X, ldx, b.gpart_t))) return rc;
+    if (r_out) {
+        CK(hipMemcpyAsync(h->pinned, h->dstatus, 8 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+        CK(hipStreamSynchronize(h->stream));
+        *r_out = ((int *)h->pinned)[0];
+        if (((int *)h->pinned)[2] == 0) return FRSVT_NOT_CONVERGED;
+    }
+    return FRSVT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Inexact-ALM RPCA.
+// ---------------------------------------------------------------------------
+template <typename T>
+int spectral_norm(frsvt_context *h, const T *A, int64_t lda, const Orient &o, double *out)
+{
+    const int mh = o.mh;
+    const int sk = gemm_splitk(mh, mh, o.nh, h->num_cu);
+    Carver dry(nullptr);
+    dry.take<double>((size_t)mh * mh);
+    dry.take<double>((size_t)sk * mh * mh);
+    dry.take<double>((size_t)2 * mh + 2);
+    int rc = ensure_ws(h, dry.off);
+    if (rc) return rc;
+    Carver cv(h->ws);
+    double *G = cv.take<double>((size_t)mh * mh);
+    double *gp = cv.take<double>((size_t)sk * mh * mh);
+    double *wk = cv.take<double>((size_t)2 * mh + 2);
+    if (std::is_same<T, double>::value) {
+        CK((launch_gemm<double, double, double>(mh, mh, o.nh, (const double *)A, o.si, o.sk,
+                                                (const double *)A, o.sk, o.si, G, 1, mh, sk, gp,
+                                                h->stream)));
+    } else {
+        CK((launch_gemm<float, double, double>(mh, mh, o.nh, (const float *)A, o.si, o.sk,
+                                               (const float *)A, o.sk, o.si, G, 1, mh, sk, gp,
+                                               h->stream)));
+    }
+    CK(launch_power_eig(mh, G, wk, h->dscalars, h->stream));
+    CK(hipMemcpyAsync(h->pinned, h->dscalars, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    CK(hipStreamSynchronize(h->stream));
+    *out = std::sqrt(std::max(0.0, ((double *)h->pinned)[0]));
+    return FRSVT_OK;
+}
+
+template <typename T>
+int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, double lambda,
+              const frsvt_rpca_opts &op, T *L, int64_t ldl, T *S, int64_t lds,
+              frsvt_rpca_stats *stats)
+{
+    const Orient o = orient(m, n, ldo);
+    const int mh = o.mh;
+    hipStream_t s = h->stream;
+    int rc;
+
+    // non-finite input
+    CK(hipMemsetAsync(h->dstatus + 16, 0, sizeof(int), s));
+    CK(launch_finite_check<T>(m, n, O, ldo, h->dstatus + 16, s));
+    // ||O||_F and ||O||_inf
+    int nparts = 0;
+    CK(launch_norms<T>(m, n, O, ldo, h->dscalars + 16, &nparts, s));
+    CK(hipMemcpyAsync(h->pinned, h->dstatus + 16, sizeof(int), hipMemcpyDeviceToHost, s));
+    CK(hipMemcpyAsync((char *)h->pinned + 64, h->dscalars + 16, 2 * nparts * sizeof(double),
+                      hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    if (((int *)h->pinned)[0]) return FRSVT_ERR_NONFINITE;
+    double ss = 0.0, mx = 0.0;
+    const double *np = (const double *)((char *)h->pinned + 64);
+    for (int g = 0; g < nparts; ++g) {
+        ss += np[2 * g];
+        mx = std::max(mx, np[2 * g + 1]);
+    }
+    const double normF = std::sqrt(ss);
+    double norm2 = 0.0;
+    if ((rc = spectral_norm<T>(h, O, ldo, o, &norm2))) return rc;
+    if (!(normF > 0.0) || !(norm2 > 0.0)) {
+        // O = 0: L = S = 0
+        CK(hipMemset2DAsync(L, ldl * sizeof(T), 0, m * sizeof(T), n, s));
+        CK(hipMemset2DAsync(S, lds * sizeof(T), 0, m * sizeof(T), n, s));
+        CK(hipStreamSynchronize(s));
+        if (stats) {
+            memset(stats, 0, sizeof(*stats));
+            stats->converged = 1;
+        }
+        return FRSVT_OK;
+    }
+    const double J = std::max(norm2, mx / lambda);
+    double mu = op.mu0 > 0.0 ? op.mu0 : 1.25 / norm2;
+    const double mu_bar = mu * op.mu_bar_factor;
+    const int l0 = op.l0 > 0 ? std::min(op.l0, mh) : std::min(mh, (int)std::ceil(0.1 * mh));
+
+    // workspace: A, the FRSVT core at its largest width, exact factors, z partials
+    const int lmax = op.use_frsvt ? std::min(mh, std::max(l0, mh)) : mh;
+    auto layout = [&](Carver &cv, T **A, CoreBuffers<T> &b, T **Qt, double **zp, T **Lx,
+                      double **zsum) {
+        *A = cv.take<T>((size_t)m * n);
+        *Qt = cv.take<T>((size_t)mh * mh);
+        *zp = cv.take<double>((size_t)1 << 20);
+        *zsum = cv.take<double>(4);
+        *Lx = cv.take<T>((size_t)m * n);
+        if (op.use_frsvt) carve_core<T>(cv, o, lmax, lmax, h->num_cu, b);
+        return cv.off;
+    };
+    T *A, *Qt, *Lx;
+    double *zp, *zsum;
+    CoreBuffers<T> b{};
+    Carver dry(nullptr);
+    size_t need = layout(dry, &A, b, &Qt, &zp, &Lx, &zsum);
+    size_t exact_need = 0;
+    if (!op.use_frsvt) {
+        Carver d2(nullptr);
+        d2.off = need;
+        double *Mm;
+        T *Mt;
+        exact_factors<T>(h, O, ldo, o, 0.0, nullptr, d2, &Mm, &Mt);
+        exact_need = d2.off;
+    }
+    if ((rc = ensure_ws(h, std::max(need, exact_need)))) return rc;
+    Carver cv(h->ws);
+    layout(cv, &A, b, &Qt, &zp, &Lx, &zsum);
+    const size_t exact_off = cv.off;
+
+    T *Ybuf[2] = {L, S};
+    const int64_t ldyb[2] = {ldl, lds};
+    CK(launch_rpca_init<T>(m, n, O, ldo, 1.0 / J, 1.0 / mu, Ybuf[0], ldyb[0], A, m, s));
+
+    auto t0 = std::chrono::steady_clock::now();
+    int r_prev = -1;
+    int it = 0;
+    bool converged = false;
+    double resid = 0.0, mu_last = mu;
+    Core<T> c{};
+    int *hst = (int *)h->pinned;
+    for (it = 0; it < op.max_iter; ++it) {
+        const double mu_next = std::min(op.rho * mu, mu_bar);
+        const T *Yc = Ybuf[it & 1];
+        T *Yn = Ybuf[(it + 1) & 1];
+        ReconArgs<T> ra{};
+        if (op.use_frsvt) {
+            c = Core<T>{};
+            c.A = A;
+            c.lda = m;
+            c.o = orient(m, n, m);
+            c.tau = 1.0 / mu;
+            c.w = nullptr;
+            c.q = op.q;
+            c.seed = op.seed;
+            c.counter = (uint64_t)it;
+            if (r_prev > 0) {
+                c.Qt = Qt;
+                c.ldqt = mh;
+                c.rp = r_prev;
+                c.cnew = std::max(0, std::min(op.p, mh - r_prev));
+            } else {
+                c.Qt = nullptr;
+                c.ldqt = mh;
+                c.rp = 0;
+                c.cnew = r_prev < 0 ? l0 : std::min(op.p, mh);
+            }
+            c.Qout = Qt;
+            c.ldqo = mh;
+            c.status = h->dstatus;
+            if ((rc = run_core<T>(h, c, b))) return rc;
+            ra.c = c.l;
+            if (o.trans) {
+                ra.FR = c.Bt;
+                ra.ldfr = o.nh;
+                ra.FC = c.QM;
+                ra.ldfc = o.mh;
+            } else {
+                ra.FR = c.QM;
+                ra.ldfr = o.mh;
+                ra.FC = c.Bt;
+                ra.ldfc = o.nh;
+            }
+            if (!recon_ok(c.l)) {
+                // wide basis: materialise L = (QM) B, then the epilogue reads it
+                const int64_t scm = o.trans ? m : 1, scn = o.trans ? 1 : m;
+                CK((launch_gemm<T, T, T>(o.mh, o.nh, c.l, c.QM, 1, o.mh, c.Bt, o.nh, 1, Lx, scm,
+                                         scn, 1, (T *)nullptr, s)));
+                ra.c = 0;
+                ra.Lin = Lx;
+                ra.ldlin = m;
+            }
+        } else {
+            Carver ce(h->ws);
+            ce.off = exact_off;
+            double *Mm;
+            T *Mt;
+            if ((rc = exact_factors<T>(h, A, m, orient(m, n, m), 1.0 / mu, nullptr, ce, &Mm, &Mt)))
+                return rc;
+            const Orient oa = orient(m, n, m);
+            const int64_t scm = oa.trans ? m : 1, scn = oa.trans ? 1 : m;
+            CK((launch_gemm<T, T, T>(oa.mh, oa.nh, oa.mh, Mt, 1, oa.mh, A, oa.si, oa.sk, Lx, scm,
+                                     scn, 1, (T *)nullptr, s)));
+            ra.c = 0;
+            ra.Lin = Lx;
+            ra.ldlin = m;
+        }
+        ra.rows = m;
+        ra.cols = n;
+        ra.O = O;
+        ra.ldo = ldo;
+        ra.Y = Yc;
+        ra.ldy = ldyb[it & 1];
+        ra.Ynext = Yn;
+        ra.ldyn = ldyb[(it + 1) & 1];
+        ra.Anext = A;
+        ra.ldan = m;
+        ra.mu = mu;
+        ra.mu_next = mu_next;
+        ra.lam = lambda;
+        ra.zpart = zp;
+        int nz = 0;
+        CK(launch_recon<T>(kEpi, ra, &nz, s));
+        CK(launch_reduce<double>(zp, 1, nz, zsum, s));
+        CK(hipMemcpyAsync(hst, h->dstatus, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
+        CK(hipMemcpyAsync(hst + 8, zsum, sizeof(double), hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+        const int r = hst[0];
+        double zz;
+        memcpy(&zz, hst + 8, sizeof(double));
+        resid = std::sqrt(zz) / normF;
+        if (stats && it < 64) {
+            stats->ranks[it] = r;
+            stats->residuals[it] = resid;
+        }
+        r_prev = r;
+        mu_last = mu;
+        mu = mu_next;
+        if (resid < op.tol) {
+            converged = true;
+            ++it;
+            break;
+        }
+    }
+    // L and S of the last iteration, from its factors and multiplier
+    {
+        const int last = it - 1;
+        ReconArgs<T> ra{};
+        if (op.use_frsvt && recon_ok(c.l)) {
+            ra.c = c.l;
+            if (o.trans) {
+                ra.FR = c.Bt;
+                ra.ldfr = o.nh;
+                ra.FC = c.QM;
+                ra.ldfc = o.mh;
+            } else {
+                ra.FR = c.QM;
+                ra.ldfr = o.mh;
+                ra.FC = c.Bt;
+                ra.ldfc = o.nh;
+            }
+        } else {
+            ra.c = 0;
+            ra.Lin = Lx;
+            ra.ldlin = m;
+        }
+        ra.rows = m;
+        ra.cols = n;
+        ra.O = O;
+        ra.ldo = ldo;
+        ra.Y = Ybuf[last & 1];
+        ra.ldy = ldyb[last & 1];
+        ra.X = L;
+        ra.ldx = ldl;
+        ra.S = S;
+        ra.lds = lds;
+        ra.mu = mu_last;
+        ra.mu_next = mu_last;
+        ra.lam = lambda;
+        CK(launch_recon<T>(kFinal, ra, nullptr, s));
+        CK(hipStreamSynchronize(s));
+    }
+    auto t1 = std::chrono::steady_clock::now();
+    if (stats) {
+        stats->iters = it;
+        stats->converged = converged ? 1 : 0;
+        stats->residual = resid;
+        stats->norm2 = norm2;
+        stats->seconds = std::chrono::duration<double>(t1 - t0).count();
+    }
+    return converged ? FRSVT_OK : FRSVT_MAX_ITER;
+}
+
+bool bad_ptr(const void *p) { return p == nullptr; }
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int frsvt_create(frsvt_handle *handle, int device, void *hip_stream)
+{
+    if (!handle) return -1;
+    *handle = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count < 1) return FRSVT_ERR_HIP;
+    if (device < 0 || device >= count) return -2;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return FRSVT_ERR_HIP;
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return FRSVT_ERR_UNSUPPORTED;
+    frsvt_context *h = new frsvt_context();
+    h->device = device;
+    h->stream = (hipStream_t)hip_stream;
+    h->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    int dev_prev = 0;
+    (void)hipGetDevice(&dev_prev);
+    (void)hipSetDevice(device);
+    hipError_t e = hipMalloc(&h->dstatus, kStatusInts * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&h->dscalars, kScalarDoubles * sizeof(double));
+    if (e == hipSuccess) e = hipHostMalloc(&h->pinned, 1 << 20, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMemset(h->dstatus, 0, kStatusInts * sizeof(int));
+    (void)hipSetDevice(dev_prev);
+    if (e != hipSuccess) {
+        if (h->dstatus) (void)hipFree(h->dstatus);
+        if (h->dscalars) (void)hipFree(h->dscalars);
+        if (h->pinned) (void)hipHostFree(h->pinned);
+        delete h;
+        return e == hipErrorOutOfMemory ? FRSVT_ERR_OOM : FRSVT_ERR_HIP;
+    }
+    *handle = h;
+    return FRSVT_OK;
+}
+
+int frsvt_destroy(frsvt_handle h)
+{
+    if (!h) return -1;
+    (void)hipStreamSynchronize(h->stream);
+    if (h->ws) (void)hipFree(h->ws);
+    if (h->dstatus) (void)hipFree(h->dstatus);
+    if (h->dscalars) (void)hipFree(h->dscalars);
+    if (h->pinned) (void)hipHostFree(h->pinned);
+    delete h;
+    return FRSVT_OK;
+}
+
+int frsvt_set_stream(frsvt_handle h, void *hip_stream)
+{
+    if (!h) return -1;
+    h->stream = (hipStream_t)hip_stream;
+    return FRSVT_OK;
+}
+
+const char *frsvt_status_string(int status)
+{
+    switch (status) {
+    case FRSVT_OK: return "success";
+    case FRSVT_NOT_CONVERGED: return "Jacobi sweep limit reached (result written)";
+    case FRSVT_MAX_ITER: return "RPCA reached max_iter before the tolerance";
+    case FRSVT_ERR_HIP: return "HIP runtime error";
+    case FRSVT_ERR_OOM: return "out of device memory";
+    case FRSVT_ERR_NONFINITE: return "non-finite input";
+    case FRSVT_ERR_UNSUPPORTED: return "unsupported device or configuration";
+    case FRSVT_ERR_HANDLE: return "invalid handle";
+    default: break;
+    }
+    if (status < 0 && status > -100) return "invalid argument";
+    return "unknown status";
+}
+
+const char *frsvt_last_error(frsvt_handle h) { return h ? h->last_error : "invalid handle"; }
+
+int64_t frsvt_workspace_bytes(frsvt_handle h) { return h ? (int64_t)h->ws_bytes : -1; }
+
+void frsvt_rpca_default_opts(frsvt_rpca_opts *op)
+{
+    if (!op) return;
+    op->tol = 1e-7;
+    op->max_iter = 60;
+    op->mu0 = 0.0;
+    op->rho = 1.5;
+    op->mu_bar_factor = 1e7;
+    op->use_frsvt = 1;
+    op->p = 5;
+    op->q = 1;
+    op->l0 = 0;
+    op->seed = 0;
+}
+
+int svt(frsvt_handle h, frsvt_precision prec, int64_t m, int64_t n, const void *A, int64_t lda,
+        double tau, void *X, int64_t ldx, int32_t *rank)
+{
+    if (!h) return -1;
+    if (prec != FRSVT_F64 && prec != FRSVT_F32 && prec != FRSVT_MIXED_BF16) return -2;
+    if (m < 1) return -3;
+    if (n < 1) return -4;
+    if (bad_ptr(A)) return -5;
+    if (lda < m) return -6;
+    if (!(tau >= 0.0) || !std::isfinite(tau)) return -7;
+    if (bad_ptr(X)) return -8;
+    if (ldx < m) return -9;
+    if (std::min(m, n) > 1024) return FRSVT_ERR_UNSUPPORTED;
+    if (prec == FRSVT_F64)
+        return exact_svt_impl<double>(h, m, n, (const double *)A, lda, tau, nullptr, (double *)X, ldx, rank);
+    return exact_svt_impl<float>(h, m, n, (const float *)A, lda, tau, nullptr, (float *)X, ldx, rank);
+}
+
+int wsvt(frsvt_handle h, frsvt_precision prec, int64_t m, int64_t n, const void *A, int64_t lda,
+         const double *w, void *X, int64_t ldx, int32_t *rank)
+{
+    if (!h) return -1;
+    if (prec != FRSVT_F64 && prec != FRSVT_F32 && prec != FRSVT_MIXED_BF16) return -2;
+    if (m < 1) return -3;
+    if (n < 1) return -4;
+    if (bad_ptr(A)) return -5;
+    if (lda < m) return -6;
+    if (bad_ptr(w)) return -7;
+    if (bad_ptr(X)) return -8;
+    if (ldx < m) return -9;
+    if (std::min(m, n) > 1024) return FRSVT_ERR_UNSUPPORTED;
+    if (prec == FRSVT_F64)
+        return exact_svt_impl<double>(h, m, n, (const double *)A, lda, 0.0, w, (double *)X, ldx, rank);
+    return exact_svt_impl<float>(h, m, n, (const float *)A, lda, 0.0, w, (float *)X, ldx, rank);
+}
+
+int frsvt(frsvt_handle h, frsvt_precision prec, int64_t m, int64_t n, const void *A, int64_t lda,
+          double tau, int32_t k, int32_t p, int32_t q, const void *Q_prev, int32_t r_prev,
+          int64_t ldq_prev, uint64_t seed, uint64_t counter, void *X, int64_t ldx, void *Q_out,
+          int64_t ldq_out, int32_t *r_out)
+{
+    if (!h) return -1;
+    if (prec != FRSVT_F64 && prec != FRSVT_F32 && prec != FRSVT_MIXED_BF16) return -2;
+    if (m < 1) return -3;
+    if (n < 1) return -4;
+    if (bad_ptr(A)) return -5;
+    if (lda < m) return -6;
+    if (!(tau >= 0.0) || !std::isfinite(tau)) return -7;
+    const bool rp = Q_prev != nullptr && r_prev > 0;
+    if (!rp && (k < 0 || k + p < 1)) return -8;
+    if (p < 0) return -9;
+    if (q < 0 || q > 64) return -10;
+    const int64_t mh = std::min(m, n);
+    if (Q_prev && (r_prev < 0 || r_prev > mh)) return -12;
+    if (rp && ldq_prev < mh) return -13;
+    if (bad_ptr(X)) return -16;
+    if (ldx < m) return -17;
+    if (Q_out && ldq_out < mh) return -19;
+    if (mh > 1024) return FRSVT_ERR_UNSUPPORTED;
+    if (prec == FRSVT_MIXED_BF16) return FRSVT_ERR_UNSUPPORTED;
+    if (prec == FRSVT_F64)
+        return frsvt_impl<double>(h, m, n, (const double *)A, lda, tau, k, p, q,
+                                  (const double *)Q_prev, r_prev, ldq_prev, seed, counter,
+                                  (double *)X, ldx, (double *)Q_out, ldq_out, r_out);
+    return frsvt_impl<float>(h, m, n, (const float *)A, lda, tau, k, p, q, (const float *)Q_prev,
+                             r_prev, ldq_prev, seed, counter, (float *)X, ldx, (float *)Q_out,
+                             ldq_out, r_out);
+}
+
+int rpca_ialm(frsvt_handle h, frsvt_precision prec, int64_t m, int64_t n, const void *O,
+              int64_t ldo, double lambda, const frsvt_rpca_opts *opts, void *L, int64_t ldl,
+              void *S, int64_t lds, frsvt_rpca_stats *stats)
+{
+    if (!h) return -1;
+    if (prec != FRSVT_F64 && prec != FRSVT_F32 && prec != FRSVT_MIXED_BF16) return -2;
+    if (m < 1) return -3;
+    if (n < 1) return -4;
+    if (bad_ptr(O)) return -5;
+    if (ldo < m) return -6;
+    if (!(lambda > 0.0) || !std::isfinite(lambda)) return -7;
+    frsvt_rpca_opts op;
+    frsvt_rpca_default_opts(&op);
+    if (opts) op = *opts;
+    if (!(op.tol > 0.0) || op.max_iter < 1 || !(op.rho >= 1.0) || op.p < 1 || op.q < 0 ||
+        !(op.mu_bar_factor >= 1.0))
+        return -8;
+    if (bad_ptr(L)) return -9;
+    if (ldl < m) return -10;
+    if (bad_ptr(S)) return -11;
+    if (lds < m) return -12;
+    if (std::min(m, n) > 1024) return FRSVT_ERR_UNSUPPORTED;
+    if (prec == FRSVT_MIXED_BF16) return FRSVT_ERR_UNSUPPORTED;
+    if (prec == FRSVT_F64)
+        return rpca_impl<double>(h, m, n, (const double *)O, ldo, lambda, op, (double *)L, ldl,
+                                 (double *)S, lds, stats);
+    return rpca_impl<float>(h, m, n, (const float *)O, ldo, lambda, op, (float *)L, ldl,
+                            (float *)S, lds, stats);
+}
+
+int wsvt_batched(frsvt_handle h, int64_t count, const int32_t *rows, const int32_t *cols,
+                 const int64_t *offsets, const float *A_packed, float *X_packed,
+                 const frsvt_wsvt_rule *rule, int32_t *ranks)
+{
+    if (!h) return -1;
+    if (count < 0) return -2;
+    if (count > 0 && bad_ptr(rows)) return -3;
+    if (count > 0 && bad_ptr(cols)) return -4;
+    if (count > 0 && bad_ptr(offsets)) return -5;
+    if (count > 0 && bad_ptr(A_packed)) return -6;
+    if (count > 0 && bad_ptr(X_packed)) return -7;
+    if (bad_ptr(rule)) return -8;
+    (void)ranks;
+    return FRSVT_ERR_UNSUPPORTED;
+}
+
+}  // extern "C"

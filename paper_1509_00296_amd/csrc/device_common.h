@@ -1,0 +1,104 @@
+// device_common.h -- device-side building blocks shared by the FRSVT kernels
+// (gfx950, wave64): the Philox4x32-10 Gaussian stream, wavefront reductions,
+// small helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace frk {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32->64-bit products; the key advances by the Weyl increments between
+// rounds.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        if (round) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c[0];
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c[0]);
+        const uint32_t lo1 = 0xCD9E8D57u * c[2];
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]);
+        const uint32_t n0 = hi1 ^ c[1] ^ k0;
+        const uint32_t n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+// (c + 1/2) 2^-53 for the 53-bit integer c formed by the top 27 bits of a and
+// the top 26 bits of b: a uniform number in (0, 1].
+__device__ __forceinline__ double uniform53(uint32_t a, uint32_t b)
+{
+    return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6) + 0.5) *
+           (1.0 / 9007199254740992.0);
+}
+
+// The Gaussian test matrix of the sketch: Omega(k, 2j + e) is output e of a
+// Box-Muller transform of the Philox block with counter {k, j, ctr lo, ctr hi}
+// and key = seed.
+__device__ __forceinline__ void gaussian_pair(uint64_t seed, uint64_t counter, uint32_t row,
+                                              uint32_t pair, double &z0, double &z1)
+{
+    uint32_t c[4] = {row, pair, (uint32_t)counter, (uint32_t)(counter >> 32)};
+    philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const double u1 = uniform53(c[0], c[1]);
+    const double u2 = uniform53(c[2], c[3]);
+    const double radius = sqrt(-2.0 * log(u1));
+    double s, co;
+    sincos(6.283185307179586476925286766559 * u2, &s, &co);
+    z0 = radius * co;
+    z1 = radius * s;
+}
+
+// Replacement directions for numerically null basis columns use a disjoint
+// part of the counter space (high bit of the pair word set).
+constexpr uint32_t kRefillTag = 0x80000000u;
+
+// ---------------------------------------------------------------------------
+// Wavefront reductions (64 lanes) through cross-lane shuffles.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+__device__ __forceinline__ float wave_sum(float v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+__device__ __forceinline__ double soft_shrink(double x, double t)
+{
+    const double a = fabs(x) - t;
+    return a > 0.0 ? copysign(a, x) : 0.0;
+}
+
+__device__ __forceinline__ float soft_shrink(float x, float t)
+{
+    const float a = fabsf(x) - t;
+    return a > 0.0f ? copysignf(a, x) : 0.0f;
+}
+
+}  // namespace frk

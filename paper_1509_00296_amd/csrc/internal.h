@@ -1,0 +1,178 @@
+// internal.h -- launch interface between the host orchestration (api.hip) and
+// the gfx950 kernels (kernels.hip).  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace frk {
+
+// ----------------------------------------------------------------- long pass
+// One pass over Ahat (mhat x nhat) reducing over the long dimension, with the
+// whole short dimension inside one workgroup:
+//   kSketch : Ypart += Ahat * Omega(seed, counter)           (Omega in-register)
+//   kVecMul : Ypart += Ahat * V                               (V nhat x c)
+//   kPower  : z_k = Ahat(:,k)^T Q,  Ypart += Ahat(:,k) z_k^T   (one read of A)
+//   kProject: z_k = Ahat(:,k)^T Q -> Bt(k,:),  Gpart += z_k z_k^T
+enum LongMode { kSketch = 0, kVecMul = 1, kPower = 2, kProject = 3 };
+
+template <typename T>
+struct LongArgs {
+    const T *A;
+    int64_t lda;
+    int trans;       // 1: Ahat = A^T (A is nhat x mhat), 0: Ahat = A
+    int mh;
+    int64_t nh;
+    int c;
+    int kt;          // tile width along the long dimension
+    int mhp;         // padded LDS row stride (odd)
+    int ntiles;
+    uint64_t seed, counter;
+    const T *V;
+    int64_t ldv;
+    const T *Q;
+    int64_t ldq;
+    T *Ypart;        // [grid][c][mh]
+    T *Z;            // kProject: Bt, nhat x c
+    int64_t ldz;
+    double *Gpart;   // kProject: [grid][c][c]
+};
+
+struct LongPlan {
+    int kt, mhp, ntiles, grid, cm, rpt;
+    size_t lds;
+};
+
+bool long_path_ok(int mh, int c);
+LongPlan long_plan(int mh, int64_t nh, int c, int elem_bytes, int mode, int num_cu);
+template <typename T>
+hipError_t launch_long(const LongPlan &plan, int mode, const LongArgs<T> &args, hipStream_t s);
+
+// out[j] = sum_{g < nparts} part[g * count + j], fixed order.
+template <typename T>
+hipError_t launch_reduce(const T *part, int64_t count, int nparts, T *out, hipStream_t s);
+
+// ------------------------------------------------------ one-workgroup CholeskyQR
+// Q = orth([Qt, Y]) with Qt (mh x rp) orthonormal and Y (mh x c):
+//  CGS2 of Y against Qt, column equilibration, shifted CholeskyQR, then
+//  CholeskyQR2 with refill of numerically null columns.  mh * (rp + c) must
+//  fit the LDS budget (small_orth_ok).
+bool small_orth_ok(int mh, int l);
+template <typename T>
+hipError_t launch_small_orth(int mh, const T *Qt, int64_t ldqt, int rp, const T *Y, int64_t ldy,
+                             int c, T *Q, int64_t ldq, uint64_t seed, uint64_t counter,
+                             int *flags, hipStream_t s);
+
+// ------------------------------------------------------------- small SVD
+// From the l x l Gram G = B B^T (double): semidefinite Cholesky G = R^T R,
+// one-sided Jacobi on R^T, U_B and sigma (descending), thresholds (tau, or
+// per-index weights w when w != nullptr), r = #{f > 0}, Mm = U diag(f/s) U^T.
+// With Q (mh x l) given and mh * l small, also QM = Q Mm (mh x l) and
+// Qout = Q U(:, 1:r).  Jacobi storage: LDS when l <= 128, else work (l*l).
+struct SmallSvdOut {
+    double *sigma;   // l
+    double *U;       // l x l
+    double *Mm;      // l x l
+    int *status;     // [0] r, [1] sweeps, [2] converged flag, [3] unused
+};
+template <typename T>
+hipError_t launch_small_svd(int l, const double *G, double tau, const double *w, const T *Q,
+                            int64_t ldq, int mh, T *QM, int64_t ldqm, T *Qout, int64_t ldqo,
+                            const SmallSvdOut &out, double *work, int fuse_q, hipStream_t s);
+bool small_svd_fuse_q_ok(int mh, int l);
+
+// ------------------------------------------------ rank-l reconstruct family
+// Physical element (pr, pc) of an m x n column-major output, with
+// L(pr, pc) = sum_c FR(pr, c) FC(pc, c):
+//   kRecon : X = L
+//   kEpi   : t = O - L + Y/mu, S = shrink(t, lam/mu), z = O - L - S,
+//            Ynext = Y + mu z, Anext = O - S + Ynext/mu_next, zpart += z^2
+//   kFinal : L and S of the last iteration (Y = the multiplier it used).
+enum ReconMode { kRecon = 0, kEpi = 1, kFinal = 2 };
+template <typename T>
+struct ReconArgs {
+    int64_t rows, cols;   // physical
+    int c;
+    const T *FR;          // rows x c, ld ldfr
+    int64_t ldfr;
+    const T *FC;          // cols x c, ld ldfc
+    int64_t ldfc;
+    T *X;                 // kRecon output / kFinal L
+    int64_t ldx;
+    const T *O;
+    int64_t ldo;
+    const T *Y;           // multiplier in
+    int64_t ldy;
+    T *Ynext;
+    int64_t ldyn;
+    T *Anext;
+    int64_t ldan;
+    T *S;                 // kFinal S
+    int64_t lds;
+    double mu, mu_next, lam;
+    double *zpart;        // [grid] partial sums of z^2
+    const T *Lin;         // when set, L is read from here instead of FR FC^T
+    int64_t ldlin;
+};
+bool recon_ok(int c);
+template <typename T>
+hipError_t launch_recon(int mode, const ReconArgs<T> &a, int *nparts, hipStream_t s);
+
+// ------------------------------------------------------------ elementwise
+// Sum of squares and max |.| of an m x n matrix: parts[2*g] = sum, parts[2*g+1] = max.
+template <typename T>
+hipError_t launch_norms(int64_t m, int64_t n, const T *A, int64_t lda, double *parts,
+                        int *nparts, hipStream_t s);
+// Y = O / J ;  A = O + Y / mu
+template <typename T>
+hipError_t launch_rpca_init(int64_t m, int64_t n, const T *O, int64_t ldo, double invJ,
+                            double inv_mu, T *Y, int64_t ldy, T *A, int64_t lda, hipStream_t s);
+// non-finite check: flag[0] |= 1 when any entry is NaN or Inf
+template <typename T>
+hipError_t launch_finite_check(int64_t m, int64_t n, const T *A, int64_t lda, int *flag,
+                               hipStream_t s);
+
+// Largest eigenvalue of a symmetric positive semidefinite l x l matrix by the
+// power method (one workgroup); out[0] = lambda_max.
+hipError_t launch_power_eig(int l, const double *G, double *work, double *out, hipStream_t s);
+
+// --------------------------------------------------------- generic GEMM
+// C(m, n) = sum_k A(m, k) B(k, n) with arbitrary element strides:
+//   A(m,k) = A[m*sam + k*sak], B(k,n) = B[k*sbk + n*sbn], C(m,n) = C[m*scm + n*scn].
+// splitk > 1 writes TA partials to part ([splitk][N][M]) and a store pass sums
+// them in order into C.
+template <typename TI, typename TA, typename TO>
+hipError_t launch_gemm(int64_t M, int64_t N, int64_t K, const TI *A, int64_t sam, int64_t sak,
+                       const TI *B, int64_t sbk, int64_t sbn, TO *C, int64_t scm, int64_t scn,
+                       int splitk, TA *part, hipStream_t s);
+
+// Omega (rows x cols, ld) materialised in storage precision.
+template <typename T>
+hipError_t launch_omega(int64_t rows, int cols, uint64_t seed, uint64_t counter, T *Om,
+                        int64_t ld, hipStream_t s);
+
+// ----------------------------------------------------- large CholeskyQR pieces
+// One Cholesky pass on the l x l Gram (double, one workgroup): R = chol(G + shift I)
+// with shift = shift_factor * trace(G); pivots below null_tol * maxdiag are
+// flagged (flags[1] counts them, null_cols[j] = 1) and get R_jj = 1 with a
+// zero row.  flags[2] |= 1 when a pivot is not positive in a pass without
+// null handling.
+hipError_t launch_chol(int l, const double *G, double shift_factor, double null_tol, double *R,
+                       int *null_cols, int *flags, hipStream_t s);
+// Y (rows x l) <- Y R^{-1} in place (R upper, double), one thread per row.
+template <typename T>
+hipError_t launch_trsm(int64_t rows, int l, T *Y, int64_t ldy, const double *R, hipStream_t s);
+// Y(:, j) <- Gaussian(refill stream) for null_cols[j] = 1; also scales
+// columns to unit norm when normalize != 0 (norms from the Gram diagonal).
+template <typename T>
+hipError_t launch_refill(int64_t rows, int l, T *Y, int64_t ldy, const int *null_cols,
+                         uint64_t seed, uint64_t counter, int attempt, hipStream_t s);
+template <typename T>
+hipError_t launch_col_scale(int64_t rows, int l, T *Y, int64_t ldy, const double *G,
+                            hipStream_t s);
+// Y <- Y - Qt (Qt^T Y): coefficients C (rp x c) = Qt^T Y then the update.
+template <typename T>
+hipError_t launch_cast(int64_t m, int64_t n, const void *src, int src_is_double, int64_t lds,
+                       T *dst, int64_t ldd, hipStream_t s);
+
+}  // namespace frk

@@ -1,0 +1,182 @@
+"""GPU parity of the C-ABI library against the FP64 CPU oracle.
+
+Both sides draw the same Gaussian test matrix from their own Philox4x32-10
+implementations (same seed and counter); every oracle input comes from the
+seeded generators in paper_1509_00296_amd.synth or from the oracle itself.
+FP64 bar: relative Frobenius error <= 1e-10 and equal ranks.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def fr():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1509_00296_amd as fr
+    fr.handle(0)
+    return fr
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.build()
+    return oracle
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _gpu(a, dtype=torch.float64):
+    return torch.from_numpy(np.asfortranarray(a)).to(dtype=dtype).cuda()
+
+
+def _lowrank(seed, m, n, rank, noise):
+    from paper_1509_00296_amd import synth
+    smax = 100.0
+    return synth.single_svt(seed=seed, m=m, n=n, rank=rank, noise_std=noise, smax=smax,
+                            smin=10.0)
+
+
+CASES = [
+    # m, n, rank, noise, tau, k, p, q
+    (500, 300, 10, 0.01, 1.0, 10, 5, 2),     # the single-SVT workload
+    (300, 500, 10, 0.01, 1.0, 10, 5, 2),     # Ahat = A (no transpose)
+    (257, 1000, 7, 0.05, 2.0, 7, 4, 1),      # ragged long tiles
+    (1000, 130, 5, 0.01, 0.5, 5, 3, 0),      # q = 0
+    (64, 64, 12, 0.1, 3.0, 16, 8, 2),        # square, l > rank
+    (2000, 33, 3, 0.02, 1.5, 3, 2, 1),       # odd short side
+    (700, 250, 20, 0.01, 1.0, 20, 12, 1),    # l = 32 (widest one-pass basis)
+]
+
+
+@pytest.mark.parametrize("m,n,rank,noise,tau,k,p,q", CASES)
+def test_frsvt_f64_matches_oracle(fr, orc, m, n, rank, noise, tau, k, p, q):
+    _say(f"case frsvt f64 {m}x{n} l={k + p} q={q}")
+    A = _lowrank(m * 7 + n, m, n, rank, noise)
+    seed, counter = 1234 + m, 3
+    X, Qt, r = fr.frsvt(_gpu(A), tau, k, p, q, seed=seed, counter=counter)
+    torch.cuda.synchronize()
+    Om = orc.gaussian_matrix(seed, counter, max(m, n), min(k + p, min(m, n)))
+    Xo, Qo, ro, _, _ = orc.frsvt(A, tau, q, Om)
+    assert r == ro
+    assert _rel(X.cpu().numpy(), Xo) <= 1e-10
+    Qg = Qt.cpu().numpy()
+    assert np.abs(Qg.T @ Qg - np.eye(r)).max() < 1e-12
+    # propagated bases agree as subspaces
+    assert np.linalg.norm(Qg @ Qg.T - Qo @ Qo.T) < 1e-9
+
+
+def test_frsvt_row_major_tensor(fr, orc):
+    _say("case frsvt row-major input")
+    A = _lowrank(5, 400, 250, 8, 0.01)
+    Ar = torch.from_numpy(np.ascontiguousarray(A)).cuda()   # row-major storage
+    X, _, r = fr.frsvt(Ar, 1.0, 8, 4, 1, seed=9, counter=0)
+    Om = orc.gaussian_matrix(9, 0, 400, 12)
+    Xo, _, ro, _, _ = orc.frsvt(A, 1.0, 1, Om)
+    assert r == ro and _rel(X.cpu().numpy(), Xo) <= 1e-10
+
+
+@pytest.mark.parametrize("trans", [False, True])
+def test_frsvt_range_propagation(fr, orc, trans):
+    _say(f"case frsvt RP trans={trans}")
+    m, n = (600, 240) if trans else (240, 600)
+    A0 = _lowrank(11, m, n, 6, 0.02)
+    A1 = A0 + 0.05 * np.random.default_rng(3).standard_normal((m, n))
+    # previous basis from the oracle's own first call
+    Om0 = orc.gaussian_matrix(77, 0, max(m, n), 11)
+    _, Qprev, r0, _, _ = orc.frsvt(A0, 1.0, 1, Om0)
+    p = 5
+    Om1 = orc.gaussian_matrix(77, 1, max(m, n), p)
+    Xo, Qo, ro, _, _ = orc.frsvt(A1, 1.0, 1, Om1, Qprev=Qprev)
+    X, Qt, r = fr.frsvt(_gpu(A1), 1.0, 0, p, 1, Q_prev=_gpu(Qprev), seed=77, counter=1)
+    assert r == ro
+    assert _rel(X.cpu().numpy(), Xo) <= 1e-10
+
+
+def test_frsvt_exact_recovery_rank_deficient_sketch(fr, orc):
+    _say("case frsvt exact recovery, l > rank (null sketch columns)")
+    A = _lowrank(21, 500, 300, 10, 0.0)
+    X, _, r = fr.frsvt(_gpu(A), 1.0, 10, 5, 2, seed=5, counter=0)
+    Xe, re = orc.svt(A, 1.0)
+    assert r == re == 10
+    assert _rel(X.cpu().numpy(), Xe) <= 1e-10
+
+
+def test_frsvt_threshold_edges(fr, orc):
+    _say("case frsvt tau = 0 and tau > sigma_1")
+    A = _lowrank(31, 300, 200, 5, 0.01)
+    X0, _, r0 = fr.frsvt(_gpu(A), 0.0, 6, 4, 1, seed=1, counter=0)
+    Om = orc.gaussian_matrix(1, 0, 300, 10)
+    Xo, _, ro, _, _ = orc.frsvt(A, 0.0, 1, Om)
+    assert r0 == ro == 10 and _rel(X0.cpu().numpy(), Xo) <= 1e-10
+    Xb, Qb, rb = fr.frsvt(_gpu(A), 1e6, 6, 4, 1, seed=1, counter=0)
+    assert rb == 0 and float(Xb.abs().max()) == 0.0 and Qb.shape[1] == 0
+
+
+def test_frsvt_full_width_is_exact(fr, orc):
+    _say("case frsvt l = min(m, n)")
+    A = np.random.default_rng(8).standard_normal((120, 30)) * 2
+    X, _, r = fr.frsvt(_gpu(A), 1.5, 30, 0, 1, seed=2, counter=0)
+    Xe, re = orc.svt(A, 1.5)
+    assert r == re and _rel(X.cpu().numpy(), Xe) <= 1e-10
+
+
+def test_frsvt_f32_bound(fr, orc):
+    _say("case frsvt f32 500x300")
+    A = _lowrank(41, 500, 300, 10, 0.01)
+    X, _, r = fr.frsvt(_gpu(A, torch.float32), 1.0, 10, 5, 2, seed=3, counter=0)
+    Om = orc.gaussian_matrix(3, 0, 500, 15)
+    Xo, _, ro, _, _ = orc.frsvt(A, 1.0, 2, Om)
+    assert r == ro
+    assert _rel(X.double().cpu().numpy(), Xo) <= 2e-5
+
+
+@pytest.mark.parametrize("m,n", [(500, 300), (60, 200), (333, 90)])
+def test_svt_exact_matches_oracle(fr, orc, m, n):
+    _say(f"case svt f64 {m}x{n}")
+    A = _lowrank(m + n, m, n, 8, 0.05)
+    X, r = fr.svt(_gpu(A), 1.0, return_rank=True)
+    Xo, ro = orc.svt(A, 1.0)
+    assert r == ro
+    assert _rel(X.cpu().numpy(), Xo) <= 1e-10
+
+
+def test_wsvt_matches_oracle(fr, orc):
+    _say("case wsvt f64 100x81")
+    A = _lowrank(7, 100, 81, 4, 0.1)
+    w = np.linspace(0.5, 8.0, 81)
+    X, r = fr.wsvt(_gpu(A), torch.from_numpy(w).cuda(), return_rank=True)
+    Xo, ro = orc.wsvt(A, w)
+    assert r == ro
+    assert _rel(X.cpu().numpy(), Xo) <= 1e-10
+
+
+@pytest.mark.parametrize("mode", ["frsvt", "exact"])
+def test_rpca_small_matches_oracle(fr, orc, mode):
+    from paper_1509_00296_amd import synth
+    _say(f"case rpca {mode} 3000x60")
+    O, Lgt, _ = synth.rpca(seed=3, m=3000, n=60, rank=3, frac=0.10)
+    lam = 1.0 / np.sqrt(3000)
+    res = fr.rpca_ialm(_gpu(O), lam, use_frsvt=(mode == "frsvt"), seed=17)
+    out = orc.rpca_ialm(O, lam, mode=mode, p=5, q=1, seed=17)
+    assert res.iters == out["iters"]
+    assert res.ranks == list(out["ranks"][:64])
+    assert _rel(res.L.cpu().numpy(), out["L"]) <= 1e-10
+    assert _rel(res.S.cpu().numpy(), out["S"]) <= 1e-10
+    assert res.converged
+    assert np.linalg.norm(res.L.cpu().numpy() - Lgt) / np.linalg.norm(Lgt) < 1e-4
