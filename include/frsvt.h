@@ -88,6 +88,37 @@ FRSVT_API const char *frsvt_last_error(frsvt_handle handle);
 /* Device bytes currently held by the handle's workspace. */
 FRSVT_API int64_t frsvt_workspace_bytes(frsvt_handle handle);
 
+/* ------------------------------------------------------------------ tracing */
+
+/* Kernel classes timed by the tracer. */
+typedef enum {
+    FRSVT_K_SKETCH = 0,   /* Y = Ahat Omega (Omega drawn in registers) */
+    FRSVT_K_POWER = 1,    /* fused power step Y = Ahat (Ahat^T Q) */
+    FRSVT_K_PROJECT = 2,  /* B^T = Ahat^T Q and the Gram B B^T */
+    FRSVT_K_REDUCE = 3,   /* split-K reductions */
+    FRSVT_K_ORTH = 4,     /* CholeskyQR re-orthonormalisation */
+    FRSVT_K_SMALL_SVD = 5,/* Cholesky + one-sided Jacobi SVD of the small factor */
+    FRSVT_K_RECON = 6,    /* shrink-and-reconstruct X = (Q Mm) B */
+    FRSVT_K_EPILOGUE = 7, /* RPCA epilogue (L on the fly, S, multiplier, next A) */
+    FRSVT_K_GEMM = 8,     /* generic tiled GEMM (large shapes, exact SVT) */
+    FRSVT_K_OTHER = 9,
+    FRSVT_K_COUNT = 10
+} frsvt_kernel_class;
+
+/* Start (enable != 0, clearing earlier records) or stop recording a pair of
+ * HIP events around every kernel launch of this handle, on the handle's
+ * stream.  Off by default. */
+FRSVT_API int frsvt_trace_enable(frsvt_handle handle, int enable);
+
+/* Waits for the recorded events and returns, for one kernel class, the total
+ * GPU time in milliseconds and the number of launches recorded since
+ * tracing was enabled. */
+FRSVT_API int frsvt_trace_read(frsvt_handle handle, int kernel_class, double *total_ms,
+                               int64_t *launches);
+
+/* Name of a kernel class (static storage). */
+FRSVT_API const char *frsvt_trace_name(int kernel_class);
+
 /* ---------------------------------------------------------- exact operator */
 
 /*

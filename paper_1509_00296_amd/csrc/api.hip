@@ -29,6 +29,12 @@ struct frsvt_context {
     double *dscalars = nullptr;  // small device scalar area (doubles)
     void *pinned = nullptr;      // host pinned status area
     char last_error[256] = {0};
+    // tracing: event pairs around launches, aggregated per kernel class
+    bool tracing = false;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> recs;
+    std::vector<hipEvent_t> pool;
+    double trace_ms[FRSVT_K_COUNT] = {0};
+    int64_t trace_n[FRSVT_K_COUNT] = {0};
 };
 
 namespace {
@@ -45,6 +51,50 @@ int fail(frsvt_context *h, hipError_t e, const char *what)
 
 #define CK(expr)                                                   \
     do {                                                           \
+        hipError_t e_ = (expr);                                    \
+        if (e_ != hipSuccess) return fail(h, e_, #expr);           \
+    } while (0)
+
+hipEvent_t ev_get(frsvt_context *h)
+{
+    if (!h->pool.empty()) {
+        hipEvent_t e = h->pool.back();
+        h->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Records a HIP event pair on the handle's stream around one launch when
+// tracing is on.
+struct Span {
+    frsvt_context *h;
+    int id;
+    hipEvent_t a = nullptr;
+    Span(frsvt_context *hh, int kid) : h(hh), id(kid)
+    {
+        if (h->tracing) {
+            a = ev_get(h);
+            if (a) (void)hipEventRecord(a, h->stream);
+        }
+    }
+    ~Span()
+    {
+        if (h->tracing && a) {
+            hipEvent_t b = ev_get(h);
+            if (b) {
+                (void)hipEventRecord(b, h->stream);
+                h->recs.push_back({id, {a, b}});
+            }
+        }
+    }
+};
+
+#define CKT(kid, expr)                                             \
+    do {                                                           \
+        Span sp_(h, kid);                                          \
         hipError_t e_ = (expr);                                    \
         if (e_ != hipSuccess) return fail(h, e_, #expr);           \
     } while (0)
@@ -199,7 +249,7 @@ int ahat_times(frsvt_context *h, const Core<T> &c, const T *V, int64_t ldv, int 
 {
     const Orient &o = c.o;
     const int sk = gemm_splitk(o.mh, cols, o.nh, h->num_cu);
-    CK((launch_gemm<T, T, T>(o.mh, cols, o.nh, c.A, o.si, o.sk, V, 1, ldv, Y, 1, o.mh, sk, part,
+    CKT(FRSVT_K_GEMM, (launch_gemm<T, T, T>(o.mh, cols, o.nh, c.A, o.si, o.sk, V, 1, ldv, Y, 1, o.mh, sk, part,
                              h->stream)));
     return FRSVT_OK;
 }
@@ -210,7 +260,7 @@ int ahat_t_times(frsvt_context *h, const Core<T> &c, const T *Qm, int64_t ldq, i
                  T *part)
 {
     const Orient &o = c.o;
-    CK((launch_gemm<T, T, T>(o.nh, cols, o.mh, c.A, o.sk, o.si, Qm, 1, ldq, Z, 1, o.nh, 1, part,
+    CKT(FRSVT_K_GEMM, (launch_gemm<T, T, T>(o.nh, cols, o.mh, c.A, o.sk, o.si, Qm, 1, ldq, Z, 1, o.nh, 1, part,
                              h->stream)));
     return FRSVT_OK;
 }
@@ -221,11 +271,11 @@ int gram(frsvt_context *h, int64_t rows, int l, const T *Y, int64_t ldy, double 
 {
     const int sk = gemm_splitk(l, l, rows, h->num_cu);
     if (std::is_same<T, double>::value) {
-        CK((launch_gemm<double, double, double>(l, l, rows, (const double *)Y, ldy, 1,
+        CKT(FRSVT_K_GEMM, (launch_gemm<double, double, double>(l, l, rows, (const double *)Y, ldy, 1,
                                                 (const double *)Y, 1, ldy, G, 1, l, sk, part,
                                                 h->stream)));
     } else {
-        CK((launch_gemm<float, double, double>(l, l, rows, (const float *)Y, ldy, 1,
+        CKT(FRSVT_K_GEMM, (launch_gemm<float, double, double>(l, l, rows, (const float *)Y, ldy, 1,
                                                (const float *)Y, 1, ldy, G, 1, l, sk, part,
                                                h->stream)));
     }
@@ -241,22 +291,22 @@ int big_orth(frsvt_context *h, int64_t rows, int l, T *Y, int64_t ldy, CoreBuffe
 {
     int rc;
     if ((rc = gram(h, rows, l, Y, ldy, b.G, b.gpart_d))) return rc;
-    CK(launch_col_scale<T>(rows, l, Y, ldy, b.G, h->stream));
+    CKT(FRSVT_K_ORTH, launch_col_scale<T>(rows, l, Y, ldy, b.G, h->stream));
     const double shift = 11.0 * ((double)rows * l + (double)l * (l + 1)) * kU;
     if ((rc = gram(h, rows, l, Y, ldy, b.G, b.gpart_d))) return rc;
-    CK(launch_chol(l, b.G, shift, 0.0, b.R, nullptr, flags, h->stream));
-    CK(launch_trsm<T>(rows, l, Y, ldy, b.R, h->stream));
+    CKT(FRSVT_K_ORTH, launch_chol(l, b.G, shift, 0.0, b.R, nullptr, flags, h->stream));
+    CKT(FRSVT_K_ORTH, launch_trsm<T>(rows, l, Y, ldy, b.R, h->stream));
     for (int attempt = 0; attempt < 2; ++attempt) {
         if ((rc = gram(h, rows, l, Y, ldy, b.G, b.gpart_d))) return rc;
-        CK(launch_chol(l, b.G, 0.0, 16.0 * l * kU, b.R, b.nullc, flags, h->stream));
-        CK(launch_refill<T>(rows, l, Y, ldy, b.nullc, seed, counter, attempt, h->stream));
+        CKT(FRSVT_K_ORTH, launch_chol(l, b.G, 0.0, 16.0 * l * kU, b.R, b.nullc, flags, h->stream));
+        CKT(FRSVT_K_ORTH, launch_refill<T>(rows, l, Y, ldy, b.nullc, seed, counter, attempt, h->stream));
     }
     if ((rc = gram(h, rows, l, Y, ldy, b.G, b.gpart_d))) return rc;
-    CK(launch_chol(l, b.G, 0.0, 16.0 * l * kU, b.R, b.nullc, flags, h->stream));
-    CK(launch_trsm<T>(rows, l, Y, ldy, b.R, h->stream));
+    CKT(FRSVT_K_ORTH, launch_chol(l, b.G, 0.0, 16.0 * l * kU, b.R, b.nullc, flags, h->stream));
+    CKT(FRSVT_K_ORTH, launch_trsm<T>(rows, l, Y, ldy, b.R, h->stream));
     if ((rc = gram(h, rows, l, Y, ldy, b.G, b.gpart_d))) return rc;
-    CK(launch_chol(l, b.G, 0.0, 0.0, b.R, nullptr, flags, h->stream));
-    CK(launch_trsm<T>(rows, l, Y, ldy, b.R, h->stream));
+    CKT(FRSVT_K_ORTH, launch_chol(l, b.G, 0.0, 0.0, b.R, nullptr, flags, h->stream));
+    CKT(FRSVT_K_ORTH, launch_trsm<T>(rows, l, Y, ldy, b.R, h->stream));
     return FRSVT_OK;
 }
 
@@ -294,17 +344,17 @@ int run_core(frsvt_context *h, Core<T> &c, CoreBuffers<T> &b)
             LongPlan p = long_plan(mh, o.nh, c.cnew, Prec<T>::bytes, kSketch, h->num_cu);
             la.c = c.cnew;
             la.Ypart = b.Ypart;
-            CK(launch_long<T>(p, kSketch, la, s));
-            CK(launch_reduce<T>(b.Ypart, (int64_t)mh * c.cnew, p.grid, b.Y, s));
+            CKT(FRSVT_K_SKETCH, launch_long<T>(p, kSketch, la, s));
+            CKT(FRSVT_K_REDUCE, launch_reduce<T>(b.Ypart, (int64_t)mh * c.cnew, p.grid, b.Y, s));
         }
-        CK(launch_small_orth<T>(mh, c.Qt, c.ldqt, c.rp, b.Y, mh, c.cnew, b.Q, mh, c.seed,
+        CKT(FRSVT_K_ORTH, launch_small_orth<T>(mh, c.Qt, c.ldqt, c.rp, b.Y, mh, c.cnew, b.Q, mh, c.seed,
                                 c.counter, oflags, s));
     } else {
         if (c.rp > 0)
             CK(hipMemcpy2DAsync(b.Q, mh * sizeof(T), c.Qt, c.ldqt * sizeof(T), mh * sizeof(T),
                                 c.rp, hipMemcpyDeviceToDevice, s));
         if (c.cnew > 0) {
-            CK(launch_omega<T>(o.nh, c.cnew, c.seed, c.counter, b.Om, o.nh, s));
+            CKT(FRSVT_K_OTHER, launch_omega<T>(o.nh, c.cnew, c.seed, c.counter, b.Om, o.nh, s));
             if ((rc = ahat_times<T>(h, c, b.Om, o.nh, c.cnew, b.Q + (size_t)c.rp * mh, b.gpart_t)))
                 return rc;
         }
@@ -320,9 +370,9 @@ int run_core(frsvt_context *h, Core<T> &c, CoreBuffers<T> &b)
             la.Q = b.Q;
             la.ldq = mh;
             la.Ypart = b.Ypart;
-            CK(launch_long<T>(p, kPower, la, s));
-            CK(launch_reduce<T>(b.Ypart, (int64_t)mh * l, p.grid, b.Y, s));
-            CK(launch_small_orth<T>(mh, (const T *)nullptr, mh, 0, b.Y, mh, l, b.Q, mh, c.seed,
+            CKT(FRSVT_K_POWER, launch_long<T>(p, kPower, la, s));
+            CKT(FRSVT_K_REDUCE, launch_reduce<T>(b.Ypart, (int64_t)mh * l, p.grid, b.Y, s));
+            CKT(FRSVT_K_ORTH, launch_small_orth<T>(mh, (const T *)nullptr, mh, 0, b.Y, mh, l, b.Q, mh, c.seed,
                                     ctr2, oflags, s));
         } else {
             if ((rc = ahat_t_times<T>(h, c, b.Q, mh, l, b.Z, b.gpart_t))) return rc;
@@ -340,8 +390,8 @@ int run_core(frsvt_context *h, Core<T> &c, CoreBuffers<T> &b)
         la.Z = b.Bt;
         la.ldz = o.nh;
         la.Gpart = b.Gpart;
-        CK(launch_long<T>(p, kProject, la, s));
-        CK(launch_reduce<double>(b.Gpart, (int64_t)l * l, p.grid, b.G, s));
+        CKT(FRSVT_K_PROJECT, launch_long<T>(p, kProject, la, s));
+        CKT(FRSVT_K_REDUCE, launch_reduce<double>(b.Gpart, (int64_t)l * l, p.grid, b.G, s));
     } else {
         if ((rc = ahat_t_times<T>(h, c, b.Q, mh, l, b.Bt, b.gpart_t))) return rc;
         if ((rc = gram<T>(h, o.nh, l, b.Bt, o.nh, b.G, b.gpart_d))) return rc;
@@ -350,16 +400,16 @@ int run_core(frsvt_context *h, Core<T> &c, CoreBuffers<T> &b)
     // Alg. 1 lines 17-19: small SVD, thresholds, reconstruction factors
     SmallSvdOut so{b.sigma, b.U, b.Mm, c.status};
     const int fuse = small_svd_fuse_q_ok(mh, l) ? 1 : 0;
-    CK(launch_small_svd<T>(l, b.G, c.tau, c.w, b.Q, mh, mh, b.QM, mh, c.Qout, c.ldqo, so, b.jwork,
+    CKT(FRSVT_K_SMALL_SVD, launch_small_svd<T>(l, b.G, c.tau, c.w, b.Q, mh, mh, b.QM, mh, c.Qout, c.ldqo, so, b.jwork,
                            fuse, s));
     if (!fuse) {
         // QM = Q Mm, Qout = Q U (double small factors cast through a copy)
         T *Mt = b.Qtmp;  // reuse: l x l in storage precision needs l*l <= mh*l
-        CK(launch_cast<T>(l, l, b.Mm, 1, l, Mt, l, s));
-        CK((launch_gemm<T, T, T>(mh, l, l, b.Q, 1, mh, Mt, 1, l, b.QM, 1, mh, 1, b.gpart_t, s)));
+        CKT(FRSVT_K_OTHER, launch_cast<T>(l, l, b.Mm, 1, l, Mt, l, s));
+        CKT(FRSVT_K_GEMM, (launch_gemm<T, T, T>(mh, l, l, b.Q, 1, mh, Mt, 1, l, b.QM, 1, mh, 1, b.gpart_t, s)));
         if (c.Qout) {
-            CK(launch_cast<T>(l, l, b.U, 1, l, Mt, l, s));
-            CK((launch_gemm<T, T, T>(mh, l, l, b.Q, 1, mh, Mt, 1, l, c.Qout, 1, c.ldqo, 1,
+            CKT(FRSVT_K_OTHER, launch_cast<T>(l, l, b.U, 1, l, Mt, l, s));
+            CKT(FRSVT_K_GEMM, (launch_gemm<T, T, T>(mh, l, l, b.Q, 1, mh, Mt, 1, l, c.Qout, 1, c.ldqo, 1,
                                      b.gpart_t, s)));
         }
     }
@@ -391,10 +441,10 @@ int write_x(frsvt_context *h, const Core<T> &c, T *X, int64_t ldx, T *part)
         }
         ra.X = X;
         ra.ldx = ldx;
-        CK(launch_recon<T>(kRecon, ra, nullptr, h->stream));
+        CKT(FRSVT_K_RECON, launch_recon<T>(kRecon, ra, nullptr, h->stream));
     } else {
         const int64_t scm = o.trans ? ldx : 1, scn = o.trans ? 1 : ldx;
-        CK((launch_gemm<T, T, T>(o.mh, o.nh, c.l, c.QM, 1, o.mh, c.Bt, o.nh, 1, X, scm, scn, 1,
+        CKT(FRSVT_K_GEMM, (launch_gemm<T, T, T>(o.mh, o.nh, c.l, c.QM, 1, o.mh, c.Bt, o.nh, 1, X, scm, scn, 1,
                                  part, h->stream)));
     }
     return FRSVT_OK;
@@ -416,18 +466,18 @@ int exact_factors(frsvt_context *h, const T *A, int64_t lda, const Orient &o, do
     T *Mt = cv.take<T>((size_t)mh * mh);
     if (!cv.base) return FRSVT_OK;
     if (std::is_same<T, double>::value) {
-        CK((launch_gemm<double, double, double>(mh, mh, o.nh, (const double *)A, o.si, o.sk,
+        CKT(FRSVT_K_GEMM, (launch_gemm<double, double, double>(mh, mh, o.nh, (const double *)A, o.si, o.sk,
                                                 (const double *)A, o.sk, o.si, G, 1, mh, sk, gp,
                                                 h->stream)));
     } else {
-        CK((launch_gemm<float, double, double>(mh, mh, o.nh, (const float *)A, o.si, o.sk,
+        CKT(FRSVT_K_GEMM, (launch_gemm<float, double, double>(mh, mh, o.nh, (const float *)A, o.si, o.sk,
                                                (const float *)A, o.sk, o.si, G, 1, mh, sk, gp,
                                                h->stream)));
     }
     SmallSvdOut so{sig, U, Mm, h->dstatus};
-    CK(launch_small_svd<T>(mh, G, tau, w, (const T *)nullptr, 0, mh, (T *)nullptr, 0,
+    CKT(FRSVT_K_SMALL_SVD, launch_small_svd<T>(mh, G, tau, w, (const T *)nullptr, 0, mh, (T *)nullptr, 0,
                            (T *)nullptr, 0, so, jw, 0, h->stream));
-    CK(launch_cast<T>(mh, mh, Mm, 1, mh, Mt, mh, h->stream));
+    CKT(FRSVT_K_OTHER, launch_cast<T>(mh, mh, Mm, 1, mh, Mt, mh, h->stream));
     *Mm_out = Mm;
     *Mt_out = Mt;
     return FRSVT_OK;
@@ -447,7 +497,7 @@ int exact_svt_impl(frsvt_context *h, int64_t m, int64_t n, const T *A, int64_t l
     Carver cv(h->ws);
     if ((rc = exact_factors<T>(h, A, lda, o, tau, w, cv, &Mm, &Mt))) return rc;
     const int64_t scm = o.trans ? ldx : 1, scn = o.trans ? 1 : ldx;
-    CK((launch_gemm<T, T, T>(o.mh, o.nh, o.mh, Mt, 1, o.mh, A, o.si, o.sk, X, scm, scn, 1,
+    CKT(FRSVT_K_GEMM, (launch_gemm<T, T, T>(o.mh, o.nh, o.mh, Mt, 1, o.mh, A, o.si, o.sk, X, scm, scn, 1,
                              (T *)nullptr, h->stream)));
     if (rank) {
         CK(hipMemcpyAsync(h->pinned, h->dstatus, 4 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
@@ -525,15 +575,15 @@ int spectral_norm(frsvt_context *h, const T *A, int64_t lda, const Orient &o, do
     double *gp = cv.take<double>((size_t)sk * mh * mh);
     double *wk = cv.take<double>((size_t)2 * mh + 2);
     if (std::is_same<T, double>::value) {
-        CK((launch_gemm<double, double, double>(mh, mh, o.nh, (const double *)A, o.si, o.sk,
+        CKT(FRSVT_K_GEMM, (launch_gemm<double, double, double>(mh, mh, o.nh, (const double *)A, o.si, o.sk,
                                                 (const double *)A, o.sk, o.si, G, 1, mh, sk, gp,
                                                 h->stream)));
     } else {
-        CK((launch_gemm<float, double, double>(mh, mh, o.nh, (const float *)A, o.si, o.sk,
+        CKT(FRSVT_K_GEMM, (launch_gemm<float, double, double>(mh, mh, o.nh, (const float *)A, o.si, o.sk,
                                                (const float *)A, o.sk, o.si, G, 1, mh, sk, gp,
                                                h->stream)));
     }
-    CK(launch_power_eig(mh, G, wk, h->dscalars, h->stream));
+    CKT(FRSVT_K_OTHER, launch_power_eig(mh, G, wk, h->dscalars, h->stream));
     CK(hipMemcpyAsync(h->pinned, h->dscalars, sizeof(double), hipMemcpyDeviceToHost, h->stream));
     CK(hipStreamSynchronize(h->stream));
     *out = std::sqrt(std::max(0.0, ((double *)h->pinned)[0]));
@@ -552,10 +602,10 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
 
     // non-finite input
     CK(hipMemsetAsync(h->dstatus + 16, 0, sizeof(int), s));
-    CK(launch_finite_check<T>(m, n, O, ldo, h->dstatus + 16, s));
+    CKT(FRSVT_K_OTHER, launch_finite_check<T>(m, n, O, ldo, h->dstatus + 16, s));
     // ||O||_F and ||O||_inf
     int nparts = 0;
-    CK(launch_norms<T>(m, n, O, ldo, h->dscalars + 16, &nparts, s));
+    CKT(FRSVT_K_OTHER, launch_norms<T>(m, n, O, ldo, h->dscalars + 16, &nparts, s));
     CK(hipMemcpyAsync(h->pinned, h->dstatus + 16, sizeof(int), hipMemcpyDeviceToHost, s));
     CK(hipMemcpyAsync((char *)h->pinned + 64, h->dscalars + 16, 2 * nparts * sizeof(double),
                       hipMemcpyDeviceToHost, s));
@@ -619,7 +669,7 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
 
     T *Ybuf[2] = {L, S};
     const int64_t ldyb[2] = {ldl, lds};
-    CK(launch_rpca_init<T>(m, n, O, ldo, 1.0 / J, 1.0 / mu, Ybuf[0], ldyb[0], A, m, s));
+    CKT(FRSVT_K_OTHER, launch_rpca_init<T>(m, n, O, ldo, 1.0 / J, 1.0 / mu, Ybuf[0], ldyb[0], A, m, s));
 
     auto t0 = std::chrono::steady_clock::now();
     int r_prev = -1;
@@ -673,7 +723,7 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
             if (!recon_ok(c.l)) {
                 // wide basis: materialise L = (QM) B, then the epilogue reads it
                 const int64_t scm = o.trans ? m : 1, scn = o.trans ? 1 : m;
-                CK((launch_gemm<T, T, T>(o.mh, o.nh, c.l, c.QM, 1, o.mh, c.Bt, o.nh, 1, Lx, scm,
+                CKT(FRSVT_K_GEMM, (launch_gemm<T, T, T>(o.mh, o.nh, c.l, c.QM, 1, o.mh, c.Bt, o.nh, 1, Lx, scm,
                                          scn, 1, (T *)nullptr, s)));
                 ra.c = 0;
                 ra.Lin = Lx;
@@ -688,7 +738,7 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
                 return rc;
             const Orient oa = orient(m, n, m);
             const int64_t scm = oa.trans ? m : 1, scn = oa.trans ? 1 : m;
-            CK((launch_gemm<T, T, T>(oa.mh, oa.nh, oa.mh, Mt, 1, oa.mh, A, oa.si, oa.sk, Lx, scm,
+            CKT(FRSVT_K_GEMM, (launch_gemm<T, T, T>(oa.mh, oa.nh, oa.mh, Mt, 1, oa.mh, A, oa.si, oa.sk, Lx, scm,
                                      scn, 1, (T *)nullptr, s)));
             ra.c = 0;
             ra.Lin = Lx;
@@ -709,8 +759,8 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
         ra.lam = lambda;
         ra.zpart = zp;
         int nz = 0;
-        CK(launch_recon<T>(kEpi, ra, &nz, s));
-        CK(launch_reduce<double>(zp, 1, nz, zsum, s));
+        CKT(FRSVT_K_EPILOGUE, launch_recon<T>(kEpi, ra, &nz, s));
+        CKT(FRSVT_K_REDUCE, launch_reduce<double>(zp, 1, nz, zsum, s));
         CK(hipMemcpyAsync(hst, h->dstatus, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
         CK(hipMemcpyAsync(hst + 8, zsum, sizeof(double), hipMemcpyDeviceToHost, s));
         CK(hipStreamSynchronize(s));
@@ -766,7 +816,7 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
         ra.mu = mu_last;
         ra.mu_next = mu_last;
         ra.lam = lambda;
-        CK(launch_recon<T>(kFinal, ra, nullptr, s));
+        CKT(FRSVT_K_OTHER, launch_recon<T>(kFinal, ra, nullptr, s));
         CK(hipStreamSynchronize(s));
     }
     auto t1 = std::chrono::steady_clock::now();
@@ -826,6 +876,11 @@ int frsvt_destroy(frsvt_handle h)
 {
     if (!h) return -1;
     (void)hipStreamSynchronize(h->stream);
+    for (auto &r : h->recs) {
+        (void)hipEventDestroy(r.second.first);
+        (void)hipEventDestroy(r.second.second);
+    }
+    for (auto e : h->pool) (void)hipEventDestroy(e);
     if (h->ws) (void)hipFree(h->ws);
     if (h->dstatus) (void)hipFree(h->dstatus);
     if (h->dscalars) (void)hipFree(h->dscalars);
@@ -861,6 +916,54 @@ const char *frsvt_status_string(int status)
 const char *frsvt_last_error(frsvt_handle h) { return h ? h->last_error : "invalid handle"; }
 
 int64_t frsvt_workspace_bytes(frsvt_handle h) { return h ? (int64_t)h->ws_bytes : -1; }
+
+static void trace_flush(frsvt_context *h)
+{
+    if (h->recs.empty()) return;
+    (void)hipStreamSynchronize(h->stream);
+    for (auto &r : h->recs) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, r.second.first, r.second.second) == hipSuccess &&
+            r.first >= 0 && r.first < FRSVT_K_COUNT) {
+            h->trace_ms[r.first] += ms;
+            h->trace_n[r.first] += 1;
+        }
+        h->pool.push_back(r.second.first);
+        h->pool.push_back(r.second.second);
+    }
+    h->recs.clear();
+}
+
+int frsvt_trace_enable(frsvt_handle h, int enable)
+{
+    if (!h) return -1;
+    trace_flush(h);
+    if (enable) {
+        for (int k = 0; k < FRSVT_K_COUNT; ++k) {
+            h->trace_ms[k] = 0.0;
+            h->trace_n[k] = 0;
+        }
+    }
+    h->tracing = enable != 0;
+    return FRSVT_OK;
+}
+
+int frsvt_trace_read(frsvt_handle h, int kernel_class, double *total_ms, int64_t *launches)
+{
+    if (!h) return -1;
+    if (kernel_class < 0 || kernel_class >= FRSVT_K_COUNT) return -2;
+    trace_flush(h);
+    if (total_ms) *total_ms = h->trace_ms[kernel_class];
+    if (launches) *launches = h->trace_n[kernel_class];
+    return FRSVT_OK;
+}
+
+const char *frsvt_trace_name(int k)
+{
+    static const char *names[FRSVT_K_COUNT] = {"sketch", "power", "project", "reduce", "orth",
+                                                "small_svd", "recon", "epilogue", "gemm", "other"};
+    return (k >= 0 && k < FRSVT_K_COUNT) ? names[k] : "unknown";
+}
 
 void frsvt_rpca_default_opts(frsvt_rpca_opts *op)
 {
