@@ -9,6 +9,8 @@
 namespace frk {
 
 constexpr int kWave = 64;
+constexpr int kThreads = 256;
+constexpr double kU = 1.1102230246251565e-16;  // unit roundoff of double
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two

@@ -1,0 +1,471 @@
+// small_dense.hip -- one-workgroup dense kernels: CholeskyQR
+// re-orthonormalisation of the sampled basis (Alg. 1 lines 6, 10-11, 14) and
+// the small SVD of B with thresholds and reconstruction factors (lines 16-19).
+#include "block_dense.h"
+#include "device_common.h"
+#include "internal.h"
+
+#include <algorithm>
+
+namespace frk {
+
+// ===========================================================================
+// Orthonormalisation of W = [Qt, Y] (mh x l, l = rp + c), all in LDS:
+//   1. CGS2: Y <- Y - Qt (Qt^T Y), twice (the partial orthogonalisation of
+//      range propagation, Alg. 1 line 10).
+//   2. Column equilibration (only the span matters).
+//   3. Fast path: CholeskyQR2.  The first Cholesky must see no null pivot
+//      and a smallest pivot ratio >= 1e-8; the second must have every pivot
+//      within 1e-6 of 1 (W^T W ~ I).  Otherwise:
+//   4. Fallback from the saved equilibrated W: shifted CholeskyQR with
+//      shift 11 (mh l + l(l+1)) u trace(W^T W) (shifted CholeskyQR3 of
+//      Fukaya et al.), then CholeskyQR passes in which numerically null
+//      columns are replaced by fresh Gaussian directions (any orthonormal
+//      completion leaves the thresholded result unchanged), then a final
+//      CholeskyQR pass.
+// flags: [0] 1 = fast path, 2 = fallback; [1] refilled columns; [2] final
+// pass failures.
+// ===========================================================================
+bool small_orth_ok(int mh, int l)
+{
+    return l >= 1 && l <= 64 && (size_t)(mh | 1) * l * 16 + (size_t)l * l * 16 <= 96 * 1024;
+}
+
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT) k_small_orth(int mh, const T *Qt, int64_t ldqt, int rp,
+                                                   const T *Y, int64_t ldy, int c, T *Q,
+                                                   int64_t ldq, uint64_t seed, uint64_t counter,
+                                                   int *flags)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int l = rp + c;
+    const int mhp = mh | 1;
+    double *W = reinterpret_cast<double *>(smem_raw);
+    double *W0 = W + (size_t)l * mhp;
+    double *G = W0 + (size_t)l * mhp;
+    double *R = G + (size_t)l * l;
+    __shared__ int null_flags[64];
+    __shared__ double scal[64];
+    const int tid = threadIdx.x;
+    const int lane = tid % kWave, wave = tid / kWave;
+    constexpr int nw = NT / kWave;
+
+    for (int idx = tid; idx < mh * rp; idx += NT) {
+        const int i = idx % mh, j = idx / mh;
+        W[(size_t)j * mhp + i] = (double)Qt[i + (int64_t)j * ldqt];
+    }
+    for (int idx = tid; idx < mh * c; idx += NT) {
+        const int i = idx % mh, j = idx / mh;
+        W[(size_t)(rp + j) * mhp + i] = (double)Y[i + (int64_t)j * ldy];
+    }
+    __syncthreads();
+
+    // 1. CGS2 against the propagated basis
+    if (rp > 0 && c > 0) {
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int p = wave; p < rp * c; p += nw) {
+                const int t = p % rp, j = p / rp;
+                const double *qa = W + (size_t)t * mhp, *ya = W + (size_t)(rp + j) * mhp;
+                double s = 0.0;
+                for (int i = lane; i < mh; i += kWave) s += qa[i] * ya[i];
+                s = wave_sum(s);
+                if (lane == 0) G[t * c + j] = s;
+            }
+            __syncthreads();
+            for (int idx = tid; idx < mh * c; idx += NT) {
+                const int i = idx % mh, j = idx / mh;
+                double v = W[(size_t)(rp + j) * mhp + i];
+                for (int t = 0; t < rp; ++t) v -= W[(size_t)t * mhp + i] * G[t * c + j];
+                W[(size_t)(rp + j) * mhp + i] = v;
+            }
+            __syncthreads();
+        }
+    }
+    // 2. column equilibration, and a saved copy for the fallback
+    for (int j = wave; j < l; j += nw) {
+        const double *wj = W + (size_t)j * mhp;
+        double s = 0.0;
+        for (int i = lane; i < mh; i += kWave) s += wj[i] * wj[i];
+        s = wave_sum(s);
+        if (lane == 0) scal[j] = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < mh * l; idx += NT) {
+        const int i = idx % mh, j = idx / mh;
+        const double v = W[(size_t)j * mhp + i] * scal[j];
+        W[(size_t)j * mhp + i] = v;
+        W0[(size_t)j * mhp + i] = v;
+    }
+    __syncthreads();
+
+    // 3. fast path: CholeskyQR2
+    bool fast = true;
+    {
+        block_gram(W, mh, mhp, l, G);
+        double mx = 0.0;
+        for (int j = 0; j < l; ++j) mx = fmax(mx, G[j * l + j]);
+        const CholInfo c1 = block_chol(G, l, 0.0, 16.0 * l * kU * fmax(mx, 1e-300), R, nullptr);
+        if (c1.nnull > 0 || c1.min_ratio < 1e-8) fast = false;
+        if (fast) {
+            block_trsm(W, mh, mhp, l, R);
+            block_gram(W, mh, mhp, l, G);
+            const CholInfo c2 = block_chol(G, l, 0.0, 0.5, R, nullptr);
+            bool near_one = c2.nnull == 0;
+            for (int j = 0; j < l && near_one; ++j) near_one = fabs(R[j * l + j] - 1.0) <= 1e-6;
+            if (near_one) block_trsm(W, mh, mhp, l, R);
+            else fast = false;
+        }
+    }
+    int refilled = 0, final_fail = 0;
+    if (!fast) {
+        // 4. fallback from the saved equilibrated basis
+        for (int idx = tid; idx < mh * l; idx += NT) {
+            const int i = idx % mh, j = idx / mh;
+            W[(size_t)j * mhp + i] = W0[(size_t)j * mhp + i];
+        }
+        __syncthreads();
+        block_gram(W, mh, mhp, l, G);
+        double tr = 0.0;
+        for (int j = 0; j < l; ++j) tr += G[j * l + j];
+        double shift = 11.0 * ((double)mh * l + (double)l * (l + 1)) * kU * tr;
+        if (!(shift > 0.0)) shift = kU;
+        block_chol(G, l, shift, 0.0, R, nullptr);
+        block_trsm(W, mh, mhp, l, R);
+        for (int attempt = 0; attempt < 4; ++attempt) {
+            block_gram(W, mh, mhp, l, G);
+            double mxd = 0.0;
+            for (int j = 0; j < l; ++j) mxd = fmax(mxd, G[j * l + j]);
+            const CholInfo ci = block_chol(G, l, 0.0, 16.0 * l * kU * fmax(mxd, 1e-300), R, null_flags);
+            if (ci.nnull == 0 || attempt == 3) break;
+            for (int j = 0; j < l; ++j) {
+                if (!null_flags[j]) continue;
+                for (int i = tid; i < mh; i += NT) {
+                    double z0, z1;
+                    gaussian_pair(seed, counter, (uint32_t)i, kRefillTag | (uint32_t)(attempt * 64 + j), z0, z1);
+                    W[(size_t)j * mhp + i] = z0;
+                }
+            }
+            __syncthreads();
+            for (int j = wave; j < l; j += nw) {
+                if (!null_flags[j]) continue;
+                double *wj = W + (size_t)j * mhp;
+                double s = 0.0;
+                for (int i = lane; i < mh; i += kWave) s += wj[i] * wj[i];
+                s = wave_sum(s);
+                const double inv = 1.0 / sqrt(s);
+                for (int i = lane; i < mh; i += kWave) wj[i] *= inv;
+            }
+            __syncthreads();
+            refilled += ci.nnull;
+        }
+        block_trsm(W, mh, mhp, l, R);
+        block_gram(W, mh, mhp, l, G);
+        final_fail = block_chol(G, l, 0.0, 0.0, R, nullptr).nnull;
+        block_trsm(W, mh, mhp, l, R);
+    }
+
+    for (int idx = tid; idx < mh * l; idx += NT) {
+        const int i = idx % mh, j = idx / mh;
+        Q[i + (int64_t)j * ldq] = (T)W[(size_t)j * mhp + i];
+    }
+    if (tid == 0 && flags) {
+        flags[0] = fast ? 1 : 2;
+        flags[1] = refilled;
+        flags[2] = final_fail;
+    }
+}
+
+template <typename T>
+hipError_t launch_small_orth(int mh, const T *Qt, int64_t ldqt, int rp, const T *Y, int64_t ldy,
+                             int c, T *Q, int64_t ldq, uint64_t seed, uint64_t counter, int *flags,
+                             hipStream_t s)
+{
+    const int l = rp + c;
+    if (!small_orth_ok(mh, l)) return hipErrorInvalidValue;
+    const size_t lds = (2 * (size_t)l * (mh | 1) + 2 * (size_t)l * l) * sizeof(double);
+    hipLaunchKernelGGL((k_small_orth<T, 256>), dim3(1), dim3(256), lds, s, mh, Qt, ldqt, rp, Y,
+                       ldy, c, Q, ldq, seed, counter, flags);
+    return hipGetLastError();
+}
+template hipError_t launch_small_orth<double>(int, const double *, int64_t, int, const double *, int64_t, int, double *, int64_t, uint64_t, uint64_t, int *, hipStream_t);
+template hipError_t launch_small_orth<float>(int, const float *, int64_t, int, const float *, int64_t, int, float *, int64_t, uint64_t, uint64_t, int *, hipStream_t);
+
+// ===========================================================================
+// Small SVD of B from G = B B^T (Alg. 1 lines 16-18 reformulated):
+//   G = R^T R (semidefinite Cholesky), one-sided Jacobi on M = R^T: M V = W S.
+//   B = R^T H^T has left singular vectors U_B = W S^{-1} (the normalised
+//   columns of the converged M) and singular values S.
+// Pairs follow the circle method (n - 1 rounds of n/2 disjoint pairs).  A
+// pair is rotated when |m_p.m_q| > rows u' sqrt(|m_p|^2 |m_q|^2).
+//
+// Two Jacobi engines:
+//   l <= 16: one wavefront; four groups of 16 lanes each rotate one pair,
+//            lane = row, with 16-lane shuffle reductions (no barriers
+//            between the rotations of a step beyond the wavefront's own).
+//   l > 16 : wavefront per pair, lanes over rows, block barrier per round.
+// ===========================================================================
+bool small_svd_fuse_q_ok(int mh, int l) { return (int64_t)mh * l * l <= (int64_t)4 << 20; }
+
+__device__ inline void circle_pair(int n2, int round, int t, int &p, int &q)
+{
+    if (t == 0) {
+        p = n2 - 1;
+        q = round;
+    } else {
+        p = (round + t) % (n2 - 1);
+        q = (round - t + n2 - 1) % (n2 - 1);
+    }
+    if (p > q) {
+        const int tmp = p;
+        p = q;
+        q = tmp;
+    }
+}
+
+__device__ inline void jacobi_rotation(double al, double be, double ga, double &cs, double &sn)
+{
+    const double zeta = (be - al) / (2.0 * ga);
+    const double t1 = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
+    cs = 1.0 / sqrt(1.0 + t1 * t1);
+    sn = cs * t1;
+}
+
+// One wavefront, l <= 16.  M column-major with ld = l.
+__device__ int jacobi_wave16(double *M, int l, int max_sweeps)
+{
+    const int lane = threadIdx.x % kWave;
+    const int g = lane / 16, row = lane % 16;
+    const int n2 = l + (l & 1);
+    const int npairs = n2 / 2;
+    const double tol = (double)l * 2.0 * kU;
+    int sweep;
+    for (sweep = 1; sweep <= max_sweeps; ++sweep) {
+        int rot = 0;
+        for (int round = 0; round < n2 - 1; ++round) {
+            for (int t0 = 0; t0 < npairs; t0 += 4) {
+                const int t = t0 + g;
+                int p = 0, q = 0;
+                bool live = false;
+                if (t < npairs) {
+                    circle_pair(n2, round, t, p, q);
+                    live = q < l;
+                }
+                double x = 0.0, y = 0.0;
+                if (live && row < l) {
+                    x = M[p * l + row];
+                    y = M[q * l + row];
+                }
+                double al = x * x, be = y * y, ga = x * y;
+#pragma unroll
+                for (int off = 8; off > 0; off >>= 1) {
+                    al += __shfl_xor(al, off, 16);
+                    be += __shfl_xor(be, off, 16);
+                    ga += __shfl_xor(ga, off, 16);
+                }
+                const bool doit = live && fabs(ga) > tol * sqrt(al * be);
+                if (doit) {
+                    double cs, sn;
+                    jacobi_rotation(al, be, ga, cs, sn);
+                    if (row < l) {
+                        M[p * l + row] = cs * x - sn * y;
+                        M[q * l + row] = sn * x + cs * y;
+                    }
+                }
+                rot |= __any(doit) ? 1 : 0;
+                __syncthreads();
+            }
+        }
+        if (!rot) break;
+    }
+    return sweep;
+}
+
+// Block of NT threads, any l; M at a generic (LDS or global) address.
+template <int NT>
+__device__ int jacobi_block(double *M, int rows, int ld, int n, int max_sweeps, int *sh_rot)
+{
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    constexpr int nw = NT / kWave;
+    const int n2 = n + (n & 1);
+    const double tol = (double)(rows > 1 ? rows : 1) * 2.0 * kU;
+    int sweep;
+    for (sweep = 1; sweep <= max_sweeps; ++sweep) {
+        if (threadIdx.x == 0) *sh_rot = 0;
+        __syncthreads();
+        for (int round = 0; round < n2 - 1; ++round) {
+            for (int t = wave; t < n2 / 2; t += nw) {
+                int p, q;
+                circle_pair(n2, round, t, p, q);
+                if (q >= n) continue;
+                double *mp = M + (size_t)p * ld, *mq = M + (size_t)q * ld;
+                double al = 0.0, be = 0.0, ga = 0.0;
+                for (int i = lane; i < rows; i += kWave) {
+                    const double x = mp[i], y = mq[i];
+                    al += x * x;
+                    be += y * y;
+                    ga += x * y;
+                }
+                al = wave_sum(al);
+                be = wave_sum(be);
+                ga = wave_sum(ga);
+                if (fabs(ga) > tol * sqrt(al * be)) {
+                    double cs, sn;
+                    jacobi_rotation(al, be, ga, cs, sn);
+                    for (int i = lane; i < rows; i += kWave) {
+                        const double x = mp[i], y = mq[i];
+                        mp[i] = cs * x - sn * y;
+                        mq[i] = sn * x + cs * y;
+                    }
+                    if (lane == 0) *sh_rot = 1;
+                }
+            }
+            __syncthreads();
+        }
+        const int rot = *sh_rot;
+        __syncthreads();
+        if (!rot) break;
+    }
+    return sweep;
+}
+
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT) k_small_svd(int l, const double *Gin, double tau,
+                                                  const double *w, const T *Q, int64_t ldq, int mh,
+                                                  T *QM, int64_t ldqm, T *Qout, int64_t ldqo,
+                                                  SmallSvdOut out, double *work, int fuse_q)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    constexpr int kLdsMax = 80;
+    double *M = (l <= kLdsMax) ? reinterpret_cast<double *>(smem_raw) : work;
+    __shared__ int sh_rot;
+    __shared__ int order[1024];
+    __shared__ double sig[1024];
+    __shared__ double coef[1024];
+    const int tid = threadIdx.x;
+    const int lane = tid % kWave, wave = tid / kWave;
+    constexpr int nw = NT / kWave;
+
+    // Row-major in-place semidefinite Cholesky: M[j*l + k] = R(j, k), k >= j.
+    // Read column-major, column j of M is row j of R, i.e. M = R^T.
+    for (int idx = tid; idx < l * l; idx += NT) M[idx] = Gin[idx];
+    __syncthreads();
+    double maxdiag = 0.0;
+    for (int j = 0; j < l; ++j) maxdiag = fmax(maxdiag, M[j * l + j]);
+    const double ptol = 4.0 * l * kU * maxdiag;
+    for (int j = 0; j < l; ++j) {
+        double d = M[j * l + j];
+        for (int t = 0; t < j; ++t) d -= M[t * l + j] * M[t * l + j];
+        const double piv = d > ptol ? sqrt(d) : 0.0;
+        __syncthreads();   // every thread has read row j before it changes
+        if (tid == 0) M[j * l + j] = piv;
+        for (int k = j + 1 + tid; k < l; k += NT) {
+            double v = 0.0;
+            if (piv > 0.0) {
+                v = M[j * l + k];
+                for (int t = 0; t < j; ++t) v -= M[t * l + j] * M[t * l + k];
+                v /= piv;
+            }
+            M[j * l + k] = v;
+        }
+        __syncthreads();
+    }
+    for (int idx = tid; idx < l * l; idx += NT) {
+        const int j = idx / l, k = idx % l;
+        if (k < j) M[idx] = 0.0;
+    }
+    __syncthreads();
+
+    int sweeps;
+    if (NT == kWave && l <= 16) sweeps = jacobi_wave16(M, l, 60);
+    else sweeps = jacobi_block<NT>(M, l, l, l, 60, &sh_rot);
+    __syncthreads();
+
+    for (int j = wave; j < l; j += nw) {
+        const double *mj = M + (size_t)j * l;
+        double s = 0.0;
+        for (int i = lane; i < l; i += kWave) s += mj[i] * mj[i];
+        s = wave_sum(s);
+        if (lane == 0) sig[j] = sqrt(s);
+    }
+    __syncthreads();
+    __shared__ int rank;
+    if (tid == 0) {
+        for (int j = 0; j < l; ++j) order[j] = j;
+        for (int a = 0; a < l; ++a) {
+            int best = a;
+            for (int b = a + 1; b < l; ++b)
+                if (sig[order[b]] > sig[order[best]]) best = b;
+            const int tmp = order[a];
+            order[a] = order[best];
+            order[best] = tmp;
+        }
+        int r = 0;
+        for (int a = 0; a < l; ++a) {
+            const double sa = sig[order[a]];
+            const double th = w ? w[a] : tau;
+            const double f = sa - th;
+            coef[a] = (f > 0.0 && sa > 0.0) ? f / sa : 0.0;
+            if (f > 0.0) ++r;
+        }
+        rank = r;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < l * l; idx += NT) {
+        const int a = idx / l, i = idx % l;
+        const double sa = sig[order[a]];
+        out.U[i + (size_t)a * l] = sa > 0.0 ? M[(size_t)order[a] * l + i] / sa : 0.0;
+    }
+    for (int a = tid; a < l; a += NT) out.sigma[a] = sig[order[a]];
+    __syncthreads();
+    // Mm = sum_a coef_a u_a u_a^T
+    for (int idx = tid; idx < l * l; idx += NT) {
+        const int i = idx % l, j = idx / l;
+        double v = 0.0;
+        for (int a = 0; a < l; ++a)
+            if (coef[a] != 0.0) v += coef[a] * out.U[i + (size_t)a * l] * out.U[j + (size_t)a * l];
+        out.Mm[i + (size_t)j * l] = v;
+    }
+    if (tid == 0) {
+        out.status[0] = rank;
+        out.status[1] = sweeps;
+        out.status[2] = sweeps <= 60 ? 1 : 0;
+    }
+    __syncthreads();
+    if (fuse_q && Q) {
+        const int r = rank;
+        for (int idx = tid; idx < mh * l; idx += NT) {
+            const int i = idx % mh, j = idx / mh;
+            double v = 0.0;
+            for (int t = 0; t < l; ++t) v += (double)Q[i + (int64_t)t * ldq] * out.Mm[t + (size_t)j * l];
+            QM[i + (int64_t)j * ldqm] = (T)v;
+        }
+        if (Qout) {
+            for (int idx = tid; idx < mh * r; idx += NT) {
+                const int i = idx % mh, j = idx / mh;
+                double v = 0.0;
+                for (int t = 0; t < l; ++t) v += (double)Q[i + (int64_t)t * ldq] * out.U[t + (size_t)j * l];
+                Qout[i + (int64_t)j * ldqo] = (T)v;
+            }
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_small_svd(int l, const double *G, double tau, const double *w, const T *Q,
+                            int64_t ldq, int mh, T *QM, int64_t ldqm, T *Qout, int64_t ldqo,
+                            const SmallSvdOut &out, double *work, int fuse_q, hipStream_t s)
+{
+    if (l < 1 || l > 1024) return hipErrorInvalidValue;
+    const size_t lds = l <= 80 ? (size_t)l * l * sizeof(double) : 0;
+    if (l <= 16)
+        hipLaunchKernelGGL((k_small_svd<T, 64>), dim3(1), dim3(64), lds, s, l, G, tau, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, work, fuse_q);
+    else if (l <= 64)
+        hipLaunchKernelGGL((k_small_svd<T, 256>), dim3(1), dim3(256), lds, s, l, G, tau, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, work, fuse_q);
+    else
+        hipLaunchKernelGGL((k_small_svd<T, 1024>), dim3(1), dim3(1024), lds, s, l, G, tau, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, work, fuse_q);
+    return hipGetLastError();
+}
+template hipError_t launch_small_svd<double>(int, const double *, double, const double *, const double *, int64_t, int, double *, int64_t, double *, int64_t, const SmallSvdOut &, double *, int, hipStream_t);
+template hipError_t launch_small_svd<float>(int, const double *, double, const double *, const float *, int64_t, int, float *, int64_t, float *, int64_t, const SmallSvdOut &, double *, int, hipStream_t);
+
+}  // namespace frk

@@ -180,3 +180,35 @@ def test_rpca_small_matches_oracle(fr, orc, mode):
     assert _rel(res.S.cpu().numpy(), out["S"]) <= 1e-10
     assert res.converged
     assert np.linalg.norm(res.L.cpu().numpy() - Lgt) / np.linalg.norm(Lgt) < 1e-4
+
+
+def test_frsvt_video_shape_single_call(fr, orc):
+    """One FRSVT call at the full 76800 x 200 RPCA shape, in the launch
+    configuration of the RPCA loop (fresh sketch l = 20, q = 1)."""
+    from paper_1509_00296_amd import synth
+    _say("case frsvt f64 76800x200 l=20 q=1")
+    O, _, _ = synth.rpca(seed=0)
+    tau = 40.0
+    X, Qt, r = fr.frsvt(_gpu(O), tau, 15, 5, 1, seed=2024, counter=0)
+    Om = orc.gaussian_matrix(2024, 0, 76800, 20)
+    Xo, Qo, ro, _, _ = orc.frsvt(O, tau, 1, Om)
+    assert r == ro
+    assert _rel(X.cpu().numpy(), Xo) <= 1e-10
+
+
+def test_rpca_video_shape_matches_oracle(fr, orc):
+    """The full RPCA workload (76800 x 200, rank 3, 10 % outliers) through
+    the C ABI against the oracle's iALM with FRSVT + range propagation: same
+    iteration count and rank sequence, L and S within 1e-10."""
+    from paper_1509_00296_amd import synth
+    _say("case rpca f64 76800x200 (oracle run takes about a minute)")
+    O, Lgt, _ = synth.rpca(seed=0)
+    lam = 1.0 / np.sqrt(76800)
+    res = fr.rpca_ialm(_gpu(O), lam, use_frsvt=True, seed=2024)
+    out = orc.rpca_ialm(O, lam, mode="frsvt", p=5, q=1, seed=2024)
+    assert res.iters == out["iters"]
+    assert res.ranks == list(out["ranks"][:64])
+    assert _rel(res.L.cpu().numpy(), out["L"]) <= 1e-10
+    assert _rel(res.S.cpu().numpy(), out["S"]) <= 1e-10
+    # identical sparsity pattern of S
+    assert np.array_equal(res.S.cpu().numpy() != 0, out["S"] != 0)
