@@ -119,6 +119,14 @@ FRSVT_API int frsvt_trace_read(frsvt_handle handle, int kernel_class, double *to
 /* Name of a kernel class (static storage). */
 FRSVT_API const char *frsvt_trace_name(int kernel_class);
 
+/* Status words of the last thresholding step, copied to the host (waits for
+ * the stream): info[0] rank r, info[1] Jacobi sweeps of the small SVD,
+ * info[2] 1 when that Jacobi met its stopping test, info[4] 1 when the last
+ * re-orthonormalisation took the CholeskyQR2 fast path (2 = shifted
+ * fallback), info[5] columns refilled, info[6] final Cholesky failures.
+ * `count` words (at most 8) are written. */
+FRSVT_API int frsvt_last_info(frsvt_handle handle, int32_t *info, int count);
+
 /* ---------------------------------------------------------- exact operator */
 
 /*

@@ -958,6 +958,19 @@ int frsvt_trace_read(frsvt_handle h, int kernel_class, double *total_ms, int64_t
     return FRSVT_OK;
 }
 
+int frsvt_last_info(frsvt_handle h, int32_t *info, int count)
+{
+    if (!h) return -1;
+    if (!info) return -2;
+    if (count < 0 || count > 8) return -3;
+    if (count == 0) return FRSVT_OK;
+    hipError_t e = hipMemcpyAsync(h->pinned, h->dstatus, 8 * sizeof(int), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return fail(h, e, "frsvt_last_info");
+    memcpy(info, h->pinned, (size_t)count * sizeof(int32_t));
+    return FRSVT_OK;
+}
+
 const char *frsvt_trace_name(int k)
 {
     static const char *names[FRSVT_K_COUNT] = {"sketch", "power", "project", "reduce", "orth",
