@@ -192,6 +192,7 @@ struct Core {
     uint64_t seed, counter;
     T *Qout;             // mh x l (ld ldqo); may alias Qt
     int64_t ldqo;
+    bool sketch_ready;   // the sketch of this call is already in the buffers
     // results (workspace)
     int l;
     T *Q, *Bt, *QM;
@@ -310,6 +311,36 @@ int big_orth(frsvt_context *h, int64_t rows, int l, T *Y, int64_t ldy, CoreBuffe
     return FRSVT_OK;
 }
 
+// Alg. 1 lines 4-5 / 8-9 on the one-workgroup path: Y = Ahat Omega into b.Y.
+// It depends only on A, the Philox stream and the number of new samples.
+template <typename T>
+int sketch_stage(frsvt_context *h, const Core<T> &c, CoreBuffers<T> &b)
+{
+    const Orient &o = c.o;
+    const int mh = o.mh;
+    if (c.cnew <= 0) return FRSVT_OK;
+    LongArgs<T> la{};
+    la.A = c.A;
+    la.lda = c.lda;
+    la.trans = o.trans ? 1 : 0;
+    la.mh = mh;
+    la.nh = o.nh;
+    la.seed = c.seed;
+    la.counter = c.counter;
+    la.c = c.cnew;
+    la.Ypart = b.Ypart;
+    LongPlan p = long_plan(mh, o.nh, c.cnew, Prec<T>::bytes, kSketch, h->num_cu);
+    CKT(FRSVT_K_SKETCH, launch_long<T>(p, kSketch, la, h->stream));
+    CKT(FRSVT_K_REDUCE, launch_reduce<T>(b.Ypart, (int64_t)mh * c.cnew, p.grid, b.Y, h->stream));
+    return FRSVT_OK;
+}
+
+template <typename T>
+bool core_small(const Core<T> &c, int l)
+{
+    return long_path_ok(c.o.mh, l) && small_orth_ok(c.o.mh, l);
+}
+
 template <typename T>
 int run_core(frsvt_context *h, Core<T> &c, CoreBuffers<T> &b)
 {
@@ -340,13 +371,7 @@ int run_core(frsvt_context *h, Core<T> &c, CoreBuffers<T> &b)
 
     // Alg. 1 lines 3-12: sketch and initial basis
     if (small) {
-        if (c.cnew > 0) {
-            LongPlan p = long_plan(mh, o.nh, c.cnew, Prec<T>::bytes, kSketch, h->num_cu);
-            la.c = c.cnew;
-            la.Ypart = b.Ypart;
-            CKT(FRSVT_K_SKETCH, launch_long<T>(p, kSketch, la, s));
-            CKT(FRSVT_K_REDUCE, launch_reduce<T>(b.Ypart, (int64_t)mh * c.cnew, p.grid, b.Y, s));
-        }
+        if (!c.sketch_ready && (rc = sketch_stage<T>(h, c, b))) return rc;
         CKT(FRSVT_K_ORTH, launch_small_orth<T>(mh, c.Qt, c.ldqt, c.rp, b.Y, mh, c.cnew, b.Q, mh, c.seed,
                                 c.counter, oflags, s));
     } else {
@@ -673,6 +698,7 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
 
     auto t0 = std::chrono::steady_clock::now();
     int r_prev = -1;
+    int spec_cnew = 0;
     int it = 0;
     bool converged = false;
     double resid = 0.0, mu_last = mu;
@@ -704,6 +730,7 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
                 c.rp = 0;
                 c.cnew = r_prev < 0 ? l0 : std::min(op.p, mh);
             }
+            c.sketch_ready = spec_cnew > 0 && spec_cnew == c.cnew && core_small<T>(c, c.rp + c.cnew);
             c.Qout = Qt;
             c.ldqo = mh;
             c.status = h->dstatus;
@@ -761,6 +788,19 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
         int nz = 0;
         CKT(FRSVT_K_EPILOGUE, launch_recon<T>(kEpi, ra, &nz, s));
         CKT(FRSVT_K_REDUCE, launch_reduce<double>(zp, 1, nz, zsum, s));
+        // The next sketch needs only the next A and its Philox counter; it
+        // is enqueued before the host waits for this iteration's rank, with
+        // p new samples (the width of every later sketch unless r + p > mh).
+        spec_cnew = 0;
+        if (op.use_frsvt && it + 1 < op.max_iter) {
+            Core<T> cn = c;
+            cn.counter = (uint64_t)(it + 1);
+            cn.cnew = std::min(op.p, mh);
+            if (cn.cnew > 0 && long_path_ok(mh, cn.cnew)) {
+                if ((rc = sketch_stage<T>(h, cn, b))) return rc;
+                spec_cnew = cn.cnew;
+            }
+        }
         CK(hipMemcpyAsync(hst, h->dstatus, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
         CK(hipMemcpyAsync(hst + 8, zsum, sizeof(double), hipMemcpyDeviceToHost, s));
         CK(hipStreamSynchronize(s));

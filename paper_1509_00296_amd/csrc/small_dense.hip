@@ -204,7 +204,7 @@ template hipError_t launch_small_orth<float>(int, const float *, int64_t, int, c
 //            between the rotations of a step beyond the wavefront's own).
 //   l > 16 : wavefront per pair, lanes over rows, block barrier per round.
 // ===========================================================================
-bool small_svd_fuse_q_ok(int mh, int l) { return (int64_t)mh * l * l <= (int64_t)4 << 20; }
+bool small_svd_fuse_q_ok(int mh, int l) { return ((size_t)mh * l + 2 * (size_t)l * l) * sizeof(double) <= 96 * 1024; }
 
 __device__ inline void circle_pair(int n2, int round, int t, int &p, int &q)
 {
@@ -432,18 +432,32 @@ __global__ void __launch_bounds__(NT) k_small_svd(int l, const double *Gin, doub
     }
     __syncthreads();
     if (fuse_q && Q) {
+        // QM = Q Mm and Qout = Q U(:, 1:r), with Q, Mm and U staged in LDS
+        // (the Jacobi storage M is free again).
+        double *sU = reinterpret_cast<double *>(smem_raw);
+        double *sMm = sU + (size_t)l * l;
+        double *sQ = sMm + (size_t)l * l;
         const int r = rank;
+        for (int idx = tid; idx < l * l; idx += NT) {
+            sU[idx] = out.U[idx];
+            sMm[idx] = out.Mm[idx];
+        }
+        for (int idx = tid; idx < mh * l; idx += NT) {
+            const int i = idx % mh, t = idx / mh;
+            sQ[(size_t)t * mh + i] = (double)Q[i + (int64_t)t * ldq];
+        }
+        __syncthreads();
         for (int idx = tid; idx < mh * l; idx += NT) {
             const int i = idx % mh, j = idx / mh;
             double v = 0.0;
-            for (int t = 0; t < l; ++t) v += (double)Q[i + (int64_t)t * ldq] * out.Mm[t + (size_t)j * l];
+            for (int t = 0; t < l; ++t) v += sQ[(size_t)t * mh + i] * sMm[t + (size_t)j * l];
             QM[i + (int64_t)j * ldqm] = (T)v;
         }
         if (Qout) {
             for (int idx = tid; idx < mh * r; idx += NT) {
                 const int i = idx % mh, j = idx / mh;
                 double v = 0.0;
-                for (int t = 0; t < l; ++t) v += (double)Q[i + (int64_t)t * ldq] * out.U[t + (size_t)j * l];
+                for (int t = 0; t < l; ++t) v += sQ[(size_t)t * mh + i] * sU[t + (size_t)j * l];
                 Qout[i + (int64_t)j * ldqo] = (T)v;
             }
         }
@@ -456,7 +470,8 @@ hipError_t launch_small_svd(int l, const double *G, double tau, const double *w,
                             const SmallSvdOut &out, double *work, int fuse_q, hipStream_t s)
 {
     if (l < 1 || l > 1024) return hipErrorInvalidValue;
-    const size_t lds = l <= 80 ? (size_t)l * l * sizeof(double) : 0;
+    size_t lds = l <= 80 ? (size_t)l * l * sizeof(double) : 0;
+    if (fuse_q && Q) lds = std::max(lds, ((size_t)mh * l + 2 * (size_t)l * l) * sizeof(double));
     if (l <= 16)
         hipLaunchKernelGGL((k_small_svd<T, 64>), dim3(1), dim3(64), lds, s, l, G, tau, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, work, fuse_q);
     else if (l <= 64)
