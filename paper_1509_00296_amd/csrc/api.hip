@@ -152,6 +152,7 @@ struct Orient {
     int mh;
     int64_t nh;
     int64_t si, sk;
+    int64_t si16, sk16;  // strides of the bfloat16 copy (leading dimension = rows of A)
 };
 Orient orient(int64_t m, int64_t n, int64_t lda)
 {
@@ -161,6 +162,9 @@ Orient orient(int64_t m, int64_t n, int64_t lda)
     o.nh = o.trans ? m : n;
     o.si = o.trans ? lda : 1;
     o.sk = o.trans ? 1 : lda;
+    const int64_t rows = o.trans ? o.nh : o.mh;
+    o.si16 = o.trans ? rows : 1;
+    o.sk16 = o.trans ? 1 : rows;
     return o;
 }
 
@@ -181,6 +185,7 @@ struct Core {
     // inputs
     const T *A;
     int64_t lda;
+    const uint16_t *A16;  // bfloat16 copy of A (precision form) or nullptr
     Orient o;
     double tau;
     const double *w;     // device weights (WSVT) or nullptr
@@ -202,13 +207,15 @@ struct Core {
 
 template <typename T>
 struct CoreBuffers {
+    uint16_t *V16;   // bfloat16 scratch (nh x l) for the precision form
     T *Ypart, *Y, *Q, *Bt, *QM, *Om, *Z, *gpart_t, *Qtmp;
     double *Gpart, *G, *U, *Mm, *sigma, *R, *gpart_d, *jwork;
     int *nullc;
 };
 
 template <typename T>
-size_t carve_core(Carver &cv, const Orient &o, int l, int cnew, int num_cu, CoreBuffers<T> &b)
+size_t carve_core(Carver &cv, const Orient &o, int l, int cnew, int num_cu, CoreBuffers<T> &b,
+                  bool force_big = false)
 {
     const int mh = o.mh;
     const int64_t nh = o.nh;
@@ -228,8 +235,10 @@ size_t carve_core(Carver &cv, const Orient &o, int l, int cnew, int num_cu, Core
     b.R = cv.take<double>((size_t)cmax * cmax);
     b.nullc = cv.take<int>((size_t)cmax);
     b.jwork = cv.take<double>((size_t)cmax * cmax);
-    const bool big = !(long_path_ok(mh, std::max(l, 1)) && small_orth_ok(mh, l));
+    const bool big = force_big || !(long_path_ok(mh, std::max(l, 1)) && small_orth_ok(mh, l));
+    b.V16 = nullptr;
     if (big) {
+        b.V16 = cv.take<uint16_t>((size_t)nh * cmax);
         b.Om = cv.take<T>((size_t)nh * std::max(cnew, 1));
         b.Z = cv.take<T>((size_t)nh * cmax);
         // GEMM split-K partials: the largest of Y = Ahat V and Gram products
@@ -243,27 +252,64 @@ size_t carve_core(Carver &cv, const Orient &o, int l, int cnew, int num_cu, Core
     return cv.off;
 }
 
-// Ahat(mh x nh) times a tall matrix V (nh x c, ld ldv): Y (mh x c, ld mh).
+// C = A B with arbitrary strides in storage precision: matrix cores when
+// each operand has a unit stride, the generic tiled kernel otherwise.
 template <typename T>
-int ahat_times(frsvt_context *h, const Core<T> &c, const T *V, int64_t ldv, int cols, T *Y,
-               T *part)
+int mm(frsvt_context *h, int64_t M, int64_t N, int64_t K, const T *A, int64_t sam, int64_t sak,
+       const T *B, int64_t sbk, int64_t sbn, T *C, int64_t scm, int64_t scn, int splitk, T *part)
 {
-    const Orient &o = c.o;
-    const int sk = gemm_splitk(o.mh, cols, o.nh, h->num_cu);
-    CKT(FRSVT_K_GEMM, (launch_gemm<T, T, T>(o.mh, cols, o.nh, c.A, o.si, o.sk, V, 1, ldv, Y, 1, o.mh, sk, part,
-                             h->stream)));
+    const bool unit = (sam == 1 || sak == 1) && (sbk == 1 || sbn == 1);
+    if (splitk > 1 && part == nullptr) splitk = 1;
+    if (unit && std::is_same<T, double>::value) {
+        CKT(FRSVT_K_GEMM, launch_gemm_f64_mfma(M, N, K, (const double *)A, sam, sak, (const double *)B, sbk,
+                                               sbn, (double *)C, scm, scn, splitk, (double *)part, h->stream));
+    } else if (unit) {
+        CKT(FRSVT_K_GEMM, launch_gemm_f32_mfma(M, N, K, (const float *)A, sam, sak, (const float *)B, sbk,
+                                               sbn, (float *)C, scm, scn, splitk, (float *)part, h->stream));
+    } else {
+        CKT(FRSVT_K_GEMM, (launch_gemm<T, T, T>(M, N, K, A, sam, sak, B, sbk, sbn, C, scm, scn, splitk,
+                                                part, h->stream)));
+    }
     return FRSVT_OK;
 }
 
-// Ahat^T (nh x mh) times Q (mh x c): Z (nh x c, ld nh).
+// Ahat(mh x nh) times a tall matrix V (nh x c, ld ldv): Y (mh x c, ld mh).
+// In the precision form (c.A16 set) the product runs on bfloat16 copies of
+// Ahat and V with float accumulation; V16 is scratch for the copy of V.
 template <typename T>
-int ahat_t_times(frsvt_context *h, const Core<T> &c, const T *Qm, int64_t ldq, int cols, T *Z,
-                 T *part)
+int ahat_times(frsvt_context *h, const Core<T> &c, const T *V, int64_t ldv, int cols, T *Y,
+               T *part, uint16_t *V16 = nullptr, bool v_is_bf16 = false)
 {
     const Orient &o = c.o;
-    CKT(FRSVT_K_GEMM, (launch_gemm<T, T, T>(o.nh, cols, o.mh, c.A, o.sk, o.si, Qm, 1, ldq, Z, 1, o.nh, 1, part,
-                             h->stream)));
-    return FRSVT_OK;
+    const int sk = gemm_splitk(o.mh, cols, o.nh, h->num_cu);
+    if (c.A16) {
+        const uint16_t *v16 = (const uint16_t *)V;
+        if (!v_is_bf16) {
+            CKT(FRSVT_K_OTHER, launch_to_bf16(o.nh, cols, (const float *)V, ldv, V16, o.nh, h->stream));
+            v16 = V16;
+            ldv = o.nh;
+        }
+        CKT(FRSVT_K_GEMM, launch_gemm_bf16(o.mh, cols, o.nh, c.A16, o.si16, o.sk16, v16, 1, ldv,
+                                           (float *)Y, 1, o.mh, sk, (float *)part, h->stream));
+        return FRSVT_OK;
+    }
+    return mm<T>(h, o.mh, cols, o.nh, c.A, o.si, o.sk, V, 1, ldv, Y, 1, o.mh, sk, part);
+}
+
+// Ahat^T (nh x mh) times Q (mh x c): Z (nh x c, ld nh).  With use16 the
+// product runs on the bfloat16 copies (Q16 is scratch for the copy of Q).
+template <typename T>
+int ahat_t_times(frsvt_context *h, const Core<T> &c, const T *Qm, int64_t ldq, int cols, T *Z,
+                 T *part, bool use16 = false, uint16_t *Q16 = nullptr)
+{
+    const Orient &o = c.o;
+    if (use16 && c.A16) {
+        CKT(FRSVT_K_OTHER, launch_to_bf16(o.mh, cols, (const float *)Qm, ldq, Q16, o.mh, h->stream));
+        CKT(FRSVT_K_GEMM, launch_gemm_bf16(o.nh, cols, o.mh, c.A16, o.sk16, o.si16, Q16, 1, o.mh,
+                                           (float *)Z, 1, o.nh, 1, (float *)part, h->stream));
+        return FRSVT_OK;
+    }
+    return mm<T>(h, o.nh, cols, o.mh, c.A, o.sk, o.si, Qm, 1, ldq, Z, 1, o.nh, 1, part);
 }
 
 // Gram G = Y^T Y (l x l, double) of a tall rows x l matrix.
@@ -355,7 +401,7 @@ int run_core(frsvt_context *h, Core<T> &c, CoreBuffers<T> &b)
     c.U = b.U;
     c.Mm = b.Mm;
     c.sigma = b.sigma;
-    const bool small = long_path_ok(mh, l) && small_orth_ok(mh, l);
+    const bool small = !c.A16 && long_path_ok(mh, l) && small_orth_ok(mh, l);
     int *oflags = c.status + 4;
     hipStream_t s = h->stream;
     int rc;
@@ -379,9 +425,16 @@ int run_core(frsvt_context *h, Core<T> &c, CoreBuffers<T> &b)
             CK(hipMemcpy2DAsync(b.Q, mh * sizeof(T), c.Qt, c.ldqt * sizeof(T), mh * sizeof(T),
                                 c.rp, hipMemcpyDeviceToDevice, s));
         if (c.cnew > 0) {
-            CKT(FRSVT_K_OTHER, launch_omega<T>(o.nh, c.cnew, c.seed, c.counter, b.Om, o.nh, s));
-            if ((rc = ahat_times<T>(h, c, b.Om, o.nh, c.cnew, b.Q + (size_t)c.rp * mh, b.gpart_t)))
-                return rc;
+            if (c.A16) {
+                CKT(FRSVT_K_OTHER, launch_omega_bf16(o.nh, c.cnew, c.seed, c.counter, b.V16, o.nh, s));
+                if ((rc = ahat_times<T>(h, c, (const T *)b.V16, o.nh, c.cnew, b.Q + (size_t)c.rp * mh,
+                                        b.gpart_t, nullptr, true)))
+                    return rc;
+            } else {
+                CKT(FRSVT_K_OTHER, launch_omega<T>(o.nh, c.cnew, c.seed, c.counter, b.Om, o.nh, s));
+                if ((rc = ahat_times<T>(h, c, b.Om, o.nh, c.cnew, b.Q + (size_t)c.rp * mh, b.gpart_t)))
+                    return rc;
+            }
         }
         if ((rc = big_orth<T>(h, mh, l, b.Q, mh, b, c.seed, c.counter, oflags))) return rc;
     }
@@ -400,14 +453,14 @@ int run_core(frsvt_context *h, Core<T> &c, CoreBuffers<T> &b)
             CKT(FRSVT_K_ORTH, launch_small_orth<T>(mh, (const T *)nullptr, mh, 0, b.Y, mh, l, b.Q, mh, c.seed,
                                     ctr2, oflags, s));
         } else {
-            if ((rc = ahat_t_times<T>(h, c, b.Q, mh, l, b.Z, b.gpart_t))) return rc;
-            if ((rc = ahat_times<T>(h, c, b.Z, o.nh, l, b.Q, b.gpart_t))) return rc;
+            if ((rc = ahat_t_times<T>(h, c, b.Q, mh, l, b.Z, b.gpart_t, true, b.V16))) return rc;
+            if ((rc = ahat_times<T>(h, c, b.Z, o.nh, l, b.Q, b.gpart_t, b.V16))) return rc;
             if ((rc = big_orth<T>(h, mh, l, b.Q, mh, b, c.seed, ctr2, oflags))) return rc;
         }
     }
 
     // Alg. 1 line 16: B^T = Ahat^T Q and its Gram B B^T
-    if (long_path_ok(mh, l)) {
+    if (small || (!c.A16 && long_path_ok(mh, l))) {
         LongPlan p = long_plan(mh, o.nh, l, Prec<T>::bytes, kProject, h->num_cu);
         la.c = l;
         la.Q = b.Q;
@@ -431,11 +484,11 @@ int run_core(frsvt_context *h, Core<T> &c, CoreBuffers<T> &b)
         // QM = Q Mm, Qout = Q U (double small factors cast through a copy)
         T *Mt = b.Qtmp;  // reuse: l x l in storage precision needs l*l <= mh*l
         CKT(FRSVT_K_OTHER, launch_cast<T>(l, l, b.Mm, 1, l, Mt, l, s));
-        CKT(FRSVT_K_GEMM, (launch_gemm<T, T, T>(mh, l, l, b.Q, 1, mh, Mt, 1, l, b.QM, 1, mh, 1, b.gpart_t, s)));
+        if ((rc = mm<T>(h, mh, l, l, b.Q, 1, mh, Mt, 1, l, b.QM, 1, mh, 1, b.gpart_t))) return rc;
         if (c.Qout) {
             CKT(FRSVT_K_OTHER, launch_cast<T>(l, l, b.U, 1, l, Mt, l, s));
-            CKT(FRSVT_K_GEMM, (launch_gemm<T, T, T>(mh, l, l, b.Q, 1, mh, Mt, 1, l, c.Qout, 1, c.ldqo, 1,
-                                     b.gpart_t, s)));
+            if ((rc = mm<T>(h, mh, l, l, b.Q, 1, mh, Mt, 1, l, c.Qout, 1, c.ldqo, 1, b.gpart_t)))
+                return rc;
         }
     }
     return FRSVT_OK;
@@ -469,8 +522,8 @@ int write_x(frsvt_context *h, const Core<T> &c, T *X, int64_t ldx, T *part)
         CKT(FRSVT_K_RECON, launch_recon<T>(kRecon, ra, nullptr, h->stream));
     } else {
         const int64_t scm = o.trans ? ldx : 1, scn = o.trans ? 1 : ldx;
-        CKT(FRSVT_K_GEMM, (launch_gemm<T, T, T>(o.mh, o.nh, c.l, c.QM, 1, o.mh, c.Bt, o.nh, 1, X, scm, scn, 1,
-                                 part, h->stream)));
+        int rc = mm<T>(h, o.mh, o.nh, c.l, c.QM, 1, o.mh, c.Bt, o.nh, 1, X, scm, scn, 1, part);
+        if (rc) return rc;
     }
     return FRSVT_OK;
 }
@@ -536,7 +589,8 @@ int exact_svt_impl(frsvt_context *h, int64_t m, int64_t n, const T *A, int64_t l
 template <typename T>
 int frsvt_impl(frsvt_context *h, int64_t m, int64_t n, const T *A, int64_t lda, double tau,
                int k, int p, int q, const T *Qprev, int r_prev, int64_t ldqp, uint64_t seed,
-               uint64_t counter, T *X, int64_t ldx, T *Qout, int64_t ldqo, int32_t *r_out)
+               uint64_t counter, T *X, int64_t ldx, T *Qout, int64_t ldqo, int32_t *r_out,
+               bool mixed = false)
 {
     const Orient o = orient(m, n, lda);
     Core<T> c{};
@@ -565,11 +619,18 @@ int frsvt_impl(frsvt_context *h, int64_t m, int64_t n, const T *A, int64_t lda, 
     const int l = c.rp + c.cnew;
     CoreBuffers<T> b{};
     Carver dry(nullptr);
-    carve_core<T>(dry, o, l, c.cnew, h->num_cu, b);
+    if (mixed) dry.take<uint16_t>((size_t)m * n);
+    carve_core<T>(dry, o, l, c.cnew, h->num_cu, b, mixed);
     int rc = ensure_ws(h, dry.off);
     if (rc) return rc;
     Carver cv(h->ws);
-    carve_core<T>(cv, o, l, c.cnew, h->num_cu, b);
+    c.A16 = nullptr;
+    if (mixed) {
+        uint16_t *A16 = cv.take<uint16_t>((size_t)m * n);
+        CKT(FRSVT_K_OTHER, launch_to_bf16(m, n, (const float *)A, lda, A16, m, h->stream));
+        c.A16 = A16;
+    }
+    carve_core<T>(cv, o, l, c.cnew, h->num_cu, b, mixed);
     if ((rc = run_core<T>(h, c, b))) return rc;
     if ((rc = write_x<T>(h, c, X, ldx, b.gpart_t))) return rc;
     if (r_out) {
@@ -1091,8 +1152,12 @@ int frsvt(frsvt_handle h, frsvt_precision prec, int64_t m, int64_t n, const void
     if (bad_ptr(X)) return -16;
     if (ldx < m) return -17;
     if (Q_out && ldq_out < mh) return -19;
-    if (mh > 1024) return FRSVT_ERR_UNSUPPORTED;
-    if (prec == FRSVT_MIXED_BF16) return FRSVT_ERR_UNSUPPORTED;
+    if (std::min<int64_t>(mh, (int64_t)(Q_prev && r_prev > 0 ? r_prev + p : k + p)) > 128 && mh > 1024)
+        return FRSVT_ERR_UNSUPPORTED;
+    if (prec == FRSVT_MIXED_BF16)
+        return frsvt_impl<float>(h, m, n, (const float *)A, lda, tau, k, p, q, (const float *)Q_prev,
+                                 r_prev, ldq_prev, seed, counter, (float *)X, ldx, (float *)Q_out,
+                                 ldq_out, r_out, true);
     if (prec == FRSVT_F64)
         return frsvt_impl<double>(h, m, n, (const double *)A, lda, tau, k, p, q,
                                   (const double *)Q_prev, r_prev, ldq_prev, seed, counter,

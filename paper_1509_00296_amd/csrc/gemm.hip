@@ -141,9 +141,10 @@ template hipError_t launch_omega<float>(int64_t, int, uint64_t, uint64_t, float 
 // ===========================================================================
 __global__ void __launch_bounds__(kThreads) k_chol(int l, const double *G, double shift_factor, double null_tol, double *R, int *null_cols, int *flags)
 {
+    // G staged in LDS; the factor is formed directly in the output R
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double *sG = reinterpret_cast<double *>(smem_raw);
-    double *sR = sG + (size_t)l * l;
+    double *sR = R;
     __shared__ double shift, tolabs;
     for (int idx = threadIdx.x; idx < l * l; idx += kThreads) sG[idx] = G[idx];
     __syncthreads();
@@ -158,7 +159,6 @@ __global__ void __launch_bounds__(kThreads) k_chol(int l, const double *G, doubl
     }
     __syncthreads();
     const CholInfo ci = block_chol(sG, l, shift, tolabs, sR, null_cols);
-    for (int idx = threadIdx.x; idx < l * l; idx += kThreads) R[idx] = sR[idx];
     if (threadIdx.x == 0 && flags) {
         flags[1] = ci.nnull;
         if (null_tol <= 0.0 && ci.nnull > 0) flags[2] |= 1;
@@ -167,8 +167,8 @@ __global__ void __launch_bounds__(kThreads) k_chol(int l, const double *G, doubl
 
 hipError_t launch_chol(int l, const double *G, double shift_factor, double null_tol, double *R, int *null_cols, int *flags, hipStream_t s)
 {
-    const size_t lds = 2 * (size_t)l * l * sizeof(double);
-    if (lds > 64 * 1024) return hipErrorInvalidValue;
+    const size_t lds = (size_t)l * l * sizeof(double);
+    if (l > 128) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_chol, dim3(1), dim3(kThreads), lds, s, l, G, shift_factor, null_tol, R, null_cols, flags);
     return hipGetLastError();
 }

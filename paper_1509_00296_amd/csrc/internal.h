@@ -176,3 +176,23 @@ hipError_t launch_cast(int64_t m, int64_t n, const void *src, int src_is_double,
                        T *dst, int64_t ldd, hipStream_t s);
 
 }  // namespace frk
+
+namespace frk {
+// Matrix-core GEMMs (gemm_mfma.hip), strides as launch_gemm; each operand
+// needs one unit stride.  splitk > 1 needs `part` ([splitk][N][M]).
+hipError_t launch_gemm_bf16(int64_t M, int64_t N, int64_t K, const uint16_t *A, int64_t sam,
+                            int64_t sak, const uint16_t *B, int64_t sbk, int64_t sbn, float *C,
+                            int64_t scm, int64_t scn, int splitk, float *part, hipStream_t s);
+hipError_t launch_gemm_f32_mfma(int64_t M, int64_t N, int64_t K, const float *A, int64_t sam,
+                                int64_t sak, const float *B, int64_t sbk, int64_t sbn, float *C,
+                                int64_t scm, int64_t scn, int splitk, float *part, hipStream_t s);
+hipError_t launch_gemm_f64_mfma(int64_t M, int64_t N, int64_t K, const double *A, int64_t sam,
+                                int64_t sak, const double *B, int64_t sbk, int64_t sbn, double *C,
+                                int64_t scm, int64_t scn, int splitk, double *part, hipStream_t s);
+// float -> bfloat16 (round to nearest even) of an m x n column-major matrix
+hipError_t launch_to_bf16(int64_t m, int64_t n, const float *src, int64_t lds, uint16_t *dst,
+                          int64_t ldd, hipStream_t s);
+// Omega drawn as in the sketch kernels, rounded to float then to bfloat16
+hipError_t launch_omega_bf16(int64_t rows, int cols, uint64_t seed, uint64_t counter, uint16_t *Om,
+                             int64_t ld, hipStream_t s);
+}  // namespace frk

@@ -335,7 +335,7 @@ __global__ void __launch_bounds__(NT) k_small_svd(int l, const double *Gin, doub
                                                   SmallSvdOut out, double *work, int fuse_q)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    constexpr int kLdsMax = 80;
+    constexpr int kLdsMax = 128;
     double *M = (l <= kLdsMax) ? reinterpret_cast<double *>(smem_raw) : work;
     __shared__ int sh_rot;
     __shared__ int order[1024];
@@ -470,7 +470,7 @@ hipError_t launch_small_svd(int l, const double *G, double tau, const double *w,
                             const SmallSvdOut &out, double *work, int fuse_q, hipStream_t s)
 {
     if (l < 1 || l > 1024) return hipErrorInvalidValue;
-    size_t lds = l <= 80 ? (size_t)l * l * sizeof(double) : 0;
+    size_t lds = l <= 128 ? (size_t)l * l * sizeof(double) : 0;
     if (fuse_q && Q) lds = std::max(lds, ((size_t)mh * l + 2 * (size_t)l * l) * sizeof(double));
     if (l <= 16)
         hipLaunchKernelGGL((k_small_svd<T, 64>), dim3(1), dim3(64), lds, s, l, G, tau, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, work, fuse_q);
