@@ -102,7 +102,10 @@ typedef enum {
     FRSVT_K_EPILOGUE = 7, /* RPCA epilogue (L on the fly, S, multiplier, next A) */
     FRSVT_K_GEMM = 8,     /* generic tiled GEMM (large shapes, exact SVT) */
     FRSVT_K_OTHER = 9,
-    FRSVT_K_COUNT = 10
+    FRSVT_K_GEMM_BF16 = 10, /* bfloat16 matrix-core sketch / power products */
+    FRSVT_K_WSVT_BATCHED = 11, /* persistent batched weighted SVT */
+    FRSVT_K_ADJOINT = 12, /* adjoint (vector-Jacobian product) kernels */
+    FRSVT_K_COUNT = 13
 } frsvt_kernel_class;
 
 /* Start (enable != 0, clearing earlier records) or stop recording a pair of

