@@ -213,11 +213,22 @@ typedef struct {
  *   A_packed     [in]  float, DEVICE.
  *   X_packed     [out] float, DEVICE; must not alias A_packed.
  *   ranks        [out, DEVICE, optional] int32 per matrix, #{sigma > w}.
- * The small SVD runs in double precision in the local data share.
+ * The small SVD runs in double precision in the local data share.  The
+ * first call with a given argument set reads the shapes to the host (it
+ * waits for the stream), orders the matrices longest first, runs the
+ * autotuner once per handle (group size of the Jacobi pair work per size
+ * bucket, timed on the device) and captures the persistent launch in a HIP
+ * graph; later calls with the same arguments replay that graph without
+ * waiting.
  */
 FRSVT_API int wsvt_batched(frsvt_handle handle, int64_t count, const int32_t *rows,
                  const int32_t *cols, const int64_t *offsets, const float *A_packed,
                  float *X_packed, const frsvt_wsvt_rule *rule, int32_t *ranks);
+
+/* Group sizes (lanes per Jacobi pair) chosen by the autotuner for the size
+ * buckets min(rows, cols) <= 48, <= 64, <= 96; zeros before the first
+ * batched call. */
+FRSVT_API int frsvt_wsvt_tuning(frsvt_handle handle, int32_t group_size[3]);
 
 /* ---------------------------------------------------------- RPCA host */
 

@@ -64,6 +64,8 @@ def _bind(path: str):
                                       ctypes.POINTER(ctypes.c_int)]
         lib.orc_svt_vjp.argtypes = [_i64, _i64, _dp, _i64, ctypes.c_double, _dp, _i64, _dp,
                                     _i64, _dp]
+        lib.orc_wsvt_rule.argtypes = [_i64, _i64, _dp, _i64, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_double, _dp, _i64, _i64p]
         _libs[path] = lib
     return _libs[path]
 
@@ -187,6 +189,17 @@ def wsvt(A, w):
     X = np.zeros((m, n), order="F")
     r = _i64()
     _check(_L().orc_wsvt(m, n, _p(A), m, _p(w), _p(X), m, ctypes.byref(r)), "wsvt")
+    return X, int(r.value)
+
+
+def wsvt_rule(A, c: float = 2.8, noise_var: float = 0.01, eps: float = 1e-8, tau: float = 0.0):
+    """Weighted SVT with w_i = c sqrt(n) / (sqrt(max(sigma_i^2 - n noise_var, 0)) + eps)."""
+    A = _f(A)
+    m, n = A.shape
+    X = np.zeros((m, n), order="F")
+    r = _i64()
+    _check(_L().orc_wsvt_rule(m, n, _p(A), m, c, noise_var, eps, tau, _p(X), m, ctypes.byref(r)),
+           "wsvt_rule")
     return X, int(r.value)
 
 

@@ -456,6 +456,38 @@ int orc_wsvt(int64_t m, int64_t n, const double *A, int64_t lda, const double *w
     return sweeps >= 1000 ? 1 : 0;
 }
 
+/* Weighted SVT under the patch-group weight rule (the weights are a
+ * function of each singular value; the noise level enters through the
+ * column count n and the per-entry noise variance). */
+int orc_wsvt_rule(int64_t m, int64_t n, const double *A, int64_t lda, double c,
+                  double noise_var, double eps, double tau, double *X, int64_t ldx,
+                  int64_t *rank)
+{
+    if (m < 1) return -1;
+    if (n < 1) return -2;
+    if (lda < m) return -4;
+    if (ldx < m) return -10;
+    int64_t k = m < n ? m : n;
+    double *U = dalloc(m * k), *S = dalloc(k), *V = dalloc(n * k), *shr = dalloc(k);
+    int sweeps = orc_svd(m, n, A, lda, U, m, S, V, n);
+    int64_t r = 0;
+    for (int64_t i = 0; i < k; ++i) {
+        double w = tau;
+        if (c > 0.0) {
+            double e = S[i] * S[i] - (double)n * noise_var;
+            double sh = e > 0.0 ? sqrt(e) : 0.0;
+            w = c * sqrt((double)n) / (sh + eps);
+        }
+        double d = S[i] - w;
+        shr[i] = d > 0.0 ? d : 0.0;
+        if (d > 0.0) ++r;
+    }
+    rank_sum(m, n, k, U, m, shr, V, n, X, ldx);
+    if (rank) *rank = r;
+    free(U); free(S); free(V); free(shr);
+    return sweeps >= 1000 ? 1 : 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* FRSVT, Alg. 1                                                            */
 /* ------------------------------------------------------------------------ */

@@ -63,6 +63,14 @@ int orc_svt(int64_t m, int64_t n, const double *A, int64_t lda, double tau,
 int orc_wsvt(int64_t m, int64_t n, const double *A, int64_t lda, const double *w,
              double *X, int64_t ldx, int64_t *rank);
 
+/* Weighted SVT with the patch-group weight rule of weighted nuclear norm
+ * denoising: w_i = c sqrt(n) / (sigma_hat_i + eps), sigma_hat_i =
+ * sqrt(max(sigma_i^2 - n noise_var, 0)), n = the number of columns.  With
+ * c <= 0 every threshold is tau (plain SVT).  rank = #{sigma_i > w_i}. */
+int orc_wsvt_rule(int64_t m, int64_t n, const double *A, int64_t lda, double c,
+                  double noise_var, double eps, double tau, double *X, int64_t ldx,
+                  int64_t *rank);
+
 /* FRSVT, Alg. 1.  Works on the oriented matrix Ahat = A (m <= n) or A^T
  * (m > n), mhat = min(m,n), nhat = max(m,n).
  *   Qt == NULL : fresh sketch, Omega is nhat x nomega, l = nomega.

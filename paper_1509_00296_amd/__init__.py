@@ -209,6 +209,40 @@ def wsvt(A, w, *, return_rank: bool = False):
     return (X, int(r.value)) if return_rank else X
 
 
+def wsvt_batched(rows, cols, offsets, A_packed, *, c: float = 2.8, noise_var: float = 0.01,
+                 eps: float = 1e-8, tau: float = 0.0, X_packed=None, ranks=None):
+    """Weighted SVT of a ragged batch in one persistent launch.  rows, cols
+    (int32), offsets (int64) and A_packed (float32) are GPU tensors; each
+    matrix is column-major at its offset.  Weights follow the patch-group
+    rule w_i = c sqrt(cols) / (sqrt(max(s_i^2 - cols noise_var, 0)) + eps)
+    (c <= 0: constant threshold tau).  Returns (X_packed, ranks)."""
+    import torch
+    h = handle(A_packed.device.index)
+    count = rows.numel()
+    for t, dt in ((rows, torch.int32), (cols, torch.int32), (offsets, torch.int64),
+                  (A_packed, torch.float32)):
+        if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+            raise TypeError("rows/cols int32, offsets int64, A_packed float32, contiguous GPU tensors")
+    if X_packed is None:
+        X_packed = torch.empty_like(A_packed)
+    if ranks is None:
+        ranks = torch.empty(count, dtype=torch.int32, device=A_packed.device)
+    rule = WsvtRule(c, noise_var, eps, tau)
+    rc = h.lib.wsvt_batched(h.ptr, count, rows.data_ptr(), cols.data_ptr(), offsets.data_ptr(),
+                            A_packed.data_ptr(), X_packed.data_ptr(), ctypes.byref(rule),
+                            ranks.data_ptr())
+    _check(h, rc, "wsvt_batched")
+    return X_packed, ranks
+
+
+def wsvt_tuning() -> list:
+    """Lanes per Jacobi pair chosen by the batched-WSVT autotuner per size bucket."""
+    h = handle()
+    g = (_i32 * 3)()
+    h.lib.frsvt_wsvt_tuning(h.ptr, g)
+    return list(g)
+
+
 def frsvt(A, tau: float, k: int, p: int, q: int, Q_prev=None, *, seed: int = 0,
           counter: int = 0, return_basis: bool = True):
     """FRSVT (Alg. 1).  Returns (X, Q~ (mhat x r), r); with Q_prev (mhat x r_prev,

@@ -29,6 +29,17 @@ struct frsvt_context {
     double *dscalars = nullptr;  // small device scalar area (doubles)
     void *pinned = nullptr;      // host pinned status area
     char last_error[256] = {0};
+    // batched weighted SVT: tuned group sizes per size bucket, the queue and
+    // order buffers, and the captured graph of the last argument set
+    int wb_gs[3] = {0, 0, 0};
+    bool wb_tuned = false;
+    int *wb_queue = nullptr;
+    int32_t *wb_gs_dev = nullptr;
+    int32_t *wb_order = nullptr;
+    int64_t wb_order_cap = 0;
+    hipStream_t wb_capture = nullptr;
+    hipGraphExec_t wb_exec = nullptr;
+    std::vector<uint64_t> wb_key;
     // tracing: event pairs around launches, aggregated per kernel class
     bool tracing = false;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> recs;
@@ -933,6 +944,163 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
 
 bool bad_ptr(const void *p) { return p == nullptr; }
 
+// ---------------------------------------------------------------------------
+// Batched weighted SVT: longest-first order, per-bucket autotuning of the
+// Jacobi group size, one persistent launch captured in a HIP graph.
+// ---------------------------------------------------------------------------
+int wb_buffers(frsvt_context *h, int64_t count)
+{
+    if (!h->wb_queue) {
+        hipError_t e = hipMalloc(&h->wb_queue, 256);
+        if (e == hipSuccess) e = hipMalloc(&h->wb_gs_dev, 256);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->wb_capture, hipStreamNonBlocking);
+        if (e != hipSuccess) return fail(h, e, "wsvt_batched buffers");
+    }
+    if (count > h->wb_order_cap) {
+        if (h->wb_order) {
+            (void)hipStreamSynchronize(h->stream);
+            (void)hipFree(h->wb_order);
+            h->wb_order = nullptr;
+        }
+        hipError_t e = hipMalloc(&h->wb_order, (size_t)count * sizeof(int32_t));
+        if (e != hipSuccess) return fail(h, e, "wsvt_batched order");
+        h->wb_order_cap = count;
+    }
+    return FRSVT_OK;
+}
+
+int wb_launch(frsvt_context *h, const WsvtBatchArgs &a, hipStream_t s)
+{
+    const int grid = h->num_cu;
+    CKT(FRSVT_K_WSVT_BATCHED, launch_wsvt_batched(a, grid, s));
+    return FRSVT_OK;
+}
+
+int wsvt_batched_impl(frsvt_context *h, int64_t count, const int32_t *rows, const int32_t *cols,
+                      const int64_t *offsets, const float *A, float *X,
+                      const frsvt_wsvt_rule &rule, int32_t *ranks)
+{
+    int rc = wb_buffers(h, count);
+    if (rc) return rc;
+    std::vector<uint64_t> key = {(uint64_t)count, (uint64_t)(uintptr_t)rows, (uint64_t)(uintptr_t)cols,
+                                 (uint64_t)(uintptr_t)offsets, (uint64_t)(uintptr_t)A,
+                                 (uint64_t)(uintptr_t)X, (uint64_t)(uintptr_t)ranks};
+    uint64_t bits[4];
+    memcpy(bits, &rule, sizeof(bits));
+    for (uint64_t b : bits) key.push_back(b);
+    if (h->wb_exec && key == h->wb_key && !h->tracing) {
+        CK(hipGraphLaunch(h->wb_exec, h->stream));
+        return FRSVT_OK;
+    }
+    // shapes to the host once per argument set: longest-first order and tuning
+    std::vector<int32_t> hr(count), hc(count);
+    CK(hipMemcpyAsync(hr.data(), rows, count * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+    CK(hipMemcpyAsync(hc.data(), cols, count * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+    CK(hipStreamSynchronize(h->stream));
+    for (int64_t j = 0; j < count; ++j) {
+        if (hr[j] < 1 || hc[j] < 1 || hr[j] > 128 || hc[j] > 128 || std::min(hr[j], hc[j]) > 96)
+            return FRSVT_ERR_UNSUPPORTED;
+    }
+    auto cost = [&](int64_t j) {
+        const double s = std::min(hr[j], hc[j]), L = std::max(hr[j], hc[j]);
+        return s * s * (L + 8.0 * s);
+    };
+    std::vector<int32_t> order(count);
+    for (int64_t j = 0; j < count; ++j) order[j] = (int32_t)j;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return cost(x) > cost(y); });
+    CK(hipMemcpyAsync(h->wb_order, order.data(), count * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+
+    WsvtBatchArgs a{};
+    a.count = count;
+    a.rows = rows;
+    a.cols = cols;
+    a.offsets = offsets;
+    a.A = A;
+    a.X = X;
+    a.c = rule.c;
+    a.noise_var = rule.noise_var;
+    a.eps = rule.eps;
+    a.tau = rule.tau;
+    a.ranks = ranks;
+    a.sweeps = nullptr;
+    a.order = h->wb_order;
+    a.queue = h->wb_queue;
+    a.group_size = h->wb_gs_dev;
+
+    if (!h->wb_tuned) {
+        // Autotuner: for each size bucket with enough members, time the kernel
+        // on (up to) 256 of its matrices with 8, 16 and 32 lanes per Jacobi
+        // pair and keep the fastest.
+        const int cand[3] = {8, 16, 32};
+        for (int b = 0; b < 3; ++b) h->wb_gs[b] = 16;
+        std::vector<int32_t> sample;
+        hipEvent_t e0, e1;
+        CK(hipEventCreate(&e0));
+        CK(hipEventCreate(&e1));
+        for (int b = 0; b < 3; ++b) {
+            sample.clear();
+            for (int64_t j = 0; j < count && (int64_t)sample.size() < 256; ++j) {
+                const int s = std::min(hr[j], hc[j]);
+                const int bb = s <= 48 ? 0 : (s <= 64 ? 1 : 2);
+                if (bb == b) sample.push_back((int32_t)j);
+            }
+            if (sample.size() < 32) continue;
+            CK(hipMemcpyAsync(h->wb_order, sample.data(), sample.size() * sizeof(int32_t),
+                              hipMemcpyHostToDevice, h->stream));
+            float best = 1e30f;
+            for (int ci = 0; ci < 3; ++ci) {
+                int32_t gs3[3] = {cand[ci], cand[ci], cand[ci]};
+                CK(hipMemcpyAsync(h->wb_gs_dev, gs3, sizeof(gs3), hipMemcpyHostToDevice, h->stream));
+                WsvtBatchArgs t = a;
+                t.count = (int64_t)sample.size();
+                t.ranks = nullptr;
+                float ms = 0.0f, tot = 0.0f;
+                for (int rep = 0; rep < 2; ++rep) {
+                    CK(hipEventRecord(e0, h->stream));
+                    if ((rc = wb_launch(h, t, h->stream))) return rc;
+                    CK(hipEventRecord(e1, h->stream));
+                    CK(hipEventSynchronize(e1));
+                    CK(hipEventElapsedTime(&ms, e0, e1));
+                    if (rep) tot += ms;
+                }
+                if (tot < best) {
+                    best = tot;
+                    h->wb_gs[b] = cand[ci];
+                }
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        h->wb_tuned = true;
+        CK(hipMemcpyAsync(h->wb_order, order.data(), count * sizeof(int32_t), hipMemcpyHostToDevice,
+                          h->stream));
+    }
+    int32_t gs3[3] = {h->wb_gs[0], h->wb_gs[1], h->wb_gs[2]};
+    CK(hipMemcpyAsync(h->wb_gs_dev, gs3, sizeof(gs3), hipMemcpyHostToDevice, h->stream));
+    CK(hipStreamSynchronize(h->stream));
+    if (h->tracing) return wb_launch(h, a, h->stream);
+    // capture the persistent launch (queue reset kernel + kernel) once
+    if (h->wb_exec) {
+        (void)hipGraphExecDestroy(h->wb_exec);
+        h->wb_exec = nullptr;
+    }
+    hipGraph_t graph = nullptr;
+    CK(hipStreamBeginCapture(h->wb_capture, hipStreamCaptureModeThreadLocal));
+    CK(launch_wsvt_batched(a, h->num_cu, h->wb_capture));
+    CK(hipStreamEndCapture(h->wb_capture, &graph));
+    hipError_t e = hipGraphInstantiate(&h->wb_exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        h->wb_exec = nullptr;
+        return fail(h, e, "hipGraphInstantiate");
+    }
+    h->wb_key = key;
+    CK(hipGraphLaunch(h->wb_exec, h->stream));
+    return FRSVT_OK;
+}
+
+
+
 }  // namespace
 
 // ===========================================================================
@@ -982,6 +1150,11 @@ int frsvt_destroy(frsvt_handle h)
         (void)hipEventDestroy(r.second.second);
     }
     for (auto e : h->pool) (void)hipEventDestroy(e);
+    if (h->wb_exec) (void)hipGraphExecDestroy(h->wb_exec);
+    if (h->wb_capture) (void)hipStreamDestroy(h->wb_capture);
+    if (h->wb_queue) (void)hipFree(h->wb_queue);
+    if (h->wb_gs_dev) (void)hipFree(h->wb_gs_dev);
+    if (h->wb_order) (void)hipFree(h->wb_order);
     if (h->ws) (void)hipFree(h->ws);
     if (h->dstatus) (void)hipFree(h->dstatus);
     if (h->dscalars) (void)hipFree(h->dscalars);
@@ -1198,6 +1371,14 @@ int rpca_ialm(frsvt_handle h, frsvt_precision prec, int64_t m, int64_t n, const 
                             (float *)S, lds, stats);
 }
 
+int frsvt_wsvt_tuning(frsvt_handle h, int32_t group_size[3])
+{
+    if (!h) return -1;
+    if (!group_size) return -2;
+    for (int b = 0; b < 3; ++b) group_size[b] = h->wb_tuned ? h->wb_gs[b] : 0;
+    return FRSVT_OK;
+}
+
 int wsvt_batched(frsvt_handle h, int64_t count, const int32_t *rows, const int32_t *cols,
                  const int64_t *offsets, const float *A_packed, float *X_packed,
                  const frsvt_wsvt_rule *rule, int32_t *ranks)
@@ -1210,8 +1391,9 @@ int wsvt_batched(frsvt_handle h, int64_t count, const int32_t *rows, const int32
     if (count > 0 && bad_ptr(A_packed)) return -6;
     if (count > 0 && bad_ptr(X_packed)) return -7;
     if (bad_ptr(rule)) return -8;
-    (void)ranks;
-    return FRSVT_ERR_UNSUPPORTED;
+    if (count == 0) return FRSVT_OK;
+    if (count > (int64_t)1 << 30) return FRSVT_ERR_UNSUPPORTED;
+    return wsvt_batched_impl(h, count, rows, cols, offsets, A_packed, X_packed, *rule, ranks);
 }
 
 }  // extern "C"

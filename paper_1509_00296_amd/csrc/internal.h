@@ -196,3 +196,22 @@ hipError_t launch_to_bf16(int64_t m, int64_t n, const float *src, int64_t lds, u
 hipError_t launch_omega_bf16(int64_t rows, int cols, uint64_t seed, uint64_t counter, uint16_t *Om,
                              int64_t ld, hipStream_t s);
 }  // namespace frk
+
+namespace frk {
+// Persistent batched weighted SVT (wsvt_batched.hip).
+struct WsvtBatchArgs {
+    int64_t count;
+    const int32_t *rows, *cols;
+    const int64_t *offsets;
+    const float *A;
+    float *X;
+    double c, noise_var, eps, tau;
+    int32_t *ranks;          // optional
+    int32_t *sweeps;         // optional, Jacobi sweeps per matrix
+    const int32_t *order;    // processing order or nullptr
+    int *queue;              // work counter
+    const int32_t *group_size;  // lanes per Jacobi pair group, per size bucket (3)
+};
+size_t wsvt_batched_lds();
+hipError_t launch_wsvt_batched(const WsvtBatchArgs &a, int grid, hipStream_t s);
+}  // namespace frk

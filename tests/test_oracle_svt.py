@@ -133,3 +133,27 @@ def test_wsvt_closed_form_and_objective(orc):
     for scale in (1e-1, 1e-3):
         for _ in range(200):
             assert obj(X + scale * rng.standard_normal(X.shape)) >= f0 - 1e-10
+
+
+def test_wsvt_rule_reduces_to_explicit_weights(orc):
+    # the rule's weights depend only on each singular value: recomputing them
+    # from the exact spectrum and calling the explicit-weight WSVT must agree
+    rng = np.random.default_rng(14)
+    for (m, n) in [(64, 40), (49, 90), (100, 30)]:
+        s = np.array([50.0, 20.0, 10.0, 5.0])
+        _, _, _, L = _known(rng, m, n, s)
+        A = L + 0.1 * rng.standard_normal((m, n))
+        sig = np.linalg.svd(A, compute_uv=False)
+        sh = np.sqrt(np.maximum(sig ** 2 - n * 0.01, 0.0))
+        w = 2.8 * np.sqrt(n) / (sh + 1e-8)
+        Xr, rr = orc.wsvt_rule(A, 2.8, 0.01, 1e-8)
+        Xw, rw = orc.wsvt(A, w)
+        assert rr == rw
+        assert np.abs(Xr - Xw).max() < 1e-12
+        # the weights are non-descending here, so this is the WNNM optimum
+        assert np.all(np.diff(w) >= 0)
+    # c <= 0 is plain SVT with threshold tau
+    A = rng.standard_normal((30, 20)) * 3
+    Xs, rs = orc.svt(A, 2.0)
+    Xr, rr = orc.wsvt_rule(A, 0.0, 0.0, 0.0, 2.0)
+    assert rs == rr and np.abs(Xs - Xr).max() < 1e-14
