@@ -262,3 +262,63 @@ def svt_vjp(A, tau: float, Xbar):
     _check(_L().orc_svt_vjp(m, n, _p(A), m, tau, _p(Xb), m, _p(Ab), m, ctypes.byref(tb)),
            "svt_vjp")
     return Ab, float(tb.value)
+
+
+# ---------------------------------------------------------------------------
+# Unrolled inexact-ALM with learnable thresholds (test infrastructure for the
+# adjoint).  The iALM loop of the RPCA host (Sec. 4.1 of the paper, the
+# standard inexact ALM): L-update by thresholding, then the S-update by
+# elementwise shrinkage, then the multiplier update.  In the unrolled form the
+# SVT threshold of step t is a free parameter tau_t (in place of 1/mu_t) and
+# the shrink threshold is lam_t (in place of lam/mu_t); mu_t keeps the plain
+# schedule, which also scales the multiplier terms.
+# ---------------------------------------------------------------------------
+def shrink(V, t: float):
+    """Elementwise soft shrinkage sgn(v) max(|v| - t, 0)."""
+    return np.sign(V) * np.maximum(np.abs(V) - t, 0.0)
+
+
+def dual_step(O, L, Y, lam: float, mu: float, mu_next: float):
+    """S, Y_next, A_next of one iALM step after the thresholding."""
+    O, L, Y = (np.asarray(x, dtype=np.float64) for x in (O, L, Y))
+    S = shrink(O - L + Y / mu, lam)
+    Yn = Y + mu * (O - L - S)
+    An = O - S + Yn / mu_next
+    return S, Yn, An
+
+
+def rpca_start(O, lam: float, norm2: float | None = None, mu0: float = 0.0):
+    """Y0 = O / J, A0 = O + Y0 / mu0 with J = max(||O||_2, ||O||_inf / lam) and
+    mu0 = 1.25 / ||O||_2 (S_0 = 0).  Returns (Y0, A0, norm2, mu0)."""
+    O = np.asarray(O, dtype=np.float64)
+    if norm2 is None:
+        norm2 = float(svd(O)[1][0])
+    J = max(norm2, float(np.abs(O).max()) / lam)
+    mu = mu0 if mu0 > 0 else 1.25 / norm2
+    Y0 = O / J
+    return Y0, O + Y0 / mu, norm2, mu
+
+
+def rpca_unrolled(O, taus, lams, k: int = 5, p: int = 5, q: int = 1, seed: int = 0,
+                  rho: float = 1.5, mu_bar_factor: float = 1e7, lam: float | None = None,
+                  norm2: float | None = None):
+    """L_T of len(taus) unrolled steps; step t thresholds with FRSVT (fresh
+    sketch, l = min(k + p, mhat), q power iterations, Omega drawn with
+    counter t from `seed`)."""
+    O = np.asarray(O, dtype=np.float64)
+    m, n = O.shape
+    mh, nh = min(m, n), max(m, n)
+    lam = lam if lam is not None else 1.0 / np.sqrt(max(m, n))
+    Y, A, _, mu = rpca_start(O, lam, norm2)
+    mu_bar = mu * mu_bar_factor
+    l = min(k + p, mh)
+    T = len(taus)
+    L = None
+    for t in range(T):
+        L = frsvt(A, float(taus[t]), q, gaussian_matrix(seed, t, nh, l))[0]
+        if t + 1 == T:
+            break
+        mu_next = min(rho * mu, mu_bar)
+        _, Y, A = dual_step(O, L, Y, float(lams[t]), mu, mu_next)
+        mu = mu_next
+    return L

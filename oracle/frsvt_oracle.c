@@ -762,6 +762,7 @@ int orc_svt_vjp(int64_t m, int64_t n, const double *A, int64_t lda, double tau,
             if (i == j) gs = above_i ? 1.0 : 0.0;
             else if (above_i && above_j) gs = 1.0;
             else if (!above_i && !above_j) gs = 0.0;
+            else if (fabs(sg[i] - sg[j]) <= 1e-12 * fmax(sg[i], sg[j])) gs = 0.5;  /* straddling pair, guard */
             else gs = (f[i] - f[j]) / (sg[i] - sg[j]);
             ga = (sg[i] + sg[j] > 0.0) ? (f[i] + f[j]) / (sg[i] + sg[j]) : 0.0;
             double xij = AT(Xp, n, i, j), xji = AT(Xp, n, j, i);

@@ -91,3 +91,27 @@ def test_svt_tau_derivative_closed_form(orc):
     UV = u[:, :r] @ vt[:r]
     _, tb = orc.svt_vjp(A, tau, UV)
     assert tb == pytest.approx(-r, rel=1e-12)
+
+
+def test_svt_vjp_straddling_pair_guard(orc):
+    """A pair of singular values straddling tau closer than 1e-12 (relative)
+    takes the divided difference 1/2 instead of f(s_i)/(s_i - s_j) (here 1/6);
+    the VJP stays a contraction (SVT is 1-Lipschitz) and finite.  A is
+    diagonal so that its singular vectors are the coordinate axes."""
+    import numpy as np
+    rng = np.random.default_rng(8)
+    m, n, tau = 12, 9, 2.0
+    s = np.array([9.0, 7.0, 5.0, tau + 1e-13, tau - 5e-13, 1.0, 0.5, 0.2, 0.1])
+    A = np.zeros((m, n))
+    A[np.arange(n), np.arange(n)] = s
+    Xb = rng.standard_normal((m, n))
+    Ab, tb = orc.svt_vjp(A, tau, Xb)
+    assert np.all(np.isfinite(Ab)) and np.isfinite(tb)
+    assert np.linalg.norm(Ab) <= np.linalg.norm(Xb) * (1 + 1e-9)
+    ga = (s[3] - tau) / (s[3] + s[4])
+    want = 0.5 * 0.5 * (Xb[3, 4] + Xb[4, 3]) + ga * 0.5 * (Xb[3, 4] - Xb[4, 3])
+    assert abs(Ab[3, 4] - want) <= 1e-12
+    # a pair above tau: symmetric part 1, antisymmetric (f_0 + f_1)/(s_0 + s_1)
+    ga01 = (s[0] + s[1] - 2 * tau) / (s[0] + s[1])
+    want01 = 0.5 * (Xb[0, 1] + Xb[1, 0]) + ga01 * 0.5 * (Xb[0, 1] - Xb[1, 0])
+    assert abs(Ab[0, 1] - want01) <= 1e-12
