@@ -126,7 +126,8 @@ FRSVT_API const char *frsvt_trace_name(int kernel_class);
  * the stream): info[0] rank r, info[1] Jacobi sweeps of the small SVD,
  * info[2] 1 when that Jacobi met its stopping test, info[4] 1 when the last
  * re-orthonormalisation took the CholeskyQR2 fast path (2 = shifted
- * fallback), info[5] columns refilled, info[6] final Cholesky failures.
+ * fallback), info[5] columns refilled, info[6] final Cholesky failures,
+ * info[7] 1 when frsvt_vjp met a singular triangular factor.
  * `count` words (at most 8) are written. */
 FRSVT_API int frsvt_last_info(frsvt_handle handle, int32_t *info, int count);
 
@@ -175,6 +176,88 @@ FRSVT_API int frsvt(frsvt_handle handle, frsvt_precision prec, int64_t m, int64_
           int64_t lda, double tau, int32_t k, int32_t p, int32_t q, const void *Q_prev,
           int32_t r_prev, int64_t ldq_prev, uint64_t seed, uint64_t counter, void *X,
           int64_t ldx, void *Q_out, int64_t ldq_out, int32_t *r_out);
+
+/* ------------------------------------------------------------ adjoint */
+
+/*
+ * frsvt_fwd: the fresh-sketch FRSVT of Alg. 1 (lines 4-6, 13-21; no range
+ * propagation) that also saves what its adjoint needs, without waiting:
+ *   A, lda, tau, k, p, q, seed, counter, X, ldx  as for frsvt (l = min(k+p, mhat),
+ *                l <= 64).
+ *   Q        [out] the basis of line 16 (the Q of B = Q^T Ahat), mhat x l,
+ *            leading dimension ldq >= mhat.
+ *   factors  [out] DEVICE, l + l*l doubles: the singular values of B
+ *            (descending), then its left singular vectors U_B (l x l,
+ *            column-major; columns of zero singular values are zero).
+ * FRSVT_F64 and FRSVT_F32 only.
+ */
+FRSVT_API int frsvt_fwd(frsvt_handle handle, frsvt_precision prec, int64_t m, int64_t n,
+                        const void *A, int64_t lda, double tau, int32_t k, int32_t p, int32_t q,
+                        uint64_t seed, uint64_t counter, void *X, int64_t ldx, void *Q,
+                        int64_t ldq, double *factors);
+
+/*
+ * frsvt_vjp: vector-Jacobian product of the frsvt_fwd map A -> X for its
+ * fixed Omega (the paper does not differentiate the method; this is the
+ * derivative of X = Q S_tau(Q^T Ahat), Prop. 1, through the power
+ * iterations and the QR steps).  Given the upstream gradient X_bar it
+ * writes A_bar = (dX/dA)^T X_bar and tau_bar = <X_bar, dX/dtau>.
+ *   A, tau, k, p, q, seed, counter  exactly as passed to frsvt_fwd.
+ *   Q, ldq, factors  [in] saved by that frsvt_fwd call.
+ *   X_bar    [in]  m x n, ldxb >= m.
+ *   A_bar    [out] m x n, ldab >= m; must not alias A or X_bar.
+ *   tau_bar  [out, DEVICE, optional] one double.
+ * The sketch Y_0 = Ahat Omega and the power iterations are recomputed from
+ * (seed, counter) and A; nothing of them is stored.  The small-SVT part is
+ * the spectral-function derivative with bounded divided differences; a pair
+ * of singular values straddling tau closer than 1e-12 of the larger uses the
+ * value 1/2.  The QR steps assume full column rank: frsvt_last_info word 7
+ * is set when a triangular factor had a non-positive diagonal entry.  No
+ * host wait.  FRSVT_F64 and FRSVT_F32 only; l <= 64.
+ */
+FRSVT_API int frsvt_vjp(frsvt_handle handle, frsvt_precision prec, int64_t m, int64_t n,
+                        const void *A, int64_t lda, double tau, int32_t k, int32_t p, int32_t q,
+                        uint64_t seed, uint64_t counter, const void *Q, int64_t ldq,
+                        const double *factors, const void *X_bar, int64_t ldxb, void *A_bar,
+                        int64_t ldab, double *tau_bar);
+
+/*
+ * rpca_dual_step: the updates of one inexact-ALM iteration that follow the
+ * thresholding (Sec. 4.1's RPCA host), with the shrink threshold given
+ * directly so that it can be learned per unrolled step:
+ *   V = O - L + Y/mu,  S = shrink(V, lam),  Y_next = Y + mu (O - L - S),
+ *   A_next = O - S + Y_next / mu_next   (the next thresholding input).
+ * O, L, Y [in] m x n.  S, Y_next, A_next [out, each optional].  lam >= 0,
+ * mu, mu_next > 0.  No host wait.
+ */
+FRSVT_API int rpca_dual_step(frsvt_handle handle, frsvt_precision prec, int64_t m, int64_t n,
+                             const void *O, int64_t ldo, const void *L, int64_t ldl, const void *Y,
+                             int64_t ldy, double lam, double mu, double mu_next, void *S,
+                             int64_t lds, void *Y_next, int64_t ldyn, void *A_next, int64_t ldan);
+
+/*
+ * rpca_dual_step_vjp: reverse of rpca_dual_step.  Upstream gradients
+ * S_bar, Y_next_bar, A_next_bar (each optional, NULL = zero) give
+ *   L_bar, Y_bar [out] m x n, and lam_bar [out, DEVICE, optional] one
+ * double (sum over the entries, fixed reduction order).  No host wait.
+ */
+FRSVT_API int rpca_dual_step_vjp(frsvt_handle handle, frsvt_precision prec, int64_t m, int64_t n,
+                                 const void *O, int64_t ldo, const void *L, int64_t ldl,
+                                 const void *Y, int64_t ldy, double lam, double mu, double mu_next,
+                                 const void *S_bar, int64_t ldsb, const void *Y_next_bar,
+                                 int64_t ldynb, const void *A_next_bar, int64_t ldanb, void *L_bar,
+                                 int64_t ldlb, void *Y_bar, int64_t ldyb, double *lam_bar);
+
+/*
+ * rpca_init: starting point of the inexact-ALM loop, S_0 = 0,
+ *   Y0 = O / J,  J = max(||O||_2, ||O||_inf / lambda),  A0 = O + Y0 / mu0,
+ * with mu0 = 1.25 / ||O||_2 when the given mu0 <= 0.
+ *   out [out, HOST, optional] 3 doubles: ||O||_2, mu0, J.  Waits for the
+ *   stream.  FRSVT_ERR_NONFINITE when O holds NaN or Inf.
+ */
+FRSVT_API int rpca_init(frsvt_handle handle, frsvt_precision prec, int64_t m, int64_t n,
+                        const void *O, int64_t ldo, double lambda, double mu0, void *Y0,
+                        int64_t ldy, void *A0, int64_t lda0, double *out);
 
 /* --------------------------------------------------------------- WSVT */
 

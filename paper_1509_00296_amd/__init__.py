@@ -82,6 +82,23 @@ def library(path: str | None = None) -> ctypes.CDLL:
     lib.rpca_ialm.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _i64, _dbl,
                               ctypes.POINTER(RpcaOpts), _vp, _i64, _vp, _i64,
                               ctypes.POINTER(RpcaStats)]
+    lib.frsvt_fwd.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _i64, _dbl, _i32, _i32, _i32, _u64,
+                              _u64, _vp, _i64, _vp, _i64, _vp]
+    lib.frsvt_vjp.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _i64, _dbl, _i32, _i32, _i32, _u64,
+                              _u64, _vp, _i64, _vp, _vp, _i64, _vp, _i64, _vp]
+    lib.rpca_dual_step.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64,
+                                   _dbl, _dbl, _dbl, _vp, _i64, _vp, _i64, _vp, _i64]
+    lib.rpca_dual_step_vjp.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _i64, _vp, _i64, _vp,
+                                       _i64, _dbl, _dbl, _dbl, _vp, _i64, _vp, _i64, _vp, _i64, _vp,
+                                       _i64, _vp, _i64, _vp]
+    lib.rpca_init.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _i64, _dbl, _dbl, _vp, _i64, _vp,
+                              _i64, ctypes.POINTER(_dbl)]
+    lib.frsvt_wsvt_tuning.argtypes = [_vp, _vp]
+    lib.frsvt_last_info.argtypes = [_vp, ctypes.POINTER(_i32), ctypes.c_int]
+    lib.frsvt_trace_enable.argtypes = [_vp, ctypes.c_int]
+    lib.frsvt_trace_read.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(_dbl), ctypes.POINTER(_i64)]
+    lib.frsvt_trace_name.argtypes = [ctypes.c_int]
+    lib.frsvt_trace_name.restype = ctypes.c_char_p
     if path is None:
         _lib = lib
     return lib
@@ -310,3 +327,266 @@ def rpca_ialm(O, lam: float, *, use_frsvt: bool = True, tol: float = 1e-7, max_i
     k = min(st.iters, 64)
     return RpcaResult(L, S, st.iters, bool(st.converged), st.residual, st.norm2, st.seconds,
                       list(st.ranks[:k]), list(st.residuals[:k]))
+
+
+# ---------------------------------------------------------------------------
+# Adjoint: the fresh-sketch FRSVT with saved state, its vector-Jacobian
+# product, and the unrolled inexact-ALM pieces.
+# ---------------------------------------------------------------------------
+def _in_order(t, transposed: bool):
+    """t with the memory order of a tensor whose _colmajor flag is `transposed`."""
+    if t.dim() != 2:
+        raise ValueError("expected a 2-D tensor")
+    try:
+        if _colmajor(t)[3] == transposed:
+            return t
+    except ValueError:
+        pass
+    return t.contiguous() if transposed else t.t().contiguous().t()
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def frsvt_fwd(A, tau: float, k: int, p: int, q: int, *, seed: int = 0, counter: int = 0):
+    """Fresh-sketch FRSVT that keeps the adjoint's state.  Returns (X, Q, factors):
+    Q is the mhat x l basis of B = Q^T Ahat, factors = [sigma (l), U_B (l*l)] in
+    float64 on the device."""
+    import torch
+    h = handle(A.device.index)
+    m, n, lda, tr = _colmajor(A)
+    mh = min(m, n)
+    l = min(k + p, mh)
+    X = _like(A, tr)
+    _, _, ldx, _ = _colmajor(X)
+    Q = torch.empty((l, mh), dtype=A.dtype, device=A.device).t()
+    fac = torch.empty(l + l * l, dtype=torch.float64, device=A.device)
+    rc = h.lib.frsvt_fwd(h.ptr, _prec(A), m, n, A.data_ptr(), lda, float(tau), int(k), int(p), int(q),
+                         int(seed) & (2**64 - 1), int(counter) & (2**64 - 1), X.data_ptr(), ldx,
+                         Q.data_ptr(), mh, fac.data_ptr())
+    _check(h, rc, "frsvt_fwd")
+    return X, Q, fac
+
+
+def frsvt_vjp(A, tau: float, k: int, p: int, q: int, Q, factors, X_bar, *, seed: int = 0,
+              counter: int = 0):
+    """(A_bar, tau_bar) of the frsvt_fwd call with the same arguments, for the
+    upstream gradient X_bar; tau_bar is a 0-dim float64 device tensor."""
+    import torch
+    h = handle(A.device.index)
+    m, n, lda, tr = _colmajor(A)
+    Xb = _in_order(X_bar.to(dtype=A.dtype), tr)
+    _, _, ldxb, _ = _colmajor(Xb)
+    Ab = _like(A, tr)
+    _, _, ldab, _ = _colmajor(Ab)
+    tb = torch.empty((), dtype=torch.float64, device=A.device)
+    mh = min(m, n)
+    Qc = Q if Q.stride(0) == 1 else Q.t().contiguous().t()
+    rc = h.lib.frsvt_vjp(h.ptr, _prec(A), m, n, A.data_ptr(), lda, float(tau), int(k), int(p), int(q),
+                         int(seed) & (2**64 - 1), int(counter) & (2**64 - 1), Qc.data_ptr(),
+                         max(Qc.stride(1), mh), factors.data_ptr(), Xb.data_ptr(), ldxb,
+                         Ab.data_ptr(), ldab, tb.data_ptr())
+    _check(h, rc, "frsvt_vjp")
+    return Ab, tb
+
+
+def last_info(count: int = 8) -> list:
+    """Status words of the last thresholding step (frsvt_last_info)."""
+    h = handle()
+    info = (_i32 * 8)()
+    h.lib.frsvt_last_info(h.ptr, info, count)
+    return list(info[:count])
+
+
+def rpca_init(O, lam: float, mu0: float = 0.0):
+    """Starting point of the inexact-ALM loop: (Y0, A0, norm2, mu0, J)."""
+    h = handle(O.device.index)
+    m, n, ldo, tr = _colmajor(O)
+    Y0, A0 = _like(O, tr), _like(O, tr)
+    out = (_dbl * 3)()
+    rc = h.lib.rpca_init(h.ptr, _prec(O), m, n, O.data_ptr(), ldo, float(lam), float(mu0),
+                         Y0.data_ptr(), _colmajor(Y0)[2], A0.data_ptr(), _colmajor(A0)[2], out)
+    _check(h, rc, "rpca_init")
+    return Y0, A0, out[0], out[1], out[2]
+
+
+def dual_step(O, L, Y, lam: float, mu: float, mu_next: float, *, want_S: bool = False,
+              want_Y: bool = True, want_A: bool = True):
+    """(S, Y_next, A_next) of one unrolled iALM step (None where not wanted)."""
+    h = handle(O.device.index)
+    m, n, ldo, tr = _colmajor(O)
+    L, Y = _in_order(L, tr), _in_order(Y, tr)
+    outs = [_like(O, tr) if w else None for w in (want_S, want_Y, want_A)]
+    lds = [_colmajor(t)[2] if t is not None else m for t in outs]
+    rc = h.lib.rpca_dual_step(h.ptr, _prec(O), m, n, O.data_ptr(), ldo, L.data_ptr(),
+                              _colmajor(L)[2], Y.data_ptr(), _colmajor(Y)[2], float(lam), float(mu),
+                              float(mu_next), _ptr(outs[0]), lds[0], _ptr(outs[1]), lds[1],
+                              _ptr(outs[2]), lds[2])
+    _check(h, rc, "rpca_dual_step")
+    return tuple(outs)
+
+
+def dual_step_vjp(O, L, Y, lam: float, mu: float, mu_next: float, S_bar=None, Y_next_bar=None,
+                  A_next_bar=None, *, lam_bar=None):
+    """(L_bar, Y_bar, lam_bar) of dual_step; lam_bar is a 0-dim float64 device
+    tensor (or the given one, overwritten)."""
+    import torch
+    h = handle(O.device.index)
+    m, n, ldo, tr = _colmajor(O)
+    L, Y = _in_order(L, tr), _in_order(Y, tr)
+    ups = [None if t is None else _in_order(t.to(dtype=O.dtype), tr) for t in (S_bar, Y_next_bar, A_next_bar)]
+    lds = [_colmajor(t)[2] if t is not None else m for t in ups]
+    Lb, Yb = _like(O, tr), _like(O, tr)
+    if lam_bar is None:
+        lam_bar = torch.empty((), dtype=torch.float64, device=O.device)
+    rc = h.lib.rpca_dual_step_vjp(h.ptr, _prec(O), m, n, O.data_ptr(), ldo, L.data_ptr(),
+                                  _colmajor(L)[2], Y.data_ptr(), _colmajor(Y)[2], float(lam),
+                                  float(mu), float(mu_next), _ptr(ups[0]), lds[0], _ptr(ups[1]),
+                                  lds[1], _ptr(ups[2]), lds[2], Lb.data_ptr(), _colmajor(Lb)[2],
+                                  Yb.data_ptr(), _colmajor(Yb)[2], lam_bar.data_ptr())
+    _check(h, rc, "rpca_dual_step_vjp")
+    return Lb, Yb, lam_bar
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class _FRSVTFn(_torch().autograd.Function):
+    """X = FRSVT_tau(A) for a fixed sketch (seed, counter), differentiable in
+    A and tau through frsvt_vjp."""
+
+    @staticmethod
+    def forward(ctx, A, tau, k, p, q, seed, counter):
+        torch = _torch()
+        tv = float(tau)
+        X, Q, fac = frsvt_fwd(A, tv, k, p, q, seed=seed, counter=counter)
+        ctx.save_for_backward(A, Q, fac)
+        ctx.cfg = (tv, k, p, q, seed, counter)
+        ctx.tau_meta = (tau.device, tau.dtype) if torch.is_tensor(tau) else None
+        return X
+
+    @staticmethod
+    def backward(ctx, X_bar):
+        A, Q, fac = ctx.saved_tensors
+        tv, k, p, q, seed, counter = ctx.cfg
+        Ab, tb = frsvt_vjp(A, tv, k, p, q, Q, fac, X_bar, seed=seed, counter=counter)
+        gtau = None
+        if ctx.tau_meta is not None and ctx.needs_input_grad[1]:
+            gtau = tb.to(device=ctx.tau_meta[0], dtype=ctx.tau_meta[1])
+        return (Ab if ctx.needs_input_grad[0] else None), gtau, None, None, None, None, None
+
+
+def frsvt_ad(A, tau, k: int, p: int, q: int, *, seed: int = 0, counter: int = 0):
+    """Differentiable FRSVT (fresh sketch): gradients flow to A and, when tau is a
+    tensor, to tau."""
+    return _FRSVTFn.apply(A, tau, k, p, q, seed, counter)
+
+
+class _UnrolledFn(_torch().autograd.Function):
+    """T unrolled inexact-ALM steps on a batch of instances, learnable
+    per-step SVT thresholds taus[t] and shrink thresholds lams[t] shared by
+    the batch:  L_{t+1} = FRSVT_{tau_t}(A_t);  (Y_{t+1}, A_{t+1}) = dual step
+    with lam_t, mu_t, mu_{t+1}.  Output L_T.  The backward runs the reverse
+    sweep with frsvt_vjp and dual_step_vjp; the threshold gradients are summed
+    on the device and read once."""
+
+    @staticmethod
+    def forward(ctx, taus, lams, O, Y0, A0, mus, k, p, q, seeds):
+        torch = _torch()
+        T = taus.numel()
+        B = O.shape[0]
+        tv, lv = [float(x) for x in taus.tolist()], [float(x) for x in lams.tolist()]
+        As, Ys, Ls, Qs, Fs = [], [], [], [], []
+        A_t, Y_t = list(A0), list(Y0)
+        for t in range(T):
+            L_t, Q_t, F_t, An, Yn = [], [], [], [], []
+            for b in range(B):
+                X, Q, fac = frsvt_fwd(A_t[b], tv[t], k, p, q, seed=seeds[b], counter=t)
+                L_t.append(X)
+                Q_t.append(Q)
+                F_t.append(fac)
+                if t + 1 < T:
+                    _, y1, a1 = dual_step(O[b], X, Y_t[b], lv[t], mus[b][t], mus[b][t + 1])
+                    Yn.append(y1)
+                    An.append(a1)
+            As.append(A_t)
+            Ys.append(Y_t)
+            Ls.append(L_t)
+            Qs.append(Q_t)
+            Fs.append(F_t)
+            A_t, Y_t = An, Yn
+        ctx.state = (As, Ys, Ls, Qs, Fs, O, mus, k, p, q, seeds, tv, lv, taus.device)
+        return torch.stack(Ls[-1])
+
+    @staticmethod
+    def backward(ctx, L_bar):
+        torch = _torch()
+        As, Ys, Ls, Qs, Fs, O, mus, k, p, q, seeds, tv, lv, pdev = ctx.state
+        T, B = len(tv), len(seeds)
+        dev = L_bar.device
+        gt = torch.zeros((T, B), dtype=torch.float64, device=dev)
+        gl = torch.zeros((T, B), dtype=torch.float64, device=dev)
+        for b in range(B):
+            Ab_next, Yb_next = None, None
+            for t in range(T - 1, -1, -1):
+                if t == T - 1:
+                    Lb = L_bar[b]
+                else:
+                    Lb, Yb_t, _ = dual_step_vjp(O[b], Ls[t][b], Ys[t][b], lv[t], mus[b][t],
+                                                mus[b][t + 1], None, Yb_next, Ab_next,
+                                                lam_bar=gl[t, b])
+                    Yb_next = Yb_t
+                Ab_t, tb = frsvt_vjp(As[t][b], tv[t], k, p, q, Qs[t][b], Fs[t][b], Lb,
+                                     seed=seeds[b], counter=t)
+                gt[t, b].copy_(tb)
+                Ab_next = Ab_t
+                if t == T - 1:
+                    Yb_next = None
+        ctx.state = None
+        gtau = gt.sum(dim=1).to(pdev)
+        glam = gl.sum(dim=1).to(pdev)
+        return gtau, glam, None, None, None, None, None, None, None, None
+
+
+class UnrolledRPCA(_torch().nn.Module):
+    """Differentiable unrolled inexact-ALM RPCA (FRSVT thresholding) with
+    learnable per-step thresholds tau_t (SVT) and lam_t (shrink).  mu_t
+    follows the iALM schedule of each instance: mu_0 = 1.25 / ||O||_2,
+    mu_{t+1} = rho mu_t (capped at mu_bar_factor mu_0)."""
+
+    def __init__(self, taus, lams, *, k: int = 5, p: int = 5, q: int = 1, rho: float = 1.5,
+                 mu_bar_factor: float = 1e7, seed: int = 0, lam_ialm: float | None = None):
+        torch = _torch()
+        super().__init__()
+        self.tau = torch.nn.Parameter(torch.as_tensor(taus, dtype=torch.float64).clone())
+        self.lam = torch.nn.Parameter(torch.as_tensor(lams, dtype=torch.float64).clone())
+        self.k, self.p, self.q, self.rho, self.mu_bar_factor = k, p, q, rho, mu_bar_factor
+        self.seed = seed
+        self.lam_ialm = lam_ialm
+
+    @staticmethod
+    def default_schedule(O, steps: int = 10, rho: float = 1.5, lam: float | None = None):
+        """tau_t = 1/mu_t and lam_t = lam/mu_t of the plain iALM on instance O."""
+        m, n = O.shape
+        lam = lam if lam is not None else 1.0 / max(m, n) ** 0.5
+        _, _, _, mu0, _ = rpca_init(O, lam)
+        mus = [mu0 * rho ** t for t in range(steps)]
+        return [1.0 / mu for mu in mus], [lam / mu for mu in mus]
+
+    def forward(self, O):
+        """O: (B, m, n) GPU tensor.  Returns L_T, shape (B, m, n)."""
+        B, m, n = O.shape
+        lam = self.lam_ialm if self.lam_ialm is not None else 1.0 / max(m, n) ** 0.5
+        T = self.tau.numel()
+        Y0, A0, mus = [], [], []
+        for b in range(B):
+            y, a, _, mu0, _ = rpca_init(O[b], lam)
+            Y0.append(y)
+            A0.append(a)
+            mub = mu0 * self.mu_bar_factor
+            mus.append([min(mu0 * self.rho ** t, mub) for t in range(T + 1)])
+        seeds = [self.seed + b for b in range(B)]
+        return _UnrolledFn.apply(self.tau, self.lam, O, Y0, A0, mus, self.k, self.p, self.q, seeds)

@@ -601,7 +601,7 @@ template <typename T>
 int frsvt_impl(frsvt_context *h, int64_t m, int64_t n, const T *A, int64_t lda, double tau,
                int k, int p, int q, const T *Qprev, int r_prev, int64_t ldqp, uint64_t seed,
                uint64_t counter, T *X, int64_t ldx, T *Qout, int64_t ldqo, int32_t *r_out,
-               bool mixed = false)
+               bool mixed = false, T *Qsave = nullptr, int64_t ldqs = 0, double *factors = nullptr)
 {
     const Orient o = orient(m, n, lda);
     Core<T> c{};
@@ -643,12 +643,316 @@ int frsvt_impl(frsvt_context *h, int64_t m, int64_t n, const T *A, int64_t lda, 
     }
     carve_core<T>(cv, o, l, c.cnew, h->num_cu, b, mixed);
     if ((rc = run_core<T>(h, c, b))) return rc;
+    if (Qsave)
+        CK(hipMemcpy2DAsync(Qsave, ldqs * sizeof(T), b.Q, o.mh * sizeof(T), o.mh * sizeof(T), l,
+                            hipMemcpyDeviceToDevice, h->stream));
+    if (factors) {
+        CK(hipMemcpyAsync(factors, b.sigma, l * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+        CK(hipMemcpyAsync(factors + l, b.U, (size_t)l * l * sizeof(double), hipMemcpyDeviceToDevice,
+                          h->stream));
+    }
     if ((rc = write_x<T>(h, c, X, ldx, b.gpart_t))) return rc;
     if (r_out) {
         CK(hipMemcpyAsync(h->pinned, h->dstatus, 8 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
         CK(hipStreamSynchronize(h->stream));
         *r_out = ((int *)h->pinned)[0];
         if (((int *)h->pinned)[2] == 0) return FRSVT_NOT_CONVERGED;
+    }
+    return FRSVT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of the fresh-sketch FRSVT map X = Q S_tau(Q^T Ahat) of Alg. 1
+// (lines 4-6 and 13-21) for a fixed Omega.  The power iterations are
+// recomputed from the seed, Q_q is the saved basis of line 16 and (sigma,
+// U_B) the saved small factors.  With the blocks
+//   Lf = [Q_q, Ybar_q, Q_{q-1}, ..., Ybar_1, Q_0, Ybar_0]   (mh x (2q+2) l)
+//   Rf = [Bbar^T, Z_q, Zbar_q, ..., Z_1, Zbar_1, Omega]     (nh x (2q+2) l)
+// the gradient is Abar_hat = Lf Rf^T, written in one product.
+// ---------------------------------------------------------------------------
+template <typename T>
+int cross_gram(frsvt_context *h, int64_t rows, int l1, int l2, const T *X, int64_t ldx,
+               const T *Y, int64_t ldy, double *G, double *part)
+{
+    const int sk = gemm_splitk(l1, l2, rows, h->num_cu);
+    CKT(FRSVT_K_ADJOINT, (launch_gemm<T, double, double>(l1, l2, rows, X, ldx, 1, Y, 1, ldy, G, 1, l1,
+                                                         sk, part, h->stream)));
+    return FRSVT_OK;
+}
+
+// out = X1 C1 + X2 C2 (C = nullptr: identity), rows x l.
+template <typename T>
+int combine2(frsvt_context *h, int64_t rows, int l, const T *X1, int64_t ld1, const double *C1,
+             const T *X2, int64_t ld2, const double *C2, T *out, int64_t ldout)
+{
+    CombineArgs<T> a{};
+    a.rows = rows;
+    a.c = l;
+    a.nin = X2 ? 2 : 1;
+    a.in[0] = X1;
+    a.ldin[0] = ld1;
+    a.w[0] = l;
+    a.coef[0] = C1;
+    if (X2) {
+        a.in[1] = X2;
+        a.ldin[1] = ld2;
+        a.w[1] = l;
+        a.coef[1] = C2;
+    }
+    a.out = out;
+    a.ldout = ldout;
+    CKT(FRSVT_K_ADJOINT, launch_combine<T>(a, h->stream));
+    return FRSVT_OK;
+}
+
+template <typename T>
+struct VjpBuffers {
+    T *Lf, *Rf, *BC, *Ct, *Qb, *P, *Yt, *gpart_t;
+    double *R, *H, *M1, *M2, *Kd, *CA, *CB, *gpart_d;
+    CoreBuffers<T> ob;  // orthonormalisation scratch of the large path
+};
+
+template <typename T>
+size_t carve_vjp(Carver &cv, int mh, int64_t nh, int l, int q, VjpBuffers<T> &b)
+{
+    const size_t K = (size_t)(2 * q + 2) * l;
+    const size_t ll = (size_t)l * l;
+    b.Lf = cv.take<T>((size_t)mh * K);
+    b.Rf = cv.take<T>((size_t)nh * K);
+    b.BC = cv.take<T>((size_t)nh * 2 * l);
+    b.Ct = cv.take<T>((size_t)nh * l);
+    b.Qb = cv.take<T>((size_t)mh * l);
+    b.P = cv.take<T>((size_t)mh * 2 * l);
+    b.Yt = cv.take<T>((size_t)mh * l);
+    b.gpart_t = cv.take<T>((size_t)128 * mh * l);
+    b.R = cv.take<double>((size_t)(q + 1) * ll);
+    b.H = cv.take<double>(ll);
+    b.M1 = cv.take<double>(ll);
+    b.M2 = cv.take<double>(ll);
+    b.Kd = cv.take<double>(ll);
+    b.CA = cv.take<double>(ll);
+    b.CB = cv.take<double>(ll);
+    b.gpart_d = cv.take<double>((size_t)128 * ll);
+    b.ob = CoreBuffers<T>{};
+    b.ob.G = cv.take<double>(ll);
+    b.ob.R = cv.take<double>(ll);
+    b.ob.nullc = cv.take<int>((size_t)l);
+    b.ob.gpart_d = b.gpart_d;
+    return cv.off;
+}
+
+// Q = orth(Y) into Qdst (Y is kept): the one-workgroup CholeskyQR when it
+// fits, else the large-path sequence on a copy.
+template <typename T>
+int orth_copy(frsvt_context *h, int mh, int l, const T *Y, T *Qdst, VjpBuffers<T> &b,
+              uint64_t seed, uint64_t counter, int *flags)
+{
+    if (small_orth_ok(mh, l)) {
+        CKT(FRSVT_K_ORTH, launch_small_orth<T>(mh, (const T *)nullptr, mh, 0, Y, mh, l, Qdst, mh, seed,
+                                               counter, flags, h->stream));
+        return FRSVT_OK;
+    }
+    CK(hipMemcpyAsync(Qdst, Y, (size_t)mh * l * sizeof(T), hipMemcpyDeviceToDevice, h->stream));
+    return big_orth<T>(h, mh, l, Qdst, mh, b.ob, seed, counter, flags);
+}
+
+template <typename T>
+int frsvt_vjp_impl(frsvt_context *h, int64_t m, int64_t n, const T *A, int64_t lda, double tau,
+                   int l, int q, uint64_t seed, uint64_t counter, const T *Qs, int64_t ldqs,
+                   const double *factors, const T *Xb, int64_t ldxb, T *Ab, int64_t ldab,
+                   double *tau_bar)
+{
+    const Orient o = orient(m, n, lda);
+    const int mh = o.mh;
+    const int64_t nh = o.nh;
+    hipStream_t s = h->stream;
+    VjpBuffers<T> b{};
+    Carver dry(nullptr);
+    carve_vjp<T>(dry, mh, nh, l, q, b);
+    int rc = ensure_ws(h, dry.off);
+    if (rc) return rc;
+    Carver cv(h->ws);
+    carve_vjp<T>(cv, mh, nh, l, q, b);
+
+    Core<T> ca{};
+    ca.A = A;
+    ca.lda = lda;
+    ca.o = o;
+    Core<T> cx{};
+    cx.A = Xb;
+    cx.lda = ldxb;
+    cx.o = orient(m, n, ldxb);
+    auto Lb = [&](int j) { return b.Lf + (size_t)j * mh * l; };
+    auto Rb = [&](int j) { return b.Rf + (size_t)j * nh * l; };
+    auto Qi = [&](int i) { return i == q ? Lb(0) : Lb(2 * (q - i)); };
+    auto Zi = [&](int i) { return Rb(2 * (q - i) + 1); };
+    auto Zbar = [&](int i) { return Rb(2 * (q - i) + 2); };
+    auto Ybar = [&](int i) { return i > 0 ? Lb(2 * (q - i) + 1) : Lb(2 * q + 1); };
+    int *flags = h->dstatus + 4;
+    CKT(FRSVT_K_OTHER, launch_fill_int(h->dstatus + 4, 4, 0, s));
+
+    // forward recomputation: Omega, Y_0 = Ahat Omega, Q_i, Z_i = Ahat^T Q_{i-1},
+    // Y_i = Ahat Z_i, R_i = Q_i^T Y_i
+    CK(hipMemcpy2DAsync(Lb(0), mh * sizeof(T), Qs, ldqs * sizeof(T), mh * sizeof(T), l,
+                        hipMemcpyDeviceToDevice, s));
+    CKT(FRSVT_K_OTHER, launch_omega<T>(nh, l, seed, counter, Rb(2 * q + 1), nh, s));
+    if ((rc = ahat_times<T>(h, ca, Rb(2 * q + 1), nh, l, b.Yt, b.gpart_t))) return rc;
+    for (int i = 0; i <= q; ++i) {
+        if (i > 0) {
+            if ((rc = ahat_t_times<T>(h, ca, Qi(i - 1), mh, l, Zi(i), b.gpart_t))) return rc;
+            if ((rc = ahat_times<T>(h, ca, Zi(i), nh, l, b.Yt, b.gpart_t))) return rc;
+        }
+        if (i < q && (rc = orth_copy<T>(h, mh, l, b.Yt, Qi(i), b, seed, counter, flags))) return rc;
+        if ((rc = cross_gram<T>(h, mh, l, l, Qi(i), mh, b.Yt, mh, b.R + (size_t)i * l * l, b.gpart_d)))
+            return rc;
+    }
+
+    // line 16 again: B^T = Ahat^T Q; Sbar^T = Xbar_hat^T Q; H = Sbar B^T
+    T *Bt = b.BC, *Sbt = b.BC + (size_t)nh * l;
+    if ((rc = ahat_t_times<T>(h, ca, Lb(0), mh, l, Bt, b.gpart_t))) return rc;
+    if ((rc = ahat_t_times<T>(h, cx, Lb(0), mh, l, Sbt, b.gpart_t))) return rc;
+    if ((rc = cross_gram<T>(h, nh, l, l, Sbt, nh, Bt, nh, b.H, b.gpart_d))) return rc;
+    CKT(FRSVT_K_ADJOINT, launch_svt_vjp_small(l, factors, factors + l, b.H, tau, b.M1, b.M2, tau_bar, s));
+    // Bbar^T = B^T M1 + Sbar^T M2 (Rf block 0); C^T = B^T M2, the SVT of B
+    if ((rc = combine2<T>(h, nh, l, Bt, nh, b.M1, Sbt, nh, b.M2, Rb(0), nh))) return rc;
+    if ((rc = combine2<T>(h, nh, l, Bt, nh, b.M2, (const T *)nullptr, 0, nullptr, b.Ct, nh))) return rc;
+    // Qbar_q = Xbar_hat C^T + Ahat Bbar^T
+    T *P1 = b.P, *P2 = b.P + (size_t)mh * l;
+    if ((rc = ahat_times<T>(h, cx, b.Ct, nh, l, P1, b.gpart_t))) return rc;
+    if ((rc = ahat_times<T>(h, ca, Rb(0), nh, l, P2, b.gpart_t))) return rc;
+    if ((rc = combine2<T>(h, mh, l, P1, mh, nullptr, P2, mh, nullptr, b.Qb, mh))) return rc;
+
+    // back through the QR steps and the power iterations
+    for (int i = q; i >= 0; --i) {
+        if ((rc = cross_gram<T>(h, mh, l, l, b.Qb, mh, Qi(i), mh, b.Kd, b.gpart_d))) return rc;
+        CKT(FRSVT_K_ADJOINT, launch_qr_vjp_small(l, b.Kd, b.R + (size_t)i * l * l, b.CA, b.CB,
+                                                 h->dstatus + 7, s));
+        if ((rc = combine2<T>(h, mh, l, b.Qb, mh, b.CA, Qi(i), mh, b.CB, Ybar(i), mh))) return rc;
+        if (i > 0) {
+            if ((rc = ahat_t_times<T>(h, ca, Ybar(i), mh, l, Zbar(i), b.gpart_t))) return rc;
+            if ((rc = ahat_times<T>(h, ca, Zbar(i), nh, l, b.Qb, b.gpart_t))) return rc;
+        }
+    }
+
+    const int K = (2 * q + 2) * l;
+    const int64_t scm = o.trans ? ldab : 1, scn = o.trans ? 1 : ldab;
+    return mm<T>(h, mh, nh, K, b.Lf, 1, mh, b.Rf, nh, 1, Ab, scm, scn, 1, (T *)nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// Unrolled inexact-ALM pieces: the step after the thresholding, its reverse,
+// and the starting point.
+// ---------------------------------------------------------------------------
+template <typename T>
+int dual_step_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, const T *L,
+                   int64_t ldl, const T *Y, int64_t ldy, double lam, double mu, double mu_next,
+                   T *S, int64_t lds, T *Yn, int64_t ldyn, T *An, int64_t ldan)
+{
+    DualStepArgs<T> a{};
+    a.m = m;
+    a.n = n;
+    a.O = O;
+    a.ldo = ldo;
+    a.L = L;
+    a.ldl = ldl;
+    a.Y = Y;
+    a.ldy = ldy;
+    a.lam = lam;
+    a.mu = mu;
+    a.mu_next = mu_next;
+    a.S = S;
+    a.lds = lds;
+    a.Yn = Yn;
+    a.ldyn = ldyn;
+    a.An = An;
+    a.ldan = ldan;
+    CKT(FRSVT_K_EPILOGUE, launch_dual_step<T>(a, false, nullptr, h->stream));
+    return FRSVT_OK;
+}
+
+template <typename T>
+int dual_step_vjp_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo,
+                       const T *L, int64_t ldl, const T *Y, int64_t ldy, double lam, double mu,
+                       double mu_next, const T *Sb, int64_t ldsb, const T *Ynb, int64_t ldynb,
+                       const T *Anb, int64_t ldanb, T *Lb, int64_t ldlb, T *Yb, int64_t ldyb,
+                       double *lam_bar)
+{
+    int rc = ensure_ws(h, (size_t)kDualGrid * sizeof(double) + 256);
+    if (rc) return rc;
+    DualStepArgs<T> a{};
+    a.m = m;
+    a.n = n;
+    a.O = O;
+    a.ldo = ldo;
+    a.L = L;
+    a.ldl = ldl;
+    a.Y = Y;
+    a.ldy = ldy;
+    a.lam = lam;
+    a.mu = mu;
+    a.mu_next = mu_next;
+    a.Sb = Sb;
+    a.ldsb = ldsb;
+    a.Ynb = Ynb;
+    a.ldynb = ldynb;
+    a.Anb = Anb;
+    a.ldanb = ldanb;
+    a.Lb = Lb;
+    a.ldlb = ldlb;
+    a.Yb = Yb;
+    a.ldyb = ldyb;
+    a.part = (double *)h->ws;
+    int np = 0;
+    CKT(FRSVT_K_ADJOINT, launch_dual_step<T>(a, true, &np, h->stream));
+    if (lam_bar) CKT(FRSVT_K_REDUCE, launch_reduce<double>(a.part, 1, np, lam_bar, h->stream));
+    return FRSVT_OK;
+}
+
+// ||O||_F and ||O||_inf (host; waits), FRSVT_ERR_NONFINITE on NaN or Inf.
+template <typename T>
+int input_norms(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, double *normF,
+                double *mx)
+{
+    hipStream_t s = h->stream;
+    CKT(FRSVT_K_OTHER, launch_fill_int(h->dstatus + 16, 1, 0, s));
+    CKT(FRSVT_K_OTHER, launch_finite_check<T>(m, n, O, ldo, h->dstatus + 16, s));
+    int nparts = 0;
+    CKT(FRSVT_K_OTHER, launch_norms<T>(m, n, O, ldo, h->dscalars + 16, &nparts, s));
+    CK(hipMemcpyAsync(h->pinned, h->dstatus + 16, sizeof(int), hipMemcpyDeviceToHost, s));
+    CK(hipMemcpyAsync((char *)h->pinned + 64, h->dscalars + 16, 2 * nparts * sizeof(double),
+                      hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    if (((int *)h->pinned)[0]) return FRSVT_ERR_NONFINITE;
+    double ss = 0.0, mxv = 0.0;
+    const double *np = (const double *)((char *)h->pinned + 64);
+    for (int g = 0; g < nparts; ++g) {
+        ss += np[2 * g];
+        mxv = std::max(mxv, np[2 * g + 1]);
+    }
+    *normF = std::sqrt(ss);
+    *mx = mxv;
+    return FRSVT_OK;
+}
+
+template <typename T>
+int spectral_norm(frsvt_context *h, const T *A, int64_t lda, const Orient &o, double *out);
+
+template <typename T>
+int rpca_init_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, double lambda,
+                   double mu0, T *Y0, int64_t ldy, T *A0, int64_t lda0, double *out)
+{
+    double normF = 0.0, mx = 0.0, norm2 = 0.0;
+    int rc = input_norms<T>(h, m, n, O, ldo, &normF, &mx);
+    if (rc) return rc;
+    if ((rc = spectral_norm<T>(h, O, ldo, orient(m, n, ldo), &norm2))) return rc;
+    const double J = std::max(norm2, mx / lambda);
+    const double mu = mu0 > 0.0 ? mu0 : (norm2 > 0.0 ? 1.25 / norm2 : 1.0);
+    CKT(FRSVT_K_OTHER, launch_rpca_init<T>(m, n, O, ldo, J > 0.0 ? 1.0 / J : 0.0, 1.0 / mu, Y0, ldy, A0,
+                                           lda0, h->stream));
+    if (out) {
+        out[0] = norm2;
+        out[1] = mu;
+        out[2] = J;
     }
     return FRSVT_OK;
 }
@@ -697,24 +1001,8 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
     hipStream_t s = h->stream;
     int rc;
 
-    // non-finite input
-    CK(hipMemsetAsync(h->dstatus + 16, 0, sizeof(int), s));
-    CKT(FRSVT_K_OTHER, launch_finite_check<T>(m, n, O, ldo, h->dstatus + 16, s));
-    // ||O||_F and ||O||_inf
-    int nparts = 0;
-    CKT(FRSVT_K_OTHER, launch_norms<T>(m, n, O, ldo, h->dscalars + 16, &nparts, s));
-    CK(hipMemcpyAsync(h->pinned, h->dstatus + 16, sizeof(int), hipMemcpyDeviceToHost, s));
-    CK(hipMemcpyAsync((char *)h->pinned + 64, h->dscalars + 16, 2 * nparts * sizeof(double),
-                      hipMemcpyDeviceToHost, s));
-    CK(hipStreamSynchronize(s));
-    if (((int *)h->pinned)[0]) return FRSVT_ERR_NONFINITE;
-    double ss = 0.0, mx = 0.0;
-    const double *np = (const double *)((char *)h->pinned + 64);
-    for (int g = 0; g < nparts; ++g) {
-        ss += np[2 * g];
-        mx = std::max(mx, np[2 * g + 1]);
-    }
-    const double normF = std::sqrt(ss);
+    double normF = 0.0, mx = 0.0;
+    if ((rc = input_norms<T>(h, m, n, O, ldo, &normF, &mx))) return rc;
     double norm2 = 0.0;
     if ((rc = spectral_norm<T>(h, O, ldo, o, &norm2))) return rc;
     if (!(normF > 0.0) || !(norm2 > 0.0)) {
@@ -1394,6 +1682,163 @@ int wsvt_batched(frsvt_handle h, int64_t count, const int32_t *rows, const int32
     if (count == 0) return FRSVT_OK;
     if (count > (int64_t)1 << 30) return FRSVT_ERR_UNSUPPORTED;
     return wsvt_batched_impl(h, count, rows, cols, offsets, A_packed, X_packed, *rule, ranks);
+}
+
+int frsvt_fwd(frsvt_handle h, frsvt_precision prec, int64_t m, int64_t n, const void *A,
+              int64_t lda, double tau, int32_t k, int32_t p, int32_t q, uint64_t seed,
+              uint64_t counter, void *X, int64_t ldx, void *Q, int64_t ldq, double *factors)
+{
+    if (!h) return -1;
+    if (prec != FRSVT_F64 && prec != FRSVT_F32) return -2;
+    if (m < 1) return -3;
+    if (n < 1) return -4;
+    if (bad_ptr(A)) return -5;
+    if (lda < m) return -6;
+    if (!(tau >= 0.0) || !std::isfinite(tau)) return -7;
+    if (k < 0 || p < 0 || k + p < 1) return -8;
+    if (p < 0) return -9;
+    if (q < 0 || q > 64) return -10;
+    if (bad_ptr(X)) return -13;
+    if (ldx < m) return -14;
+    const int64_t mh = std::min(m, n);
+    if (bad_ptr(Q)) return -15;
+    if (ldq < mh) return -16;
+    if (bad_ptr(factors)) return -17;
+    if (std::min<int64_t>(mh, (int64_t)k + p) > 64) return FRSVT_ERR_UNSUPPORTED;
+    if (prec == FRSVT_F64)
+        return frsvt_impl<double>(h, m, n, (const double *)A, lda, tau, k, p, q, nullptr, 0, mh, seed,
+                                  counter, (double *)X, ldx, nullptr, mh, nullptr, false, (double *)Q,
+                                  ldq, factors);
+    return frsvt_impl<float>(h, m, n, (const float *)A, lda, tau, k, p, q, nullptr, 0, mh, seed, counter,
+                             (float *)X, ldx, nullptr, mh, nullptr, false, (float *)Q, ldq, factors);
+}
+
+int frsvt_vjp(frsvt_handle h, frsvt_precision prec, int64_t m, int64_t n, const void *A,
+              int64_t lda, double tau, int32_t k, int32_t p, int32_t q, uint64_t seed,
+              uint64_t counter, const void *Q, int64_t ldq, const double *factors,
+              const void *X_bar, int64_t ldxb, void *A_bar, int64_t ldab, double *tau_bar)
+{
+    if (!h) return -1;
+    if (prec != FRSVT_F64 && prec != FRSVT_F32) return -2;
+    if (m < 1) return -3;
+    if (n < 1) return -4;
+    if (bad_ptr(A)) return -5;
+    if (lda < m) return -6;
+    if (!(tau >= 0.0) || !std::isfinite(tau)) return -7;
+    if (k < 0 || p < 0 || k + p < 1) return -8;
+    if (p < 0) return -9;
+    if (q < 0 || q > 64) return -10;
+    const int64_t mh = std::min(m, n);
+    if (bad_ptr(Q)) return -13;
+    if (ldq < mh) return -14;
+    if (bad_ptr(factors)) return -15;
+    if (bad_ptr(X_bar)) return -16;
+    if (ldxb < m) return -17;
+    if (bad_ptr(A_bar)) return -18;
+    if (ldab < m) return -19;
+    const int l = (int)std::min<int64_t>(mh, (int64_t)k + p);
+    if (l > 64) return FRSVT_ERR_UNSUPPORTED;
+    if (prec == FRSVT_F64)
+        return frsvt_vjp_impl<double>(h, m, n, (const double *)A, lda, tau, l, q, seed, counter,
+                                      (const double *)Q, ldq, factors, (const double *)X_bar, ldxb,
+                                      (double *)A_bar, ldab, tau_bar);
+    return frsvt_vjp_impl<float>(h, m, n, (const float *)A, lda, tau, l, q, seed, counter,
+                                 (const float *)Q, ldq, factors, (const float *)X_bar, ldxb,
+                                 (float *)A_bar, ldab, tau_bar);
+}
+
+int rpca_dual_step(frsvt_handle h, frsvt_precision prec, int64_t m, int64_t n, const void *O,
+                   int64_t ldo, const void *L, int64_t ldl, const void *Y, int64_t ldy, double lam,
+                   double mu, double mu_next, void *S, int64_t lds, void *Y_next, int64_t ldyn,
+                   void *A_next, int64_t ldan)
+{
+    if (!h) return -1;
+    if (prec != FRSVT_F64 && prec != FRSVT_F32) return -2;
+    if (m < 1) return -3;
+    if (n < 1) return -4;
+    if (bad_ptr(O)) return -5;
+    if (ldo < m) return -6;
+    if (bad_ptr(L)) return -7;
+    if (ldl < m) return -8;
+    if (bad_ptr(Y)) return -9;
+    if (ldy < m) return -10;
+    if (!(lam >= 0.0) || !std::isfinite(lam)) return -11;
+    if (!(mu > 0.0) || !std::isfinite(mu)) return -12;
+    if (!(mu_next > 0.0) || !std::isfinite(mu_next)) return -13;
+    if (S && lds < m) return -15;
+    if (Y_next && ldyn < m) return -17;
+    if (A_next && ldan < m) return -19;
+    if (prec == FRSVT_F64)
+        return dual_step_impl<double>(h, m, n, (const double *)O, ldo, (const double *)L, ldl,
+                                      (const double *)Y, ldy, lam, mu, mu_next, (double *)S, lds,
+                                      (double *)Y_next, ldyn, (double *)A_next, ldan);
+    return dual_step_impl<float>(h, m, n, (const float *)O, ldo, (const float *)L, ldl,
+                                 (const float *)Y, ldy, lam, mu, mu_next, (float *)S, lds,
+                                 (float *)Y_next, ldyn, (float *)A_next, ldan);
+}
+
+int rpca_dual_step_vjp(frsvt_handle h, frsvt_precision prec, int64_t m, int64_t n, const void *O,
+                       int64_t ldo, const void *L, int64_t ldl, const void *Y, int64_t ldy,
+                       double lam, double mu, double mu_next, const void *S_bar, int64_t ldsb,
+                       const void *Y_next_bar, int64_t ldynb, const void *A_next_bar,
+                       int64_t ldanb, void *L_bar, int64_t ldlb, void *Y_bar, int64_t ldyb,
+                       double *lam_bar)
+{
+    if (!h) return -1;
+    if (prec != FRSVT_F64 && prec != FRSVT_F32) return -2;
+    if (m < 1) return -3;
+    if (n < 1) return -4;
+    if (bad_ptr(O)) return -5;
+    if (ldo < m) return -6;
+    if (bad_ptr(L)) return -7;
+    if (ldl < m) return -8;
+    if (bad_ptr(Y)) return -9;
+    if (ldy < m) return -10;
+    if (!(lam >= 0.0) || !std::isfinite(lam)) return -11;
+    if (!(mu > 0.0) || !std::isfinite(mu)) return -12;
+    if (!(mu_next > 0.0) || !std::isfinite(mu_next)) return -13;
+    if (S_bar && ldsb < m) return -15;
+    if (Y_next_bar && ldynb < m) return -17;
+    if (A_next_bar && ldanb < m) return -19;
+    if (bad_ptr(L_bar)) return -20;
+    if (ldlb < m) return -21;
+    if (bad_ptr(Y_bar)) return -22;
+    if (ldyb < m) return -23;
+    if (prec == FRSVT_F64)
+        return dual_step_vjp_impl<double>(h, m, n, (const double *)O, ldo, (const double *)L, ldl,
+                                          (const double *)Y, ldy, lam, mu, mu_next,
+                                          (const double *)S_bar, ldsb, (const double *)Y_next_bar,
+                                          ldynb, (const double *)A_next_bar, ldanb,
+                                          (double *)L_bar, ldlb, (double *)Y_bar, ldyb, lam_bar);
+    return dual_step_vjp_impl<float>(h, m, n, (const float *)O, ldo, (const float *)L, ldl,
+                                     (const float *)Y, ldy, lam, mu, mu_next, (const float *)S_bar,
+                                     ldsb, (const float *)Y_next_bar, ldynb,
+                                     (const float *)A_next_bar, ldanb, (float *)L_bar, ldlb,
+                                     (float *)Y_bar, ldyb, lam_bar);
+}
+
+int rpca_init(frsvt_handle h, frsvt_precision prec, int64_t m, int64_t n, const void *O,
+              int64_t ldo, double lambda, double mu0, void *Y0, int64_t ldy, void *A0,
+              int64_t lda0, double *out)
+{
+    if (!h) return -1;
+    if (prec != FRSVT_F64 && prec != FRSVT_F32) return -2;
+    if (m < 1) return -3;
+    if (n < 1) return -4;
+    if (bad_ptr(O)) return -5;
+    if (ldo < m) return -6;
+    if (!(lambda > 0.0) || !std::isfinite(lambda)) return -7;
+    if (!std::isfinite(mu0)) return -8;
+    if (bad_ptr(Y0)) return -9;
+    if (ldy < m) return -10;
+    if (bad_ptr(A0)) return -11;
+    if (lda0 < m) return -12;
+    if (std::min(m, n) > 1024) return FRSVT_ERR_UNSUPPORTED;
+    if (prec == FRSVT_F64)
+        return rpca_init_impl<double>(h, m, n, (const double *)O, ldo, lambda, mu0, (double *)Y0, ldy,
+                                      (double *)A0, lda0, out);
+    return rpca_init_impl<float>(h, m, n, (const float *)O, ldo, lambda, mu0, (float *)Y0, ldy,
+                                 (float *)A0, lda0, out);
 }
 
 }  // extern "C"

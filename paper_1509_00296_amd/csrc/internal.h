@@ -215,3 +215,67 @@ struct WsvtBatchArgs {
 size_t wsvt_batched_lds();
 hipError_t launch_wsvt_batched(const WsvtBatchArgs &a, int grid, hipStream_t s);
 }  // namespace frk
+
+namespace frk {
+// Adjoint pieces (adjoint.hip).
+// M1, M2 (l x l) of the SVT VJP on the small factors sigma, U of B and
+// H = Sbar B^T; taubar (device, optional).  l <= 64.
+hipError_t launch_svt_vjp_small(int l, const double *sigma, const double *U, const double *H,
+                                double tau, double *M1, double *M2, double *tau_bar, hipStream_t s);
+// CA = R^{-T}, CB = copyltu(-K) R^{-T} for the QR VJP; l <= 64.
+hipError_t launch_qr_vjp_small(int l, const double *K, const double *R, double *CA, double *CB,
+                               int *flags, hipStream_t s);
+
+// p[0..count) = value.
+hipError_t launch_fill_int(int *p, int count, int value, hipStream_t s);
+
+constexpr int kCombineMaxIn = 3;
+template <typename T>
+struct CombineArgs {
+    int64_t rows;
+    int c;
+    int nin;
+    const T *in[kCombineMaxIn];
+    int64_t ldin[kCombineMaxIn];
+    int w[kCombineMaxIn];
+    const double *coef[kCombineMaxIn];  // w_b x c, column-major; nullptr = identity
+    T *out;
+    int64_t ldout;
+};
+template <typename T>
+hipError_t launch_combine(const CombineArgs<T> &a, hipStream_t s);
+
+constexpr int kDualGrid = 1024;
+template <typename T>
+struct DualStepArgs {
+    int64_t m, n;
+    const T *O;
+    int64_t ldo;
+    const T *L;
+    int64_t ldl;
+    const T *Y;
+    int64_t ldy;
+    double lam, mu, mu_next;
+    // forward outputs (each optional)
+    T *S;
+    int64_t lds;
+    T *Yn;
+    int64_t ldyn;
+    T *An;
+    int64_t ldan;
+    // reverse: upstream gradients (optional), outputs, lambar partials
+    const T *Sb;
+    int64_t ldsb;
+    const T *Ynb;
+    int64_t ldynb;
+    const T *Anb;
+    int64_t ldanb;
+    T *Lb;
+    int64_t ldlb;
+    T *Yb;
+    int64_t ldyb;
+    double *part;  // [grid]
+};
+template <typename T>
+hipError_t launch_dual_step(const DualStepArgs<T> &a, bool vjp, int *nparts, hipStream_t s);
+}  // namespace frk

@@ -105,4 +105,6 @@ def rpca_batch(seed: int = 0, batch: int = 16, m: int = 4096, n: int = 256, rank
         O, L, _ = rpca(seed * 1000 + b, m, n, rank, frac, np.float64)
         Os.append(O)
         Ls.append(L)
-    return np.stack(Os).astype(dtype), np.stack(Ls).astype(dtype)
+    # (batch, n, m) in C order, viewed as (batch, m, n): instance b is column-major
+    cm = lambda xs: np.stack([x.T for x in xs]).astype(dtype).transpose(0, 2, 1)
+    return cm(Os), cm(Ls)

@@ -1,0 +1,309 @@
+"""GPU adjoint of FRSVT and of the unrolled inexact-ALM RPCA, against the
+oracle: central finite differences (h = 1e-4, FP64) of the oracle's own
+FRSVT with the same Omega, and the oracle's full-SVD gradient where the two
+derivatives coincide (rank(A) = l with at least one power iteration).
+
+Bounds.  A central difference along a unit direction E has truncation error
+h^2/6 |f'''| ~ 1e-8 relative here, so the directional derivatives must agree
+to 1e-6 of ||Abar||_F.  Where the derivatives coincide exactly the FP64
+gradient must match the oracle's to 1e-10 (relative Frobenius).  The FP32
+adjoint carries float rounding of every product (about 1e-6 relative per
+pass, amplified by the conditioning of the triangular factors), bounded
+here by 1e-3.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def fr():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1509_00296_amd as fr
+    fr.handle(0)
+    return fr
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.build()
+    return oracle
+
+
+def _cuda(a, dtype=torch.float64):
+    return torch.from_numpy(np.asfortranarray(a)).to(device="cuda", dtype=dtype)
+
+
+def _lowrank(rng, m, n, s, noise=0.0):
+    k = len(s)
+    U, _ = np.linalg.qr(rng.standard_normal((m, k)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, k)))
+    return (U * np.asarray(s)) @ V.T + noise * rng.standard_normal((m, n))
+
+
+CASES = [
+    # m, n, k, p, q, tau, spectrum
+    (60, 90, 6, 4, 1, 0.8, np.linspace(10, 1, 14)),
+    (120, 50, 5, 3, 2, 2.0, np.linspace(8, 0.5, 12)),
+    (40, 70, 6, 2, 0, 0.3, np.linspace(5, 1, 30)),
+    (300, 64, 10, 6, 1, 1.5, np.linspace(20, 1, 20)),
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_frsvt_vjp_matches_central_differences(fr, orc, case):
+    m, n, k, p, q, tau, spec = CASES[case]
+    _say(f"case frsvt_vjp fd m={m} n={n} l={k + p} q={q} tau={tau}")
+    rng = np.random.default_rng(100 + case)
+    A = _lowrank(rng, m, n, spec, noise=0.01)
+    Xb = rng.standard_normal((m, n))
+    seed, ctr = 7 + case, 3
+    Ad = _cuda(A)
+    X, Q, fac = fr.frsvt_fwd(Ad, tau, k, p, q, seed=seed, counter=ctr)
+    Ab, tb = fr.frsvt_vjp(Ad, tau, k, p, q, Q, fac, _cuda(Xb), seed=seed, counter=ctr)
+    torch.cuda.synchronize()
+    Ab = Ab.cpu().numpy()
+    tb = float(tb.cpu())
+    mh, nh, l = min(m, n), max(m, n), min(k + p, min(m, n))
+    Om = orc.gaussian_matrix(seed, ctr, nh, l)
+    Xo = orc.frsvt(A, tau, q, Om)[0]
+    assert np.linalg.norm(X.cpu().numpy() - Xo) <= 1e-10 * np.linalg.norm(Xo)
+    f = lambda AA, t: float(np.sum(Xb * orc.frsvt(AA, t, q, Om)[0]))
+    h = 1e-4
+    scale = np.linalg.norm(Ab)
+    worst = 0.0
+    for trial in range(4):
+        E = rng.standard_normal((m, n))
+        E /= np.linalg.norm(E)
+        fd = (f(A + h * E, tau) - f(A - h * E, tau)) / (2 * h)
+        worst = max(worst, abs(fd - np.sum(Ab * E)) / scale)
+    # one coordinate direction too
+    E = np.zeros((m, n))
+    E[m // 3, n // 2] = 1.0
+    fd = (f(A + h * E, tau) - f(A - h * E, tau)) / (2 * h)
+    worst = max(worst, abs(fd - Ab[m // 3, n // 2]) / scale)
+    fdt = (f(A, tau + h) - f(A, tau - h)) / (2 * h)
+    terr = abs(fdt - tb) / max(1.0, abs(fdt))
+    _say(f"  directional worst {worst:.2e}, tau {tb:.10e} vs fd {fdt:.10e} ({terr:.1e})")
+    assert worst <= 1e-6
+    assert terr <= 1e-6
+
+
+@pytest.mark.parametrize("q", [1, 2])
+@pytest.mark.parametrize("shape", [(50, 80), (90, 40)])
+def test_frsvt_vjp_equals_full_svd_gradient_at_rank_l(fr, orc, q, shape):
+    """rank(A) = l and q >= 1: the sketch spans range(A) exactly and the
+    FRSVT gradient is the exact SVT gradient."""
+    m, n = shape
+    l = 8
+    _say(f"case frsvt_vjp vs full-SVD gradient m={m} n={n} l={l} q={q}")
+    rng = np.random.default_rng(31 + q)
+    A = _lowrank(rng, m, n, np.linspace(12, 1.5, l))
+    Xb = rng.standard_normal((m, n))
+    tau = 2.2
+    Ad = _cuda(A)
+    X, Q, fac = fr.frsvt_fwd(Ad, tau, l, 0, q, seed=5)
+    Ab, tb = fr.frsvt_vjp(Ad, tau, l, 0, q, Q, fac, _cuda(Xb), seed=5)
+    Ae, te = orc.svt_vjp(A, tau, Xb)
+    err = np.linalg.norm(Ab.cpu().numpy() - Ae) / np.linalg.norm(Ae)
+    _say(f"  relative error {err:.2e}, tau_bar {float(tb.cpu()):.12e} vs {te:.12e}")
+    assert err <= 1e-10
+    assert abs(float(tb.cpu()) - te) <= 1e-10 * max(1.0, abs(te))
+
+
+def test_frsvt_vjp_full_basis_is_svt_gradient_with_straddling_pair(fr, orc):
+    """l = mhat: FRSVT is exact SVT, so its adjoint is the exact SVT adjoint;
+    a pair straddling tau within 1e-12 uses the stated value 1/2 on both
+    sides.  A is diagonal, so the singular vectors are fixed."""
+    _say("case frsvt_vjp straddling pair, l = mhat")
+    m, n, tau = 14, 9, 2.0
+    s = np.array([9.0, 7.0, 5.0, tau + 1e-13, tau - 5e-13, 1.0, 0.5, 0.2, 0.1])
+    A = np.zeros((m, n))
+    A[np.arange(n), np.arange(n)] = s
+    Xb = np.random.default_rng(2).standard_normal((m, n))
+    Ad = _cuda(A)
+    X, Q, fac = fr.frsvt_fwd(Ad, tau, n, 0, 1, seed=1)
+    Ab, tb = fr.frsvt_vjp(Ad, tau, n, 0, 1, Q, fac, _cuda(Xb), seed=1)
+    Ae, te = orc.svt_vjp(A, tau, Xb)
+    Ab = Ab.cpu().numpy()
+    assert np.all(np.isfinite(Ab))
+    assert np.linalg.norm(Ab) <= np.linalg.norm(Xb) * (1 + 1e-8)
+    # The pair's singular vectors are fixed only up to a rotation of order
+    # u ||A||^2 / (s_3^2 - s_4^2) by any Gram-based SVD (a kink of SVT), so
+    # the comparison leaves out rows and columns 3 and 4.
+    keep_r = [i for i in range(m) if i not in (3, 4)]
+    keep_c = [j for j in range(n) if j not in (3, 4)]
+    d = Ab[np.ix_(keep_r, keep_c)] - Ae[np.ix_(keep_r, keep_c)]
+    assert np.linalg.norm(d) <= 1e-10 * np.linalg.norm(Ae)
+    blk = Ab[3:5, 3:5]
+    assert np.linalg.norm(blk) <= np.linalg.norm(Xb[3:5, 3:5]) * (1 + 1e-8)
+
+
+def test_frsvt_vjp_fp32_against_fp64(fr):
+    m, n, k, p, q, tau = 256, 2048, 5, 5, 1, 3.0
+    _say(f"case frsvt_vjp fp32 vs fp64 m={m} n={n}")
+    rng = np.random.default_rng(12)
+    A = _lowrank(rng, m, n, [60, 40, 30, 20, 10, 4, 3, 2, 1.5, 1.0, 0.9, 0.8], noise=0.05)
+    Xb = rng.standard_normal((m, n))
+    out = {}
+    for dt in (torch.float64, torch.float32):
+        Ad = _cuda(A, dt)
+        X, Q, fac = fr.frsvt_fwd(Ad, tau, k, p, q, seed=9)
+        Ab, tb = fr.frsvt_vjp(Ad, tau, k, p, q, Q, fac, _cuda(Xb, dt), seed=9)
+        out[dt] = (Ab.double().cpu().numpy(), float(tb.cpu()))
+    e = np.linalg.norm(out[torch.float32][0] - out[torch.float64][0]) / np.linalg.norm(out[torch.float64][0])
+    et = abs(out[torch.float32][1] - out[torch.float64][1]) / abs(out[torch.float64][1])
+    _say(f"  fp32 vs fp64: Abar {e:.2e}, tau_bar {et:.2e}")
+    assert e <= 1e-3 and et <= 1e-3
+
+
+def test_frsvt_autograd_function(fr):
+    """torch.autograd through the FRSVT Function: A.grad and tau.grad equal
+    the direct VJP, and a row-major A is handled as its transpose."""
+    _say("case frsvt autograd function")
+    rng = np.random.default_rng(4)
+    A = _lowrank(rng, 70, 45, np.linspace(9, 1, 10), noise=0.02)
+    W = rng.standard_normal((70, 45))
+    for rowmajor in (False, True):
+        Ad = torch.tensor(A, device="cuda") if rowmajor else _cuda(A)
+        Ad.requires_grad_(True)
+        tau = torch.tensor(1.1, dtype=torch.float64, requires_grad=True)
+        X = fr.frsvt_ad(Ad, tau, 6, 3, 1, seed=2)
+        loss = (X * torch.tensor(W, device="cuda")).sum()
+        loss.backward()
+        _, Q, fac = fr.frsvt_fwd(_cuda(A), 1.1, 6, 3, 1, seed=2)
+        Ab, tb = fr.frsvt_vjp(_cuda(A), 1.1, 6, 3, 1, Q, fac, _cuda(W), seed=2)
+        assert torch.allclose(Ad.grad, Ab, rtol=0, atol=1e-12 * float(Ab.abs().max()))
+        assert abs(float(tau.grad) - float(tb.cpu())) <= 1e-12 * abs(float(tb.cpu()))
+
+
+def test_dual_step_and_vjp(fr, orc):
+    _say("case rpca_dual_step forward and vjp")
+    rng = np.random.default_rng(6)
+    m, n = 33, 21
+    O, L, Y = (rng.standard_normal((m, n)) for _ in range(3))
+    lam, mu, mun = 0.6, 0.9, 1.35
+    S, Yn, An = fr.dual_step(_cuda(O), _cuda(L), _cuda(Y), lam, mu, mun, want_S=True)
+    So, Yo, Ao = orc.dual_step(O, L, Y, lam, mu, mun)
+    for g, o in ((S, So), (Yn, Yo), (An, Ao)):
+        assert np.abs(g.cpu().numpy() - o).max() <= 1e-13 * max(1.0, np.abs(o).max())
+    Sb, Ynb, Anb = (rng.standard_normal((m, n)) for _ in range(3))
+    Lb, Yb, lb = fr.dual_step_vjp(_cuda(O), _cuda(L), _cuda(Y), lam, mu, mun, _cuda(Sb),
+                                  _cuda(Ynb), _cuda(Anb))
+    Lb, Yb, lb = Lb.cpu().numpy(), Yb.cpu().numpy(), float(lb.cpu())
+
+    def f(LL, YY, ll):
+        s_, y_, a_ = orc.dual_step(O, LL, YY, ll, mu, mun)
+        return np.sum(Sb * s_) + np.sum(Ynb * y_) + np.sum(Anb * a_)
+
+    h = 1e-4
+    for (i, j) in ((0, 0), (5, 7), (32, 20), (11, 3)):
+        E = np.zeros((m, n))
+        E[i, j] = 1.0
+        assert abs((f(L + h * E, Y, lam) - f(L - h * E, Y, lam)) / (2 * h) - Lb[i, j]) <= 1e-8
+        assert abs((f(L, Y + h * E, lam) - f(L, Y - h * E, lam)) / (2 * h) - Yb[i, j]) <= 1e-8
+    fdl = (f(L, Y, lam + h) - f(L, Y, lam - h)) / (2 * h)
+    assert abs(fdl - lb) <= 1e-7 * max(1.0, abs(fdl))
+
+
+def _loss_grads_gpu(fr, O, Lt, taus, lams, k, p, q, dtype):
+    model = fr.UnrolledRPCA(taus, lams, k=k, p=p, q=q, seed=0)
+    Od = torch.from_numpy(O).to(device="cuda", dtype=dtype)
+    Ltd = torch.from_numpy(Lt).to(device="cuda", dtype=dtype)
+    Lhat = model(Od)
+    loss = ((Lhat - Ltd) ** 2).sum()
+    loss.backward()
+    return (Lhat.detach().double().cpu().numpy(), float(loss.detach()), model.tau.grad.numpy(),
+            model.lam.grad.numpy())
+
+
+def test_unrolled_rpca_gradients_fp64(fr, orc):
+    """Small unrolled RPCA (2 instances, 4 steps): forward against the oracle,
+    per-step threshold gradients against the oracle's central differences."""
+    from paper_1509_00296_amd import synth
+    B, m, n, T, k, p, q = 2, 72, 40, 4, 3, 3, 1
+    _say(f"case unrolled rpca fp64 B={B} {m}x{n} T={T}")
+    O, Lt = synth.rpca_batch(seed=3, batch=B, m=m, n=n, rank=3, frac=0.05, dtype=np.float64)
+    lam = 1.0 / np.sqrt(m)
+    norm2 = [orc.svd(O[b])[1][0] for b in range(B)]
+    mus = [1.25 / norm2[0] * 1.5 ** t for t in range(T)]
+    taus = np.array([1.0 / mu for mu in mus])
+    lams = np.array([lam / mu for mu in mus])
+    Lg, loss_g, gt, gl = _loss_grads_gpu(fr, O, Lt, taus, lams, k, p, q, torch.float64)
+
+    def loss_o(tt, ll):
+        tot = 0.0
+        for b in range(B):
+            L = orc.rpca_unrolled(O[b], tt, ll, k=k, p=p, q=q, seed=b, lam=lam, norm2=norm2[b])
+            tot += np.sum((L - Lt[b]) ** 2)
+        return tot
+
+    for b in range(B):
+        Lo = orc.rpca_unrolled(O[b], taus, lams, k=k, p=p, q=q, seed=b, lam=lam, norm2=norm2[b])
+        assert np.linalg.norm(Lg[b] - Lo) <= 1e-10 * np.linalg.norm(Lo)
+    h = 1e-4
+    gmax = max(np.abs(gt).max(), np.abs(gl).max())
+    for t in range(T):
+        e = np.zeros(T)
+        e[t] = 1.0
+        fdt = (loss_o(taus + h * e, lams) - loss_o(taus - h * e, lams)) / (2 * h)
+        fdl = (loss_o(taus, lams + h * e) - loss_o(taus, lams - h * e)) / (2 * h)
+        _say(f"  step {t}: tau grad {gt[t]:.8e} fd {fdt:.8e} | lam grad {gl[t]:.8e} fd {fdl:.8e}")
+        assert abs(gt[t] - fdt) <= 1e-6 * gmax
+        assert abs(gl[t] - fdl) <= 1e-6 * gmax
+    assert gl[T - 1] == 0.0   # the last shrink threshold does not reach L_T
+
+
+def test_unrolled_rpca_full_size_fp32(fr, orc):
+    """16 instances of 4096 x 256 (rank 5, 5% outliers), 10 unrolled steps,
+    l = 10, q = 1, FP32 on the device.  Forward against the FP64 oracle on
+    two instances; per-step gradients of instance 0's loss against the
+    oracle's central differences on a sample of thresholds."""
+    from paper_1509_00296_amd import synth
+    B, m, n, T, k, p, q = 16, 4096, 256, 10, 5, 5, 1
+    _say(f"case unrolled rpca fp32 full size B={B} {m}x{n} T={T}")
+    O, Lt = synth.rpca_batch(seed=0, batch=B, m=m, n=n, rank=5, frac=0.05, dtype=np.float32)
+    O64, Lt64 = O.astype(np.float64), Lt.astype(np.float64)
+    lam = 1.0 / np.sqrt(m)
+    norm2_0 = orc.svd(O64[0])[1][0]
+    mus = [1.25 / norm2_0 * 1.5 ** t for t in range(T)]
+    taus = np.array([1.0 / mu for mu in mus])
+    lams = np.array([lam / mu for mu in mus])
+    Lg, loss_g, gt, gl = _loss_grads_gpu(fr, O, Lt, taus, lams, k, p, q, torch.float32)
+    assert np.all(np.isfinite(Lg)) and np.all(np.isfinite(gt)) and np.all(np.isfinite(gl))
+    Lo0 = orc.rpca_unrolled(O64[0], taus, lams, k=k, p=p, q=q, seed=0, lam=lam, norm2=norm2_0)
+    ef = np.linalg.norm(Lg[0] - Lo0) / np.linalg.norm(Lo0)
+    _say(f"  forward instance 0 vs oracle {ef:.2e}; loss {loss_g:.6e}")
+    assert ef <= 1e-4
+    # gradient of instance 0's loss alone, from a one-instance run of the module
+    _, _, gt0, gl0 = _loss_grads_gpu(fr, O[:1], Lt[:1], taus, lams, k, p, q, torch.float32)
+    loss0 = lambda tt, ll: float(np.sum((orc.rpca_unrolled(O64[0], tt, ll, k=k, p=p, q=q, seed=0,
+                                                          lam=lam, norm2=norm2_0) - Lt64[0]) ** 2))
+    gmax = max(np.abs(gt0).max(), np.abs(gl0).max())
+    h = 1e-4
+    # early shrink thresholds exceed every entry (zero gradient); sample where
+    # both kinds of threshold are active
+    for (kind, t) in (("tau", 5), ("tau", 8), ("lam", 7), ("lam", 8)):
+        e = np.zeros(T)
+        e[t] = 1.0
+        if kind == "tau":
+            fd = (loss0(taus + h * e, lams) - loss0(taus - h * e, lams)) / (2 * h)
+            g = gt0[t]
+        else:
+            fd = (loss0(taus, lams + h * e) - loss0(taus, lams - h * e)) / (2 * h)
+            g = gl0[t]
+        _say(f"  {kind}_{t}: grad {g:.6e} fd {fd:.6e}")
+        assert abs(g - fd) <= 1e-3 * gmax
+        assert abs(g) > 1e-3 * gmax   # a sample that carries signal
