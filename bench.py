@@ -1,23 +1,31 @@
 #!/usr/bin/env python3
 """Benchmark of the FRSVT hot path on one MI355X.
 
-Workload: inexact-ALM RPCA on a 76800 x 200 observation (320 x 240 video
-frames as columns, 200 frames), O = L + S with L = P R^T of rank 3 (P, R iid
-U[0,1]) and S holding exactly 10 % of the entries at uniform random
-positions with values U[-1, 1]; lambda = 1/sqrt(76800), mu0 = 1.25/||O||_2,
-rho = 1.5, stop at ||O - L - S||_F / ||O||_F < 1e-7 or 60 iterations,
-FRSVT with range propagation (first sketch l0 = 20, then l = r + 5), q = 1.
+Main workload (the metric): inexact-ALM RPCA on a 76800 x 200 observation
+(320 x 240 video frames as columns, 200 frames), O = L + S with L = P R^T of
+rank 3 (P, R iid U[0,1]) and S holding exactly 10 % of the entries at uniform
+random positions with values U[-1, 1]; lambda = 1/sqrt(76800), mu0 =
+1.25/||O||_2, rho = 1.5, stop at ||O - L - S||_F / ||O||_F < 1e-7 or 60
+iterations, FRSVT with range propagation (first sketch l0 = 20, then
+l = r + 5), q = 1.  One step = one complete RPCA solve, inputs resident in
+HBM; the metric is iALM iterations per second.  The same iALM loop with an
+exact SVD-based SVT is timed beside it on the same GPU, twice: with this
+library's exact svt and with torch.linalg.svd (the vendor solver).
 
-One step = one complete RPCA solve, inputs resident in HBM.  The metric is
-iALM iterations per second; the same solve with exact SVT (full SVD of the
-Gram factor) on the same GPU is timed beside it, with both final errors.
+Further workloads, reported under "workloads" in the same JSON line:
+  single   500 x 300 FRSVT (rank 10 + noise, tau 1, k 10, p 5, q 2), calls/s
+  precision 8192 x 8192 FRSVT in the bfloat16 form and in FP64, calls/s
+  batched  8192 patch-group WSVT problems in one persistent launch, matrices/s
+  unrolled 16 x 4096 x 256 unrolled RPCA (10 steps), train steps/s
 
 Prints ONE JSON line.  --gpus above 1 is refused: this build runs on one GPU.
 """
 import argparse
 import ctypes
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -26,6 +34,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 M, N, RANK, FRAC = 76800, 200, 3, 0.10
+N_CLASSES = 13
 
 
 def parse():
@@ -34,10 +43,219 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--prec", choices=["f64", "f32"], default="f64")
-    ap.add_argument("--exact-steps", type=int, default=1)
+    ap.add_argument("--exact-steps", type=int, default=1,
+                    help="complete RPCA solves with this library's exact SVT")
+    ap.add_argument("--vendor-iters", type=int, default=3,
+                    help="iALM iterations with torch.linalg.svd as the SVT (0 = skip)")
     ap.add_argument("--cpu-iters", type=int, default=6,
                     help="iterations of the oracle timed for the CPU baseline (0 = skip)")
+    ap.add_argument("--only-main", action="store_true", help="skip the further workloads")
+    ap.add_argument("--workloads", default="single,precision,batched,unrolled")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="one untimed device copy of this size first (counter calibration)")
     return ap.parse_args()
+
+
+class Tracer:
+    """Per-kernel-class GPU time from the library's event pairs (recorded on
+    the library's own stream around each launch)."""
+
+    def __init__(self, fr):
+        self.lib = fr.library()
+        self.h = fr.handle(0)
+
+    def start(self):
+        self.lib.frsvt_trace_enable(self.h.ptr, 1)
+
+    def stop(self):
+        self.lib.frsvt_trace_enable(self.h.ptr, 0)
+        out = {}
+        for k in range(N_CLASSES):
+            ms, n = ctypes.c_double(), ctypes.c_int64()
+            self.lib.frsvt_trace_read(self.h.ptr, k, ctypes.byref(ms), ctypes.byref(n))
+            if n.value:
+                out[self.lib.frsvt_trace_name(k).decode()] = {
+                    "total_ms": ms.value, "launches": n.value, "avg_us": 1e3 * ms.value / n.value}
+        return out
+
+
+def _progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _r(d):
+    return {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+            for k, v in d.items()}
+
+
+def traffic_from_profile(kernel_file: str, name: str):
+    """HBM bytes per launch measured by the committed counter summary for this
+    kernel, or None when the summary is missing or the kernel source changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", name)
+    src = os.path.join(ROOT, "paper_1509_00296_amd", "csrc", kernel_file)
+    if not (os.path.exists(path) and os.path.exists(src)):
+        return None
+    text = open(path).read()
+    mb = re.search(r"traffic_bytes_per_launch\s*=\s*([0-9.eE+]+)", text)
+    mh = re.search(r"kernel_source_sha256\s*=\s*([0-9a-f]{64})", text)
+    if not (mb and mh):
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != mh.group(1):
+        return None
+    return float(mb.group(1))
+
+
+# ---------------------------------------------------------------------------
+# Exact SVT iALM with the vendor SVD (baseline only)
+# ---------------------------------------------------------------------------
+def vendor_ialm_iters(torch, O, lam, iters):
+    """The same iALM iterations with SVT by torch.linalg.svd of the 76800 x 200
+    iterate (thin SVD); returns seconds per iteration."""
+    norm2 = float(torch.linalg.matrix_norm(O, ord=2))
+    J = max(norm2, float(O.abs().max()) / lam)
+    mu = 1.25 / norm2
+    Y = O / J
+    S = torch.zeros_like(O)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        U, s, Vh = torch.linalg.svd(O - S + Y / mu, full_matrices=False)
+        f = torch.clamp(s - 1.0 / mu, min=0.0)
+        L = (U * f) @ Vh
+        V = O - L + Y / mu
+        S = torch.sign(V) * torch.clamp(V.abs() - lam / mu, min=0.0)
+        Y = Y + mu * (O - L - S)
+        mu = 1.5 * mu
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / iters
+
+
+# ---------------------------------------------------------------------------
+# Further workloads
+# ---------------------------------------------------------------------------
+def wl_single(torch, fr, synth, tracer):
+    import numpy as np
+    A = torch.from_numpy(synth.single_svt(seed=0)).cuda()
+    for _ in range(3):
+        fr.frsvt(A, 1.0, 10, 5, 2, seed=1)
+        fr.svt(A, 1.0)
+    torch.cuda.synchronize()
+    K = 50
+    tracer.start()
+    t0 = time.perf_counter()
+    for i in range(K):
+        X, _, r = fr.frsvt(A, 1.0, 10, 5, 2, seed=1, counter=i)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / K
+    kern = tracer.stop()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        Xe = fr.svt(A, 1.0)
+    torch.cuda.synchronize()
+    dte = (time.perf_counter() - t0) / K
+    err = float(torch.linalg.norm(X - Xe) / torch.linalg.norm(Xe))
+    return {"workload": "frsvt_500x300_f64", "metric": "FRSVT calls/s", "value": round(1.0 / dt, 1),
+            "unit": "calls/s", "ms_per_call": round(1e3 * dt, 4), "rank": r,
+            "exact_svt_calls_per_s": round(1.0 / dte, 1), "rel_err_vs_exact_svt": err,
+            "config": {"m": 500, "n": 300, "rank": 10, "tau": 1.0, "k": 10, "p": 5, "q": 2},
+            "kernels": _r(kern)}
+
+
+def wl_precision(torch, fr, synth, tracer):
+    lib, h = fr.library(), fr.handle(0)
+    n = 8192
+    A = synth.precision(seed=0, n=n)
+    out = {"workload": "frsvt_8192x8192", "metric": "FRSVT calls/s", "unit": "calls/s",
+           "config": {"n": n, "rank": 100, "tau": 5.0, "k": 100, "p": 10, "q": 2}}
+    for tag, prec, dt in (("bf16_mixed", fr.MIXED_BF16, torch.float32), ("f64", fr.F64, torch.float64)):
+        Ad = torch.from_numpy(A).to(dt).cuda()
+        X = torch.empty((n, n), dtype=dt, device="cuda").t()
+
+        def call():
+            return lib.frsvt(h.ptr, prec, n, n, Ad.data_ptr(), n, 5.0, 100, 10, 2, None, 0, n, 1000,
+                             0, X.data_ptr(), n, None, n, None)
+
+        assert call() == 0
+        torch.cuda.synchronize()
+        K = 4
+        tracer.start()
+        t0 = time.perf_counter()
+        for _ in range(K):
+            assert call() == 0
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / K
+        kern = tracer.stop()
+        entry = {"value": round(1.0 / sec, 3), "ms_per_call": round(1e3 * sec, 3), "kernels": _r(kern)}
+        if "gemm_bf16" in kern:
+            # each bfloat16 product reads the 8192^2 bfloat16 copy of A once
+            g = kern["gemm_bf16"]
+            bytes_launch = n * n * 2
+            entry["gemm_bf16_GBs"] = round(bytes_launch / (g["avg_us"] * 1e-6) / 1e9, 1)
+            entry["gemm_bf16_frac_hbm"] = round(entry["gemm_bf16_GBs"] / HBM_PEAK_GBS, 4)
+        out[tag] = entry
+        del Ad, X
+    out["value"] = out["bf16_mixed"]["value"]
+    return out
+
+
+def wl_batched(torch, fr, synth, tracer):
+    rows, cols, offs, packed = synth.patch_groups(seed=0, count=8192)
+    t = lambda a: torch.from_numpy(a).cuda()
+    R, C, Of, P = t(rows), t(cols), t(offs), t(packed)
+    X, rk = fr.wsvt_batched(R, C, Of, P)   # orders, tunes, captures
+    torch.cuda.synchronize()
+    K = 20
+    tracer.start()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        fr.wsvt_batched(R, C, Of, P, X_packed=X, ranks=rk)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / K
+    kern = tracer.stop()
+    elems = int(packed.size)
+    return {"workload": "wsvt_batched_8192_patch_groups", "metric": "matrices/s",
+            "value": round(8192 / sec, 1), "unit": "matrices/s", "ms_per_batch": round(1e3 * sec, 4),
+            "hbm_GBs": round(2 * 4 * elems / sec / 1e9, 1), "tuned_group_size": fr.wsvt_tuning(),
+            "mean_rank": float(rk.double().mean()),
+            "config": {"count": 8192, "rows": [49, 64, 81, 100], "cols": [30, 90], "rank": 4,
+                       "noise_std": 0.1, "c": 2.8},
+            "kernels": _r(kern)}
+
+
+def wl_unrolled(torch, fr, synth, tracer):
+    import numpy as np
+    B, m, n, T = 16, 4096, 256, 10
+    O, Lt = synth.rpca_batch(seed=0, batch=B, m=m, n=n, rank=5, frac=0.05, dtype=np.float32)
+    Od = torch.from_numpy(O).cuda()
+    Ltd = torch.from_numpy(Lt).cuda()
+    taus, lams = fr.UnrolledRPCA.default_schedule(Od[0], steps=T)
+    model = fr.UnrolledRPCA(taus, lams, k=5, p=5, q=1)
+    opt = torch.optim.SGD(model.parameters(), lr=1e-6)
+
+    def step():
+        opt.zero_grad()
+        loss = ((model(Od) - Ltd) ** 2).sum()
+        loss.backward()
+        opt.step()
+        return float(loss.detach())
+
+    l0 = step()
+    torch.cuda.synchronize()
+    K = 2
+    tracer.start()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        loss = step()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / K
+    kern = tracer.stop()
+    return {"workload": "unrolled_rpca_16x4096x256_T10_f32", "metric": "train steps/s",
+            "value": round(1.0 / sec, 3), "unit": "steps/s", "ms_per_step": round(1e3 * sec, 2),
+            "loss_first": l0, "loss_last": loss,
+            "config": {"batch": B, "m": m, "n": n, "steps": T, "l": 10, "q": 1, "rank": 5,
+                       "outliers": 0.05},
+            "kernels": _r(kern)}
 
 
 def main():
@@ -54,6 +272,14 @@ def main():
     import paper_1509_00296_amd as fr
     from paper_1509_00296_amd import synth
 
+    if args.calib_copy_mb > 0:
+        nb = args.calib_copy_mb << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)   # streaming kernel: reads and writes nb bytes
+        torch.cuda.synchronize()
+        del src, dst
+
     dtype = torch.float64 if args.prec == "f64" else torch.float32
     ebytes = 8 if args.prec == "f64" else 4
     O_np, L_gt, S_gt = synth.rpca(seed=0, m=M, n=N, rank=RANK, frac=FRAC)
@@ -61,24 +287,20 @@ def main():
     assert O.stride() == (1, M)
     Lgt = torch.from_numpy(L_gt).cuda()
     lam = 1.0 / np.sqrt(M)
-    h = fr.handle(0)
-    lib = fr.library()
-    lib.frsvt_trace_enable.argtypes = [ctypes.c_void_p, ctypes.c_int]
-    lib.frsvt_trace_read.argtypes = [ctypes.c_void_p, ctypes.c_int,
-                                     ctypes.POINTER(ctypes.c_double),
-                                     ctypes.POINTER(ctypes.c_int64)]
-    lib.frsvt_trace_name.restype = ctypes.c_char_p
+    tracer = Tracer(fr)
 
     def solve(use_frsvt):
         return fr.rpca_ialm(O, lam, use_frsvt=use_frsvt, tol=1e-7, max_iter=60, p=5, q=1,
                             seed=2024)
 
+    _progress("warmup")
     for _ in range(args.warmup):
         solve(True)
     torch.cuda.synchronize()
+    _progress("timed FRSVT solves")
 
     # ---------------- timed region: FRSVT + range propagation
-    lib.frsvt_trace_enable(h.ptr, 1)
+    tracer.start()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     iters = 0
@@ -88,20 +310,13 @@ def main():
         iters += res.iters
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    lib.frsvt_trace_enable(h.ptr, 0)
-    kernels = {}
-    for k in range(10):
-        ms, n = ctypes.c_double(), ctypes.c_int64()
-        lib.frsvt_trace_read(h.ptr, k, ctypes.byref(ms), ctypes.byref(n))
-        if n.value:
-            kernels[lib.frsvt_trace_name(k).decode()] = {"total_ms": ms.value, "launches": n.value,
-                                                         "avg_us": 1e3 * ms.value / n.value}
+    kernels = tracer.stop()
     elapsed = t1 - t0
     value = iters / elapsed
     nrmse = float(torch.linalg.norm(res.L.double() - Lgt) / torch.linalg.norm(Lgt))
 
-    # ---------------- comparator: exact SVT inside the same iALM loop
-    lib.frsvt_trace_enable(h.ptr, 0)
+    # ---------------- comparators: exact SVT inside the same iALM loop
+    _progress("exact SVT comparators")
     ex_iters, ex_time, ex = 0, 0.0, None
     for _ in range(args.exact_steps):
         torch.cuda.synchronize()
@@ -112,6 +327,12 @@ def main():
         ex_iters += ex.iters
     ex_value = ex_iters / ex_time if ex_time > 0 else None
     ex_nrmse = float(torch.linalg.norm(ex.L.double() - Lgt) / torch.linalg.norm(Lgt)) if ex else None
+    vendor = None
+    if args.vendor_iters > 0:
+        vendor_ialm_iters(torch, O, lam, 1)
+        sec = vendor_ialm_iters(torch, O, lam, args.vendor_iters)
+        vendor = {"iters_per_s": round(1.0 / sec, 3), "iters_timed": args.vendor_iters,
+                  "svd": "torch.linalg.svd (thin) of the 76800 x 200 iterate"}
 
     # ---------------- roofline of the dominant kernel
     # Algorithmic bytes per launch, unit = one element of the 76800 x 200
@@ -119,17 +340,39 @@ def main():
     # epilogue reads O and Y and writes Y and the next A.
     elems = M * N
     unit_elems = {"sketch": 1, "power": 1, "project": 1, "epilogue": 4}
+    src_of = {"sketch": "long_pass.hip", "power": "long_pass.hip", "project": "long_pass.hip",
+              "epilogue": "elementwise.hip"}
     dom = max((k for k in kernels if k in unit_elems), key=lambda k: kernels[k]["total_ms"])
     bytes_per_launch = unit_elems[dom] * elems * ebytes
     achieved = bytes_per_launch / (kernels[dom]["avg_us"] * 1e-6) / 1e9
+    traffic = traffic_from_profile(src_of[dom], f"{dom}_rpca76800x200_{args.prec}_traffic.md")
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "bytes_per_launch": bytes_per_launch,
+                "traffic": traffic, "bytes_per_launch": bytes_per_launch,
                 "avg_launch_us": round(kernels[dom]["avg_us"], 2)}
+    passes = {}
+    for k, ue in unit_elems.items():
+        if k in kernels:
+            gbs = ue * elems * ebytes / (kernels[k]["avg_us"] * 1e-6) / 1e9
+            passes[k] = {"GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+    # ---------------- further workloads
+    workloads = {}
+    if not args.only_main:
+        fns = {"single": wl_single, "precision": wl_precision, "batched": wl_batched,
+               "unrolled": wl_unrolled}
+        for name in [w for w in args.workloads.split(",") if w]:
+            _progress(f"workload {name}")
+            try:
+                workloads[name] = fns[name](torch, fr, synth, tracer)
+            except Exception as e:  # reported, never hidden
+                workloads[name] = {"error": f"{type(e).__name__}: {e}"}
+            torch.cuda.synchronize()
 
     # ---------------- CPU baseline: the oracle on a bounded sample
     cpu = None
     if args.cpu_iters > 0:
+        _progress("cpu baseline (oracle)")
         import oracle
         oracle.build()
         a = time.perf_counter()
@@ -154,7 +397,7 @@ def main():
         "vs_baseline": None,
         "dtype": args.prec,
         "data": "synthetic",
-        "config": {"workload": "rpca_ialm_frsvt_rp", "m": M, "n": N, "rank": RANK,
+        "config": {"workload": "rpca_ialm_frsvt_rp_76800x200", "m": M, "n": N, "rank": RANK,
                    "outliers": FRAC, "lambda": lam, "p": 5, "q": 1, "l0": 20, "tol": 1e-7,
                    "max_iter": 60},
         "iters_per_solve": res.iters,
@@ -165,11 +408,14 @@ def main():
                       "iters_per_solve": ex.iters if ex else None,
                       "nrmse_L": ex_nrmse,
                       "converged": ex.converged if ex else None},
+        "exact_svt_vendor": vendor,
         "speedup_per_iter_vs_exact_svt": round(value / ex_value, 2) if ex_value else None,
+        "speedup_per_iter_vs_vendor_svd": round(value / vendor["iters_per_s"], 2) if vendor else None,
         "roofline": roofline,
+        "passes": passes,
         "cpu_baseline": cpu,
-        "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv)
-                        for kk, vv in v.items()} for k, v in kernels.items()},
+        "kernels": _r(kernels),
+        "workloads": workloads,
     }
     print(json.dumps(line), flush=True)
 
