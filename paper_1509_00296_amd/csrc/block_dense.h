@@ -73,14 +73,35 @@ __device__ inline CholInfo block_chol(const double *G, int l, double shift, doub
     return info;
 }
 
-// W <- W R^{-1} (R upper, row-major), each thread owns rows.
+// W <- W R^{-1} (R upper, row-major), each thread owns rows; for l <= 16 a
+// row is held in registers while it is solved.
 __device__ inline void block_trsm(double *W, int mh, int mhp, int l, const double *R)
 {
-    for (int i = threadIdx.x; i < mh; i += blockDim.x) {
-        for (int j = 0; j < l; ++j) {
-            double v = W[(size_t)j * mhp + i];
-            for (int t = 0; t < j; ++t) v -= W[(size_t)t * mhp + i] * R[t * l + j];
-            W[(size_t)j * mhp + i] = v / R[j * l + j];
+    if (l <= 16) {
+        for (int i = threadIdx.x; i < mh; i += blockDim.x) {
+            double w[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) w[j] = j < l ? W[(size_t)j * mhp + i] : 0.0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                if (j < l) {
+                    double v = w[j];
+#pragma unroll
+                    for (int t = 0; t < j; ++t) v -= w[t] * R[t * l + j];
+                    w[j] = v / R[j * l + j];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                if (j < l) W[(size_t)j * mhp + i] = w[j];
+        }
+    } else {
+        for (int i = threadIdx.x; i < mh; i += blockDim.x) {
+            for (int j = 0; j < l; ++j) {
+                double v = W[(size_t)j * mhp + i];
+                for (int t = 0; t < j; ++t) v -= W[(size_t)t * mhp + i] * R[t * l + j];
+                W[(size_t)j * mhp + i] = v / R[j * l + j];
+            }
         }
     }
     __syncthreads();

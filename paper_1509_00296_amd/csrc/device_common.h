@@ -68,27 +68,78 @@ __device__ __forceinline__ void gaussian_pair(uint64_t seed, uint64_t counter, u
 constexpr uint32_t kRefillTag = 0x80000000u;
 
 // ---------------------------------------------------------------------------
-// Wavefront reductions (64 lanes) through cross-lane shuffles.
+// Wavefront reductions through DPP lane moves (VALU, no LDS round trip):
+// within a 16-lane row the partners are quad_perm [1,0,3,2], quad_perm
+// [2,3,0,1], row_half_mirror and row_mirror; after each step every lane of
+// the segment holds the same value (x + y and y + x round identically).  The
+// four row sums of a wavefront are then read from lanes 0, 16, 32, 48 and
+// added in that order.  Floating-point contraction is off inside these
+// helpers: an add fused with the caller's product (x*x + dpp(x*x) as one
+// FMA) would round differently in the two lanes of a pair, and lanes that
+// must agree (a Jacobi rotation) would not.
 // ---------------------------------------------------------------------------
+template <int CTRL, typename T>
+__device__ __forceinline__ T dpp_mov(T v)
+{
+    return __builtin_amdgcn_update_dpp(T(0), v, CTRL, 0xF, 0xF, false);
+}
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+
+template <typename T>
+__device__ __forceinline__ T seg8_sum(T v)
+{
+#pragma clang fp contract(off)
+    v += dpp_mov<kDppXor1>(v);
+    v += dpp_mov<kDppXor2>(v);
+    v += dpp_mov<kDppHalfMirror>(v);
+    return v;
+}
+template <typename T>
+__device__ __forceinline__ T seg16_sum(T v)
+{
+#pragma clang fp contract(off)
+    v = seg8_sum(v);
+    v += dpp_mov<kDppMirror>(v);
+    return v;
+}
+__device__ __forceinline__ double read_lane(double v, int l)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ float read_lane(float v, int l)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+// lanes 0-31 get the sum over lanes 0-31, lanes 32-63 over lanes 32-63
+template <typename T>
+__device__ __forceinline__ T seg32_sum(T v)
+{
+#pragma clang fp contract(off)
+    v = seg16_sum(v);
+    const T lo = read_lane(v, 0) + read_lane(v, 16), hi = read_lane(v, 32) + read_lane(v, 48);
+    return (threadIdx.x & 32) ? hi : lo;
+}
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
+#pragma clang fp contract(off)
+    v = seg16_sum(v);
+    return ((read_lane(v, 0) + read_lane(v, 16)) + read_lane(v, 32)) + read_lane(v, 48);
 }
-
 __device__ __forceinline__ float wave_sum(float v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
+#pragma clang fp contract(off)
+    v = seg16_sum(v);
+    return ((read_lane(v, 0) + read_lane(v, 16)) + read_lane(v, 32)) + read_lane(v, 48);
 }
-
 __device__ __forceinline__ double wave_max(double v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
-    return v;
+    v = fmax(v, dpp_mov<kDppXor1>(v));
+    v = fmax(v, dpp_mov<kDppXor2>(v));
+    v = fmax(v, dpp_mov<kDppHalfMirror>(v));
+    v = fmax(v, dpp_mov<kDppMirror>(v));
+    return fmax(fmax(read_lane(v, 0), read_lane(v, 16)), fmax(read_lane(v, 32), read_lane(v, 48)));
 }
 
 __device__ __forceinline__ double soft_shrink(double x, double t)

@@ -25,7 +25,7 @@ struct LongArgs {
     int64_t nh;
     int c;
     int kt;          // tile width along the long dimension
-    int mhp;         // padded LDS row stride (odd)
+    int mhp;         // rows padded to whole 16-row blocks
     int ntiles;
     uint64_t seed, counter;
     const T *V;
@@ -41,6 +41,10 @@ struct LongArgs {
 struct LongPlan {
     int kt, mhp, ntiles, grid, cm, rpt;
     size_t lds;
+    // vector-FMA form (narrow c): columns padded to cmv, rows per thread rptv
+    int vec, cmv, rptv;
+    size_t ldsv;
+    size_t ldst;   // transposed fast form
 };
 
 bool long_path_ok(int mh, int c);

@@ -10,87 +10,132 @@
 namespace frk {
 
 // ===========================================================================
-// One workgroup (256 threads) walks tiles of kKT long-dimension indices; each
-// tile holds the whole short dimension (mh <= 512) in LDS as
-// sTile[kk * mhp + i] with an odd row stride.  The next tile is prefetched
-// into registers while the current one is processed.
+// One workgroup (256 threads, 4 wavefronts) walks tiles of kKT = 16
+// long-dimension indices; a tile holds the whole short dimension (mh <= 512,
+// padded to whole 16-row blocks) in LDS as sT[i * LD + kk] (k contiguous per
+// row).  The next tile is prefetched into registers while the current one is
+// processed.  Both contractions run on the matrix cores (16x16x4 f64 / f32):
 //
-//  phase 1 (power / projection): z(kk, :) = sum_i Ahat(i, k0+kk) Q(i, :).
-//    Thread (kk, column group cg, slice s) sums the rows i = s, s+S, ...;
-//    the S slices are combined in a fixed order through LDS.
-//  phase 2 (sketch / power): Y(i, :) += sum_kk Ahat(i, k0+kk) v(kk, :), one
-//    thread per short index i, v broadcast from LDS (no cross-lane sums).
-//  projection: B^T rows written out, Gram B B^T accumulated in double.
+//  phase 1 (power, projection): Z(kk, j) = sum_i Ahat(i, k0+kk) Q(i, j).
+//    Wavefront w takes the 4-row steps i0 = 4w, 4w + 16, ...; the four
+//    partial 16 x 16 blocks are added in a fixed order through LDS.
+//  phase 2 (sketch, power):     Y(i, j) += sum_kk Ahat(i, k0+kk) V(kk, j),
+//    wavefront w owns the row blocks w, w + 4, ... and keeps their
+//    accumulators in registers for the whole pass.
+//  projection: B^T rows written out, the Gram B B^T accumulated in double.
+// Columns beyond c and rows beyond mh are zero in LDS, so they contribute
+// nothing; the output is written for i < mh, j < c only.
 // ===========================================================================
 constexpr int kKT = 16;
 constexpr int kMaxMh = 512;
+
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float lp_floatx4;
+typedef __attribute__((__vector_size__(4 * sizeof(double)))) double lp_doublex4;
+
+template <typename T>
+struct LpMfma;
+template <>
+struct LpMfma<double> {
+    using V4 = lp_doublex4;
+    static constexpr int kLD = 18;  // LDS row stride of the tile (144 bytes)
+    __device__ static V4 mma(double a, double b, V4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    // row of D element r held by lane l
+    __device__ static int drow(int l, int r) { return (l >> 4) + 4 * r; }
+};
+template <>
+struct LpMfma<float> {
+    using V4 = lp_floatx4;
+    static constexpr int kLD = 20;  // 80 bytes
+    __device__ static V4 mma(float a, float b, V4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    __device__ static int drow(int l, int r) { return 4 * (l >> 4) + r; }
+};
 
 bool long_path_ok(int mh, int c) { return mh >= 1 && mh <= kMaxMh && c >= 1 && c <= 32; }
 
 LongPlan long_plan(int mh, int64_t nh, int c, int elem_bytes, int mode, int num_cu)
 {
     LongPlan p{};
-    p.mhp = mh | 1;
-    p.cm = c <= 8 ? 8 : (c <= 16 ? 16 : 32);
-    p.rpt = (mh + kThreads - 1) / kThreads;
+    const int nrb = (mh + 15) / 16;
+    p.mhp = nrb * 16;                      // padded rows
+    p.cm = c <= 16 ? 16 : 32;              // padded columns (VLD)
+    p.rpt = nrb <= 16 ? 4 : 8;             // row blocks per wavefront (phase 2)
     p.kt = kKT;
     p.ntiles = (int)((nh + kKT - 1) / kKT);
     p.grid = std::max(1, std::min(p.ntiles, 2 * num_cu));
     const bool needs_q = (mode == kPower || mode == kProject);
-    const int cg = p.cm / 8, slices = 16 / cg;
-    p.lds = (size_t)kKT * p.mhp * elem_bytes + (size_t)kKT * p.cm * elem_bytes +
-            (needs_q ? (size_t)mh * p.cm * elem_bytes + (size_t)slices * kKT * p.cm * elem_bytes : 0);
+    const int ld = elem_bytes == 8 ? LpMfma<double>::kLD : LpMfma<float>::kLD;
+    p.lds = (size_t)p.mhp * ld * elem_bytes + (size_t)kKT * p.cm * elem_bytes +
+            (needs_q ? (size_t)p.mhp * p.cm * elem_bytes + (size_t)4 * kKT * p.cm * elem_bytes : 0);
+    // vector-FMA form
+    p.cmv = c <= 8 ? 8 : (c <= 16 ? 16 : 32);
+    p.rptv = mh <= kThreads ? 1 : 2;
+    const int gch = 96 / p.cmv, slices = 16 / (p.cmv / 8);
+    p.ldsv = (size_t)p.mhp * ld * elem_bytes +
+             (size_t)(mode == kSketch ? gch : 1) * kKT * p.cmv * elem_bytes +
+             (needs_q ? (size_t)mh * p.cmv * elem_bytes + (size_t)slices * kKT * p.cmv * elem_bytes : 0);
+    p.vec = 0;
+    // transposed fast form: LDS = tile + V (or the Gaussian chunk) + phase-1 partials
+    p.ldst = (size_t)p.mhp * ld * elem_bytes +
+             (size_t)(mode == kSketch ? 12 : 1) * kKT * p.cm * elem_bytes +
+             (needs_q ? (size_t)4 * kKT * p.cm * elem_bytes : 0);
     return p;
 }
 
-template <typename T, bool TR, int MODE, int CM, int RPT>
+template <typename T, bool TR, int MODE, int NB, int MAXRB>
 __global__ void __launch_bounds__(kThreads) k_long(LongArgs<T> a)
 {
+    using M = LpMfma<T>;
+    using V4 = typename M::V4;
     constexpr bool kNeedQ = (MODE == kPower || MODE == kProject);
-    constexpr int kCG = CM / 8;          // groups of 8 columns
-    constexpr int kS = 16 / kCG;         // row slices of phase 1
-    constexpr int kPF = kKT * RPT;       // prefetch registers per thread (mh <= 256 RPT)
+    constexpr bool kPhase2 = (MODE != kProject);
+    constexpr int LD = M::kLD;
+    constexpr int VLD = 16 * NB;
+    constexpr int kPF = kKT * 64 * MAXRB / kThreads;   // prefetch registers (>= 16 mh / 256)
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int mh = a.mh, c = a.c, mhp = a.mhp;
-    T *sTile = reinterpret_cast<T *>(smem_raw);
-    T *sV = sTile + (size_t)kKT * mhp;
-    T *sQ = sV + (size_t)kKT * CM;
-    T *sZp = sQ + (size_t)mh * CM;
+    const int nrb = mhp >> 4;
+    T *sT = reinterpret_cast<T *>(smem_raw);
+    T *sV = sT + (size_t)mhp * LD;
+    T *sQ = sV + (size_t)kKT * VLD;
+    T *sZp = sQ + (size_t)mhp * VLD;
 
-    for (int idx = tid; idx < kKT * CM; idx += kThreads) sV[idx] = T(0);
-    if (kNeedQ) {
-        for (int idx = tid; idx < mh * CM; idx += kThreads) {
-            const int i = idx / CM, cc = idx % CM;
-            sQ[idx] = cc < c ? a.Q[i + (int64_t)cc * a.ldq] : T(0);
+    // padding rows of the tile stay zero; Q padded with zeros
+    for (int idx = tid; idx < (mhp - mh) * LD; idx += kThreads) sT[(size_t)mh * LD + idx] = T(0);
+    if (kNeedQ)
+        for (int idx = tid; idx < mhp * VLD; idx += kThreads) {
+            const int i = idx / VLD, j = idx % VLD;
+            sQ[idx] = (i < mh && j < c) ? a.Q[i + (int64_t)j * a.ldq] : T(0);
         }
-    }
-    T acc[RPT][CM];
+    V4 acc[MAXRB][NB];
 #pragma unroll
-    for (int r = 0; r < RPT; ++r)
+    for (int r = 0; r < MAXRB; ++r)
 #pragma unroll
-        for (int cc = 0; cc < CM; ++cc) acc[r][cc] = T(0);
+        for (int b = 0; b < NB; ++b) acc[r][b] = V4{0, 0, 0, 0};
     double gacc[4] = {0.0, 0.0, 0.0, 0.0};
 
     const int per_tile = kKT * mh;
+    const int npf = (per_tile + kThreads - 1) / kThreads;
     T pre[kPF];
     auto load_tile = [&](int tile) {
         const int64_t k0 = (int64_t)tile * kKT;
         const int64_t kval = min((int64_t)kKT, a.nh - k0);
 #pragma unroll
         for (int j = 0; j < kPF; ++j) {
-            const int e = tid + j * kThreads;
             T v = T(0);
-            if (e < per_tile) {
-                int kk, i;
-                if (TR) {
-                    kk = e % kKT;
-                    i = e / kKT;
-                } else {
-                    i = e % mh;
-                    kk = e / mh;
+            if (j < npf) {
+                const int e = tid + j * kThreads;
+                if (e < per_tile) {
+                    int kk, i;
+                    if (TR) {
+                        kk = e % kKT;
+                        i = e / kKT;
+                    } else {
+                        i = e % mh;
+                        kk = e / mh;
+                    }
+                    if (kk < kval) v = TR ? a.A[(k0 + kk) + (int64_t)i * a.lda] : a.A[i + (k0 + kk) * a.lda];
                 }
-                if (kk < kval) v = TR ? a.A[(k0 + kk) + (int64_t)i * a.lda] : a.A[i + (k0 + kk) * a.lda];
             }
             pre[j] = v;
         }
@@ -102,67 +147,283 @@ __global__ void __launch_bounds__(kThreads) k_long(LongArgs<T> a)
         const int kval = (int)min((int64_t)kKT, a.nh - k0);
 #pragma unroll
         for (int j = 0; j < kPF; ++j) {
-            const int e = tid + j * kThreads;
-            if (e < per_tile) {
-                int kk, i;
-                if (TR) {
-                    kk = e % kKT;
-                    i = e / kKT;
-                } else {
-                    i = e % mh;
-                    kk = e / mh;
+            if (j < npf) {
+                const int e = tid + j * kThreads;
+                if (e < per_tile) {
+                    int kk, i;
+                    if (TR) {
+                        kk = e % kKT;
+                        i = e / kKT;
+                    } else {
+                        i = e % mh;
+                        kk = e / mh;
+                    }
+                    sT[i * LD + kk] = pre[j];
                 }
-                sTile[kk * mhp + i] = pre[j];
             }
         }
         if (MODE == kSketch) {
+            // pairs spread over the four wavefronts
             const int npair = (c + 1) / 2;
-            for (int idx = tid; idx < kKT * npair; idx += kThreads) {
-                const int kk = idx % kKT, j = idx / kKT;
+            for (int p = (tid & 3) * 64 + (tid >> 2); p < kKT * (VLD / 2); p += kThreads) {
+                const int kk = p % kKT, j = p / kKT;
                 double z0 = 0.0, z1 = 0.0;
-                if (kk < kval) gaussian_pair(a.seed, a.counter, (uint32_t)(k0 + kk), (uint32_t)j, z0, z1);
-                sV[kk * CM + 2 * j] = T(z0);
-                if (2 * j + 1 < c) sV[kk * CM + 2 * j + 1] = T(z1);
+                if (kk < kval && j < npair) gaussian_pair(a.seed, a.counter, (uint32_t)(k0 + kk), (uint32_t)j, z0, z1);
+                sV[kk * VLD + 2 * j] = T(z0);
+                sV[kk * VLD + 2 * j + 1] = (2 * j + 1 < c) ? T(z1) : T(0);
             }
         } else if (MODE == kVecMul) {
-            for (int idx = tid; idx < kKT * c; idx += kThreads) {
-                const int kk = idx % kKT, cc = idx / kKT;
-                sV[kk * CM + cc] = kk < kval ? a.V[(k0 + kk) + (int64_t)cc * a.ldv] : T(0);
+            for (int idx = tid; idx < kKT * VLD; idx += kThreads) {
+                const int kk = idx % kKT, j = idx / kKT;
+                sV[kk * VLD + j] = (kk < kval && j < c) ? a.V[(k0 + kk) + (int64_t)j * a.ldv] : T(0);
             }
         }
         __syncthreads();
         if (tile + (int)gridDim.x < a.ntiles) load_tile(tile + gridDim.x);
 
         if (kNeedQ) {
-            // phase 1
-            const int kk = tid % kKT;
-            const int cg = (tid / kKT) % kCG;
-            const int s = tid / (kKT * kCG);
-            T z[8];
+            // phase 1: Z = Ahat(:, tile)^T Q over this wavefront's 4-row steps
+            V4 z[NB];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) z[u] = T(0);
-            const T *trow = sTile + kk * mhp;
-            for (int i = s; i < mh; i += kS) {
-                const T av = trow[i];
-                const T *qr = sQ + i * CM + cg * 8;
+            for (int b = 0; b < NB; ++b) z[b] = V4{0, 0, 0, 0};
+            const int kk = lane & 15, ko = lane >> 4;
+            for (int i0 = 4 * wave; i0 < mhp; i0 += 16) {
+                const T av = sT[(i0 + ko) * LD + kk];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) z[u] += av * qr[u];
+                for (int b = 0; b < NB; ++b) z[b] = M::mma(av, sQ[(i0 + ko) * VLD + b * 16 + kk], z[b]);
             }
-            T *zp = sZp + ((size_t)s * kKT + kk) * CM + cg * 8;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) zp[u] = z[u];
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    sZp[((size_t)wave * kKT + M::drow(lane, r)) * VLD + b * 16 + (lane & 15)] = z[b][r];
             __syncthreads();
-            for (int idx = tid; idx < kKT * CM; idx += kThreads) {
-                T t = T(0);
-                for (int ss = 0; ss < kS; ++ss) t += sZp[(size_t)ss * kKT * CM + idx];
-                sV[idx] = t;
+            for (int idx = tid; idx < kKT * VLD; idx += kThreads) {
+                const size_t st = (size_t)kKT * VLD;
+                sV[idx] = ((sZp[idx] + sZp[st + idx]) + sZp[2 * st + idx]) + sZp[3 * st + idx];
             }
             __syncthreads();
         }
         if (MODE == kProject) {
             for (int idx = tid; idx < kKT * c; idx += kThreads) {
-                const int kk = idx % kKT, cc = idx / kKT;
-                if (kk < kval) a.Z[(k0 + kk) + (int64_t)cc * a.ldz] = sV[kk * CM + cc];
+                const int kk = idx % kKT, j = idx / kKT;
+                if (kk < kval) a.Z[(k0 + kk) + (int64_t)j * a.ldz] = sV[kk * VLD + j];
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int p = tid + e * kThreads;
+                if (p < c * c) {
+                    const int x = p % c, y = p / c;
+                    double sum = 0.0;
+#pragma unroll
+                    for (int kk = 0; kk < kKT; ++kk) sum += (double)sV[kk * VLD + x] * (double)sV[kk * VLD + y];
+                    gacc[e] += sum;
+                }
+            }
+        }
+        if (kPhase2) {
+            // phase 2: Y(block rows) += Ahat(:, tile) V
+#pragma unroll
+            for (int r = 0; r < MAXRB; ++r) {
+                const int rb = wave + 4 * r;
+                if (rb < nrb) {
+                    const int i = rb * 16 + (lane & 15);
+#pragma unroll
+                    for (int ks = 0; ks < kKT / 4; ++ks) {
+                        const int kk = ks * 4 + (lane >> 4);
+                        const T av = sT[i * LD + kk];
+#pragma unroll
+                        for (int b = 0; b < NB; ++b)
+                            acc[r][b] = M::mma(av, sV[kk * VLD + b * 16 + (lane & 15)], acc[r][b]);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (MODE == kProject) {
+        double *gp = a.Gpart + (size_t)blockIdx.x * c * c;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int p = tid + e * kThreads;
+            if (p < c * c) gp[p] = gacc[e];
+        }
+    } else {
+        T *yp = a.Ypart + (size_t)blockIdx.x * mh * c;
+#pragma unroll
+        for (int r = 0; r < MAXRB; ++r) {
+            const int rb = wave + 4 * r;
+            if (rb < nrb) {
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    const int j = b * 16 + (lane & 15);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int i = rb * 16 + M::drow(lane, q);
+                        if (i < mh && j < c) yp[i + (size_t)j * mh] = acc[r][b][q];
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Vector-FMA form of the same passes for narrow column counts (c <= 8 or
+// 16), where the 16-column matrix-core tiles would waste half their work:
+//  phase 1: thread (kk, column group of 8, row slice) sums its rows, four
+//    rows per batch of LDS reads; the slices are added in a fixed order;
+//  phase 2: one thread per short index i (RPT of them), KB long-dimension
+//    indices per batch of LDS reads.
+// The sketch draws the Gaussian columns of the workgroup's next GCH tiles in
+// one go (overlapping the first tile's load) into LDS.
+// ---------------------------------------------------------------------------
+template <typename T, bool TR, int MODE, int CM, int RPT>
+__global__ void __launch_bounds__(kThreads) k_long_v(LongArgs<T> a)
+{
+    constexpr bool kNeedQ = (MODE == kPower || MODE == kProject);
+    constexpr bool kPhase2 = (MODE != kProject);
+    constexpr int LD = LpMfma<T>::kLD;
+    constexpr int kCG = CM / 8;
+    constexpr int kS = 16 / kCG;
+    constexpr int KB = CM == 8 ? 4 : (CM == 16 ? 2 : 1);
+    constexpr int GCH = 96 / CM;
+    constexpr int kPF = kKT * kThreads * RPT / kThreads;   // 16 RPT >= 16 mh / 256
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int tid = threadIdx.x;
+    const int mh = a.mh, c = a.c;
+    T *sT = reinterpret_cast<T *>(smem_raw);
+    T *sV = sT + (size_t)a.mhp * LD;                      // kKT x CM (or GCH x kKT x CM)
+    T *sQ = sV + (size_t)(MODE == kSketch ? GCH : 1) * kKT * CM;
+    T *sZp = sQ + (size_t)mh * CM;
+
+    if (kNeedQ)
+        for (int idx = tid; idx < mh * CM; idx += kThreads) {
+            const int i = idx / CM, j = idx % CM;
+            sQ[idx] = j < c ? a.Q[i + (int64_t)j * a.ldq] : T(0);
+        }
+    T acc[RPT][CM];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r)
+#pragma unroll
+        for (int cc = 0; cc < CM; ++cc) acc[r][cc] = T(0);
+    double gacc[4] = {0.0, 0.0, 0.0, 0.0};
+
+    const int per_tile = kKT * mh;
+    const int npf = (per_tile + kThreads - 1) / kThreads;
+    T pre[kPF];
+    auto load_tile = [&](int tile) {
+        const int64_t k0 = (int64_t)tile * kKT;
+        const int64_t kval = min((int64_t)kKT, a.nh - k0);
+#pragma unroll
+        for (int j = 0; j < kPF; ++j) {
+            T v = T(0);
+            if (j < npf) {
+                const int e = tid + j * kThreads;
+                if (e < per_tile) {
+                    int kk, i;
+                    if (TR) {
+                        kk = e % kKT;
+                        i = e / kKT;
+                    } else {
+                        i = e % mh;
+                        kk = e / mh;
+                    }
+                    if (kk < kval) v = TR ? a.A[(k0 + kk) + (int64_t)i * a.lda] : a.A[i + (k0 + kk) * a.lda];
+                }
+            }
+            pre[j] = v;
+        }
+    };
+    // Gaussian columns of the tiles blockIdx + (t0 + g) gridDim, g < GCH
+    auto draw = [&](int t0) {
+        const int npair = (c + 1) / 2;
+        for (int p = tid; p < GCH * kKT * (CM / 2); p += kThreads) {
+            const int g = p / (kKT * (CM / 2)), rem = p % (kKT * (CM / 2));
+            const int kk = rem % kKT, j = rem / kKT;
+            const int64_t tile = (int64_t)blockIdx.x + (int64_t)(t0 + g) * gridDim.x;
+            const int64_t k = tile * kKT + kk;
+            double z0 = 0.0, z1 = 0.0;
+            if (tile < a.ntiles && k < a.nh && j < npair)
+                gaussian_pair(a.seed, a.counter, (uint32_t)k, (uint32_t)j, z0, z1);
+            T *dst = sV + ((size_t)g * kKT + kk) * CM + 2 * j;
+            dst[0] = T(z0);
+            dst[1] = (2 * j + 1 < c) ? T(z1) : T(0);
+        }
+    };
+    if ((int)blockIdx.x < a.ntiles) load_tile(blockIdx.x);
+    if (MODE == kSketch) draw(0);
+
+    int it = 0;
+    for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x, ++it) {
+        const int64_t k0 = (int64_t)tile * kKT;
+        const int kval = (int)min((int64_t)kKT, a.nh - k0);
+        if (MODE == kSketch && it > 0 && it % GCH == 0) draw(it);
+#pragma unroll
+        for (int j = 0; j < kPF; ++j) {
+            if (j < npf) {
+                const int e = tid + j * kThreads;
+                if (e < per_tile) {
+                    int kk, i;
+                    if (TR) {
+                        kk = e % kKT;
+                        i = e / kKT;
+                    } else {
+                        i = e % mh;
+                        kk = e / mh;
+                    }
+                    sT[i * LD + kk] = pre[j];
+                }
+            }
+        }
+        if (MODE == kVecMul) {
+            for (int idx = tid; idx < kKT * CM; idx += kThreads) {
+                const int kk = idx % kKT, j = idx / kKT;
+                sV[kk * CM + j] = (kk < kval && j < c) ? a.V[(k0 + kk) + (int64_t)j * a.ldv] : T(0);
+            }
+        }
+        __syncthreads();
+        if (tile + (int)gridDim.x < a.ntiles) load_tile(tile + gridDim.x);
+
+        if (kNeedQ) {
+            const int kk = tid % kKT, cg = (tid / kKT) % kCG, sl = tid / (kKT * kCG);
+            T z[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) z[u] = T(0);
+            for (int i0 = sl; i0 < mh; i0 += 4 * kS) {
+                T av[4], qv[4][8];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int i = i0 + b * kS;
+                    const bool ok = i < mh;
+                    av[b] = ok ? sT[i * LD + kk] : T(0);
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) qv[b][u] = ok ? sQ[i * CM + cg * 8 + u] : T(0);
+                }
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) z[u] += av[b] * qv[b][u];
+            }
+            T *zp = sZp + ((size_t)sl * kKT + kk) * CM + cg * 8;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) zp[u] = z[u];
+            __syncthreads();
+            for (int idx = tid; idx < kKT * CM; idx += kThreads) {
+                T t[kS];
+#pragma unroll
+                for (int q = 0; q < kS; ++q) t[q] = sZp[(size_t)q * kKT * CM + idx];
+                T sum = T(0);
+#pragma unroll
+                for (int q = 0; q < kS; ++q) sum += t[q];
+                sV[idx] = sum;
+            }
+            __syncthreads();
+        }
+        if (MODE == kProject) {
+            for (int idx = tid; idx < kKT * c; idx += kThreads) {
+                const int kk = idx % kKT, j = idx / kKT;
+                if (kk < kval) a.Z[(k0 + kk) + (int64_t)j * a.ldz] = sV[kk * CM + j];
             }
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
@@ -175,18 +436,27 @@ __global__ void __launch_bounds__(kThreads) k_long(LongArgs<T> a)
                     gacc[e] += sum;
                 }
             }
-        } else {
-            // phase 2
+        }
+        if (kPhase2) {
+            const T *vbase = sV + (MODE == kSketch ? (size_t)(it % GCH) * kKT * CM : 0);
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {
                 const int i = tid + r * kThreads;
                 if (i < mh) {
-#pragma unroll 4
-                    for (int kk = 0; kk < kKT; ++kk) {
-                        const T av = sTile[kk * mhp + i];
-                        const T *vr = sV + kk * CM;
+                    const T *arow = sT + i * LD;
 #pragma unroll
-                        for (int cc = 0; cc < CM; ++cc) acc[r][cc] += av * vr[cc];
+                    for (int k0b = 0; k0b < kKT; k0b += KB) {
+                        T av[KB], vv[KB][CM];
+#pragma unroll
+                        for (int b = 0; b < KB; ++b) {
+                            av[b] = arow[k0b + b];
+#pragma unroll
+                            for (int cc = 0; cc < CM; ++cc) vv[b][cc] = vbase[(k0b + b) * CM + cc];
+                        }
+#pragma unroll
+                        for (int b = 0; b < KB; ++b)
+#pragma unroll
+                            for (int cc = 0; cc < CM; ++cc) acc[r][cc] += av[b] * vv[b][cc];
                     }
                 }
             }
@@ -213,22 +483,259 @@ __global__ void __launch_bounds__(kThreads) k_long(LongArgs<T> a)
     }
 }
 
-template <typename T, bool TR, int MODE, int CM>
-static hipError_t launch_long_rpt(const LongPlan &p, const LongArgs<T> &a, hipStream_t s)
+// ---------------------------------------------------------------------------
+// Transposed orientation (Ahat = A^T, the long dimension contiguous in
+// memory), mh <= 256.  The coalesced load of a tile -- 16 lanes over 16
+// consecutive long indices of one column, four columns per instruction --
+// is exactly the A-operand layout of phase 1 (M = kk, K = i), so phase 1 runs
+// from the prefetch registers with Q's B-operand held in registers for the
+// whole pass; the registers are also written to LDS for phase 2.  Loads are
+// buffer loads with one per-thread offset and a per-tile offset; lanes past
+// the end of the long dimension (or rows past mh) use an offset outside the
+// buffer, which the hardware returns as zero.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kOob = 0x80000000u;
+
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
+template <>
+__device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
 {
-    if (p.rpt == 1)
-        hipLaunchKernelGGL((k_long<T, TR, MODE, CM, 1>), dim3(p.grid), dim3(kThreads), p.lds, s, a);
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
+template <typename T, int MODE, int NB>
+__global__ void __launch_bounds__(kThreads) k_long_tr(LongArgs<T> a, uint32_t span_bytes)
+{
+    using M = LpMfma<T>;
+    using V4 = typename M::V4;
+    constexpr bool kNeedQ = (MODE == kPower || MODE == kProject);
+    constexpr bool kPhase2 = (MODE != kProject);
+    constexpr int LD = M::kLD;
+    constexpr int VLD = 16 * NB;
+    constexpr int NJ = 16;            // row groups of 16 per thread: mhp <= 256
+    constexpr int GCH = 12;           // tiles per Gaussian chunk (sketch)
+    constexpr uint32_t ESZ = sizeof(T);
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int mh = a.mh, c = a.c, mhp = a.mhp;
+    const int nrb = mhp >> 4;
+    const int nj = nrb;               // row groups present (i_j = (tid >> 4) + 16 j < mhp)
+    T *sT = reinterpret_cast<T *>(smem_raw);
+    T *sV = sT + (size_t)mhp * LD;
+    T *sZp = sV + (size_t)(MODE == kSketch ? GCH : 1) * kKT * VLD;
+
+    const __amdgpu_buffer_rsrc_t rsrc =
+        __builtin_amdgcn_make_buffer_rsrc((void *)a.A, (short)0, (int)span_bytes, 0x00020000);
+    const int kk_l = tid & 15, r0 = tid >> 4;
+    const uint32_t v0 = ((uint32_t)kk_l + (uint32_t)r0 * (uint32_t)a.lda) * ESZ;
+    const uint32_t rowstep = 16u * (uint32_t)a.lda * ESZ;   // bytes between row groups
+    // Q as the phase-1 B operand: row i_j, column b*16 + (lane & 15)
+    T qreg[NJ][NB];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int i = r0 + 16 * j, col = b * 16 + (lane & 15);
+            qreg[j][b] = (kNeedQ && j < nj && i < mh && col < c) ? a.Q[i + (int64_t)col * a.ldq] : T(0);
+        }
+    V4 acc[4][NB];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[r][b] = V4{0, 0, 0, 0};
+    double gacc[4] = {0.0, 0.0, 0.0, 0.0};
+
+    T pre[NJ], cur[NJ];
+    auto load_tile = [&](int tile) {
+        const int64_t k0 = (int64_t)tile * kKT;
+        const bool kin = k0 + kk_l < a.nh;
+        const uint32_t vt = kin ? v0 + (uint32_t)k0 * ESZ : kOob;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            if (j < nj) {
+                const uint32_t vo = (r0 + 16 * j < mh) ? vt : kOob;
+                pre[j] = buf_load<T>(rsrc, vo, (uint32_t)j * rowstep);
+            }
+        }
+    };
+    auto draw = [&](int t0) {
+        const int npair = (c + 1) / 2;
+        for (int p = tid; p < GCH * kKT * (VLD / 2); p += kThreads) {
+            const int g = p / (kKT * (VLD / 2)), rem = p % (kKT * (VLD / 2));
+            const int kk = rem % kKT, j = rem / kKT;
+            const int64_t tile = (int64_t)blockIdx.x + (int64_t)(t0 + g) * gridDim.x;
+            const int64_t k = tile * kKT + kk;
+            double z0 = 0.0, z1 = 0.0;
+            if (tile < a.ntiles && k < a.nh && j < npair)
+                gaussian_pair(a.seed, a.counter, (uint32_t)k, (uint32_t)j, z0, z1);
+            T *dst = sV + ((size_t)g * kKT + kk) * VLD + 2 * j;
+            dst[0] = T(z0);
+            dst[1] = (2 * j + 1 < c) ? T(z1) : T(0);
+        }
+    };
+    if ((int)blockIdx.x < a.ntiles) load_tile(blockIdx.x);
+    if (MODE == kSketch) draw(0);
+
+    int it = 0;
+    for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x, ++it) {
+        const int64_t k0 = (int64_t)tile * kKT;
+        const int kval = (int)min((int64_t)kKT, a.nh - k0);
+        if (MODE == kSketch && it > 0 && it % GCH == 0) draw(it);
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+            if (j < nj) {
+                cur[j] = pre[j];
+                sT[(r0 + 16 * j) * LD + kk_l] = cur[j];
+            }
+        if (MODE == kVecMul) {
+            for (int idx = tid; idx < kKT * VLD; idx += kThreads) {
+                const int kk = idx % kKT, j = idx / kKT;
+                sV[kk * VLD + j] = (kk < kval && j < c) ? a.V[(k0 + kk) + (int64_t)j * a.ldv] : T(0);
+            }
+        }
+        if (tile + (int)gridDim.x < a.ntiles) load_tile(tile + gridDim.x);
+
+        if (kNeedQ) {
+            // phase 1 from registers: rows r0 + 16 j, two accumulation chains
+            V4 z0[NB], z1[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                z0[b] = V4{0, 0, 0, 0};
+                z1[b] = V4{0, 0, 0, 0};
+            }
+#pragma unroll
+            for (int j = 0; j < NJ; j += 2) {
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    if (j < nj) z0[b] = M::mma(cur[j], qreg[j][b], z0[b]);
+                    if (j + 1 < nj) z1[b] = M::mma(cur[j + 1], qreg[j + 1][b], z1[b]);
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    sZp[((size_t)wave * kKT + M::drow(lane, r)) * VLD + b * 16 + (lane & 15)] = z0[b][r] + z1[b][r];
+            __syncthreads();
+            for (int idx = tid; idx < kKT * VLD; idx += kThreads) {
+                const size_t st = (size_t)kKT * VLD;
+                sV[idx] = ((sZp[idx] + sZp[st + idx]) + sZp[2 * st + idx]) + sZp[3 * st + idx];
+            }
+        }
+        __syncthreads();
+        if (MODE == kProject) {
+            for (int idx = tid; idx < kKT * c; idx += kThreads) {
+                const int kk = idx % kKT, j = idx / kKT;
+                if (kk < kval) a.Z[(k0 + kk) + (int64_t)j * a.ldz] = sV[kk * VLD + j];
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int p = tid + e * kThreads;
+                if (p < c * c) {
+                    const int x = p % c, y = p / c;
+                    double sum = 0.0;
+#pragma unroll
+                    for (int kk = 0; kk < kKT; ++kk) sum += (double)sV[kk * VLD + x] * (double)sV[kk * VLD + y];
+                    gacc[e] += sum;
+                }
+            }
+        }
+        if (kPhase2) {
+            const T *vb = sV + (MODE == kSketch ? (size_t)(it % GCH) * kKT * VLD : 0);
+            T bv[4][NB];
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+                for (int b = 0; b < NB; ++b) bv[ks][b] = vb[(ks * 4 + (lane >> 4)) * VLD + b * 16 + (lane & 15)];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int rb = wave + 4 * r;
+                if (rb < nrb) {
+                    const int i = rb * 16 + (lane & 15);
+#pragma unroll
+                    for (int ks = 0; ks < 4; ++ks) {
+                        const T av = sT[i * LD + ks * 4 + (lane >> 4)];
+#pragma unroll
+                        for (int b = 0; b < NB; ++b) acc[r][b] = M::mma(av, bv[ks][b], acc[r][b]);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (MODE == kProject) {
+        double *gp = a.Gpart + (size_t)blockIdx.x * c * c;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int p = tid + e * kThreads;
+            if (p < c * c) gp[p] = gacc[e];
+        }
+    } else {
+        T *yp = a.Ypart + (size_t)blockIdx.x * mh * c;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int rb = wave + 4 * r;
+            if (rb < nrb) {
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    const int j = b * 16 + (lane & 15);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int i = rb * 16 + M::drow(lane, q);
+                        if (i < mh && j < c) yp[i + (size_t)j * mh] = acc[r][b][q];
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <typename T, bool TR, int MODE, int NB>
+static hipError_t launch_long_rb(const LongPlan &p, const LongArgs<T> &a, hipStream_t s)
+{
+    if (p.rpt == 4)
+        hipLaunchKernelGGL((k_long<T, TR, MODE, NB, 4>), dim3(p.grid), dim3(kThreads), p.lds, s, a);
     else
-        hipLaunchKernelGGL((k_long<T, TR, MODE, CM, 2>), dim3(p.grid), dim3(kThreads), p.lds, s, a);
+        hipLaunchKernelGGL((k_long<T, TR, MODE, NB, 8>), dim3(p.grid), dim3(kThreads), p.lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, bool TR, int MODE, int CM>
+static hipError_t launch_long_v(const LongPlan &p, const LongArgs<T> &a, hipStream_t s)
+{
+    if (p.rptv == 1)
+        hipLaunchKernelGGL((k_long_v<T, TR, MODE, CM, 1>), dim3(p.grid), dim3(kThreads), p.ldsv, s, a);
+    else
+        hipLaunchKernelGGL((k_long_v<T, TR, MODE, CM, 2>), dim3(p.grid), dim3(kThreads), p.ldsv, s, a);
     return hipGetLastError();
 }
 
 template <typename T, bool TR, int MODE>
 static hipError_t launch_long_cm(const LongPlan &p, const LongArgs<T> &a, hipStream_t s)
 {
-    if (p.cm == 8) return launch_long_rpt<T, TR, MODE, 8>(p, a, s);
-    if (p.cm == 16) return launch_long_rpt<T, TR, MODE, 16>(p, a, s);
-    return launch_long_rpt<T, TR, MODE, 32>(p, a, s);
+    if (p.vec) {
+        if (p.cmv == 8) return launch_long_v<T, TR, MODE, 8>(p, a, s);
+        if (p.cmv == 16) return launch_long_v<T, TR, MODE, 16>(p, a, s);
+        return launch_long_v<T, TR, MODE, 32>(p, a, s);
+    }
+    if (p.cm == 16) return launch_long_rb<T, TR, MODE, 1>(p, a, s);
+    return launch_long_rb<T, TR, MODE, 2>(p, a, s);
+}
+
+template <typename T, int MODE>
+static hipError_t launch_long_tr(const LongPlan &p, const LongArgs<T> &a, uint32_t span, hipStream_t s)
+{
+    if (p.cm == 16)
+        hipLaunchKernelGGL((k_long_tr<T, MODE, 1>), dim3(p.grid), dim3(kThreads), p.ldst, s, a, span);
+    else
+        hipLaunchKernelGGL((k_long_tr<T, MODE, 2>), dim3(p.grid), dim3(kThreads), p.ldst, s, a, span);
+    return hipGetLastError();
 }
 
 template <typename T, bool TR>
@@ -245,11 +752,29 @@ static hipError_t launch_long_mode(const LongPlan &p, int mode, const LongArgs<T
 template <typename T>
 hipError_t launch_long(const LongPlan &p, int mode, const LongArgs<T> &a0, hipStream_t s)
 {
-    if (!long_path_ok(a0.mh, a0.c) || p.rpt > 2) return hipErrorInvalidValue;
+    if (!long_path_ok(a0.mh, a0.c) || p.mhp < a0.mh || p.mhp > kMaxMh || p.cm < a0.c ||
+        (p.rpt != 4 && p.rpt != 8) || 4 * p.rpt * 16 < p.mhp)
+        return hipErrorInvalidValue;
+    if (p.vec && (p.cmv < a0.c || (p.cmv != 8 && p.cmv != 16 && p.cmv != 32) || p.rptv < 1 ||
+                  p.rptv > 2 || p.rptv * kThreads < a0.mh))
+        return hipErrorInvalidValue;
     LongArgs<T> a = a0;
     a.kt = p.kt;
     a.mhp = p.mhp;
     a.ntiles = p.ntiles;
+    if (a.trans && p.mhp <= 256 && !p.vec) {
+        // byte span of A touched: rows (long index) < nh of columns < mh
+        const uint64_t span = ((uint64_t)(a.nh - 1) + (uint64_t)(a.mh - 1) * (uint64_t)a.lda + 1) * sizeof(T);
+        const uint64_t rows16 = (uint64_t)16 * (uint64_t)a.lda * sizeof(T) * (uint64_t)(p.mhp / 16);
+        if (span < kOob && rows16 < kOob) {
+            switch (mode) {
+            case kSketch: return launch_long_tr<T, kSketch>(p, a, (uint32_t)span, s);
+            case kVecMul: return launch_long_tr<T, kVecMul>(p, a, (uint32_t)span, s);
+            case kPower: return launch_long_tr<T, kPower>(p, a, (uint32_t)span, s);
+            default: return launch_long_tr<T, kProject>(p, a, (uint32_t)span, s);
+            }
+        }
+    }
     if (a.trans) return launch_long_mode<T, true>(p, mode, a, s);
     return launch_long_mode<T, false>(p, mode, a, s);
 }

@@ -204,7 +204,7 @@ template hipError_t launch_small_orth<float>(int, const float *, int64_t, int, c
 //            between the rotations of a step beyond the wavefront's own).
 //   l > 16 : wavefront per pair, lanes over rows, block barrier per round.
 // ===========================================================================
-bool small_svd_fuse_q_ok(int mh, int l) { return ((size_t)mh * l + 2 * (size_t)l * l) * sizeof(double) <= 96 * 1024; }
+bool small_svd_fuse_q_ok(int mh, int l) { return mh >= 1 && l >= 1 && 2 * (size_t)l * l * sizeof(double) <= 96 * 1024; }
 
 __device__ inline void circle_pair(int n2, int round, int t, int &p, int &q)
 {
@@ -256,12 +256,9 @@ __device__ int jacobi_wave16(double *M, int l, int max_sweeps)
                     y = M[q * l + row];
                 }
                 double al = x * x, be = y * y, ga = x * y;
-#pragma unroll
-                for (int off = 8; off > 0; off >>= 1) {
-                    al += __shfl_xor(al, off, 16);
-                    be += __shfl_xor(be, off, 16);
-                    ga += __shfl_xor(ga, off, 16);
-                }
+                al = seg16_sum(al);
+                be = seg16_sum(be);
+                ga = seg16_sum(ga);
                 const bool doit = live && fabs(ga) > tol * sqrt(al * be);
                 if (doit) {
                     double cs, sn;
@@ -432,33 +429,47 @@ __global__ void __launch_bounds__(NT) k_small_svd(int l, const double *Gin, doub
     }
     __syncthreads();
     if (fuse_q && Q) {
-        // QM = Q Mm and Qout = Q U(:, 1:r), with Q, Mm and U staged in LDS
-        // (the Jacobi storage M is free again).
+        // QM = Q Mm and Qout = Q U(:, 1:r): one row of Q per thread in
+        // registers, Mm and U broadcast from LDS (the Jacobi storage M is free).
         double *sU = reinterpret_cast<double *>(smem_raw);
         double *sMm = sU + (size_t)l * l;
-        double *sQ = sMm + (size_t)l * l;
         const int r = rank;
         for (int idx = tid; idx < l * l; idx += NT) {
             sU[idx] = out.U[idx];
             sMm[idx] = out.Mm[idx];
         }
-        for (int idx = tid; idx < mh * l; idx += NT) {
-            const int i = idx % mh, t = idx / mh;
-            sQ[(size_t)t * mh + i] = (double)Q[i + (int64_t)t * ldq];
-        }
         __syncthreads();
-        for (int idx = tid; idx < mh * l; idx += NT) {
-            const int i = idx % mh, j = idx / mh;
-            double v = 0.0;
-            for (int t = 0; t < l; ++t) v += sQ[(size_t)t * mh + i] * sMm[t + (size_t)j * l];
-            QM[i + (int64_t)j * ldqm] = (T)v;
-        }
-        if (Qout) {
-            for (int idx = tid; idx < mh * r; idx += NT) {
+        if (l <= 16) {
+            for (int i = tid; i < mh; i += NT) {
+                double q[16];
+#pragma unroll
+                for (int t = 0; t < 16; ++t) q[t] = t < l ? (double)Q[i + (int64_t)t * ldq] : 0.0;
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    if (j < l) {
+                        double v = 0.0, u = 0.0;
+#pragma unroll
+                        for (int t = 0; t < 16; ++t)
+                            if (t < l) {
+                                v += q[t] * sMm[t + j * l];
+                                u += q[t] * sU[t + j * l];
+                            }
+                        QM[i + (int64_t)j * ldqm] = (T)v;
+                        if (Qout && j < r) Qout[i + (int64_t)j * ldqo] = (T)u;
+                    }
+                }
+            }
+        } else {
+            for (int idx = tid; idx < mh * l; idx += NT) {
                 const int i = idx % mh, j = idx / mh;
-                double v = 0.0;
-                for (int t = 0; t < l; ++t) v += sQ[(size_t)t * mh + i] * sU[t + (size_t)j * l];
-                Qout[i + (int64_t)j * ldqo] = (T)v;
+                double v = 0.0, u = 0.0;
+                for (int t = 0; t < l; ++t) {
+                    const double qt = (double)Q[i + (int64_t)t * ldq];
+                    v += qt * sMm[t + (size_t)j * l];
+                    u += qt * sU[t + (size_t)j * l];
+                }
+                QM[i + (int64_t)j * ldqm] = (T)v;
+                if (Qout && j < r) Qout[i + (int64_t)j * ldqo] = (T)u;
             }
         }
     }
@@ -471,7 +482,7 @@ hipError_t launch_small_svd(int l, const double *G, double tau, const double *w,
 {
     if (l < 1 || l > 1024) return hipErrorInvalidValue;
     size_t lds = l <= 128 ? (size_t)l * l * sizeof(double) : 0;
-    if (fuse_q && Q) lds = std::max(lds, ((size_t)mh * l + 2 * (size_t)l * l) * sizeof(double));
+    if (fuse_q && Q) lds = std::max(lds, 2 * (size_t)l * l * sizeof(double));
     if (l <= 16)
         hipLaunchKernelGGL((k_small_svd<T, 64>), dim3(1), dim3(64), lds, s, l, G, tau, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, work, fuse_q);
     else if (l <= 64)

@@ -27,10 +27,12 @@ constexpr int kWMaxShort = 96;    // shortest side
 
 size_t wsvt_batched_lds() { return (size_t)kWMaxLong * kWMaxShort * 4 + (size_t)kWMaxShort * kWMaxShort * 8 + (size_t)kWMaxShort * kWMaxShort * 4; }
 
+// sum over the aligned group of gs lanes (gs = 8, 16 or 32), in every lane
 __device__ __forceinline__ double seg_sum(double v, int gs)
 {
-    for (int off = gs >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, gs);
-    return v;
+    if (gs == 8) return seg8_sum(v);
+    if (gs == 16) return seg16_sum(v);
+    return seg32_sum(v);
 }
 
 __global__ void __launch_bounds__(kWB) k_wsvt_batched(WsvtBatchArgs a)

@@ -212,3 +212,22 @@ def test_rpca_video_shape_matches_oracle(fr, orc):
     assert _rel(res.S.cpu().numpy(), out["S"]) <= 1e-10
     # identical sparsity pattern of S
     assert np.array_equal(res.S.cpu().numpy() != 0, out["S"] != 0)
+
+
+@pytest.mark.parametrize("q", [0, 1])
+def test_frsvt_near_degenerate_pair_full_basis(fr, orc, q):
+    """A pair of singular values 6e-13 apart straddling tau, l = mhat: the
+    result is exact SVT and must match the oracle to 1e-10.  The one-sided
+    Jacobi of the small SVD needs every lane of a pair group to agree on each
+    rotation; a lane-inconsistent reduction shows up here first."""
+    import numpy as np
+    m, n, tau = 14, 9, 2.0
+    s = np.array([9.0, 7.0, 5.0, tau + 1e-13, tau - 5e-13, 1.0, 0.5, 0.2, 0.1])
+    A = np.zeros((m, n))
+    A[np.arange(n), np.arange(n)] = s
+    Ad = torch.from_numpy(np.asfortranarray(A)).cuda()
+    X, Q, fac = fr.frsvt_fwd(Ad, tau, n, 0, q, seed=1)
+    Xo = orc.frsvt(A, tau, q, orc.gaussian_matrix(1, 0, m, n))[0]
+    sig = fac.cpu().numpy()[:n]
+    assert np.abs(sig - s).max() <= 1e-13 * s[0]
+    assert np.linalg.norm(X.cpu().numpy() - Xo) <= 1e-10 * np.linalg.norm(Xo)
