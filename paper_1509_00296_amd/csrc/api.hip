@@ -40,6 +40,8 @@ struct frsvt_context {
     hipStream_t wb_capture = nullptr;
     hipGraphExec_t wb_exec = nullptr;
     std::vector<uint64_t> wb_key;
+    // per-iteration status event of the RPCA host loop
+    hipEvent_t ev_iter = nullptr;
     // tracing: event pairs around launches, aggregated per kernel class
     bool tracing = false;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> recs;
@@ -1148,6 +1150,14 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
         int nz = 0;
         CKT(FRSVT_K_EPILOGUE, launch_recon<T>(kEpi, ra, &nz, s));
         CKT(FRSVT_K_REDUCE, launch_reduce<double>(zp, 1, nz, zsum, s));
+        // status words (rank, residual) to the host, marked by an event; the
+        // host waits for that event only, so the GPU keeps working on the
+        // speculative sketch below while the host reads them and enqueues
+        // the next iteration.
+        CK(hipMemcpyAsync(hst, h->dstatus, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
+        CK(hipMemcpyAsync(hst + 8, zsum, sizeof(double), hipMemcpyDeviceToHost, s));
+        if (!h->ev_iter) CK(hipEventCreateWithFlags(&h->ev_iter, hipEventDisableTiming));
+        CK(hipEventRecord(h->ev_iter, s));
         // The next sketch needs only the next A and its Philox counter; it
         // is enqueued before the host waits for this iteration's rank, with
         // p new samples (the width of every later sketch unless r + p > mh).
@@ -1161,9 +1171,7 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
                 spec_cnew = cn.cnew;
             }
         }
-        CK(hipMemcpyAsync(hst, h->dstatus, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
-        CK(hipMemcpyAsync(hst + 8, zsum, sizeof(double), hipMemcpyDeviceToHost, s));
-        CK(hipStreamSynchronize(s));
+        CK(hipEventSynchronize(h->ev_iter));
         const int r = hst[0];
         double zz;
         memcpy(&zz, hst + 8, sizeof(double));
@@ -1438,6 +1446,7 @@ int frsvt_destroy(frsvt_handle h)
         (void)hipEventDestroy(r.second.second);
     }
     for (auto e : h->pool) (void)hipEventDestroy(e);
+    if (h->ev_iter) (void)hipEventDestroy(h->ev_iter);
     if (h->wb_exec) (void)hipGraphExecDestroy(h->wb_exec);
     if (h->wb_capture) (void)hipStreamDestroy(h->wb_capture);
     if (h->wb_queue) (void)hipFree(h->wb_queue);

@@ -28,7 +28,7 @@ namespace frk {
 // ===========================================================================
 bool small_orth_ok(int mh, int l)
 {
-    return l >= 1 && l <= 64 && (size_t)(mh | 1) * l * 16 + (size_t)l * l * 16 <= 96 * 1024;
+    return l >= 1 && l <= 64 && (size_t)(mh | 1) * l * 16 + (size_t)l * l * 16 + 8192 <= 96 * 1024;
 }
 
 template <typename T, int NT>
@@ -60,47 +60,112 @@ __global__ void __launch_bounds__(NT) k_small_orth(int mh, const T *Qt, int64_t 
     }
     __syncthreads();
 
-    // 1. CGS2 against the propagated basis
-    if (rp > 0 && c > 0) {
-        for (int pass = 0; pass < 2; ++pass) {
-            for (int p = wave; p < rp * c; p += nw) {
-                const int t = p % rp, j = p / rp;
-                const double *qa = W + (size_t)t * mhp, *ya = W + (size_t)(rp + j) * mhp;
-                double s = 0.0;
-                for (int i = lane; i < mh; i += kWave) s += qa[i] * ya[i];
-                s = wave_sum(s);
-                if (lane == 0) G[t * c + j] = s;
-            }
-            __syncthreads();
-            for (int idx = tid; idx < mh * c; idx += NT) {
-                const int i = idx % mh, j = idx / mh;
-                double v = W[(size_t)(rp + j) * mhp + i];
-                for (int t = 0; t < rp; ++t) v -= W[(size_t)t * mhp + i] * G[t * c + j];
-                W[(size_t)(rp + j) * mhp + i] = v;
-            }
-            __syncthreads();
-        }
-    }
-    // 2. column equilibration, and a saved copy for the fallback
-    for (int j = wave; j < l; j += nw) {
-        const double *wj = W + (size_t)j * mhp;
-        double s = 0.0;
-        for (int i = lane; i < mh; i += kWave) s += wj[i] * wj[i];
-        s = wave_sum(s);
-        if (lane == 0) scal[j] = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
-    }
-    __syncthreads();
-    for (int idx = tid; idx < mh * l; idx += NT) {
-        const int i = idx % mh, j = idx / mh;
-        const double v = W[(size_t)j * mhp + i] * scal[j];
-        W[(size_t)j * mhp + i] = v;
-        W0[(size_t)j * mhp + i] = v;
-    }
-    __syncthreads();
-
-    // 3. fast path: CholeskyQR2
+    __shared__ int sh_info[2];
+    __shared__ double sh_ratio[2];
     bool fast = true;
-    {
+    if (l <= 16 && NT == 256) {
+        // ---- l <= 16: Grams on the matrix cores, Cholesky in one wavefront
+        double *part = R + (size_t)l * l;
+        // 1. CGS2: coefficients from the Qt-Y block of the Gram of [Qt, Y]
+        if (rp > 0 && c > 0) {
+            for (int pass = 0; pass < 2; ++pass) {
+                gram16_mfma(W, mh, mhp, l, G, part);
+                for (int i = tid; i < mh; i += NT) {
+                    double qt[16];
+#pragma unroll
+                    for (int t = 0; t < 16; ++t) qt[t] = t < rp ? W[(size_t)t * mhp + i] : 0.0;
+                    for (int j = 0; j < c; ++j) {
+                        double v = W[(size_t)(rp + j) * mhp + i];
+#pragma unroll
+                        for (int t = 0; t < 16; ++t)
+                            if (t < rp) v -= qt[t] * G[t * l + rp + j];
+                        W[(size_t)(rp + j) * mhp + i] = v;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        // 2. equilibration from the Gram's diagonal; the Gram of the scaled
+        //    basis is the scaled Gram
+        gram16_mfma(W, mh, mhp, l, G, part);
+        for (int j = tid; j < l; j += NT) {
+            const double d = G[j * l + j];
+            scal[j] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
+        }
+        __syncthreads();
+        for (int idx = tid; idx < mh * l; idx += NT) {
+            const int i = idx % mh, j = idx / mh;
+            const double v = W[(size_t)j * mhp + i] * scal[j];
+            W[(size_t)j * mhp + i] = v;
+            W0[(size_t)j * mhp + i] = v;
+        }
+        for (int idx = tid; idx < l * l; idx += NT) G[idx] *= scal[idx / l] * scal[idx % l];
+        __syncthreads();
+        // 3. CholeskyQR2
+        double mx = 0.0;
+        for (int j = 0; j < l; ++j) mx = fmax(mx, G[j * l + j]);
+        if (wave == 0) {
+            const CholInfo c1 = wave_chol16(G, l, 0.0, 16.0 * l * kU * fmax(mx, 1e-300), R, nullptr);
+            if (lane == 0) {
+                sh_info[0] = c1.nnull;
+                sh_ratio[0] = c1.min_ratio;
+            }
+        }
+        __syncthreads();
+        if (sh_info[0] > 0 || sh_ratio[0] < 1e-8) fast = false;
+        if (fast) {
+            block_trsm(W, mh, mhp, l, R);
+            gram16_mfma(W, mh, mhp, l, G, part);
+            if (wave == 0) {
+                const CholInfo c2 = wave_chol16(G, l, 0.0, 0.5, R, nullptr);
+                if (lane == 0) sh_info[1] = c2.nnull;
+            }
+            __syncthreads();
+            bool near_one = sh_info[1] == 0;
+            for (int j = 0; j < l && near_one; ++j) near_one = fabs(R[j * l + j] - 1.0) <= 1e-6;
+            if (near_one) block_trsm(W, mh, mhp, l, R);
+            else fast = false;
+        }
+    } else {
+        // 1. CGS2 against the propagated basis
+        if (rp > 0 && c > 0) {
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int p = wave; p < rp * c; p += nw) {
+                    const int t = p % rp, j = p / rp;
+                    const double *qa = W + (size_t)t * mhp, *ya = W + (size_t)(rp + j) * mhp;
+                    double s = 0.0;
+                    for (int i = lane; i < mh; i += kWave) s += qa[i] * ya[i];
+                    s = wave_sum(s);
+                    if (lane == 0) G[t * c + j] = s;
+                }
+                __syncthreads();
+                for (int idx = tid; idx < mh * c; idx += NT) {
+                    const int i = idx % mh, j = idx / mh;
+                    double v = W[(size_t)(rp + j) * mhp + i];
+                    for (int t = 0; t < rp; ++t) v -= W[(size_t)t * mhp + i] * G[t * c + j];
+                    W[(size_t)(rp + j) * mhp + i] = v;
+                }
+                __syncthreads();
+            }
+        }
+        // 2. column equilibration, and a saved copy for the fallback
+        for (int j = wave; j < l; j += nw) {
+            const double *wj = W + (size_t)j * mhp;
+            double s = 0.0;
+            for (int i = lane; i < mh; i += kWave) s += wj[i] * wj[i];
+            s = wave_sum(s);
+            if (lane == 0) scal[j] = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+        }
+        __syncthreads();
+        for (int idx = tid; idx < mh * l; idx += NT) {
+            const int i = idx % mh, j = idx / mh;
+            const double v = W[(size_t)j * mhp + i] * scal[j];
+            W[(size_t)j * mhp + i] = v;
+            W0[(size_t)j * mhp + i] = v;
+        }
+        __syncthreads();
+
+        // 3. fast path: CholeskyQR2
         block_gram(W, mh, mhp, l, G);
         double mx = 0.0;
         for (int j = 0; j < l; ++j) mx = fmax(mx, G[j * l + j]);
@@ -182,7 +247,7 @@ hipError_t launch_small_orth(int mh, const T *Qt, int64_t ldqt, int rp, const T 
 {
     const int l = rp + c;
     if (!small_orth_ok(mh, l)) return hipErrorInvalidValue;
-    const size_t lds = (2 * (size_t)l * (mh | 1) + 2 * (size_t)l * l) * sizeof(double);
+    const size_t lds = (2 * (size_t)l * (mh | 1) + 2 * (size_t)l * l + 4 * 256) * sizeof(double);
     hipLaunchKernelGGL((k_small_orth<T, 256>), dim3(1), dim3(256), lds, s, mh, Qt, ldqt, rp, Y,
                        ldy, c, Q, ldq, seed, counter, flags);
     return hipGetLastError();
@@ -222,15 +287,37 @@ __device__ inline void circle_pair(int n2, int round, int t, int &p, int &q)
     }
 }
 
+// Rotation of the pair with squared norms al, be and inner product ga:
+// t = sgn(zeta) / (|zeta| + sqrt(1 + zeta^2)), zeta = (be - al) / (2 ga),
+// evaluated as sgn(d) 2ga / (|d| + sqrt(d^2 + 4 ga^2)), d = be - al (one
+// square root and one division fewer); the zeta form is kept for operands
+// whose squares would overflow.
 __device__ inline void jacobi_rotation(double al, double be, double ga, double &cs, double &sn)
 {
-    const double zeta = (be - al) / (2.0 * ga);
-    const double t1 = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
+    const double d = be - al, g2 = 2.0 * ga;
+    const double h = sqrt(d * d + g2 * g2);
+    double t1;
+    if (h < 1e300) {
+        t1 = (d >= 0.0 ? g2 : -g2) / (fabs(d) + h);
+    } else {
+        const double zeta = d / g2;
+        t1 = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
+    }
     cs = 1.0 / sqrt(1.0 + t1 * t1);
     sn = cs * t1;
 }
 
-// One wavefront, l <= 16.  M column-major with ld = l.
+// Orders this wavefront's LDS accesses around a point (DS instructions of one
+// wavefront execute in order); used where a single wavefront works alone.
+__device__ __forceinline__ void wave_sync()
+{
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_wave_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// One wavefront, l <= 16, run by a single wavefront of the workgroup (no
+// block barrier inside).  M column-major with ld = l.
 __device__ int jacobi_wave16(double *M, int l, int max_sweeps)
 {
     const int lane = threadIdx.x % kWave;
@@ -269,7 +356,7 @@ __device__ int jacobi_wave16(double *M, int l, int max_sweeps)
                     }
                 }
                 rot |= __any(doit) ? 1 : 0;
-                __syncthreads();
+                wave_sync();
             }
         }
         if (!rot) break;
@@ -346,6 +433,18 @@ __global__ void __launch_bounds__(NT) k_small_svd(int l, const double *Gin, doub
     // Read column-major, column j of M is row j of R, i.e. M = R^T.
     for (int idx = tid; idx < l * l; idx += NT) M[idx] = Gin[idx];
     __syncthreads();
+    int sweeps = 0;
+    if (NT >= 256 && l <= 16) {
+        // wavefront 0 alone: register Cholesky, then the Jacobi
+        if (wave == 0) {
+            double maxdiag = 0.0;
+            for (int j = 0; j < l; ++j) maxdiag = fmax(maxdiag, M[j * l + j]);
+            wave_chol16(M, l, 0.0, 4.0 * l * kU * maxdiag, M, nullptr, false);
+            wave_sync();
+            sweeps = jacobi_wave16(M, l, 60);
+        }
+        __syncthreads();
+    } else {
     double maxdiag = 0.0;
     for (int j = 0; j < l; ++j) maxdiag = fmax(maxdiag, M[j * l + j]);
     const double ptol = 4.0 * l * kU * maxdiag;
@@ -372,10 +471,10 @@ __global__ void __launch_bounds__(NT) k_small_svd(int l, const double *Gin, doub
     }
     __syncthreads();
 
-    int sweeps;
     if (NT == kWave && l <= 16) sweeps = jacobi_wave16(M, l, 60);
     else sweeps = jacobi_block<NT>(M, l, l, l, 60, &sh_rot);
     __syncthreads();
+    }
 
     for (int j = wave; j < l; j += nw) {
         const double *mj = M + (size_t)j * l;
@@ -483,9 +582,7 @@ hipError_t launch_small_svd(int l, const double *G, double tau, const double *w,
     if (l < 1 || l > 1024) return hipErrorInvalidValue;
     size_t lds = l <= 128 ? (size_t)l * l * sizeof(double) : 0;
     if (fuse_q && Q) lds = std::max(lds, 2 * (size_t)l * l * sizeof(double));
-    if (l <= 16)
-        hipLaunchKernelGGL((k_small_svd<T, 64>), dim3(1), dim3(64), lds, s, l, G, tau, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, work, fuse_q);
-    else if (l <= 64)
+    if (l <= 64)
         hipLaunchKernelGGL((k_small_svd<T, 256>), dim3(1), dim3(256), lds, s, l, G, tau, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, work, fuse_q);
     else
         hipLaunchKernelGGL((k_small_svd<T, 1024>), dim3(1), dim3(1024), lds, s, l, G, tau, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, work, fuse_q);
