@@ -329,6 +329,10 @@ int ahat_t_times(frsvt_context *h, const Core<T> &c, const T *Qm, int64_t ldq, i
 template <typename T>
 int gram(frsvt_context *h, int64_t rows, int l, const T *Y, int64_t ldy, double *G, double *part)
 {
+    if (l <= 128) {
+        CKT(FRSVT_K_GEMM, launch_gram_tall<T>(rows, l, Y, ldy, part, G, h->stream));
+        return FRSVT_OK;
+    }
     const int sk = gemm_splitk(l, l, rows, h->num_cu);
     if (std::is_same<T, double>::value) {
         CKT(FRSVT_K_GEMM, (launch_gemm<double, double, double>(l, l, rows, (const double *)Y, ldy, 1,

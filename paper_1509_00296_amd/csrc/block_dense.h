@@ -9,7 +9,7 @@ namespace frk {
 // [a * l + b] (R upper triangular, row-major).
 
 // G = W^T W (full symmetric), one wavefront per (a, b) pair, lanes over rows.
-__device__ inline void block_gram(const double *W, int mh, int mhp, int l, double *G)
+__device__ __forceinline__ void block_gram(const double *W, int mh, int mhp, int l, double *G)
 {
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     const int nw = blockDim.x / kWave;
@@ -42,7 +42,7 @@ struct CholInfo {
 // forms the pivot itself from LDS (no broadcast step), so each column costs
 // one barrier.  Pivots <= null_tol are numerically null: R_jj = 1, zero row,
 // null_flags[j] = 1.
-__device__ inline CholInfo block_chol(const double *G, int l, double shift, double null_tol,
+__device__ __forceinline__ CholInfo block_chol(const double *G, int l, double shift, double null_tol,
                                       double *R, int *null_flags)
 {
     const int tid = threadIdx.x;
@@ -75,7 +75,7 @@ __device__ inline CholInfo block_chol(const double *G, int l, double shift, doub
 
 // W <- W R^{-1} (R upper, row-major), each thread owns rows; for l <= 16 a
 // row is held in registers while it is solved.
-__device__ inline void block_trsm(double *W, int mh, int mhp, int l, const double *R)
+__device__ __forceinline__ void block_trsm(double *W, int mh, int mhp, int l, const double *R)
 {
     if (l <= 16) {
         for (int i = threadIdx.x; i < mh; i += blockDim.x) {
@@ -118,7 +118,7 @@ typedef __attribute__((__vector_size__(4 * sizeof(double)))) double bd_doublex4;
 // the same element W(i, a) with a = lane % 16, i = step + lane / 16.  The
 // four partial 16 x 16 blocks are added in a fixed order.  part: 4 * 256
 // doubles of LDS.  Ends with a barrier.
-__device__ inline void gram16_mfma(const double *W, int mh, int mhp, int l, double *G, double *part)
+__device__ __forceinline__ void gram16_mfma(const double *W, int mh, int mhp, int l, double *G, double *part)
 {
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     const int a = lane & 15, ko = lane >> 4;
@@ -154,7 +154,7 @@ __device__ inline void gram16_mfma(const double *W, int mh, int mhp, int l, doub
 // numerically null: a zero row with R_jj = 1 (null_pivot_one) or 0.  G may
 // alias R (it is read into registers first).  No barrier inside: call from
 // one wavefront, synchronise afterwards.
-__device__ inline CholInfo wave_chol16(const double *G, int l, double shift, double null_tol,
+__device__ __forceinline__ CholInfo wave_chol16(const double *G, int l, double shift, double null_tol,
                                        double *R, int *null_flags, bool null_pivot_one = true)
 {
     const int k = threadIdx.x % kWave;
@@ -185,15 +185,122 @@ __device__ inline CholInfo wave_chol16(const double *G, int l, double shift, dou
         else if (k > j && k < l && !isnull) rjk = gj * inv;
         if (k < l) R[j * l + k] = rjk;
         if (k == 0 && null_flags) null_flags[j] = isnull ? 1 : 0;
+        // rows i >= l take zero updates (lanes k >= l hold rjk = 0), so the
+        // loop needs no runtime bound
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            if (i > j && i < l) {
+            if (i > j) {
                 const double rji = read_lane(rjk, i);
-                if (k > j) g[i] -= rji * rjk;
+                g[i] = (k > j) ? g[i] - rji * rjk : g[i];
             }
         }
     }
     return info;
+}
+
+// Cholesky of the symmetric l x l matrix M (row-major; the upper triangle
+// is read) by NT threads: thread t owns one 4 x 4 block (bi <= bj, dealt in
+// row-major order over the block triangle; nb (nb + 1) / 2 <= NT blocks,
+// nb = ceil(l / 4)) in registers.  Step j: the owner of (j, j) has
+// published the updated diagonal d_j in sh_d[j]; every thread forms the
+// pivot from it (d_j <= tol: numerically null, pivot null_piv and a zero
+// row); the owners of row j scale it and publish it in rowbuf (16-byte
+// aligned, at least 4 nb doubles); the trailing triangle takes the rank-one
+// update (eight reads of rowbuf for sixteen products per thread) and the
+// owner of (j + 1, j + 1) publishes d_{j+1}.  Two barriers per step.  R is
+// written back into M (upper, row-major, zeros below).  Returns the number
+// of null pivots; null_flags[j] (if given) marks them.
+template <int NT>
+__device__ __forceinline__ int chol_blk4(double *M, int l, double tol, double null_piv, double *rowbuf,
+                                         double *sh_d, int *null_flags)
+{
+    const int tid = threadIdx.x;
+    const int nb = (l + 3) / 4;
+    int bi = nb, bj = nb;
+    {
+        int rem = tid, r = 0;
+        while (r < nb && rem >= nb - r) {
+            rem -= nb - r;
+            ++r;
+        }
+        if (r < nb) {
+            bi = r;
+            bj = r + rem;
+        }
+    }
+    const bool owner = bi < nb;
+    const int a0 = 4 * bi, b0 = 4 * bj;
+    double v[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int a = a0 + r, b = b0 + c;
+            v[r][c] = (owner && a < l && b < l && b >= a) ? M[a * l + b] : 0.0;
+        }
+    if (owner && bi == 0 && bj == 0) sh_d[0] = v[0][0];
+    __syncthreads();
+    int nnull = 0;
+    for (int j = 0; j < l; ++j) {
+        const double d = sh_d[j];
+        const bool isnull = !(d > tol);
+        const double piv = isnull ? null_piv : sqrt(d);
+        const double inv = isnull ? 0.0 : 1.0 / piv;
+        nnull += isnull ? 1 : 0;
+        if (owner && bi == (j >> 2)) {
+            const int rj = j & 3;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (r == rj) {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const int b = b0 + c;
+                        v[r][c] = b == j ? piv : (b > j ? v[r][c] * inv : v[r][c]);
+                        if (b > j && b < l) rowbuf[b] = v[r][c];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (!isnull && owner && b0 + 3 > j) {
+            const double2 *ra2 = reinterpret_cast<const double2 *>(rowbuf + a0);
+            const double2 *rb2 = reinterpret_cast<const double2 *>(rowbuf + b0);
+            const double2 x0 = ra2[0], x1 = ra2[1], y0 = rb2[0], y1 = rb2[1];
+            const double xa[4] = {x0.x, x0.y, x1.x, x1.y}, yb[4] = {y0.x, y0.y, y1.x, y1.y};
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int a = a0 + r, b = b0 + c;
+                    const double nv = v[r][c] - xa[r] * yb[c];
+                    v[r][c] = (a > j && b >= a) ? nv : v[r][c];
+                }
+        }
+        const int j1 = j + 1;
+        if (owner && j1 < l && bi == (j1 >> 2) && bj == bi) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (r == (j1 & 3)) sh_d[j1] = v[r][r];
+        }
+        __syncthreads();
+    }
+    for (int idx = tid; idx < l * l; idx += NT) {
+        const int a = idx / l, b = idx - a * l;
+        if (b < a) M[idx] = 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int a = a0 + r, b = b0 + c;
+            if (owner && a < l && b < l && b >= a) M[a * l + b] = v[r][c];
+        }
+    // the published diagonals decide the null flags (no global store inside
+    // the step loop, whose barriers would wait for it)
+    if (null_flags)
+        for (int j = tid; j < l; j += NT) null_flags[j] = (sh_d[j] > tol) ? 0 : 1;
+    __syncthreads();
+    return nnull;
 }
 
 }  // namespace frk

@@ -137,31 +137,117 @@ template hipError_t launch_omega<double>(int64_t, int, uint64_t, uint64_t, doubl
 template hipError_t launch_omega<float>(int64_t, int, uint64_t, uint64_t, float *, int64_t, hipStream_t);
 
 // ===========================================================================
-// Large-path CholeskyQR pieces.
+// Large-path CholeskyQR pieces (l <= 128 columns).
 // ===========================================================================
-__global__ void __launch_bounds__(kThreads) k_chol(int l, const double *G, double shift_factor, double null_tol, double *R, int *null_cols, int *flags)
+typedef __attribute__((__vector_size__(4 * sizeof(double)))) double gd_doublex4;
+
+// Partial Grams of a tall rows x l matrix Y (column-major, ld) on the
+// matrix cores: workgroup g takes rows [g rpw, (g + 1) rpw) and writes
+// the full l x l partial Gram to part + g l^2 ([a * l + b]).  The 16 x 16
+// blocks (bi <= bj) of the upper triangle are dealt round-robin to the four
+// wavefronts; a step takes 8 rows as two 16x16x4 products, k-slot s of the
+// first holding row 2s and of the second row 2s + 1.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_gram_tall(int64_t rows, int l, const T *__restrict__ Y,
+                                                        int64_t ldy, int64_t rpw, double *part)
 {
-    // G staged in LDS; the factor is formed directly in the output R
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    const int c = lane & 15, s = lane >> 4;
+    const int nb = (l + 15) / 16;
+    const int64_t r0 = (int64_t)blockIdx.x * rpw, r1 = min(rows, r0 + rpw);
+    gd_doublex4 acc[9];
+#pragma unroll
+    for (int p = 0; p < 9; ++p) acc[p] = gd_doublex4{0.0, 0.0, 0.0, 0.0};
+    for (int64_t i0 = r0; i0 < r1; i0 += 8) {
+        const int64_t ia = i0 + 2 * s, ib = ia + 1;
+        double v0[8], v1[8];
+#pragma unroll
+        for (int bk = 0; bk < 8; ++bk) {
+            const int col = 16 * bk + c;
+            const bool okc = bk < nb && col < l;
+            const T *yc = Y + (int64_t)col * ldy;
+            v0[bk] = (okc && ia < r1) ? (double)yc[ia] : 0.0;
+            v1[bk] = (okc && ib < r1) ? (double)yc[ib] : 0.0;
+        }
+        int idx = 0;
+#pragma unroll
+        for (int bi = 0; bi < 8; ++bi)
+#pragma unroll
+            for (int bj = bi; bj < 8; ++bj, ++idx) {
+                if ((idx & 3) == wave && bj < nb) {
+                    acc[idx >> 2] = __builtin_amdgcn_mfma_f64_16x16x4f64(v0[bi], v0[bj], acc[idx >> 2], 0, 0, 0);
+                    acc[idx >> 2] = __builtin_amdgcn_mfma_f64_16x16x4f64(v1[bi], v1[bj], acc[idx >> 2], 0, 0, 0);
+                }
+            }
+    }
+    double *pg = part + (int64_t)blockIdx.x * l * l;
+    int idx = 0;
+#pragma unroll
+    for (int bi = 0; bi < 8; ++bi)
+#pragma unroll
+        for (int bj = bi; bj < 8; ++bj, ++idx) {
+            if ((idx & 3) == wave && bj < nb) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int a = 16 * bi + s + 4 * e, b = 16 * bj + c;
+                    if (a < l && b < l) {
+                        pg[a * l + b] = acc[idx >> 2][e];
+                        pg[b * l + a] = acc[idx >> 2][e];
+                    }
+                }
+            }
+        }
+}
+
+template <typename T>
+hipError_t launch_gram_tall(int64_t rows, int l, const T *Y, int64_t ldy, double *part, double *G,
+                            hipStream_t s)
+{
+    if (l < 1 || l > 128) return hipErrorInvalidValue;
+    int64_t rpw = std::max<int64_t>(64, (rows + 63) / 64);
+    rpw = (rpw + 7) / 8 * 8;
+    const int nparts = (int)std::max<int64_t>(1, (rows + rpw - 1) / rpw);
+    hipLaunchKernelGGL((k_gram_tall<T>), dim3(nparts), dim3(kThreads), 0, s, rows, l, Y, ldy, rpw, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_reduce<double>(part, (int64_t)l * l, nparts, G, s);
+}
+template hipError_t launch_gram_tall<double>(int64_t, int, const double *, int64_t, double *, double *, hipStream_t);
+template hipError_t launch_gram_tall<float>(int64_t, int, const float *, int64_t, double *, double *, hipStream_t);
+
+// Cholesky of (G + shift I), shift = shift_factor trace(G), by one
+// workgroup with the upper triangle dealt to the threads' registers in
+// 4 x 4 blocks (chol_blk4).  Pivots <= null_tol max_j G_jj are
+// numerically null: R_jj = 1 and a zero row (null_cols[j] = 1).  R is
+// written whole (upper, row-major [j * l + k], zeros below the diagonal).
+constexpr int kCholThreads = 576;  // >= 528 blocks of 4 x 4 for l <= 128
+__global__ void __launch_bounds__(kCholThreads) k_chol(int l, const double *G, double shift_factor, double null_tol, double *R, int *null_cols, int *flags)
+{
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    double *sG = reinterpret_cast<double *>(smem_raw);
-    double *sR = R;
+    double *M = reinterpret_cast<double *>(smem_raw);
     __shared__ double shift, tolabs;
-    for (int idx = threadIdx.x; idx < l * l; idx += kThreads) sG[idx] = G[idx];
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < l * l; idx += kCholThreads) M[idx] = G[idx];
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         double tr = 0.0, mx = 0.0;
         for (int j = 0; j < l; ++j) {
-            tr += sG[j * l + j];
-            mx = fmax(mx, sG[j * l + j]);
+            tr += M[j * l + j];
+            mx = fmax(mx, M[j * l + j]);
         }
         shift = shift_factor * tr;
         tolabs = null_tol > 0.0 ? null_tol * fmax(mx, 1e-300) : 0.0;
     }
     __syncthreads();
-    const CholInfo ci = block_chol(sG, l, shift, tolabs, sR, null_cols);
-    if (threadIdx.x == 0 && flags) {
-        flags[1] = ci.nnull;
-        if (null_tol <= 0.0 && ci.nnull > 0) flags[2] |= 1;
+    for (int j = tid; j < l; j += kCholThreads) M[j * l + j] += shift;
+    __syncthreads();
+    __shared__ __align__(16) double rowbuf[128];
+    __shared__ double sh_d[128];
+    const int nn = chol_blk4<kCholThreads>(M, l, tolabs, 1.0, rowbuf, sh_d, null_cols);
+    for (int idx = tid; idx < l * l; idx += kCholThreads) R[idx] = M[idx];
+    if (tid == 0 && flags) {
+        flags[1] = nn;
+        if (null_tol <= 0.0 && nn > 0) flags[2] |= 1;
     }
 }
 
@@ -169,38 +255,94 @@ hipError_t launch_chol(int l, const double *G, double shift_factor, double null_
 {
     const size_t lds = (size_t)l * l * sizeof(double);
     if (l > 128) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_chol, dim3(1), dim3(kThreads), lds, s, l, G, shift_factor, null_tol, R, null_cols, flags);
+    hipLaunchKernelGGL(k_chol, dim3(1), dim3(kCholThreads), lds, s, l, G, shift_factor, null_tol, R, null_cols, flags);
     return hipGetLastError();
 }
 
+// Y <- Y R^{-1} (R upper, row-major, l <= 128).  A workgroup of four
+// wavefronts takes 64 rows, one row per lane, and solves blocks of 16
+// columns: for block J the four wavefronts split the update by the
+// already-solved column t (t = w mod 4), their partial sums are added in
+// wavefront order, and wavefront 0 solves the 16 x 16 diagonal block with
+// the reciprocals of R's diagonal.  Solved columns stay in LDS (column t at
+// sY[t * 64 + lane]); the panel R(0 : J + 16, J : J + 16) is staged in LDS
+// (zero off the diagonal and unit diagonal past column l) and read by
+// broadcast.
+constexpr int kTrsmThreads = 256;
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_trsm(int64_t rows, int l, T *Y, int64_t ldy, const double *R)
+__global__ void __launch_bounds__(kTrsmThreads) k_trsm(int64_t rows, int l, T *Y, int64_t ldy, const double *__restrict__ R)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const double *sR = R;
-    if (l <= 90) {
-        double *t = reinterpret_cast<double *>(smem_raw);
-        for (int idx = threadIdx.x; idx < l * l; idx += kThreads) t[idx] = R[idx];
-        sR = t;
+    __shared__ double sY[128 * kWave];
+    __shared__ __align__(16) double sR[128 * 16];
+    __shared__ double sRinv[16];
+    __shared__ double sPart[3 * 16 * kWave];
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    const int64_t i = (int64_t)blockIdx.x * kWave + lane;
+    const bool live = i < rows;
+    for (int J = 0; J < l; J += 16) {
+        const int ne = (J + 16) * 16;
+        for (int e = threadIdx.x; e < ne; e += kTrsmThreads) {
+            const int t = e / 16, c = J + e % 16;
+            sR[e] = (t < l && c < l) ? R[(int64_t)t * l + c] : (t == c ? 1.0 : 0.0);
+        }
+        if (threadIdx.x < 16) {
+            const int c = J + threadIdx.x;
+            sRinv[threadIdx.x] = c < l ? 1.0 / R[(int64_t)c * l + c] : 1.0;
+        }
+        double acc[16];
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj)
+            acc[jj] = (wave == 0 && live && J + jj < l) ? (double)Y[i + (int64_t)(J + jj) * ldy] : 0.0;
+        __syncthreads();
+#pragma unroll 2
+        for (int t = wave; t < J; t += 4) {
+            const double yt = sY[t * kWave + lane];
+            const double2 *rt = reinterpret_cast<const double2 *>(sR + t * 16);
+#pragma unroll
+            for (int h = 0; h < 8; ++h) {
+                const double2 r = rt[h];
+                acc[2 * h] -= yt * r.x;
+                acc[2 * h + 1] -= yt * r.y;
+            }
+        }
+        if (J > 0) {
+            if (wave > 0) {
+#pragma unroll
+                for (int jj = 0; jj < 16; ++jj) sPart[((wave - 1) * 16 + jj) * kWave + lane] = acc[jj];
+            }
+            __syncthreads();
+        }
+        if (wave == 0) {
+            if (J > 0) {
+#pragma unroll
+                for (int jj = 0; jj < 16; ++jj)
+                    acc[jj] = ((acc[jj] + sPart[jj * kWave + lane]) + sPart[(16 + jj) * kWave + lane]) +
+                              sPart[(32 + jj) * kWave + lane];
+            }
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj) {
+                double v = acc[jj];
+#pragma unroll
+                for (int tt = 0; tt < jj; ++tt) v -= acc[tt] * sR[(J + tt) * 16 + jj];
+                acc[jj] = v * sRinv[jj];
+            }
+            // stores after the block's solves: a global store ahead of a
+            // later load's first use would make that use wait for the store
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj) {
+                sY[(J + jj) * kWave + lane] = acc[jj];
+                if (live && J + jj < l) Y[i + (int64_t)(J + jj) * ldy] = (T)acc[jj];
+            }
+        }
         __syncthreads();
     }
-    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i >= rows) return;
-    double y[128];
-    for (int j = 0; j < l; ++j) {
-        double v = (double)Y[i + (int64_t)j * ldy];
-        for (int t = 0; t < j; ++t) v -= y[t] * sR[t * l + j];
-        y[j] = v / sR[j * l + j];
-    }
-    for (int j = 0; j < l; ++j) Y[i + (int64_t)j * ldy] = (T)y[j];
 }
 
 template <typename T>
 hipError_t launch_trsm(int64_t rows, int l, T *Y, int64_t ldy, const double *R, hipStream_t s)
 {
     if (l > 128) return hipErrorInvalidValue;
-    const size_t lds = l <= 90 ? (size_t)l * l * sizeof(double) : 0;
-    hipLaunchKernelGGL((k_trsm<T>), dim3((unsigned)((rows + kThreads - 1) / kThreads)), dim3(kThreads), lds, s, rows, l, Y, ldy, R);
+    hipLaunchKernelGGL((k_trsm<T>), dim3((unsigned)((rows + kWave - 1) / kWave)), dim3(kTrsmThreads), 0, s, rows, l, Y, ldy, R);
     return hipGetLastError();
 }
 template hipError_t launch_trsm<double>(int64_t, int, double *, int64_t, const double *, hipStream_t);
@@ -231,9 +373,10 @@ template hipError_t launch_refill<float>(int64_t, int, float *, int64_t, const i
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_col_scale(int64_t rows, int l, T *Y, int64_t ldy, const double *G)
 {
-    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i >= rows) return;
-    for (int j = 0; j < l; ++j) {
+    const int64_t total = rows * l;
+    for (int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * kThreads) {
+        const int64_t i = idx % rows;
+        const int j = (int)(idx / rows);
         const double g = G[j * l + j];
         const double sc = g > 0.0 ? 1.0 / sqrt(g) : 0.0;
         Y[i + (int64_t)j * ldy] = (T)((double)Y[i + (int64_t)j * ldy] * sc);
@@ -243,7 +386,9 @@ __global__ void __launch_bounds__(kThreads) k_col_scale(int64_t rows, int l, T *
 template <typename T>
 hipError_t launch_col_scale(int64_t rows, int l, T *Y, int64_t ldy, const double *G, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_col_scale<T>), dim3((unsigned)((rows + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, rows, l, Y, ldy, G);
+    const int64_t total = rows * l;
+    const unsigned g = (unsigned)std::min<int64_t>(2048, std::max<int64_t>(1, (total + kThreads - 1) / kThreads));
+    hipLaunchKernelGGL((k_col_scale<T>), dim3(g), dim3(kThreads), 0, s, rows, l, Y, ldy, G);
     return hipGetLastError();
 }
 template hipError_t launch_col_scale<double>(int64_t, int, double *, int64_t, const double *, hipStream_t);

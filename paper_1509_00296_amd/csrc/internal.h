@@ -161,9 +161,15 @@ hipError_t launch_omega(int64_t rows, int cols, uint64_t seed, uint64_t counter,
 // flagged (flags[1] counts them, null_cols[j] = 1) and get R_jj = 1 with a
 // zero row.  flags[2] |= 1 when a pivot is not positive in a pass without
 // null handling.
+// G = Y^T Y (l x l, [a * l + b]) for a tall rows x l matrix, l <= 128:
+// partial Grams on the matrix cores into part (at most 64 l^2 doubles), then
+// their sum.
+template <typename T>
+hipError_t launch_gram_tall(int64_t rows, int l, const T *Y, int64_t ldy, double *part, double *G,
+                            hipStream_t s);
 hipError_t launch_chol(int l, const double *G, double shift_factor, double null_tol, double *R,
                        int *null_cols, int *flags, hipStream_t s);
-// Y (rows x l) <- Y R^{-1} in place (R upper, double), one thread per row.
+// Y (rows x l) <- Y R^{-1} in place (R upper, double), one lane per row.
 template <typename T>
 hipError_t launch_trsm(int64_t rows, int l, T *Y, int64_t ldy, const double *R, hipStream_t s);
 // Y(:, j) <- Gaussian(refill stream) for null_cols[j] = 1; also scales

@@ -267,18 +267,22 @@ template hipError_t launch_small_orth<float>(int, const float *, int64_t, int, c
 //   l <= 16: one wavefront; four groups of 16 lanes each rotate one pair,
 //            lane = row, with 16-lane shuffle reductions (no barriers
 //            between the rotations of a step beyond the wavefront's own).
-//   l > 16 : wavefront per pair, lanes over rows, block barrier per round.
+//   l > 16 : groups of 16 lanes (64 beyond l = 256), one pair per group,
+//            rows in registers, one block barrier per round.
 // ===========================================================================
 bool small_svd_fuse_q_ok(int mh, int l) { return mh >= 1 && l >= 1 && 2 * (size_t)l * l * sizeof(double) <= 96 * 1024; }
 
 __device__ inline void circle_pair(int n2, int round, int t, int &p, int &q)
 {
+    // 0 <= round, t < n2 - 1: both sums lie in [0, 2 (n2 - 1))
     if (t == 0) {
         p = n2 - 1;
         q = round;
     } else {
-        p = (round + t) % (n2 - 1);
-        q = (round - t + n2 - 1) % (n2 - 1);
+        p = round + t;
+        q = round - t + n2 - 1;
+        if (p >= n2 - 1) p -= n2 - 1;
+        if (q >= n2 - 1) q -= n2 - 1;
     }
     if (p > q) {
         const int tmp = p;
@@ -303,8 +307,16 @@ __device__ inline void jacobi_rotation(double al, double be, double ga, double &
         const double zeta = d / g2;
         t1 = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
     }
-    cs = 1.0 / sqrt(1.0 + t1 * t1);
+    cs = rsqrt(1.0 + t1 * t1);
     sn = cs * t1;
+}
+
+// The rotation test |ga| > tol sqrt(al be), squared where al be is finite
+// and far from overflow (no square root on the common path).
+__device__ __forceinline__ bool jacobi_needed(double al, double be, double ga, double tol)
+{
+    const double ab = al * be;
+    return ab < 1e300 ? ga * ga > (tol * tol) * ab : fabs(ga) > tol * sqrt(ab);
 }
 
 // Orders this wavefront's LDS accesses around a point (DS instructions of one
@@ -318,7 +330,7 @@ __device__ __forceinline__ void wave_sync()
 
 // One wavefront, l <= 16, run by a single wavefront of the workgroup (no
 // block barrier inside).  M column-major with ld = l.
-__device__ int jacobi_wave16(double *M, int l, int max_sweeps)
+__device__ __forceinline__ int jacobi_wave16(double *M, int l, int max_sweeps)
 {
     const int lane = threadIdx.x % kWave;
     const int g = lane / 16, row = lane % 16;
@@ -346,7 +358,7 @@ __device__ int jacobi_wave16(double *M, int l, int max_sweeps)
                 al = seg16_sum(al);
                 be = seg16_sum(be);
                 ga = seg16_sum(ga);
-                const bool doit = live && fabs(ga) > tol * sqrt(al * be);
+                const bool doit = live && jacobi_needed(al, be, ga, tol);
                 if (doit) {
                     double cs, sn;
                     jacobi_rotation(al, be, ga, cs, sn);
@@ -364,43 +376,74 @@ __device__ int jacobi_wave16(double *M, int l, int max_sweeps)
     return sweep;
 }
 
-// Block of NT threads, any l; M at a generic (LDS or global) address.
-template <int NT>
-__device__ int jacobi_block(double *M, int rows, int ld, int n, int max_sweeps, int *sh_rot)
+// One-sided Jacobi on the n columns (length rows, stride ld) of M by groups
+// of G lanes (G = 16 or 64): a group rotates one pair of the round, lane i of
+// the group holding rows i, i + G, ..., i + (E - 1) G in registers.  Rounds
+// with more pairs than groups take several passes (their pairs are
+// disjoint); one block barrier per round.  M may be in LDS or global memory.
+template <int NT, int G, int E>
+__device__ __forceinline__ int jacobi_groups(double *M, int rows, int ld, int n, int max_sweeps, int *sh_rot)
 {
-    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-    constexpr int nw = NT / kWave;
-    const int n2 = n + (n & 1);
+    constexpr int ngroups = NT / G;
+    const int gl = threadIdx.x % G, gid = threadIdx.x / G;
+    const int n2 = n + (n & 1), npairs = n2 / 2;
     const double tol = (double)(rows > 1 ? rows : 1) * 2.0 * kU;
     int sweep;
     for (sweep = 1; sweep <= max_sweeps; ++sweep) {
         if (threadIdx.x == 0) *sh_rot = 0;
         __syncthreads();
         for (int round = 0; round < n2 - 1; ++round) {
-            for (int t = wave; t < n2 / 2; t += nw) {
-                int p, q;
-                circle_pair(n2, round, t, p, q);
-                if (q >= n) continue;
-                double *mp = M + (size_t)p * ld, *mq = M + (size_t)q * ld;
-                double al = 0.0, be = 0.0, ga = 0.0;
-                for (int i = lane; i < rows; i += kWave) {
-                    const double x = mp[i], y = mq[i];
-                    al += x * x;
-                    be += y * y;
-                    ga += x * y;
+            for (int t0 = 0; t0 < npairs; t0 += ngroups) {
+                const int t = t0 + gid;
+                int p = 0, q = 0;
+                bool live = false;
+                if (t < npairs) {
+                    circle_pair(n2, round, t, p, q);
+                    live = q < n;
                 }
-                al = wave_sum(al);
-                be = wave_sum(be);
-                ga = wave_sum(ga);
-                if (fabs(ga) > tol * sqrt(al * be)) {
+                double *mp = M + (size_t)p * ld, *mq = M + (size_t)q * ld;
+                double x[E], y[E];
+                double al = 0.0, be = 0.0, ga = 0.0;
+                // loads at clamped addresses, masked afterwards (no branch per
+                // element)
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int i = gl + G * e;
+                    const int ic = i < rows ? i : 0;
+                    x[e] = mp[ic];
+                    y[e] = mq[ic];
+                }
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const bool in = live && gl + G * e < rows;
+                    x[e] = in ? x[e] : 0.0;
+                    y[e] = in ? y[e] : 0.0;
+                    al += x[e] * x[e];
+                    be += y[e] * y[e];
+                    ga += x[e] * y[e];
+                }
+                if (G == 16) {
+                    al = seg16_sum(al);
+                    be = seg16_sum(be);
+                    ga = seg16_sum(ga);
+                } else {
+                    al = wave_sum(al);
+                    be = wave_sum(be);
+                    ga = wave_sum(ga);
+                }
+                const bool doit = live && jacobi_needed(al, be, ga, tol);
+                if (doit) {
                     double cs, sn;
                     jacobi_rotation(al, be, ga, cs, sn);
-                    for (int i = lane; i < rows; i += kWave) {
-                        const double x = mp[i], y = mq[i];
-                        mp[i] = cs * x - sn * y;
-                        mq[i] = sn * x + cs * y;
+#pragma unroll
+                    for (int e = 0; e < E; ++e) {
+                        const int i = gl + G * e;
+                        if (i < rows) {
+                            mp[i] = cs * x[e] - sn * y[e];
+                            mq[i] = sn * x[e] + cs * y[e];
+                        }
                     }
-                    if (lane == 0) *sh_rot = 1;
+                    if (gl == 0) *sh_rot = 1;
                 }
             }
             __syncthreads();
@@ -412,22 +455,19 @@ __device__ int jacobi_block(double *M, int rows, int ld, int n, int max_sweeps, 
     return sweep;
 }
 
+// The body of k_small_svd with the Jacobi storage M either in LDS or in
+// global memory (inlined once for each, so LDS accesses compile to LDS
+// instructions); smem is the dynamic LDS block.
 template <typename T, int NT>
-__global__ void __launch_bounds__(NT) k_small_svd(int l, const double *Gin, double tau,
-                                                  const double *w, const T *Q, int64_t ldq, int mh,
-                                                  T *QM, int64_t ldqm, T *Qout, int64_t ldqo,
-                                                  SmallSvdOut out, double *work, int fuse_q)
+__device__ __forceinline__ void small_svd_body(double *M, double *smem, int l, const double *Gin,
+                                               double tau, const double *w, const T *Q,
+                                               int64_t ldq, int mh, T *QM, int64_t ldqm, T *Qout,
+                                               int64_t ldqo, const SmallSvdOut &out, int fuse_q,
+                                               int &sh_rot, int &rank, int *order, double *sig,
+                                               double *coef, double *wc)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    constexpr int kLdsMax = 128;
-    double *M = (l <= kLdsMax) ? reinterpret_cast<double *>(smem_raw) : work;
-    __shared__ int sh_rot;
-    __shared__ int order[1024];
-    __shared__ double sig[1024];
-    __shared__ double coef[1024];
     const int tid = threadIdx.x;
-    const int lane = tid % kWave, wave = tid / kWave;
-    constexpr int nw = NT / kWave;
+    const int wave = tid / kWave;
 
     // Row-major in-place semidefinite Cholesky: M[j*l + k] = R(j, k), k >= j.
     // Read column-major, column j of M is row j of R, i.e. M = R^T.
@@ -445,66 +485,73 @@ __global__ void __launch_bounds__(NT) k_small_svd(int l, const double *Gin, doub
         }
         __syncthreads();
     } else {
-    double maxdiag = 0.0;
-    for (int j = 0; j < l; ++j) maxdiag = fmax(maxdiag, M[j * l + j]);
-    const double ptol = 4.0 * l * kU * maxdiag;
-    for (int j = 0; j < l; ++j) {
-        double d = M[j * l + j];
-        for (int t = 0; t < j; ++t) d -= M[t * l + j] * M[t * l + j];
-        const double piv = d > ptol ? sqrt(d) : 0.0;
-        __syncthreads();   // every thread has read row j before it changes
-        if (tid == 0) M[j * l + j] = piv;
-        for (int k = j + 1 + tid; k < l; k += NT) {
-            double v = 0.0;
-            if (piv > 0.0) {
-                v = M[j * l + k];
-                for (int t = 0; t < j; ++t) v -= M[t * l + j] * M[t * l + k];
-                v /= piv;
+        // semidefinite Cholesky: pivots at or below ptol give a zero row
+        double maxdiag = 0.0;
+        for (int j = 0; j < l; ++j) maxdiag = fmax(maxdiag, M[j * l + j]);
+        const double ptol = 4.0 * l * kU * maxdiag;
+        if (l <= 128) {
+            // sig and coef serve as the step buffers here
+            chol_blk4<NT>(M, l, ptol, 0.0, coef, sig, nullptr);
+        } else {
+            // right-looking in place: row j of R is scaled, then the trailing
+            // upper triangle takes its rank-one update
+            for (int j = 0; j < l; ++j) {
+                const double d = M[j * l + j];
+                const double piv = d > ptol ? sqrt(d) : 0.0;
+                const double inv = piv > 0.0 ? 1.0 / piv : 0.0;
+                for (int k = j + 1 + tid; k < l; k += NT) M[j * l + k] = piv > 0.0 ? M[j * l + k] * inv : 0.0;
+                __syncthreads();
+                if (tid == 0) M[j * l + j] = piv;
+                const int m = l - j - 1;
+                for (int idx = tid; idx < m * m; idx += NT) {
+                    const int a = idx / m, b = idx - a * m;
+                    if (b >= a) M[(j + 1 + a) * l + (j + 1 + b)] -= M[j * l + j + 1 + a] * M[j * l + j + 1 + b];
+                }
+                __syncthreads();
             }
-            M[j * l + k] = v;
+        }
+        for (int idx = tid; idx < l * l; idx += NT) {
+            const int j = idx / l, k = idx % l;
+            if (k < j) M[idx] = 0.0;
         }
         __syncthreads();
-    }
-    for (int idx = tid; idx < l * l; idx += NT) {
-        const int j = idx / l, k = idx % l;
-        if (k < j) M[idx] = 0.0;
-    }
-    __syncthreads();
-
-    if (NT == kWave && l <= 16) sweeps = jacobi_wave16(M, l, 60);
-    else sweeps = jacobi_block<NT>(M, l, l, l, 60, &sh_rot);
-    __syncthreads();
+        if (l <= 128) sweeps = jacobi_groups<NT, 16, 8>(M, l, l, l, 60, &sh_rot);
+        else if (l <= 256) sweeps = jacobi_groups<NT, 16, 16>(M, l, l, l, 60, &sh_rot);
+        else sweeps = jacobi_groups<NT, 64, 16>(M, l, l, l, 60, &sh_rot);
+        __syncthreads();
     }
 
-    for (int j = wave; j < l; j += nw) {
+    // singular values: column norms of the converged M, one 16-lane group
+    // per column
+    for (int j = tid / 16; j < l; j += NT / 16) {
         const double *mj = M + (size_t)j * l;
         double s = 0.0;
-        for (int i = lane; i < l; i += kWave) s += mj[i] * mj[i];
-        s = wave_sum(s);
-        if (lane == 0) sig[j] = sqrt(s);
+        for (int i = tid % 16; i < l; i += 16) s += mj[i] * mj[i];
+        s = seg16_sum(s);
+        if (tid % 16 == 0) sig[j] = sqrt(s);
+    }
+    if (tid == 0) rank = 0;
+    __syncthreads();
+    // descending order by counting (ties by column index)
+    for (int a = tid; a < l; a += NT) {
+        const double sa = sig[a];
+        int pos = 0;
+        for (int b = 0; b < l; ++b) {
+            const double sb = sig[b];
+            pos += (sb > sa || (sb == sa && b < a)) ? 1 : 0;
+        }
+        order[pos] = a;
     }
     __syncthreads();
-    __shared__ int rank;
-    if (tid == 0) {
-        for (int j = 0; j < l; ++j) order[j] = j;
-        for (int a = 0; a < l; ++a) {
-            int best = a;
-            for (int b = a + 1; b < l; ++b)
-                if (sig[order[b]] > sig[order[best]]) best = b;
-            const int tmp = order[a];
-            order[a] = order[best];
-            order[best] = tmp;
-        }
-        int r = 0;
-        for (int a = 0; a < l; ++a) {
-            const double sa = sig[order[a]];
-            const double th = w ? w[a] : tau;
-            const double f = sa - th;
-            coef[a] = (f > 0.0 && sa > 0.0) ? f / sa : 0.0;
-            if (f > 0.0) ++r;
-        }
-        rank = r;
+    int rloc = 0;
+    for (int a = tid; a < l; a += NT) {
+        const double sa = sig[order[a]];
+        const double th = w ? w[a] : tau;
+        const double f = sa - th;
+        coef[a] = (f > 0.0 && sa > 0.0) ? f / sa : 0.0;
+        if (f > 0.0) ++rloc;
     }
+    if (rloc) atomicAdd(&rank, rloc);
     __syncthreads();
     for (int idx = tid; idx < l * l; idx += NT) {
         const int a = idx / l, i = idx % l;
@@ -512,14 +559,41 @@ __global__ void __launch_bounds__(NT) k_small_svd(int l, const double *Gin, doub
         out.U[i + (size_t)a * l] = sa > 0.0 ? M[(size_t)order[a] * l + i] / sa : 0.0;
     }
     for (int a = tid; a < l; a += NT) out.sigma[a] = sig[order[a]];
-    __syncthreads();
-    // Mm = sum_a coef_a u_a u_a^T
-    for (int idx = tid; idx < l * l; idx += NT) {
-        const int i = idx % l, j = idx / l;
-        double v = 0.0;
-        for (int a = 0; a < l; ++a)
-            if (coef[a] != 0.0) v += coef[a] * out.U[i + (size_t)a * l] * out.U[j + (size_t)a * l];
-        out.Mm[i + (size_t)j * l] = v;
+    // Mm = sum_a coef_a u_a u_a^T = sum_c wc_c m_c m_c^T over the unsorted
+    // columns m_c of M, wc = coef(position of c) / sigma_c^2; 4 x 4 output
+    // blocks per thread
+    {
+        for (int p = tid; p < l; p += NT) {
+            const int c = order[p];
+            const double sc = sig[c];
+            wc[c] = sc > 0.0 ? coef[p] / (sc * sc) : 0.0;
+        }
+        __syncthreads();
+        const int nb = (l + 3) / 4;
+        for (int blk = tid; blk < nb * nb; blk += NT) {
+            const int bi = 4 * (blk % nb), bj = 4 * (blk / nb);
+            double acc[4][4] = {};
+            for (int c = 0; c < l; ++c) {
+                const double wcc = wc[c];
+                if (wcc == 0.0) continue;
+                const double *mc = M + (size_t)c * l;
+                double xi[4], xj[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    xi[e] = bi + e < l ? mc[bi + e] : 0.0;
+                    xj[e] = bj + e < l ? wcc * mc[bj + e] : 0.0;
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+#pragma unroll
+                    for (int f = 0; f < 4; ++f) acc[e][f] += xi[e] * xj[f];
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int f = 0; f < 4; ++f)
+                    if (bi + e < l && bj + f < l) out.Mm[(bi + e) + (size_t)(bj + f) * l] = acc[e][f];
+        }
     }
     if (tid == 0) {
         out.status[0] = rank;
@@ -530,7 +604,7 @@ __global__ void __launch_bounds__(NT) k_small_svd(int l, const double *Gin, doub
     if (fuse_q && Q) {
         // QM = Q Mm and Qout = Q U(:, 1:r): one row of Q per thread in
         // registers, Mm and U broadcast from LDS (the Jacobi storage M is free).
-        double *sU = reinterpret_cast<double *>(smem_raw);
+        double *sU = smem;
         double *sMm = sU + (size_t)l * l;
         const int r = rank;
         for (int idx = tid; idx < l * l; idx += NT) {
@@ -574,6 +648,26 @@ __global__ void __launch_bounds__(NT) k_small_svd(int l, const double *Gin, doub
     }
 }
 
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT) k_small_svd(int l, const double *Gin, double tau,
+                                                  const double *w, const T *Q, int64_t ldq, int mh,
+                                                  T *QM, int64_t ldqm, T *Qout, int64_t ldqo,
+                                                  SmallSvdOut out, double *work, int fuse_q)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int sh_rot, rank;
+    __shared__ int order[1024];
+    __shared__ __align__(16) double coef[1024];
+    __shared__ double sig[1024], wc[1024];
+    double *smem = reinterpret_cast<double *>(smem_raw);
+    if (l <= 128)
+        small_svd_body<T, NT>(smem, smem, l, Gin, tau, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, fuse_q,
+                              sh_rot, rank, order, sig, coef, wc);
+    else
+        small_svd_body<T, NT>(work, smem, l, Gin, tau, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, fuse_q,
+                              sh_rot, rank, order, sig, coef, wc);
+}
+
 template <typename T>
 hipError_t launch_small_svd(int l, const double *G, double tau, const double *w, const T *Q,
                             int64_t ldq, int mh, T *QM, int64_t ldqm, T *Qout, int64_t ldqo,
@@ -582,7 +676,7 @@ hipError_t launch_small_svd(int l, const double *G, double tau, const double *w,
     if (l < 1 || l > 1024) return hipErrorInvalidValue;
     size_t lds = l <= 128 ? (size_t)l * l * sizeof(double) : 0;
     if (fuse_q && Q) lds = std::max(lds, 2 * (size_t)l * l * sizeof(double));
-    if (l <= 64)
+    if (l <= 32)
         hipLaunchKernelGGL((k_small_svd<T, 256>), dim3(1), dim3(256), lds, s, l, G, tau, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, work, fuse_q);
     else
         hipLaunchKernelGGL((k_small_svd<T, 1024>), dim3(1), dim3(1024), lds, s, l, G, tau, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, work, fuse_q);
