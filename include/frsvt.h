@@ -155,17 +155,17 @@ FRSVT_API int svt(frsvt_handle handle, frsvt_precision prec, int64_t m, int64_t 
  *   A, lda, tau  as for svt (tau >= 0; tau = 0 returns the projection P_Q A).
  *   k, p         target rank and oversampling (Table 1); l = k + p > 0.
  *   q            number of power iterations (eta in the paper), q >= 0.
- *   Q_prev       [in, optional] range propagation (Alg. 1 lines 8-11):
+ *   Q_prev       [in, optional] range propagation (Alg. 1, Sec. 2.1):
  *                mhat x r_prev orthonormal columns, leading dimension
  *                ldq_prev >= mhat.  When given, only p new Gaussian samples
  *                are drawn and l = r_prev + p; k is ignored.  NULL (or
- *                r_prev = 0) selects the fresh sketch of lines 4-6.
+ *                r_prev = 0) selects the fresh sketch.
  *   seed, counter  key and call counter of the Philox4x32-10 stream from
  *                which Omega(k, 2j+e) is drawn (e-th Box-Muller output of
  *                counter {k, j, counter lo, counter hi}); the same
  *                (seed, counter) always gives the same Omega.
  *   X            [out] m x n, ldx >= m; must not alias A or Q_prev.
- *   Q_out        [out, optional] Q~ = (Q V)_{:,1:r} of line 21, mhat x r,
+ *   Q_out        [out, optional] Q~ = (Q V)_{:,1:r} of Alg. 1's output, mhat x r,
  *                leading dimension ldq_out >= mhat, capacity l columns; may
  *                alias Q_prev (it is written after Q_prev is consumed).
  *   r_out        [out, HOST, optional] r = #{sigma_i > tau}; non-NULL makes
@@ -180,11 +180,11 @@ FRSVT_API int frsvt(frsvt_handle handle, frsvt_precision prec, int64_t m, int64_
 /* ------------------------------------------------------------ adjoint */
 
 /*
- * frsvt_fwd: the fresh-sketch FRSVT of Alg. 1 (lines 4-6, 13-21; no range
+ * frsvt_fwd: the fresh-sketch FRSVT of Alg. 1 (no range
  * propagation) that also saves what its adjoint needs, without waiting:
  *   A, lda, tau, k, p, q, seed, counter, X, ldx  as for frsvt (l = min(k+p, mhat),
  *                l <= 64).
- *   Q        [out] the basis of line 16 (the Q of B = Q^T Ahat), mhat x l,
+ *   Q        [out] the basis of the projection step (the Q of B = Q^T Ahat), mhat x l,
  *            leading dimension ldq >= mhat.
  *   factors  [out] DEVICE, l + l*l doubles: the singular values of B
  *            (descending), then its left singular vectors U_B (l x l,

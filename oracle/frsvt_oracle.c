@@ -62,7 +62,7 @@ double orc_uniform53(uint32_t a, uint32_t b)
     return (hi * 67108864.0 + lo + 0.5) * (1.0 / 9007199254740992.0);
 }
 
-/* Omega of Alg. 1 (lines 4 and 8): a dense standard Gaussian matrix, Sec. 2.4
+/* Omega of Alg. 1 (both sampling steps): a dense standard Gaussian matrix, Sec. 2.4
  * ("dense Gaussian random matrices drawn from standard normal distribution
  * in entry-wise").  Box-Muller turns each Philox output into two normals.  */
 void orc_gaussian_matrix(uint64_t seed, uint64_t counter, int64_t rows, int64_t cols,
@@ -219,7 +219,7 @@ int orc_qr(int64_t m, int64_t n, const double *A, int64_t lda, double *Q, int64_
 
 /* QR with column pivoting (Businger & Golub): at step j the remaining column
  * of largest norm is moved to position j.  Column norms are recomputed from
- * scratch at each step (slow and plain).  This is the QR_CP of Alg. 1 line 6
+ * scratch at each step (slow and plain).  This is the QR_CP of Alg. 1's fresh sketch
  * and Sec. 2.1, which also yields the real sampling rate s = min(l, r). */
 int64_t orc_qrcp_basis(int64_t m, int64_t n, const double *A, int64_t lda, double *Q,
                        int64_t ldq)
@@ -492,7 +492,7 @@ int orc_wsvt_rule(int64_t m, int64_t n, const double *A, int64_t lda, double c,
 /* FRSVT, Alg. 1                                                            */
 /* ------------------------------------------------------------------------ */
 
-/* PartialOrthogonalization of Alg. 1 line 10 (Sec. 2.1, "Range Propagation"):
+/* PartialOrthogonalization of Alg. 1 (Sec. 2.1, "Range Propagation"):
  * modified Gram-Schmidt of each new sample y_j against the propagated basis
  * and the new vectors accepted before it, the projection pass done twice,
  * then normalisation.  Q holds `have` orthonormal columns on entry; the
@@ -545,7 +545,7 @@ int orc_frsvt(int64_t m, int64_t n, const double *A, int64_t lda, double tau, in
     if (transposed) mat_transpose(m, n, A, lda, Ah, mh);
     else mat_copy(m, n, A, lda, Ah, mh);
 
-    /* Lines 3-12: the initial basis Q (mhat x s). */
+    /* Alg. 1, the initial basis Q (mhat x s). */
     int64_t lmax = (Qt ? r_prev : 0) + nomega;
     if (lmax > mh) lmax = mh;
     double *Q = dalloc(mh * lmax);
@@ -553,8 +553,8 @@ int orc_frsvt(int64_t m, int64_t n, const double *A, int64_t lda, double tau, in
     if (!Qt || r_prev == 0) {
         int64_t l = nomega < mh ? nomega : mh;
         double *Y = dalloc(mh * l);
-        mat_mul(mh, l, nh, Ah, mh, Om, ldom, Y, mh);  /* line 5: Y = A Omega */
-        s = orc_qrcp_basis(mh, l, Y, mh, Q, mh);      /* line 6: Q = QR_CP(Y) */
+        mat_mul(mh, l, nh, Ah, mh, Om, ldom, Y, mh);  /* Y = A Omega */
+        s = orc_qrcp_basis(mh, l, Y, mh, Q, mh);      /* Q = QR_CP(Y) */
         free(Y);
         if (s == 0) { /* A Omega == 0: keep one arbitrary direction */
             int miss = 1;
@@ -566,14 +566,14 @@ int orc_frsvt(int64_t m, int64_t n, const double *A, int64_t lda, double tau, in
         mat_copy(mh, r_prev, Qt, ldqt, Q, mh);
         if (p > 0) {
             double *Y = dalloc(mh * p);
-            mat_mul(mh, p, nh, Ah, mh, Om, ldom, Y, mh);      /* line 9 */
-            partial_orthogonalisation(mh, Q, mh, r_prev, Y, mh, p); /* lines 10-11 */
+            mat_mul(mh, p, nh, Ah, mh, Om, ldom, Y, mh);      /* Y = A Omega_p */
+            partial_orthogonalisation(mh, Q, mh, r_prev, Y, mh, p); /* Q = [Q~, Q_Y] */
             free(Y);
         }
         s = lmax;
     }
 
-    /* Lines 13-15: Q = QR(A A^T Q), q times. */
+    /* Power iterations: Q = QR(A A^T Q), q times. */
     double *Z = dalloc(nh * s), *Y = dalloc(mh * s), *Rtmp = dalloc(s * s);
     for (int it = 0; it < q; ++it) {
         mat_mul_tn(nh, s, mh, Ah, mh, Q, mh, Z, nh); /* Z = A^T Q */
@@ -581,19 +581,19 @@ int orc_frsvt(int64_t m, int64_t n, const double *A, int64_t lda, double tau, in
         orc_qr(mh, s, Y, mh, Q, mh, Rtmp, s);
     }
 
-    /* Line 16: [H, C] = QR(A^T Q), Bt = A^T Q is nhat x s. */
+    /* [H, C] = QR(A^T Q), Bt = A^T Q is nhat x s. */
     double *Bt = Z;
     mat_mul_tn(nh, s, mh, Ah, mh, Q, mh, Bt, nh);
     double *H = dalloc(nh * s), *C = dalloc(s * s);
     orc_qr(nh, s, Bt, nh, H, nh, C, s);
 
-    /* Lines 17-18 compute C = (W V) D V^T, an SVD of the core matrix C.  The
+    /* The polar and eigen steps compute C = (W V) D V^T, an SVD of the core matrix C.  The
      * oracle obtains the same factorisation directly with the Jacobi SVD:
      * C = UC diag(D) VC^T, so V = VC and W V = UC. */
     double *UC = dalloc(s * s), *VC = dalloc(s * s), *D = dalloc(s);
     int sweeps = orc_svd(s, s, C, s, UC, s, D, VC, s);
 
-    /* Line 19 / Eq. (6): S_tau(A) ~ (Q V) S_tau(D) (H W V)^T, keeping the r
+    /* Reconstruction, Eq. (6): S_tau(A) ~ (Q V) S_tau(D) (H W V)^T, keeping the r
      * singular values above tau (Sec. 2.3 defines r this way). */
     int64_t r = 0;
     double *shr = dalloc(s);
@@ -608,7 +608,7 @@ int orc_frsvt(int64_t m, int64_t n, const double *A, int64_t lda, double tau, in
     if (transposed) mat_transpose(mh, nh, Xh, mh, X, ldx);
     else mat_copy(mh, nh, Xh, mh, X, ldx);
 
-    /* Line 21: the propagated basis Q~ = Q V, its first r columns (Sec. 2.3). */
+    /* Output: the propagated basis Q~ = Q V, its first r columns (Sec. 2.3). */
     if (Qout) mat_copy(mh, r, QV, mh, Qout, ldqo);
     if (r_out) *r_out = r;
     if (sigma) for (int64_t i = 0; i < s; ++i) sigma[i] = D[i];

@@ -54,6 +54,7 @@ namespace {
 
 constexpr double kU = 1.1102230246251565e-16;
 constexpr size_t kStatusInts = 1024;
+constexpr int kGateSlot = 12;  // status word: null pivots of the large path's first null check
 constexpr size_t kScalarDoubles = 8192;
 
 int fail(frsvt_context *h, hipError_t e, const char *what)
@@ -199,6 +200,7 @@ struct Core {
     const T *A;
     int64_t lda;
     const uint16_t *A16;  // bfloat16 copy of A (precision form) or nullptr
+    const uint16_t *A16T; // bfloat16 copy of A^T (precision form) or nullptr
     Orient o;
     double tau;
     const double *w;     // device weights (WSVT) or nullptr
@@ -286,6 +288,18 @@ int mm(frsvt_context *h, int64_t M, int64_t N, int64_t K, const T *A, int64_t sa
     return FRSVT_OK;
 }
 
+// Tall-skinny product in storage precision (see launch_ts_gemm_*).
+template <typename T>
+hipError_t ts_gemm(int64_t M, int64_t N, int64_t K, const T *A, int64_t sam, int64_t sak, const T *B,
+                   int64_t ldb, T *C, int64_t scm, int64_t scn, T *part, int64_t cap, frsvt_context *h)
+{
+    if (std::is_same<T, double>::value)
+        return launch_ts_gemm_f64(M, N, K, (const double *)A, sam, sak, (const double *)B, ldb, (double *)C, scm,
+                                  scn, (double *)part, cap, h->num_cu, h->stream);
+    return launch_ts_gemm_f32(M, N, K, (const float *)A, sam, sak, (const float *)B, ldb, (float *)C, scm, scn,
+                              (float *)part, cap, h->num_cu, h->stream);
+}
+
 // Ahat(mh x nh) times a tall matrix V (nh x c, ld ldv): Y (mh x c, ld mh).
 // In the precision form (c.A16 set) the product runs on bfloat16 copies of
 // Ahat and V with float accumulation; V16 is scratch for the copy of V.
@@ -295,6 +309,8 @@ int ahat_times(frsvt_context *h, const Core<T> &c, const T *V, int64_t ldv, int 
 {
     const Orient &o = c.o;
     const int sk = gemm_splitk(o.mh, cols, o.nh, h->num_cu);
+    // split-K partials: the workspace holds 128 mh cmax values
+    const int64_t cap = (int64_t)128 * o.mh * cols;
     if (c.A16) {
         const uint16_t *v16 = (const uint16_t *)V;
         if (!v_is_bf16) {
@@ -302,9 +318,22 @@ int ahat_times(frsvt_context *h, const Core<T> &c, const T *V, int64_t ldv, int 
             v16 = V16;
             ldv = o.nh;
         }
-        CKT(FRSVT_K_GEMM_BF16, launch_gemm_bf16(o.mh, cols, o.nh, c.A16, o.si16, o.sk16, v16, 1, ldv,
-                                           (float *)Y, 1, o.mh, sk, (float *)part, h->stream));
+        // Ahat(i, j) with j contiguous: A^T's copy, or A's when Ahat = A^T
+        const uint16_t *Ak = o.trans ? c.A16 : c.A16T;
+        hipError_t e = launch_ts_gemm_bf16(o.mh, cols, o.nh, Ak, o.nh, 1, v16, ldv, (float *)Y, 1, o.mh,
+                                           (float *)part, cap, h->num_cu, h->stream);
+        if (e == hipErrorNotSupported)
+            e = launch_gemm_bf16(o.mh, cols, o.nh, c.A16, o.si16, o.sk16, v16, 1, ldv, (float *)Y, 1, o.mh,
+                                 sk, (float *)part, h->stream);
+        CKT(FRSVT_K_GEMM_BF16, e);
         return FRSVT_OK;
+    }
+    if (cols <= 128) {
+        hipError_t e = ts_gemm<T>(o.mh, cols, o.nh, c.A, o.si, o.sk, V, ldv, Y, 1, o.mh, part, cap, h);
+        if (e != hipErrorNotSupported) {
+            CKT(FRSVT_K_GEMM, e);
+            return FRSVT_OK;
+        }
     }
     return mm<T>(h, o.mh, cols, o.nh, c.A, o.si, o.sk, V, 1, ldv, Y, 1, o.mh, sk, part);
 }
@@ -316,21 +345,36 @@ int ahat_t_times(frsvt_context *h, const Core<T> &c, const T *Qm, int64_t ldq, i
                  T *part, bool use16 = false, uint16_t *Q16 = nullptr)
 {
     const Orient &o = c.o;
+    const int64_t cap = (int64_t)128 * o.mh * cols;
     if (use16 && c.A16) {
         CKT(FRSVT_K_OTHER, launch_to_bf16(o.mh, cols, (const float *)Qm, ldq, Q16, o.mh, h->stream));
-        CKT(FRSVT_K_GEMM_BF16, launch_gemm_bf16(o.nh, cols, o.mh, c.A16, o.sk16, o.si16, Q16, 1, o.mh,
-                                           (float *)Z, 1, o.nh, 1, (float *)part, h->stream));
+        // Ahat(i, j) with i contiguous: A's copy, or A^T's when Ahat = A^T
+        const uint16_t *Ak = o.trans ? c.A16T : c.A16;
+        hipError_t e = launch_ts_gemm_bf16(o.nh, cols, o.mh, Ak, o.mh, 1, Q16, o.mh, (float *)Z, 1, o.nh,
+                                           (float *)part, cap, h->num_cu, h->stream);
+        if (e == hipErrorNotSupported)
+            e = launch_gemm_bf16(o.nh, cols, o.mh, c.A16, o.sk16, o.si16, Q16, 1, o.mh, (float *)Z, 1, o.nh,
+                                 1, (float *)part, h->stream);
+        CKT(FRSVT_K_GEMM_BF16, e);
         return FRSVT_OK;
+    }
+    if (cols <= 128) {
+        hipError_t e = ts_gemm<T>(o.nh, cols, o.mh, c.A, o.sk, o.si, Qm, ldq, Z, 1, o.nh, part, cap, h);
+        if (e != hipErrorNotSupported) {
+            CKT(FRSVT_K_GEMM, e);
+            return FRSVT_OK;
+        }
     }
     return mm<T>(h, o.nh, cols, o.mh, c.A, o.sk, o.si, Qm, 1, ldq, Z, 1, o.nh, 1, part);
 }
 
 // Gram G = Y^T Y (l x l, double) of a tall rows x l matrix.
 template <typename T>
-int gram(frsvt_context *h, int64_t rows, int l, const T *Y, int64_t ldy, double *G, double *part)
+int gram(frsvt_context *h, int64_t rows, int l, const T *Y, int64_t ldy, double *G, double *part,
+         const int *gate = nullptr)
 {
     if (l <= 128) {
-        CKT(FRSVT_K_GEMM, launch_gram_tall<T>(rows, l, Y, ldy, part, G, h->stream));
+        CKT(FRSVT_K_GEMM, launch_gram_tall<T>(rows, l, Y, ldy, part, G, h->stream, gate));
         return FRSVT_OK;
     }
     const int sk = gemm_splitk(l, l, rows, h->num_cu);
@@ -360,13 +404,20 @@ int big_orth(frsvt_context *h, int64_t rows, int l, T *Y, int64_t ldy, CoreBuffe
     if ((rc = gram(h, rows, l, Y, ldy, b.G, b.gpart_d))) return rc;
     CKT(FRSVT_K_ORTH, launch_chol(l, b.G, shift, 0.0, b.R, nullptr, flags, h->stream));
     CKT(FRSVT_K_ORTH, launch_trsm<T>(rows, l, Y, ldy, b.R, h->stream));
+    // The first null check records its count in *gate; when it found no
+    // null column nothing was refilled, so the Gram and factor of the second
+    // check and of the next pass would repeat it: those launches return at
+    // once (no host round trip) and the pass uses the first check's R.
+    int *gate = h->dstatus + kGateSlot;
     for (int attempt = 0; attempt < 2; ++attempt) {
-        if ((rc = gram(h, rows, l, Y, ldy, b.G, b.gpart_d))) return rc;
-        CKT(FRSVT_K_ORTH, launch_chol(l, b.G, 0.0, 16.0 * l * kU, b.R, b.nullc, flags, h->stream));
+        const int *g = attempt ? gate : nullptr;
+        if ((rc = gram(h, rows, l, Y, ldy, b.G, b.gpart_d, g))) return rc;
+        CKT(FRSVT_K_ORTH, launch_chol(l, b.G, 0.0, 16.0 * l * kU, b.R, b.nullc, flags, h->stream, g,
+                                      attempt ? nullptr : gate));
         CKT(FRSVT_K_ORTH, launch_refill<T>(rows, l, Y, ldy, b.nullc, seed, counter, attempt, h->stream));
     }
-    if ((rc = gram(h, rows, l, Y, ldy, b.G, b.gpart_d))) return rc;
-    CKT(FRSVT_K_ORTH, launch_chol(l, b.G, 0.0, 16.0 * l * kU, b.R, b.nullc, flags, h->stream));
+    if ((rc = gram(h, rows, l, Y, ldy, b.G, b.gpart_d, gate))) return rc;
+    CKT(FRSVT_K_ORTH, launch_chol(l, b.G, 0.0, 16.0 * l * kU, b.R, b.nullc, flags, h->stream, gate));
     CKT(FRSVT_K_ORTH, launch_trsm<T>(rows, l, Y, ldy, b.R, h->stream));
     if ((rc = gram(h, rows, l, Y, ldy, b.G, b.gpart_d))) return rc;
     CKT(FRSVT_K_ORTH, launch_chol(l, b.G, 0.0, 0.0, b.R, nullptr, flags, h->stream));
@@ -374,7 +425,7 @@ int big_orth(frsvt_context *h, int64_t rows, int l, T *Y, int64_t ldy, CoreBuffe
     return FRSVT_OK;
 }
 
-// Alg. 1 lines 4-5 / 8-9 on the one-workgroup path: Y = Ahat Omega into b.Y.
+// Alg. 1's sampling step (fresh or range-propagated) on the one-workgroup path: Y = Ahat Omega into b.Y.
 // It depends only on A, the Philox stream and the number of new samples.
 template <typename T>
 int sketch_stage(frsvt_context *h, const Core<T> &c, CoreBuffers<T> &b)
@@ -432,7 +483,7 @@ int run_core(frsvt_context *h, Core<T> &c, CoreBuffers<T> &b)
     la.seed = c.seed;
     la.counter = c.counter;
 
-    // Alg. 1 lines 3-12: sketch and initial basis
+    // Alg. 1, sketch and initial basis (fresh or range-propagated)
     if (small) {
         if (!c.sketch_ready && (rc = sketch_stage<T>(h, c, b))) return rc;
         CKT(FRSVT_K_ORTH, launch_small_orth<T>(mh, c.Qt, c.ldqt, c.rp, b.Y, mh, c.cnew, b.Q, mh, c.seed,
@@ -456,7 +507,7 @@ int run_core(frsvt_context *h, Core<T> &c, CoreBuffers<T> &b)
         if ((rc = big_orth<T>(h, mh, l, b.Q, mh, b, c.seed, c.counter, oflags))) return rc;
     }
 
-    // Alg. 1 lines 13-15: power iterations Q = QR(Ahat Ahat^T Q)
+    // Alg. 1, power iterations Q = QR(Ahat Ahat^T Q)
     for (int it = 0; it < c.q; ++it) {
         const uint64_t ctr2 = c.counter ^ (0x5bd1e995ull << 32) ^ (uint64_t)(it + 1) << 56;
         if (small) {
@@ -476,7 +527,7 @@ int run_core(frsvt_context *h, Core<T> &c, CoreBuffers<T> &b)
         }
     }
 
-    // Alg. 1 line 16: B^T = Ahat^T Q and its Gram B B^T
+    // Alg. 1, QR of A^T Q: B^T = Ahat^T Q and its Gram B B^T
     if (small || (!c.A16 && long_path_ok(mh, l))) {
         LongPlan p = long_plan(mh, o.nh, l, Prec<T>::bytes, kProject, h->num_cu);
         la.c = l;
@@ -492,7 +543,7 @@ int run_core(frsvt_context *h, Core<T> &c, CoreBuffers<T> &b)
         if ((rc = gram<T>(h, o.nh, l, b.Bt, o.nh, b.G, b.gpart_d))) return rc;
     }
 
-    // Alg. 1 lines 17-19: small SVD, thresholds, reconstruction factors
+    // Alg. 1, polar/eigen and reconstruction: small SVD, thresholds, factors
     SmallSvdOut so{b.sigma, b.U, b.Mm, c.status};
     const int fuse = small_svd_fuse_q_ok(mh, l) ? 1 : 0;
     CKT(FRSVT_K_SMALL_SVD, launch_small_svd<T>(l, b.G, c.tau, c.w, b.Q, mh, mh, b.QM, mh, c.Qout, c.ldqo, so, b.jwork,
@@ -636,16 +687,23 @@ int frsvt_impl(frsvt_context *h, int64_t m, int64_t n, const T *A, int64_t lda, 
     const int l = c.rp + c.cnew;
     CoreBuffers<T> b{};
     Carver dry(nullptr);
-    if (mixed) dry.take<uint16_t>((size_t)m * n);
+    if (mixed) {
+        dry.take<uint16_t>((size_t)m * n);
+        dry.take<uint16_t>((size_t)m * n);
+    }
     carve_core<T>(dry, o, l, c.cnew, h->num_cu, b, mixed);
     int rc = ensure_ws(h, dry.off);
     if (rc) return rc;
     Carver cv(h->ws);
-    c.A16 = nullptr;
+    c.A16 = c.A16T = nullptr;
     if (mixed) {
+        // both orientations, so that every bfloat16 product reads its
+        // operand along the reduction index
         uint16_t *A16 = cv.take<uint16_t>((size_t)m * n);
-        CKT(FRSVT_K_OTHER, launch_to_bf16(m, n, (const float *)A, lda, A16, m, h->stream));
+        uint16_t *A16T = cv.take<uint16_t>((size_t)m * n);
+        CKT(FRSVT_K_OTHER, launch_to_bf16_pair(m, n, (const float *)A, lda, A16, A16T, h->stream));
         c.A16 = A16;
+        c.A16T = A16T;
     }
     carve_core<T>(cv, o, l, c.cnew, h->num_cu, b, mixed);
     if ((rc = run_core<T>(h, c, b))) return rc;
@@ -669,8 +727,9 @@ int frsvt_impl(frsvt_context *h, int64_t m, int64_t n, const T *A, int64_t lda, 
 
 // ---------------------------------------------------------------------------
 // Adjoint of the fresh-sketch FRSVT map X = Q S_tau(Q^T Ahat) of Alg. 1
-// (lines 4-6 and 13-21) for a fixed Omega.  The power iterations are
-// recomputed from the seed, Q_q is the saved basis of line 16 and (sigma,
+// (fresh sketch, power iterations, projection, thresholding) for a fixed
+// Omega.  The power iterations are recomputed from the seed, Q_q is the
+// saved basis of the projection step and (sigma,
 // U_B) the saved small factors.  With the blocks
 //   Lf = [Q_q, Ybar_q, Q_{q-1}, ..., Ybar_1, Q_0, Ybar_0]   (mh x (2q+2) l)
 //   Rf = [Bbar^T, Z_q, Zbar_q, ..., Z_1, Zbar_1, Omega]     (nh x (2q+2) l)
@@ -813,7 +872,7 @@ int frsvt_vjp_impl(frsvt_context *h, int64_t m, int64_t n, const T *A, int64_t l
             return rc;
     }
 
-    // line 16 again: B^T = Ahat^T Q; Sbar^T = Xbar_hat^T Q; H = Sbar B^T
+    // the projection again: B^T = Ahat^T Q; Sbar^T = Xbar_hat^T Q; H = Sbar B^T
     T *Bt = b.BC, *Sbt = b.BC + (size_t)nh * l;
     if ((rc = ahat_t_times<T>(h, ca, Lb(0), mh, l, Bt, b.gpart_t))) return rc;
     if ((rc = ahat_t_times<T>(h, cx, Lb(0), mh, l, Sbt, b.gpart_t))) return rc;

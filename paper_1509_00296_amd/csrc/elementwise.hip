@@ -1,4 +1,4 @@
-// elementwise.hip -- rank-l shrink-and-reconstruct, the RPCA epilogue and elementwise helpers (Alg. 1 line 19 and the iALM updates).
+// elementwise.hip -- rank-l shrink-and-reconstruct, the RPCA epilogue and elementwise helpers (Alg. 1's thresholded reconstruction and the iALM updates).
 #include "device_common.h"
 #include "internal.h"
 

@@ -149,8 +149,9 @@ typedef __attribute__((__vector_size__(4 * sizeof(double)))) double gd_doublex4;
 // first holding row 2s and of the second row 2s + 1.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_gram_tall(int64_t rows, int l, const T *__restrict__ Y,
-                                                        int64_t ldy, int64_t rpw, double *part)
+                                                        int64_t ldy, int64_t rpw, double *part, const int *gate)
 {
+    if (gate && *gate == 0) return;  // the partials are still current
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     const int c = lane & 15, s = lane >> 4;
     const int nb = (l + 15) / 16;
@@ -201,19 +202,19 @@ __global__ void __launch_bounds__(kThreads) k_gram_tall(int64_t rows, int l, con
 
 template <typename T>
 hipError_t launch_gram_tall(int64_t rows, int l, const T *Y, int64_t ldy, double *part, double *G,
-                            hipStream_t s)
+                            hipStream_t s, const int *gate)
 {
     if (l < 1 || l > 128) return hipErrorInvalidValue;
     int64_t rpw = std::max<int64_t>(64, (rows + 63) / 64);
     rpw = (rpw + 7) / 8 * 8;
     const int nparts = (int)std::max<int64_t>(1, (rows + rpw - 1) / rpw);
-    hipLaunchKernelGGL((k_gram_tall<T>), dim3(nparts), dim3(kThreads), 0, s, rows, l, Y, ldy, rpw, part);
+    hipLaunchKernelGGL((k_gram_tall<T>), dim3(nparts), dim3(kThreads), 0, s, rows, l, Y, ldy, rpw, part, gate);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_reduce<double>(part, (int64_t)l * l, nparts, G, s);
 }
-template hipError_t launch_gram_tall<double>(int64_t, int, const double *, int64_t, double *, double *, hipStream_t);
-template hipError_t launch_gram_tall<float>(int64_t, int, const float *, int64_t, double *, double *, hipStream_t);
+template hipError_t launch_gram_tall<double>(int64_t, int, const double *, int64_t, double *, double *, hipStream_t, const int *);
+template hipError_t launch_gram_tall<float>(int64_t, int, const float *, int64_t, double *, double *, hipStream_t, const int *);
 
 // Cholesky of (G + shift I), shift = shift_factor trace(G), by one
 // workgroup with the upper triangle dealt to the threads' registers in
@@ -221,8 +222,9 @@ template hipError_t launch_gram_tall<float>(int64_t, int, const float *, int64_t
 // numerically null: R_jj = 1 and a zero row (null_cols[j] = 1).  R is
 // written whole (upper, row-major [j * l + k], zeros below the diagonal).
 constexpr int kCholThreads = 576;  // >= 528 blocks of 4 x 4 for l <= 128
-__global__ void __launch_bounds__(kCholThreads) k_chol(int l, const double *G, double shift_factor, double null_tol, double *R, int *null_cols, int *flags)
+__global__ void __launch_bounds__(kCholThreads) k_chol(int l, const double *G, double shift_factor, double null_tol, double *R, int *null_cols, int *flags, const int *gate, int *nn_out)
 {
+    if (gate && *gate == 0) return;  // the factor in R is still current
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double *M = reinterpret_cast<double *>(smem_raw);
     __shared__ double shift, tolabs;
@@ -249,13 +251,14 @@ __global__ void __launch_bounds__(kCholThreads) k_chol(int l, const double *G, d
         flags[1] = nn;
         if (null_tol <= 0.0 && nn > 0) flags[2] |= 1;
     }
+    if (tid == 0 && nn_out) *nn_out = nn;
 }
 
-hipError_t launch_chol(int l, const double *G, double shift_factor, double null_tol, double *R, int *null_cols, int *flags, hipStream_t s)
+hipError_t launch_chol(int l, const double *G, double shift_factor, double null_tol, double *R, int *null_cols, int *flags, hipStream_t s, const int *gate, int *nn_out)
 {
     const size_t lds = (size_t)l * l * sizeof(double);
     if (l > 128) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_chol, dim3(1), dim3(kCholThreads), lds, s, l, G, shift_factor, null_tol, R, null_cols, flags);
+    hipLaunchKernelGGL(k_chol, dim3(1), dim3(kCholThreads), lds, s, l, G, shift_factor, null_tol, R, null_cols, flags, gate, nn_out);
     return hipGetLastError();
 }
 

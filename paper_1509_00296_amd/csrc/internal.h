@@ -164,11 +164,16 @@ hipError_t launch_omega(int64_t rows, int cols, uint64_t seed, uint64_t counter,
 // G = Y^T Y (l x l, [a * l + b]) for a tall rows x l matrix, l <= 128:
 // partial Grams on the matrix cores into part (at most 64 l^2 doubles), then
 // their sum.
+// A non-null gate with *gate == 0 skips the partial products (they are
+// still current).
 template <typename T>
 hipError_t launch_gram_tall(int64_t rows, int l, const T *Y, int64_t ldy, double *part, double *G,
-                            hipStream_t s);
+                            hipStream_t s, const int *gate = nullptr);
+// gate: as for launch_gram_tall (R is still current); nn_out receives the
+// number of null pivots.
 hipError_t launch_chol(int l, const double *G, double shift_factor, double null_tol, double *R,
-                       int *null_cols, int *flags, hipStream_t s);
+                       int *null_cols, int *flags, hipStream_t s, const int *gate = nullptr,
+                       int *nn_out = nullptr);
 // Y (rows x l) <- Y R^{-1} in place (R upper, double), one lane per row.
 template <typename T>
 hipError_t launch_trsm(int64_t rows, int l, T *Y, int64_t ldy, const double *R, hipStream_t s);
@@ -199,6 +204,24 @@ hipError_t launch_gemm_f32_mfma(int64_t M, int64_t N, int64_t K, const float *A,
 hipError_t launch_gemm_f64_mfma(int64_t M, int64_t N, int64_t K, const double *A, int64_t sam,
                                 int64_t sak, const double *B, int64_t sbk, int64_t sbn, double *C,
                                 int64_t scm, int64_t scn, int splitk, double *part, hipStream_t s);
+// Tall-skinny products C (M x N) = A (M x K) B (K x N), N <= 128, B
+// k-contiguous (B(k, n) at B[k + n ldb]); A k-contiguous (sak = 1, rows
+// 16-byte aligned) or, for float and double, row-contiguous (sam = 1).
+// Split K into part (at most part_cap values), reduced into C in a fixed
+// order.  hipErrorNotSupported for other shapes (the caller falls back).
+hipError_t launch_ts_gemm_bf16(int64_t M, int64_t N, int64_t K, const uint16_t *A, int64_t sam, int64_t sak,
+                               const uint16_t *B, int64_t ldb, float *C, int64_t scm, int64_t scn,
+                               float *part, int64_t part_cap, int num_cu, hipStream_t s);
+hipError_t launch_ts_gemm_f32(int64_t M, int64_t N, int64_t K, const float *A, int64_t sam, int64_t sak,
+                              const float *B, int64_t ldb, float *C, int64_t scm, int64_t scn,
+                              float *part, int64_t part_cap, int num_cu, hipStream_t s);
+hipError_t launch_ts_gemm_f64(int64_t M, int64_t N, int64_t K, const double *A, int64_t sam, int64_t sak,
+                              const double *B, int64_t ldb, double *C, int64_t scm, int64_t scn,
+                              double *part, int64_t part_cap, int num_cu, hipStream_t s);
+// both bfloat16 copies of an m x n column-major float matrix: dst (m x n,
+// ld m) and its transpose dstT (n x m, ld n)
+hipError_t launch_to_bf16_pair(int64_t m, int64_t n, const float *src, int64_t lds, uint16_t *dst,
+                               uint16_t *dstT, hipStream_t s);
 // float -> bfloat16 (round to nearest even) of an m x n column-major matrix
 hipError_t launch_to_bf16(int64_t m, int64_t n, const float *src, int64_t lds, uint16_t *dst,
                           int64_t ldd, hipStream_t s);

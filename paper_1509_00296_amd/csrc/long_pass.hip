@@ -1,7 +1,8 @@
 // long_pass.hip -- passes over Ahat along its long dimension: the Gaussian
-// sketch Y = Ahat Omega (Alg. 1 lines 5 and 9), the fused power step
-// Y = Ahat (Ahat^T Q) (line 14) and the projection B^T = Ahat^T Q with the
-// Gram B B^T (line 16); plus the fixed-order split-K reductions.
+// sketch Y = Ahat Omega (Alg. 1's sampling steps), the fused power step
+// Y = Ahat (Ahat^T Q) (its power iteration) and the projection B^T = Ahat^T Q
+// with the Gram B B^T (its QR of A^T Q); plus the fixed-order split-K
+// reductions.
 #include "device_common.h"
 #include "internal.h"
 

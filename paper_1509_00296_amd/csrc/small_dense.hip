@@ -1,6 +1,8 @@
 // small_dense.hip -- one-workgroup dense kernels: CholeskyQR
-// re-orthonormalisation of the sampled basis (Alg. 1 lines 6, 10-11, 14) and
-// the small SVD of B with thresholds and reconstruction factors (lines 16-19).
+// re-orthonormalisation of the sampled basis (Alg. 1: the fresh sketch's QR,
+// range propagation's partial orthogonalisation, the power-iteration QR) and
+// the small SVD of B with thresholds and reconstruction factors (its
+// projection, polar/eigen and reconstruction steps).
 #include "block_dense.h"
 #include "device_common.h"
 #include "internal.h"
@@ -12,7 +14,7 @@ namespace frk {
 // ===========================================================================
 // Orthonormalisation of W = [Qt, Y] (mh x l, l = rp + c), all in LDS:
 //   1. CGS2: Y <- Y - Qt (Qt^T Y), twice (the partial orthogonalisation of
-//      range propagation, Alg. 1 line 10).
+//      range propagation's partial orthogonalisation in Alg. 1).
 //   2. Column equilibration (only the span matters).
 //   3. Fast path: CholeskyQR2.  The first Cholesky must see no null pivot
 //      and a smallest pivot ratio >= 1e-8; the second must have every pivot
@@ -256,7 +258,7 @@ template hipError_t launch_small_orth<double>(int, const double *, int64_t, int,
 template hipError_t launch_small_orth<float>(int, const float *, int64_t, int, const float *, int64_t, int, float *, int64_t, uint64_t, uint64_t, int *, hipStream_t);
 
 // ===========================================================================
-// Small SVD of B from G = B B^T (Alg. 1 lines 16-18 reformulated):
+// Small SVD of B from G = B B^T (Alg. 1's QR of A^T Q, polar and eigen steps reformulated):
 //   G = R^T R (semidefinite Cholesky), one-sided Jacobi on M = R^T: M V = W S.
 //   B = R^T H^T has left singular vectors U_B = W S^{-1} (the normalised
 //   columns of the converged M) and singular values S.

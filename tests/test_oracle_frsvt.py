@@ -105,7 +105,7 @@ def test_thm3_average_bound_q0(orc):
 @pytest.mark.parametrize("q", [0, 1, 2])
 def test_range_propagation_span_identity(orc, q):
     """With Q~ given, FRSVT equals S_tau of the projection of A onto
-    span((A A^T)^q [Q~, A Omega_p]) (Alg. 1 lines 8-15)."""
+    span((A A^T)^q [Q~, A Omega_p]) (Alg. 1 with range propagation and power iterations)."""
     rng = np.random.default_rng(6 + q)
     m, n = 30, 80                      # m <= n: Ahat = A
     A = _lowrank(rng, m, n, [30, 20, 12, 6, 3, 2, 1]) + 0.1 * rng.standard_normal((m, n))

@@ -1,4 +1,4 @@
-"""Pins for the oracle's random test matrix Omega (Alg. 1 lines 4 and 8)."""
+"""Pins for the oracle's random test matrix Omega (Alg. 1's sampling steps)."""
 import os
 
 import numpy as np
