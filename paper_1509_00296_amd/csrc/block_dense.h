@@ -73,17 +73,19 @@ __device__ __forceinline__ CholInfo block_chol(const double *G, int l, double sh
     return info;
 }
 
-// W <- W R^{-1} (R upper, row-major), each thread owns rows; for l <= 16 a
-// row is held in registers while it is solved.
+// W <- W R^{-1} (R upper, row-major), each thread owns rows; for l <= LM
+// (LM <= 16, a compile-time bound) a row is held in registers while it is
+// solved.
+template <int LM = 16>
 __device__ __forceinline__ void block_trsm(double *W, int mh, int mhp, int l, const double *R)
 {
-    if (l <= 16) {
+    if (l <= LM) {
         for (int i = threadIdx.x; i < mh; i += blockDim.x) {
-            double w[16];
+            double w[LM];
 #pragma unroll
-            for (int j = 0; j < 16; ++j) w[j] = j < l ? W[(size_t)j * mhp + i] : 0.0;
+            for (int j = 0; j < LM; ++j) w[j] = j < l ? W[(size_t)j * mhp + i] : 0.0;
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
+            for (int j = 0; j < LM; ++j) {
                 if (j < l) {
                     double v = w[j];
 #pragma unroll
@@ -92,7 +94,7 @@ __device__ __forceinline__ void block_trsm(double *W, int mh, int mhp, int l, co
                 }
             }
 #pragma unroll
-            for (int j = 0; j < 16; ++j)
+            for (int j = 0; j < LM; ++j)
                 if (j < l) W[(size_t)j * mhp + i] = w[j];
         }
     } else {
@@ -114,7 +116,7 @@ __device__ __forceinline__ void block_trsm(double *W, int mh, int mhp, int l, co
 typedef __attribute__((__vector_size__(4 * sizeof(double)))) double bd_doublex4;
 
 // G = W^T W (l <= 16, G row-major [a * l + b]) on the matrix cores: K = rows,
-// wavefront w takes the 4-row steps 4w, 4w + 16, ...; A and B operands are
+// wavefront w takes the 4-row steps 4w, 4w + 16, ... (four chains); A and B operands are
 // the same element W(i, a) with a = lane % 16, i = step + lane / 16.  The
 // four partial 16 x 16 blocks are added in a fixed order.  part: 4 * 256
 // doubles of LDS.  Ends with a barrier.
@@ -122,22 +124,25 @@ __device__ __forceinline__ void gram16_mfma(const double *W, int mh, int mhp, in
 {
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     const int a = lane & 15, ko = lane >> 4;
-    bd_doublex4 z0 = {0, 0, 0, 0}, z1 = {0, 0, 0, 0};
-    int i0 = 4 * wave;
-    for (; i0 + 16 < mh; i0 += 32) {
-        const int i = i0 + ko, i2 = i0 + 16 + ko;
-        const double x = (a < l) ? W[(size_t)a * mhp + i] : 0.0;
-        const double y = (a < l && i2 < mh) ? W[(size_t)a * mhp + i2] : 0.0;
-        z0 = __builtin_amdgcn_mfma_f64_16x16x4f64(x, x, z0, 0, 0, 0);
-        z1 = __builtin_amdgcn_mfma_f64_16x16x4f64(y, y, z1, 0, 0, 0);
-    }
-    if (i0 < mh) {
-        const int i = i0 + ko;
-        const double x = (a < l && i < mh) ? W[(size_t)a * mhp + i] : 0.0;
-        z0 = __builtin_amdgcn_mfma_f64_16x16x4f64(x, x, z0, 0, 0, 0);
+    bd_doublex4 z0 = {0, 0, 0, 0}, z1 = {0, 0, 0, 0}, z2 = {0, 0, 0, 0}, z3 = {0, 0, 0, 0};
+    // four independent accumulation chains over row steps 4 w + 16 t; all
+    // loads of an iteration are issued before its products
+    const double *wa = W + (size_t)(a < l ? a : 0) * mhp;
+    for (int i0 = 4 * wave; i0 < mh; i0 += 64) {
+        double x[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int i = i0 + 16 * t + ko;
+            x[t] = (a < l && i < mh) ? wa[i < mh ? i : 0] : 0.0;
+        }
+        z0 = __builtin_amdgcn_mfma_f64_16x16x4f64(x[0], x[0], z0, 0, 0, 0);
+        z1 = __builtin_amdgcn_mfma_f64_16x16x4f64(x[1], x[1], z1, 0, 0, 0);
+        z2 = __builtin_amdgcn_mfma_f64_16x16x4f64(x[2], x[2], z2, 0, 0, 0);
+        z3 = __builtin_amdgcn_mfma_f64_16x16x4f64(x[3], x[3], z3, 0, 0, 0);
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) part[wave * 256 + ((lane >> 4) + 4 * r) * 16 + a] = z0[r] + z1[r];
+    for (int r = 0; r < 4; ++r)
+        part[wave * 256 + ((lane >> 4) + 4 * r) * 16 + a] = (z0[r] + z1[r]) + (z2[r] + z3[r]);
     __syncthreads();
     for (int idx = threadIdx.x; idx < l * l; idx += blockDim.x) {
         const int x = idx / l, y = idx % l;
@@ -147,39 +152,43 @@ __device__ __forceinline__ void gram16_mfma(const double *W, int mh, int mhp, in
     __syncthreads();
 }
 
-// Cholesky of (G + shift I), l <= 16, by ONE wavefront: lane k holds column
+// Cholesky of (G + shift I), l <= LM <= 16 (LM a compile-time bound), by
+// ONE wavefront: lane k holds column
 // k of the trailing matrix in registers; each pivot and each row of R is
 // broadcast with readlane.  Writes R (upper, row-major [j * l + k], the
 // strict lower triangle set to zero) and null_flags; pivots <= null_tol are
 // numerically null: a zero row with R_jj = 1 (null_pivot_one) or 0.  G may
 // alias R (it is read into registers first).  No barrier inside: call from
 // one wavefront, synchronise afterwards.
+template <int LM = 16>
 __device__ __forceinline__ CholInfo wave_chol16(const double *G, int l, double shift, double null_tol,
                                        double *R, int *null_flags, bool null_pivot_one = true)
 {
     const int k = threadIdx.x % kWave;
-    double g[16];
+    double g[LM];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) g[i] = (i < l && k < l) ? G[i * l + k] + (i == k ? shift : 0.0) : 0.0;
+    for (int i = 0; i < LM; ++i) g[i] = (i < l && k < l) ? G[i * l + k] + (i == k ? shift : 0.0) : 0.0;
     double gkk = 0.0;
 #pragma unroll
-    for (int i = 0; i < 16; ++i)
+    for (int i = 0; i < LM; ++i)
         if (i == k) gkk = g[i];
     CholInfo info{0, 1.0};
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
+    for (int j = 0; j < LM; ++j) {
         if (j >= l) break;
         double gj = 0.0;   // this lane's element j of its column: G'(j, k)
 #pragma unroll
-        for (int i = 0; i < 16; ++i)
+        for (int i = 0; i < LM; ++i)
             if (i == j) gj = g[i];
         const double d = read_lane(gj, j);
         const double ojj = read_lane(gkk, j);
         const bool isnull = !(d > null_tol);
-        const double piv = isnull ? (null_pivot_one ? 1.0 : 0.0) : sqrt(d);
+        // pivot and its reciprocal from one reciprocal square root
+        const double rs = rsqrt(isnull ? 1.0 : d);
+        const double piv = isnull ? (null_pivot_one ? 1.0 : 0.0) : d * rs;
         if (isnull) ++info.nnull;
         else if (ojj > 0.0) info.min_ratio = fmin(info.min_ratio, d / ojj);
-        const double inv = isnull ? 0.0 : 1.0 / piv;
+        const double inv = isnull ? 0.0 : rs;
         double rjk = 0.0;
         if (k == j) rjk = piv;
         else if (k > j && k < l && !isnull) rjk = gj * inv;
@@ -188,7 +197,7 @@ __device__ __forceinline__ CholInfo wave_chol16(const double *G, int l, double s
         // rows i >= l take zero updates (lanes k >= l hold rjk = 0), so the
         // loop needs no runtime bound
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
+        for (int i = 0; i < LM; ++i) {
             if (i > j) {
                 const double rji = read_lane(rjk, i);
                 g[i] = (k > j) ? g[i] - rji * rjk : g[i];
@@ -244,8 +253,10 @@ __device__ __forceinline__ int chol_blk4(double *M, int l, double tol, double nu
     for (int j = 0; j < l; ++j) {
         const double d = sh_d[j];
         const bool isnull = !(d > tol);
-        const double piv = isnull ? null_piv : sqrt(d);
-        const double inv = isnull ? 0.0 : 1.0 / piv;
+        // pivot and its reciprocal from one reciprocal square root
+        const double rs = rsqrt(isnull ? 1.0 : d);
+        const double piv = isnull ? null_piv : d * rs;
+        const double inv = isnull ? 0.0 : rs;
         nnull += isnull ? 1 : 0;
         if (owner && bi == (j >> 2)) {
             const int rj = j & 3;

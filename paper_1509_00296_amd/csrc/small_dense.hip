@@ -33,7 +33,7 @@ bool small_orth_ok(int mh, int l)
     return l >= 1 && l <= 64 && (size_t)(mh | 1) * l * 16 + (size_t)l * l * 16 + 8192 <= 96 * 1024;
 }
 
-template <typename T, int NT>
+template <typename T, int NT, int LM>
 __global__ void __launch_bounds__(NT) k_small_orth(int mh, const T *Qt, int64_t ldqt, int rp,
                                                    const T *Y, int64_t ldy, int c, T *Q,
                                                    int64_t ldq, uint64_t seed, uint64_t counter,
@@ -65,21 +65,21 @@ __global__ void __launch_bounds__(NT) k_small_orth(int mh, const T *Qt, int64_t 
     __shared__ int sh_info[2];
     __shared__ double sh_ratio[2];
     bool fast = true;
-    if (l <= 16 && NT == 256) {
-        // ---- l <= 16: Grams on the matrix cores, Cholesky in one wavefront
+    if (l <= LM && NT == 256) {
+        // ---- l <= LM (8 or 16): Grams on the matrix cores, Cholesky in one wavefront
         double *part = R + (size_t)l * l;
         // 1. CGS2: coefficients from the Qt-Y block of the Gram of [Qt, Y]
         if (rp > 0 && c > 0) {
             for (int pass = 0; pass < 2; ++pass) {
                 gram16_mfma(W, mh, mhp, l, G, part);
                 for (int i = tid; i < mh; i += NT) {
-                    double qt[16];
+                    double qt[LM];
 #pragma unroll
-                    for (int t = 0; t < 16; ++t) qt[t] = t < rp ? W[(size_t)t * mhp + i] : 0.0;
+                    for (int t = 0; t < LM; ++t) qt[t] = t < rp ? W[(size_t)t * mhp + i] : 0.0;
                     for (int j = 0; j < c; ++j) {
                         double v = W[(size_t)(rp + j) * mhp + i];
 #pragma unroll
-                        for (int t = 0; t < 16; ++t)
+                        for (int t = 0; t < LM; ++t)
                             if (t < rp) v -= qt[t] * G[t * l + rp + j];
                         W[(size_t)(rp + j) * mhp + i] = v;
                     }
@@ -107,7 +107,7 @@ __global__ void __launch_bounds__(NT) k_small_orth(int mh, const T *Qt, int64_t 
         double mx = 0.0;
         for (int j = 0; j < l; ++j) mx = fmax(mx, G[j * l + j]);
         if (wave == 0) {
-            const CholInfo c1 = wave_chol16(G, l, 0.0, 16.0 * l * kU * fmax(mx, 1e-300), R, nullptr);
+            const CholInfo c1 = wave_chol16<LM>(G, l, 0.0, 16.0 * l * kU * fmax(mx, 1e-300), R, nullptr);
             if (lane == 0) {
                 sh_info[0] = c1.nnull;
                 sh_ratio[0] = c1.min_ratio;
@@ -116,16 +116,16 @@ __global__ void __launch_bounds__(NT) k_small_orth(int mh, const T *Qt, int64_t 
         __syncthreads();
         if (sh_info[0] > 0 || sh_ratio[0] < 1e-8) fast = false;
         if (fast) {
-            block_trsm(W, mh, mhp, l, R);
+            block_trsm<LM>(W, mh, mhp, l, R);
             gram16_mfma(W, mh, mhp, l, G, part);
             if (wave == 0) {
-                const CholInfo c2 = wave_chol16(G, l, 0.0, 0.5, R, nullptr);
+                const CholInfo c2 = wave_chol16<LM>(G, l, 0.0, 0.5, R, nullptr);
                 if (lane == 0) sh_info[1] = c2.nnull;
             }
             __syncthreads();
             bool near_one = sh_info[1] == 0;
             for (int j = 0; j < l && near_one; ++j) near_one = fabs(R[j * l + j] - 1.0) <= 1e-6;
-            if (near_one) block_trsm(W, mh, mhp, l, R);
+            if (near_one) block_trsm<LM>(W, mh, mhp, l, R);
             else fast = false;
         }
     } else {
@@ -250,8 +250,12 @@ hipError_t launch_small_orth(int mh, const T *Qt, int64_t ldqt, int rp, const T 
     const int l = rp + c;
     if (!small_orth_ok(mh, l)) return hipErrorInvalidValue;
     const size_t lds = (2 * (size_t)l * (mh | 1) + 2 * (size_t)l * l + 4 * 256) * sizeof(double);
-    hipLaunchKernelGGL((k_small_orth<T, 256>), dim3(1), dim3(256), lds, s, mh, Qt, ldqt, rp, Y,
-                       ldy, c, Q, ldq, seed, counter, flags);
+    if (l <= 8)
+        hipLaunchKernelGGL((k_small_orth<T, 256, 8>), dim3(1), dim3(256), lds, s, mh, Qt, ldqt, rp, Y,
+                           ldy, c, Q, ldq, seed, counter, flags);
+    else
+        hipLaunchKernelGGL((k_small_orth<T, 256, 16>), dim3(1), dim3(256), lds, s, mh, Qt, ldqt, rp, Y,
+                           ldy, c, Q, ldq, seed, counter, flags);
     return hipGetLastError();
 }
 template hipError_t launch_small_orth<double>(int, const double *, int64_t, int, const double *, int64_t, int, double *, int64_t, uint64_t, uint64_t, int *, hipStream_t);
@@ -293,24 +297,32 @@ __device__ inline void circle_pair(int n2, int round, int t, int &p, int &q)
     }
 }
 
-// Rotation of the pair with squared norms al, be and inner product ga:
-// t = sgn(zeta) / (|zeta| + sqrt(1 + zeta^2)), zeta = (be - al) / (2 ga),
-// evaluated as sgn(d) 2ga / (|d| + sqrt(d^2 + 4 ga^2)), d = be - al (one
-// square root and one division fewer); the zeta form is kept for operands
-// whose squares would overflow.
+// Rotation of the pair with squared norms al, be and inner product ga.
+// With d = be - al, g2 = 2 ga and h = sqrt(d^2 + g2^2), the angle theta
+// (|theta| <= pi/4) has cos 2theta = |d| / h and sin 2theta = sgn(d) g2 / h,
+// and the half-angle formulas give cs = sqrt((1 + cos 2theta) / 2),
+// sn = sin 2theta / (2 cs): two dependent reciprocal square roots (1/h and
+// 1/cs) instead of a square root, a division and a reciprocal square root.
+// Operands whose squares would overflow or underflow take the tangent form
+// t = sgn(zeta) / (|zeta| + sqrt(1 + zeta^2)), zeta = d / g2.
 __device__ inline void jacobi_rotation(double al, double be, double ga, double &cs, double &sn)
 {
     const double d = be - al, g2 = 2.0 * ga;
-    const double h = sqrt(d * d + g2 * g2);
-    double t1;
-    if (h < 1e300) {
-        t1 = (d >= 0.0 ? g2 : -g2) / (fabs(d) + h);
+    const double h2 = d * d + g2 * g2;
+    if (h2 > 1e-290 && h2 < 1e290) {
+        const double rh = rsqrt(h2);
+        const double c2 = fabs(d) * rh;
+        const double s2 = (d >= 0.0 ? g2 : -g2) * rh;
+        const double hc = 0.5 * (1.0 + c2);
+        const double rc = rsqrt(hc);
+        cs = hc * rc;
+        sn = 0.5 * s2 * rc;
     } else {
         const double zeta = d / g2;
-        t1 = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
+        const double t1 = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
+        cs = rsqrt(1.0 + t1 * t1);
+        sn = cs * t1;
     }
-    cs = rsqrt(1.0 + t1 * t1);
-    sn = cs * t1;
 }
 
 // The rotation test |ga| > tol sqrt(al be), squared where al be is finite
@@ -460,7 +472,7 @@ __device__ __forceinline__ int jacobi_groups(double *M, int rows, int ld, int n,
 // The body of k_small_svd with the Jacobi storage M either in LDS or in
 // global memory (inlined once for each, so LDS accesses compile to LDS
 // instructions); smem is the dynamic LDS block.
-template <typename T, int NT>
+template <typename T, int NT, int LM>
 __device__ __forceinline__ void small_svd_body(double *M, double *smem, int l, const double *Gin,
                                                double tau, const double *w, const T *Q,
                                                int64_t ldq, int mh, T *QM, int64_t ldqm, T *Qout,
@@ -471,17 +483,25 @@ __device__ __forceinline__ void small_svd_body(double *M, double *smem, int l, c
     const int tid = threadIdx.x;
     const int wave = tid / kWave;
 
+    // l <= 16 with fused products: this thread's first row of Q is loaded
+    // now, so that its latency passes during the factorisation
+    constexpr int kPre = NT <= 256 ? LM : 1;  // the l <= LM path runs with 256 threads
+    double qpre[kPre];
+    const bool pre = NT <= 256 && fuse_q && Q && l <= LM && tid < mh;
+#pragma unroll
+    for (int t = 0; t < kPre; ++t) qpre[t] = (pre && t < l) ? (double)Q[tid + (int64_t)t * ldq] : 0.0;
+
     // Row-major in-place semidefinite Cholesky: M[j*l + k] = R(j, k), k >= j.
     // Read column-major, column j of M is row j of R, i.e. M = R^T.
     for (int idx = tid; idx < l * l; idx += NT) M[idx] = Gin[idx];
     __syncthreads();
     int sweeps = 0;
-    if (NT >= 256 && l <= 16) {
+    if (NT >= 256 && l <= LM) {
         // wavefront 0 alone: register Cholesky, then the Jacobi
         if (wave == 0) {
             double maxdiag = 0.0;
             for (int j = 0; j < l; ++j) maxdiag = fmax(maxdiag, M[j * l + j]);
-            wave_chol16(M, l, 0.0, 4.0 * l * kU * maxdiag, M, nullptr, false);
+            wave_chol16<LM>(M, l, 0.0, 4.0 * l * kU * maxdiag, M, nullptr, false);
             wave_sync();
             sweeps = jacobi_wave16(M, l, 60);
         }
@@ -614,17 +634,22 @@ __device__ __forceinline__ void small_svd_body(double *M, double *smem, int l, c
             sMm[idx] = out.Mm[idx];
         }
         __syncthreads();
-        if (l <= 16) {
+        if (l <= LM) {
             for (int i = tid; i < mh; i += NT) {
-                double q[16];
+                double q[LM];
+                if (kPre == LM && i == tid) {
 #pragma unroll
-                for (int t = 0; t < 16; ++t) q[t] = t < l ? (double)Q[i + (int64_t)t * ldq] : 0.0;
+                    for (int t = 0; t < LM; ++t) q[t] = qpre[t < kPre ? t : 0];
+                } else {
 #pragma unroll
-                for (int j = 0; j < 16; ++j) {
+                    for (int t = 0; t < LM; ++t) q[t] = t < l ? (double)Q[i + (int64_t)t * ldq] : 0.0;
+                }
+#pragma unroll
+                for (int j = 0; j < LM; ++j) {
                     if (j < l) {
                         double v = 0.0, u = 0.0;
 #pragma unroll
-                        for (int t = 0; t < 16; ++t)
+                        for (int t = 0; t < LM; ++t)
                             if (t < l) {
                                 v += q[t] * sMm[t + j * l];
                                 u += q[t] * sU[t + j * l];
@@ -650,7 +675,7 @@ __device__ __forceinline__ void small_svd_body(double *M, double *smem, int l, c
     }
 }
 
-template <typename T, int NT>
+template <typename T, int NT, int LM>
 __global__ void __launch_bounds__(NT) k_small_svd(int l, const double *Gin, double tau,
                                                   const double *w, const T *Q, int64_t ldq, int mh,
                                                   T *QM, int64_t ldqm, T *Qout, int64_t ldqo,
@@ -663,10 +688,10 @@ __global__ void __launch_bounds__(NT) k_small_svd(int l, const double *Gin, doub
     __shared__ double sig[1024], wc[1024];
     double *smem = reinterpret_cast<double *>(smem_raw);
     if (l <= 128)
-        small_svd_body<T, NT>(smem, smem, l, Gin, tau, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, fuse_q,
+        small_svd_body<T, NT, LM>(smem, smem, l, Gin, tau, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, fuse_q,
                               sh_rot, rank, order, sig, coef, wc);
     else
-        small_svd_body<T, NT>(work, smem, l, Gin, tau, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, fuse_q,
+        small_svd_body<T, NT, LM>(work, smem, l, Gin, tau, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, fuse_q,
                               sh_rot, rank, order, sig, coef, wc);
 }
 
@@ -678,10 +703,12 @@ hipError_t launch_small_svd(int l, const double *G, double tau, const double *w,
     if (l < 1 || l > 1024) return hipErrorInvalidValue;
     size_t lds = l <= 128 ? (size_t)l * l * sizeof(double) : 0;
     if (fuse_q && Q) lds = std::max(lds, 2 * (size_t)l * l * sizeof(double));
-    if (l <= 32)
-        hipLaunchKernelGGL((k_small_svd<T, 256>), dim3(1), dim3(256), lds, s, l, G, tau, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, work, fuse_q);
+    if (l <= 8)
+        hipLaunchKernelGGL((k_small_svd<T, 256, 8>), dim3(1), dim3(256), lds, s, l, G, tau, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, work, fuse_q);
+    else if (l <= 32)
+        hipLaunchKernelGGL((k_small_svd<T, 256, 16>), dim3(1), dim3(256), lds, s, l, G, tau, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, work, fuse_q);
     else
-        hipLaunchKernelGGL((k_small_svd<T, 1024>), dim3(1), dim3(1024), lds, s, l, G, tau, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, work, fuse_q);
+        hipLaunchKernelGGL((k_small_svd<T, 1024, 16>), dim3(1), dim3(1024), lds, s, l, G, tau, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, work, fuse_q);
     return hipGetLastError();
 }
 template hipError_t launch_small_svd<double>(int, const double *, double, const double *, const double *, int64_t, int, double *, int64_t, double *, int64_t, const SmallSvdOut &, double *, int, hipStream_t);
