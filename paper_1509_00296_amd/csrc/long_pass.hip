@@ -785,7 +785,8 @@ template hipError_t launch_long<float>(const LongPlan &, int, const LongArgs<flo
 // ===========================================================================
 // Fixed-order reductions: out[j] = sum_g part[g * count + j].
 //   Columns: a 64 x 16 thread block; thread (x, y) sums the parts g = y,
-//   y + 16, ... of output x; the 16 slices are then added in order.
+//   y + 16, ... of output x in eight interleaved partial sums (added in a
+//   fixed tree); the 16 slices are then added in order.
 //   Scalars (count small): all 1024 threads stride over the parts, then a
 //   fixed tree.  Both orders are independent of timing, so results repeat
 //   bit for bit.
@@ -796,16 +797,23 @@ __global__ void __launch_bounds__(1024) k_reduce_cols(const T *part, int64_t cou
     __shared__ T red[16][65];
     const int x = threadIdx.x % 64, y = threadIdx.x / 64;
     const int64_t j = (int64_t)blockIdx.x * 64 + x;
-    T s0 = T(0), s1 = T(0);
+    // eight independent partial sums (parts g + 16 k), their loads issued
+    // together
+    T acc[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] = T(0);
     if (j < count) {
         int g = y;
-        for (; g + 16 < nparts; g += 32) {
-            s0 += part[(int64_t)g * count + j];
-            s1 += part[(int64_t)(g + 16) * count + j];
+        for (; g + 7 * 16 < nparts; g += 8 * 16) {
+            T v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = part[(int64_t)(g + 16 * k) * count + j];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) acc[k] += v[k];
         }
-        if (g < nparts) s0 += part[(int64_t)g * count + j];
+        for (; g < nparts; g += 16) acc[0] += part[(int64_t)g * count + j];
     }
-    red[y][x] = s0 + s1;
+    red[y][x] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     __syncthreads();
     if (y == 0 && j < count) {
         T t = T(0);
