@@ -320,20 +320,17 @@ int ahat_times(frsvt_context *h, const Core<T> &c, const T *V, int64_t ldv, int 
         }
         // Ahat(i, j) with j contiguous: A^T's copy, or A's when Ahat = A^T
         const uint16_t *Ak = o.trans ? c.A16 : c.A16T;
-        hipError_t e = launch_ts_gemm_bf16(o.mh, cols, o.nh, Ak, o.nh, 1, v16, ldv, (float *)Y, 1, o.mh,
-                                           (float *)part, cap, h->num_cu, h->stream);
-        if (e == hipErrorNotSupported)
-            e = launch_gemm_bf16(o.mh, cols, o.nh, c.A16, o.si16, o.sk16, v16, 1, ldv, (float *)Y, 1, o.mh,
-                                 sk, (float *)part, h->stream);
-        CKT(FRSVT_K_GEMM_BF16, e);
+        if (ts_gemm_ok(cols, o.nh, 1, Ak, 2))
+            CKT(FRSVT_K_GEMM_BF16, launch_ts_gemm_bf16(o.mh, cols, o.nh, Ak, o.nh, 1, v16, ldv, (float *)Y, 1,
+                                                       o.mh, (float *)part, cap, h->num_cu, h->stream));
+        else
+            CKT(FRSVT_K_GEMM_BF16, launch_gemm_bf16(o.mh, cols, o.nh, c.A16, o.si16, o.sk16, v16, 1, ldv,
+                                                    (float *)Y, 1, o.mh, sk, (float *)part, h->stream));
         return FRSVT_OK;
     }
-    if (cols <= 128) {
-        hipError_t e = ts_gemm<T>(o.mh, cols, o.nh, c.A, o.si, o.sk, V, ldv, Y, 1, o.mh, part, cap, h);
-        if (e != hipErrorNotSupported) {
-            CKT(FRSVT_K_GEMM, e);
-            return FRSVT_OK;
-        }
+    if (ts_gemm_ok(cols, o.si, o.sk, c.A, (int)sizeof(T))) {
+        CKT(FRSVT_K_GEMM, ts_gemm<T>(o.mh, cols, o.nh, c.A, o.si, o.sk, V, ldv, Y, 1, o.mh, part, cap, h));
+        return FRSVT_OK;
     }
     return mm<T>(h, o.mh, cols, o.nh, c.A, o.si, o.sk, V, 1, ldv, Y, 1, o.mh, sk, part);
 }
@@ -350,20 +347,17 @@ int ahat_t_times(frsvt_context *h, const Core<T> &c, const T *Qm, int64_t ldq, i
         CKT(FRSVT_K_OTHER, launch_to_bf16(o.mh, cols, (const float *)Qm, ldq, Q16, o.mh, h->stream));
         // Ahat(i, j) with i contiguous: A's copy, or A^T's when Ahat = A^T
         const uint16_t *Ak = o.trans ? c.A16T : c.A16;
-        hipError_t e = launch_ts_gemm_bf16(o.nh, cols, o.mh, Ak, o.mh, 1, Q16, o.mh, (float *)Z, 1, o.nh,
-                                           (float *)part, cap, h->num_cu, h->stream);
-        if (e == hipErrorNotSupported)
-            e = launch_gemm_bf16(o.nh, cols, o.mh, c.A16, o.sk16, o.si16, Q16, 1, o.mh, (float *)Z, 1, o.nh,
-                                 1, (float *)part, h->stream);
-        CKT(FRSVT_K_GEMM_BF16, e);
+        if (ts_gemm_ok(cols, o.mh, 1, Ak, 2))
+            CKT(FRSVT_K_GEMM_BF16, launch_ts_gemm_bf16(o.nh, cols, o.mh, Ak, o.mh, 1, Q16, o.mh, (float *)Z, 1,
+                                                       o.nh, (float *)part, cap, h->num_cu, h->stream));
+        else
+            CKT(FRSVT_K_GEMM_BF16, launch_gemm_bf16(o.nh, cols, o.mh, c.A16, o.sk16, o.si16, Q16, 1, o.mh,
+                                                    (float *)Z, 1, o.nh, 1, (float *)part, h->stream));
         return FRSVT_OK;
     }
-    if (cols <= 128) {
-        hipError_t e = ts_gemm<T>(o.nh, cols, o.mh, c.A, o.sk, o.si, Qm, ldq, Z, 1, o.nh, part, cap, h);
-        if (e != hipErrorNotSupported) {
-            CKT(FRSVT_K_GEMM, e);
-            return FRSVT_OK;
-        }
+    if (ts_gemm_ok(cols, o.sk, o.si, c.A, (int)sizeof(T))) {
+        CKT(FRSVT_K_GEMM, ts_gemm<T>(o.nh, cols, o.mh, c.A, o.sk, o.si, Qm, ldq, Z, 1, o.nh, part, cap, h));
+        return FRSVT_OK;
     }
     return mm<T>(h, o.nh, cols, o.mh, c.A, o.sk, o.si, Qm, 1, ldq, Z, 1, o.nh, 1, part);
 }
@@ -612,9 +606,9 @@ int exact_factors(frsvt_context *h, const T *A, int64_t lda, const Orient &o, do
     T *Mt = cv.take<T>((size_t)mh * mh);
     if (!cv.base) return FRSVT_OK;
     if (std::is_same<T, double>::value) {
-        CKT(FRSVT_K_GEMM, (launch_gemm<double, double, double>(mh, mh, o.nh, (const double *)A, o.si, o.sk,
-                                                (const double *)A, o.sk, o.si, G, 1, mh, sk, gp,
-                                                h->stream)));
+        // on the matrix cores (each operand has a unit stride)
+        CKT(FRSVT_K_GEMM, launch_gemm_f64_mfma(mh, mh, o.nh, (const double *)A, o.si, o.sk, (const double *)A,
+                                               o.sk, o.si, G, 1, mh, sk, gp, h->stream));
     } else {
         CKT(FRSVT_K_GEMM, (launch_gemm<float, double, double>(mh, mh, o.nh, (const float *)A, o.si, o.sk,
                                                (const float *)A, o.sk, o.si, G, 1, mh, sk, gp,
@@ -1041,9 +1035,9 @@ int spectral_norm(frsvt_context *h, const T *A, int64_t lda, const Orient &o, do
     double *gp = cv.take<double>((size_t)sk * mh * mh);
     double *wk = cv.take<double>((size_t)2 * mh + 2);
     if (std::is_same<T, double>::value) {
-        CKT(FRSVT_K_GEMM, (launch_gemm<double, double, double>(mh, mh, o.nh, (const double *)A, o.si, o.sk,
-                                                (const double *)A, o.sk, o.si, G, 1, mh, sk, gp,
-                                                h->stream)));
+        // on the matrix cores (each operand has a unit stride)
+        CKT(FRSVT_K_GEMM, launch_gemm_f64_mfma(mh, mh, o.nh, (const double *)A, o.si, o.sk, (const double *)A,
+                                               o.sk, o.si, G, 1, mh, sk, gp, h->stream));
     } else {
         CKT(FRSVT_K_GEMM, (launch_gemm<float, double, double>(mh, mh, o.nh, (const float *)A, o.si, o.sk,
                                                (const float *)A, o.sk, o.si, G, 1, mh, sk, gp,

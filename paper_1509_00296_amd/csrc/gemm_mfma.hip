@@ -547,6 +547,13 @@ __global__ void __launch_bounds__(kThreads, FM >= 4 ? 1 : 2) k_ts_gemm(int64_t M
         }
 }
 
+bool ts_gemm_ok(int64_t N, int64_t sam, int64_t sak, const void *A, int esize)
+{
+    if (N < 1 || N > kTsMaxN) return false;
+    if (sak == 1) return ((uintptr_t)A % 16) == 0 && (sam * esize) % 16 == 0;
+    return sam == 1 && esize != 2;
+}
+
 template <typename TI, typename TO>
 hipError_t launch_ts_gemm(int64_t M, int64_t N, int64_t K, const TI *A, int64_t sam, int64_t sak,
                           const TI *B, int64_t ldb, TO *C, int64_t scm, int64_t scn,
@@ -556,12 +563,9 @@ hipError_t launch_ts_gemm(int64_t M, int64_t N, int64_t K, const TI *A, int64_t 
     constexpr int KB = TsTraits<TI>::KB;
     constexpr int FM = 2;
     if (M <= 0 || N <= 0) return hipSuccess;
-    if (N > kTsMaxN) return hipErrorNotSupported;
+    if (!ts_gemm_ok(N, sam, sak, A, (int)sizeof(TI))) return hipErrorNotSupported;
     const bool akc = sak == 1;
-    if (!akc && (sam != 1 || sizeof(TI) == 2)) return hipErrorNotSupported;
     const int64_t lda = akc ? sam : sak;
-    // 16-byte A vectors need 16-byte aligned rows
-    if (akc && (((uintptr_t)A % 16) != 0 || (lda * (int64_t)sizeof(TI)) % 16 != 0)) return hipErrorNotSupported;
     const int bvec = ((uintptr_t)B % 16) == 0 && (ldb * (int64_t)sizeof(TI)) % 16 == 0;
     const int64_t mt = (M + 64 * FM - 1) / (64 * FM);
     // split K until the grid fills the compute units (per_cu workgroups each),

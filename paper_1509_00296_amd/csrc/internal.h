@@ -209,6 +209,10 @@ hipError_t launch_gemm_f64_mfma(int64_t M, int64_t N, int64_t K, const double *A
 // 16-byte aligned) or, for float and double, row-contiguous (sam = 1).
 // Split K into part (at most part_cap values), reduced into C in a fixed
 // order.  hipErrorNotSupported for other shapes (the caller falls back).
+// whether launch_ts_gemm_* takes these operands (esize: bytes per element;
+// k-contiguous A needs 16-byte aligned rows; row-contiguous A is float or
+// double only)
+bool ts_gemm_ok(int64_t N, int64_t sam, int64_t sak, const void *A, int esize);
 hipError_t launch_ts_gemm_bf16(int64_t M, int64_t N, int64_t K, const uint16_t *A, int64_t sam, int64_t sak,
                                const uint16_t *B, int64_t ldb, float *C, int64_t scm, int64_t scn,
                                float *part, int64_t part_cap, int num_cu, hipStream_t s);
