@@ -1324,7 +1324,7 @@ int wb_buffers(frsvt_context *h, int64_t count)
 
 int wb_launch(frsvt_context *h, const WsvtBatchArgs &a, hipStream_t s)
 {
-    const int grid = h->num_cu;
+    const int grid = 2 * h->num_cu;  // two persistent workgroups per compute unit
     CKT(FRSVT_K_WSVT_BATCHED, launch_wsvt_batched(a, grid, s));
     return FRSVT_OK;
 }
@@ -1439,7 +1439,7 @@ int wsvt_batched_impl(frsvt_context *h, int64_t count, const int32_t *rows, cons
     }
     hipGraph_t graph = nullptr;
     CK(hipStreamBeginCapture(h->wb_capture, hipStreamCaptureModeThreadLocal));
-    CK(launch_wsvt_batched(a, h->num_cu, h->wb_capture));
+    CK(launch_wsvt_batched(a, 2 * h->num_cu, h->wb_capture));
     CK(hipStreamEndCapture(h->wb_capture, &graph));
     hipError_t e = hipGraphInstantiate(&h->wb_exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);

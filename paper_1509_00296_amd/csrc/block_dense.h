@@ -208,46 +208,50 @@ __device__ __forceinline__ CholInfo wave_chol16(const double *G, int l, double s
 }
 
 // Cholesky of the symmetric l x l matrix M (row-major; the upper triangle
-// is read) by NT threads: thread t owns one 4 x 4 block (bi <= bj, dealt in
-// row-major order over the block triangle; nb (nb + 1) / 2 <= NT blocks,
-// nb = ceil(l / 4)) in registers.  Step j: the owner of (j, j) has
-// published the updated diagonal d_j in sh_d[j]; every thread forms the
-// pivot from it (d_j <= tol: numerically null, pivot null_piv and a zero
-// row); the owners of row j scale it and publish it in rowbuf (16-byte
-// aligned, at least 4 nb doubles); the trailing triangle takes the rank-one
-// update (eight reads of rowbuf for sixteen products per thread) and the
-// owner of (j + 1, j + 1) publishes d_{j+1}.  Two barriers per step.  R is
-// written back into M (upper, row-major, zeros below).  Returns the number
-// of null pivots; null_flags[j] (if given) marks them.
-template <int NT>
+// is read) by NT threads: thread t owns the 4 x 4 blocks t, t + NT, ...
+// (BPT of them; blocks bi <= bj dealt in row-major order over the block
+// triangle, nb (nb + 1) / 2 <= BPT NT, nb = ceil(l / 4)) in registers.
+// Step j: the owner of (j, j) has published the updated diagonal d_j in
+// sh_d[j]; every thread forms the pivot from it (d_j <= tol: numerically
+// null, pivot null_piv and a zero row); the owners of row j scale it and
+// publish it in rowbuf (16-byte aligned, at least 4 nb doubles); the trailing
+// triangle takes the rank-one update (eight reads of rowbuf for sixteen
+// products per block) and the owner of (j + 1, j + 1) publishes d_{j+1}.
+// Two barriers per step.  R is written back into M (upper, row-major, zeros
+// below).  Returns the number of null pivots; null_flags[j] (if given) marks
+// them.
+template <int NT, int BPT = 1>
 __device__ __forceinline__ int chol_blk4(double *M, int l, double tol, double null_piv, double *rowbuf,
                                          double *sh_d, int *null_flags)
 {
     const int tid = threadIdx.x;
     const int nb = (l + 3) / 4;
-    int bi = nb, bj = nb;
-    {
-        int rem = tid, r = 0;
+    int bi[BPT], bj[BPT];
+    bool owner[BPT];
+    double v[BPT][4][4];
+#pragma unroll
+    for (int q = 0; q < BPT; ++q) {
+        bi[q] = nb;
+        bj[q] = nb;
+        int rem = tid + q * NT, r = 0;
         while (r < nb && rem >= nb - r) {
             rem -= nb - r;
             ++r;
         }
         if (r < nb) {
-            bi = r;
-            bj = r + rem;
+            bi[q] = r;
+            bj[q] = r + rem;
         }
+        owner[q] = bi[q] < nb;
+#pragma unroll
+        for (int r2 = 0; r2 < 4; ++r2)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int aa = 4 * bi[q] + r2, bb = 4 * bj[q] + c;
+                v[q][r2][c] = (owner[q] && aa < l && bb < l && bb >= aa) ? M[aa * l + bb] : 0.0;
+            }
+        if (owner[q] && bi[q] == 0 && bj[q] == 0) sh_d[0] = v[q][0][0];
     }
-    const bool owner = bi < nb;
-    const int a0 = 4 * bi, b0 = 4 * bj;
-    double v[4][4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int a = a0 + r, b = b0 + c;
-            v[r][c] = (owner && a < l && b < l && b >= a) ? M[a * l + b] : 0.0;
-        }
-    if (owner && bi == 0 && bj == 0) sh_d[0] = v[0][0];
     __syncthreads();
     int nnull = 0;
     for (int j = 0; j < l; ++j) {
@@ -258,60 +262,221 @@ __device__ __forceinline__ int chol_blk4(double *M, int l, double tol, double nu
         const double piv = isnull ? null_piv : d * rs;
         const double inv = isnull ? 0.0 : rs;
         nnull += isnull ? 1 : 0;
-        if (owner && bi == (j >> 2)) {
-            const int rj = j & 3;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                if (r == rj) {
+        for (int q = 0; q < BPT; ++q) {
+            if (owner[q] && bi[q] == (j >> 2)) {
+                const int rj = j & 3;
+                const int b0 = 4 * bj[q];
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        const int b = b0 + c;
-                        v[r][c] = b == j ? piv : (b > j ? v[r][c] * inv : v[r][c]);
-                        if (b > j && b < l) rowbuf[b] = v[r][c];
+                for (int r2 = 0; r2 < 4; ++r2) {
+                    if (r2 == rj) {
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            const int bb = b0 + c;
+                            v[q][r2][c] = bb == j ? piv : (bb > j ? v[q][r2][c] * inv : v[q][r2][c]);
+                            if (bb > j && bb < l) rowbuf[bb] = v[q][r2][c];
+                        }
                     }
                 }
             }
         }
         __syncthreads();
-        if (!isnull && owner && b0 + 3 > j) {
-            const double2 *ra2 = reinterpret_cast<const double2 *>(rowbuf + a0);
-            const double2 *rb2 = reinterpret_cast<const double2 *>(rowbuf + b0);
-            const double2 x0 = ra2[0], x1 = ra2[1], y0 = rb2[0], y1 = rb2[1];
-            const double xa[4] = {x0.x, x0.y, x1.x, x1.y}, yb[4] = {y0.x, y0.y, y1.x, y1.y};
+        if (!isnull) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
+            for (int q = 0; q < BPT; ++q) {
+                const int a0 = 4 * bi[q], b0 = 4 * bj[q];
+                if (owner[q] && b0 + 3 > j) {
+                    const double2 *ra2 = reinterpret_cast<const double2 *>(rowbuf + a0);
+                    const double2 *rb2 = reinterpret_cast<const double2 *>(rowbuf + b0);
+                    const double2 x0 = ra2[0], x1 = ra2[1], y0 = rb2[0], y1 = rb2[1];
+                    const double xa[4] = {x0.x, x0.y, x1.x, x1.y}, yb[4] = {y0.x, y0.y, y1.x, y1.y};
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const int a = a0 + r, b = b0 + c;
-                    const double nv = v[r][c] - xa[r] * yb[c];
-                    v[r][c] = (a > j && b >= a) ? nv : v[r][c];
+                    for (int r2 = 0; r2 < 4; ++r2)
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            const int aa = a0 + r2, bb = b0 + c;
+                            const double nv = v[q][r2][c] - xa[r2] * yb[c];
+                            v[q][r2][c] = (aa > j && bb >= aa) ? nv : v[q][r2][c];
+                        }
                 }
+            }
         }
         const int j1 = j + 1;
-        if (owner && j1 < l && bi == (j1 >> 2) && bj == bi) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                if (r == (j1 & 3)) sh_d[j1] = v[r][r];
+        for (int q = 0; q < BPT; ++q) {
+            if (owner[q] && j1 < l && bi[q] == (j1 >> 2) && bj[q] == bi[q]) {
+#pragma unroll
+                for (int r2 = 0; r2 < 4; ++r2)
+                    if (r2 == (j1 & 3)) sh_d[j1] = v[q][r2][r2];
+            }
         }
         __syncthreads();
     }
     for (int idx = tid; idx < l * l; idx += NT) {
-        const int a = idx / l, b = idx - a * l;
-        if (b < a) M[idx] = 0.0;
+        const int aa = idx / l, bb = idx - aa * l;
+        if (bb < aa) M[idx] = 0.0;
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int q = 0; q < BPT; ++q)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int a = a0 + r, b = b0 + c;
-            if (owner && a < l && b < l && b >= a) M[a * l + b] = v[r][c];
-        }
+        for (int r2 = 0; r2 < 4; ++r2)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int aa = 4 * bi[q] + r2, bb = 4 * bj[q] + c;
+                if (owner[q] && aa < l && bb < l && bb >= aa) M[aa * l + bb] = v[q][r2][c];
+            }
     // the published diagonals decide the null flags (no global store inside
     // the step loop, whose barriers would wait for it)
     if (null_flags)
         for (int j = tid; j < l; j += NT) null_flags[j] = (sh_d[j] > tol) ? 0 : 1;
     __syncthreads();
     return nnull;
+}
+
+// ---------------------------------------------------------------------------
+// One-sided Jacobi pieces: the circle ordering, the rotation, its test and
+// the group engine (shared by the small SVD and the batched WSVT).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void circle_pair(int n2, int round, int t, int &p, int &q)
+{
+    // 0 <= round, t < n2 - 1: both sums lie in [0, 2 (n2 - 1))
+    if (t == 0) {
+        p = n2 - 1;
+        q = round;
+    } else {
+        p = round + t;
+        q = round - t + n2 - 1;
+        if (p >= n2 - 1) p -= n2 - 1;
+        if (q >= n2 - 1) q -= n2 - 1;
+    }
+    if (p > q) {
+        const int tmp = p;
+        p = q;
+        q = tmp;
+    }
+}
+
+// Rotation of the pair with squared norms al, be and inner product ga.
+// With d = be - al, g2 = 2 ga and h = sqrt(d^2 + g2^2), the angle theta
+// (|theta| <= pi/4) has cos 2theta = |d| / h and sin 2theta = sgn(d) g2 / h,
+// and the half-angle formulas give cs = sqrt((1 + cos 2theta) / 2),
+// sn = sin 2theta / (2 cs): two dependent reciprocal square roots (1/h and
+// 1/cs) instead of a square root, a division and a reciprocal square root.
+// Operands whose squares would overflow or underflow take the tangent form
+// t = sgn(zeta) / (|zeta| + sqrt(1 + zeta^2)), zeta = d / g2.
+__device__ __forceinline__ void jacobi_rotation(double al, double be, double ga, double &cs, double &sn)
+{
+    const double d = be - al, g2 = 2.0 * ga;
+    const double h2 = d * d + g2 * g2;
+    if (h2 > 1e-290 && h2 < 1e290) {
+        const double rh = rsqrt(h2);
+        const double c2 = fabs(d) * rh;
+        const double s2 = (d >= 0.0 ? g2 : -g2) * rh;
+        const double hc = 0.5 * (1.0 + c2);
+        const double rc = rsqrt(hc);
+        cs = hc * rc;
+        sn = 0.5 * s2 * rc;
+    } else {
+        const double zeta = d / g2;
+        const double t1 = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
+        cs = rsqrt(1.0 + t1 * t1);
+        sn = cs * t1;
+    }
+}
+
+// The rotation test |ga| > tol sqrt(al be), squared where al be is finite
+// and far from overflow (no square root on the common path).
+__device__ __forceinline__ bool jacobi_needed(double al, double be, double ga, double tol)
+{
+    const double ab = al * be;
+    return ab < 1e300 ? ga * ga > (tol * tol) * ab : fabs(ga) > tol * sqrt(ab);
+}
+
+// One-sided Jacobi on the n columns (length rows, stride ld) of M by groups
+// of G lanes (G = 8, 16, 32 or 64): a group rotates one pair of the round, lane i of
+// the group holding rows i, i + G, ..., i + (E - 1) G in registers.  Rounds
+// with more pairs than groups take several passes (their pairs are
+// disjoint); one block barrier per round.  M may be in LDS or global memory.
+template <int NT, int G, int E>
+__device__ __forceinline__ int jacobi_groups(double *M, int rows, int ld, int n, int max_sweeps, int *sh_rot)
+{
+    constexpr int ngroups = NT / G;
+    const int gl = threadIdx.x % G, gid = threadIdx.x / G;
+    const int n2 = n + (n & 1), npairs = n2 / 2;
+    const double tol = (double)(rows > 1 ? rows : 1) * 2.0 * kU;
+    int sweep;
+    for (sweep = 1; sweep <= max_sweeps; ++sweep) {
+        if (threadIdx.x == 0) *sh_rot = 0;
+        __syncthreads();
+        for (int round = 0; round < n2 - 1; ++round) {
+            for (int t0 = 0; t0 < npairs; t0 += ngroups) {
+                const int t = t0 + gid;
+                int p = 0, q = 0;
+                bool live = false;
+                if (t < npairs) {
+                    circle_pair(n2, round, t, p, q);
+                    live = q < n;
+                }
+                double *mp = M + (size_t)p * ld, *mq = M + (size_t)q * ld;
+                double x[E], y[E];
+                double al = 0.0, be = 0.0, ga = 0.0;
+                // loads at clamped addresses, masked afterwards (no branch per
+                // element)
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int i = gl + G * e;
+                    const int ic = i < rows ? i : 0;
+                    x[e] = mp[ic];
+                    y[e] = mq[ic];
+                }
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const bool in = live && gl + G * e < rows;
+                    x[e] = in ? x[e] : 0.0;
+                    y[e] = in ? y[e] : 0.0;
+                    al += x[e] * x[e];
+                    be += y[e] * y[e];
+                    ga += x[e] * y[e];
+                }
+                if (G == 8) {
+                    al = seg8_sum(al);
+                    be = seg8_sum(be);
+                    ga = seg8_sum(ga);
+                } else if (G == 16) {
+                    al = seg16_sum(al);
+                    be = seg16_sum(be);
+                    ga = seg16_sum(ga);
+                } else if (G == 32) {
+                    al = seg32_sum(al);
+                    be = seg32_sum(be);
+                    ga = seg32_sum(ga);
+                } else {
+                    al = wave_sum(al);
+                    be = wave_sum(be);
+                    ga = wave_sum(ga);
+                }
+                const bool doit = live && jacobi_needed(al, be, ga, tol);
+                if (doit) {
+                    double cs, sn;
+                    jacobi_rotation(al, be, ga, cs, sn);
+#pragma unroll
+                    for (int e = 0; e < E; ++e) {
+                        const int i = gl + G * e;
+                        if (i < rows) {
+                            mp[i] = cs * x[e] - sn * y[e];
+                            mq[i] = sn * x[e] + cs * y[e];
+                        }
+                    }
+                    if (gl == 0) *sh_rot = 1;
+                }
+            }
+            __syncthreads();
+        }
+        const int rot = *sh_rot;
+        __syncthreads();
+        if (!rot) break;
+    }
+    return sweep;
 }
 
 }  // namespace frk

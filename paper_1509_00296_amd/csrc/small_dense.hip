@@ -278,61 +278,6 @@ template hipError_t launch_small_orth<float>(int, const float *, int64_t, int, c
 // ===========================================================================
 bool small_svd_fuse_q_ok(int mh, int l) { return mh >= 1 && l >= 1 && 2 * (size_t)l * l * sizeof(double) <= 96 * 1024; }
 
-__device__ inline void circle_pair(int n2, int round, int t, int &p, int &q)
-{
-    // 0 <= round, t < n2 - 1: both sums lie in [0, 2 (n2 - 1))
-    if (t == 0) {
-        p = n2 - 1;
-        q = round;
-    } else {
-        p = round + t;
-        q = round - t + n2 - 1;
-        if (p >= n2 - 1) p -= n2 - 1;
-        if (q >= n2 - 1) q -= n2 - 1;
-    }
-    if (p > q) {
-        const int tmp = p;
-        p = q;
-        q = tmp;
-    }
-}
-
-// Rotation of the pair with squared norms al, be and inner product ga.
-// With d = be - al, g2 = 2 ga and h = sqrt(d^2 + g2^2), the angle theta
-// (|theta| <= pi/4) has cos 2theta = |d| / h and sin 2theta = sgn(d) g2 / h,
-// and the half-angle formulas give cs = sqrt((1 + cos 2theta) / 2),
-// sn = sin 2theta / (2 cs): two dependent reciprocal square roots (1/h and
-// 1/cs) instead of a square root, a division and a reciprocal square root.
-// Operands whose squares would overflow or underflow take the tangent form
-// t = sgn(zeta) / (|zeta| + sqrt(1 + zeta^2)), zeta = d / g2.
-__device__ inline void jacobi_rotation(double al, double be, double ga, double &cs, double &sn)
-{
-    const double d = be - al, g2 = 2.0 * ga;
-    const double h2 = d * d + g2 * g2;
-    if (h2 > 1e-290 && h2 < 1e290) {
-        const double rh = rsqrt(h2);
-        const double c2 = fabs(d) * rh;
-        const double s2 = (d >= 0.0 ? g2 : -g2) * rh;
-        const double hc = 0.5 * (1.0 + c2);
-        const double rc = rsqrt(hc);
-        cs = hc * rc;
-        sn = 0.5 * s2 * rc;
-    } else {
-        const double zeta = d / g2;
-        const double t1 = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
-        cs = rsqrt(1.0 + t1 * t1);
-        sn = cs * t1;
-    }
-}
-
-// The rotation test |ga| > tol sqrt(al be), squared where al be is finite
-// and far from overflow (no square root on the common path).
-__device__ __forceinline__ bool jacobi_needed(double al, double be, double ga, double tol)
-{
-    const double ab = al * be;
-    return ab < 1e300 ? ga * ga > (tol * tol) * ab : fabs(ga) > tol * sqrt(ab);
-}
-
 // Orders this wavefront's LDS accesses around a point (DS instructions of one
 // wavefront execute in order); used where a single wavefront works alone.
 __device__ __forceinline__ void wave_sync()
@@ -385,85 +330,6 @@ __device__ __forceinline__ int jacobi_wave16(double *M, int l, int max_sweeps)
                 wave_sync();
             }
         }
-        if (!rot) break;
-    }
-    return sweep;
-}
-
-// One-sided Jacobi on the n columns (length rows, stride ld) of M by groups
-// of G lanes (G = 16 or 64): a group rotates one pair of the round, lane i of
-// the group holding rows i, i + G, ..., i + (E - 1) G in registers.  Rounds
-// with more pairs than groups take several passes (their pairs are
-// disjoint); one block barrier per round.  M may be in LDS or global memory.
-template <int NT, int G, int E>
-__device__ __forceinline__ int jacobi_groups(double *M, int rows, int ld, int n, int max_sweeps, int *sh_rot)
-{
-    constexpr int ngroups = NT / G;
-    const int gl = threadIdx.x % G, gid = threadIdx.x / G;
-    const int n2 = n + (n & 1), npairs = n2 / 2;
-    const double tol = (double)(rows > 1 ? rows : 1) * 2.0 * kU;
-    int sweep;
-    for (sweep = 1; sweep <= max_sweeps; ++sweep) {
-        if (threadIdx.x == 0) *sh_rot = 0;
-        __syncthreads();
-        for (int round = 0; round < n2 - 1; ++round) {
-            for (int t0 = 0; t0 < npairs; t0 += ngroups) {
-                const int t = t0 + gid;
-                int p = 0, q = 0;
-                bool live = false;
-                if (t < npairs) {
-                    circle_pair(n2, round, t, p, q);
-                    live = q < n;
-                }
-                double *mp = M + (size_t)p * ld, *mq = M + (size_t)q * ld;
-                double x[E], y[E];
-                double al = 0.0, be = 0.0, ga = 0.0;
-                // loads at clamped addresses, masked afterwards (no branch per
-                // element)
-#pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    const int i = gl + G * e;
-                    const int ic = i < rows ? i : 0;
-                    x[e] = mp[ic];
-                    y[e] = mq[ic];
-                }
-#pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    const bool in = live && gl + G * e < rows;
-                    x[e] = in ? x[e] : 0.0;
-                    y[e] = in ? y[e] : 0.0;
-                    al += x[e] * x[e];
-                    be += y[e] * y[e];
-                    ga += x[e] * y[e];
-                }
-                if (G == 16) {
-                    al = seg16_sum(al);
-                    be = seg16_sum(be);
-                    ga = seg16_sum(ga);
-                } else {
-                    al = wave_sum(al);
-                    be = wave_sum(be);
-                    ga = wave_sum(ga);
-                }
-                const bool doit = live && jacobi_needed(al, be, ga, tol);
-                if (doit) {
-                    double cs, sn;
-                    jacobi_rotation(al, be, ga, cs, sn);
-#pragma unroll
-                    for (int e = 0; e < E; ++e) {
-                        const int i = gl + G * e;
-                        if (i < rows) {
-                            mp[i] = cs * x[e] - sn * y[e];
-                            mq[i] = sn * x[e] + cs * y[e];
-                        }
-                    }
-                    if (gl == 0) *sh_rot = 1;
-                }
-            }
-            __syncthreads();
-        }
-        const int rot = *sh_rot;
-        __syncthreads();
         if (!rot) break;
     }
     return sweep;

@@ -3,50 +3,103 @@
 // Sec. 1 / footnote 1 of arXiv:1509.00296, applied to patch groups).
 //
 // Each workgroup pops matrix indices from an atomic queue (longest first) and
-// for matrix j (rows x cols, column-major, float):
-//   1. stages A in LDS (float), forms the Gram G of its short side in double
-//      (A^T A when cols <= rows, else A A^T), s = min(rows, cols);
-//   2. semidefinite Cholesky G = R^T R in place;
-//   3. one-sided Jacobi on M = R^T: its normalised columns are the
-//      eigenvectors V of G (the singular vectors of A on the short side) and
-//      its column norms the singular values of A;
-//   4. thresholds w_i from the weight rule (or a constant), coef = f/s;
-//   5. P = V diag(coef) V^T (float) and X = A P (or P A), written as float.
-// Jacobi pairs (circle method) are spread over groups of `gs` lanes; gs is
-// chosen per size bucket by the host autotuner and read from a table.
+// for matrix j (rows x cols, column-major, float), with s = min(rows, cols)
+// and W the long-by-short view of A (W = A when cols <= rows, else A^T):
+//   1. G = W^T W in double on the matrix cores, straight from A in memory
+//      (the upper 16 x 16 blocks dealt to the wavefronts);
+//   2. semidefinite Cholesky G = R^T R in LDS (4 x 4 register blocks);
+//   3. one-sided Jacobi on M = R^T by groups of gs lanes, one pair per group:
+//      the normalised columns of M are the eigenvectors of G (the singular
+//      vectors of A on the short side), its column norms the singular values;
+//   4. thresholds w_i from the weight rule (or a constant), coef = f / s^3;
+//   5. X = A P (or P A) with P = sum coef_c m_c m_c^T as a rank-r update:
+//      Z = A m_c (or A^T m_c) for the kept columns, four at a time, then
+//      X += coef_c Z m_c^T.
+// LDS holds M (and the four Z columns) only, so two workgroups share a
+// compute unit.  gs (8, 16 or 32 lanes per pair) is chosen per size bucket
+// by the host autotuner and read from a table.
 #include "device_common.h"
 #include "internal.h"
+#include "block_dense.h"
 
 #include <algorithm>
 
 namespace frk {
 
-constexpr int kWB = 512;          // threads per workgroup
+constexpr int kWB = 256;          // threads per workgroup (four wavefronts, one per SIMD)
 constexpr int kWMaxLong = 128;    // longest side
 constexpr int kWMaxShort = 96;    // shortest side
+constexpr int kWZ = 4;            // kept singular vectors per update chunk
 
-size_t wsvt_batched_lds() { return (size_t)kWMaxLong * kWMaxShort * 4 + (size_t)kWMaxShort * kWMaxShort * 8 + (size_t)kWMaxShort * kWMaxShort * 4; }
-
-// sum over the aligned group of gs lanes (gs = 8, 16 or 32), in every lane
-__device__ __forceinline__ double seg_sum(double v, int gs)
+size_t wsvt_batched_lds()
 {
-    if (gs == 8) return seg8_sum(v);
-    if (gs == 16) return seg16_sum(v);
-    return seg32_sum(v);
+    return (size_t)kWMaxShort * kWMaxShort * sizeof(double) + (size_t)kWZ * kWMaxLong * sizeof(double);
 }
 
-__global__ void __launch_bounds__(kWB) k_wsvt_batched(WsvtBatchArgs a)
+// G = W^T W (s x s, row-major into M), W(i, x) = A[i * wsi + x * wsx],
+// i < L, x < s <= 96.  Step: 8 rows as two 16x16x4 products (k-slot q of
+// the first holds row 2q, of the second row 2q + 1).
+__device__ __forceinline__ void wsvt_gram(const float *__restrict__ A, int64_t wsi, int64_t wsx, int L, int s,
+                                          double *M)
+{
+    constexpr int NW = kWB / kWave;
+    constexpr int NP = (21 + NW - 1) / NW;  // block pairs per wavefront
+    typedef __attribute__((__vector_size__(4 * sizeof(double)))) double dx4;
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    const int c = lane & 15, q = lane >> 4;
+    const int nb = (s + 15) / 16;
+    dx4 acc[NP];
+#pragma unroll
+    for (int t = 0; t < NP; ++t) acc[t] = dx4{0.0, 0.0, 0.0, 0.0};
+    for (int i0 = 0; i0 < L; i0 += 8) {
+        const int ia = i0 + 2 * q, ib = ia + 1;
+        double v0[6], v1[6];
+#pragma unroll
+        for (int bk = 0; bk < 6; ++bk) {
+            const int x = 16 * bk + c;
+            const bool ok = bk < nb && x < s;
+            v0[bk] = (ok && ia < L) ? (double)A[ia * wsi + x * wsx] : 0.0;
+            v1[bk] = (ok && ib < L) ? (double)A[ib * wsi + x * wsx] : 0.0;
+        }
+        int idx = 0;
+#pragma unroll
+        for (int bi = 0; bi < 6; ++bi)
+#pragma unroll
+            for (int bj = bi; bj < 6; ++bj, ++idx) {
+                if (idx % NW == wave && bj < nb) {
+                    acc[idx / NW] = __builtin_amdgcn_mfma_f64_16x16x4f64(v0[bi], v0[bj], acc[idx / NW], 0, 0, 0);
+                    acc[idx / NW] = __builtin_amdgcn_mfma_f64_16x16x4f64(v1[bi], v1[bj], acc[idx / NW], 0, 0, 0);
+                }
+            }
+    }
+    int idx = 0;
+#pragma unroll
+    for (int bi = 0; bi < 6; ++bi)
+#pragma unroll
+        for (int bj = bi; bj < 6; ++bj, ++idx) {
+            if (idx % NW == wave && bj < nb) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int x = 16 * bi + q + 4 * e, y = 16 * bj + c;
+                    if (x < s && y < s) {
+                        M[x * s + y] = acc[idx / NW][e];
+                        M[y * s + x] = acc[idx / NW][e];
+                    }
+                }
+            }
+        }
+}
+
+__global__ void __launch_bounds__(kWB, 2) k_wsvt_batched(WsvtBatchArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    float *sA = reinterpret_cast<float *>(smem_raw);                               // rows x cols
-    double *sM = reinterpret_cast<double *>(smem_raw + (size_t)kWMaxLong * kWMaxShort * 4);
-    float *sP = reinterpret_cast<float *>(smem_raw + (size_t)kWMaxLong * kWMaxShort * 4 +
-                                          (size_t)kWMaxShort * kWMaxShort * 8);
-    __shared__ int sh_idx, sh_rot, sh_rank;
-    __shared__ double sig[kWMaxShort], coef[kWMaxShort];
+    double *M = reinterpret_cast<double *>(smem_raw);
+    double *Z = M + kWMaxShort * kWMaxShort;  // [kWZ][kWMaxLong]
+    __shared__ int sh_idx, sh_rot, sh_rank, sh_nz;
+    __shared__ __align__(16) double coef[kWMaxShort];
+    __shared__ double sig[kWMaxShort];
+    __shared__ int nzc[kWMaxShort];
     const int tid = threadIdx.x;
-    const int64_t nrot_local = 0;
-    (void)nrot_local;
     for (;;) {
         if (tid == 0) sh_idx = atomicAdd(a.queue, 1);
         __syncthreads();
@@ -55,155 +108,96 @@ __global__ void __launch_bounds__(kWB) k_wsvt_batched(WsvtBatchArgs a)
         const int j = a.order ? a.order[qi] : (int)qi;
         const int m = a.rows[j], n = a.cols[j];
         const int64_t off = a.offsets[j];
+        const float *Aj = a.A + off;
         const bool tall = n <= m;
         const int s = tall ? n : m, L = tall ? m : n;
         const int bucket = s <= 48 ? 0 : (s <= 64 ? 1 : 2);
         const int gs = a.group_size[bucket];
-        const int ngroups = kWB / gs;
 
-        for (int idx = tid; idx < m * n; idx += kWB) sA[idx] = a.A[off + idx];
+        // 1. Gram of the short side (W(i, x) = A(i, x) tall, A(x, i) wide)
+        wsvt_gram(Aj, tall ? 1 : m, tall ? m : 1, L, s, M);
         __syncthreads();
-        // 1. Gram of the short side, double
-        const int npairs = s * (s + 1) / 2;
-        for (int p = tid; p < npairs; p += kWB) {
-            int x = 0, rem = p;
-            while (rem >= s - x) {
-                rem -= s - x;
-                ++x;
-            }
-            const int y = x + rem;
-            double acc = 0.0;
-            if (tall) {
-                const float *ca = sA + (size_t)x * m, *cb = sA + (size_t)y * m;
-                for (int i = 0; i < m; ++i) acc += (double)ca[i] * (double)cb[i];
-            } else {
-                for (int k = 0; k < n; ++k) acc += (double)sA[x + (size_t)k * m] * (double)sA[y + (size_t)k * m];
-            }
-            sM[x * s + y] = acc;
-            sM[y * s + x] = acc;
-        }
-        __syncthreads();
-        // 2. semidefinite Cholesky, row-major in place (sM[r*s + c] = R(r, c))
+        // 2. semidefinite Cholesky (coef and sig serve as its step buffers)
         double maxdiag = 0.0;
-        for (int d = 0; d < s; ++d) maxdiag = fmax(maxdiag, sM[d * s + d]);
-        const double ptol = 4.0 * s * kU * maxdiag;
-        for (int c0 = 0; c0 < s; ++c0) {
-            double d = sM[c0 * s + c0];
-            for (int t = 0; t < c0; ++t) d -= sM[t * s + c0] * sM[t * s + c0];
-            const double piv = d > ptol ? sqrt(d) : 0.0;
-            __syncthreads();
-            if (tid == 0) sM[c0 * s + c0] = piv;
-            for (int k = c0 + 1 + tid; k < s; k += kWB) {
-                double v = 0.0;
-                if (piv > 0.0) {
-                    v = sM[c0 * s + k];
-                    for (int t = 0; t < c0; ++t) v -= sM[t * s + c0] * sM[t * s + k];
-                    v /= piv;
-                }
-                sM[c0 * s + k] = v;
-            }
-            __syncthreads();
+        for (int d = 0; d < s; ++d) maxdiag = fmax(maxdiag, M[d * s + d]);
+        chol_blk4<kWB, 2>(M, s, 4.0 * s * kU * maxdiag, 0.0, coef, sig, nullptr);
+        // 3. one-sided Jacobi on M = R^T
+        //    (rows per lane E = ceil(bucket bound / gs), so no lane reads past
+        //    its bucket)
+        int sweeps;
+        if (bucket == 0) {
+            if (gs == 8) sweeps = jacobi_groups<kWB, 8, 6>(M, s, s, s, 40, &sh_rot);
+            else if (gs == 32) sweeps = jacobi_groups<kWB, 32, 2>(M, s, s, s, 40, &sh_rot);
+            else sweeps = jacobi_groups<kWB, 16, 3>(M, s, s, s, 40, &sh_rot);
+        } else if (bucket == 1) {
+            if (gs == 8) sweeps = jacobi_groups<kWB, 8, 8>(M, s, s, s, 40, &sh_rot);
+            else if (gs == 32) sweeps = jacobi_groups<kWB, 32, 2>(M, s, s, s, 40, &sh_rot);
+            else sweeps = jacobi_groups<kWB, 16, 4>(M, s, s, s, 40, &sh_rot);
+        } else {
+            if (gs == 8) sweeps = jacobi_groups<kWB, 8, 12>(M, s, s, s, 40, &sh_rot);
+            else if (gs == 32) sweeps = jacobi_groups<kWB, 32, 3>(M, s, s, s, 40, &sh_rot);
+            else sweeps = jacobi_groups<kWB, 16, 6>(M, s, s, s, 40, &sh_rot);
         }
-        for (int idx = tid; idx < s * s; idx += kWB)
-            if (idx % s < idx / s) sM[idx] = 0.0;
-        __syncthreads();
-        // 3. one-sided Jacobi on M = R^T (column c of M = row c of R)
-        const int n2 = s + (s & 1);
-        const int pairs = n2 / 2;
-        const int g = tid / gs, gl = tid % gs;
-        const double tol = (double)s * 2.0 * kU;
-        int sweeps = 0;
-        for (int sweep = 0; sweep < 40; ++sweep) {
-            if (tid == 0) sh_rot = 0;
-            __syncthreads();
-            for (int round = 0; round < n2 - 1; ++round) {
-                for (int t0 = 0; t0 < pairs; t0 += ngroups) {
-                    const int t = t0 + g;
-                    int p = 0, q = 0;
-                    bool live = false;
-                    if (t < pairs) {
-                        if (t == 0) {
-                            p = n2 - 1;
-                            q = round;
-                        } else {
-                            p = (round + t) % (n2 - 1);
-                            q = (round - t + n2 - 1) % (n2 - 1);
-                        }
-                        if (p > q) {
-                            const int tmp = p;
-                            p = q;
-                            q = tmp;
-                        }
-                        live = q < s;
-                    }
-                    double al = 0.0, be = 0.0, ga = 0.0;
-                    if (live)
-                        for (int i = gl; i < s; i += gs) {
-                            const double x = sM[p * s + i], y = sM[q * s + i];
-                            al += x * x;
-                            be += y * y;
-                            ga += x * y;
-                        }
-                    al = seg_sum(al, gs);
-                    be = seg_sum(be, gs);
-                    ga = seg_sum(ga, gs);
-                    if (live && fabs(ga) > tol * sqrt(al * be)) {
-                        const double zeta = (be - al) / (2.0 * ga);
-                        const double t1 = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
-                        const double cs = 1.0 / sqrt(1.0 + t1 * t1), sn = cs * t1;
-                        for (int i = gl; i < s; i += gs) {
-                            const double x = sM[p * s + i], y = sM[q * s + i];
-                            sM[p * s + i] = cs * x - sn * y;
-                            sM[q * s + i] = sn * x + cs * y;
-                        }
-                        if (gl == 0) sh_rot = 1;
-                    }
-                    __syncthreads();
-                }
-            }
-            sweeps = sweep + 1;
-            const int rot = sh_rot;
-            __syncthreads();
-            if (!rot) break;
-        }
-        // 4. singular values, thresholds
-        for (int c = tid; c < s; c += kWB) {
+        // 4. singular values, thresholds: P = sum_c (f_c / s_c) v_c v_c^T with
+        //    v_c = m_c / s_c, i.e. coef_c = f_c / s_c^3 on the columns m_c
+        for (int cc = tid / 16; cc < s; cc += kWB / 16) {
+            const double *mc = M + (size_t)cc * s;
             double ss = 0.0;
-            for (int i = 0; i < s; ++i) ss += sM[c * s + i] * sM[c * s + i];
-            const double sv = sqrt(ss);
-            double w = a.tau;
-            if (a.c > 0.0) {
-                const double e = sv * sv - (double)n * a.noise_var;
-                w = a.c * sqrt((double)n) / ((e > 0.0 ? sqrt(e) : 0.0) + a.eps);
+            for (int i = tid % 16; i < s; i += 16) ss += mc[i] * mc[i];
+            ss = seg16_sum(ss);
+            if (tid % 16 == 0) {
+                const double sv = sqrt(ss);
+                double w = a.tau;
+                if (a.c > 0.0) {
+                    const double e = sv * sv - (double)n * a.noise_var;
+                    w = a.c * sqrt((double)n) / ((e > 0.0 ? sqrt(e) : 0.0) + a.eps);
+                }
+                const double f = sv - w;
+                sig[cc] = sv;
+                coef[cc] = (f > 0.0 && sv > 0.0) ? f / (sv * sv * sv) : 0.0;
             }
-            const double f = sv - w;
-            sig[c] = sv;
-            // P = sum_c (f_c / s_c) v_c v_c^T with v_c = m_c / s_c
-            coef[c] = (f > 0.0 && sv > 0.0) ? f / (sv * sv * sv) : 0.0;
         }
         __syncthreads();
         if (tid == 0) {
             int r = 0;
-            for (int c = 0; c < s; ++c) r += coef[c] > 0.0 ? 1 : 0;
+            for (int cc = 0; cc < s; ++cc)
+                if (coef[cc] != 0.0) nzc[r++] = cc;
             sh_rank = r;
-        }
-        // 5. P = sum_c coef_c m_c m_c^T
-        for (int idx = tid; idx < s * s; idx += kWB) {
-            const int x = idx % s, y = idx / s;
-            double v = 0.0;
-            for (int c = 0; c < s; ++c)
-                if (coef[c] != 0.0) v += coef[c] * sM[c * s + x] * sM[c * s + y];
-            sP[idx] = (float)v;
+            sh_nz = r;
         }
         __syncthreads();
-        for (int idx = tid; idx < m * n; idx += kWB) {
-            const int i = idx % m, k = idx / m;
-            float v = 0.0f;
-            if (tall)
-                for (int t = 0; t < n; ++t) v += sA[i + t * m] * sP[t + k * s];
-            else
-                for (int t = 0; t < m; ++t) v += sP[i + t * s] * sA[t + k * m];
-            a.X[off + idx] = v;
+        // 5. X = sum_c coef_c Z_c m_c^T (tall) or coef_c m_c Z_c^T (wide); a
+        //    chunk after the first adds to what the same thread stored
+        const int nz = sh_nz;
+        if (nz == 0)
+            for (int idx = tid; idx < m * n; idx += kWB) a.X[off + idx] = 0.0f;
+        for (int c0 = 0; c0 < nz; c0 += kWZ) {
+            const int cn = min(kWZ, nz - c0);
+            for (int idx = tid; idx < cn * L; idx += kWB) {
+                const int cc = idx / L, i = idx - cc * L;
+                const double *mc = M + (size_t)nzc[c0 + cc] * s;
+                double z = 0.0;
+                if (tall) {
+#pragma unroll 8
+                    for (int t = 0; t < s; ++t) z += (double)Aj[i + (int64_t)t * m] * mc[t];
+                } else {
+#pragma unroll 8
+                    for (int t = 0; t < s; ++t) z += mc[t] * (double)Aj[t + (int64_t)i * m];
+                }
+                Z[cc * kWMaxLong + i] = z;
+            }
+            __syncthreads();
+            for (int idx = tid; idx < m * n; idx += kWB) {
+                const int i = idx % m, k = idx / m;
+                double v = c0 ? (double)a.X[off + idx] : 0.0;
+                for (int cc = 0; cc < cn; ++cc) {
+                    const int col = nzc[c0 + cc];
+                    const double *mc = M + (size_t)col * s;
+                    v += tall ? coef[col] * Z[cc * kWMaxLong + i] * mc[k] : coef[col] * mc[i] * Z[cc * kWMaxLong + k];
+                }
+                a.X[off + idx] = (float)v;
+            }
+            __syncthreads();
         }
         if (tid == 0) {
             if (a.ranks) a.ranks[j] = sh_rank;
