@@ -145,14 +145,23 @@ _handles: dict = {}
 
 
 def handle(device: int | None = None) -> Handle:
+    """The handle of (device, torch's current stream): work issued on
+    different streams uses different handles, so their workspaces never
+    overlap."""
     import torch
     if device is None:
         device = torch.cuda.current_device()
-    if device not in _handles:
-        _handles[device] = Handle(device)
-    h = _handles[device]
+    key = (device, torch.cuda.current_stream(device).cuda_stream)
+    if key not in _handles:
+        _handles[key] = Handle(device)
+    h = _handles[key]
     h.bind_current_stream()
     return h
+
+
+def handles(device: int = 0) -> list:
+    """Every handle created on a device (one per stream used)."""
+    return [h for (d, _), h in _handles.items() if d == device]
 
 
 def _check(h: Handle, rc: int, name: str, ok=(OK,)):
@@ -493,31 +502,54 @@ class _UnrolledFn(_torch().autograd.Function):
     sweep with frsvt_vjp and dual_step_vjp; the threshold gradients are summed
     on the device and read once."""
 
+    # Instances are independent: instance b runs on side stream b mod
+    # _STREAMS (its own library handle and workspace), and the caller's stream
+    # waits for all of them, so the GPU overlaps the instances' small kernels.
+    _STREAMS = 4
+
+    _side: dict = {}
+
+    @staticmethod
+    def _side_streams(dev, count):
+        """The caller's stream and `count` side streams of the device (made
+        once and reused, so each keeps its one library handle); the side
+        streams wait for the caller's."""
+        torch = _torch()
+        cur = torch.cuda.current_stream(dev)
+        key = dev.index if dev.index is not None else torch.cuda.current_device()
+        pool = _UnrolledFn._side.setdefault(key, [])
+        while len(pool) < count:
+            pool.append(torch.cuda.Stream(device=dev))
+        side = pool[:count]
+        for s in side:
+            s.wait_stream(cur)
+        return cur, side
+
     @staticmethod
     def forward(ctx, taus, lams, O, Y0, A0, mus, k, p, q, seeds):
         torch = _torch()
         T = taus.numel()
         B = O.shape[0]
         tv, lv = [float(x) for x in taus.tolist()], [float(x) for x in lams.tolist()]
-        As, Ys, Ls, Qs, Fs = [], [], [], [], []
-        A_t, Y_t = list(A0), list(Y0)
-        for t in range(T):
-            L_t, Q_t, F_t, An, Yn = [], [], [], [], []
-            for b in range(B):
-                X, Q, fac = frsvt_fwd(A_t[b], tv[t], k, p, q, seed=seeds[b], counter=t)
-                L_t.append(X)
-                Q_t.append(Q)
-                F_t.append(fac)
-                if t + 1 < T:
-                    _, y1, a1 = dual_step(O[b], X, Y_t[b], lv[t], mus[b][t], mus[b][t + 1])
-                    Yn.append(y1)
-                    An.append(a1)
-            As.append(A_t)
-            Ys.append(Y_t)
-            Ls.append(L_t)
-            Qs.append(Q_t)
-            Fs.append(F_t)
-            A_t, Y_t = An, Yn
+        As = [[None] * B for _ in range(T)]
+        Ys = [[None] * B for _ in range(T)]
+        Ls = [[None] * B for _ in range(T)]
+        Qs = [[None] * B for _ in range(T)]
+        Fs = [[None] * B for _ in range(T)]
+        cur, side = _UnrolledFn._side_streams(O.device, min(B, _UnrolledFn._STREAMS))
+        for b in range(B):
+            with torch.cuda.stream(side[b % len(side)]):
+                A_b, Y_b = A0[b], Y0[b]
+                for t in range(T):
+                    X, Q, fac = frsvt_fwd(A_b, tv[t], k, p, q, seed=seeds[b], counter=t)
+                    As[t][b], Ys[t][b], Ls[t][b], Qs[t][b], Fs[t][b] = A_b, Y_b, X, Q, fac
+                    if t + 1 < T:
+                        _, Y_b, A_b = dual_step(O[b], X, Y_b, lv[t], mus[b][t], mus[b][t + 1])
+        for s in side:
+            cur.wait_stream(s)
+        # tensors made on a side stream and used on the caller's stream
+        for b in range(B):
+            Ls[-1][b].record_stream(cur)
         ctx.state = (As, Ys, Ls, Qs, Fs, O, mus, k, p, q, seeds, tv, lv, taus.device)
         return torch.stack(Ls[-1])
 
@@ -529,22 +561,26 @@ class _UnrolledFn(_torch().autograd.Function):
         dev = L_bar.device
         gt = torch.zeros((T, B), dtype=torch.float64, device=dev)
         gl = torch.zeros((T, B), dtype=torch.float64, device=dev)
+        cur, side = _UnrolledFn._side_streams(dev, min(B, _UnrolledFn._STREAMS))
         for b in range(B):
-            Ab_next, Yb_next = None, None
-            for t in range(T - 1, -1, -1):
-                if t == T - 1:
-                    Lb = L_bar[b]
-                else:
-                    Lb, Yb_t, _ = dual_step_vjp(O[b], Ls[t][b], Ys[t][b], lv[t], mus[b][t],
-                                                mus[b][t + 1], None, Yb_next, Ab_next,
-                                                lam_bar=gl[t, b])
-                    Yb_next = Yb_t
-                Ab_t, tb = frsvt_vjp(As[t][b], tv[t], k, p, q, Qs[t][b], Fs[t][b], Lb,
-                                     seed=seeds[b], counter=t)
-                gt[t, b].copy_(tb)
-                Ab_next = Ab_t
-                if t == T - 1:
-                    Yb_next = None
+            with torch.cuda.stream(side[b % len(side)]):
+                Ab_next, Yb_next = None, None
+                for t in range(T - 1, -1, -1):
+                    if t == T - 1:
+                        Lb = L_bar[b]
+                    else:
+                        Lb, Yb_t, _ = dual_step_vjp(O[b], Ls[t][b], Ys[t][b], lv[t], mus[b][t],
+                                                    mus[b][t + 1], None, Yb_next, Ab_next,
+                                                    lam_bar=gl[t, b])
+                        Yb_next = Yb_t
+                    Ab_t, tb = frsvt_vjp(As[t][b], tv[t], k, p, q, Qs[t][b], Fs[t][b], Lb,
+                                         seed=seeds[b], counter=t)
+                    gt[t, b].copy_(tb)
+                    Ab_next = Ab_t
+                    if t == T - 1:
+                        Yb_next = None
+        for s in side:
+            cur.wait_stream(s)
         ctx.state = None
         gtau = gt.sum(dim=1).to(pdev)
         glam = gl.sum(dim=1).to(pdev)
