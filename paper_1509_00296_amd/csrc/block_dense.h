@@ -217,13 +217,16 @@ __device__ __forceinline__ CholInfo wave_chol16(const double *G, int l, double s
 // publish it in rowbuf (16-byte aligned, at least 4 nb doubles); the trailing
 // triangle takes the rank-one update (eight reads of rowbuf for sixteen
 // products per block) and the owner of (j + 1, j + 1) publishes d_{j+1}.
-// Two barriers per step.  R is written back into M (upper, row-major, zeros
-// below).  Returns the number of null pivots; null_flags[j] (if given) marks
-// them.
+// Two barriers per step.  R is written back into M (upper, row-major with
+// row stride ldo or l, zeros below and past column l - 1).  Returns the
+// number of null pivots; null_flags[j] (if given) marks them.
 template <int NT, int BPT = 1>
 __device__ __forceinline__ int chol_blk4(double *M, int l, double tol, double null_piv, double *rowbuf,
-                                         double *sh_d, int *null_flags)
+                                         double *sh_d, int *null_flags, int ldo = 0)
 {
+    // R goes back with row stride ld (ldo if given, else l); entries past
+    // column l - 1 of a row are zero
+    const int ld = ldo > 0 ? ldo : l;
     const int tid = threadIdx.x;
     const int nb = (l + 3) / 4;
     int bi[BPT], bj[BPT];
@@ -312,9 +315,9 @@ __device__ __forceinline__ int chol_blk4(double *M, int l, double tol, double nu
         }
         __syncthreads();
     }
-    for (int idx = tid; idx < l * l; idx += NT) {
-        const int aa = idx / l, bb = idx - aa * l;
-        if (bb < aa) M[idx] = 0.0;
+    for (int idx = tid; idx < l * ld; idx += NT) {
+        const int aa = idx / ld, bb = idx - aa * ld;
+        if (bb < aa || bb >= l) M[idx] = 0.0;
     }
 #pragma unroll
     for (int q = 0; q < BPT; ++q)
@@ -323,7 +326,7 @@ __device__ __forceinline__ int chol_blk4(double *M, int l, double tol, double nu
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const int aa = 4 * bi[q] + r2, bb = 4 * bj[q] + c;
-                if (owner[q] && aa < l && bb < l && bb >= aa) M[aa * l + bb] = v[q][r2][c];
+                if (owner[q] && aa < l && bb < l && bb >= aa) M[aa * ld + bb] = v[q][r2][c];
             }
     // the published diagonals decide the null flags (no global store inside
     // the step loop, whose barriers would wait for it)
@@ -393,11 +396,13 @@ __device__ __forceinline__ bool jacobi_needed(double al, double be, double ga, d
 }
 
 // One-sided Jacobi on the n columns (length rows, stride ld) of M by groups
-// of G lanes (G = 8, 16, 32 or 64): a group rotates one pair of the round, lane i of
-// the group holding rows i, i + G, ..., i + (E - 1) G in registers.  Rounds
+// of G lanes (G = 8, 16, 32 or 64): a group rotates one pair of the round,
+// lane i of the group holding rows i, i + G, ..., i + (E - 1) G in
+// registers.  With PAD the caller keeps ld >= G E and zeros in rows
+// [rows, G E) of every column, so loads and stores need no bounds.  Rounds
 // with more pairs than groups take several passes (their pairs are
 // disjoint); one block barrier per round.  M may be in LDS or global memory.
-template <int NT, int G, int E>
+template <int NT, int G, int E, bool PAD = false>
 __device__ __forceinline__ int jacobi_groups(double *M, int rows, int ld, int n, int max_sweeps, int *sh_rot)
 {
     constexpr int ngroups = NT / G;
@@ -417,26 +422,42 @@ __device__ __forceinline__ int jacobi_groups(double *M, int rows, int ld, int n,
                     circle_pair(n2, round, t, p, q);
                     live = q < n;
                 }
+                if (!live) p = q = 0;  // a group without a pair reads column 0
                 double *mp = M + (size_t)p * ld, *mq = M + (size_t)q * ld;
                 double x[E], y[E];
                 double al = 0.0, be = 0.0, ga = 0.0;
-                // loads at clamped addresses, masked afterwards (no branch per
-                // element)
+                if (PAD) {
+                    // rows [rows, G E) hold zeros: plain loads
 #pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    const int i = gl + G * e;
-                    const int ic = i < rows ? i : 0;
-                    x[e] = mp[ic];
-                    y[e] = mq[ic];
-                }
+                    for (int e = 0; e < E; ++e) {
+                        x[e] = mp[gl + G * e];
+                        y[e] = mq[gl + G * e];
+                    }
 #pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    const bool in = live && gl + G * e < rows;
-                    x[e] = in ? x[e] : 0.0;
-                    y[e] = in ? y[e] : 0.0;
-                    al += x[e] * x[e];
-                    be += y[e] * y[e];
-                    ga += x[e] * y[e];
+                    for (int e = 0; e < E; ++e) {
+                        al += x[e] * x[e];
+                        be += y[e] * y[e];
+                        ga += x[e] * y[e];
+                    }
+                } else {
+                    // loads at clamped addresses, masked afterwards (no
+                    // branch per element)
+#pragma unroll
+                    for (int e = 0; e < E; ++e) {
+                        const int i = gl + G * e;
+                        const int ic = i < rows ? i : 0;
+                        x[e] = mp[ic];
+                        y[e] = mq[ic];
+                    }
+#pragma unroll
+                    for (int e = 0; e < E; ++e) {
+                        const bool in = live && gl + G * e < rows;
+                        x[e] = in ? x[e] : 0.0;
+                        y[e] = in ? y[e] : 0.0;
+                        al += x[e] * x[e];
+                        be += y[e] * y[e];
+                        ga += x[e] * y[e];
+                    }
                 }
                 if (G == 8) {
                     al = seg8_sum(al);
@@ -462,7 +483,7 @@ __device__ __forceinline__ int jacobi_groups(double *M, int rows, int ld, int n,
 #pragma unroll
                     for (int e = 0; e < E; ++e) {
                         const int i = gl + G * e;
-                        if (i < rows) {
+                        if (PAD || i < rows) {
                             mp[i] = cs * x[e] - sn * y[e];
                             mq[i] = sn * x[e] + cs * y[e];
                         }

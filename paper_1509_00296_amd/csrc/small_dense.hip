@@ -362,6 +362,10 @@ __device__ __forceinline__ void small_svd_body(double *M, double *smem, int l, c
     for (int idx = tid; idx < l * l; idx += NT) M[idx] = Gin[idx];
     __syncthreads();
     int sweeps = 0;
+    // column stride of M after the factorisation: l, or for 16 < l <= 128
+    // (M in LDS) the Jacobi groups' row capacity 32, 64 or 128, the rows past
+    // l held at zero
+    const int ldm = (l > LM && l <= 128) ? (l <= 32 ? 32 : (l <= 64 ? 64 : 128)) : l;
     if (NT >= 256 && l <= LM) {
         // wavefront 0 alone: register Cholesky, then the Jacobi
         if (wave == 0) {
@@ -378,8 +382,12 @@ __device__ __forceinline__ void small_svd_body(double *M, double *smem, int l, c
         for (int j = 0; j < l; ++j) maxdiag = fmax(maxdiag, M[j * l + j]);
         const double ptol = 4.0 * l * kU * maxdiag;
         if (l <= 128) {
-            // sig and coef serve as the step buffers here
-            chol_blk4<NT>(M, l, ptol, 0.0, coef, sig, nullptr);
+            // sig and coef serve as the step buffers here; R comes back with
+            // row stride ldm (zeros past column l - 1)
+            chol_blk4<NT>(M, l, ptol, 0.0, coef, sig, nullptr, ldm);
+            if (ldm == 32) sweeps = jacobi_groups<NT, 16, 2, true>(M, l, ldm, l, 60, &sh_rot);
+            else if (ldm == 64) sweeps = jacobi_groups<NT, 16, 4, true>(M, l, ldm, l, 60, &sh_rot);
+            else sweeps = jacobi_groups<NT, 16, 8, true>(M, l, ldm, l, 60, &sh_rot);
         } else {
             // right-looking in place: row j of R is scaled, then the trailing
             // upper triangle takes its rank-one update
@@ -397,22 +405,21 @@ __device__ __forceinline__ void small_svd_body(double *M, double *smem, int l, c
                 }
                 __syncthreads();
             }
+            for (int idx = tid; idx < l * l; idx += NT) {
+                const int j = idx / l, k = idx % l;
+                if (k < j) M[idx] = 0.0;
+            }
+            __syncthreads();
+            if (l <= 256) sweeps = jacobi_groups<NT, 16, 16>(M, l, l, l, 60, &sh_rot);
+            else sweeps = jacobi_groups<NT, 64, 16>(M, l, l, l, 60, &sh_rot);
         }
-        for (int idx = tid; idx < l * l; idx += NT) {
-            const int j = idx / l, k = idx % l;
-            if (k < j) M[idx] = 0.0;
-        }
-        __syncthreads();
-        if (l <= 128) sweeps = jacobi_groups<NT, 16, 8>(M, l, l, l, 60, &sh_rot);
-        else if (l <= 256) sweeps = jacobi_groups<NT, 16, 16>(M, l, l, l, 60, &sh_rot);
-        else sweeps = jacobi_groups<NT, 64, 16>(M, l, l, l, 60, &sh_rot);
         __syncthreads();
     }
 
     // singular values: column norms of the converged M, one 16-lane group
     // per column
     for (int j = tid / 16; j < l; j += NT / 16) {
-        const double *mj = M + (size_t)j * l;
+        const double *mj = M + (size_t)j * ldm;
         double s = 0.0;
         for (int i = tid % 16; i < l; i += 16) s += mj[i] * mj[i];
         s = seg16_sum(s);
@@ -444,7 +451,7 @@ __device__ __forceinline__ void small_svd_body(double *M, double *smem, int l, c
     for (int idx = tid; idx < l * l; idx += NT) {
         const int a = idx / l, i = idx % l;
         const double sa = sig[order[a]];
-        out.U[i + (size_t)a * l] = sa > 0.0 ? M[(size_t)order[a] * l + i] / sa : 0.0;
+        out.U[i + (size_t)a * l] = sa > 0.0 ? M[(size_t)order[a] * ldm + i] / sa : 0.0;
     }
     for (int a = tid; a < l; a += NT) out.sigma[a] = sig[order[a]];
     // Mm = sum_a coef_a u_a u_a^T = sum_c wc_c m_c m_c^T over the unsorted
@@ -464,7 +471,7 @@ __device__ __forceinline__ void small_svd_body(double *M, double *smem, int l, c
             for (int c = 0; c < l; ++c) {
                 const double wcc = wc[c];
                 if (wcc == 0.0) continue;
-                const double *mc = M + (size_t)c * l;
+                const double *mc = M + (size_t)c * ldm;
                 double xi[4], xj[4];
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
@@ -567,7 +574,10 @@ hipError_t launch_small_svd(int l, const double *G, double tau, const double *w,
                             const SmallSvdOut &out, double *work, int fuse_q, hipStream_t s)
 {
     if (l < 1 || l > 1024) return hipErrorInvalidValue;
-    size_t lds = l <= 128 ? (size_t)l * l * sizeof(double) : 0;
+    // M in LDS up to l = 128, columns padded to 32, 64 or 128 rows past l = LM
+    const int lm = l <= 8 ? 8 : 16;
+    const int ldm = (l > lm && l <= 128) ? (l <= 32 ? 32 : (l <= 64 ? 64 : 128)) : l;
+    size_t lds = l <= 128 ? (size_t)l * std::max(l, ldm) * sizeof(double) : 0;
     if (fuse_q && Q) lds = std::max(lds, 2 * (size_t)l * l * sizeof(double));
     if (l <= 8)
         hipLaunchKernelGGL((k_small_svd<T, 256, 8>), dim3(1), dim3(256), lds, s, l, G, tau, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, work, fuse_q);

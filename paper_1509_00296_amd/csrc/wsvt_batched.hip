@@ -120,28 +120,31 @@ __global__ void __launch_bounds__(kWB, 2) k_wsvt_batched(WsvtBatchArgs a)
         // 2. semidefinite Cholesky (coef and sig serve as its step buffers)
         double maxdiag = 0.0;
         for (int d = 0; d < s; ++d) maxdiag = fmax(maxdiag, M[d * s + d]);
-        chol_blk4<kWB, 2>(M, s, 4.0 * s * kU * maxdiag, 0.0, coef, sig, nullptr);
+        // column stride of the factor: the Jacobi groups' row capacity
+        // (gs x rows per lane), the rows past s held at zero
+        const int ldm = bucket == 0 ? (gs == 32 ? 64 : 48) : (bucket == 1 ? 64 : 96);
+        chol_blk4<kWB, 2>(M, s, 4.0 * s * kU * maxdiag, 0.0, coef, sig, nullptr, ldm);
         // 3. one-sided Jacobi on M = R^T
         //    (rows per lane E = ceil(bucket bound / gs), so no lane reads past
         //    its bucket)
         int sweeps;
         if (bucket == 0) {
-            if (gs == 8) sweeps = jacobi_groups<kWB, 8, 6>(M, s, s, s, 40, &sh_rot);
-            else if (gs == 32) sweeps = jacobi_groups<kWB, 32, 2>(M, s, s, s, 40, &sh_rot);
-            else sweeps = jacobi_groups<kWB, 16, 3>(M, s, s, s, 40, &sh_rot);
+            if (gs == 8) sweeps = jacobi_groups<kWB, 8, 6, true>(M, s, ldm, s, 40, &sh_rot);
+            else if (gs == 32) sweeps = jacobi_groups<kWB, 32, 2, true>(M, s, ldm, s, 40, &sh_rot);
+            else sweeps = jacobi_groups<kWB, 16, 3, true>(M, s, ldm, s, 40, &sh_rot);
         } else if (bucket == 1) {
-            if (gs == 8) sweeps = jacobi_groups<kWB, 8, 8>(M, s, s, s, 40, &sh_rot);
-            else if (gs == 32) sweeps = jacobi_groups<kWB, 32, 2>(M, s, s, s, 40, &sh_rot);
-            else sweeps = jacobi_groups<kWB, 16, 4>(M, s, s, s, 40, &sh_rot);
+            if (gs == 8) sweeps = jacobi_groups<kWB, 8, 8, true>(M, s, ldm, s, 40, &sh_rot);
+            else if (gs == 32) sweeps = jacobi_groups<kWB, 32, 2, true>(M, s, ldm, s, 40, &sh_rot);
+            else sweeps = jacobi_groups<kWB, 16, 4, true>(M, s, ldm, s, 40, &sh_rot);
         } else {
-            if (gs == 8) sweeps = jacobi_groups<kWB, 8, 12>(M, s, s, s, 40, &sh_rot);
-            else if (gs == 32) sweeps = jacobi_groups<kWB, 32, 3>(M, s, s, s, 40, &sh_rot);
-            else sweeps = jacobi_groups<kWB, 16, 6>(M, s, s, s, 40, &sh_rot);
+            if (gs == 8) sweeps = jacobi_groups<kWB, 8, 12, true>(M, s, ldm, s, 40, &sh_rot);
+            else if (gs == 32) sweeps = jacobi_groups<kWB, 32, 3, true>(M, s, ldm, s, 40, &sh_rot);
+            else sweeps = jacobi_groups<kWB, 16, 6, true>(M, s, ldm, s, 40, &sh_rot);
         }
         // 4. singular values, thresholds: P = sum_c (f_c / s_c) v_c v_c^T with
         //    v_c = m_c / s_c, i.e. coef_c = f_c / s_c^3 on the columns m_c
         for (int cc = tid / 16; cc < s; cc += kWB / 16) {
-            const double *mc = M + (size_t)cc * s;
+            const double *mc = M + (size_t)cc * ldm;
             double ss = 0.0;
             for (int i = tid % 16; i < s; i += 16) ss += mc[i] * mc[i];
             ss = seg16_sum(ss);
@@ -175,7 +178,7 @@ __global__ void __launch_bounds__(kWB, 2) k_wsvt_batched(WsvtBatchArgs a)
             const int cn = min(kWZ, nz - c0);
             for (int idx = tid; idx < cn * L; idx += kWB) {
                 const int cc = idx / L, i = idx - cc * L;
-                const double *mc = M + (size_t)nzc[c0 + cc] * s;
+                const double *mc = M + (size_t)nzc[c0 + cc] * ldm;
                 double z = 0.0;
                 if (tall) {
 #pragma unroll 8
@@ -192,7 +195,7 @@ __global__ void __launch_bounds__(kWB, 2) k_wsvt_batched(WsvtBatchArgs a)
                 double v = c0 ? (double)a.X[off + idx] : 0.0;
                 for (int cc = 0; cc < cn; ++cc) {
                     const int col = nzc[c0 + cc];
-                    const double *mc = M + (size_t)col * s;
+                    const double *mc = M + (size_t)col * ldm;
                     v += tall ? coef[col] * Z[cc * kWMaxLong + i] * mc[k] : coef[col] * mc[i] * Z[cc * kWMaxLong + k];
                 }
                 a.X[off + idx] = (float)v;
