@@ -42,6 +42,8 @@ struct frsvt_context {
     std::vector<uint64_t> wb_key;
     // per-iteration status event of the RPCA host loop
     hipEvent_t ev_iter = nullptr;
+    void *host_iter = nullptr;       // coherent mapped host words of the RPCA loop
+    void *host_iter_dev = nullptr;   // its device address
     // tracing: event pairs around launches, aggregated per kernel class
     bool tracing = false;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> recs;
@@ -1122,7 +1124,11 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
     bool converged = false;
     double resid = 0.0, mu_last = mu;
     Core<T> c{};
-    int *hst = (int *)h->pinned;
+    if (!h->host_iter) {
+        CK(hipHostMalloc(&h->host_iter, 256, hipHostMallocCoherent | hipHostMallocMapped));
+        CK(hipHostGetDevicePointer(&h->host_iter_dev, h->host_iter, 0));
+    }
+    volatile int *hst = (volatile int *)h->host_iter;
     for (it = 0; it < op.max_iter; ++it) {
         const double mu_next = std::min(op.rho * mu, mu_bar);
         const T *Yc = Ybuf[it & 1];
@@ -1206,13 +1212,12 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
         ra.zpart = zp;
         int nz = 0;
         CKT(FRSVT_K_EPILOGUE, launch_recon<T>(kEpi, ra, &nz, s));
-        CKT(FRSVT_K_REDUCE, launch_reduce<double>(zp, 1, nz, zsum, s));
-        // status words (rank, residual) to the host, marked by an event; the
-        // host waits for that event only, so the GPU keeps working on the
-        // speculative sketch below while the host reads them and enqueues
-        // the next iteration.
-        CK(hipMemcpyAsync(hst, h->dstatus, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
-        CK(hipMemcpyAsync(hst + 8, zsum, sizeof(double), hipMemcpyDeviceToHost, s));
+        // status words (rank, residual) written by the last kernel straight
+        // to mapped host memory, marked by an event; the host waits for that
+        // event only, so the GPU keeps working on the speculative sketch
+        // below while the host reads them and enqueues the next iteration.
+        int *hdev = (int *)h->host_iter_dev;
+        CKT(FRSVT_K_REDUCE, launch_finish_iter(zp, nz, h->dstatus, 8, hdev, (double *)(hdev + 8), s));
         if (!h->ev_iter) CK(hipEventCreateWithFlags(&h->ev_iter, hipEventDisableTiming));
         CK(hipEventRecord(h->ev_iter, s));
         // The next sketch needs only the next A and its Philox counter; it
@@ -1231,7 +1236,9 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
         CK(hipEventSynchronize(h->ev_iter));
         const int r = hst[0];
         double zz;
-        memcpy(&zz, hst + 8, sizeof(double));
+        const int zw[2] = {hst[8], hst[9]};
+        memcpy(&zz, zw, sizeof(double));
+        (void)zsum;
         resid = std::sqrt(zz) / normF;
         if (stats && it < 64) {
             stats->ranks[it] = r;
@@ -1504,6 +1511,7 @@ int frsvt_destroy(frsvt_handle h)
     }
     for (auto e : h->pool) (void)hipEventDestroy(e);
     if (h->ev_iter) (void)hipEventDestroy(h->ev_iter);
+    if (h->host_iter) (void)hipHostFree(h->host_iter);
     if (h->wb_exec) (void)hipGraphExecDestroy(h->wb_exec);
     if (h->wb_capture) (void)hipStreamDestroy(h->wb_capture);
     if (h->wb_queue) (void)hipFree(h->wb_queue);

@@ -55,6 +55,11 @@ hipError_t launch_long(const LongPlan &plan, int mode, const LongArgs<T> &args, 
 // out[j] = sum_{g < nparts} part[g * count + j], fixed order.
 template <typename T>
 hipError_t launch_reduce(const T *part, int64_t count, int nparts, T *out, hipStream_t s);
+// sum of nparts doubles (the order of launch_reduce with count 1) and the
+// first nstatus status words, written to mapped host memory (device
+// pointers host_status, host_z)
+hipError_t launch_finish_iter(const double *part, int nparts, const int *status, int nstatus,
+                              int *host_status, double *host_z, hipStream_t s);
 
 // ------------------------------------------------------ one-workgroup CholeskyQR
 // Q = orth([Qt, Y]) with Qt (mh x rp) orthonormal and Y (mh x c):

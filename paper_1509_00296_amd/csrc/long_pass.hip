@@ -839,6 +839,35 @@ __global__ void __launch_bounds__(1024) k_reduce_scalar(const T *part, int64_t c
     }
 }
 
+// The RPCA iteration's last step: the residual partials summed as
+// k_reduce_scalar does (same order, same result), written with the first
+// nstatus status words straight to mapped host memory, so that the host
+// reads them after an event without a copy on the stream.
+__global__ void __launch_bounds__(1024) k_finish_iter(const double *part, int nparts, const int *status,
+                                                      int nstatus, int *host_status, double *host_z)
+{
+    __shared__ double red[16];
+    double s = 0.0;
+    for (int g = threadIdx.x; g < nparts; g += 1024) s += part[g];
+    s = wave_sum(s);
+    if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < 16; ++w) t += red[w];
+        for (int i = 0; i < nstatus; ++i) host_status[i] = status[i];
+        *host_z = t;
+        __threadfence_system();
+    }
+}
+
+hipError_t launch_finish_iter(const double *part, int nparts, const int *status, int nstatus,
+                              int *host_status, double *host_z, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finish_iter, dim3(1), dim3(1024), 0, s, part, nparts, status, nstatus, host_status, host_z);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_reduce(const T *part, int64_t count, int nparts, T *out, hipStream_t s)
 {
