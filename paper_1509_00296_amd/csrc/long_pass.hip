@@ -76,7 +76,7 @@ LongPlan long_plan(int mh, int64_t nh, int c, int elem_bytes, int mode, int num_
              (needs_q ? (size_t)mh * p.cmv * elem_bytes + (size_t)slices * kKT * p.cmv * elem_bytes : 0);
     p.vec = 0;
     // transposed fast form: LDS = tile + V (or the Gaussian chunk) + phase-1 partials
-    p.ldst = (size_t)p.mhp * ld * elem_bytes +
+    p.ldst = (size_t)(p.mhp + 1) * ld * elem_bytes +
              (size_t)(mode == kSketch ? 12 : 1) * kKT * p.cm * elem_bytes +
              (needs_q ? (size_t)4 * kKT * p.cm * elem_bytes : 0);
     return p;
@@ -510,7 +510,7 @@ __device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, uint3
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
 
-template <typename T, int MODE, int NB>
+template <typename T, int MODE, int NB, int RING, int NJ>
 __global__ void __launch_bounds__(kThreads) k_long_tr(LongArgs<T> a, uint32_t span_bytes)
 {
     using M = LpMfma<T>;
@@ -519,7 +519,6 @@ __global__ void __launch_bounds__(kThreads) k_long_tr(LongArgs<T> a, uint32_t sp
     constexpr bool kPhase2 = (MODE != kProject);
     constexpr int LD = M::kLD;
     constexpr int VLD = 16 * NB;
-    constexpr int NJ = 16;            // row groups of 16 per thread: mhp <= 256
     constexpr int GCH = 12;           // tiles per Gaussian chunk (sketch)
     constexpr uint32_t ESZ = sizeof(T);
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -528,7 +527,8 @@ __global__ void __launch_bounds__(kThreads) k_long_tr(LongArgs<T> a, uint32_t sp
     const int nrb = mhp >> 4;
     const int nj = nrb;               // row groups present (i_j = (tid >> 4) + 16 j < mhp)
     T *sT = reinterpret_cast<T *>(smem_raw);
-    T *sV = sT + (size_t)mhp * LD;
+    // row mhp of the tile takes the stores of row groups past mhp
+    T *sV = sT + (size_t)(mhp + 1) * LD;
     T *sZp = sV + (size_t)(MODE == kSketch ? GCH : 1) * kKT * VLD;
 
     const __amdgpu_buffer_rsrc_t rsrc =
@@ -552,17 +552,21 @@ __global__ void __launch_bounds__(kThreads) k_long_tr(LongArgs<T> a, uint32_t sp
         for (int b = 0; b < NB; ++b) acc[r][b] = V4{0, 0, 0, 0};
     double gacc[4] = {0.0, 0.0, 0.0, 0.0};
 
-    T pre[NJ], cur[NJ];
-    auto load_tile = [&](int tile) {
+    // Register ring of RING tiles: while one is consumed, the loads of the
+    // next RING - 1 are in flight.
+    T pa[NJ], pb[NJ];
+    auto load_tile = [&](T (&pre)[NJ], int tile) {
         const int64_t k0 = (int64_t)tile * kKT;
         const bool kin = k0 + kk_l < a.nh;
         const uint32_t vt = kin ? v0 + (uint32_t)k0 * ESZ : kOob;
+        // every row group is loaded, groups past mhp and tiles past the end
+        // through the out-of-range offset, so that the loads are
+        // unconditional and the waits for them exact
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
-            if (j < nj) {
-                const uint32_t vo = (r0 + 16 * j < mh) ? vt : kOob;
-                pre[j] = buf_load<T>(rsrc, vo, (uint32_t)j * rowstep);
-            }
+            const bool jin = j < nj;
+            const uint32_t vo = (jin && r0 + 16 * j < mh) ? vt : kOob;
+            pre[j] = buf_load<T>(rsrc, vo, jin ? (uint32_t)j * rowstep : 0u);
         }
     };
     auto draw = [&](int t0) {
@@ -580,27 +584,26 @@ __global__ void __launch_bounds__(kThreads) k_long_tr(LongArgs<T> a, uint32_t sp
             dst[1] = (2 * j + 1 < c) ? T(z1) : T(0);
         }
     };
-    if ((int)blockIdx.x < a.ntiles) load_tile(blockIdx.x);
+    load_tile(pa, blockIdx.x);
+    // issue order pa, pb kept (the waits in the loop count on it)
+    __builtin_amdgcn_sched_barrier(0);
+    if (RING > 1) load_tile(pb, blockIdx.x + gridDim.x);
     if (MODE == kSketch) draw(0);
 
-    int it = 0;
-    for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x, ++it) {
+    auto process = [&](T (&pre)[NJ], int tile, int it) {
         const int64_t k0 = (int64_t)tile * kKT;
         const int kval = (int)min((int64_t)kKT, a.nh - k0);
         if (MODE == kSketch && it > 0 && it % GCH == 0) draw(it);
+        // branch-free over the NJ row groups (groups past nj hold zeros)
 #pragma unroll
-        for (int j = 0; j < NJ; ++j)
-            if (j < nj) {
-                cur[j] = pre[j];
-                sT[(r0 + 16 * j) * LD + kk_l] = cur[j];
-            }
+        for (int j = 0; j < NJ; ++j) sT[(j < nj ? r0 + 16 * j : mhp) * LD + kk_l] = pre[j];
         if (MODE == kVecMul) {
             for (int idx = tid; idx < kKT * VLD; idx += kThreads) {
                 const int kk = idx % kKT, j = idx / kKT;
                 sV[kk * VLD + j] = (kk < kval && j < c) ? a.V[(k0 + kk) + (int64_t)j * a.ldv] : T(0);
             }
         }
-        if (tile + (int)gridDim.x < a.ntiles) load_tile(tile + gridDim.x);
+        if (!kNeedQ) load_tile(pre, tile + RING * gridDim.x);
 
         if (kNeedQ) {
             // phase 1 from registers: rows r0 + 16 j, two accumulation chains
@@ -614,10 +617,12 @@ __global__ void __launch_bounds__(kThreads) k_long_tr(LongArgs<T> a, uint32_t sp
             for (int j = 0; j < NJ; j += 2) {
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
-                    if (j < nj) z0[b] = M::mma(cur[j], qreg[j][b], z0[b]);
-                    if (j + 1 < nj) z1[b] = M::mma(cur[j + 1], qreg[j + 1][b], z1[b]);
+                    z0[b] = M::mma(pre[j], qreg[j][b], z0[b]);
+                    if (j + 1 < NJ) z1[b] = M::mma(pre[j + 1], qreg[j + 1][b], z1[b]);
                 }
             }
+            // the registers are free once phase 1 has read them
+            load_tile(pre, tile + RING * gridDim.x);
 #pragma unroll
             for (int b = 0; b < NB; ++b)
 #pragma unroll
@@ -669,6 +674,14 @@ __global__ void __launch_bounds__(kThreads) k_long_tr(LongArgs<T> a, uint32_t sp
             }
         }
         __syncthreads();
+    };
+    // One exit: the second tile of a pair is processed even past the end
+    // (its loads return zeros, its outputs are masked), so that every
+    // iteration leaves the loads in the same order.
+    int it = 0;
+    for (int tile = blockIdx.x; tile < a.ntiles; tile += RING * gridDim.x) {
+        process(pa, tile, it++);
+        if (RING > 1) process(pb, tile + gridDim.x, it++);
     }
     if (MODE == kProject) {
         double *gp = a.Gpart + (size_t)blockIdx.x * c * c;
@@ -732,10 +745,16 @@ static hipError_t launch_long_cm(const LongPlan &p, const LongArgs<T> &a, hipStr
 template <typename T, int MODE>
 static hipError_t launch_long_tr(const LongPlan &p, const LongArgs<T> &a, uint32_t span, hipStream_t s)
 {
-    if (p.cm == 16)
-        hipLaunchKernelGGL((k_long_tr<T, MODE, 1>), dim3(p.grid), dim3(kThreads), p.ldst, s, a, span);
+    // NJ row groups of 16 per thread: 8 for mhp <= 128, else 16
+    const bool nj8 = p.mhp <= 128;
+    if (p.cm == 16 && nj8)
+        hipLaunchKernelGGL((k_long_tr<T, MODE, 1, 2, 8>), dim3(p.grid), dim3(kThreads), p.ldst, s, a, span);
+    else if (p.cm == 16)
+        hipLaunchKernelGGL((k_long_tr<T, MODE, 1, 2, 16>), dim3(p.grid), dim3(kThreads), p.ldst, s, a, span);
+    else if (nj8)
+        hipLaunchKernelGGL((k_long_tr<T, MODE, 2, 1, 8>), dim3(p.grid), dim3(kThreads), p.ldst, s, a, span);
     else
-        hipLaunchKernelGGL((k_long_tr<T, MODE, 2>), dim3(p.grid), dim3(kThreads), p.ldst, s, a, span);
+        hipLaunchKernelGGL((k_long_tr<T, MODE, 2, 1, 16>), dim3(p.grid), dim3(kThreads), p.ldst, s, a, span);
     return hipGetLastError();
 }
 
@@ -784,42 +803,47 @@ template hipError_t launch_long<float>(const LongPlan &, int, const LongArgs<flo
 
 // ===========================================================================
 // Fixed-order reductions: out[j] = sum_g part[g * count + j].
-//   Columns: a 64 x 16 thread block; thread (x, y) sums the parts g = y,
-//   y + 16, ... of output x in eight interleaved partial sums (added in a
-//   fixed tree); the 16 slices are then added in order.
+//   Columns: a W x (1024 / W) thread block; thread (x, y) sums the parts
+//   g = y, y + S, ... (S = 1024 / W) of output x in eight interleaved partial
+//   sums (added in a fixed tree); the S slices are then added by a pairwise
+//   tree in LDS.  W is 64, 16 or 4 by the output count, so that narrow
+//   outputs over many parts still spread over enough workgroups and each
+//   thread issues only a batch or two of loads.
 //   Scalars (count small): all 1024 threads stride over the parts, then a
 //   fixed tree.  Both orders are independent of timing, so results repeat
 //   bit for bit.
 // ===========================================================================
-template <typename T>
+template <typename T, int W>
 __global__ void __launch_bounds__(1024) k_reduce_cols(const T *part, int64_t count, int nparts, T *out)
 {
-    __shared__ T red[16][65];
-    const int x = threadIdx.x % 64, y = threadIdx.x / 64;
-    const int64_t j = (int64_t)blockIdx.x * 64 + x;
-    // eight independent partial sums (parts g + 16 k), their loads issued
+    constexpr int S = 1024 / W;
+    __shared__ T red[S][W + 1];
+    const int x = threadIdx.x % W, y = threadIdx.x / W;
+    const int64_t j = (int64_t)blockIdx.x * W + x;
+    // eight independent partial sums (parts g + S k), their loads issued
     // together
     T acc[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) acc[k] = T(0);
     if (j < count) {
         int g = y;
-        for (; g + 7 * 16 < nparts; g += 8 * 16) {
+        for (; g + 7 * S < nparts; g += 8 * S) {
             T v[8];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) v[k] = part[(int64_t)(g + 16 * k) * count + j];
+            for (int k = 0; k < 8; ++k) v[k] = part[(int64_t)(g + S * k) * count + j];
 #pragma unroll
             for (int k = 0; k < 8; ++k) acc[k] += v[k];
         }
-        for (; g < nparts; g += 16) acc[0] += part[(int64_t)g * count + j];
+        for (; g < nparts; g += S) acc[0] += part[(int64_t)g * count + j];
     }
     red[y][x] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     __syncthreads();
-    if (y == 0 && j < count) {
-        T t = T(0);
-        for (int yy = 0; yy < 16; ++yy) t += red[yy][x];
-        out[j] = t;
+#pragma unroll
+    for (int h = S / 2; h > 0; h >>= 1) {
+        if (y < h) red[y][x] += red[y + h][x];
+        __syncthreads();
     }
+    if (y == 0 && j < count) out[j] = red[0][x];
 }
 
 template <typename T>
@@ -874,8 +898,15 @@ hipError_t launch_reduce(const T *part, int64_t count, int nparts, T *out, hipSt
     if (count <= 0) return hipSuccess;
     if (count <= 8)
         hipLaunchKernelGGL((k_reduce_scalar<T>), dim3((unsigned)count), dim3(1024), 0, s, part, count, nparts, out);
+    else if (count >= 64 * 256)
+        hipLaunchKernelGGL((k_reduce_cols<T, 64>), dim3((unsigned)((count + 63) / 64)), dim3(1024), 0, s, part, count,
+                           nparts, out);
+    else if (count >= 16 * 64)
+        hipLaunchKernelGGL((k_reduce_cols<T, 16>), dim3((unsigned)((count + 15) / 16)), dim3(1024), 0, s, part, count,
+                           nparts, out);
     else
-        hipLaunchKernelGGL((k_reduce_cols<T>), dim3((unsigned)((count + 63) / 64)), dim3(1024), 0, s, part, count, nparts, out);
+        hipLaunchKernelGGL((k_reduce_cols<T, 4>), dim3((unsigned)((count + 3) / 4)), dim3(1024), 0, s, part, count,
+                           nparts, out);
     return hipGetLastError();
 }
 template hipError_t launch_reduce<double>(const double *, int64_t, int, double *, hipStream_t);
