@@ -228,6 +228,7 @@ struct CoreBuffers {
     T *Ypart, *Y, *Q, *Bt, *QM, *Om, *Z, *gpart_t, *Qtmp;
     double *Gpart, *G, *U, *Mm, *sigma, *R, *gpart_d, *jwork;
     int *nullc;
+    size_t ypart_cap;   // elements of Ypart
 };
 
 template <typename T>
@@ -239,6 +240,7 @@ size_t carve_core(Carver &cv, const Orient &o, int l, int cnew, int num_cu, Core
     const int grid = 2 * num_cu;
     const int cmax = std::max(l, 1);
     b.Ypart = cv.take<T>((size_t)grid * mh * cmax);
+    b.ypart_cap = (size_t)grid * mh * cmax;
     b.Y = cv.take<T>((size_t)mh * cmax);
     b.Q = cv.take<T>((size_t)mh * cmax);
     b.Qtmp = cv.take<T>((size_t)mh * cmax);
@@ -1210,6 +1212,24 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
         ra.mu_next = mu_next;
         ra.lam = lambda;
         ra.zpart = zp;
+        // The next sketch needs only the next A and its Philox counter, with
+        // p new samples (the width of every later sketch unless r + p > mh).
+        // Where the rows of A are the long index, the epilogue forms it from
+        // the values of A it writes (partials per row block); otherwise it
+        // is a pass of its own below.
+        Core<T> cn = c;
+        cn.counter = (uint64_t)(it + 1);
+        cn.cnew = std::min(op.p, mh);
+        const bool next_sketch = op.use_frsvt && it + 1 < op.max_iter && cn.cnew > 0 && long_path_ok(mh, cn.cnew);
+        const int64_t rblocks = recon_row_blocks(m);
+        const bool fuse_sketch = next_sketch && std::is_same<T, double>::value && o.trans && cn.cnew <= 8 &&
+                                 (size_t)rblocks * (size_t)n * (size_t)cn.cnew <= b.ypart_cap;
+        if (fuse_sketch) {
+            ra.ysk = b.Ypart;
+            ra.csk = cn.cnew;
+            ra.seed = cn.seed;
+            ra.counter = cn.counter;
+        }
         int nz = 0;
         CKT(FRSVT_K_EPILOGUE, launch_recon<T>(kEpi, ra, &nz, s));
         // status words (rank, residual) written by the last kernel straight
@@ -1220,18 +1240,15 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
         CKT(FRSVT_K_REDUCE, launch_finish_iter(zp, nz, h->dstatus, 8, hdev, (double *)(hdev + 8), s));
         if (!h->ev_iter) CK(hipEventCreateWithFlags(&h->ev_iter, hipEventDisableTiming));
         CK(hipEventRecord(h->ev_iter, s));
-        // The next sketch needs only the next A and its Philox counter; it
-        // is enqueued before the host waits for this iteration's rank, with
-        // p new samples (the width of every later sketch unless r + p > mh).
+        // the next sketch is completed (or run) before the host waits for
+        // this iteration's rank
         spec_cnew = 0;
-        if (op.use_frsvt && it + 1 < op.max_iter) {
-            Core<T> cn = c;
-            cn.counter = (uint64_t)(it + 1);
-            cn.cnew = std::min(op.p, mh);
-            if (cn.cnew > 0 && long_path_ok(mh, cn.cnew)) {
-                if ((rc = sketch_stage<T>(h, cn, b))) return rc;
-                spec_cnew = cn.cnew;
-            }
+        if (fuse_sketch) {
+            CKT(FRSVT_K_REDUCE, launch_reduce<T>(b.Ypart, (int64_t)mh * cn.cnew, (int)rblocks, b.Y, s));
+            spec_cnew = cn.cnew;
+        } else if (next_sketch) {
+            if ((rc = sketch_stage<T>(h, cn, b))) return rc;
+            spec_cnew = cn.cnew;
         }
         CK(hipEventSynchronize(h->ev_iter));
         const int r = hst[0];

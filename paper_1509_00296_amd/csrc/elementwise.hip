@@ -3,6 +3,7 @@
 #include "internal.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace frk {
 
@@ -13,8 +14,63 @@ namespace frk {
 // ===========================================================================
 constexpr int kReconCols = 16;
 bool recon_ok(int c) { return c >= 0 && c <= 32; }
+int64_t recon_row_blocks(int64_t rows) { return (rows + kThreads - 1) / kThreads; }
 
-template <typename T, int MODE, int CM>
+// With SK (kEpi, double), the workgroup also forms its part of the next
+// iteration's sketch Y = Ahat Omega (Ahat = A^T, so a row of A is a long
+// index k): for its 16 columns i and j < csk, the sum over its rows k of
+// Anext(k, i) Omega(k, j).  Per wavefront that is Omega^T (16 x 64, rows of
+// Omega past csk zero) times Anext (64 x 16) on the matrix cores, both
+// operands moved through LDS from the lane-per-row layout of the epilogue to
+// the 16-lanes-per-row operand layout; the four wavefronts' products are
+// added in a fixed order.
+__device__ __forceinline__ void sketch_rows(const ReconArgs<double> &a, int64_t pr, double (&an)[16], double *sW)
+{
+    const int lane = threadIdx.x % kWave;
+    // Omega row pr, columns j < csk (the sketch pass's draw: pair p of row k
+    // gives columns 2p and 2p + 1)
+    double om[8];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        double z0 = 0.0, z1 = 0.0;
+        if (2 * p < a.csk && pr < a.rows) gaussian_pair(a.seed, a.counter, (uint32_t)pr, (uint32_t)p, z0, z1);
+        om[2 * p] = z0;
+        om[2 * p + 1] = (2 * p + 1 < a.csk) ? z1 : 0.0;
+    }
+    constexpr int LDW = 17;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) sW[lane * LDW + j] = om[j];
+    __syncthreads();
+    const int ro = lane >> 4, co = lane & 15;
+    double aop[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) aop[s] = co < 8 ? sW[(4 * s + ro) * LDW + co] : 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 16; ++j) sW[lane * LDW + j] = an[j];
+    __syncthreads();
+    typedef __attribute__((__vector_size__(4 * sizeof(double)))) double d4;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 16; ++s)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[s], sW[(4 * s + ro) * LDW + co], acc, 0, 0, 0);
+    __syncthreads();
+    // D(j, i): lane holds j = ro + 4 r, i = co; rows j < 8 kept
+    double *sC = sW - (threadIdx.x / kWave) * 64 * LDW;   // start of the workgroup's area
+    const int w = threadIdx.x / kWave;
+    sC[(w * 8 + ro) * 16 + co] = acc[0];
+    sC[(w * 8 + ro + 4) * 16 + co] = acc[1];
+    __syncthreads();
+    if (threadIdx.x < 128) {
+        const int j = threadIdx.x >> 4, i = threadIdx.x & 15;
+        const int64_t pc = (int64_t)blockIdx.y * kReconCols + i;
+        const double t = ((sC[(0 * 8 + j) * 16 + i] + sC[(1 * 8 + j) * 16 + i]) + sC[(2 * 8 + j) * 16 + i]) +
+                         sC[(3 * 8 + j) * 16 + i];
+        if (j < a.csk && pc < a.cols) a.ysk[(int64_t)blockIdx.x * a.cols * a.csk + pc + (int64_t)j * a.cols] = t;
+    }
+}
+
+template <typename T, int MODE, int CM, bool SK = false>
 __global__ void __launch_bounds__(kThreads) k_recon(ReconArgs<T> a)
 {
     __shared__ T sFC[kReconCols][CM];
@@ -32,30 +88,56 @@ __global__ void __launch_bounds__(kThreads) k_recon(ReconArgs<T> a)
     for (int cc = 0; cc < CM; ++cc) fr[cc] = (cc < c && pr < a.rows && a.FR) ? a.FR[pr + (int64_t)cc * a.ldfr] : T(0);
     __syncthreads();
     double zz = 0.0;
+    T anv[SK ? kReconCols : 1];
+#pragma unroll
+    for (int j = 0; j < (SK ? kReconCols : 1); ++j) anv[j] = T(0);
     if (pr < a.rows) {
         const T mu = (T)a.mu, inv_mu = (T)(1.0 / a.mu), inv_mu_next = (T)(1.0 / a.mu_next);
         const T thr = (T)(a.lam / a.mu);
-        for (int j = 0; j < kReconCols; ++j) {
-            const int64_t pc = pc0 + j;
-            if (pc >= a.cols) break;
-            T L = T(0);
-            if (a.Lin) {
-                L = a.Lin[pr + pc * a.ldlin];
-            } else {
+        const int ncol = (int)min((int64_t)kReconCols, a.cols - pc0);
+        // the loads of all the columns are issued first, so that their
+        // latencies overlap; then the arithmetic and the stores
+        // (columns past the end load the last column again: unconditional
+        // loads, nothing stored for them)
+        T lv[kReconCols], ov[kReconCols], yv[kReconCols];
+        if (MODE != kRecon) {
+#pragma unroll
+            for (int j = 0; j < kReconCols; ++j) {
+                const int64_t pc = pc0 + min(j, ncol - 1);
+                ov[j] = a.O[pr + pc * a.ldo];
+                yv[j] = a.Y[pr + pc * a.ldy];
+            }
+        }
+        if (a.Lin) {
+#pragma unroll
+            for (int j = 0; j < kReconCols; ++j) lv[j] = a.Lin[pr + (pc0 + min(j, ncol - 1)) * a.ldlin];
+        } else {
+#pragma unroll
+            for (int j = 0; j < kReconCols; ++j) {
+                T L = T(0);
 #pragma unroll
                 for (int cc = 0; cc < CM; ++cc) L += fr[cc] * sFC[j][cc];
+                lv[j] = L;
             }
+        }
+#pragma unroll
+        for (int j = 0; j < kReconCols; ++j) {
+            if (j >= ncol) break;
+            const int64_t pc = pc0 + j;
+            const T L = lv[j];
             if (MODE == kRecon) {
                 a.X[pr + pc * a.ldx] = L;
             } else {
-                const T o = a.O[pr + pc * a.ldo];
-                const T y = a.Y[pr + pc * a.ldy];
+                const T o = ov[j];
+                const T y = yv[j];
                 const T sv = soft_shrink(o - L + y * inv_mu, thr);
                 if (MODE == kEpi) {
                     const T z = o - L - sv;
                     const T yn = y + mu * z;
                     a.Ynext[pr + pc * a.ldyn] = yn;
-                    a.Anext[pr + pc * a.ldan] = o - sv + yn * inv_mu_next;
+                    const T an = o - sv + yn * inv_mu_next;
+                    a.Anext[pr + pc * a.ldan] = an;
+                    if constexpr (SK) anv[j] = an;
                     zz += (double)z * (double)z;
                 } else {
                     a.X[pr + pc * a.ldx] = L;
@@ -63,6 +145,10 @@ __global__ void __launch_bounds__(kThreads) k_recon(ReconArgs<T> a)
                 }
             }
         }
+    }
+    if constexpr (SK) {
+        __shared__ double sW[kThreads / kWave][64 * 17];
+        sketch_rows(a, pr, anv, sW[threadIdx.x / kWave]);
     }
     if (MODE == kEpi) {
         zz = wave_sum(zz);
@@ -79,6 +165,16 @@ __global__ void __launch_bounds__(kThreads) k_recon(ReconArgs<T> a)
 template <typename T, int MODE>
 static hipError_t launch_recon_cm(const ReconArgs<T> &a, dim3 grid, hipStream_t s)
 {
+    if constexpr (MODE == kEpi && std::is_same<T, double>::value) {
+        if (a.ysk) {
+            if (a.c <= 8) hipLaunchKernelGGL((k_recon<T, MODE, 8, true>), grid, dim3(kThreads), 0, s, a);
+            else if (a.c <= 16) hipLaunchKernelGGL((k_recon<T, MODE, 16, true>), grid, dim3(kThreads), 0, s, a);
+            else hipLaunchKernelGGL((k_recon<T, MODE, 32, true>), grid, dim3(kThreads), 0, s, a);
+            return hipGetLastError();
+        }
+    } else {
+        if (a.ysk) return hipErrorInvalidValue;
+    }
     if (a.c <= 8) hipLaunchKernelGGL((k_recon<T, MODE, 8>), grid, dim3(kThreads), 0, s, a);
     else if (a.c <= 16) hipLaunchKernelGGL((k_recon<T, MODE, 16>), grid, dim3(kThreads), 0, s, a);
     else hipLaunchKernelGGL((k_recon<T, MODE, 32>), grid, dim3(kThreads), 0, s, a);
@@ -89,6 +185,7 @@ template <typename T>
 hipError_t launch_recon(int mode, const ReconArgs<T> &a, int *nparts, hipStream_t s)
 {
     if (!recon_ok(a.c)) return hipErrorInvalidValue;
+    if (a.ysk && (mode != kEpi || a.csk < 1 || a.csk > 8)) return hipErrorInvalidValue;
     dim3 grid((unsigned)((a.rows + kThreads - 1) / kThreads), (unsigned)((a.cols + kReconCols - 1) / kReconCols));
     if (nparts) *nparts = (int)(grid.x * grid.y);
     if (mode == kRecon) return launch_recon_cm<T, kRecon>(a, grid, s);

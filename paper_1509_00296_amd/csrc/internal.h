@@ -122,8 +122,17 @@ struct ReconArgs {
     double *zpart;        // [grid] partial sums of z^2
     const T *Lin;         // when set, L is read from here instead of FR FC^T
     int64_t ldlin;
+    // kEpi, T = double, rows = the long index: when ysk is set, the Gaussian
+    // sketch of Anext for the next iteration is accumulated alongside,
+    // ysk[blockIdx.x][i + j * cols] = sum over the workgroup's rows k of
+    // Anext(k, i) Omega(k, j), j < csk <= 8, Omega drawn from (seed, counter)
+    // as the sketch pass draws it.
+    T *ysk;
+    int csk;
+    uint64_t seed, counter;
 };
 bool recon_ok(int c);
+int64_t recon_row_blocks(int64_t rows);   // grid.x of the epilogue launch
 template <typename T>
 hipError_t launch_recon(int mode, const ReconArgs<T> &a, int *nparts, hipStream_t s);
 

@@ -166,12 +166,14 @@ def test_wsvt_matches_oracle(fr, orc):
     assert _rel(X.cpu().numpy(), Xo) <= 1e-10
 
 
-@pytest.mark.parametrize("mode", ["frsvt", "exact"])
-def test_rpca_small_matches_oracle(fr, orc, mode):
+@pytest.mark.parametrize("mode,m,n", [("frsvt", 3000, 60), ("exact", 3000, 60), ("frsvt", 60, 3000)])
+def test_rpca_small_matches_oracle(fr, orc, mode, m, n):
+    """Tall (the next sketch formed inside the epilogue) and wide (the next
+    sketch as a pass of its own) observations."""
     from paper_1509_00296_amd import synth
-    _say(f"case rpca {mode} 3000x60")
-    O, Lgt, _ = synth.rpca(seed=3, m=3000, n=60, rank=3, frac=0.10)
-    lam = 1.0 / np.sqrt(3000)
+    _say(f"case rpca {mode} {m}x{n}")
+    O, Lgt, _ = synth.rpca(seed=3, m=m, n=n, rank=3, frac=0.10)
+    lam = 1.0 / np.sqrt(max(m, n))
     res = fr.rpca_ialm(_gpu(O), lam, use_frsvt=(mode == "frsvt"), seed=17)
     out = orc.rpca_ialm(O, lam, mode=mode, p=5, q=1, seed=17)
     assert res.iters == out["iters"]
