@@ -1086,11 +1086,13 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
 
     // workspace: A, the FRSVT core at its largest width, exact factors, z partials
     const int lmax = op.use_frsvt ? std::min(mh, std::max(l0, mh)) : mh;
+    // residual partials: one per epilogue workgroup (256 x 16 elements)
+    const size_t zcap = (size_t)((m + 255) / 256) * (size_t)((n + 15) / 16);
     auto layout = [&](Carver &cv, T **A, CoreBuffers<T> &b, T **Qt, double **zp, T **Lx,
                       double **zsum) {
         *A = cv.take<T>((size_t)m * n);
         *Qt = cv.take<T>((size_t)mh * mh);
-        *zp = cv.take<double>((size_t)1 << 20);
+        *zp = cv.take<double>(zcap);
         *zsum = cv.take<double>(4);
         *Lx = cv.take<T>((size_t)m * n);
         if (op.use_frsvt) carve_core<T>(cv, o, lmax, lmax, h->num_cu, b);
