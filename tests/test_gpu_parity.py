@@ -61,6 +61,8 @@ CASES = [
     (64, 64, 12, 0.1, 3.0, 16, 8, 2),        # square, l > rank
     (2000, 33, 3, 0.02, 1.5, 3, 2, 1),       # odd short side
     (700, 250, 20, 0.01, 1.0, 20, 12, 1),    # l = 32 (widest one-pass basis)
+    (3000, 100, 8, 0.02, 2.0, 14, 6, 1),     # transposed passes: 8 row groups, 32 columns
+    (20000, 120, 6, 0.02, 4.0, 6, 4, 1),     # transposed passes: 2-3 tiles per workgroup
 ]
 
 
