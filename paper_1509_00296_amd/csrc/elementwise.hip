@@ -96,7 +96,10 @@ __global__ void __launch_bounds__(kThreads) k_recon(ReconArgs<T> a)
         const T thr = (T)(a.lam / a.mu);
         const int ncol = (int)min((int64_t)kReconCols, a.cols - pc0);
         // the loads of all the columns are issued first, so that their
-        // latencies overlap; then the arithmetic and the stores
+        // latencies overlap; then the arithmetic and the stores.  O, Y and
+        // the next multiplier are streamed (non-temporal: they are not read
+        // again before the next epilogue), so that the caches keep the next
+        // A for the passes that read it
         // (columns past the end load the last column again: unconditional
         // loads, nothing stored for them)
         T lv[kReconCols], ov[kReconCols], yv[kReconCols];
@@ -104,8 +107,8 @@ __global__ void __launch_bounds__(kThreads) k_recon(ReconArgs<T> a)
 #pragma unroll
             for (int j = 0; j < kReconCols; ++j) {
                 const int64_t pc = pc0 + min(j, ncol - 1);
-                ov[j] = a.O[pr + pc * a.ldo];
-                yv[j] = a.Y[pr + pc * a.ldy];
+                ov[j] = __builtin_nontemporal_load(&a.O[pr + pc * a.ldo]);
+                yv[j] = __builtin_nontemporal_load(&a.Y[pr + pc * a.ldy]);
             }
         }
         if (a.Lin) {
@@ -134,7 +137,7 @@ __global__ void __launch_bounds__(kThreads) k_recon(ReconArgs<T> a)
                 if (MODE == kEpi) {
                     const T z = o - L - sv;
                     const T yn = y + mu * z;
-                    a.Ynext[pr + pc * a.ldyn] = yn;
+                    __builtin_nontemporal_store(yn, &a.Ynext[pr + pc * a.ldyn]);
                     const T an = o - sv + yn * inv_mu_next;
                     a.Anext[pr + pc * a.ldan] = an;
                     if constexpr (SK) anv[j] = an;
