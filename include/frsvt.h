@@ -324,8 +324,19 @@ typedef struct {
     int32_t use_frsvt;     /* 1: FRSVT with range propagation; 0: exact svt */
     int32_t p;             /* oversampling of the propagated sketch (5) */
     int32_t q;             /* power iterations (1) */
-    int32_t l0;            /* first sketch width; <= 0 selects ceil(0.1 mhat) */
+    int32_t l0;            /* first sketch width; <= 0 selects ceil(0.1 b) (b = mhat
+                              without adaptive prediction) */
     uint64_t seed;         /* Philox key; iteration i uses counter i */
+    /* Adaptive rank prediction (Sec. 2.3, Eq. 7), with n of Eq. 7 the short
+     * side mhat: after an iteration of sketch width l_i and rank r_i the next
+     * width is l_{i+1} = min(r_i + p_{i+1}, b), p_{i+1} = ap_a if r_i < l_i,
+     * else ceil(ap_rho mhat); b = ceil(ap_gamma mhat); the r_i propagated
+     * columns are part of it (no new sample once r_i = b: the propagated
+     * basis alone, power iterations still applied).  p is unused then. */
+    int32_t ap;            /* 1: adaptive prediction; 0: p new samples (default) */
+    int32_t ap_a;          /* a >= 1 (2) */
+    double ap_rho;         /* rho in (0, 1] (0.05) */
+    double ap_gamma;       /* gamma in (0, 1] (1.0) */
 } frsvt_rpca_opts;
 
 typedef struct {
@@ -336,6 +347,7 @@ typedef struct {
     double seconds;        /* wall time of the iteration loop */
     int32_t ranks[64];     /* r_i of the first 64 iterations */
     double residuals[64];  /* residual of the first 64 iterations */
+    int32_t widths[64];    /* sketch width l_i of the first 64 iterations (FRSVT) */
 } frsvt_rpca_stats;
 
 /* Fill `opts` with the defaults listed above. */

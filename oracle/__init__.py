@@ -62,6 +62,12 @@ def _bind(path: str):
                                       ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                       ctypes.c_double, _dp, _i64, _dp, _i64, _i64p, _dp,
                                       ctypes.POINTER(ctypes.c_int)]
+        lib.orc_rpca_ialm_ap.argtypes = [_i64, _i64, _dp, _i64, ctypes.c_double, ctypes.c_int,
+                                         _i64, ctypes.c_int, ctypes.c_uint64, ctypes.c_double,
+                                         ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_int, _i64, ctypes.c_double,
+                                         ctypes.c_double, _dp, _i64, _dp, _i64, _i64p, _i64p,
+                                         _dp, ctypes.POINTER(ctypes.c_int)]
         lib.orc_svt_vjp.argtypes = [_i64, _i64, _dp, _i64, ctypes.c_double, _dp, _i64, _dp,
                                     _i64, _dp]
         lib.orc_wsvt_rule.argtypes = [_i64, _i64, _dp, _i64, ctypes.c_double, ctypes.c_double,
@@ -234,23 +240,29 @@ def frsvt(A, tau: float, q: int, Omega, Qprev=None):
 
 def rpca_ialm(O, lam: float, mode: str = "frsvt", p: int = 5, q: int = 1, seed: int = 0,
               tol: float = 1e-7, max_iter: int = 60, mu0: float = 0.0, rho: float = 1.5,
-              mu_bar_factor: float = 1e7):
-    """Inexact-ALM RPCA; mode 'exact' (SVT by full SVD) or 'frsvt' (FRSVT + RP).
+              mu_bar_factor: float = 1e7, ap: bool = False, ap_a: int = 2, ap_rho: float = 0.05,
+              ap_gamma: float = 1.0):
+    """Inexact-ALM RPCA; mode 'exact' (SVT by full SVD) or 'frsvt' (FRSVT + RP),
+    with the sketch widths of adaptive rank prediction (Sec. 2.3, Eq. 7) when
+    ap is set.
 
-    Returns dict(L, S, ranks, resid, iters, converged)."""
+    Returns dict(L, S, ranks, widths, resid, iters, converged)."""
     O = _f(O)
     m, n = O.shape
     L = np.zeros((m, n), order="F")
     S = np.zeros((m, n), order="F")
     ranks = np.zeros(max_iter, dtype=np.int64)
+    widths = np.zeros(max_iter, dtype=np.int64)
     resid = np.zeros(max_iter)
     it = ctypes.c_int()
-    rc = _L().orc_rpca_ialm(m, n, _p(O), m, lam, 0 if mode == "exact" else 1, p, q, seed,
-                            tol, max_iter, mu0, rho, mu_bar_factor, _p(L), m, _p(S), m,
-                            ranks.ctypes.data_as(_i64p), _p(resid), ctypes.byref(it))
+    rc = _L().orc_rpca_ialm_ap(m, n, _p(O), m, lam, 0 if mode == "exact" else 1, p, q, seed,
+                               tol, max_iter, mu0, rho, mu_bar_factor, int(ap), ap_a, ap_rho,
+                               ap_gamma, _p(L), m, _p(S), m, ranks.ctypes.data_as(_i64p),
+                               widths.ctypes.data_as(_i64p), _p(resid), ctypes.byref(it))
     _check(rc, "rpca_ialm")
     k = int(it.value)
-    return dict(L=L, S=S, ranks=ranks[:k], resid=resid[:k], iters=k, converged=(rc == 0))
+    return dict(L=L, S=S, ranks=ranks[:k], widths=widths[:k], resid=resid[:k], iters=k,
+                converged=(rc == 0))
 
 
 def svt_vjp(A, tau: float, Xbar):

@@ -537,7 +537,7 @@ int orc_frsvt(int64_t m, int64_t n, const double *A, int64_t lda, double tau, in
     const int transposed = m > n;
     const int64_t mh = transposed ? n : m, nh = transposed ? m : n;
     if (!Om || ldom < nh) return -8;
-    if (nomega < 1) return -9;
+    if (nomega < 0 || (nomega < 1 && !(Qt && r_prev > 0))) return -9;
     if (Qt && (r_prev < 0 || r_prev > mh || ldqt < mh)) return -12;
     if (ldx < m) return -14;
 
@@ -625,18 +625,29 @@ int orc_frsvt(int64_t m, int64_t n, const double *A, int64_t lda, double tau, in
 /* method without formulas; this is its standard form: an SVT step on L, a   */
 /* soft-shrinkage step on S, a dual ascent step on Y, mu grown by rho.      */
 /* ------------------------------------------------------------------------ */
-int orc_rpca_ialm(int64_t m, int64_t n, const double *O, int64_t ldo, double lambda,
-                  int svt_mode, int64_t p, int q, uint64_t seed, double tol, int max_iter,
-                  double mu0, double rho, double mu_bar_factor, double *L, int64_t ldl,
-                  double *S, int64_t lds, int64_t *ranks, double *resid, int *iters)
+/* Sketch widths (Sec. 2.1, 2.3).  Fixed rule: first call l0 = ceil(0.1 mhat),
+ * then p new samples beside the r propagated columns.  Adaptive rank
+ * prediction (Eq. 7, ap != 0), with n of Eq. 7 the short side mhat:
+ *   p_{i+1} = a             if r_i < l_i,
+ *             ceil(rho mhat) otherwise,
+ *   l_{i+1} = min(r_i + p_{i+1}, b),  b = ceil(gamma mhat),  l_0 = ceil(0.1 b);
+ * the propagated basis holds r_i columns, so l_{i+1} - r_i samples are new
+ * (none once r_i = b: the propagated basis alone, power iterations still
+ * applied).  widths[i] = l_i. */
+int orc_rpca_ialm_ap(int64_t m, int64_t n, const double *O, int64_t ldo, double lambda,
+                     int svt_mode, int64_t p, int q, uint64_t seed, double tol, int max_iter,
+                     double mu0, double rho, double mu_bar_factor, int ap, int64_t ap_a,
+                     double ap_rho, double ap_gamma, double *L, int64_t ldl, double *S,
+                     int64_t lds, int64_t *ranks, int64_t *widths, double *resid, int *iters)
 {
     if (m < 1) return -1;
     if (n < 1) return -2;
     if (ldo < m) return -4;
     if (!(lambda > 0.0)) return -5;
     if (svt_mode != 0 && svt_mode != 1) return -6;
-    if (svt_mode == 1 && p < 1) return -7;
+    if (svt_mode == 1 && p < 1 && !ap) return -7;
     if (max_iter < 1) return -11;
+    if (ap && (ap_a < 1 || !(ap_rho > 0.0) || !(ap_gamma > 0.0) || ap_gamma > 1.0)) return -15;
     const int64_t mn = m * n;
     const int64_t mh = m < n ? m : n, nh = m < n ? n : m;
 
@@ -664,7 +675,14 @@ int orc_rpca_ialm(int64_t m, int64_t n, const double *O, int64_t ldo, double lam
 
     double *Qt = dalloc(mh * mh), *Qnew = dalloc(mh * mh);
     int64_t r_prev = -1; /* -1: no propagated basis yet */
-    const int64_t l0 = (int64_t)ceil(0.1 * (double)mh);
+    int64_t bmax = mh, l_prev = 0;
+    if (ap) {
+        bmax = (int64_t)ceil(ap_gamma * (double)mh);
+        if (bmax < 1) bmax = 1;
+        if (bmax > mh) bmax = mh;
+    }
+    int64_t l0 = (int64_t)ceil(0.1 * (double)bmax);
+    if (l0 < 1) l0 = 1;
     int status = 2;
     int it;
     for (it = 0; it < max_iter; ++it) {
@@ -678,16 +696,30 @@ int orc_rpca_ialm(int64_t m, int64_t n, const double *O, int64_t ldo, double lam
         } else {
             int64_t nomega;
             const double *Qprop = NULL;
-            if (r_prev < 0) nomega = l0;            /* first call: l0 = 0.1 b, b = mhat */
-            else if (r_prev == 0) nomega = p;       /* nothing to propagate */
-            else {                                   /* range propagation */
+            if (r_prev < 0) {
+                nomega = l0;                         /* first call: l0 = 0.1 b */
+            } else if (ap) {
+                const int64_t pn = r_prev < l_prev ? ap_a : (int64_t)ceil(ap_rho * (double)mh);
+                const int64_t ln = r_prev + pn < bmax ? r_prev + pn : bmax;
+                if (r_prev == 0) nomega = ln;        /* nothing to propagate */
+                else {
+                    Qprop = Qt;
+                    nomega = ln - r_prev;            /* may be 0 once r = b */
+                }
+            } else if (r_prev == 0) {
+                nomega = p;                          /* nothing to propagate */
+            } else {                                 /* range propagation */
                 Qprop = Qt;
                 nomega = p;
                 if (r_prev + nomega > mh) nomega = mh - r_prev;
             }
-            if (nomega < 1) nomega = 1;
-            double *Om = dalloc(nh * nomega);
-            orc_gaussian_matrix(seed, (uint64_t)it, nh, nomega, Om, nh);
+            if (nomega < 1 && !Qprop) nomega = 1;
+            if (nomega < 0) nomega = 0;
+            const int64_t lw = (Qprop ? r_prev : 0) + nomega;
+            l_prev = lw < mh ? lw : mh;
+            if (widths) widths[it] = l_prev;
+            double *Om = dalloc(nh * (nomega > 0 ? nomega : 1));
+            if (nomega > 0) orc_gaussian_matrix(seed, (uint64_t)it, nh, nomega, Om, nh);
             orc_frsvt(m, n, A, m, 1.0 / mu, q, Om, nh, nomega, Qprop, mh,
                       Qprop ? r_prev : 0, Lk, m, Qnew, mh, &r, NULL, NULL);
             free(Om);
@@ -720,6 +752,15 @@ int orc_rpca_ialm(int64_t m, int64_t n, const double *O, int64_t ldo, double lam
     mat_copy(m, n, Sk, m, S, lds);
     free(Y); free(A); free(Lk); free(Sk); free(Qt); free(Qnew);
     return status;
+}
+
+int orc_rpca_ialm(int64_t m, int64_t n, const double *O, int64_t ldo, double lambda,
+                  int svt_mode, int64_t p, int q, uint64_t seed, double tol, int max_iter,
+                  double mu0, double rho, double mu_bar_factor, double *L, int64_t ldl,
+                  double *S, int64_t lds, int64_t *ranks, double *resid, int *iters)
+{
+    return orc_rpca_ialm_ap(m, n, O, ldo, lambda, svt_mode, p, q, seed, tol, max_iter, mu0, rho,
+                            mu_bar_factor, 0, 0, 0.0, 0.0, L, ldl, S, lds, ranks, NULL, resid, iters);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -95,6 +95,19 @@ int orc_rpca_ialm(int64_t m, int64_t n, const double *O, int64_t ldo, double lam
                   double *L, int64_t ldl, double *S, int64_t lds,
                   int64_t *ranks, double *resid, int *iters);
 
+/* The same with the sketch widths of adaptive rank prediction (Sec. 2.3,
+ * Eq. 7) when ap != 0: after a call of width l_i and rank r_i the next width
+ * is l_{i+1} = min(r_i + (r_i < l_i ? a : ceil(rho mhat)), b), b =
+ * ceil(gamma mhat), l_0 = ceil(0.1 b); the propagated basis holds r_i of
+ * them (no new sample once r_i = b).  p is unused then.  widths[] (length
+ * max_iter, optional) receives l_i; returns -15 for a < 1, rho <= 0 or gamma
+ * outside (0, 1]. */
+int orc_rpca_ialm_ap(int64_t m, int64_t n, const double *O, int64_t ldo, double lambda,
+                     int svt_mode, int64_t p, int q, uint64_t seed, double tol, int max_iter,
+                     double mu0, double rho, double mu_bar_factor, int ap, int64_t ap_a,
+                     double ap_rho, double ap_gamma, double *L, int64_t ldl, double *S,
+                     int64_t lds, int64_t *ranks, int64_t *widths, double *resid, int *iters);
+
 /* Vector-Jacobian product of exact SVT from a full SVD: given Xbar,
  * Abar = (dX/dA)^T Xbar and taubar = <Xbar, dX/dtau>. */
 int orc_svt_vjp(int64_t m, int64_t n, const double *A, int64_t lda, double tau,

@@ -37,12 +37,14 @@ class FRSVTError(RuntimeError):
 class RpcaOpts(ctypes.Structure):
     _fields_ = [("tol", _dbl), ("max_iter", _i32), ("mu0", _dbl), ("rho", _dbl),
                 ("mu_bar_factor", _dbl), ("use_frsvt", _i32), ("p", _i32), ("q", _i32),
-                ("l0", _i32), ("seed", _u64)]
+                ("l0", _i32), ("seed", _u64), ("ap", _i32), ("ap_a", _i32), ("ap_rho", _dbl),
+                ("ap_gamma", _dbl)]
 
 
 class RpcaStats(ctypes.Structure):
     _fields_ = [("iters", _i32), ("converged", _i32), ("residual", _dbl), ("norm2", _dbl),
-                ("seconds", _dbl), ("ranks", _i32 * 64), ("residuals", _dbl * 64)]
+                ("seconds", _dbl), ("ranks", _i32 * 64), ("residuals", _dbl * 64),
+                ("widths", _i32 * 64)]
 
 
 class WsvtRule(ctypes.Structure):
@@ -312,13 +314,17 @@ class RpcaResult:
     seconds: float
     ranks: list = field(default_factory=list)
     residuals: list = field(default_factory=list)
+    widths: list = field(default_factory=list)
 
 
 def rpca_ialm(O, lam: float, *, use_frsvt: bool = True, tol: float = 1e-7, max_iter: int = 60,
               mu0: float = 0.0, rho: float = 1.5, mu_bar_factor: float = 1e7, p: int = 5,
-              q: int = 1, l0: int = 0, seed: int = 0) -> RpcaResult:
+              q: int = 1, l0: int = 0, seed: int = 0, ap: bool = False, ap_a: int = 2,
+              ap_rho: float = 0.05, ap_gamma: float = 1.0) -> RpcaResult:
     """Inexact-ALM RPCA (the host of Sec. 4.1) with FRSVT + range propagation
-    or exact SVT.  O is a GPU tensor (m x n)."""
+    or exact SVT.  O is a GPU tensor (m x n).  With ap the sketch widths follow
+    adaptive rank prediction (Sec. 2.3, Eq. 7: a, rho, gamma) instead of p
+    new samples per iteration."""
     h = handle(O.device.index)
     m, n, ldo, tr = _colmajor(O)
     L = _like(O, tr)
@@ -329,13 +335,15 @@ def rpca_ialm(O, lam: float, *, use_frsvt: bool = True, tol: float = 1e-7, max_i
     h.lib.frsvt_rpca_default_opts(ctypes.byref(op))
     op.tol, op.max_iter, op.mu0, op.rho, op.mu_bar_factor = tol, max_iter, mu0, rho, mu_bar_factor
     op.use_frsvt, op.p, op.q, op.l0, op.seed = int(use_frsvt), p, q, l0, seed
+    op.ap, op.ap_a, op.ap_rho, op.ap_gamma = int(ap), ap_a, ap_rho, ap_gamma
     st = RpcaStats()
     rc = h.lib.rpca_ialm(h.ptr, _prec(O), m, n, O.data_ptr(), ldo, float(lam), ctypes.byref(op),
                          L.data_ptr(), ldl, S.data_ptr(), lds, ctypes.byref(st))
     _check(h, rc, "rpca_ialm", ok=(OK, MAX_ITER))
     k = min(st.iters, 64)
     return RpcaResult(L, S, st.iters, bool(st.converged), st.residual, st.norm2, st.seconds,
-                      list(st.ranks[:k]), list(st.residuals[:k]))
+                      list(st.ranks[:k]), list(st.residuals[:k]),
+                      list(st.widths[:k]) if use_frsvt else [])
 
 
 # ---------------------------------------------------------------------------

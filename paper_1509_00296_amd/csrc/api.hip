@@ -1082,7 +1082,9 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
     const double J = std::max(norm2, mx / lambda);
     double mu = op.mu0 > 0.0 ? op.mu0 : 1.25 / norm2;
     const double mu_bar = mu * op.mu_bar_factor;
-    const int l0 = op.l0 > 0 ? std::min(op.l0, mh) : std::min(mh, (int)std::ceil(0.1 * mh));
+    // widest sketch: b = ceil(gamma mhat) under adaptive prediction, else mhat
+    const int bmax = op.ap ? std::max(1, std::min(mh, (int)std::ceil(op.ap_gamma * mh))) : mh;
+    const int l0 = op.l0 > 0 ? std::min(op.l0, bmax) : std::max(1, std::min(bmax, (int)std::ceil(0.1 * bmax)));
 
     // workspace: A, the FRSVT core at its largest width, exact factors, z partials
     const int lmax = op.use_frsvt ? std::min(mh, std::max(l0, mh)) : mh;
@@ -1122,7 +1124,7 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
     CKT(FRSVT_K_OTHER, launch_rpca_init<T>(m, n, O, ldo, 1.0 / J, 1.0 / mu, Ybuf[0], ldyb[0], A, m, s));
 
     auto t0 = std::chrono::steady_clock::now();
-    int r_prev = -1;
+    int r_prev = -1, l_prev = 0;
     int spec_cnew = 0;
     int it = 0;
     bool converged = false;
@@ -1148,17 +1150,26 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
             c.q = op.q;
             c.seed = op.seed;
             c.counter = (uint64_t)it;
+            // new samples: p beside the propagated columns, or under
+            // adaptive prediction (Eq. 7) l_{i+1} - r_i with
+            // l_{i+1} = min(r_i + (r_i < l_i ? a : ceil(rho mhat)), b)
+            auto ap_width = [&](int r, int lw) {
+                const int pn = r < lw ? op.ap_a : (int)std::ceil(op.ap_rho * (double)mh);
+                return std::min(r + pn, bmax);
+            };
             if (r_prev > 0) {
                 c.Qt = Qt;
                 c.ldqt = mh;
                 c.rp = r_prev;
-                c.cnew = std::max(0, std::min(op.p, mh - r_prev));
+                c.cnew = op.ap ? ap_width(r_prev, l_prev) - r_prev : std::max(0, std::min(op.p, mh - r_prev));
             } else {
                 c.Qt = nullptr;
                 c.ldqt = mh;
                 c.rp = 0;
-                c.cnew = r_prev < 0 ? l0 : std::min(op.p, mh);
+                c.cnew = r_prev < 0 ? l0 : (op.ap ? ap_width(0, l_prev) : std::min(op.p, mh));
             }
+            l_prev = std::min(mh, c.rp + c.cnew);
+            if (stats && it < 64) stats->widths[it] = l_prev;
             c.sketch_ready = spec_cnew > 0 && spec_cnew == c.cnew && core_small<T>(c, c.rp + c.cnew);
             c.Qout = Qt;
             c.ldqo = mh;
@@ -1221,7 +1232,8 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
         // is a pass of its own below.
         Core<T> cn = c;
         cn.counter = (uint64_t)(it + 1);
-        cn.cnew = std::min(op.p, mh);
+        // (under adaptive prediction the width of the common case, r < l)
+        cn.cnew = std::min(op.ap ? op.ap_a : op.p, mh);
         const bool next_sketch = op.use_frsvt && it + 1 < op.max_iter && cn.cnew > 0 && long_path_ok(mh, cn.cnew);
         const int64_t rblocks = recon_row_blocks(m);
         const bool fuse_sketch = next_sketch && std::is_same<T, double>::value && o.trans && cn.cnew <= 8 &&
@@ -1647,6 +1659,10 @@ void frsvt_rpca_default_opts(frsvt_rpca_opts *op)
     op->q = 1;
     op->l0 = 0;
     op->seed = 0;
+    op->ap = 0;
+    op->ap_a = 2;
+    op->ap_rho = 0.05;
+    op->ap_gamma = 1.0;
 }
 
 int svt(frsvt_handle h, frsvt_precision prec, int64_t m, int64_t n, const void *A, int64_t lda,
@@ -1738,6 +1754,10 @@ int rpca_ialm(frsvt_handle h, frsvt_precision prec, int64_t m, int64_t n, const 
     if (opts) op = *opts;
     if (!(op.tol > 0.0) || op.max_iter < 1 || !(op.rho >= 1.0) || op.p < 1 || op.q < 0 ||
         !(op.mu_bar_factor >= 1.0))
+        return -8;
+    if (op.ap != 0 && op.ap != 1) return -8;
+    if (op.ap && (op.ap_a < 1 || !(op.ap_rho > 0.0) || !(op.ap_rho <= 1.0) || !(op.ap_gamma > 0.0) ||
+                  !(op.ap_gamma <= 1.0)))
         return -8;
     if (bad_ptr(L)) return -9;
     if (ldl < m) return -10;

@@ -118,3 +118,24 @@ def test_binding_refuses_missing_library(tmp_path):
     import paper_1509_00296_amd as fr
     with pytest.raises(ImportError):
         fr.library(str(tmp_path / "missing.so"))
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The Python binding's ctypes structures have the sizes and field
+    offsets that a C compiler gives the header's structures."""
+    import paper_1509_00296_amd as fr
+    src = tmp_path / "sizes.c"
+    src.write_text(
+        '#include <stddef.h>\n#include <stdio.h>\n#include "frsvt.h"\n'
+        "int main(void) {\n"
+        '  printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(frsvt_rpca_opts), sizeof(frsvt_rpca_stats),\n'
+        "         offsetof(frsvt_rpca_opts, seed), offsetof(frsvt_rpca_opts, ap_gamma),\n"
+        "         offsetof(frsvt_rpca_stats, widths), sizeof(frsvt_wsvt_rule));\n"
+        "  return 0;\n}\n")
+    exe = tmp_path / "sizes"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    want = [ctypes.sizeof(fr.RpcaOpts), ctypes.sizeof(fr.RpcaStats), fr.RpcaOpts.seed.offset,
+            fr.RpcaOpts.ap_gamma.offset, fr.RpcaStats.widths.offset, ctypes.sizeof(fr.WsvtRule)]
+    assert got == want

@@ -180,6 +180,29 @@ def test_rpca_small_matches_oracle(fr, orc, mode, m, n):
     out = orc.rpca_ialm(O, lam, mode=mode, p=5, q=1, seed=17)
     assert res.iters == out["iters"]
     assert res.ranks == list(out["ranks"][:64])
+    if mode == "frsvt":
+        assert res.widths == list(out["widths"][:64])
+    assert _rel(res.L.cpu().numpy(), out["L"]) <= 1e-10
+    assert _rel(res.S.cpu().numpy(), out["S"]) <= 1e-10
+    assert res.converged
+    assert np.linalg.norm(res.L.cpu().numpy() - Lgt) / np.linalg.norm(Lgt) < 1e-4
+
+
+@pytest.mark.parametrize("m,n,gamma", [(3000, 60, 1.0), (60, 3000, 1.0), (3000, 60, 0.05)])
+def test_rpca_adaptive_rank_prediction_matches_oracle(fr, orc, m, n, gamma):
+    """Sketch widths by adaptive rank prediction (Sec. 2.3, Eq. 7; a = 2,
+    rho = 0.05): the same width and rank sequences as the oracle, L and S
+    within 1e-10.  gamma = 0.05 bounds the width at the true rank 3, so the
+    later iterations take no new sample (the propagated basis alone)."""
+    from paper_1509_00296_amd import synth
+    _say(f"case rpca ap {m}x{n} gamma={gamma}")
+    O, Lgt, _ = synth.rpca(seed=3, m=m, n=n, rank=3, frac=0.10)
+    lam = 1.0 / np.sqrt(max(m, n))
+    res = fr.rpca_ialm(_gpu(O), lam, use_frsvt=True, seed=17, ap=True, ap_gamma=gamma)
+    out = orc.rpca_ialm(O, lam, mode="frsvt", q=1, seed=17, ap=True, ap_gamma=gamma)
+    assert res.iters == out["iters"]
+    assert res.ranks == list(out["ranks"][:64])
+    assert res.widths == list(out["widths"][:64])
     assert _rel(res.L.cpu().numpy(), out["L"]) <= 1e-10
     assert _rel(res.S.cpu().numpy(), out["S"]) <= 1e-10
     assert res.converged
