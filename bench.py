@@ -17,6 +17,10 @@ Further workloads, reported under "workloads" in the same JSON line:
   precision 8192 x 8192 FRSVT in the bfloat16 form and in FP64, calls/s
   batched  8192 patch-group WSVT problems in one persistent launch, matrices/s
   unrolled 16 x 4096 x 256 unrolled RPCA (10 steps), train steps/s
+  ablation the main RPCA workload with p new samples in {2, 5, 10} x q power
+           iterations in {0, 1, 2}, and with adaptive rank prediction
+           (Sec. 2.3, Eq. 7: a = 2, rho = 0.05, gamma = 1; q = 1): iters/s,
+           iterations, sketch widths and the error of L
 
 Prints ONE JSON line.  --gpus above 1 is refused: this build runs on one GPU.
 """
@@ -50,7 +54,7 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=6,
                     help="iterations of the oracle timed for the CPU baseline (0 = skip)")
     ap.add_argument("--only-main", action="store_true", help="skip the further workloads")
-    ap.add_argument("--workloads", default="single,precision,batched,unrolled")
+    ap.add_argument("--workloads", default="single,precision,batched,unrolled,ablation")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="one untimed device copy of this size first (counter calibration)")
     return ap.parse_args()
@@ -277,6 +281,38 @@ def wl_unrolled(torch, fr, synth, tracer):
             "kernels": _r(kern)}
 
 
+def wl_ablation(torch, fr, synth, tracer):
+    import numpy as np
+    O_np, L_gt, _ = synth.rpca(seed=0, m=M, n=N, rank=RANK, frac=FRAC)
+    O = torch.from_numpy(O_np).cuda()
+    Lgt = torch.from_numpy(L_gt).cuda()
+    lam = 1.0 / np.sqrt(M)
+    runs = []
+    cases = [dict(p=p, q=q, ap=False) for q in (0, 1, 2) for p in (2, 5, 10)]
+    cases.append(dict(p=5, q=1, ap=True))
+    for cs in cases:
+        def solve():
+            return fr.rpca_ialm(O, lam, use_frsvt=True, tol=1e-7, max_iter=60, p=cs["p"], q=cs["q"],
+                                seed=2024, ap=cs["ap"], ap_a=2, ap_rho=0.05, ap_gamma=1.0)
+        solve()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        K, iters = 2, 0
+        for _ in range(K):
+            res = solve()
+            iters += res.iters
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        err = float(torch.linalg.norm(res.L - Lgt) / torch.linalg.norm(Lgt))
+        runs.append({"rule": "adaptive (a 2, rho 0.05, gamma 1)" if cs["ap"] else f"p {cs['p']}",
+                     "q": cs["q"], "iters_per_s": round(iters / sec, 1), "iters": res.iters,
+                     "ms_per_solve": round(1e3 * sec / K, 3), "converged": res.converged,
+                     "nrmse_L": err, "widths_last": res.widths[-1] if res.widths else None,
+                     "widths_max": max(res.widths) if res.widths else None})
+    return {"workload": "rpca_ialm_76800x200_p_q_ablation", "metric": "iters/s", "unit": "iters/s",
+            "runs": runs}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -384,7 +420,7 @@ def main():
     workloads = {}
     if not args.only_main:
         fns = {"single": wl_single, "precision": wl_precision, "batched": wl_batched,
-               "unrolled": wl_unrolled}
+               "unrolled": wl_unrolled, "ablation": wl_ablation}
         for name in [w for w in args.workloads.split(",") if w]:
             _progress(f"workload {name}")
             try:
