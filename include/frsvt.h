@@ -348,6 +348,13 @@ typedef struct {
     int32_t ranks[64];     /* r_i of the first 64 iterations */
     double residuals[64];  /* residual of the first 64 iterations */
     int32_t widths[64];    /* sketch width l_i of the first 64 iterations (FRSVT) */
+    /* Prop. 4 (with Lemma 3, alpha = 20): 20 sqrt(2/pi) ||(I - Q~ Q~^T) y||_2
+     * for the first new sample y = Ahat omega of iteration i, Q~ the
+     * propagated basis (none for a fresh sketch) -- an upper bound on
+     * sigma_{r+1} of that iteration's Ahat with probability >= 0.95, computed
+     * from the orthonormalisation's by-products; -1 when no sample was drawn
+     * (FRSVT) */
+    double resid_est[64];
 } frsvt_rpca_stats;
 
 /* Fill `opts` with the defaults listed above. */

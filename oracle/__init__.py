@@ -67,7 +67,10 @@ def _bind(path: str):
                                          ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_double, ctypes.c_int, _i64, ctypes.c_double,
                                          ctypes.c_double, _dp, _i64, _dp, _i64, _i64p, _i64p,
-                                         _dp, ctypes.POINTER(ctypes.c_int)]
+                                         _dp, _dp, ctypes.POINTER(ctypes.c_int)]
+        lib.orc_residual_estimate.argtypes = [_i64, _i64, _dp, _i64, _dp, _i64, _i64, _dp,
+                                              ctypes.c_double]
+        lib.orc_residual_estimate.restype = ctypes.c_double
         lib.orc_svt_vjp.argtypes = [_i64, _i64, _dp, _i64, ctypes.c_double, _dp, _i64, _dp,
                                     _i64, _dp]
         lib.orc_wsvt_rule.argtypes = [_i64, _i64, _dp, _i64, ctypes.c_double, ctypes.c_double,
@@ -253,16 +256,34 @@ def rpca_ialm(O, lam: float, mode: str = "frsvt", p: int = 5, q: int = 1, seed: 
     S = np.zeros((m, n), order="F")
     ranks = np.zeros(max_iter, dtype=np.int64)
     widths = np.zeros(max_iter, dtype=np.int64)
+    resid_est = np.zeros(max_iter)
     resid = np.zeros(max_iter)
     it = ctypes.c_int()
     rc = _L().orc_rpca_ialm_ap(m, n, _p(O), m, lam, 0 if mode == "exact" else 1, p, q, seed,
                                tol, max_iter, mu0, rho, mu_bar_factor, int(ap), ap_a, ap_rho,
                                ap_gamma, _p(L), m, _p(S), m, ranks.ctypes.data_as(_i64p),
-                               widths.ctypes.data_as(_i64p), _p(resid), ctypes.byref(it))
+                               widths.ctypes.data_as(_i64p), _p(resid_est), _p(resid),
+                               ctypes.byref(it))
     _check(rc, "rpca_ialm")
     k = int(it.value)
-    return dict(L=L, S=S, ranks=ranks[:k], widths=widths[:k], resid=resid[:k], iters=k,
-                converged=(rc == 0))
+    return dict(L=L, S=S, ranks=ranks[:k], widths=widths[:k], resid_est=resid_est[:k],
+                resid=resid[:k], iters=k, converged=(rc == 0))
+
+
+def residual_estimate(A, Qt, omega, alpha: float = 20.0) -> float:
+    """Prop. 4: alpha sqrt(2/pi) ||(I - Q~ Q~^T) Ahat omega||_2, an upper
+    bound on sigma_{r+1}(Ahat) with probability >= 1 - 1/alpha."""
+    A = _f(A)
+    m, n = A.shape
+    mh = min(m, n)
+    om = np.ascontiguousarray(omega, dtype=np.float64)
+    assert om.shape == (max(m, n),)
+    if Qt is None or Qt.shape[1] == 0:
+        Q, r = np.zeros((mh, 1), order="F"), 0
+    else:
+        Q = _f(Qt)
+        r = Q.shape[1]
+    return float(_L().orc_residual_estimate(m, n, _p(A), m, _p(Q), mh, r, _p(om), alpha))
 
 
 def svt_vjp(A, tau: float, Xbar):

@@ -620,6 +620,33 @@ int orc_frsvt(int64_t m, int64_t n, const double *A, int64_t lda, double tau, in
 }
 
 /* ------------------------------------------------------------------------ */
+/* Residual singular-value estimate (Prop. 4 with Lemma 3): for Q~ (mhat x r, */
+/* orthonormal columns) and one standard Gaussian vector omega (length nhat), */
+/*   est = alpha sqrt(2/pi) ||(I - Q~ Q~^T) Ahat omega||_2                    */
+/* bounds sigma_{r+1}(Ahat) from above with probability >= 1 - 1/alpha.  The  */
+/* projection is applied twice (classical Gram-Schmidt, two passes), as the   */
+/* range propagation's partial orthogonalisation forms it.                    */
+/* ------------------------------------------------------------------------ */
+double orc_residual_estimate(int64_t m, int64_t n, const double *A, int64_t lda, const double *Qt,
+                             int64_t ldq, int64_t r, const double *omega, double alpha)
+{
+    const int transposed = m > n;
+    const int64_t mh = transposed ? n : m;
+    double *y = dalloc(mh);
+    if (transposed) mat_mul_tn(mh, 1, m, A, lda, omega, m, y, mh);   /* y = A^T omega */
+    else mat_mul(mh, 1, n, A, lda, omega, n, y, mh);                  /* y = A omega   */
+    for (int pass = 0; pass < 2; ++pass)
+        for (int64_t c = 0; c < r; ++c) {
+            const double d = col_dot(mh, &AT(Qt, ldq, 0, c), y);
+            for (int64_t i = 0; i < mh; ++i) y[i] -= d * AT(Qt, ldq, i, c);
+        }
+    const double pi = 3.14159265358979323846;
+    const double est = alpha * sqrt(2.0 / pi) * col_norm(mh, y);
+    free(y);
+    return est;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Inexact augmented Lagrange multiplier RPCA (the iALM host of Sec. 4.1,    */
 /* "Robust PCA test"; lambda = 1/sqrt(max(m,n)) there).  The paper cites the */
 /* method without formulas; this is its standard form: an SVT step on L, a   */
@@ -638,7 +665,8 @@ int orc_rpca_ialm_ap(int64_t m, int64_t n, const double *O, int64_t ldo, double 
                      int svt_mode, int64_t p, int q, uint64_t seed, double tol, int max_iter,
                      double mu0, double rho, double mu_bar_factor, int ap, int64_t ap_a,
                      double ap_rho, double ap_gamma, double *L, int64_t ldl, double *S,
-                     int64_t lds, int64_t *ranks, int64_t *widths, double *resid, int *iters)
+                     int64_t lds, int64_t *ranks, int64_t *widths, double *resid_est,
+                     double *resid, int *iters)
 {
     if (m < 1) return -1;
     if (n < 1) return -2;
@@ -720,6 +748,11 @@ int orc_rpca_ialm_ap(int64_t m, int64_t n, const double *O, int64_t ldo, double 
             if (widths) widths[it] = l_prev;
             double *Om = dalloc(nh * (nomega > 0 ? nomega : 1));
             if (nomega > 0) orc_gaussian_matrix(seed, (uint64_t)it, nh, nomega, Om, nh);
+            /* Prop. 4 with the first new sample (alpha = 20); -1: no sample */
+            if (resid_est)
+                resid_est[it] = nomega > 0 ? orc_residual_estimate(m, n, A, m, Qt, mh, Qprop ? r_prev : 0,
+                                                                   Om, 20.0)
+                                           : -1.0;
             orc_frsvt(m, n, A, m, 1.0 / mu, q, Om, nh, nomega, Qprop, mh,
                       Qprop ? r_prev : 0, Lk, m, Qnew, mh, &r, NULL, NULL);
             free(Om);
@@ -760,7 +793,8 @@ int orc_rpca_ialm(int64_t m, int64_t n, const double *O, int64_t ldo, double lam
                   double *S, int64_t lds, int64_t *ranks, double *resid, int *iters)
 {
     return orc_rpca_ialm_ap(m, n, O, ldo, lambda, svt_mode, p, q, seed, tol, max_iter, mu0, rho,
-                            mu_bar_factor, 0, 0, 0.0, 0.0, L, ldl, S, lds, ranks, NULL, resid, iters);
+                            mu_bar_factor, 0, 0, 0.0, 0.0, L, ldl, S, lds, ranks, NULL, NULL, resid,
+                            iters);
 }
 
 /* ------------------------------------------------------------------------ */

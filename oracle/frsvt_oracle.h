@@ -100,13 +100,24 @@ int orc_rpca_ialm(int64_t m, int64_t n, const double *O, int64_t ldo, double lam
  * is l_{i+1} = min(r_i + (r_i < l_i ? a : ceil(rho mhat)), b), b =
  * ceil(gamma mhat), l_0 = ceil(0.1 b); the propagated basis holds r_i of
  * them (no new sample once r_i = b).  p is unused then.  widths[] (length
- * max_iter, optional) receives l_i; returns -15 for a < 1, rho <= 0 or gamma
+ * max_iter, optional) receives l_i, resid_est[] the estimate below; returns -15 for a < 1, rho <= 0 or gamma
  * outside (0, 1]. */
 int orc_rpca_ialm_ap(int64_t m, int64_t n, const double *O, int64_t ldo, double lambda,
                      int svt_mode, int64_t p, int q, uint64_t seed, double tol, int max_iter,
                      double mu0, double rho, double mu_bar_factor, int ap, int64_t ap_a,
                      double ap_rho, double ap_gamma, double *L, int64_t ldl, double *S,
-                     int64_t lds, int64_t *ranks, int64_t *widths, double *resid, int *iters);
+                     int64_t lds, int64_t *ranks, int64_t *widths, double *resid_est,
+                     double *resid, int *iters);
+
+/* Prop. 4's residual singular-value estimate alpha sqrt(2/pi)
+ * ||(I - Q~ Q~^T) Ahat omega||_2 (Ahat = A if m <= n, else A^T; Q~ mhat x r
+ * orthonormal, omega of length nhat), an upper bound on sigma_{r+1}(Ahat)
+ * with probability >= 1 - 1/alpha.  In orc_rpca_ialm_ap, resid_est[i] is
+ * this estimate (alpha = 20) for the first new sample of iteration i, with
+ * the propagated basis as Q~ (none for a fresh sketch), -1 when no sample is
+ * drawn. */
+double orc_residual_estimate(int64_t m, int64_t n, const double *A, int64_t lda, const double *Qt,
+                             int64_t ldq, int64_t r, const double *omega, double alpha);
 
 /* Vector-Jacobian product of exact SVT from a full SVD: given Xbar,
  * Abar = (dX/dA)^T Xbar and taubar = <Xbar, dX/dtau>. */

@@ -44,7 +44,7 @@ class RpcaOpts(ctypes.Structure):
 class RpcaStats(ctypes.Structure):
     _fields_ = [("iters", _i32), ("converged", _i32), ("residual", _dbl), ("norm2", _dbl),
                 ("seconds", _dbl), ("ranks", _i32 * 64), ("residuals", _dbl * 64),
-                ("widths", _i32 * 64)]
+                ("widths", _i32 * 64), ("resid_est", _dbl * 64)]
 
 
 class WsvtRule(ctypes.Structure):
@@ -315,6 +315,7 @@ class RpcaResult:
     ranks: list = field(default_factory=list)
     residuals: list = field(default_factory=list)
     widths: list = field(default_factory=list)
+    resid_est: list = field(default_factory=list)
 
 
 def rpca_ialm(O, lam: float, *, use_frsvt: bool = True, tol: float = 1e-7, max_iter: int = 60,
@@ -343,7 +344,8 @@ def rpca_ialm(O, lam: float, *, use_frsvt: bool = True, tol: float = 1e-7, max_i
     k = min(st.iters, 64)
     return RpcaResult(L, S, st.iters, bool(st.converged), st.residual, st.norm2, st.seconds,
                       list(st.ranks[:k]), list(st.residuals[:k]),
-                      list(st.widths[:k]) if use_frsvt else [])
+                      list(st.widths[:k]) if use_frsvt else [],
+                      list(st.resid_est[:k]) if use_frsvt else [])
 
 
 # ---------------------------------------------------------------------------

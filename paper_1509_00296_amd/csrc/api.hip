@@ -57,6 +57,7 @@ namespace {
 constexpr double kU = 1.1102230246251565e-16;
 constexpr size_t kStatusInts = 1024;
 constexpr int kGateSlot = 12;  // status word: null pivots of the large path's first null check
+constexpr int kResidSlot = 20; // status words 20-21: a double, Prop. 4's squared residual
 constexpr size_t kScalarDoubles = 8192;
 
 int fail(frsvt_context *h, hipError_t e, const char *what)
@@ -220,6 +221,7 @@ struct Core {
     T *Q, *Bt, *QM;
     double *G, *U, *Mm, *sigma;
     int *status;         // device: [0] r, [1] sweeps, [2] converged, [4..] orth flags
+    double *resid_out = nullptr;   // device, optional: squared residual of the first new sample (Prop. 4)
 };
 
 template <typename T>
@@ -485,7 +487,7 @@ int run_core(frsvt_context *h, Core<T> &c, CoreBuffers<T> &b)
     if (small) {
         if (!c.sketch_ready && (rc = sketch_stage<T>(h, c, b))) return rc;
         CKT(FRSVT_K_ORTH, launch_small_orth<T>(mh, c.Qt, c.ldqt, c.rp, b.Y, mh, c.cnew, b.Q, mh, c.seed,
-                                c.counter, oflags, s));
+                                c.counter, oflags, c.resid_out, s));
     } else {
         if (c.rp > 0)
             CK(hipMemcpy2DAsync(b.Q, mh * sizeof(T), c.Qt, c.ldqt * sizeof(T), mh * sizeof(T),
@@ -502,6 +504,7 @@ int run_core(frsvt_context *h, Core<T> &c, CoreBuffers<T> &b)
                     return rc;
             }
         }
+        if (c.resid_out) CKT(FRSVT_K_ORTH, launch_resid_est<T>(mh, b.Q, mh, c.rp, c.cnew, c.resid_out, s));
         if ((rc = big_orth<T>(h, mh, l, b.Q, mh, b, c.seed, c.counter, oflags))) return rc;
     }
 
@@ -517,7 +520,7 @@ int run_core(frsvt_context *h, Core<T> &c, CoreBuffers<T> &b)
             CKT(FRSVT_K_POWER, launch_long<T>(p, kPower, la, s));
             CKT(FRSVT_K_REDUCE, launch_reduce<T>(b.Ypart, (int64_t)mh * l, p.grid, b.Y, s));
             CKT(FRSVT_K_ORTH, launch_small_orth<T>(mh, (const T *)nullptr, mh, 0, b.Y, mh, l, b.Q, mh, c.seed,
-                                    ctr2, oflags, s));
+                                    ctr2, oflags, (double *)nullptr, s));
         } else {
             if ((rc = ahat_t_times<T>(h, c, b.Q, mh, l, b.Z, b.gpart_t, true, b.V16))) return rc;
             if ((rc = ahat_times<T>(h, c, b.Z, o.nh, l, b.Q, b.gpart_t, b.V16))) return rc;
@@ -812,7 +815,7 @@ int orth_copy(frsvt_context *h, int mh, int l, const T *Y, T *Qdst, VjpBuffers<T
 {
     if (small_orth_ok(mh, l)) {
         CKT(FRSVT_K_ORTH, launch_small_orth<T>(mh, (const T *)nullptr, mh, 0, Y, mh, l, Qdst, mh, seed,
-                                               counter, flags, h->stream));
+                                               counter, flags, (double *)nullptr, h->stream));
         return FRSVT_OK;
     }
     CK(hipMemcpyAsync(Qdst, Y, (size_t)mh * l * sizeof(T), hipMemcpyDeviceToDevice, h->stream));
@@ -1174,6 +1177,7 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
             c.Qout = Qt;
             c.ldqo = mh;
             c.status = h->dstatus;
+            c.resid_out = reinterpret_cast<double *>(h->dstatus + kResidSlot);
             if ((rc = run_core<T>(h, c, b))) return rc;
             ra.c = c.l;
             if (o.trans) {
@@ -1251,7 +1255,10 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
         // event only, so the GPU keeps working on the speculative sketch
         // below while the host reads them and enqueues the next iteration.
         int *hdev = (int *)h->host_iter_dev;
-        CKT(FRSVT_K_REDUCE, launch_finish_iter(zp, nz, h->dstatus, 8, hdev, (double *)(hdev + 8), s));
+        CKT(FRSVT_K_REDUCE, launch_finish_iter(zp, nz, h->dstatus, 8, hdev, (double *)(hdev + 8),
+                                               op.use_frsvt ? reinterpret_cast<const double *>(h->dstatus + kResidSlot)
+                                                            : nullptr,
+                                               (double *)(hdev + 10), s));
         if (!h->ev_iter) CK(hipEventCreateWithFlags(&h->ev_iter, hipEventDisableTiming));
         CK(hipEventRecord(h->ev_iter, s));
         // the next sketch is completed (or run) before the host waits for
@@ -1270,6 +1277,14 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
         const int zw[2] = {hst[8], hst[9]};
         memcpy(&zz, zw, sizeof(double));
         (void)zsum;
+        if (stats && it < 64 && op.use_frsvt) {
+            // Prop. 4 with Lemma 3 (alpha = 20): an upper bound on
+            // sigma_{r+1} of this iteration's A with probability >= 0.95
+            const int rw[2] = {hst[10], hst[11]};
+            double r2;
+            memcpy(&r2, rw, sizeof(double));
+            stats->resid_est[it] = r2 < 0.0 ? -1.0 : 20.0 * std::sqrt(2.0 / 3.14159265358979323846) * std::sqrt(r2);
+        }
         resid = std::sqrt(zz) / normF;
         if (stats && it < 64) {
             stats->ranks[it] = r;

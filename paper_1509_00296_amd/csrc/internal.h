@@ -55,22 +55,30 @@ hipError_t launch_long(const LongPlan &plan, int mode, const LongArgs<T> &args, 
 // out[j] = sum_{g < nparts} part[g * count + j], fixed order.
 template <typename T>
 hipError_t launch_reduce(const T *part, int64_t count, int nparts, T *out, hipStream_t s);
-// sum of nparts doubles (the order of launch_reduce with count 1) and the
-// first nstatus status words, written to mapped host memory (device
-// pointers host_status, host_z)
+// sum of nparts doubles (the order of launch_reduce with count 1), the
+// first nstatus status words and the double *res (-1 when res is null),
+// written to mapped host memory (device pointers host_status, host_z,
+// host_res)
 hipError_t launch_finish_iter(const double *part, int nparts, const int *status, int nstatus,
-                              int *host_status, double *host_z, hipStream_t s);
+                              int *host_status, double *host_z, const double *res, double *host_res,
+                              hipStream_t s);
 
 // ------------------------------------------------------ one-workgroup CholeskyQR
 // Q = orth([Qt, Y]) with Qt (mh x rp) orthonormal and Y (mh x c):
 //  CGS2 of Y against Qt, column equilibration, shifted CholeskyQR, then
 //  CholeskyQR2 with refill of numerically null columns.  mh * (rp + c) must
-//  fit the LDS budget (small_orth_ok).
+//  fit the LDS budget (small_orth_ok).  resid2 (optional, device) receives
+//  the squared norm of the first new column after CGS2 (-1 when c = 0).
 bool small_orth_ok(int mh, int l);
 template <typename T>
 hipError_t launch_small_orth(int mh, const T *Qt, int64_t ldqt, int rp, const T *Y, int64_t ldy,
                              int c, T *Q, int64_t ldq, uint64_t seed, uint64_t counter,
-                             int *flags, hipStream_t s);
+                             int *flags, double *resid2, hipStream_t s);
+// The same squared residual for a basis block Q = [Qt (rp columns), samples
+// (c columns)] (two classical Gram-Schmidt passes of column rp against the
+// first rp columns); -1 when c = 0.  (mh + rp) doubles of LDS, at most 64 KB.
+template <typename T>
+hipError_t launch_resid_est(int mh, const T *Q, int64_t ldq, int rp, int c, double *out, hipStream_t s);
 
 // ------------------------------------------------------------- small SVD
 // From the l x l Gram G = B B^T (double): semidefinite Cholesky G = R^T R,

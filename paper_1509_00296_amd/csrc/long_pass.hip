@@ -868,7 +868,8 @@ __global__ void __launch_bounds__(1024) k_reduce_scalar(const T *part, int64_t c
 // nstatus status words straight to mapped host memory, so that the host
 // reads them after an event without a copy on the stream.
 __global__ void __launch_bounds__(1024) k_finish_iter(const double *part, int nparts, const int *status,
-                                                      int nstatus, int *host_status, double *host_z)
+                                                      int nstatus, int *host_status, double *host_z,
+                                                      const double *res, double *host_res)
 {
     __shared__ double red[16];
     double s = 0.0;
@@ -881,14 +882,17 @@ __global__ void __launch_bounds__(1024) k_finish_iter(const double *part, int np
         for (int w = 0; w < 16; ++w) t += red[w];
         for (int i = 0; i < nstatus; ++i) host_status[i] = status[i];
         *host_z = t;
+        if (host_res) *host_res = res ? *res : -1.0;
         __threadfence_system();
     }
 }
 
 hipError_t launch_finish_iter(const double *part, int nparts, const int *status, int nstatus,
-                              int *host_status, double *host_z, hipStream_t s)
+                              int *host_status, double *host_z, const double *res, double *host_res,
+                              hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finish_iter, dim3(1), dim3(1024), 0, s, part, nparts, status, nstatus, host_status, host_z);
+    hipLaunchKernelGGL(k_finish_iter, dim3(1), dim3(1024), 0, s, part, nparts, status, nstatus, host_status, host_z,
+                       res, host_res);
     return hipGetLastError();
 }
 

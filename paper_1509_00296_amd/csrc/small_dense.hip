@@ -37,7 +37,7 @@ template <typename T, int NT, int LM>
 __global__ void __launch_bounds__(NT) k_small_orth(int mh, const T *Qt, int64_t ldqt, int rp,
                                                    const T *Y, int64_t ldy, int c, T *Q,
                                                    int64_t ldq, uint64_t seed, uint64_t counter,
-                                                   int *flags)
+                                                   int *flags, double *resid2)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int l = rp + c;
@@ -90,6 +90,9 @@ __global__ void __launch_bounds__(NT) k_small_orth(int mh, const T *Qt, int64_t 
         // 2. equilibration from the Gram's diagonal; the Gram of the scaled
         //    basis is the scaled Gram
         gram16_mfma(W, mh, mhp, l, G, part);
+        // the first new column's squared residual against Qt (its norm when
+        // nothing is propagated): Prop. 4's by-product
+        if (resid2 && tid == 0) *resid2 = c > 0 ? G[rp * l + rp] : -1.0;
         for (int j = tid; j < l; j += NT) {
             const double d = G[j * l + j];
             scal[j] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
@@ -156,8 +159,12 @@ __global__ void __launch_bounds__(NT) k_small_orth(int mh, const T *Qt, int64_t 
             double s = 0.0;
             for (int i = lane; i < mh; i += kWave) s += wj[i] * wj[i];
             s = wave_sum(s);
-            if (lane == 0) scal[j] = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+            if (lane == 0) {
+                scal[j] = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+                if (resid2 && j == rp) *resid2 = s;
+            }
         }
+        if (resid2 && c == 0 && tid == 0) *resid2 = -1.0;
         __syncthreads();
         for (int idx = tid; idx < mh * l; idx += NT) {
             const int i = idx % mh, j = idx / mh;
@@ -245,21 +252,77 @@ __global__ void __launch_bounds__(NT) k_small_orth(int mh, const T *Qt, int64_t 
 template <typename T>
 hipError_t launch_small_orth(int mh, const T *Qt, int64_t ldqt, int rp, const T *Y, int64_t ldy,
                              int c, T *Q, int64_t ldq, uint64_t seed, uint64_t counter, int *flags,
-                             hipStream_t s)
+                             double *resid2, hipStream_t s)
 {
     const int l = rp + c;
     if (!small_orth_ok(mh, l)) return hipErrorInvalidValue;
     const size_t lds = (2 * (size_t)l * (mh | 1) + 2 * (size_t)l * l + 4 * 256) * sizeof(double);
     if (l <= 8)
         hipLaunchKernelGGL((k_small_orth<T, 256, 8>), dim3(1), dim3(256), lds, s, mh, Qt, ldqt, rp, Y,
-                           ldy, c, Q, ldq, seed, counter, flags);
+                           ldy, c, Q, ldq, seed, counter, flags, resid2);
     else
         hipLaunchKernelGGL((k_small_orth<T, 256, 16>), dim3(1), dim3(256), lds, s, mh, Qt, ldqt, rp, Y,
-                           ldy, c, Q, ldq, seed, counter, flags);
+                           ldy, c, Q, ldq, seed, counter, flags, resid2);
     return hipGetLastError();
 }
-template hipError_t launch_small_orth<double>(int, const double *, int64_t, int, const double *, int64_t, int, double *, int64_t, uint64_t, uint64_t, int *, hipStream_t);
-template hipError_t launch_small_orth<float>(int, const float *, int64_t, int, const float *, int64_t, int, float *, int64_t, uint64_t, uint64_t, int *, hipStream_t);
+template hipError_t launch_small_orth<double>(int, const double *, int64_t, int, const double *, int64_t, int, double *, int64_t, uint64_t, uint64_t, int *, double *, hipStream_t);
+template hipError_t launch_small_orth<float>(int, const float *, int64_t, int, const float *, int64_t, int, float *, int64_t, uint64_t, uint64_t, int *, double *, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Prop. 4's residual where the basis is orthonormalised without an explicit
+// Gram-Schmidt step (the large path): column rp of Q (the first new sample)
+// against columns 0 .. rp-1 (the propagated basis), two classical
+// Gram-Schmidt passes; the squared norm goes to out, -1 without a new
+// sample.  Wavefront w forms the inner products of columns w, w + 4, ...
+// (lanes over rows), then every thread updates its rows.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_resid_est(int mh, const T *Q, int64_t ldq, int rp, int c, double *out)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double *y = reinterpret_cast<double *>(smem_raw);
+    double *d = y + mh;
+    __shared__ double red[4];
+    const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+    if (c <= 0) {
+        if (tid == 0) *out = -1.0;
+        return;
+    }
+    for (int i = tid; i < mh; i += 256) y[i] = (double)Q[i + (int64_t)rp * ldq];
+    __syncthreads();
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int t = wave; t < rp; t += 4) {
+            double s = 0.0;
+            for (int i = lane; i < mh; i += kWave) s += (double)Q[i + (int64_t)t * ldq] * y[i];
+            s = wave_sum(s);
+            if (lane == 0) d[t] = s;
+        }
+        __syncthreads();
+        for (int i = tid; i < mh; i += 256) {
+            double v = y[i];
+            for (int t = 0; t < rp; ++t) v -= (double)Q[i + (int64_t)t * ldq] * d[t];
+            y[i] = v;
+        }
+        __syncthreads();
+    }
+    double s = 0.0;
+    for (int i = tid; i < mh; i += 256) s += y[i] * y[i];
+    s = wave_sum(s);
+    if (lane == 0) red[wave] = s;
+    __syncthreads();
+    if (tid == 0) *out = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+template <typename T>
+hipError_t launch_resid_est(int mh, const T *Q, int64_t ldq, int rp, int c, double *out, hipStream_t s)
+{
+    const size_t lds = ((size_t)mh + (size_t)std::max(rp, 1)) * sizeof(double);
+    if (mh < 1 || rp < 0 || ldq < mh || lds > 64 * 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_resid_est<T>), dim3(1), dim3(256), lds, s, mh, Q, ldq, rp, c, out);
+    return hipGetLastError();
+}
+template hipError_t launch_resid_est<double>(int, const double *, int64_t, int, int, double *, hipStream_t);
+template hipError_t launch_resid_est<float>(int, const float *, int64_t, int, int, double *, hipStream_t);
 
 // ===========================================================================
 // Small SVD of B from G = B B^T (Alg. 1's QR of A^T Q, polar and eigen steps reformulated):

@@ -182,18 +182,30 @@ def test_rpca_small_matches_oracle(fr, orc, mode, m, n):
     assert res.ranks == list(out["ranks"][:64])
     if mode == "frsvt":
         assert res.widths == list(out["widths"][:64])
+        _resid_est_close(res.resid_est, out["resid_est"][:64])
     assert _rel(res.L.cpu().numpy(), out["L"]) <= 1e-10
     assert _rel(res.S.cpu().numpy(), out["S"]) <= 1e-10
     assert res.converged
     assert np.linalg.norm(res.L.cpu().numpy() - Lgt) / np.linalg.norm(Lgt) < 1e-4
 
 
-@pytest.mark.parametrize("m,n,gamma", [(3000, 60, 1.0), (60, 3000, 1.0), (3000, 60, 0.05)])
+def _resid_est_close(got, want):
+    got, want = np.asarray(got), np.asarray(want)
+    assert np.array_equal(got < 0, want < 0)
+    ok = want >= 0
+    assert np.all(np.abs(got[ok] - want[ok]) <= 1e-8 * want[ok])
+
+
+@pytest.mark.parametrize("m,n,gamma", [(3000, 60, 1.0), (60, 3000, 1.0), (3000, 60, 0.05),
+                                       (2000, 600, 1.0)])
 def test_rpca_adaptive_rank_prediction_matches_oracle(fr, orc, m, n, gamma):
     """Sketch widths by adaptive rank prediction (Sec. 2.3, Eq. 7; a = 2,
     rho = 0.05): the same width and rank sequences as the oracle, L and S
-    within 1e-10.  gamma = 0.05 bounds the width at the true rank 3, so the
-    later iterations take no new sample (the propagated basis alone)."""
+    within 1e-10, and Prop. 4's residual estimate per iteration.
+    gamma = 0.05 bounds the width at the true rank 3, so the later
+    iterations take no new sample (the propagated basis alone); 2000 x 600
+    runs the large path (short side above 512) and reaches the ceil(rho mhat)
+    branch of Eq. 7."""
     from paper_1509_00296_amd import synth
     _say(f"case rpca ap {m}x{n} gamma={gamma}")
     O, Lgt, _ = synth.rpca(seed=3, m=m, n=n, rank=3, frac=0.10)
@@ -203,6 +215,7 @@ def test_rpca_adaptive_rank_prediction_matches_oracle(fr, orc, m, n, gamma):
     assert res.iters == out["iters"]
     assert res.ranks == list(out["ranks"][:64])
     assert res.widths == list(out["widths"][:64])
+    _resid_est_close(res.resid_est, out["resid_est"][:64])
     assert _rel(res.L.cpu().numpy(), out["L"]) <= 1e-10
     assert _rel(res.S.cpu().numpy(), out["S"]) <= 1e-10
     assert res.converged
@@ -235,6 +248,8 @@ def test_rpca_video_shape_matches_oracle(fr, orc):
     out = orc.rpca_ialm(O, lam, mode="frsvt", p=5, q=1, seed=2024)
     assert res.iters == out["iters"]
     assert res.ranks == list(out["ranks"][:64])
+    assert res.widths == list(out["widths"][:64])
+    _resid_est_close(res.resid_est, out["resid_est"][:64])
     assert _rel(res.L.cpu().numpy(), out["L"]) <= 1e-10
     assert _rel(res.S.cpu().numpy(), out["S"]) <= 1e-10
     # identical sparsity pattern of S

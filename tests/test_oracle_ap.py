@@ -53,3 +53,37 @@ def test_ap_matches_exact_ialm(orc, problem):
     assert ap["widths"].max() <= 6
     assert np.linalg.norm(ap["L"] - ex["L"]) / np.linalg.norm(ex["L"]) < 1e-6
     assert np.linalg.norm(ap["L"] - Lgt) / np.linalg.norm(Lgt) < 1e-4
+
+
+def test_residual_estimate_prop4(orc):
+    """Prop. 4 (with Lemma 3): for Q~ spanning the top-r left singular
+    vectors of Ahat, ||(I - Q~Q~^T) Ahat omega|| <= sigma_{r+1} ||omega||
+    always, and alpha sqrt(2/pi) ||(I - Q~Q~^T) Ahat omega|| >= sigma_{r+1}
+    with probability >= 1 - 1/alpha; a basis of the whole range gives 0."""
+    rng = np.random.default_rng(5)
+    m, n, r, alpha = 400, 120, 5, 20.0
+    U, _ = np.linalg.qr(rng.standard_normal((m, n)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    s = np.geomspace(100.0, 0.1, n)
+    A = np.asfortranarray((U * s) @ V.T)          # m > n: Ahat = A^T, its left vectors are V
+    Q = np.asfortranarray(V[:, :r])
+    c = alpha * math.sqrt(2.0 / math.pi)
+    hits = 0
+    for _ in range(200):
+        om = rng.standard_normal(m)
+        est = orc.residual_estimate(A, Q, om, alpha)
+        assert est / c <= s[r] * np.linalg.norm(om) * (1 + 1e-12)
+        hits += est >= s[r]
+    assert hits >= 190
+    full = orc.residual_estimate(A, np.asfortranarray(V), rng.standard_normal(m), alpha)
+    assert full <= 1e-10 * s[0]
+
+
+def test_rpca_reports_residual_estimate(orc, problem):
+    O, _, lam = problem
+    out = orc.rpca_ialm(O, lam, mode="frsvt", q=1, seed=17, ap=True, ap_gamma=0.05)  # b = 3
+    est, w, r = out["resid_est"], out["widths"], out["ranks"]
+    # a sample is drawn exactly when the width exceeds the propagated rank
+    prev = np.concatenate([[0], r[:-1]])
+    assert np.array_equal(est < 0, w == prev)
+    assert np.all(est[est >= 0] > 0)
