@@ -337,6 +337,18 @@ typedef struct {
     int32_t ap_a;          /* a >= 1 (2) */
     double ap_rho;         /* rho in (0, 1] (0.05) */
     double ap_gamma;       /* gamma in (0, 1] (1.0) */
+    /* Partial SVT (the truncated nuclear norm, Type B of Table 6): the
+     * largest keep singular values pass unshrunk, the rest by 1/mu (0: SVT). */
+    int32_t keep;
+    /* Semi-online use over consecutive observations (Sec. 4, Type B): an
+     * initial propagated basis for the first FRSVT call (DEVICE, mhat x
+     * r_init, leading dimension mhat, orthonormal columns, same precision as
+     * O; r_init = 0: a fresh first sketch), and optionally the propagated
+     * basis of the last call (DEVICE, mhat x mhat capacity, leading dimension
+     * mhat; its column count is stats->ranks of the last iteration). */
+    const void *q_init;
+    int32_t r_init;
+    void *q_final;
 } frsvt_rpca_opts;
 
 typedef struct {

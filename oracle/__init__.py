@@ -66,8 +66,10 @@ def _bind(path: str):
                                          _i64, ctypes.c_int, ctypes.c_uint64, ctypes.c_double,
                                          ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_double, ctypes.c_int, _i64, ctypes.c_double,
-                                         ctypes.c_double, _dp, _i64, _dp, _i64, _i64p, _i64p,
-                                         _dp, _dp, ctypes.POINTER(ctypes.c_int)]
+                                         ctypes.c_double, _i64, _dp, _i64, _dp, _i64p, _dp, _i64,
+                                         _dp, _i64, _i64p, _i64p, _dp, _dp,
+                                         ctypes.POINTER(ctypes.c_int)]
+        lib.orc_psvt.argtypes = [_i64, _i64, _dp, _i64, ctypes.c_double, _i64, _dp, _i64, _i64p]
         lib.orc_residual_estimate.argtypes = [_i64, _i64, _dp, _i64, _dp, _i64, _i64, _dp,
                                               ctypes.c_double]
         lib.orc_residual_estimate.restype = ctypes.c_double
@@ -244,12 +246,16 @@ def frsvt(A, tau: float, q: int, Omega, Qprev=None):
 def rpca_ialm(O, lam: float, mode: str = "frsvt", p: int = 5, q: int = 1, seed: int = 0,
               tol: float = 1e-7, max_iter: int = 60, mu0: float = 0.0, rho: float = 1.5,
               mu_bar_factor: float = 1e7, ap: bool = False, ap_a: int = 2, ap_rho: float = 0.05,
-              ap_gamma: float = 1.0):
+              ap_gamma: float = 1.0, keep: int = 0, q_init=None):
     """Inexact-ALM RPCA; mode 'exact' (SVT by full SVD) or 'frsvt' (FRSVT + RP),
     with the sketch widths of adaptive rank prediction (Sec. 2.3, Eq. 7) when
     ap is set.
 
-    Returns dict(L, S, ranks, widths, resid, iters, converged)."""
+    keep > 0 selects partial SVT (the keep largest singular values unshrunk);
+    q_init (mhat x r) is the first call's propagated basis (semi-online use).
+
+    Returns dict(L, S, ranks, widths, resid_est, resid, iters, converged, Q)
+    with Q the last propagated basis."""
     O = _f(O)
     m, n = O.shape
     L = np.zeros((m, n), order="F")
@@ -258,16 +264,38 @@ def rpca_ialm(O, lam: float, mode: str = "frsvt", p: int = 5, q: int = 1, seed: 
     widths = np.zeros(max_iter, dtype=np.int64)
     resid_est = np.zeros(max_iter)
     resid = np.zeros(max_iter)
+    mh = min(m, n)
+    Qf = np.zeros((mh, mh), order="F")
+    rf = _i64()
+    if q_init is None:
+        Qi, ri = np.zeros((mh, 1), order="F"), 0
+    else:
+        Qi = _f(q_init)
+        assert Qi.shape[0] == mh
+        ri = Qi.shape[1]
     it = ctypes.c_int()
     rc = _L().orc_rpca_ialm_ap(m, n, _p(O), m, lam, 0 if mode == "exact" else 1, p, q, seed,
                                tol, max_iter, mu0, rho, mu_bar_factor, int(ap), ap_a, ap_rho,
-                               ap_gamma, _p(L), m, _p(S), m, ranks.ctypes.data_as(_i64p),
+                               ap_gamma, keep, _p(Qi), ri, _p(Qf), ctypes.byref(rf),
+                               _p(L), m, _p(S), m, ranks.ctypes.data_as(_i64p),
                                widths.ctypes.data_as(_i64p), _p(resid_est), _p(resid),
                                ctypes.byref(it))
     _check(rc, "rpca_ialm")
     k = int(it.value)
     return dict(L=L, S=S, ranks=ranks[:k], widths=widths[:k], resid_est=resid_est[:k],
-                resid=resid[:k], iters=k, converged=(rc == 0))
+                resid=resid[:k], iters=k, converged=(rc == 0),
+                Q=np.asfortranarray(Qf[:, :int(rf.value)]))
+
+
+def psvt(A, tau: float, keep: int):
+    """Partial SVT: the keep largest singular values unshrunk, the rest
+    soft-thresholded by tau.  Returns X, rank."""
+    A = _f(A)
+    m, n = A.shape
+    X = np.zeros((m, n), order="F")
+    r = _i64()
+    _check(_L().orc_psvt(m, n, _p(A), m, tau, keep, _p(X), m, ctypes.byref(r)), "psvt")
+    return X, int(r.value)
 
 
 def residual_estimate(A, Qt, omega, alpha: float = 20.0) -> float:

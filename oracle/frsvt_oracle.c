@@ -431,6 +431,32 @@ int orc_svt(int64_t m, int64_t n, const double *A, int64_t lda, double tau, doub
     return sweeps >= 1000 ? 1 : 0;
 }
 
+/* Partial SVT (the proximal step of the truncated nuclear norm, Type B of
+ * Table 6): the keep largest singular values pass unshrunk, the others are
+ * soft-thresholded by tau; rank counts the nonzero results. */
+int orc_psvt(int64_t m, int64_t n, const double *A, int64_t lda, double tau, int64_t keep,
+             double *X, int64_t ldx, int64_t *rank)
+{
+    if (m < 1) return -1;
+    if (n < 1) return -2;
+    if (lda < m) return -4;
+    if (!(tau >= 0.0)) return -5;
+    if (keep < 0) return -6;
+    if (ldx < m) return -8;
+    int64_t k = m < n ? m : n;
+    double *U = dalloc(m * k), *S = dalloc(k), *V = dalloc(n * k), *shr = dalloc(k);
+    int sweeps = orc_svd(m, n, A, lda, U, m, S, V, n);
+    int64_t r = 0;
+    for (int64_t i = 0; i < k; ++i) {
+        shr[i] = i < keep ? S[i] : soft_shrink(S[i], tau);
+        if (shr[i] > 0.0) ++r;
+    }
+    rank_sum(m, n, r, U, m, shr, V, n, X, ldx);
+    if (rank) *rank = r;
+    free(U); free(S); free(V); free(shr);
+    return sweeps >= 1000 ? 1 : 0;
+}
+
 /* Weighted SVT (the WSVT of the weighted nuclear norm named in Sec. 1 and
  * footnote 1): threshold the i-th largest singular value by w_i. */
 int orc_wsvt(int64_t m, int64_t n, const double *A, int64_t lda, const double *w, double *X,
@@ -522,10 +548,10 @@ static void partial_orthogonalisation(int64_t m, double *Q, int64_t ldq, int64_t
     free(missing);
 }
 
-int orc_frsvt(int64_t m, int64_t n, const double *A, int64_t lda, double tau, int q,
-              const double *Om, int64_t ldom, int64_t nomega, const double *Qt,
-              int64_t ldqt, int64_t r_prev, double *X, int64_t ldx, double *Qout,
-              int64_t ldqo, int64_t *r_out, double *sigma, int64_t *s_out)
+int orc_frsvt_keep(int64_t m, int64_t n, const double *A, int64_t lda, double tau, int64_t keep,
+                   int q, const double *Om, int64_t ldom, int64_t nomega, const double *Qt,
+                   int64_t ldqt, int64_t r_prev, double *X, int64_t ldx, double *Qout,
+                   int64_t ldqo, int64_t *r_out, double *sigma, int64_t *s_out)
 {
     if (m < 1) return -1;
     if (n < 1) return -2;
@@ -594,12 +620,13 @@ int orc_frsvt(int64_t m, int64_t n, const double *A, int64_t lda, double tau, in
     int sweeps = orc_svd(s, s, C, s, UC, s, D, VC, s);
 
     /* Reconstruction, Eq. (6): S_tau(A) ~ (Q V) S_tau(D) (H W V)^T, keeping the r
-     * singular values above tau (Sec. 2.3 defines r this way). */
+     * singular values above tau (Sec. 2.3 defines r this way); with keep > 0
+     * the keep largest pass unshrunk (partial SVT). */
     int64_t r = 0;
     double *shr = dalloc(s);
     for (int64_t i = 0; i < s; ++i) {
-        shr[i] = soft_shrink(D[i], tau);
-        if (D[i] > tau) ++r;
+        shr[i] = i < keep ? D[i] : soft_shrink(D[i], tau);
+        if (shr[i] > 0.0) ++r;
     }
     double *QV = dalloc(mh * s), *HWV = dalloc(nh * s), *Xh = dalloc(mh * nh);
     mat_mul(mh, s, s, Q, mh, VC, s, QV, mh);
@@ -617,6 +644,15 @@ int orc_frsvt(int64_t m, int64_t n, const double *A, int64_t lda, double tau, in
     free(Ah); free(Q); free(Z); free(Y); free(Rtmp); free(H); free(C);
     free(UC); free(VC); free(D); free(shr); free(QV); free(HWV); free(Xh);
     return sweeps >= 1000 ? 1 : 0;
+}
+
+int orc_frsvt(int64_t m, int64_t n, const double *A, int64_t lda, double tau, int q,
+              const double *Om, int64_t ldom, int64_t nomega, const double *Qt,
+              int64_t ldqt, int64_t r_prev, double *X, int64_t ldx, double *Qout,
+              int64_t ldqo, int64_t *r_out, double *sigma, int64_t *s_out)
+{
+    return orc_frsvt_keep(m, n, A, lda, tau, 0, q, Om, ldom, nomega, Qt, ldqt, r_prev, X, ldx, Qout,
+                          ldqo, r_out, sigma, s_out);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -664,8 +700,9 @@ double orc_residual_estimate(int64_t m, int64_t n, const double *A, int64_t lda,
 int orc_rpca_ialm_ap(int64_t m, int64_t n, const double *O, int64_t ldo, double lambda,
                      int svt_mode, int64_t p, int q, uint64_t seed, double tol, int max_iter,
                      double mu0, double rho, double mu_bar_factor, int ap, int64_t ap_a,
-                     double ap_rho, double ap_gamma, double *L, int64_t ldl, double *S,
-                     int64_t lds, int64_t *ranks, int64_t *widths, double *resid_est,
+                     double ap_rho, double ap_gamma, int64_t keep, const double *Qinit,
+                     int64_t r_init, double *Qfinal, int64_t *r_final, double *L, int64_t ldl,
+                     double *S, int64_t lds, int64_t *ranks, int64_t *widths, double *resid_est,
                      double *resid, int *iters)
 {
     if (m < 1) return -1;
@@ -676,6 +713,7 @@ int orc_rpca_ialm_ap(int64_t m, int64_t n, const double *O, int64_t ldo, double 
     if (svt_mode == 1 && p < 1 && !ap) return -7;
     if (max_iter < 1) return -11;
     if (ap && (ap_a < 1 || !(ap_rho > 0.0) || !(ap_gamma > 0.0) || ap_gamma > 1.0)) return -15;
+    if (keep < 0) return -19;
     const int64_t mn = m * n;
     const int64_t mh = m < n ? m : n, nh = m < n ? n : m;
 
@@ -703,7 +741,13 @@ int orc_rpca_ialm_ap(int64_t m, int64_t n, const double *O, int64_t ldo, double 
 
     double *Qt = dalloc(mh * mh), *Qnew = dalloc(mh * mh);
     int64_t r_prev = -1; /* -1: no propagated basis yet */
-    int64_t bmax = mh, l_prev = 0;
+    if (svt_mode == 1 && Qinit && r_init > 0) {
+        /* semi-online: the caller's basis is the first call's propagated basis */
+        if (r_init > mh) { free(Qt); free(Qnew); free(Y); free(A); free(Lk); free(Sk); return -20; }
+        mat_copy(mh, r_init, Qinit, mh, Qt, mh);
+        r_prev = r_init;
+    }
+    int64_t bmax = mh, l_prev = r_prev > 0 ? r_prev : 0;
     if (ap) {
         bmax = (int64_t)ceil(ap_gamma * (double)mh);
         if (bmax < 1) bmax = 1;
@@ -720,7 +764,7 @@ int orc_rpca_ialm_ap(int64_t m, int64_t n, const double *O, int64_t ldo, double 
                 AT(A, m, i, j) = AT(O, ldo, i, j) - AT(Sk, m, i, j) + AT(Y, m, i, j) / mu;
         int64_t r = 0;
         if (svt_mode == 0) {
-            orc_svt(m, n, A, m, 1.0 / mu, Lk, m, &r);
+            orc_psvt(m, n, A, m, 1.0 / mu, keep, Lk, m, &r);
         } else {
             int64_t nomega;
             const double *Qprop = NULL;
@@ -753,8 +797,8 @@ int orc_rpca_ialm_ap(int64_t m, int64_t n, const double *O, int64_t ldo, double 
                 resid_est[it] = nomega > 0 ? orc_residual_estimate(m, n, A, m, Qt, mh, Qprop ? r_prev : 0,
                                                                    Om, 20.0)
                                            : -1.0;
-            orc_frsvt(m, n, A, m, 1.0 / mu, q, Om, nh, nomega, Qprop, mh,
-                      Qprop ? r_prev : 0, Lk, m, Qnew, mh, &r, NULL, NULL);
+            orc_frsvt_keep(m, n, A, m, 1.0 / mu, keep, q, Om, nh, nomega, Qprop, mh,
+                           Qprop ? r_prev : 0, Lk, m, Qnew, mh, &r, NULL, NULL);
             free(Om);
             mat_copy(mh, r, Qnew, mh, Qt, mh);
             r_prev = r;
@@ -781,6 +825,8 @@ int orc_rpca_ialm_ap(int64_t m, int64_t n, const double *O, int64_t ldo, double 
         }
     }
     if (iters) *iters = it;
+    if (r_final) *r_final = svt_mode == 1 && r_prev > 0 ? r_prev : 0;
+    if (Qfinal && svt_mode == 1 && r_prev > 0) mat_copy(mh, r_prev, Qt, mh, Qfinal, mh);
     mat_copy(m, n, Lk, m, L, ldl);
     mat_copy(m, n, Sk, m, S, lds);
     free(Y); free(A); free(Lk); free(Sk); free(Qt); free(Qnew);
@@ -793,8 +839,8 @@ int orc_rpca_ialm(int64_t m, int64_t n, const double *O, int64_t ldo, double lam
                   double *S, int64_t lds, int64_t *ranks, double *resid, int *iters)
 {
     return orc_rpca_ialm_ap(m, n, O, ldo, lambda, svt_mode, p, q, seed, tol, max_iter, mu0, rho,
-                            mu_bar_factor, 0, 0, 0.0, 0.0, L, ldl, S, lds, ranks, NULL, NULL, resid,
-                            iters);
+                            mu_bar_factor, 0, 0, 0.0, 0.0, 0, NULL, 0, NULL, NULL, L, ldl, S, lds,
+                            ranks, NULL, NULL, resid, iters);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -105,9 +105,23 @@ int orc_rpca_ialm(int64_t m, int64_t n, const double *O, int64_t ldo, double lam
 int orc_rpca_ialm_ap(int64_t m, int64_t n, const double *O, int64_t ldo, double lambda,
                      int svt_mode, int64_t p, int q, uint64_t seed, double tol, int max_iter,
                      double mu0, double rho, double mu_bar_factor, int ap, int64_t ap_a,
-                     double ap_rho, double ap_gamma, double *L, int64_t ldl, double *S,
-                     int64_t lds, int64_t *ranks, int64_t *widths, double *resid_est,
+                     double ap_rho, double ap_gamma, int64_t keep, const double *Qinit,
+                     int64_t r_init, double *Qfinal, int64_t *r_final, double *L, int64_t ldl,
+                     double *S, int64_t lds, int64_t *ranks, int64_t *widths, double *resid_est,
                      double *resid, int *iters);
+
+/* Partial SVT: the keep largest singular values pass unshrunk, the others
+ * are soft-thresholded by tau (the truncated nuclear norm's proximal step).
+ * orc_frsvt_keep is orc_frsvt with that thresholding; orc_rpca_ialm_ap uses
+ * it (and orc_psvt in the exact mode) with its keep argument, starts from
+ * the propagated basis Qinit (mhat x r_init, ld mhat) when r_init > 0, and
+ * returns the last propagated basis in Qfinal (mhat x *r_final, ld mhat). */
+int orc_psvt(int64_t m, int64_t n, const double *A, int64_t lda, double tau, int64_t keep,
+             double *X, int64_t ldx, int64_t *rank);
+int orc_frsvt_keep(int64_t m, int64_t n, const double *A, int64_t lda, double tau, int64_t keep,
+                   int q, const double *Om, int64_t ldom, int64_t nomega, const double *Qt,
+                   int64_t ldqt, int64_t r_prev, double *X, int64_t ldx, double *Qout,
+                   int64_t ldqo, int64_t *r_out, double *sigma, int64_t *s_out);
 
 /* Prop. 4's residual singular-value estimate alpha sqrt(2/pi)
  * ||(I - Q~ Q~^T) Ahat omega||_2 (Ahat = A if m <= n, else A^T; Q~ mhat x r

@@ -38,7 +38,8 @@ class RpcaOpts(ctypes.Structure):
     _fields_ = [("tol", _dbl), ("max_iter", _i32), ("mu0", _dbl), ("rho", _dbl),
                 ("mu_bar_factor", _dbl), ("use_frsvt", _i32), ("p", _i32), ("q", _i32),
                 ("l0", _i32), ("seed", _u64), ("ap", _i32), ("ap_a", _i32), ("ap_rho", _dbl),
-                ("ap_gamma", _dbl)]
+                ("ap_gamma", _dbl), ("keep", _i32), ("q_init", ctypes.c_void_p), ("r_init", _i32),
+                ("q_final", ctypes.c_void_p)]
 
 
 class RpcaStats(ctypes.Structure):
@@ -316,16 +317,22 @@ class RpcaResult:
     residuals: list = field(default_factory=list)
     widths: list = field(default_factory=list)
     resid_est: list = field(default_factory=list)
+    Q: object = None
 
 
 def rpca_ialm(O, lam: float, *, use_frsvt: bool = True, tol: float = 1e-7, max_iter: int = 60,
               mu0: float = 0.0, rho: float = 1.5, mu_bar_factor: float = 1e7, p: int = 5,
               q: int = 1, l0: int = 0, seed: int = 0, ap: bool = False, ap_a: int = 2,
-              ap_rho: float = 0.05, ap_gamma: float = 1.0) -> RpcaResult:
+              ap_rho: float = 0.05, ap_gamma: float = 1.0, keep: int = 0, q_init=None,
+              return_basis: bool = False) -> RpcaResult:
     """Inexact-ALM RPCA (the host of Sec. 4.1) with FRSVT + range propagation
     or exact SVT.  O is a GPU tensor (m x n).  With ap the sketch widths follow
     adaptive rank prediction (Sec. 2.3, Eq. 7: a, rho, gamma) instead of p
-    new samples per iteration."""
+    new samples per iteration.  keep > 0 selects partial SVT (the keep largest
+    singular values unshrunk: the truncated nuclear norm).  q_init (GPU, mhat x
+    r, orthonormal columns) is the first call's propagated basis and
+    return_basis returns the last one in .Q (semi-online use)."""
+    import torch
     h = handle(O.device.index)
     m, n, ldo, tr = _colmajor(O)
     L = _like(O, tr)
@@ -337,15 +344,63 @@ def rpca_ialm(O, lam: float, *, use_frsvt: bool = True, tol: float = 1e-7, max_i
     op.tol, op.max_iter, op.mu0, op.rho, op.mu_bar_factor = tol, max_iter, mu0, rho, mu_bar_factor
     op.use_frsvt, op.p, op.q, op.l0, op.seed = int(use_frsvt), p, q, l0, seed
     op.ap, op.ap_a, op.ap_rho, op.ap_gamma = int(ap), ap_a, ap_rho, ap_gamma
+    op.keep = keep
+    mh = min(m, n)
+    qi = None
+    if q_init is not None:
+        if q_init.dim() != 2 or q_init.shape[0] != mh or q_init.dtype != O.dtype or \
+                q_init.device != O.device:
+            raise ValueError("q_init must be a GPU tensor of shape (min(m, n), r) with the dtype of O")
+        qi = q_init.t().contiguous().t()          # column-major, leading dimension mhat
+        op.q_init, op.r_init = qi.data_ptr(), qi.shape[1]
+    qf = None
+    if return_basis and use_frsvt:
+        qf = torch.empty((mh, mh), dtype=O.dtype, device=O.device).t()   # column-major
+        op.q_final = qf.data_ptr()
     st = RpcaStats()
     rc = h.lib.rpca_ialm(h.ptr, _prec(O), m, n, O.data_ptr(), ldo, float(lam), ctypes.byref(op),
                          L.data_ptr(), ldl, S.data_ptr(), lds, ctypes.byref(st))
     _check(h, rc, "rpca_ialm", ok=(OK, MAX_ITER))
     k = min(st.iters, 64)
+    Qf = qf[:, :st.ranks[k - 1]] if (qf is not None and k > 0) else None
     return RpcaResult(L, S, st.iters, bool(st.converged), st.residual, st.norm2, st.seconds,
                       list(st.ranks[:k]), list(st.residuals[:k]),
                       list(st.widths[:k]) if use_frsvt else [],
-                      list(st.resid_est[:k]) if use_frsvt else [])
+                      list(st.resid_est[:k]) if use_frsvt else [], Qf)
+
+
+def rpca_sliding(frames, n: int, lam=None, *, keep: int = 1, l: int = 3, q: int = 2,
+                 seed: int = 0, tol: float = 1e-7, max_iter: int = 60, rho: float = 1.5):
+    """Semi-online low-rank + sparse decomposition of a frame sequence (Sec. 4,
+    Type B of Table 6): consecutive windows of n frames (the columns of
+    frames, m x F on the GPU), each by the partial-SVT iALM (the keep largest
+    singular values unshrunk) with FRSVT, the sketch width bounded by l
+    (adaptive prediction, a = l - keep, b = l) and q power iterations; each
+    window starts from the previous window's propagated basis.  lam defaults
+    to 1/sqrt(max(m, n)).  Frames past the last whole window are left out.
+    Returns L, S (m x F, zero past the last window) and the per-window
+    results."""
+    import numpy as np
+    import torch
+    m, F = frames.shape
+    if n < 2 or n > F:
+        raise ValueError("window length n must lie in [2, number of frames]")
+    if not 1 <= keep < l <= n:
+        raise ValueError("need 1 <= keep < l <= n")
+    lam = 1.0 / float(np.sqrt(max(m, n))) if lam is None else lam
+    L = torch.zeros_like(frames)
+    S = torch.zeros_like(frames)
+    runs, basis = [], None
+    for w in range(F // n):
+        Ow = frames[:, w * n:(w + 1) * n]
+        res = rpca_ialm(Ow, lam, use_frsvt=True, tol=tol, max_iter=max_iter, rho=rho, q=q,
+                        seed=seed + w, ap=True, ap_a=l - keep, ap_gamma=l / n, keep=keep,
+                        q_init=basis, return_basis=True)
+        L[:, w * n:(w + 1) * n] = res.L
+        S[:, w * n:(w + 1) * n] = res.S
+        basis = res.Q if (res.Q is not None and res.Q.shape[1] > 0) else None
+        runs.append(res)
+    return L, S, runs
 
 
 # ---------------------------------------------------------------------------

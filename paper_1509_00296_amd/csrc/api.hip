@@ -222,6 +222,7 @@ struct Core {
     double *G, *U, *Mm, *sigma;
     int *status;         // device: [0] r, [1] sweeps, [2] converged, [4..] orth flags
     double *resid_out = nullptr;   // device, optional: squared residual of the first new sample (Prop. 4)
+    int keep = 0;        // partial SVT: the first keep singular values pass unshrunk
 };
 
 template <typename T>
@@ -547,7 +548,7 @@ int run_core(frsvt_context *h, Core<T> &c, CoreBuffers<T> &b)
     // Alg. 1, polar/eigen and reconstruction: small SVD, thresholds, factors
     SmallSvdOut so{b.sigma, b.U, b.Mm, c.status};
     const int fuse = small_svd_fuse_q_ok(mh, l) ? 1 : 0;
-    CKT(FRSVT_K_SMALL_SVD, launch_small_svd<T>(l, b.G, c.tau, c.w, b.Q, mh, mh, b.QM, mh, c.Qout, c.ldqo, so, b.jwork,
+    CKT(FRSVT_K_SMALL_SVD, launch_small_svd<T>(l, b.G, c.tau, c.w, c.keep, b.Q, mh, mh, b.QM, mh, c.Qout, c.ldqo, so, b.jwork,
                            fuse, s));
     if (!fuse) {
         // QM = Q Mm, Qout = Q U (double small factors cast through a copy)
@@ -600,7 +601,7 @@ int write_x(frsvt_context *h, const Core<T> &c, T *X, int64_t ldx, T *part)
 // Exact SVT / WSVT: G = Ahat Ahat^T, small SVD of size mh, X = Mm Ahat.
 template <typename T>
 int exact_factors(frsvt_context *h, const T *A, int64_t lda, const Orient &o, double tau,
-                  const double *w, Carver &cv, double **Mm_out, T **Mt_out)
+                  const double *w, Carver &cv, double **Mm_out, T **Mt_out, int keep = 0)
 {
     const int mh = o.mh;
     const int sk = gemm_splitk(mh, mh, o.nh, h->num_cu);
@@ -622,7 +623,7 @@ int exact_factors(frsvt_context *h, const T *A, int64_t lda, const Orient &o, do
                                                h->stream)));
     }
     SmallSvdOut so{sig, U, Mm, h->dstatus};
-    CKT(FRSVT_K_SMALL_SVD, launch_small_svd<T>(mh, G, tau, w, (const T *)nullptr, 0, mh, (T *)nullptr, 0,
+    CKT(FRSVT_K_SMALL_SVD, launch_small_svd<T>(mh, G, tau, w, keep, (const T *)nullptr, 0, mh, (T *)nullptr, 0,
                            (T *)nullptr, 0, so, jw, 0, h->stream));
     CKT(FRSVT_K_OTHER, launch_cast<T>(mh, mh, Mm, 1, mh, Mt, mh, h->stream));
     *Mm_out = Mm;
@@ -1129,6 +1130,14 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
     auto t0 = std::chrono::steady_clock::now();
     int r_prev = -1, l_prev = 0;
     int spec_cnew = 0;
+    // semi-online: the caller's basis is the first call's propagated basis
+    if (op.use_frsvt && op.r_init > 0) {
+        if (op.r_init > mh) return -8;
+        CK(hipMemcpy2DAsync(Qt, mh * sizeof(T), op.q_init, mh * sizeof(T), mh * sizeof(T), op.r_init,
+                            hipMemcpyDeviceToDevice, s));
+        r_prev = op.r_init;
+        l_prev = op.r_init;
+    }
     int it = 0;
     bool converged = false;
     double resid = 0.0, mu_last = mu;
@@ -1149,6 +1158,7 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
             c.lda = m;
             c.o = orient(m, n, m);
             c.tau = 1.0 / mu;
+            c.keep = op.keep;
             c.w = nullptr;
             c.q = op.q;
             c.seed = op.seed;
@@ -1205,7 +1215,7 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
             ce.off = exact_off;
             double *Mm;
             T *Mt;
-            if ((rc = exact_factors<T>(h, A, m, orient(m, n, m), 1.0 / mu, nullptr, ce, &Mm, &Mt)))
+            if ((rc = exact_factors<T>(h, A, m, orient(m, n, m), 1.0 / mu, nullptr, ce, &Mm, &Mt, op.keep)))
                 return rc;
             const Orient oa = orient(m, n, m);
             const int64_t scm = oa.trans ? m : 1, scn = oa.trans ? 1 : m;
@@ -1299,6 +1309,10 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
             break;
         }
     }
+    // the last propagated basis to the caller (semi-online use)
+    if (op.use_frsvt && op.q_final && r_prev > 0)
+        CK(hipMemcpy2DAsync(op.q_final, mh * sizeof(T), Qt, mh * sizeof(T), mh * sizeof(T), r_prev,
+                            hipMemcpyDeviceToDevice, s));
     // L and S of the last iteration, from its factors and multiplier
     {
         const int last = it - 1;
@@ -1678,6 +1692,10 @@ void frsvt_rpca_default_opts(frsvt_rpca_opts *op)
     op->ap_a = 2;
     op->ap_rho = 0.05;
     op->ap_gamma = 1.0;
+    op->keep = 0;
+    op->q_init = nullptr;
+    op->r_init = 0;
+    op->q_final = nullptr;
 }
 
 int svt(frsvt_handle h, frsvt_precision prec, int64_t m, int64_t n, const void *A, int64_t lda,
@@ -1771,6 +1789,7 @@ int rpca_ialm(frsvt_handle h, frsvt_precision prec, int64_t m, int64_t n, const 
         !(op.mu_bar_factor >= 1.0))
         return -8;
     if (op.ap != 0 && op.ap != 1) return -8;
+    if (op.keep < 0 || op.r_init < 0 || (op.r_init > 0 && bad_ptr(op.q_init))) return -8;
     if (op.ap && (op.ap_a < 1 || !(op.ap_rho > 0.0) || !(op.ap_rho <= 1.0) || !(op.ap_gamma > 0.0) ||
                   !(op.ap_gamma <= 1.0)))
         return -8;

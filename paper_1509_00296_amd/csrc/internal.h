@@ -92,8 +92,10 @@ struct SmallSvdOut {
     double *Mm;      // l x l
     int *status;     // [0] r, [1] sweeps, [2] converged flag, [3] unused
 };
+//  Thresholds in descending order of sigma: w[a] when w is set, else 0 for
+//  the first keep values (partial SVT: they pass unshrunk) and tau after.
 template <typename T>
-hipError_t launch_small_svd(int l, const double *G, double tau, const double *w, const T *Q,
+hipError_t launch_small_svd(int l, const double *G, double tau, const double *w, int keep, const T *Q,
                             int64_t ldq, int mh, T *QM, int64_t ldqm, T *Qout, int64_t ldqo,
                             const SmallSvdOut &out, double *work, int fuse_q, hipStream_t s);
 bool small_svd_fuse_q_ok(int mh, int l);

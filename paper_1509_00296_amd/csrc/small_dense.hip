@@ -403,7 +403,7 @@ __device__ __forceinline__ int jacobi_wave16(double *M, int l, int max_sweeps)
 // instructions); smem is the dynamic LDS block.
 template <typename T, int NT, int LM>
 __device__ __forceinline__ void small_svd_body(double *M, double *smem, int l, const double *Gin,
-                                               double tau, const double *w, const T *Q,
+                                               double tau, const double *w, int keep, const T *Q,
                                                int64_t ldq, int mh, T *QM, int64_t ldqm, T *Qout,
                                                int64_t ldqo, const SmallSvdOut &out, int fuse_q,
                                                int &sh_rot, int &rank, int *order, double *sig,
@@ -504,7 +504,9 @@ __device__ __forceinline__ void small_svd_body(double *M, double *smem, int l, c
     int rloc = 0;
     for (int a = tid; a < l; a += NT) {
         const double sa = sig[order[a]];
-        const double th = w ? w[a] : tau;
+        // the first keep values pass unshrunk (partial SVT), the rest by
+        // tau, or by their own thresholds w
+        const double th = w ? w[a] : (a < keep ? 0.0 : tau);
         const double f = sa - th;
         coef[a] = (f > 0.0 && sa > 0.0) ? f / sa : 0.0;
         if (f > 0.0) ++rloc;
@@ -612,7 +614,7 @@ __device__ __forceinline__ void small_svd_body(double *M, double *smem, int l, c
 }
 
 template <typename T, int NT, int LM>
-__global__ void __launch_bounds__(NT) k_small_svd(int l, const double *Gin, double tau,
+__global__ void __launch_bounds__(NT) k_small_svd(int l, const double *Gin, double tau, int keep,
                                                   const double *w, const T *Q, int64_t ldq, int mh,
                                                   T *QM, int64_t ldqm, T *Qout, int64_t ldqo,
                                                   SmallSvdOut out, double *work, int fuse_q)
@@ -624,15 +626,15 @@ __global__ void __launch_bounds__(NT) k_small_svd(int l, const double *Gin, doub
     __shared__ double sig[1024], wc[1024];
     double *smem = reinterpret_cast<double *>(smem_raw);
     if (l <= 128)
-        small_svd_body<T, NT, LM>(smem, smem, l, Gin, tau, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, fuse_q,
+        small_svd_body<T, NT, LM>(smem, smem, l, Gin, tau, w, keep, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, fuse_q,
                               sh_rot, rank, order, sig, coef, wc);
     else
-        small_svd_body<T, NT, LM>(work, smem, l, Gin, tau, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, fuse_q,
+        small_svd_body<T, NT, LM>(work, smem, l, Gin, tau, w, keep, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, fuse_q,
                               sh_rot, rank, order, sig, coef, wc);
 }
 
 template <typename T>
-hipError_t launch_small_svd(int l, const double *G, double tau, const double *w, const T *Q,
+hipError_t launch_small_svd(int l, const double *G, double tau, const double *w, int keep, const T *Q,
                             int64_t ldq, int mh, T *QM, int64_t ldqm, T *Qout, int64_t ldqo,
                             const SmallSvdOut &out, double *work, int fuse_q, hipStream_t s)
 {
@@ -643,14 +645,14 @@ hipError_t launch_small_svd(int l, const double *G, double tau, const double *w,
     size_t lds = l <= 128 ? (size_t)l * std::max(l, ldm) * sizeof(double) : 0;
     if (fuse_q && Q) lds = std::max(lds, 2 * (size_t)l * l * sizeof(double));
     if (l <= 8)
-        hipLaunchKernelGGL((k_small_svd<T, 256, 8>), dim3(1), dim3(256), lds, s, l, G, tau, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, work, fuse_q);
+        hipLaunchKernelGGL((k_small_svd<T, 256, 8>), dim3(1), dim3(256), lds, s, l, G, tau, keep, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, work, fuse_q);
     else if (l <= 32)
-        hipLaunchKernelGGL((k_small_svd<T, 256, 16>), dim3(1), dim3(256), lds, s, l, G, tau, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, work, fuse_q);
+        hipLaunchKernelGGL((k_small_svd<T, 256, 16>), dim3(1), dim3(256), lds, s, l, G, tau, keep, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, work, fuse_q);
     else
-        hipLaunchKernelGGL((k_small_svd<T, 1024, 16>), dim3(1), dim3(1024), lds, s, l, G, tau, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, work, fuse_q);
+        hipLaunchKernelGGL((k_small_svd<T, 1024, 16>), dim3(1), dim3(1024), lds, s, l, G, tau, keep, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, work, fuse_q);
     return hipGetLastError();
 }
-template hipError_t launch_small_svd<double>(int, const double *, double, const double *, const double *, int64_t, int, double *, int64_t, double *, int64_t, const SmallSvdOut &, double *, int, hipStream_t);
-template hipError_t launch_small_svd<float>(int, const double *, double, const double *, const float *, int64_t, int, float *, int64_t, float *, int64_t, const SmallSvdOut &, double *, int, hipStream_t);
+template hipError_t launch_small_svd<double>(int, const double *, double, const double *, int, const double *, int64_t, int, double *, int64_t, double *, int64_t, const SmallSvdOut &, double *, int, hipStream_t);
+template hipError_t launch_small_svd<float>(int, const double *, double, const double *, int, const float *, int64_t, int, float *, int64_t, float *, int64_t, const SmallSvdOut &, double *, int, hipStream_t);
 
 }  // namespace frk

@@ -129,7 +129,7 @@ def test_struct_layouts_match_header(tmp_path):
         '#include <stddef.h>\n#include <stdio.h>\n#include "frsvt.h"\n'
         "int main(void) {\n"
         '  printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(frsvt_rpca_opts), sizeof(frsvt_rpca_stats),\n'
-        "         offsetof(frsvt_rpca_opts, seed), offsetof(frsvt_rpca_opts, ap_gamma),\n"
+        "         offsetof(frsvt_rpca_opts, seed), offsetof(frsvt_rpca_opts, q_final),\n"
         "         offsetof(frsvt_rpca_stats, resid_est), sizeof(frsvt_wsvt_rule));\n"
         "  return 0;\n}\n")
     exe = tmp_path / "sizes"
@@ -137,5 +137,5 @@ def test_struct_layouts_match_header(tmp_path):
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
                                           check=True).stdout.split()]
     want = [ctypes.sizeof(fr.RpcaOpts), ctypes.sizeof(fr.RpcaStats), fr.RpcaOpts.seed.offset,
-            fr.RpcaOpts.ap_gamma.offset, fr.RpcaStats.resid_est.offset, ctypes.sizeof(fr.WsvtRule)]
+            fr.RpcaOpts.q_final.offset, fr.RpcaStats.resid_est.offset, ctypes.sizeof(fr.WsvtRule)]
     assert got == want

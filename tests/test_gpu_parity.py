@@ -222,6 +222,56 @@ def test_rpca_adaptive_rank_prediction_matches_oracle(fr, orc, m, n, gamma):
     assert np.linalg.norm(res.L.cpu().numpy() - Lgt) / np.linalg.norm(Lgt) < 1e-4
 
 
+@pytest.mark.parametrize("mode", ["frsvt", "exact"])
+def test_rpca_partial_svt_matches_oracle(fr, orc, mode):
+    """Partial SVT (keep = 1, the truncated nuclear norm of Type B) inside the
+    iALM on one window of n = 5 frames: FRSVT with q = 2 and widths up to
+    l = 3, or the exact partial SVT; same ranks, widths, L and S within 1e-10
+    as the oracle."""
+    from paper_1509_00296_amd import synth
+    _say(f"case rpca partial svt {mode} 6000x5")
+    O, _, _ = synth.rpca(seed=11, m=6000, n=5, rank=1, frac=0.05)
+    lam = 1.0 / np.sqrt(6000)
+    if mode == "frsvt":
+        res = fr.rpca_ialm(_gpu(O), lam, use_frsvt=True, q=2, seed=3, keep=1, ap=True, ap_a=2,
+                           ap_gamma=0.6)
+        out = orc.rpca_ialm(O, lam, mode="frsvt", q=2, seed=3, keep=1, ap=True, ap_a=2,
+                            ap_gamma=0.6)
+        assert res.widths == list(out["widths"][:64])
+    else:
+        res = fr.rpca_ialm(_gpu(O), lam, use_frsvt=False, keep=1)
+        out = orc.rpca_ialm(O, lam, mode="exact", keep=1)
+    assert res.iters == out["iters"]
+    assert res.ranks == list(out["ranks"][:64])
+    assert _rel(res.L.cpu().numpy(), out["L"]) <= 1e-10
+    assert _rel(res.S.cpu().numpy(), out["S"]) <= 1e-10
+
+
+def test_rpca_sliding_windows_match_oracle(fr, orc):
+    """Semi-online decomposition (Sec. 4, Type B): three consecutive windows
+    of 5 frames, each partial-SVT iALM starting from the previous window's
+    propagated basis; every window's L and S within 1e-10 of the oracle run
+    with the same hand-over."""
+    from paper_1509_00296_amd import synth
+    _say("case rpca sliding 4000 x 15, n = 5")
+    O, _, _ = synth.rpca(seed=12, m=4000, n=15, rank=1, frac=0.05)
+    lam = 1.0 / np.sqrt(4000)
+    L, S, runs = fr.rpca_sliding(_gpu(O), 5, lam, keep=1, l=3, q=2, seed=40)
+    Q = None
+    for w in range(3):
+        out = orc.rpca_ialm(O[:, 5 * w:5 * w + 5], lam, mode="frsvt", q=2, seed=40 + w, keep=1,
+                            ap=True, ap_a=2, ap_gamma=0.6, q_init=Q)
+        Q = out["Q"] if out["Q"].shape[1] > 0 else None
+        assert runs[w].iters == out["iters"]
+        assert runs[w].ranks == list(out["ranks"][:64])
+        assert runs[w].widths == list(out["widths"][:64])
+        assert _rel(L[:, 5 * w:5 * w + 5].cpu().numpy(), out["L"]) <= 1e-10
+        assert _rel(S[:, 5 * w:5 * w + 5].cpu().numpy(), out["S"]) <= 1e-10
+        Qg = runs[w].Q.cpu().numpy()       # the same subspace (signs are arbitrary)
+        assert Qg.shape == out["Q"].shape
+        assert np.abs(Qg @ Qg.T - out["Q"] @ out["Q"].T).max() <= 1e-9
+
+
 def test_frsvt_video_shape_single_call(fr, orc):
     """One FRSVT call at the full 76800 x 200 RPCA shape, in the launch
     configuration of the RPCA loop (fresh sketch l = 20, q = 1)."""

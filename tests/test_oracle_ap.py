@@ -87,3 +87,79 @@ def test_rpca_reports_residual_estimate(orc, problem):
     prev = np.concatenate([[0], r[:-1]])
     assert np.array_equal(est < 0, w == prev)
     assert np.all(est[est >= 0] > 0)
+
+
+# ---------------------------------------------------------------------------
+# Partial SVT (the truncated nuclear norm's proximal step, Type B of Table 6)
+# ---------------------------------------------------------------------------
+def test_psvt_definition_on_diagonal(orc):
+    s = np.array([9.0, 5.0, 3.0, 1.5, 0.5])
+    A = np.zeros((7, 5))
+    A[np.arange(5), np.arange(5)] = s
+    X, r = orc.psvt(A, 2.0, 2)
+    want = np.array([9.0, 5.0, 1.0, 0.0, 0.0])
+    assert np.allclose(np.diag(X[:5]), want, atol=1e-14) and abs(X).sum() - want.sum() < 1e-12
+    assert r == 3
+
+
+def test_psvt_special_cases_and_invariance(orc):
+    rng = np.random.default_rng(9)
+    A = rng.standard_normal((40, 25))
+    X0, r0 = orc.psvt(A, 1.5, 0)
+    Xs, rs = orc.svt(A, 1.5)
+    assert r0 == rs and np.abs(X0 - Xs).max() < 1e-12
+    Xk, rk = orc.psvt(A, 100.0, 25)          # every singular value kept
+    assert rk == 25 and np.abs(Xk - A).max() < 1e-11
+    U, _ = np.linalg.qr(rng.standard_normal((40, 40)))
+    V, _ = np.linalg.qr(rng.standard_normal((25, 25)))
+    X1, _ = orc.psvt(A, 1.5, 3)
+    X2, _ = orc.psvt(U @ A @ V.T, 1.5, 3)
+    assert np.abs(U @ X1 @ V.T - X2).max() < 1e-11
+
+
+def test_rpca_partial_svt_recovers_rank_one(orc):
+    """Type B: a rank-1 scene over n = 5 frames with 5 % sparse outliers; the
+    partial-SVT iALM (k = 1) with FRSVT (widths up to l = 3, q = 2) and the
+    exact PSVT iALM reach nearly the same L, and leaving the largest singular
+    value unshrunk recovers the scene better than SVT does with so few
+    frames (the degradation the section describes)."""
+    from paper_1509_00296_amd import synth
+    O, Lgt, _ = synth.rpca(seed=11, m=6000, n=5, rank=1, frac=0.05)
+    lam = 1.0 / math.sqrt(6000)
+    fr = orc.rpca_ialm(O, lam, mode="frsvt", q=2, seed=3, keep=1, ap=True, ap_a=2, ap_gamma=0.6)
+    ex = orc.rpca_ialm(O, lam, mode="exact", keep=1)
+    sv = orc.rpca_ialm(O, lam, mode="exact")
+    assert fr["converged"] and ex["converged"]
+    assert fr["widths"].max() <= 3
+    assert np.linalg.norm(fr["L"] - ex["L"]) / np.linalg.norm(ex["L"]) < 1e-3
+    err = lambda d: np.linalg.norm(d["L"] - Lgt) / np.linalg.norm(Lgt)
+    assert err(ex) < 0.85 * err(sv)
+
+
+def test_rpca_initial_basis(orc):
+    """Starting from the previous solve's propagated basis (semi-online use)
+    reaches the same solution."""
+    from paper_1509_00296_amd import synth
+    O, _, _ = synth.rpca(seed=3, m=3000, n=60, rank=3, frac=0.10)
+    lam = 1.0 / math.sqrt(3000)
+    a = orc.rpca_ialm(O, lam, mode="frsvt", q=1, seed=17)
+    assert a["Q"].shape == (60, a["ranks"][-1])
+    assert np.abs(a["Q"].T @ a["Q"] - np.eye(a["Q"].shape[1])).max() < 1e-12
+    b = orc.rpca_ialm(O, lam, mode="frsvt", q=1, seed=17, q_init=a["Q"])
+    assert b["converged"] and b["widths"][0] == a["ranks"][-1] + 5
+    assert np.linalg.norm(b["L"] - a["L"]) / np.linalg.norm(a["L"]) < 1e-6
+
+
+def test_ap_saturated_iteration_oversamples_more(orc, problem):
+    """Sec. 2.3: when the rank reaches the predicted width the rule predicts
+    optimistically with the larger rate ceil(rho mhat); otherwise it adds
+    only a.  With a = 1 and rho = 0.5 (30 columns at mhat = 60) the run whose
+    rank grows from 1 to 3 must sketch at least 30 columns once after the
+    first call, and stays within the rank plus one elsewhere."""
+    O, Lgt, lam = problem
+    out = orc.rpca_ialm(O, lam, mode="frsvt", q=1, seed=17, ap=True, ap_a=1, ap_rho=0.5)
+    w, r = out["widths"], out["ranks"]
+    assert out["converged"]
+    assert w[1:].max() >= 30
+    assert np.sum(w[1:] > r[:-1] + 1) == 1
+    assert np.linalg.norm(out["L"] - Lgt) / np.linalg.norm(Lgt) < 1e-4

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "frsvt_oracle.c")
 PIN_FILES = ["tests/test_oracle_rng.py", "tests/test_oracle_linalg.py",
              "tests/test_oracle_svt.py", "tests/test_oracle_frsvt.py",
-             "tests/test_oracle_rpca_grad.py"]
+             "tests/test_oracle_rpca_grad.py", "tests/test_oracle_ap.py"]
 
 # (name, original text, planted mistake)
 MUTANTS = [
@@ -29,7 +29,16 @@ MUTANTS = [
      "for (int it = 1; it < q; ++it) {"),
     ("rp_no_partial_orthogonalisation", "for (int pass = 0; pass < 2; ++pass)\n            for (int64_t c = 0; c < have + j; ++c) {",
      "for (int pass = 0; pass < 0; ++pass)\n            for (int64_t c = 0; c < have + j; ++c) {"),
-    ("frsvt_rank_off_by_one", "if (D[i] > tau) ++r;", "if (D[i] > tau && i > 0) ++r;"),
+    ("frsvt_rank_off_by_one", "shr[i] = i < keep ? D[i] : soft_shrink(D[i], tau);\n        if (shr[i] > 0.0) ++r;",
+     "shr[i] = i < keep ? D[i] : soft_shrink(D[i], tau);\n        if (shr[i] > 0.0 && i > 0) ++r;"),
+    ("frsvt_partial_ignored", "shr[i] = i < keep ? D[i] : soft_shrink(D[i], tau);",
+     "shr[i] = soft_shrink(D[i], tau);"),
+    ("psvt_keep_off_by_one", "shr[i] = i < keep ? S[i] : soft_shrink(S[i], tau);",
+     "shr[i] = i <= keep ? S[i] : soft_shrink(S[i], tau);"),
+    ("ap_branch_swapped", "const int64_t pn = r_prev < l_prev ? ap_a : (int64_t)ceil(ap_rho * (double)mh);",
+     "const int64_t pn = r_prev <= l_prev ? ap_a : (int64_t)ceil(ap_rho * (double)mh);"),
+    ("residual_one_pass", "    for (int pass = 0; pass < 2; ++pass)\n        for (int64_t c = 0; c < r; ++c) {",
+     "    for (int pass = 0; pass < 2; ++pass)\n        for (int64_t c = 0; c < r - 1; ++c) {"),
     ("ialm_dual_sign", "AT(Y, m, i, j) += mu * z;", "AT(Y, m, i, j) -= mu * z;"),
     ("ialm_shrink_lambda", "lambda / mu);", "lambda * mu);"),
     ("vjp_antisymmetric_term", "(f[i] + f[j]) / (sg[i] + sg[j])", "(f[i] - f[j]) / (sg[i] + sg[j])"),
