@@ -21,6 +21,11 @@ Further workloads, reported under "workloads" in the same JSON line:
            iterations in {0, 1, 2}, and with adaptive rank prediction
            (Sec. 2.3, Eq. 7: a = 2, rho = 0.05, gamma = 1; q = 1): iters/s,
            iterations, sketch widths and the error of L
+  typeb    semi-online partial-SVT decomposition (Sec. 4, Type B: k = 1, q = 2)
+           of a 384 x 288 x 60 synthetic sequence (rank-1 scene, 5 % sparse
+           outliers) in consecutive windows of n in {3, 5, 7, 10} frames
+           (l = 2, 3, 3, 3), each window starting from the previous basis:
+           ms per frame
 
 Prints ONE JSON line.  --gpus above 1 is refused: this build runs on one GPU.
 """
@@ -54,7 +59,7 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=6,
                     help="iterations of the oracle timed for the CPU baseline (0 = skip)")
     ap.add_argument("--only-main", action="store_true", help="skip the further workloads")
-    ap.add_argument("--workloads", default="single,precision,batched,unrolled,ablation")
+    ap.add_argument("--workloads", default="single,precision,batched,unrolled,ablation,typeb")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="one untimed device copy of this size first (counter calibration)")
     return ap.parse_args()
@@ -313,6 +318,31 @@ def wl_ablation(torch, fr, synth, tracer):
             "runs": runs}
 
 
+def wl_typeb(torch, fr, synth, tracer):
+    import numpy as np
+    m, F = 384 * 288, 60
+    O_np, L_gt, _ = synth.rpca(seed=7, m=m, n=F, rank=1, frac=0.05)
+    O = torch.from_numpy(O_np).cuda()
+    Lgt = torch.from_numpy(L_gt).cuda()
+    runs = []
+    for n, l in ((3, 2), (5, 3), (7, 3), (10, 3)):
+        fr.rpca_sliding(O, n, keep=1, l=l, q=2, seed=100)      # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L, S, res = fr.rpca_sliding(O, n, keep=1, l=l, q=2, seed=100)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        used = (F // n) * n
+        err = float(torch.linalg.norm(L[:, :used] - Lgt[:, :used]) / torch.linalg.norm(Lgt[:, :used]))
+        runs.append({"n": n, "l": l, "windows": F // n, "ms_per_frame": round(1e3 * sec / used, 4),
+                     "ms_per_window": round(1e3 * sec / (F // n), 3),
+                     "iters_per_window": round(float(np.mean([r.iters for r in res])), 2),
+                     "converged": all(r.converged for r in res), "nrmse_L": err})
+    return {"workload": "typeb_sliding_psvt_384x288x60_f64", "metric": "ms per frame",
+            "unit": "ms/frame", "config": {"m": m, "frames": F, "keep": 1, "q": 2, "outliers": 0.05},
+            "runs": runs}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -420,7 +450,7 @@ def main():
     workloads = {}
     if not args.only_main:
         fns = {"single": wl_single, "precision": wl_precision, "batched": wl_batched,
-               "unrolled": wl_unrolled, "ablation": wl_ablation}
+               "unrolled": wl_unrolled, "ablation": wl_ablation, "typeb": wl_typeb}
         for name in [w for w in args.workloads.split(",") if w]:
             _progress(f"workload {name}")
             try:
