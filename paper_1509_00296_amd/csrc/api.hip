@@ -1789,7 +1789,8 @@ int rpca_ialm(frsvt_handle h, frsvt_precision prec, int64_t m, int64_t n, const 
         !(op.mu_bar_factor >= 1.0))
         return -8;
     if (op.ap != 0 && op.ap != 1) return -8;
-    if (op.keep < 0 || op.r_init < 0 || (op.r_init > 0 && bad_ptr(op.q_init))) return -8;
+    if (op.keep < 0 || op.r_init < 0 || op.r_init > std::min(m, n) || (op.r_init > 0 && bad_ptr(op.q_init)))
+        return -8;
     if (op.ap && (op.ap_a < 1 || !(op.ap_rho > 0.0) || !(op.ap_rho <= 1.0) || !(op.ap_gamma > 0.0) ||
                   !(op.ap_gamma <= 1.0)))
         return -8;

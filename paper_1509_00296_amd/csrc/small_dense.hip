@@ -398,6 +398,13 @@ __device__ __forceinline__ int jacobi_wave16(double *M, int l, int max_sweeps)
     return sweep;
 }
 
+// Row capacity of the Jacobi groups for 16 < l <= 128 (16 lanes x 2, 4, 6,
+// 7 or 8 rows each): the column stride of M, rows past l held at zero.
+__host__ __device__ __forceinline__ int svd_row_capacity(int l)
+{
+    return l <= 32 ? 32 : (l <= 64 ? 64 : (l <= 96 ? 96 : (l <= 112 ? 112 : 128)));
+}
+
 // The body of k_small_svd with the Jacobi storage M either in LDS or in
 // global memory (inlined once for each, so LDS accesses compile to LDS
 // instructions); smem is the dynamic LDS block.
@@ -426,9 +433,9 @@ __device__ __forceinline__ void small_svd_body(double *M, double *smem, int l, c
     __syncthreads();
     int sweeps = 0;
     // column stride of M after the factorisation: l, or for 16 < l <= 128
-    // (M in LDS) the Jacobi groups' row capacity 32, 64 or 128, the rows past
+    // (M in LDS) the Jacobi groups' row capacity 32, 64, 96, 112 or 128, the rows past
     // l held at zero
-    const int ldm = (l > LM && l <= 128) ? (l <= 32 ? 32 : (l <= 64 ? 64 : 128)) : l;
+    const int ldm = (l > LM && l <= 128) ? svd_row_capacity(l) : l;
     if (NT >= 256 && l <= LM) {
         // wavefront 0 alone: register Cholesky, then the Jacobi
         if (wave == 0) {
@@ -450,6 +457,8 @@ __device__ __forceinline__ void small_svd_body(double *M, double *smem, int l, c
             chol_blk4<NT>(M, l, ptol, 0.0, coef, sig, nullptr, ldm);
             if (ldm == 32) sweeps = jacobi_groups<NT, 16, 2, true>(M, l, ldm, l, 60, &sh_rot);
             else if (ldm == 64) sweeps = jacobi_groups<NT, 16, 4, true>(M, l, ldm, l, 60, &sh_rot);
+            else if (ldm == 96) sweeps = jacobi_groups<NT, 16, 6, true>(M, l, ldm, l, 60, &sh_rot);
+            else if (ldm == 112) sweeps = jacobi_groups<NT, 16, 7, true>(M, l, ldm, l, 60, &sh_rot);
             else sweeps = jacobi_groups<NT, 16, 8, true>(M, l, ldm, l, 60, &sh_rot);
         } else {
             // right-looking in place: row j of R is scaled, then the trailing
@@ -639,9 +648,9 @@ hipError_t launch_small_svd(int l, const double *G, double tau, const double *w,
                             const SmallSvdOut &out, double *work, int fuse_q, hipStream_t s)
 {
     if (l < 1 || l > 1024) return hipErrorInvalidValue;
-    // M in LDS up to l = 128, columns padded to 32, 64 or 128 rows past l = LM
+    // M in LDS up to l = 128, columns padded to svd_row_capacity(l) rows past l = LM
     const int lm = l <= 8 ? 8 : 16;
-    const int ldm = (l > lm && l <= 128) ? (l <= 32 ? 32 : (l <= 64 ? 64 : 128)) : l;
+    const int ldm = (l > lm && l <= 128) ? svd_row_capacity(l) : l;
     size_t lds = l <= 128 ? (size_t)l * std::max(l, ldm) * sizeof(double) : 0;
     if (fuse_q && Q) lds = std::max(lds, 2 * (size_t)l * l * sizeof(double));
     if (l <= 8)

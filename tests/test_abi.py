@@ -97,6 +97,18 @@ def test_argument_validation_precedes_device_use(lib):
     lib.rpca_ialm.argtypes = [vp, ctypes.c_int, i64, i64, vp, i64, d, vp, vp, i64, vp, i64, vp]
     assert lib.rpca_ialm(dummy, 0, 10, 10, buf, 10, 0.0, None, buf, 10, buf, 10, None) == -7
     assert lib.rpca_ialm(dummy, 0, 10, 10, buf, 10, 0.1, None, None, 10, buf, 10, None) == -9
+    import paper_1509_00296_amd as fr
+    for field, val in (("ap_gamma", 1.5), ("ap", 1), ("keep", -1), ("r_init", 11), ("r_init", 2)):
+        op = fr.RpcaOpts()
+        lib.frsvt_rpca_default_opts(ctypes.byref(op))
+        setattr(op, field, val)
+        if field == "ap":
+            op.ap_a = 0                       # a >= 1 required
+        if field == "ap_gamma":
+            op.ap = 1
+        # r_init = 11 > min(m, n); r_init = 2 without q_init
+        assert lib.rpca_ialm(dummy, 0, 10, 10, buf, 10, 0.1, ctypes.byref(op), buf, 10, buf, 10,
+                             None) == -8, field
     lib.wsvt_batched.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp]
     assert lib.wsvt_batched(dummy, -1, None, None, None, None, None, None, None) == -2
 

@@ -63,6 +63,8 @@ CASES = [
     (700, 250, 20, 0.01, 1.0, 20, 12, 1),    # l = 32 (widest one-pass basis)
     (3000, 100, 8, 0.02, 2.0, 14, 6, 1),     # transposed passes: 8 row groups, 32 columns
     (20000, 120, 6, 0.02, 4.0, 6, 4, 1),     # transposed passes: 2-3 tiles per workgroup
+    (600, 400, 60, 0.01, 1.0, 70, 10, 1),    # l = 80: Jacobi rows padded to 96
+    (700, 500, 90, 0.01, 1.0, 95, 10, 1),    # l = 105: Jacobi rows padded to 112
 ]
 
 
