@@ -69,6 +69,10 @@ def _bind(path: str):
                                          ctypes.c_double, _i64, _dp, _i64, _dp, _i64p, _dp, _i64,
                                          _dp, _i64, _i64p, _i64p, _dp, _dp,
                                          ctypes.POINTER(ctypes.c_int)]
+        lib.orc_lrr_ialm.argtypes = [_i64, _i64, _dp, _i64, ctypes.c_double, ctypes.c_int, _i64,
+                                     ctypes.c_int, ctypes.c_uint64, ctypes.c_double, ctypes.c_int,
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp, _i64,
+                                     _dp, _i64, _i64p, ctypes.POINTER(ctypes.c_int)]
         lib.orc_psvt.argtypes = [_i64, _i64, _dp, _i64, ctypes.c_double, _i64, _dp, _i64, _i64p]
         lib.orc_residual_estimate.argtypes = [_i64, _i64, _dp, _i64, _dp, _i64, _i64, _dp,
                                               ctypes.c_double]
@@ -383,3 +387,23 @@ def rpca_unrolled(O, taus, lams, k: int = 5, p: int = 5, q: int = 1, seed: int =
         _, Y, A = dual_step(O, L, Y, float(lams[t]), mu, mu_next)
         mu = mu_next
     return L
+
+
+def lrr_ialm(X, lam: float, mode: str = "exact", p: int = 5, q: int = 1, seed: int = 0,
+             tol: float = 1e-8, max_iter: int = 1000, mu0: float = 1e-6, rho: float = 1.1,
+             mu_max: float = 1e10):
+    """Low-rank representation (Type A of Table 6) by its inexact ALM: the J
+    step by exact SVT (mode 'exact') or FRSVT + range propagation ('frsvt').
+    Returns dict(Z, E, ranks, iters, converged)."""
+    X = _f(X)
+    d, n = X.shape
+    Z = np.zeros((n, n), order="F")
+    E = np.zeros((d, n), order="F")
+    ranks = np.zeros(max_iter, dtype=np.int64)
+    it = ctypes.c_int()
+    rc = _L().orc_lrr_ialm(d, n, _p(X), d, lam, 0 if mode == "exact" else 1, p, q, seed, tol,
+                           max_iter, mu0, rho, mu_max, _p(Z), n, _p(E), d,
+                           ranks.ctypes.data_as(_i64p), ctypes.byref(it))
+    _check(rc, "lrr_ialm")
+    k = int(it.value)
+    return dict(Z=Z, E=E, ranks=ranks[:k], iters=k, converged=(rc == 0))

@@ -917,3 +917,152 @@ int orc_svt_vjp(int64_t m, int64_t n, const double *A, int64_t lda, double tau,
     free(T); free(UtT); free(M2); free(UPb);
     return sweeps >= 1000 ? 1 : 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Low-rank representation (Type A of Table 6), solved by the inexact ALM of */
+/* the LRR method the paper hosts FRSVT in:                                  */
+/*   min ||J||_* + lambda ||E||_{2,1}  s.t.  X = X Z + E,  Z = J,            */
+/* from Z = J = E = Y1 = Y2 = 0 and mu = mu0, each iteration                */
+/*   J  = SVT_{1/mu}(Z + Y2/mu)   (exact, or FRSVT + range propagation with  */
+/*                                 the widths of the RPCA host, counter = k) */
+/*   Z  = (I + X^T X)^{-1} (X^T (X - E) + J + (X^T Y1 - Y2)/mu)              */
+/*   E  = column-wise shrink_{lambda/mu}(X - X Z + Y1/mu)                    */
+/*   Y1 += mu (X - X Z - E),  Y2 += mu (Z - J),  mu = min(rho mu, mu_max)    */
+/* until max|X - X Z - E| < tol and max|Z - J| < tol.                        */
+/* ------------------------------------------------------------------------ */
+
+/* In-place Cholesky A = L L^T of an SPD n x n matrix (lower triangle). */
+static void chol_lower(int64_t n, double *A, int64_t lda)
+{
+    for (int64_t j = 0; j < n; ++j) {
+        double d = AT(A, lda, j, j);
+        for (int64_t k = 0; k < j; ++k) d -= AT(A, lda, j, k) * AT(A, lda, j, k);
+        d = sqrt(d);
+        AT(A, lda, j, j) = d;
+        for (int64_t i = j + 1; i < n; ++i) {
+            double s = AT(A, lda, i, j);
+            for (int64_t k = 0; k < j; ++k) s -= AT(A, lda, i, k) * AT(A, lda, j, k);
+            AT(A, lda, i, j) = s / d;
+        }
+    }
+}
+
+/* B <- (L L^T)^{-1} B for n x m B (forward then backward substitution). */
+static void chol_solve(int64_t n, const double *L, int64_t ldl, int64_t m, double *B, int64_t ldb)
+{
+    for (int64_t c = 0; c < m; ++c) {
+        double *b = &AT(B, ldb, 0, c);
+        for (int64_t i = 0; i < n; ++i) {
+            double s = b[i];
+            for (int64_t k = 0; k < i; ++k) s -= AT(L, ldl, i, k) * b[k];
+            b[i] = s / AT(L, ldl, i, i);
+        }
+        for (int64_t i = n - 1; i >= 0; --i) {
+            double s = b[i];
+            for (int64_t k = i + 1; k < n; ++k) s -= AT(L, ldl, k, i) * b[k];
+            b[i] = s / AT(L, ldl, i, i);
+        }
+    }
+}
+
+int orc_lrr_ialm(int64_t d, int64_t n, const double *X, int64_t ldx, double lambda, int svt_mode,
+                 int64_t p, int q, uint64_t seed, double tol, int max_iter, double mu0, double rho,
+                 double mu_max, double *Z, int64_t ldz, double *E, int64_t lde, int64_t *ranks,
+                 int *iters)
+{
+    if (d < 1) return -1;
+    if (n < 1) return -2;
+    if (ldx < d) return -4;
+    if (!(lambda > 0.0)) return -5;
+    if (svt_mode != 0 && svt_mode != 1) return -6;
+    if (svt_mode == 1 && p < 1) return -7;
+    if (max_iter < 1) return -11;
+    if (!(mu0 > 0.0) || !(rho >= 1.0) || !(mu_max >= mu0)) return -12;
+
+    double *Lc = dalloc(n * n);                    /* I + X^T X, then its Cholesky factor */
+    mat_mul_tn(n, n, d, X, ldx, X, ldx, Lc, n);
+    for (int64_t i = 0; i < n; ++i) AT(Lc, n, i, i) += 1.0;
+    chol_lower(n, Lc, n);
+
+    double *Zk = dalloc(n * n), *J = dalloc(n * n), *Ek = dalloc(d * n);
+    double *Y1 = dalloc(d * n), *Y2 = dalloc(n * n), *XZ = dalloc(d * n);
+    double *T = dalloc(n * n), *W = dalloc(d * n), *R = dalloc(n * n);
+    double *Qt = dalloc(n * n), *Qnew = dalloc(n * n);
+    const int64_t l0 = (int64_t)ceil(0.1 * (double)n) > 0 ? (int64_t)ceil(0.1 * (double)n) : 1;
+    int64_t r_prev = -1;
+    double mu = mu0;
+    int status = 2, it;
+    for (it = 0; it < max_iter; ++it) {
+        /* J = SVT_{1/mu}(Z + Y2/mu) */
+        for (int64_t i = 0; i < n * n; ++i) T[i] = Zk[i] + Y2[i] / mu;
+        int64_t r = 0;
+        if (svt_mode == 0) {
+            orc_svt(n, n, T, n, 1.0 / mu, J, n, &r);
+        } else {
+            int64_t nomega = r_prev < 0 ? l0 : p;
+            const double *Qprop = NULL;
+            if (r_prev > 0) {
+                Qprop = Qt;
+                if (r_prev + nomega > n) nomega = n - r_prev;
+            }
+            if (nomega < 1 && !Qprop) nomega = 1;
+            if (nomega < 0) nomega = 0;
+            double *Om = dalloc(n * (nomega > 0 ? nomega : 1));
+            if (nomega > 0) orc_gaussian_matrix(seed, (uint64_t)it, n, nomega, Om, n);
+            orc_frsvt(n, n, T, n, 1.0 / mu, q, Om, n, nomega, Qprop, n, Qprop ? r_prev : 0, J, n,
+                      Qnew, n, &r, NULL, NULL);
+            free(Om);
+            mat_copy(n, r, Qnew, n, Qt, n);
+            r_prev = r;
+        }
+        if (ranks) ranks[it] = r;
+        /* Z = (I + X^T X)^{-1} (X^T (X - E + Y1/mu) + J - Y2/mu) */
+        for (int64_t i = 0; i < d * n; ++i) W[i] = 0.0;
+        for (int64_t j = 0; j < n; ++j)
+            for (int64_t i = 0; i < d; ++i)
+                AT(W, d, i, j) = AT(X, ldx, i, j) - AT(Ek, d, i, j) + AT(Y1, d, i, j) / mu;
+        mat_mul_tn(n, n, d, X, ldx, W, d, R, n);
+        for (int64_t i = 0; i < n * n; ++i) R[i] += J[i] - Y2[i] / mu;
+        chol_solve(n, Lc, n, n, R, n);
+        memcpy(Zk, R, (size_t)(n * n) * sizeof(double));
+        /* E = column shrink_{lambda/mu}(X - X Z + Y1/mu) */
+        mat_mul(d, n, n, X, ldx, Zk, n, XZ, d);
+        const double thr = lambda / mu;
+        for (int64_t j = 0; j < n; ++j) {
+            double nrm = 0.0;
+            for (int64_t i = 0; i < d; ++i) {
+                const double v = AT(X, ldx, i, j) - AT(XZ, d, i, j) + AT(Y1, d, i, j) / mu;
+                AT(W, d, i, j) = v;
+                nrm += v * v;
+            }
+            nrm = sqrt(nrm);
+            const double f = nrm > thr ? (nrm - thr) / nrm : 0.0;
+            for (int64_t i = 0; i < d; ++i) AT(Ek, d, i, j) = f * AT(W, d, i, j);
+        }
+        /* multipliers, penalty, stopping test */
+        double r1 = 0.0, r2 = 0.0;
+        for (int64_t j = 0; j < n; ++j)
+            for (int64_t i = 0; i < d; ++i) {
+                const double z = AT(X, ldx, i, j) - AT(XZ, d, i, j) - AT(Ek, d, i, j);
+                AT(Y1, d, i, j) += mu * z;
+                if (fabs(z) > r1) r1 = fabs(z);
+            }
+        for (int64_t i = 0; i < n * n; ++i) {
+            const double z = Zk[i] - J[i];
+            Y2[i] += mu * z;
+            if (fabs(z) > r2) r2 = fabs(z);
+        }
+        mu = rho * mu < mu_max ? rho * mu : mu_max;
+        if (r1 < tol && r2 < tol) {
+            status = 0;
+            ++it;
+            break;
+        }
+    }
+    if (iters) *iters = it;
+    mat_copy(n, n, Zk, n, Z, ldz);
+    mat_copy(d, n, Ek, d, E, lde);
+    free(Lc); free(Zk); free(J); free(Ek); free(Y1); free(Y2); free(XZ); free(T); free(W);
+    free(R); free(Qt); free(Qnew);
+    return status;
+}

@@ -133,6 +133,19 @@ int orc_frsvt_keep(int64_t m, int64_t n, const double *A, int64_t lda, double ta
 double orc_residual_estimate(int64_t m, int64_t n, const double *A, int64_t lda, const double *Qt,
                              int64_t ldq, int64_t r, const double *omega, double alpha);
 
+/* Low-rank representation (Type A of Table 6) by its inexact ALM:
+ *   min ||J||_* + lambda ||E||_{2,1} s.t. X = X Z + E, Z = J
+ * (X d x n; Z n x n; E d x n).  svt_mode 0: exact SVT for the J step; 1:
+ * FRSVT with range propagation (l0 = ceil(0.1 n), then r + p; q power
+ * iterations; counter = iteration).  mu0, rho, mu_max: the penalty
+ * schedule; stops when max|X - XZ - E| < tol and max|Z - J| < tol.
+ * ranks[] (length max_iter) optional.  Returns 0 when converged, 2 when
+ * max_iter was reached. */
+int orc_lrr_ialm(int64_t d, int64_t n, const double *X, int64_t ldx, double lambda, int svt_mode,
+                 int64_t p, int q, uint64_t seed, double tol, int max_iter, double mu0, double rho,
+                 double mu_max, double *Z, int64_t ldz, double *E, int64_t lde, int64_t *ranks,
+                 int *iters);
+
 /* Vector-Jacobian product of exact SVT from a full SVD: given Xbar,
  * Abar = (dX/dA)^T Xbar and taubar = <Xbar, dX/dtau>. */
 int orc_svt_vjp(int64_t m, int64_t n, const double *A, int64_t lda, double tau,

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "frsvt_oracle.c")
 PIN_FILES = ["tests/test_oracle_rng.py", "tests/test_oracle_linalg.py",
              "tests/test_oracle_svt.py", "tests/test_oracle_frsvt.py",
-             "tests/test_oracle_rpca_grad.py", "tests/test_oracle_ap.py"]
+             "tests/test_oracle_rpca_grad.py", "tests/test_oracle_ap.py", "tests/test_oracle_lrr.py"]
 
 # (name, original text, planted mistake)
 MUTANTS = [
@@ -37,6 +37,9 @@ MUTANTS = [
      "shr[i] = i <= keep ? S[i] : soft_shrink(S[i], tau);"),
     ("ap_branch_swapped", "const int64_t pn = r_prev < l_prev ? ap_a : (int64_t)ceil(ap_rho * (double)mh);",
      "const int64_t pn = r_prev <= l_prev ? ap_a : (int64_t)ceil(ap_rho * (double)mh);"),
+    ("lrr_dual_sign", "Y2[i] += mu * z;", "Y2[i] -= mu * z;"),
+    ("lrr_shrink_threshold", "const double thr = lambda / mu;", "const double thr = lambda * mu;"),
+    ("lrr_rhs_without_multiplier", "R[i] += J[i] - Y2[i] / mu;", "R[i] += J[i];"),
     ("residual_one_pass", "    for (int pass = 0; pass < 2; ++pass)\n        for (int64_t c = 0; c < r; ++c) {",
      "    for (int pass = 0; pass < 2; ++pass)\n        for (int64_t c = 0; c < r - 1; ++c) {"),
     ("ialm_dual_sign", "AT(Y, m, i, j) += mu * z;", "AT(Y, m, i, j) -= mu * z;"),
