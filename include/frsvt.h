@@ -393,6 +393,57 @@ FRSVT_API int rpca_ialm(frsvt_handle handle, frsvt_precision prec, int64_t m, in
               int64_t ldo, double lambda, const frsvt_rpca_opts *opts, void *L, int64_t ldl,
               void *S, int64_t lds, frsvt_rpca_stats *stats);
 
+/* ---------------------------------------------------------- LRR host */
+
+typedef struct {
+    double tol;            /* stop when max|X - XZ - E| and max|Z - J| fall below tol (1e-8) */
+    int32_t max_iter;      /* iteration limit (1000) */
+    double mu0;            /* initial penalty (1e-6) */
+    double rho;            /* penalty growth (1.1) */
+    double mu_max;         /* penalty cap (1e10) */
+    int32_t use_frsvt;     /* 1: FRSVT with range propagation for the J step; 0: exact svt */
+    int32_t p;             /* new samples beside the propagated basis (5) */
+    int32_t q;             /* power iterations (1) */
+    uint64_t seed;         /* Philox key; iteration i uses counter i */
+} frsvt_lrr_opts;
+
+typedef struct {
+    int32_t iters;         /* iterations run */
+    int32_t converged;     /* 1 when the tolerance was met */
+    int32_t rank;          /* rank of J in the last iteration */
+    double primal;         /* final max|X - XZ - E| */
+    double dual;           /* final max|Z - J| */
+    double seconds;        /* wall time of the iteration loop */
+} frsvt_lrr_stats;
+
+/* Fill `opts` with the defaults listed above. */
+FRSVT_API void frsvt_lrr_default_opts(frsvt_lrr_opts *opts);
+
+/*
+ * lrr_ialm: low-rank representation (Type A of Table 6, the host of Sec. 4's
+ * subspace-clustering experiments), min ||Z||_* + lambda ||E||_{2,1}
+ * s.t. X = X Z + E, by the inexact ALM of the LRR method with the auxiliary
+ * J = Z.  From Z = J = E = 0, Y1 = Y2 = 0, mu = mu0, each iteration
+ *   J = SVT_{1/mu}(Z + Y2/mu)  (FRSVT + range propagation: first sketch
+ *       ceil(0.1 n) wide, then r + p; or exact svt),
+ *   Z = (I + X^T X)^{-1} (X^T (X - E + Y1/mu) + J - Y2/mu),
+ *   E = column-wise shrink_{lambda/mu}(X - X Z + Y1/mu),
+ *   Y1 += mu (X - X Z - E), Y2 += mu (Z - J), mu = min(rho mu, mu_max),
+ * until both max-norm residuals fall below tol.  (I + X^T X)^{-1} is formed
+ * once by Newton-Schulz iterations on the matrix cores.
+ *   prec   FRSVT_F64 only (others: FRSVT_ERR_UNSUPPORTED).
+ *   X      [in]  d x n, ldx >= d (DEVICE).  n <= 1024.
+ *   Z      [out] n x n, ldz >= n;  E [out] d x n, lde >= d (DEVICE).
+ *   opts   [in, optional] NULL selects frsvt_lrr_default_opts.
+ *   stats  [out, HOST, optional].
+ * The call allocates its iteration state (about 4 d n + 9 n^2 doubles) and
+ * frees it before returning; the host reads two residuals per iteration.
+ * Returns FRSVT_MAX_ITER when max_iter was reached before tol.
+ */
+FRSVT_API int lrr_ialm(frsvt_handle handle, frsvt_precision prec, int64_t d, int64_t n, const void *X,
+                       int64_t ldx, double lambda, const frsvt_lrr_opts *opts, void *Z, int64_t ldz,
+                       void *E, int64_t lde, frsvt_lrr_stats *stats);
+
 #ifdef __cplusplus
 }
 #endif

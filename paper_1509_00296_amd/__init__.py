@@ -42,6 +42,16 @@ class RpcaOpts(ctypes.Structure):
                 ("q_final", ctypes.c_void_p)]
 
 
+class LrrOpts(ctypes.Structure):
+    _fields_ = [("tol", _dbl), ("max_iter", _i32), ("mu0", _dbl), ("rho", _dbl), ("mu_max", _dbl),
+                ("use_frsvt", _i32), ("p", _i32), ("q", _i32), ("seed", _u64)]
+
+
+class LrrStats(ctypes.Structure):
+    _fields_ = [("iters", _i32), ("converged", _i32), ("rank", _i32), ("primal", _dbl), ("dual", _dbl),
+                ("seconds", _dbl)]
+
+
 class RpcaStats(ctypes.Structure):
     _fields_ = [("iters", _i32), ("converged", _i32), ("residual", _dbl), ("norm2", _dbl),
                 ("seconds", _dbl), ("ranks", _i32 * 64), ("residuals", _dbl * 64),
@@ -85,6 +95,10 @@ def library(path: str | None = None) -> ctypes.CDLL:
     lib.rpca_ialm.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _i64, _dbl,
                               ctypes.POINTER(RpcaOpts), _vp, _i64, _vp, _i64,
                               ctypes.POINTER(RpcaStats)]
+    lib.frsvt_lrr_default_opts.argtypes = [ctypes.POINTER(LrrOpts)]
+    lib.frsvt_lrr_default_opts.restype = None
+    lib.lrr_ialm.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _i64, _dbl, ctypes.POINTER(LrrOpts), _vp, _i64,
+                             _vp, _i64, ctypes.POINTER(LrrStats)]
     lib.frsvt_fwd.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _i64, _dbl, _i32, _i32, _i32, _u64,
                               _u64, _vp, _i64, _vp, _i64, _vp]
     lib.frsvt_vjp.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _i64, _dbl, _i32, _i32, _i32, _u64,
@@ -691,3 +705,41 @@ class UnrolledRPCA(_torch().nn.Module):
             mus.append([min(mu0 * self.rho ** t, mub) for t in range(T + 1)])
         seeds = [self.seed + b for b in range(B)]
         return _UnrolledFn.apply(self.tau, self.lam, O, Y0, A0, mus, self.k, self.p, self.q, seeds)
+
+
+@dataclass
+class LrrResult:
+    Z: object
+    E: object
+    iters: int
+    converged: bool
+    rank: int
+    primal: float
+    dual: float
+    seconds: float
+
+
+def lrr_ialm(X, lam: float, *, use_frsvt: bool = True, p: int = 5, q: int = 1, seed: int = 0,
+             tol: float = 1e-8, max_iter: int = 1000, mu0: float = 1e-6, rho: float = 1.1,
+             mu_max: float = 1e10) -> LrrResult:
+    """Low-rank representation (Type A of Table 6), min ||Z||_* + lam ||E||_{2,1}
+    s.t. X = X Z + E, by its inexact ALM with the J step by FRSVT + range
+    propagation (or exact SVT).  X is a float64 GPU tensor (d x n samples)."""
+    import torch
+    h = handle(X.device.index)
+    if X.dtype != torch.float64:
+        raise TypeError("lrr_ialm takes float64 data")
+    Xc = X.t().contiguous().t() if X.stride(0) != 1 else X
+    d, n = Xc.shape
+    ldx = max(Xc.stride(1), d, 1)
+    Z = torch.empty((n, n), dtype=X.dtype, device=X.device).t()
+    E = torch.empty((n, d), dtype=X.dtype, device=X.device).t()
+    op = LrrOpts()
+    h.lib.frsvt_lrr_default_opts(ctypes.byref(op))
+    op.tol, op.max_iter, op.mu0, op.rho, op.mu_max = tol, max_iter, mu0, rho, mu_max
+    op.use_frsvt, op.p, op.q, op.seed = int(use_frsvt), p, q, seed
+    st = LrrStats()
+    rc = h.lib.lrr_ialm(h.ptr, F64, d, n, Xc.data_ptr(), ldx, float(lam), ctypes.byref(op), Z.data_ptr(), n,
+                        E.data_ptr(), d, ctypes.byref(st))
+    _check(h, rc, "lrr_ialm", ok=(OK, MAX_ITER))
+    return LrrResult(Z, E, st.iters, bool(st.converged), st.rank, st.primal, st.dual, st.seconds)

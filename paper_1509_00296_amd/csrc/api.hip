@@ -1521,6 +1521,125 @@ int wsvt_batched_impl(frsvt_context *h, int64_t count, const int32_t *rows, cons
 
 
 
+// ---------------------------------------------------------------------------
+// Low-rank representation (Type A of Table 6) by its inexact ALM; the steps
+// are listed with the lrr_ialm declaration.  The iteration state lives in
+// one allocation of its own (the FRSVT calls of the J step grow and may move
+// the handle's workspace).
+// ---------------------------------------------------------------------------
+struct DevBlock {
+    void *p = nullptr;
+    ~DevBlock()
+    {
+        if (p) (void)hipFree(p);
+    }
+};
+
+int lrr_impl(frsvt_context *h, int64_t d, int64_t n, const double *X, int64_t ldx, double lambda,
+             const frsvt_lrr_opts &op, double *Z, int64_t ldz, double *E, int64_t lde, frsvt_lrr_stats *stats)
+{
+    hipStream_t s = h->stream;
+    if (stats) memset(stats, 0, sizeof(*stats));
+    const int num_cu = h->num_cu;
+    // split-K partials large enough for every product below
+    const int sk1 = gemm_splitk(n, n, d, num_cu), sk2 = gemm_splitk(n, n, n, num_cu);
+    const int sk3 = gemm_splitk(d, n, n, num_cu);
+    const size_t part = std::max({(size_t)sk1 * n * n, (size_t)sk2 * n * n, (size_t)sk3 * d * n});
+    const size_t nn = (size_t)n * n, dn = (size_t)d * n;
+    const int np = lrr_dual_parts();
+    const size_t total = 8 * nn + 3 * dn + part + 2 * (size_t)np + 8;
+    DevBlock blk;
+    CK(hipMalloc(&blk.p, total * sizeof(double)));
+    double *J = (double *)blk.p, *Y2 = J + nn, *T = Y2 + nn, *R = T + nn, *Minv = R + nn;
+    double *P1 = Minv + nn, *P2 = P1 + nn, *Qt = P2 + nn;
+    double *Y1 = Qt + nn, *W = Y1 + dn, *XZ = W + dn, *gp = XZ + dn, *mparts = gp + part;
+    double *dres = mparts + 2 * (size_t)np;
+    auto gemm = [&](int64_t M, int64_t N, int64_t K, const double *A, int64_t sam, int64_t sak, const double *B,
+                    int64_t sbk, int64_t sbn, double *C, int64_t ldc) -> int {
+        const int sk = gemm_splitk(M, N, K, num_cu);
+        CKT(FRSVT_K_GEMM, launch_gemm_f64_mfma(M, N, K, A, sam, sak, B, sbk, sbn, C, 1, ldc, sk, gp, s));
+        return FRSVT_OK;
+    };
+    int rc;
+    // state: Z = J = E = Y1 = Y2 = 0
+    CK(launch_lrr_comb(n, n, 0, nullptr, 0, 0, nullptr, 0, 0, nullptr, 0, 0.0, Z, ldz, s));
+    CK(launch_lrr_comb(d, n, 0, nullptr, 0, 0, nullptr, 0, 0, nullptr, 0, 0.0, E, lde, s));
+    CK(launch_lrr_comb(n, n, 0, nullptr, 0, 0, nullptr, 0, 0, nullptr, 0, 0.0, Y2, n, s));
+    CK(launch_lrr_comb(d, n, 0, nullptr, 0, 0, nullptr, 0, 0, nullptr, 0, 0.0, Y1, d, s));
+    // (I + X^T X)^{-1} by Newton-Schulz: M <- 2 M - M (A M) from M = I / ||A||_inf;
+    // the error I - A M squares each step from below 1 - 1 / ||A||_inf
+    if ((rc = gemm(n, n, d, X, ldx, 1, X, 1, ldx, T, n))) return rc;
+    CK(launch_lrr_comb(n, n, 1.0, T, n, 0, nullptr, 0, 0, nullptr, 0, 1.0, T, n, s));
+    CK(launch_lrr_norm_inf(n, T, n, dres, s));
+    double ninf = 1.0;
+    CK(hipMemcpyAsync(&ninf, dres, sizeof(double), hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    if (!(ninf >= 1.0) || !std::isfinite(ninf)) return FRSVT_ERR_NONFINITE;
+    // steps until (1 - 1/ninf)^(2^k) < 2^-60, plus two
+    const int ns_steps = std::min(80, (int)std::ceil(std::log2(60.0 * std::log(2.0) * ninf + 1.0)) + 2);
+    CK(launch_lrr_comb(n, n, 0, nullptr, 0, 0, nullptr, 0, 0, nullptr, 0, 1.0 / ninf, Minv, n, s));
+    for (int k = 0; k < ns_steps; ++k) {
+        if ((rc = gemm(n, n, n, T, 1, n, Minv, 1, n, P1, n))) return rc;       // A M
+        if ((rc = gemm(n, n, n, Minv, 1, n, P1, 1, n, P2, n))) return rc;      // M A M
+        CK(launch_lrr_comb(n, n, 2.0, Minv, n, -1.0, P2, n, 0, nullptr, 0, 0.0, Minv, n, s));
+    }
+    const int l0 = std::max(1, (int)std::ceil(0.1 * (double)n));
+    int r_prev = -1, r = 0;
+    double mu = op.mu0, primal = 0.0, dual = 0.0;
+    bool converged = false;
+    int it;
+    const auto t0 = std::chrono::steady_clock::now();
+    for (it = 0; it < op.max_iter; ++it) {
+        // J = SVT_{1/mu}(Z + Y2/mu)
+        CK(launch_lrr_comb(n, n, 1.0, Z, ldz, 1.0 / mu, Y2, n, 0, nullptr, 0, 0.0, T, n, s));
+        int32_t rr = 0;
+        if (op.use_frsvt) {
+            const bool prop = r_prev > 0;
+            const int kk = r_prev < 0 ? l0 : 0, pp = r_prev < 0 ? 0 : op.p;
+            if ((rc = frsvt_impl<double>(h, n, n, T, n, 1.0 / mu, kk, pp, op.q, prop ? Qt : nullptr,
+                                         prop ? r_prev : 0, n, op.seed, (uint64_t)it, J, n, Qt, n, &rr)))
+                return rc;
+            r_prev = rr;
+        } else {
+            if ((rc = exact_svt_impl<double>(h, n, n, T, n, 1.0 / mu, nullptr, J, n, &rr))) return rc;
+        }
+        r = rr;
+        // Z = (I + X^T X)^{-1} (X^T (X - E + Y1/mu) + J - Y2/mu)
+        CK(launch_lrr_comb(d, n, 1.0, X, ldx, -1.0, E, lde, 1.0 / mu, Y1, d, 0.0, W, d, s));
+        if ((rc = gemm(n, n, d, X, ldx, 1, W, 1, d, R, n))) return rc;
+        CK(launch_lrr_comb(n, n, 1.0, R, n, 1.0, J, n, -1.0 / mu, Y2, n, 0.0, R, n, s));
+        if ((rc = gemm(n, n, n, Minv, 1, n, R, 1, n, Z, ldz))) return rc;
+        // E = column shrink_{lambda/mu}(X - X Z + Y1/mu)
+        if ((rc = gemm(d, n, n, X, 1, ldx, Z, 1, ldz, XZ, d))) return rc;
+        CK(launch_lrr_colshrink(d, n, X, ldx, XZ, Y1, 1.0 / mu, lambda / mu, E, lde, s));
+        // multipliers and the max-norm residuals
+        CK(launch_lrr_dual(d, n, mu, X, ldx, XZ, d, E, lde, Y1, mparts, s));
+        CK(launch_lrr_dual(n, n, mu, Z, ldz, J, n, nullptr, 0, Y2, mparts + np, s));
+        CK(launch_lrr_max_parts(mparts, np, 2, dres, s));
+        double res[2];
+        CK(hipMemcpyAsync(res, dres, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+        primal = res[0];
+        dual = res[1];
+        mu = std::min(op.rho * mu, op.mu_max);
+        if (primal < op.tol && dual < op.tol) {
+            converged = true;
+            ++it;
+            break;
+        }
+    }
+    if (stats) {
+        stats->iters = it;
+        stats->converged = converged ? 1 : 0;
+        stats->rank = r;
+        stats->primal = primal;
+        stats->dual = dual;
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    CK(hipStreamSynchronize(s));
+    return converged ? FRSVT_OK : FRSVT_MAX_ITER;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1990,3 +2109,41 @@ int rpca_init(frsvt_handle h, frsvt_precision prec, int64_t m, int64_t n, const 
 }
 
 }  // extern "C"
+
+void frsvt_lrr_default_opts(frsvt_lrr_opts *op)
+{
+    if (!op) return;
+    op->tol = 1e-8;
+    op->max_iter = 1000;
+    op->mu0 = 1e-6;
+    op->rho = 1.1;
+    op->mu_max = 1e10;
+    op->use_frsvt = 1;
+    op->p = 5;
+    op->q = 1;
+    op->seed = 0;
+}
+
+int lrr_ialm(frsvt_handle h, frsvt_precision prec, int64_t d, int64_t n, const void *X, int64_t ldx, double lambda,
+             const frsvt_lrr_opts *opts, void *Z, int64_t ldz, void *E, int64_t lde, frsvt_lrr_stats *stats)
+{
+    if (!h) return -1;
+    if (prec != FRSVT_F64 && prec != FRSVT_F32 && prec != FRSVT_MIXED_BF16) return -2;
+    if (d < 1) return -3;
+    if (n < 1) return -4;
+    if (bad_ptr(X)) return -5;
+    if (ldx < d) return -6;
+    if (!(lambda > 0.0) || !std::isfinite(lambda)) return -7;
+    frsvt_lrr_opts op;
+    frsvt_lrr_default_opts(&op);
+    if (opts) op = *opts;
+    if (!(op.tol > 0.0) || op.max_iter < 1 || !(op.mu0 > 0.0) || !(op.rho >= 1.0) || !(op.mu_max >= op.mu0) ||
+        op.p < 1 || op.q < 0 || (op.use_frsvt != 0 && op.use_frsvt != 1))
+        return -8;
+    if (bad_ptr(Z)) return -9;
+    if (ldz < n) return -10;
+    if (bad_ptr(E)) return -11;
+    if (lde < d) return -12;
+    if (prec != FRSVT_F64 || n > 1024) return FRSVT_ERR_UNSUPPORTED;
+    return lrr_impl(h, d, n, (const double *)X, ldx, lambda, op, (double *)Z, ldz, (double *)E, lde, stats);
+}

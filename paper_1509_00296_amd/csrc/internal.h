@@ -339,4 +339,22 @@ struct DualStepArgs {
 };
 template <typename T>
 hipError_t launch_dual_step(const DualStepArgs<T> &a, bool vjp, int *nparts, hipStream_t s);
+// ------------------------------------------------ low-rank representation host
+// out = a A + b B + c C + g I (m x n, column-major; null operands skipped;
+// out may alias A).
+hipError_t launch_lrr_comb(int64_t m, int64_t n, double a, const double *A, int64_t lda, double b,
+                           const double *B, int64_t ldb, double c, const double *C, int64_t ldc, double g,
+                           double *out, int64_t ldo, hipStream_t s);
+// out[0] = max_i sum_j |A(i, j)| (n x n)
+hipError_t launch_lrr_norm_inf(int64_t n, const double *A, int64_t lda, double *out, hipStream_t s);
+// E(:, j) = max(0, 1 - thr / ||v_j||) v_j, v = X - XZ + Y1 inv_mu (XZ, Y1 d x n, ld d)
+hipError_t launch_lrr_colshrink(int64_t d, int64_t n, const double *X, int64_t ldx, const double *XZ,
+                                const double *Y1, double inv_mu, double thr, double *E, int64_t lde, hipStream_t s);
+// Y (ld m) += mu (P - Q - R), part[lrr_dual_parts()] = per-block max |P - Q - R|
+int lrr_dual_parts();
+hipError_t launch_lrr_dual(int64_t m, int64_t n, double mu, const double *P, int64_t ldp, const double *Q,
+                           int64_t ldq, const double *R, int64_t ldr, double *Y, double *part, hipStream_t s);
+// out[k] = max_g part[k * nparts + g], k < count
+hipError_t launch_lrr_max_parts(const double *part, int nparts, int count, double *out, hipStream_t s);
+
 }  // namespace frk

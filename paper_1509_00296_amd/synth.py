@@ -19,6 +19,10 @@ for fast tests):
                    {49, 64, 81, 100}, cols in [30, 90], rank-4 Haar signal with
                    s = (50, 20, 10, 5) plus iid N(0, 0.1^2) noise.
 * ``rpca_batch``   unrolled-RPCA batch: instances built like ``rpca``.
+* ``subspaces``    low-rank representation input: 10 random 9-dimensional
+                   subspaces of R^2016, 64 samples each (the 2016 x 640 shape
+                   of the face-clustering experiment), 10 % of the columns
+                   corrupted by Gaussian noise of about a sample's norm.
 """
 from __future__ import annotations
 
@@ -108,3 +112,24 @@ def rpca_batch(seed: int = 0, batch: int = 16, m: int = 4096, n: int = 256, rank
     # (batch, n, m) in C order, viewed as (batch, m, n): instance b is column-major
     cm = lambda xs: np.stack([x.T for x in xs]).astype(dtype).transpose(0, 2, 1)
     return cm(Os), cm(Ls)
+
+
+def subspaces(seed: int = 0, d: int = 2016, groups: int = 10, per_group: int = 64, dim: int = 9,
+              corrupt: float = 0.1, noise_scale: float = 1.0):
+    """Union of `groups` random `dim`-dimensional subspaces of R^d with
+    `per_group` samples each (columns grouped in order; unit-variance
+    coefficients, so a sample's norm is about sqrt(dim)); a fraction `corrupt`
+    of the columns (exact count, random positions) gets an added iid Gaussian
+    corruption of about the same norm (entries N(0, noise_scale^2 dim / d)).  Returns (X d x n column-major, labels n, the
+    corrupted column indices)."""
+    rng = np.random.default_rng(seed)
+    n = groups * per_group
+    X = np.empty((d, n), order="F")
+    labels = np.repeat(np.arange(groups), per_group)
+    for g in range(groups):
+        U = haar(rng, d, dim)
+        X[:, g * per_group:(g + 1) * per_group] = U @ rng.standard_normal((dim, per_group))
+    bad = np.sort(rng.choice(n, int(round(corrupt * n)), replace=False))
+    scale = noise_scale * np.sqrt(dim / d)
+    X[:, bad] += scale * rng.standard_normal((d, bad.size))
+    return X, labels, bad

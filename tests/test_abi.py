@@ -143,11 +143,14 @@ def test_struct_layouts_match_header(tmp_path):
         '  printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(frsvt_rpca_opts), sizeof(frsvt_rpca_stats),\n'
         "         offsetof(frsvt_rpca_opts, seed), offsetof(frsvt_rpca_opts, q_final),\n"
         "         offsetof(frsvt_rpca_stats, resid_est), sizeof(frsvt_wsvt_rule));\n"
+        '  printf("%zu %zu %zu\\n", sizeof(frsvt_lrr_opts), sizeof(frsvt_lrr_stats),\n'
+        "         offsetof(frsvt_lrr_opts, seed));\n"
         "  return 0;\n}\n")
     exe = tmp_path / "sizes"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
                                           check=True).stdout.split()]
     want = [ctypes.sizeof(fr.RpcaOpts), ctypes.sizeof(fr.RpcaStats), fr.RpcaOpts.seed.offset,
-            fr.RpcaOpts.q_final.offset, fr.RpcaStats.resid_est.offset, ctypes.sizeof(fr.WsvtRule)]
+            fr.RpcaOpts.q_final.offset, fr.RpcaStats.resid_est.offset, ctypes.sizeof(fr.WsvtRule),
+            ctypes.sizeof(fr.LrrOpts), ctypes.sizeof(fr.LrrStats), fr.LrrOpts.seed.offset]
     assert got == want

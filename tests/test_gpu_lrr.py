@@ -1,0 +1,86 @@
+"""Low-rank representation (Type A of Table 6) on the GPU against the oracle:
+the same iteration count and final rank, Z and E within 1e-8.  The tolerance
+is looser than the single-call 1e-10: the GPU applies (I + X^T X)^{-1} formed
+once by Newton-Schulz iterations where the oracle solves with a Cholesky
+factor each time, and some 150-300 iterations carry that rounding
+difference forward (each step is a contraction, so it does not grow).
+The final J-step rank is compared up to singular values at rounding level;
+on corrupted data Z and E are compared at 1e-7 for the reason given below."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fr():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1509_00296_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    return oracle
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _subspaces(seed, d=80, K=3, dim=4, N=20):
+    rng = np.random.default_rng(seed)
+    blocks = []
+    for _ in range(K):
+        U, _ = np.linalg.qr(rng.standard_normal((d, dim)))
+        blocks.append(U @ rng.standard_normal((dim, N)))
+    return np.hstack(blocks), rng
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+@pytest.mark.parametrize("mode,corrupt", [("exact", False), ("frsvt", False), ("exact", True), ("frsvt", True)])
+def test_lrr_matches_oracle(fr, orc, mode, corrupt):
+    X, rng = _subspaces(2 if corrupt else 1)
+    lam = 100.0
+    if corrupt:
+        bad = rng.choice(60, 6, replace=False)
+        X[:, bad] += 3.0 * rng.standard_normal((80, 6))
+        lam = 0.1
+    _say(f"case lrr {mode} corrupt={corrupt} 80x60")
+    Xd = torch.from_numpy(np.asfortranarray(X)).cuda()
+    res = fr.lrr_ialm(Xd, lam, use_frsvt=(mode == "frsvt"), p=5, q=1, seed=3, max_iter=1000)
+    out = orc.lrr_ialm(X, lam, mode=mode, p=5, q=1, seed=3, max_iter=1000)
+    assert res.converged and out["converged"]
+    assert res.iters == out["iters"]
+    Zg = res.Z.cpu().numpy()
+    Eg = res.E.cpu().numpy()
+    # Clean data: J's spectrum has a wide gap at the threshold and the runs
+    # agree to 1e-8.  Corrupted data: the late J inputs keep singular values
+    # at the 1e-8 scale of the stopping tolerance, which rounding puts either
+    # side of 1/mu; each such flip moves Z by about that much, hence 1e-7.
+    tol = 1e-7 if corrupt else 1e-8
+    assert _rel(Zg, out["Z"]) <= tol
+    assert _rel(Eg, out["E"]) <= tol or np.abs(out["E"]).max() < 1e-12
+    # the GPU's own result meets the equality constraint X = XZ + E to the
+    # stopping tolerance (its dual residual Z - J is not observable here)
+    assert np.abs(X - X @ Zg - Eg).max() < 1e-8
+    # The final J-step rank counts singular values above 1/mu_max = 1e-10;
+    # those below the stopping tolerance's scale (~1e-8) are rounding-level
+    # and may fall either side of it.  What is unique is the rank of Z above
+    # that noise; the reported ranks may differ only by values inside it.
+    so = np.linalg.svd(out["Z"], compute_uv=False)
+    sg = np.linalg.svd(Zg, compute_uv=False)
+    r_robust = int((so > 1e-4 * so[0]).sum())
+    assert r_robust == int((sg > 1e-4 * sg[0]).sum())
+    noise = int(((so > 1e-12) & (so <= 1e-6)).sum())
+    assert r_robust <= res.rank and abs(res.rank - int(out["ranks"][-1])) <= noise
+    if not corrupt:
+        assert res.rank == out["ranks"][-1] == 12

@@ -150,7 +150,7 @@ def test_frsvt_f32_bound(fr, orc):
     assert _rel(X.double().cpu().numpy(), Xo) <= 2e-5
 
 
-@pytest.mark.parametrize("m,n", [(500, 300), (60, 200), (333, 90)])
+@pytest.mark.parametrize("m,n", [(500, 300), (60, 200), (333, 90), (700, 640)])
 def test_svt_exact_matches_oracle(fr, orc, m, n):
     _say(f"case svt f64 {m}x{n}")
     A = _lowrank(m + n, m, n, 8, 0.05)
