@@ -407,3 +407,93 @@ def lrr_ialm(X, lam: float, mode: str = "exact", p: int = 5, q: int = 1, seed: i
     _check(rc, "lrr_ialm")
     k = int(it.value)
     return dict(Z=Z, E=E, ranks=ranks[:k], iters=k, converged=(rc == 0))
+
+
+# ---------------------------------------------------------------- tensor host (Type C)
+
+def unfold(T, mode: int) -> np.ndarray:
+    """Mode-`mode` unfolding (mode in 0, 1, 2) of a 3-way array: rows indexed
+    by that mode, columns by the other two with the earlier one varying
+    fastest (the convention of the tensor notation the paper refers to)."""
+    T = np.asarray(T, dtype=np.float64)
+    return np.asfortranarray(np.moveaxis(T, mode, 0).reshape(T.shape[mode], -1, order="F"))
+
+
+def fold(M, mode: int, shape) -> np.ndarray:
+    """Inverse of unfold."""
+    rest = [s for i, s in enumerate(shape) if i != mode]
+    T = np.asarray(M).reshape([shape[mode]] + rest, order="F")
+    return np.asfortranarray(np.moveaxis(T, 0, mode))
+
+
+def tensor_rpca(O, alpha, lam: float, mode: str = "exact", p: int = 5, q: int = 1, seed: int = 0,
+                tol: float = 1e-7, max_iter: int = 100, mu0: float = 0.0, rho: float = 1.5,
+                mu_max: float = 1e10):
+    """Low-rank + sparse decomposition of a 3-way tensor (Type C of Table 6
+    with the alignment fixed to the identity): min sum_i alpha_i ||L_(i)||_*
+    + lam ||E||_1 s.t. O = L + E, by an inexact ALM over one copy L_i of L
+    per mode, each tied to O by its own constraint O = L_i + E:
+
+      L_i = fold_i(SVT_{alpha_i / mu}(unfold_i(O - E + Y_i / mu)))
+      E   = shrink_{lam / (3 mu)}(mean_i(O - L_i + Y_i / mu))
+      Y_i = Y_i + mu (O - L_i - E),  mu = min(rho mu, mu_max)
+
+    from E = Y_i = 0, mu0 = 1.25 / ||O_(1)||_2 unless given; stop when
+    max_i ||O - L_i - E||_F / ||O||_F < tol.  The SVT of mode i is exact
+    (mode 'exact') or FRSVT with range propagation ('frsvt': first sketch
+    ceil(0.1 mhat_i) columns, then r_i + p; q power iterations; the Gaussian
+    matrix of mode i in iteration t drawn with seed + i and counter t).
+    Returns dict(L = mean of the L_i, E, Ls, ranks (iters x 3), iters,
+    converged, resid)."""
+    O = np.asfortranarray(np.asarray(O, dtype=np.float64))
+    shape = O.shape
+    assert len(shape) == 3
+    alpha = [float(a) for a in alpha]
+    normO = np.linalg.norm(O)
+    if mu0 <= 0.0:
+        mu0 = 1.25 / svd(unfold(O, 0))[1][0]
+    mu = mu0
+    E = np.zeros(shape, order="F")
+    Y = [np.zeros(shape, order="F") for _ in range(3)]
+    Ls = [None] * 3
+    Qs = [None] * 3
+    rprev = [-1, -1, -1]
+    ranks, resid = [], []
+    converged = False
+    it = 0
+    for it in range(1, max_iter + 1):
+        rk = []
+        for i in range(3):
+            M = unfold(O - E + Y[i] / mu, i)
+            if mode == "exact":
+                X, r = svt(M, alpha[i] / mu)
+            else:
+                mh, nh = min(M.shape), max(M.shape)
+                l0 = max(1, int(np.ceil(0.1 * mh)))
+                Qp = Qs[i] if rprev[i] > 0 else None
+                nom = l0 if rprev[i] < 0 else p
+                if Qp is not None and rprev[i] + nom > mh:
+                    nom = mh - rprev[i]
+                if nom < 1 and Qp is None:
+                    nom = 1
+                Om = gaussian_matrix(seed + i, it - 1, nh, nom)
+                X, Qs[i], r, _, _ = frsvt(M, alpha[i] / mu, q, Om, Qp)
+                rprev[i] = r
+            Ls[i] = fold(X, i, shape)
+            rk.append(r)
+        V = sum(O - Ls[i] + Y[i] / mu for i in range(3)) / 3.0
+        E = np.asfortranarray(shrink(V, lam / (3.0 * mu)))
+        res = 0.0
+        for i in range(3):
+            Z = O - Ls[i] - E
+            Y[i] = Y[i] + mu * Z
+            res = max(res, np.linalg.norm(Z) / normO)
+        ranks.append(rk)
+        resid.append(res)
+        mu = min(rho * mu, mu_max)
+        if res < tol:
+            converged = True
+            break
+    L = (Ls[0] + Ls[1] + Ls[2]) / 3.0
+    return dict(L=L, E=E, Ls=Ls, Y=Y, ranks=np.array(ranks, dtype=np.int64).reshape(-1, 3), iters=it,
+                converged=converged, resid=np.array(resid), mu0=mu0)

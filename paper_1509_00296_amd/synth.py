@@ -133,3 +133,23 @@ def subspaces(seed: int = 0, d: int = 2016, groups: int = 10, per_group: int = 6
     scale = noise_scale * np.sqrt(dim / d)
     X[:, bad] += scale * rng.standard_normal((d, bad.size))
     return X, labels, bad
+
+
+def tensor_lowrank(seed: int = 0, shape=(32, 22, 3000), ranks=(3, 3, 5), frac: float = 0.05):
+    """3-way O = L + S: L = G x1 U1 x2 U2 x3 U3 with iid U[0,1] core and
+    factors, scaled to mean 1; S holds exactly `frac` of the entries at random
+    positions with values U[-1, 1].  Arrays are column-major (first index
+    fastest).  Returns (O, L, S)."""
+    rng = np.random.default_rng(seed)
+    I1, I2, I3 = shape
+    G = rng.random(ranks)
+    U = [rng.random((s, r)) for s, r in zip(shape, ranks)]
+    L = np.einsum("abc,ia,jb,kc->ijk", G, U[0], U[1], U[2])
+    L /= L.mean()
+    N = I1 * I2 * I3
+    S = np.zeros(N)
+    idx = rng.choice(N, int(round(frac * N)), replace=False)
+    S[idx] = rng.uniform(-1.0, 1.0, idx.size)
+    S = S.reshape(shape, order="F")
+    f = lambda a: np.asfortranarray(a)
+    return f(L + S), f(L), f(S)
