@@ -30,6 +30,11 @@ Further workloads, reported under "workloads" in the same JSON line:
            10 nine-dimensional subspaces with 10 % corrupted columns,
            lambda = 0.1, FRSVT + range propagation in the J step (p 5, q 1):
            seconds per solve, with the exact-SVT loop timed over 4 iterations
+  tensor   low-rank + sparse decomposition of a 32 x 22 x 3000 tensor (the
+           gait-sequence shape of Sec. 4, Type C with the alignment fixed;
+           Tucker ranks 3, 3, 5, 5 % outliers, alpha = 0.15, 0.15, 0.7,
+           lambda = 0.5 / sqrt(32 * 22)), three FRSVTs per iteration:
+           ms per solve, with the exact-SVT loop timed over 3 iterations
 
 Prints ONE JSON line.  --gpus above 1 is refused: this build runs on one GPU.
 """
@@ -63,7 +68,7 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=6,
                     help="iterations of the oracle timed for the CPU baseline (0 = skip)")
     ap.add_argument("--only-main", action="store_true", help="skip the further workloads")
-    ap.add_argument("--workloads", default="single,precision,batched,unrolled,ablation,typeb,lrr")
+    ap.add_argument("--workloads", default="single,precision,batched,unrolled,ablation,typeb,lrr,tensor")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="one untimed device copy of this size first (counter calibration)")
     return ap.parse_args()
@@ -380,6 +385,37 @@ def wl_lrr(torch, fr, synth, tracer):
             "exact_svt_est_seconds": round(ex_sec / ex.iters * res.iters, 2)}
 
 
+def wl_tensor(torch, fr, synth, tracer):
+    import numpy as np
+    shape = (32, 22, 3000)
+    O_np, L_gt, _ = synth.tensor_lowrank(seed=0, shape=shape)
+    O = torch.from_numpy(O_np).cuda()
+    Lgt = torch.from_numpy(L_gt).cuda()
+    alpha, lam = (0.15, 0.15, 0.7), 0.5 / np.sqrt(shape[0] * shape[1])
+    fr.tensor_rpca(O, alpha, lam, seed=9, max_iter=3)      # warm-up
+    torch.cuda.synchronize()
+    K, sec, its = 3, 0.0, 0
+    for _ in range(K):
+        t0 = time.perf_counter()
+        res = fr.tensor_rpca(O, alpha, lam, seed=9)
+        torch.cuda.synchronize()
+        sec += time.perf_counter() - t0
+        its += res.iters
+    err = float(torch.linalg.norm(res.L - Lgt) / torch.linalg.norm(Lgt))
+    # the same loop with exact SVTs, a bounded number of iterations
+    KE = 3
+    t1 = time.perf_counter()
+    ex = fr.tensor_rpca(O, alpha, lam, use_frsvt=False, max_iter=KE)
+    torch.cuda.synchronize()
+    ex_sec = time.perf_counter() - t1
+    return {"workload": "tensor_rpca_32x22x3000_f64", "metric": "ms per solve", "unit": "ms",
+            "config": {"shape": list(shape), "tucker_ranks": [3, 3, 5], "outliers": 0.05, "alpha": list(alpha),
+                       "lambda": lam, "p": 5, "q": 1, "tol": 1e-7},
+            "ms_per_solve": round(1e3 * sec / K, 3), "iters": res.iters, "converged": res.converged,
+            "ms_per_iter": round(1e3 * sec / its, 4), "ranks": list(res.rank), "nrmse_L": err,
+            "exact_svt_ms_per_iter": round(1e3 * ex_sec / ex.iters, 3)}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -487,7 +523,8 @@ def main():
     workloads = {}
     if not args.only_main:
         fns = {"single": wl_single, "precision": wl_precision, "batched": wl_batched,
-               "unrolled": wl_unrolled, "ablation": wl_ablation, "typeb": wl_typeb, "lrr": wl_lrr}
+               "unrolled": wl_unrolled, "ablation": wl_ablation, "typeb": wl_typeb, "lrr": wl_lrr,
+               "tensor": wl_tensor}
         for name in [w for w in args.workloads.split(",") if w]:
             _progress(f"workload {name}")
             try:

@@ -444,6 +444,61 @@ FRSVT_API int lrr_ialm(frsvt_handle handle, frsvt_precision prec, int64_t d, int
                        int64_t ldx, double lambda, const frsvt_lrr_opts *opts, void *Z, int64_t ldz,
                        void *E, int64_t lde, frsvt_lrr_stats *stats);
 
+/* ---------------------------------------------------------- 3-way tensor host */
+
+typedef struct {
+    double tol;            /* stop when max_i ||O - L_i - E||_F / ||O||_F < tol (1e-7) */
+    int32_t max_iter;      /* iteration limit (100) */
+    double mu0;            /* initial penalty; 0 selects 1.25 / ||O_(1)||_2 (0) */
+    double rho;            /* penalty growth (1.5) */
+    double mu_max;         /* penalty cap (1e10) */
+    int32_t use_frsvt;     /* 1: FRSVT with range propagation per mode; 0: exact svt */
+    int32_t p;             /* new samples beside the propagated basis (5) */
+    int32_t q;             /* power iterations (1) */
+    uint64_t seed;         /* Philox key of mode 1; mode i uses seed + i - 1, iteration t counter t */
+} frsvt_tensor_opts;
+
+typedef struct {
+    int32_t iters;         /* iterations run */
+    int32_t converged;     /* 1 when the tolerance was met */
+    int32_t rank[3];       /* rank of each mode's SVT in the last iteration */
+    double resid;          /* final max_i ||O - L_i - E||_F / ||O||_F */
+    double mu0;            /* the initial penalty used */
+    double seconds;        /* wall time of the iteration loop */
+} frsvt_tensor_stats;
+
+/* Fill `opts` with the defaults listed above. */
+FRSVT_API void frsvt_tensor_default_opts(frsvt_tensor_opts *opts);
+
+/*
+ * tensor_rpca: low-rank + sparse decomposition of a 3-way tensor, the convex
+ * program of Type C in Table 6 with the alignment fixed to the identity:
+ * min sum_i alpha_i ||L_(i)||_* + lambda ||E||_1 s.t. O = L + E, where L_(i)
+ * is the mode-i unfolding (rows indexed by mode i, columns by the other two
+ * modes with the earlier one varying fastest).  Inexact ALM over one copy
+ * L_i of L per mode, each with its own constraint O = L_i + E and
+ * multiplier Y_i; from E = Y_i = 0, each iteration
+ *   L_i = fold_i(SVT_{alpha_i/mu}(unfold_i(O - E + Y_i/mu)))  (FRSVT + range
+ *         propagation per mode: first sketch ceil(0.1 mhat_i) wide, then
+ *         r_i + p; or exact svt),
+ *   E   = shrink_{lambda/(3 mu)}(mean_i(O - L_i + Y_i/mu)),
+ *   Y_i += mu (O - L_i - E),  mu = min(rho mu, mu_max).
+ *   prec   FRSVT_F64 only (others: FRSVT_ERR_UNSUPPORTED).
+ *   O      [in]  I1 x I2 x I3, column-major, contiguous (DEVICE).  Each
+ *          unfolding's short side must be <= 1024.
+ *   alpha  [in, HOST] three weights >= 0 (Table 6 assumes they sum to 1).
+ *   L      [out] the mean of the three copies L_i; E [out]; both
+ *          contiguous like O and distinct from O and from each other (DEVICE).
+ *   opts   [in, optional] NULL selects frsvt_tensor_default_opts.
+ *   stats  [out, HOST, optional].
+ * The call allocates its iteration state (8 tensors plus the three modes'
+ * bases) and frees it before returning; the host reads three residuals per
+ * iteration.  Returns FRSVT_MAX_ITER when max_iter was reached before tol.
+ */
+FRSVT_API int tensor_rpca(frsvt_handle handle, frsvt_precision prec, int64_t I1, int64_t I2, int64_t I3,
+                          const void *O, const double *alpha, double lambda, const frsvt_tensor_opts *opts,
+                          void *L, void *E, frsvt_tensor_stats *stats);
+
 #ifdef __cplusplus
 }
 #endif

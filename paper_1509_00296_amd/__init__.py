@@ -52,6 +52,16 @@ class LrrStats(ctypes.Structure):
                 ("seconds", _dbl)]
 
 
+class TensorOpts(ctypes.Structure):
+    _fields_ = [("tol", _dbl), ("max_iter", _i32), ("mu0", _dbl), ("rho", _dbl), ("mu_max", _dbl),
+                ("use_frsvt", _i32), ("p", _i32), ("q", _i32), ("seed", _u64)]
+
+
+class TensorStats(ctypes.Structure):
+    _fields_ = [("iters", _i32), ("converged", _i32), ("rank", _i32 * 3), ("resid", _dbl), ("mu0", _dbl),
+                ("seconds", _dbl)]
+
+
 class RpcaStats(ctypes.Structure):
     _fields_ = [("iters", _i32), ("converged", _i32), ("residual", _dbl), ("norm2", _dbl),
                 ("seconds", _dbl), ("ranks", _i32 * 64), ("residuals", _dbl * 64),
@@ -99,6 +109,10 @@ def library(path: str | None = None) -> ctypes.CDLL:
     lib.frsvt_lrr_default_opts.restype = None
     lib.lrr_ialm.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _i64, _dbl, ctypes.POINTER(LrrOpts), _vp, _i64,
                              _vp, _i64, ctypes.POINTER(LrrStats)]
+    lib.frsvt_tensor_default_opts.argtypes = [ctypes.POINTER(TensorOpts)]
+    lib.frsvt_tensor_default_opts.restype = None
+    lib.tensor_rpca.argtypes = [_vp, ctypes.c_int, _i64, _i64, _i64, _vp, ctypes.POINTER(_dbl), _dbl,
+                                ctypes.POINTER(TensorOpts), _vp, _vp, ctypes.POINTER(TensorStats)]
     lib.frsvt_fwd.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _i64, _dbl, _i32, _i32, _i32, _u64,
                               _u64, _vp, _i64, _vp, _i64, _vp]
     lib.frsvt_vjp.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _i64, _dbl, _i32, _i32, _i32, _u64,
@@ -743,3 +757,46 @@ def lrr_ialm(X, lam: float, *, use_frsvt: bool = True, p: int = 5, q: int = 1, s
                         E.data_ptr(), d, ctypes.byref(st))
     _check(h, rc, "lrr_ialm", ok=(OK, MAX_ITER))
     return LrrResult(Z, E, st.iters, bool(st.converged), st.rank, st.primal, st.dual, st.seconds)
+
+
+@dataclass
+class TensorResult:
+    L: object
+    E: object
+    iters: int
+    converged: bool
+    rank: tuple
+    resid: float
+    mu0: float
+    seconds: float
+
+
+def tensor_rpca(O, alpha, lam: float, *, use_frsvt: bool = True, p: int = 5, q: int = 1, seed: int = 0,
+                tol: float = 1e-7, max_iter: int = 100, mu0: float = 0.0, rho: float = 1.5,
+                mu_max: float = 1e10) -> TensorResult:
+    """Low-rank + sparse decomposition of a 3-way tensor (Type C of Table 6,
+    alignment fixed): min sum_i alpha_i ||L_(i)||_* + lam ||E||_1 s.t.
+    O = L + E, each mode's SVT by FRSVT + range propagation (or exact SVT).
+    O is a float64 GPU tensor of shape (I1, I2, I3); it is used in
+    column-major order (first index fastest), copied once if it is not
+    stored that way.  L and E come back with O's shape."""
+    import torch
+    h = handle(O.device.index)
+    if O.dtype != torch.float64 or O.dim() != 3:
+        raise TypeError("tensor_rpca takes a 3-way float64 tensor")
+    I1, I2, I3 = O.shape
+    Oc = O.permute(2, 1, 0).contiguous().permute(2, 1, 0)
+    L = torch.empty((I3, I2, I1), dtype=O.dtype, device=O.device).permute(2, 1, 0)
+    E = torch.empty((I3, I2, I1), dtype=O.dtype, device=O.device).permute(2, 1, 0)
+    if len(alpha) != 3:
+        raise ValueError("alpha holds one weight per mode")
+    al = (_dbl * 3)(*[float(a) for a in alpha])
+    op = TensorOpts()
+    h.lib.frsvt_tensor_default_opts(ctypes.byref(op))
+    op.tol, op.max_iter, op.mu0, op.rho, op.mu_max = tol, max_iter, mu0, rho, mu_max
+    op.use_frsvt, op.p, op.q, op.seed = int(use_frsvt), p, q, seed
+    st = TensorStats()
+    rc = h.lib.tensor_rpca(h.ptr, F64, I1, I2, I3, Oc.data_ptr(), al, float(lam), ctypes.byref(op),
+                           L.data_ptr(), E.data_ptr(), ctypes.byref(st))
+    _check(h, rc, "tensor_rpca", ok=(OK, MAX_ITER))
+    return TensorResult(L, E, st.iters, bool(st.converged), tuple(st.rank), st.resid, st.mu0, st.seconds)

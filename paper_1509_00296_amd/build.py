@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfrsvt.so")
-SOURCES = ["long_pass.hip", "small_dense.hip", "elementwise.hip", "gemm.hip", "gemm_mfma.hip", "wsvt_batched.hip", "adjoint.hip", "lrr.hip", "api.hip"]
+SOURCES = ["long_pass.hip", "small_dense.hip", "elementwise.hip", "gemm.hip", "gemm_mfma.hip", "wsvt_batched.hip", "adjoint.hip", "lrr.hip", "tensor.hip", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

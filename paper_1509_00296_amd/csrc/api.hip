@@ -1640,6 +1640,103 @@ int lrr_impl(frsvt_context *h, int64_t d, int64_t n, const double *X, int64_t ld
     return converged ? FRSVT_OK : FRSVT_MAX_ITER;
 }
 
+
+// 3-way tensor host: O (I1 x I2 x I3, column-major) = L + E with the
+// weighted sum of the unfoldings' nuclear norms and lambda ||E||_1, by an
+// inexact ALM over one copy L_i of L per mode (each with its own constraint
+// O = L_i + E and multiplier Y_i).  Mode 1's unfolding is O itself (ld I1),
+// mode 3's is the transpose of the (I1 I2) x I3 view (the SVT commutes with
+// the transpose and the sketch sees the same short-by-long matrix), mode 2's
+// lives in a permuted buffer.
+int tensor_impl(frsvt_context *h, int64_t I1, int64_t I2, int64_t I3, const double *O, const double *alpha,
+                double lambda, const frsvt_tensor_opts &op, double *L, double *E, frsvt_tensor_stats *stats)
+{
+    hipStream_t s = h->stream;
+    if (stats) memset(stats, 0, sizeof(*stats));
+    const int64_t N = I1 * I2 * I3;
+    const int64_t vm[3] = {I1, I2, I1 * I2}, vn[3] = {I2 * I3, I1 * I3, I3};
+    int64_t mh[3];
+    for (int i = 0; i < 3; ++i) mh[i] = std::min(vm[i], vn[i]);
+    double normF = 0.0, mx = 0.0, norm2 = 0.0;
+    int rc = input_norms<double>(h, I1, I2 * I3, O, I1, &normF, &mx);
+    if (rc) return rc;
+    if (!(normF > 0.0)) return FRSVT_ERR_NONFINITE;
+    double mu = op.mu0;
+    if (!(mu > 0.0)) {
+        if ((rc = spectral_norm<double>(h, O, I1, orient(I1, I2 * I3, I1), &norm2))) return rc;
+        mu = 1.25 / norm2;
+    }
+    const double mu0 = mu;
+    const int np = ten_parts();
+    const size_t total = 8 * (size_t)N + (size_t)(mh[0] * mh[0] + mh[1] * mh[1] + mh[2] * mh[2]) + 3 * (size_t)np + 4;
+    DevBlock blk;
+    CK(hipMalloc(&blk.p, total * sizeof(double)));
+    double *L2p = (double *)blk.p, *L3 = L2p + N, *Y1 = L3 + N, *Y2 = Y1 + N, *Y3 = Y2 + N;
+    double *A1 = Y3 + N, *A2p = A1 + N, *A3 = A2p + N;
+    double *Q[3];
+    Q[0] = A3 + N;
+    Q[1] = Q[0] + mh[0] * mh[0];
+    Q[2] = Q[1] + mh[1] * mh[1];
+    double *part = Q[2] + mh[2] * mh[2], *sums = part + 3 * (size_t)np;
+    double *L1 = L;
+    CK(launch_lrr_comb(N, 1, 0, nullptr, 0, 0, nullptr, 0, 0, nullptr, 0, 0.0, Y1, N, s));
+    CK(launch_lrr_comb(N, 1, 0, nullptr, 0, 0, nullptr, 0, 0, nullptr, 0, 0.0, Y2, N, s));
+    CK(launch_lrr_comb(N, 1, 0, nullptr, 0, 0, nullptr, 0, 0, nullptr, 0, 0.0, Y3, N, s));
+    CK(launch_ten_perm(I1, I2, I3, O, A2p, s));
+    double *X[3] = {L1, L2p, L3};
+    int r_prev[3] = {-1, -1, -1}, r[3] = {0, 0, 0};
+    double res = 0.0;
+    bool converged = false;
+    int it;
+    const auto t0 = std::chrono::steady_clock::now();
+    for (it = 0; it < op.max_iter; ++it) {
+        // the iteration's SVT inputs O - E + Y_i / mu (O itself at the start)
+        const double *A[3] = {it ? A1 : O, A2p, it ? A3 : O};
+        for (int i = 0; i < 3; ++i) {
+            int32_t rr = 0;
+            const double tau = alpha[i] / mu;
+            if (op.use_frsvt) {
+                const int l0 = std::max(1, (int)std::ceil(0.1 * (double)mh[i]));
+                const bool prop = r_prev[i] > 0;
+                const int kk = r_prev[i] < 0 ? l0 : 0, pp = r_prev[i] < 0 ? 0 : op.p;
+                if ((rc = frsvt_impl<double>(h, vm[i], vn[i], A[i], vm[i], tau, kk, pp, op.q, prop ? Q[i] : nullptr,
+                                             prop ? r_prev[i] : 0, mh[i], op.seed + (uint64_t)i, (uint64_t)it,
+                                             X[i], vm[i], Q[i], mh[i], &rr)))
+                    return rc;
+                r_prev[i] = rr;
+            } else {
+                if ((rc = exact_svt_impl<double>(h, vm[i], vn[i], A[i], vm[i], tau, nullptr, X[i], vm[i], &rr)))
+                    return rc;
+            }
+            r[i] = rr;
+        }
+        const double mu_next = std::min(op.rho * mu, op.mu_max);
+        CK(launch_ten_update(I1, I2, I3, O, L1, L2p, L3, Y1, Y2, Y3, E, A1, A2p, A3, mu, lambda / (3.0 * mu),
+                             mu_next, part, sums, s));
+        CK(hipMemcpyAsync(h->pinned, sums, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+        const double *hs = (const double *)h->pinned;
+        res = std::sqrt(std::max({hs[0], hs[1], hs[2]})) / normF;
+        mu = mu_next;
+        if (res < op.tol) {
+            converged = true;
+            ++it;
+            break;
+        }
+    }
+    CK(launch_ten_mean(I1, I2, I3, L1, L2p, L3, L, s));
+    CK(hipStreamSynchronize(s));
+    if (stats) {
+        stats->iters = it;
+        stats->converged = converged ? 1 : 0;
+        for (int i = 0; i < 3; ++i) stats->rank[i] = r[i];
+        stats->resid = res;
+        stats->mu0 = mu0;
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return converged ? FRSVT_OK : FRSVT_MAX_ITER;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -2146,4 +2243,49 @@ int lrr_ialm(frsvt_handle h, frsvt_precision prec, int64_t d, int64_t n, const v
     if (lde < d) return -12;
     if (prec != FRSVT_F64 || n > 1024) return FRSVT_ERR_UNSUPPORTED;
     return lrr_impl(h, d, n, (const double *)X, ldx, lambda, op, (double *)Z, ldz, (double *)E, lde, stats);
+}
+
+void frsvt_tensor_default_opts(frsvt_tensor_opts *op)
+{
+    if (!op) return;
+    memset(op, 0, sizeof(*op));
+    op->tol = 1e-7;
+    op->max_iter = 100;
+    op->mu0 = 0.0;
+    op->rho = 1.5;
+    op->mu_max = 1e10;
+    op->use_frsvt = 1;
+    op->p = 5;
+    op->q = 1;
+    op->seed = 0;
+}
+
+int tensor_rpca(frsvt_handle h, frsvt_precision prec, int64_t I1, int64_t I2, int64_t I3, const void *O,
+                const double *alpha, double lambda, const frsvt_tensor_opts *opts, void *L, void *E,
+                frsvt_tensor_stats *stats)
+{
+    if (!h) return -1;
+    if (prec != FRSVT_F64 && prec != FRSVT_F32 && prec != FRSVT_MIXED_BF16) return -2;
+    if (I1 < 1) return -3;
+    if (I2 < 1) return -4;
+    if (I3 < 1) return -5;
+    if (bad_ptr(O)) return -6;
+    if (!alpha) return -7;
+    for (int i = 0; i < 3; ++i)
+        if (!(alpha[i] >= 0.0) || !std::isfinite(alpha[i])) return -7;
+    if (!(lambda > 0.0) || !std::isfinite(lambda)) return -8;
+    frsvt_tensor_opts op;
+    frsvt_tensor_default_opts(&op);
+    if (opts) op = *opts;
+    if (!(op.tol > 0.0) || op.max_iter < 1 || !(op.mu0 >= 0.0) || !(op.rho >= 1.0) || !(op.mu_max > 0.0) ||
+        (op.mu0 > 0.0 && op.mu_max < op.mu0) || op.p < 1 || op.q < 0 || (op.use_frsvt != 0 && op.use_frsvt != 1))
+        return -9;
+    if (bad_ptr(L)) return -10;
+    if (bad_ptr(E)) return -11;
+    if (L == E || L == O || E == O) return -11;
+    if (prec != FRSVT_F64) return FRSVT_ERR_UNSUPPORTED;
+    if (I1 > (int64_t)1 << 20 || I2 > (int64_t)1 << 20 || I3 > (int64_t)1 << 20) return FRSVT_ERR_UNSUPPORTED;
+    if (std::min(I1, I2 * I3) > 1024 || std::min(I2, I1 * I3) > 1024 || std::min(I1 * I2, I3) > 1024)
+        return FRSVT_ERR_UNSUPPORTED;
+    return tensor_impl(h, I1, I2, I3, (const double *)O, alpha, lambda, op, (double *)L, (double *)E, stats);
 }

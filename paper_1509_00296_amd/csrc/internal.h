@@ -356,5 +356,20 @@ hipError_t launch_lrr_dual(int64_t m, int64_t n, double mu, const double *P, int
                            int64_t ldq, const double *R, int64_t ldr, double *Y, double *part, hipStream_t s);
 // out[k] = max_g part[k * nparts + g], k < count
 hipError_t launch_lrr_max_parts(const double *part, int nparts, int count, double *out, hipStream_t s);
+// ------------------------------------------------ 3-way tensor host
+// (column-major I1 x I2 x I3; "mode-2 layout" = the mode-2 unfolding,
+// rows i2, columns i1 + I1 i3)
+int ten_parts();
+// A2p = O in mode-2 layout
+hipError_t launch_ten_perm(int64_t I1, int64_t I2, int64_t I3, const double *O, double *A2p, hipStream_t s);
+// E = shrink_thr(mean_i(O - L_i + Y_i/mu)), Y_i += mu (O - L_i - E),
+// A_i = O - E + Y_i/mu_next; sums[i] = ||O - L_i - E||_F^2 (part: 3 ten_parts())
+hipError_t launch_ten_update(int64_t I1, int64_t I2, int64_t I3, const double *O, const double *L1,
+                             const double *L2p, const double *L3, double *Y1, double *Y2, double *Y3, double *E,
+                             double *A1, double *A2p, double *A3, double mu, double thr, double mu_next,
+                             double *part, double *sums, hipStream_t s);
+// L = (L1 + L2 + L3) / 3 (L may alias L1)
+hipError_t launch_ten_mean(int64_t I1, int64_t I2, int64_t I3, const double *L1, const double *L2p,
+                           const double *L3, double *L, hipStream_t s);
 
 }  // namespace frk

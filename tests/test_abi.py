@@ -109,6 +109,19 @@ def test_argument_validation_precedes_device_use(lib):
         # r_init = 11 > min(m, n); r_init = 2 without q_init
         assert lib.rpca_ialm(dummy, 0, 10, 10, buf, 10, 0.1, ctypes.byref(op), buf, 10, buf, 10,
                              None) == -8, field
+    lib.tensor_rpca.argtypes = [vp, ctypes.c_int, i64, i64, i64, vp, vp, d, vp, vp, vp, vp]
+    al = (d * 3)(0.2, 0.3, 0.5)
+    bad_al = (d * 3)(0.2, -0.3, 0.5)
+    assert lib.tensor_rpca(dummy, 0, 4, 0, 5, buf, al, 0.1, None, buf, buf, None) == -4     # I2 < 1
+    assert lib.tensor_rpca(dummy, 0, 4, 3, 5, buf, None, 0.1, None, buf, buf, None) == -7   # alpha NULL
+    assert lib.tensor_rpca(dummy, 0, 4, 3, 5, buf, bad_al, 0.1, None, buf, buf, None) == -7
+    assert lib.tensor_rpca(dummy, 0, 4, 3, 5, buf, al, 0.0, None, buf, buf, None) == -8     # lambda
+    top = fr.TensorOpts()
+    lib.frsvt_tensor_default_opts(ctypes.byref(top))
+    top.rho = 0.5
+    assert lib.tensor_rpca(dummy, 0, 4, 3, 5, buf, al, 0.1, ctypes.byref(top), buf, buf, None) == -9
+    buf2 = ctypes.c_void_p(ctypes.addressof(ctypes.create_string_buffer(64)))
+    assert lib.tensor_rpca(dummy, 0, 4, 3, 5, buf, al, 0.1, None, buf2, buf2, None) == -11  # L aliases E
     lib.wsvt_batched.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp]
     assert lib.wsvt_batched(dummy, -1, None, None, None, None, None, None, None) == -2
 
@@ -145,6 +158,8 @@ def test_struct_layouts_match_header(tmp_path):
         "         offsetof(frsvt_rpca_stats, resid_est), sizeof(frsvt_wsvt_rule));\n"
         '  printf("%zu %zu %zu\\n", sizeof(frsvt_lrr_opts), sizeof(frsvt_lrr_stats),\n'
         "         offsetof(frsvt_lrr_opts, seed));\n"
+        '  printf("%zu %zu %zu %zu\\n", sizeof(frsvt_tensor_opts), sizeof(frsvt_tensor_stats),\n'
+        "         offsetof(frsvt_tensor_opts, seed), offsetof(frsvt_tensor_stats, resid));\n"
         "  return 0;\n}\n")
     exe = tmp_path / "sizes"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
@@ -152,5 +167,7 @@ def test_struct_layouts_match_header(tmp_path):
                                           check=True).stdout.split()]
     want = [ctypes.sizeof(fr.RpcaOpts), ctypes.sizeof(fr.RpcaStats), fr.RpcaOpts.seed.offset,
             fr.RpcaOpts.q_final.offset, fr.RpcaStats.resid_est.offset, ctypes.sizeof(fr.WsvtRule),
-            ctypes.sizeof(fr.LrrOpts), ctypes.sizeof(fr.LrrStats), fr.LrrOpts.seed.offset]
+            ctypes.sizeof(fr.LrrOpts), ctypes.sizeof(fr.LrrStats), fr.LrrOpts.seed.offset,
+            ctypes.sizeof(fr.TensorOpts), ctypes.sizeof(fr.TensorStats), fr.TensorOpts.seed.offset,
+            fr.TensorStats.resid.offset]
     assert got == want
