@@ -53,6 +53,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 M, N, RANK, FRAC = 76800, 200, 3, 0.10
 N_CLASSES = 13
+EXACT_COMPARATORS = True    # the further workloads' exact-SVT loops (off with --exact-steps 0)
 
 
 def parse():
@@ -62,7 +63,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--prec", choices=["f64", "f32"], default="f64")
     ap.add_argument("--exact-steps", type=int, default=1,
-                    help="complete RPCA solves with this library's exact SVT")
+                    help="complete RPCA solves with this library's exact SVT (0 also skips the "
+                         "further workloads' exact-SVT loops)")
     ap.add_argument("--vendor-iters", type=int, default=3,
                     help="iALM iterations with torch.linalg.svd as the SVT (0 = skip)")
     ap.add_argument("--cpu-iters", type=int, default=6,
@@ -370,19 +372,20 @@ def wl_lrr(torch, fr, synth, tracer):
     ecol = torch.linalg.norm(res.E, dim=0).cpu().numpy()
     found = len(set(np.argsort(-ecol)[:bad.size].tolist()) & set(bad.tolist())) / bad.size
     # the same loop with the exact SVT in the J step, a bounded number of iterations
-    K = 4
-    t1 = time.perf_counter()
-    ex = fr.lrr_ialm(X, lam, use_frsvt=False, max_iter=K)
-    torch.cuda.synchronize()
-    ex_sec = time.perf_counter() - t1
+    ex_ms = None
+    if EXACT_COMPARATORS:
+        t1 = time.perf_counter()
+        ex = fr.lrr_ialm(X, lam, use_frsvt=False, max_iter=4)
+        torch.cuda.synchronize()
+        ex_ms = 1e3 * (time.perf_counter() - t1) / ex.iters
     return {"workload": "lrr_ialm_2016x640_f64", "metric": "s per solve", "unit": "s",
             "config": {"d": d, "n": n, "groups": 10, "dim": 9, "corrupt_cols": int(bad.size),
                        "lambda": lam, "p": 5, "q": 1, "tol": 1e-8},
             "seconds": round(sec, 4), "iters": res.iters, "converged": res.converged,
             "ms_per_iter": round(1e3 * sec / res.iters, 3), "rank": res.rank,
             "z_mass_in_blocks": round(float(inblock), 4), "corrupt_cols_found": round(found, 4),
-            "exact_svt_ms_per_iter": round(1e3 * ex_sec / ex.iters, 3),
-            "exact_svt_est_seconds": round(ex_sec / ex.iters * res.iters, 2)}
+            "exact_svt_ms_per_iter": round(ex_ms, 3) if ex_ms else None,
+            "exact_svt_est_seconds": round(ex_ms * res.iters / 1e3, 2) if ex_ms else None}
 
 
 def wl_tensor(torch, fr, synth, tracer):
@@ -403,21 +406,24 @@ def wl_tensor(torch, fr, synth, tracer):
         its += res.iters
     err = float(torch.linalg.norm(res.L - Lgt) / torch.linalg.norm(Lgt))
     # the same loop with exact SVTs, a bounded number of iterations
-    KE = 3
-    t1 = time.perf_counter()
-    ex = fr.tensor_rpca(O, alpha, lam, use_frsvt=False, max_iter=KE)
-    torch.cuda.synchronize()
-    ex_sec = time.perf_counter() - t1
+    ex_ms = None
+    if EXACT_COMPARATORS:
+        t1 = time.perf_counter()
+        ex = fr.tensor_rpca(O, alpha, lam, use_frsvt=False, max_iter=3)
+        torch.cuda.synchronize()
+        ex_ms = 1e3 * (time.perf_counter() - t1) / ex.iters
     return {"workload": "tensor_rpca_32x22x3000_f64", "metric": "ms per solve", "unit": "ms",
             "config": {"shape": list(shape), "tucker_ranks": [3, 3, 5], "outliers": 0.05, "alpha": list(alpha),
                        "lambda": lam, "p": 5, "q": 1, "tol": 1e-7},
             "ms_per_solve": round(1e3 * sec / K, 3), "iters": res.iters, "converged": res.converged,
             "ms_per_iter": round(1e3 * sec / its, 4), "ranks": list(res.rank), "nrmse_L": err,
-            "exact_svt_ms_per_iter": round(1e3 * ex_sec / ex.iters, 3)}
+            "exact_svt_ms_per_iter": round(ex_ms, 3) if ex_ms else None}
 
 
 def main():
     args = parse()
+    global EXACT_COMPARATORS
+    EXACT_COMPARATORS = args.exact_steps > 0
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build targets exactly one GPU; multi-GPU runs are not part of it "
