@@ -66,3 +66,63 @@ def test_pins_reject_planted_mistake(tmp_path, name, orig, bad):
                            "--timeout", "120", *PIN_FILES], cwd=ROOT, env=env,
                           capture_output=True, text=True, timeout=900)
     assert proc.returncode != 0, f"mutant {name} survived the pin tests:\n{proc.stdout[-2000:]}"
+
+
+# The tensor host of the oracle is numpy glue in oracle/__init__.py: its
+# mutants are planted in a copy of the package and checked against its pins.
+PY_SRC = os.path.join(ROOT, "oracle", "__init__.py")
+PY_PIN_FILES = ["tests/test_oracle_tensor.py"]
+PY_MUTANTS = [
+    ("tensor_shrink_threshold", "shrink(V, lam / (3.0 * mu))", "shrink(V, lam / mu)"),
+    ("tensor_svt_ignores_weight", "X, r = svt(M, alpha[i] / mu)", "X, r = svt(M, 1.0 / mu)"),
+    ("tensor_dual_sign", "Y[i] = Y[i] + mu * Z", "Y[i] = Y[i] - mu * Z"),
+    ("tensor_mean_divisor", "for i in range(3)) / 3.0", "for i in range(3)) / 2.0"),
+    ("tensor_input_without_multiplier", "M = unfold(O - E + Y[i] / mu, i)", "M = unfold(O - E, i)"),
+    ("tensor_residual_min", "res = max(res, np.linalg.norm(Z) / normO)", "res = min(res, np.linalg.norm(Z) / normO)"),
+    ("unfold_row_major_columns", 'reshape(T.shape[mode], -1, order="F")', 'reshape(T.shape[mode], -1, order="C")'),
+    ("fold_wrong_axis", "np.moveaxis(T, 0, mode)", "np.moveaxis(T, mode, 0)"),
+]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,orig,bad", PY_MUTANTS, ids=[m[0] for m in PY_MUTANTS])
+def test_tensor_pins_reject_planted_mistake(tmp_path, name, orig, bad):
+    import shutil
+    src = open(PY_SRC).read()
+    assert src.count(orig) == 1, f"mutation anchor for {name} not unique"
+    pkg = tmp_path / "oracle"
+    pkg.mkdir()
+    for f in ("frsvt_oracle.c", "frsvt_oracle.h", "liboracle.so"):
+        if os.path.exists(os.path.join(ROOT, "oracle", f)):
+            shutil.copy(os.path.join(ROOT, "oracle", f), pkg / f)
+    (pkg / "__init__.py").write_text(src.replace(orig, bad))
+    # run from the copy's parent so that `import oracle` finds the mutant first
+    env = dict(os.environ, PYTHONPATH=ROOT)
+    env.pop("FRSVT_ORACLE_LIB", None)
+    proc = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                           "--timeout", "120", "--rootdir", ROOT,
+                           *[os.path.join(ROOT, f) for f in PY_PIN_FILES]],
+                          cwd=str(tmp_path), env=env, capture_output=True, text=True, timeout=900)
+    assert proc.returncode != 0, f"mutant {name} survived the pin tests:\n{proc.stdout[-2000:]}"
+
+
+def test_tensor_mutant_harness_uses_the_copy(tmp_path):
+    """The harness above really imports the copy: an unchanged copy passes
+    and a copy whose tensor host raises fails."""
+    import shutil
+    pkg = tmp_path / "oracle"
+    pkg.mkdir()
+    for f in ("frsvt_oracle.c", "frsvt_oracle.h", "liboracle.so"):
+        if os.path.exists(os.path.join(ROOT, "oracle", f)):
+            shutil.copy(os.path.join(ROOT, "oracle", f), pkg / f)
+    src = open(PY_SRC).read()
+    env = dict(os.environ, PYTHONPATH=ROOT)
+    env.pop("FRSVT_ORACLE_LIB", None)
+    cmd = [sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "--rootdir", ROOT,
+           os.path.join(ROOT, "tests", "test_oracle_tensor.py")]
+    (pkg / "__init__.py").write_text(src)
+    assert subprocess.run(cmd, cwd=str(tmp_path), env=env, capture_output=True).returncode == 0
+    anchor = "    O = np.asfortranarray(np.asarray(O, dtype=np.float64))\n    shape = O.shape\n"
+    assert src.count(anchor) == 1
+    (pkg / "__init__.py").write_text(src.replace(anchor, anchor + "    raise RuntimeError('copy')\n"))
+    assert subprocess.run(cmd, cwd=str(tmp_path), env=env, capture_output=True).returncode != 0
