@@ -13,6 +13,7 @@ namespace frk {
 
 constexpr int kTenThreads = 256;
 constexpr int kTenBlocks = 1024;
+constexpr int64_t kTenSlice = 8192;   // frontal slices up to this size go whole to one workgroup
 
 __device__ __forceinline__ int64_t mode2_index(int64_t t, int64_t I1, int64_t I2)
 {
@@ -40,7 +41,7 @@ __global__ void __launch_bounds__(kTenThreads)
 {
     __shared__ double red[3][kTenThreads / kWave];
     double s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    for (int64_t t = (int64_t)blockIdx.x * kTenThreads + threadIdx.x; t < N; t += (int64_t)gridDim.x * kTenThreads) {
+    auto step = [&](int64_t t) {
         const int64_t tp = mode2_index(t, I1, I2);
         const double o = O[t];
         const double l1 = L1[t], l2 = L2p[tp], l3 = L3[t];
@@ -63,6 +64,20 @@ __global__ void __launch_bounds__(kTenThreads)
         A1[t] = oe + y1 * inv_mu_next;
         A2p[tp] = oe + y2 * inv_mu_next;
         A3[t] = oe + y3 * inv_mu_next;
+    };
+    // Small frontal slices go whole to one workgroup, so that a slice's
+    // region of the mode-2 buffer (its I1 I2 values, consecutive there) is
+    // read and written by one workgroup and its cache lines are completed in
+    // one L2; larger slices are dealt out element by element.
+    const int64_t S = I1 * I2;
+    if (S <= kTenSlice) {
+        const int64_t nslice = N / S;
+        for (int64_t sl = blockIdx.x; sl < nslice; sl += gridDim.x)
+            for (int64_t e = threadIdx.x; e < S; e += kTenThreads) step(sl * S + e);
+    } else {
+        for (int64_t t = (int64_t)blockIdx.x * kTenThreads + threadIdx.x; t < N;
+             t += (int64_t)gridDim.x * kTenThreads)
+            step(t);
     }
     s1 = wave_sum(s1);
     s2 = wave_sum(s2);

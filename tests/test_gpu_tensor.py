@@ -48,10 +48,13 @@ def _check(fr, orc, O, alpha, lam, mode, **kw):
 
 # (shape, Tucker ranks, lambda * sqrt(max(I1 I2, I3)), alpha): the first has
 # every unfolding wide, the second a tall mode-1 unfolding (short side I2 I3),
-# the third a wide mode-3 unfolding (short side I3); each recovers L
+# the third a wide mode-3 unfolding (short side I3), the fourth frontal slices
+# above 8192 values (the update pass deals them out element by element
+# instead of one slice per workgroup); each recovers L
 @pytest.mark.parametrize("shape,ranks,c,alpha", [((12, 10, 50), (2, 2, 3), 1.0, (0.15, 0.15, 0.7)),
                                                  ((60, 6, 8), (2, 2, 2), 2.0, (0.5, 0.25, 0.25)),
-                                                 ((7, 33, 9), (2, 2, 2), 1.0, (0.15, 0.15, 0.7))])
+                                                 ((7, 33, 9), (2, 2, 2), 1.0, (0.15, 0.15, 0.7)),
+                                                 ((100, 90, 3), (2, 2, 2), 2.0, (0.4, 0.4, 0.2))])
 @pytest.mark.parametrize("mode", ["exact", "frsvt"])
 def test_tensor_rpca_matches_oracle(fr, orc, shape, ranks, c, alpha, mode):
     from paper_1509_00296_amd import synth
