@@ -493,7 +493,8 @@ FRSVT_API void frsvt_tensor_default_opts(frsvt_tensor_opts *opts);
  *   stats  [out, HOST, optional].
  * The call allocates its iteration state (8 tensors plus the three modes'
  * bases) and frees it before returning; the host reads three residuals per
- * iteration.  Returns FRSVT_MAX_ITER when max_iter was reached before tol.
+ * iteration.  O = 0 returns L = E = 0 with no iteration.  Returns
+ * FRSVT_MAX_ITER when max_iter was reached before tol.
  */
 FRSVT_API int tensor_rpca(frsvt_handle handle, frsvt_precision prec, int64_t I1, int64_t I2, int64_t I3,
                           const void *O, const double *alpha, double lambda, const frsvt_tensor_opts *opts,

@@ -1660,7 +1660,14 @@ int tensor_impl(frsvt_context *h, int64_t I1, int64_t I2, int64_t I3, const doub
     double normF = 0.0, mx = 0.0, norm2 = 0.0;
     int rc = input_norms<double>(h, I1, I2 * I3, O, I1, &normF, &mx);
     if (rc) return rc;
-    if (!(normF > 0.0)) return FRSVT_ERR_NONFINITE;
+    if (!(normF > 0.0)) {
+        // O = 0: the minimiser is L = E = 0
+        CK(launch_lrr_comb(N, 1, 0, nullptr, 0, 0, nullptr, 0, 0, nullptr, 0, 0.0, L, N, s));
+        CK(launch_lrr_comb(N, 1, 0, nullptr, 0, 0, nullptr, 0, 0, nullptr, 0, 0.0, E, N, s));
+        CK(hipStreamSynchronize(s));
+        if (stats) stats->converged = 1;
+        return FRSVT_OK;
+    }
     double mu = op.mu0;
     if (!(mu > 0.0)) {
         if ((rc = spectral_norm<double>(h, O, I1, orient(I1, I2 * I3, I1), &norm2))) return rc;

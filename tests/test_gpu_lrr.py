@@ -84,3 +84,27 @@ def test_lrr_matches_oracle(fr, orc, mode, corrupt):
     assert r_robust <= res.rank and abs(res.rank - int(out["ranks"][-1])) <= noise
     if not corrupt:
         assert res.rank == out["ranks"][-1] == 12
+
+
+def test_lrr_iteration_limit(fr, orc):
+    """A run stopped by the iteration limit (200 iterations, threshold 1/mu
+    near 5e-3, rank settled at 11): the same partial iterate."""
+    X, rng = _subspaces(2)
+    bad = rng.choice(60, 6, replace=False)
+    X[:, bad] += 3.0 * rng.standard_normal((80, 6))
+    _say("case lrr frsvt limit 80x60")
+    res = fr.lrr_ialm(torch.from_numpy(np.asfortranarray(X)).cuda(), 0.1, p=5, q=1, seed=3, max_iter=200)
+    out = orc.lrr_ialm(X, 0.1, mode="frsvt", p=5, q=1, seed=3, max_iter=200)
+    assert not res.converged and not out["converged"] and res.iters == out["iters"] == 200
+    assert res.rank == out["ranks"][-1] == 11
+    assert _rel(res.Z.cpu().numpy(), out["Z"]) <= 1e-8
+    assert _rel(res.E.cpu().numpy(), out["E"]) <= 1e-8
+
+
+def test_lrr_zero_data(fr):
+    """X = 0: Z = E = 0 after one iteration (both residuals vanish)."""
+    _say("case lrr zero")
+    X = torch.zeros((30, 20), dtype=torch.float64, device="cuda")
+    res = fr.lrr_ialm(X, 0.1)
+    assert res.converged and res.iters == 1 and res.rank == 0
+    assert float(res.Z.abs().max()) == 0.0 and float(res.E.abs().max()) == 0.0

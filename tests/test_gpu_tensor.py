@@ -84,3 +84,12 @@ def test_tensor_rpca_gait_shape(fr, orc):
     res, out = _check(fr, orc, O, (0.15, 0.15, 0.7), lam, "frsvt")
     assert res.converged and list(res.rank) == [3, 3, 5]
     assert _rel(res.L.cpu().numpy(), L) < 1e-6
+
+
+def test_tensor_rpca_zero_tensor(fr):
+    """O = 0: the minimiser is L = E = 0, returned without iterating."""
+    _say("case tensor zero")
+    O = torch.zeros((5, 4, 6), dtype=torch.float64, device="cuda")
+    res = fr.tensor_rpca(O, (0.3, 0.3, 0.4), 0.1)
+    assert res.converged and res.iters == 0
+    assert float(res.L.abs().max()) == 0.0 and float(res.E.abs().max()) == 0.0
