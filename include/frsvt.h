@@ -24,14 +24,15 @@
  *   nhat = max(m,n) columns, so that the power iteration acts on the short
  *   side.  The sketch Omega is nhat x l; the propagated basis Q~ is mhat x r.
  * - Ownership: the caller owns every input and output buffer.  The library
- *   owns only its workspace, held in the handle, grown on demand and freed by
- *   frsvt_destroy.  All work is enqueued on the handle's HIP stream in order;
+ *   owns its workspace, held in the handle, grown on demand and freed by
+ *   frsvt_destroy; lrr_ialm and tensor_rpca also allocate their iteration
+ *   state for the duration of the call.  All work is enqueued on the handle's HIP stream in order;
  *   an entry point blocks the host only when it writes a HOST output pointer
  *   (ranks, statistics), which it documents.
  * - Status codes (LAPACK-like `info`): 0 success; -i the i-th argument is
  *   invalid (nothing is launched); FRSVT_NOT_CONVERGED (+1) a Jacobi sweep
- *   limit was reached (the result is still written); FRSVT_MAX_ITER (+2) RPCA
- *   stopped at max_iter; FRSVT_ERR_* below for runtime failures.  No C++
+ *   limit was reached (the result is still written); FRSVT_MAX_ITER (+2) an
+ *   iterative host (rpca_ialm, lrr_ialm, tensor_rpca) stopped at max_iter; FRSVT_ERR_* below for runtime failures.  No C++
  *   exception crosses this interface.
  */
 #ifndef FRSVT_H
