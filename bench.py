@@ -573,6 +573,35 @@ def main():
             further["tensor"] = {"value": round(o["iters"] / dt, 4), "unit": "iters/s",
                                  "sample": f"32x22x3000 FP64, first {o['iters']} iterations with FRSVT-RP per "
                                            f"mode (including ||O_(1)||_2), single thread, {dt:.1f} s"}
+        if "single" in workloads and "error" not in workloads["single"]:
+            A_np = synth.single_svt(seed=0)
+            Om = oracle.gaussian_matrix(1, 0, 500, 15)
+            a = time.perf_counter()
+            k = 0
+            while time.perf_counter() - a < 1.0:
+                oracle.frsvt(A_np, 1.0, 2, Om)
+                k += 1
+            dt = time.perf_counter() - a
+            b = time.perf_counter()
+            oracle.svt(A_np, 1.0)
+            de = time.perf_counter() - b
+            further["single"] = {"value": round(k / dt, 3), "unit": "calls/s",
+                                 "exact_svt_calls_per_s": round(1.0 / de, 3),
+                                 "sample": f"500x300 FP64 FRSVT (l 15, q 2), {k} calls in {dt:.1f} s, and one "
+                                           f"exact SVT ({de:.2f} s), single thread"}
+        if "batched" in workloads and "error" not in workloads["batched"]:
+            import numpy as np
+            rows, cols, offs, packed = synth.patch_groups(seed=0, count=8192)
+            K = 512
+            a = time.perf_counter()
+            for j in range(K):
+                rj, cj = int(rows[j]), int(cols[j])
+                Mj = packed[offs[j]:offs[j] + rj * cj].astype(np.float64).reshape((rj, cj), order="F")
+                oracle.wsvt_rule(Mj, c=2.8, noise_var=0.01)
+            dt = time.perf_counter() - a
+            further["batched"] = {"value": round(K / dt, 2), "unit": "matrices/s",
+                                  "sample": f"the first {K} of the 8192 patch-group matrices, FP64 WSVT with the "
+                                            f"patch-group weights, single thread, {dt:.1f} s"}
         if further:
             cpu["further"] = further
 
