@@ -62,9 +62,9 @@ double orc_uniform53(uint32_t a, uint32_t b)
     return (hi * 67108864.0 + lo + 0.5) * (1.0 / 9007199254740992.0);
 }
 
-/* Omega of Alg. 1 (both sampling steps): a dense standard Gaussian matrix, Sec. 2.4
- * ("dense Gaussian random matrices drawn from standard normal distribution
- * in entry-wise").  Box-Muller turns each Philox output into two normals.  */
+/* Omega of Alg. 1 (both sampling steps): Sec. 2.4 takes a dense test matrix
+ * with iid N(0,1) entries.  Box-Muller turns each Philox output into two
+ * normals.  */
 void orc_gaussian_matrix(uint64_t seed, uint64_t counter, int64_t rows, int64_t cols,
                          double *Om, int64_t ld)
 {
