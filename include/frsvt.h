@@ -66,6 +66,10 @@ typedef enum {
 #define FRSVT_ERR_NONFINITE (-102)
 #define FRSVT_ERR_UNSUPPORTED (-104)
 #define FRSVT_ERR_HANDLE (-105)
+#define FRSVT_ERR_SCRATCH (-106)
+
+/* Size of the fixed device scratch behind frsvt_noalloc (64 MiB per GPU). */
+#define FRSVT_NOALLOC_SCRATCH_BYTES (64u << 20)
 
 /* ------------------------------------------------------------------ handle */
 
@@ -177,6 +181,34 @@ FRSVT_API int frsvt(frsvt_handle handle, frsvt_precision prec, int64_t m, int64_
           int64_t lda, double tau, int32_t k, int32_t p, int32_t q, const void *Q_prev,
           int32_t r_prev, int64_t ldq_prev, uint64_t seed, uint64_t counter, void *X,
           int64_t ldx, void *Q_out, int64_t ldq_out, int32_t *r_out);
+
+/*
+ * frsvt_noalloc: frsvt without any allocation, for callers that cannot
+ * allocate device memory during the call (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  Arguments,
+ * results and status codes are those of frsvt, computed by the same kernels
+ * in the same order (results equal frsvt's bit for bit).
+ * Differences:
+ *   - the workspace is a fixed device array of FRSVT_NOALLOC_SCRATCH_BYTES
+ *     that each GPU holds until the process ends, not the handle's
+ *     growable workspace; the call allocates and frees nothing;
+ *   - a problem whose workspace exceeds it returns FRSVT_ERR_SCRATCH before
+ *     anything is launched (frsvt_last_error states the bytes needed; the
+ *     sketch's split-K partials dominate: about 4096 * mhat * l bytes in
+ *     FP64, e.g. 18.4 MB for mhat = 300, l = 15);
+ *   - every call on one GPU shares that GPU's array, which keeps the last
+ *     call's contents: calls that overlap on one GPU (two streams or two
+ *     host threads) race and must be serialised by the caller.  No part of
+ *     the scratch needs to start at zero (every buffer carved from it is
+ *     written before it is read).
+ * The handle must come from frsvt_create, which looks up the array's device
+ * address on its device; r_out (HOST) waits for the stream as in frsvt.
+ */
+FRSVT_API int frsvt_noalloc(frsvt_handle handle, frsvt_precision prec, int64_t m, int64_t n,
+                            const void *A, int64_t lda, double tau, int32_t k, int32_t p, int32_t q,
+                            const void *Q_prev, int32_t r_prev, int64_t ldq_prev, uint64_t seed,
+                            uint64_t counter, void *X, int64_t ldx, void *Q_out, int64_t ldq_out,
+                            int32_t *r_out);
 
 /* ------------------------------------------------------------ adjoint */
 

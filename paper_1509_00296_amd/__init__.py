@@ -24,6 +24,8 @@ LIB_PATH = os.path.join(_HERE, "libfrsvt.so")
 F64, F32, MIXED_BF16 = 0, 1, 2
 OK, NOT_CONVERGED, MAX_ITER = 0, 1, 2
 ERR_HIP, ERR_OOM, ERR_NONFINITE, ERR_UNSUPPORTED = -100, -101, -102, -104
+ERR_SCRATCH = -106
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 _i32, _i64, _u64, _dbl, _vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p
 
@@ -97,6 +99,7 @@ def library(path: str | None = None) -> ctypes.CDLL:
                         ctypes.POINTER(_i32)]
     lib.frsvt.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _i64, _dbl, _i32, _i32, _i32, _vp,
                           _i32, _i64, _u64, _u64, _vp, _i64, _vp, _i64, ctypes.POINTER(_i32)]
+    lib.frsvt_noalloc.argtypes = lib.frsvt.argtypes
     lib.wsvt.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _i64, _vp, _vp, _i64,
                          ctypes.POINTER(_i32)]
     lib.wsvt_batched.argtypes = [_vp, _i64, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(WsvtRule), _vp]
@@ -301,14 +304,17 @@ def wsvt_tuning() -> list:
 
 
 def frsvt(A, tau: float, k: int, p: int, q: int, Q_prev=None, *, seed: int = 0,
-          counter: int = 0, return_basis: bool = True):
+          counter: int = 0, return_basis: bool = True, out=None, noalloc: bool = False):
     """FRSVT (Alg. 1).  Returns (X, Q~ (mhat x r), r); with Q_prev (mhat x r_prev,
-    orthonormal columns) the basis is propagated and only p samples are drawn."""
+    orthonormal columns) the basis is propagated and only p samples are drawn.
+    out = (X, Qout) supplies the output buffers (X like A, Qout column-major
+    mhat x l); noalloc calls frsvt_noalloc, whose workspace is the library's
+    fixed device scratch."""
     import torch
     h = handle(A.device.index)
     m, n, lda, tr = _colmajor(A)
     mh = min(m, n)
-    X = _like(A, tr)
+    X = _like(A, tr) if out is None else out[0]
     _, _, ldx, _ = _colmajor(X)
     if Q_prev is not None:
         Qp = Q_prev.to(dtype=A.dtype)
@@ -321,13 +327,21 @@ def frsvt(A, tau: float, k: int, p: int, q: int, Q_prev=None, *, seed: int = 0,
     else:
         qptr, rp, ldq = None, 0, mh
         lcap = min(max(k + p, 1), mh)
-    Qout = torch.empty((max(lcap, 1), mh), dtype=A.dtype, device=A.device).t()
+    if out is None:
+        Qout = torch.empty((max(lcap, 1), mh), dtype=A.dtype, device=A.device).t()
+    else:
+        Qout = out[1]
+        if Qout.shape[0] != mh or Qout.shape[1] < lcap or Qout.stride(0) != 1 or Qout.stride(1) != mh:
+            raise ValueError("out[1] must be column-major mhat x l with leading dimension mhat")
+        if X.shape != A.shape or X.dtype != A.dtype or _colmajor(X)[3] != tr:
+            raise ValueError("out[0] must have the shape, dtype and memory order of A")
     r = _i32()
-    rc = h.lib.frsvt(h.ptr, _prec(A), m, n, A.data_ptr(), lda, float(tau), int(k), int(p), int(q),
-                     qptr, int(rp), int(ldq), int(seed) & (2**64 - 1), int(counter) & (2**64 - 1),
-                     X.data_ptr(), ldx, Qout.data_ptr() if return_basis else None, mh,
-                     ctypes.byref(r))
-    _check(h, rc, "frsvt")
+    fn = h.lib.frsvt_noalloc if noalloc else h.lib.frsvt
+    rc = fn(h.ptr, _prec(A), m, n, A.data_ptr(), lda, float(tau), int(k), int(p), int(q),
+            qptr, int(rp), int(ldq), int(seed) & (2**64 - 1), int(counter) & (2**64 - 1),
+            X.data_ptr(), ldx, Qout.data_ptr() if return_basis else None, mh,
+            ctypes.byref(r))
+    _check(h, rc, "frsvt_noalloc" if noalloc else "frsvt")
     rr = int(r.value)
     return X, Qout[:, :rr], rr
 

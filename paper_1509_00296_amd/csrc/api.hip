@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -28,6 +29,7 @@ struct frsvt_context {
     int *dstatus = nullptr;      // small device status area (ints)
     double *dscalars = nullptr;  // small device scalar area (doubles)
     void *pinned = nullptr;      // host pinned status area
+    void *scratch_dev = nullptr; // device address of this device's fixed scratch (frsvt_noalloc)
     char last_error[256] = {0};
     // batched weighted SVT: tuned group sizes per size bucket, the queue and
     // order buffers, and the captured graph of the last argument set
@@ -51,6 +53,44 @@ struct frsvt_context {
     double trace_ms[FRSVT_K_COUNT] = {0};
     int64_t trace_n[FRSVT_K_COUNT] = {0};
 };
+
+// Fixed scratch of frsvt_noalloc: a workspace that is never allocated at
+// run time.  Each GPU the library runs on holds its own copy of this array
+// until the process ends.  Host code never uses the array's name as an
+// address: frsvt_create looks up the device address once per device (with
+// that device current) and every launch takes that pointer.
+static __device__ __align__(256) unsigned char scratch[FRSVT_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices] = {nullptr};
+bool g_scratch_done[kMaxDevices] = {false};
+
+// Device address of `scratch` on the current device `device` (looked up
+// once per device; nullptr when the lookup fails).
+void *scratch_address(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_done[device]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        g_scratch_addr[device] = e == hipSuccess ? ptr : nullptr;
+        g_scratch_done[device] = true;
+    }
+    return g_scratch_addr[device];
+}
+
+// A workspace supplied by the caller of an implementation instead of the
+// handle's growable one.
+struct FixedWs {
+    void *base;
+    size_t cap;
+};
+
+} // namespace
 
 namespace {
 
@@ -660,7 +700,8 @@ template <typename T>
 int frsvt_impl(frsvt_context *h, int64_t m, int64_t n, const T *A, int64_t lda, double tau,
                int k, int p, int q, const T *Qprev, int r_prev, int64_t ldqp, uint64_t seed,
                uint64_t counter, T *X, int64_t ldx, T *Qout, int64_t ldqo, int32_t *r_out,
-               bool mixed = false, T *Qsave = nullptr, int64_t ldqs = 0, double *factors = nullptr)
+               bool mixed = false, T *Qsave = nullptr, int64_t ldqs = 0, double *factors = nullptr,
+               const FixedWs *fixed = nullptr)
 {
     const Orient o = orient(m, n, lda);
     Core<T> c{};
@@ -694,9 +735,25 @@ int frsvt_impl(frsvt_context *h, int64_t m, int64_t n, const T *A, int64_t lda, 
         dry.take<uint16_t>((size_t)m * n);
     }
     carve_core<T>(dry, o, l, c.cnew, h->num_cu, b, mixed);
-    int rc = ensure_ws(h, dry.off);
-    if (rc) return rc;
-    Carver cv(h->ws);
+    int rc;
+    void *base;
+    if (fixed) {
+        if (!fixed->base) {
+            snprintf(h->last_error, sizeof(h->last_error), "device address of the fixed scratch unavailable");
+            return FRSVT_ERR_HIP;
+        }
+        if (dry.off > fixed->cap) {
+            snprintf(h->last_error, sizeof(h->last_error),
+                     "frsvt_noalloc: this call needs %zu bytes of scratch, the fixed scratch holds %zu",
+                     dry.off, fixed->cap);
+            return FRSVT_ERR_SCRATCH;
+        }
+        base = fixed->base;
+    } else {
+        if ((rc = ensure_ws(h, dry.off))) return rc;
+        base = h->ws;
+    }
+    Carver cv(base);
     c.A16 = c.A16T = nullptr;
     if (mixed) {
         // both orientations, so that every bfloat16 product reads its
@@ -1772,6 +1829,7 @@ int frsvt_create(frsvt_handle *handle, int device, void *hip_stream)
     if (e == hipSuccess) e = hipMalloc(&h->dscalars, kScalarDoubles * sizeof(double));
     if (e == hipSuccess) e = hipHostMalloc(&h->pinned, 1 << 20, hipHostMallocDefault);
     if (e == hipSuccess) e = hipMemset(h->dstatus, 0, kStatusInts * sizeof(int));
+    if (e == hipSuccess) h->scratch_dev = scratch_address(device);
     (void)hipSetDevice(dev_prev);
     if (e != hipSuccess) {
         if (h->dstatus) (void)hipFree(h->dstatus);
@@ -1826,6 +1884,7 @@ const char *frsvt_status_string(int status)
     case FRSVT_ERR_NONFINITE: return "non-finite input";
     case FRSVT_ERR_UNSUPPORTED: return "unsupported device or configuration";
     case FRSVT_ERR_HANDLE: return "invalid handle";
+    case FRSVT_ERR_SCRATCH: return "problem too large for the fixed scratch of frsvt_noalloc";
     default: break;
     }
     if (status < 0 && status > -100) return "invalid argument";
@@ -1957,10 +2016,10 @@ int wsvt(frsvt_handle h, frsvt_precision prec, int64_t m, int64_t n, const void 
     return exact_svt_impl<float>(h, m, n, (const float *)A, lda, 0.0, w, (float *)X, ldx, rank);
 }
 
-int frsvt(frsvt_handle h, frsvt_precision prec, int64_t m, int64_t n, const void *A, int64_t lda,
-          double tau, int32_t k, int32_t p, int32_t q, const void *Q_prev, int32_t r_prev,
-          int64_t ldq_prev, uint64_t seed, uint64_t counter, void *X, int64_t ldx, void *Q_out,
-          int64_t ldq_out, int32_t *r_out)
+static int frsvt_entry(frsvt_handle h, frsvt_precision prec, int64_t m, int64_t n, const void *A,
+                       int64_t lda, double tau, int32_t k, int32_t p, int32_t q, const void *Q_prev,
+                       int32_t r_prev, int64_t ldq_prev, uint64_t seed, uint64_t counter, void *X,
+                       int64_t ldx, void *Q_out, int64_t ldq_out, int32_t *r_out, const FixedWs *fixed)
 {
     if (!h) return -1;
     if (prec != FRSVT_F64 && prec != FRSVT_F32 && prec != FRSVT_MIXED_BF16) return -2;
@@ -1984,14 +2043,36 @@ int frsvt(frsvt_handle h, frsvt_precision prec, int64_t m, int64_t n, const void
     if (prec == FRSVT_MIXED_BF16)
         return frsvt_impl<float>(h, m, n, (const float *)A, lda, tau, k, p, q, (const float *)Q_prev,
                                  r_prev, ldq_prev, seed, counter, (float *)X, ldx, (float *)Q_out,
-                                 ldq_out, r_out, true);
+                                 ldq_out, r_out, true, nullptr, 0, nullptr, fixed);
     if (prec == FRSVT_F64)
         return frsvt_impl<double>(h, m, n, (const double *)A, lda, tau, k, p, q,
                                   (const double *)Q_prev, r_prev, ldq_prev, seed, counter,
-                                  (double *)X, ldx, (double *)Q_out, ldq_out, r_out);
+                                  (double *)X, ldx, (double *)Q_out, ldq_out, r_out, false, nullptr, 0,
+                                  nullptr, fixed);
     return frsvt_impl<float>(h, m, n, (const float *)A, lda, tau, k, p, q, (const float *)Q_prev,
                              r_prev, ldq_prev, seed, counter, (float *)X, ldx, (float *)Q_out,
-                             ldq_out, r_out);
+                             ldq_out, r_out, false, nullptr, 0, nullptr, fixed);
+}
+
+int frsvt(frsvt_handle h, frsvt_precision prec, int64_t m, int64_t n, const void *A, int64_t lda,
+          double tau, int32_t k, int32_t p, int32_t q, const void *Q_prev, int32_t r_prev,
+          int64_t ldq_prev, uint64_t seed, uint64_t counter, void *X, int64_t ldx, void *Q_out,
+          int64_t ldq_out, int32_t *r_out)
+{
+    return frsvt_entry(h, prec, m, n, A, lda, tau, k, p, q, Q_prev, r_prev, ldq_prev, seed, counter, X, ldx,
+                       Q_out, ldq_out, r_out, nullptr);
+}
+
+int frsvt_noalloc(frsvt_handle h, frsvt_precision prec, int64_t m, int64_t n, const void *A, int64_t lda,
+                  double tau, int32_t k, int32_t p, int32_t q, const void *Q_prev, int32_t r_prev,
+                  int64_t ldq_prev, uint64_t seed, uint64_t counter, void *X, int64_t ldx, void *Q_out,
+                  int64_t ldq_out, int32_t *r_out)
+{
+    if (!h) return -1;
+    // the device's own copy of the fixed scratch, looked up at frsvt_create
+    const FixedWs fx{h->scratch_dev, (size_t)FRSVT_NOALLOC_SCRATCH_BYTES};
+    return frsvt_entry(h, prec, m, n, A, lda, tau, k, p, q, Q_prev, r_prev, ldq_prev, seed, counter, X, ldx,
+                       Q_out, ldq_out, r_out, &fx);
 }
 
 int rpca_ialm(frsvt_handle h, frsvt_precision prec, int64_t m, int64_t n, const void *O,
