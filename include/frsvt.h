@@ -32,8 +32,14 @@
  * - Status codes (LAPACK-like `info`): 0 success; -i the i-th argument is
  *   invalid (nothing is launched); FRSVT_NOT_CONVERGED (+1) a Jacobi sweep
  *   limit was reached (the result is still written); FRSVT_MAX_ITER (+2) an
- *   iterative host (rpca_ialm, lrr_ialm, tensor_rpca) stopped at max_iter; FRSVT_ERR_* below for runtime failures.  No C++
- *   exception crosses this interface.
+ *   iterative host (rpca_ialm, lrr_ialm, tensor_rpca) stopped at max_iter; FRSVT_ERR_* below for runtime failures:
+ *   -100 a HIP runtime error, -101 out of device memory, -102 non-finite
+ *   input, -103 the final Cholesky factor of a re-orthonormalisation still
+ *   failed after the shifted fallback and the refill of null columns
+ *   (reported where the call reads its status words: frsvt/svt with a rank
+ *   output, and every rpca_ialm iteration), -104 unsupported device or size,
+ *   -105 invalid handle, -106 problem too large for frsvt_noalloc's scratch.
+ *   No C++ exception crosses this interface.
  */
 #ifndef FRSVT_H
 #define FRSVT_H
@@ -64,6 +70,7 @@ typedef enum {
 #define FRSVT_ERR_HIP (-100)
 #define FRSVT_ERR_OOM (-101)
 #define FRSVT_ERR_NONFINITE (-102)
+#define FRSVT_ERR_CHOLESKY (-103)
 #define FRSVT_ERR_UNSUPPORTED (-104)
 #define FRSVT_ERR_HANDLE (-105)
 #define FRSVT_ERR_SCRATCH (-106)
@@ -292,6 +299,58 @@ FRSVT_API int rpca_init(frsvt_handle handle, frsvt_precision prec, int64_t m, in
                         const void *O, int64_t ldo, double lambda, double mu0, void *Y0,
                         int64_t ldy, void *A0, int64_t lda0, double *out);
 
+/*
+ * Unrolled inexact-ALM RPCA over a batch (the differentiation form): T steps
+ * of Sec. 4.1's iALM with a learnable SVT threshold tau_t and shrink
+ * threshold lam_t per step (they replace 1/mu_t and lambda/mu_t):
+ *   (Y_0, A_0) = rpca_init(O_b),  mu_t = min(mu_0 rho^t, mu_bar_factor mu_0),
+ *   mu_0 = 1.25 / ||O_b||_2,
+ *   L_{t+1} = frsvt_fwd(A_t, tau_t, k, p, q, seed + b, counter t),
+ *   (Y_{t+1}, A_{t+1}) = rpca_dual_step(O_b, L_{t+1}, Y_t, lam_t, mu_t, mu_{t+1}),
+ * output L_T of every instance.  Instance b of a batched argument X is the
+ * column-major matrix at X + b * strideX (elements) with its leading
+ * dimension.  taus, lams are DEVICE arrays of `steps` doubles (read once,
+ * waiting for the stream).  Instances run concurrently on side streams of
+ * the handle that start after the work already enqueued on its stream; the
+ * handle's stream waits for them before the call returns (the forward
+ * waits for the host once per instance, for ||O_b||_2).
+ *
+ * rpca_unrolled_saved_bytes: bytes of the state the forward keeps for the
+ * reverse sweep (per instance: mu_t, every A_t and Y_t, L_t for t < T - 1,
+ * the bases Q_t and the small factors); -1 for invalid sizes.
+ */
+FRSVT_API int64_t rpca_unrolled_saved_bytes(frsvt_precision prec, int32_t batch, int32_t steps, int64_t m,
+                                            int64_t n, int32_t k, int32_t p);
+
+/* rpca_unrolled_schedule: the plain iALM schedule of one instance O,
+ * tau_t = 1/mu_t and lam_t = lambda/mu_t for t < steps (mu_t as above), into
+ * HOST arrays; the starting values of the learnable thresholds.  Waits. */
+FRSVT_API int rpca_unrolled_schedule(frsvt_handle handle, frsvt_precision prec, int64_t m, int64_t n,
+                                     const void *O, int64_t ldo, double lambda, double rho,
+                                     double mu_bar_factor, int32_t steps, double *taus, double *lams);
+
+/* rpca_unrolled_fwd: the forward pass.  L [out] batch of m x n results
+ * (ldl, strideL); saved [out] caller-owned DEVICE buffer of at least
+ * rpca_unrolled_saved_bytes bytes, passed unchanged to rpca_unrolled_bwd.
+ * FRSVT_F64 and FRSVT_F32; l = min(k + p, mhat) <= 64. */
+FRSVT_API int rpca_unrolled_fwd(frsvt_handle handle, frsvt_precision prec, int32_t batch, int32_t steps,
+                                int64_t m, int64_t n, const void *O, int64_t ldo, int64_t strideO,
+                                const double *taus, const double *lams, double lambda, double rho,
+                                double mu_bar_factor, int32_t k, int32_t p, int32_t q, uint64_t seed,
+                                void *L, int64_t ldl, int64_t strideL, void *saved, int64_t saved_bytes);
+
+/* rpca_unrolled_bwd: the reverse sweep of the forward call with the same
+ * arguments and `saved`: given the upstream gradient L_bar of the outputs
+ * it writes tau_bar and lam_bar [out, DEVICE, `steps` doubles each], the
+ * gradients of sum_b <L_bar_b, L_T(b)> in tau_t and lam_t, summed over the
+ * batch in a fixed order (lam_bar[T-1] = 0: lam_{T-1} does not reach L_T).
+ * Reverse of each step: rpca_dual_step_vjp, then frsvt_vjp. */
+FRSVT_API int rpca_unrolled_bwd(frsvt_handle handle, frsvt_precision prec, int32_t batch, int32_t steps,
+                                int64_t m, int64_t n, const void *O, int64_t ldo, int64_t strideO,
+                                const double *taus, const double *lams, int32_t k, int32_t p, int32_t q,
+                                uint64_t seed, const void *saved, int64_t saved_bytes, const void *L_bar,
+                                int64_t ldlb, int64_t strideLb, double *tau_bar, double *lam_bar);
+
 /* --------------------------------------------------------------- WSVT */
 
 /*
@@ -382,6 +441,16 @@ typedef struct {
     const void *q_init;
     int32_t r_init;
     void *q_final;
+    /* Residual check steering the sampling (Sec. 3.2 after Prop. 4): the
+     * new samples y_j of an iteration are taken in order and each is
+     * projected off the basis it would extend, [Q~, y_1, ..., y_{j-1}]
+     * (classical Gram-Schmidt, two passes); sampling stops at the first
+     * whose estimate 20 sqrt(2/pi) ||residual|| is at most the iteration's
+     * threshold 1/mu (y_j itself is kept); otherwise every sample of the
+     * width rule is taken.  1: on, 0: off (default).  FRSVT mode on the
+     * one-workgroup path only (short side and widths small enough for it):
+     * FRSVT_ERR_UNSUPPORTED otherwise.  Costs one host wait per iteration. */
+    int32_t resid_check;
 } frsvt_rpca_opts;
 
 typedef struct {
@@ -425,6 +494,32 @@ FRSVT_API void frsvt_rpca_default_opts(frsvt_rpca_opts *opts);
 FRSVT_API int rpca_ialm(frsvt_handle handle, frsvt_precision prec, int64_t m, int64_t n, const void *O,
               int64_t ldo, double lambda, const frsvt_rpca_opts *opts, void *L, int64_t ldl,
               void *S, int64_t lds, frsvt_rpca_stats *stats);
+
+/*
+ * rpca_sliding: semi-online low-rank + sparse decomposition of a frame
+ * sequence (Type B of Table 6, Sec. 4).  The columns of F (m x frames,
+ * ldf) are split into consecutive windows of `window` frames; window w is
+ * decomposed by rpca_ialm with FRSVT and partial SVT (the keep largest
+ * singular values unshrunk), q power iterations, sketch widths by adaptive
+ * prediction bounded by l (ap_a = l - keep, ap_gamma = l / window), seed +
+ * w, and the previous window's last propagated basis as its initial basis
+ * (q_init / r_init; none for the first window).  Frames past the last whole
+ * window are left untouched in L and S.
+ *   lambda   > 0, commonly 1/sqrt(max(m, window)).  1 <= keep < l <= window, l <= m.
+ *   L, S     [out] m x frames (ldl, lds >= m).
+ *   stats    [out, HOST, optional] frames / window entries, one per window.
+ *   bases    [out, DEVICE, optional] frames / window blocks of mhat x l
+ *            (mhat = min(m, window)): window w's last propagated basis at
+ *            bases + w * mhat * l, leading dimension mhat, its width the
+ *            last rank in stats[w] (the rest of the block is not written).
+ * Returns FRSVT_OK when every window ran (a window stopped at max_iter
+ * still counts; its stats say so); max_iter <= 64.  Waits for the stream.
+ */
+FRSVT_API int rpca_sliding(frsvt_handle handle, frsvt_precision prec, int64_t m, int64_t frames,
+                           const void *F, int64_t ldf, int32_t window, double lambda, int32_t keep,
+                           int32_t l, int32_t q, uint64_t seed, double tol, int32_t max_iter, double rho,
+                           void *L, int64_t ldl, void *S, int64_t lds, frsvt_rpca_stats *stats,
+                           void *bases);
 
 /* ---------------------------------------------------------- LRR host */
 

@@ -69,6 +69,16 @@ def _bind(path: str):
                                          ctypes.c_double, _i64, _dp, _i64, _dp, _i64p, _dp, _i64,
                                          _dp, _i64, _i64p, _i64p, _dp, _dp,
                                          ctypes.POINTER(ctypes.c_int)]
+        lib.orc_rpca_ialm_rc.argtypes = [_i64, _i64, _dp, _i64, ctypes.c_double, ctypes.c_int,
+                                         _i64, ctypes.c_int, ctypes.c_uint64, ctypes.c_double,
+                                         ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_int, _i64, ctypes.c_double,
+                                         ctypes.c_double, _i64, _dp, _i64, _dp, _i64p, ctypes.c_int,
+                                         _dp, _i64, _dp, _i64, _i64p, _i64p, _dp, _dp,
+                                         ctypes.POINTER(ctypes.c_int)]
+        lib.orc_residual_check.argtypes = [_i64, _i64, _dp, _i64, _dp, _i64, _i64, _dp, _i64, _i64,
+                                           ctypes.c_double, ctypes.c_double, _dp]
+        lib.orc_residual_check.restype = _i64
         lib.orc_lrr_ialm.argtypes = [_i64, _i64, _dp, _i64, ctypes.c_double, ctypes.c_int, _i64,
                                      ctypes.c_int, ctypes.c_uint64, ctypes.c_double, ctypes.c_int,
                                      ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp, _i64,
@@ -250,13 +260,15 @@ def frsvt(A, tau: float, q: int, Omega, Qprev=None):
 def rpca_ialm(O, lam: float, mode: str = "frsvt", p: int = 5, q: int = 1, seed: int = 0,
               tol: float = 1e-7, max_iter: int = 60, mu0: float = 0.0, rho: float = 1.5,
               mu_bar_factor: float = 1e7, ap: bool = False, ap_a: int = 2, ap_rho: float = 0.05,
-              ap_gamma: float = 1.0, keep: int = 0, q_init=None):
+              ap_gamma: float = 1.0, keep: int = 0, q_init=None, resid_check: bool = False):
     """Inexact-ALM RPCA; mode 'exact' (SVT by full SVD) or 'frsvt' (FRSVT + RP),
     with the sketch widths of adaptive rank prediction (Sec. 2.3, Eq. 7) when
     ap is set.
 
     keep > 0 selects partial SVT (the keep largest singular values unshrunk);
-    q_init (mhat x r) is the first call's propagated basis (semi-online use).
+    q_init (mhat x r) is the first call's propagated basis (semi-online use);
+    resid_check stops each iteration's sampling at the first new sample whose
+    residual estimate (Prop. 4, alpha = 20) is at most the threshold 1/mu.
 
     Returns dict(L, S, ranks, widths, resid_est, resid, iters, converged, Q)
     with Q the last propagated basis."""
@@ -278,10 +290,10 @@ def rpca_ialm(O, lam: float, mode: str = "frsvt", p: int = 5, q: int = 1, seed: 
         assert Qi.shape[0] == mh
         ri = Qi.shape[1]
     it = ctypes.c_int()
-    rc = _L().orc_rpca_ialm_ap(m, n, _p(O), m, lam, 0 if mode == "exact" else 1, p, q, seed,
+    rc = _L().orc_rpca_ialm_rc(m, n, _p(O), m, lam, 0 if mode == "exact" else 1, p, q, seed,
                                tol, max_iter, mu0, rho, mu_bar_factor, int(ap), ap_a, ap_rho,
                                ap_gamma, keep, _p(Qi), ri, _p(Qf), ctypes.byref(rf),
-                               _p(L), m, _p(S), m, ranks.ctypes.data_as(_i64p),
+                               int(resid_check), _p(L), m, _p(S), m, ranks.ctypes.data_as(_i64p),
                                widths.ctypes.data_as(_i64p), _p(resid_est), _p(resid),
                                ctypes.byref(it))
     _check(rc, "rpca_ialm")
@@ -289,6 +301,21 @@ def rpca_ialm(O, lam: float, mode: str = "frsvt", p: int = 5, q: int = 1, seed: 
     return dict(L=L, S=S, ranks=ranks[:k], widths=widths[:k], resid_est=resid_est[:k],
                 resid=resid[:k], iters=k, converged=(rc == 0),
                 Q=np.asfortranarray(Qf[:, :int(rf.value)]))
+
+
+def residual_check(A, Qt, Om, tau: float, alpha: float = 20.0):
+    """Sequential residual check (Sec. 3.2): (samples kept, estimates of the
+    samples checked).  Qt (mhat x r) may have r = 0 columns; Om is nhat x c."""
+    A, Om = _f(A), _f(Om)
+    m, n = A.shape
+    mh = min(m, n)
+    r = 0 if Qt is None else Qt.shape[1]
+    Qb = np.zeros((mh, max(r, 1)), order="F") if r == 0 else _f(Qt)
+    c = Om.shape[1]
+    est = np.full(c, np.nan)
+    kept = _L().orc_residual_check(m, n, _p(A), m, _p(Qb), mh, r, _p(Om), Om.shape[0], c, tau, alpha,
+                                   _p(est))
+    return int(kept), est
 
 
 def psvt(A, tau: float, keep: int):

@@ -683,6 +683,55 @@ double orc_residual_estimate(int64_t m, int64_t n, const double *A, int64_t lda,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Residual check that steers sampling (Sec. 3.2 after Prop. 4): the new     */
+/* samples y_j = Ahat omega_j are taken in order; each is compared with the  */
+/* basis it would extend, Q_j = [Q~, y_1, ..., y_{j-1}] orthonormalised, by  */
+/*   s_j = alpha sqrt(2/pi) ||(I - Q_j Q_j^T) y_j||_2,                       */
+/* an upper bound on sigma_{k+1}(Ahat) (k = columns of Q_j) with probability */
+/* >= 1 - 1/alpha.  Once s_j <= tau no direction above the threshold is left */
+/* outside [Q_j, y_j] (with that probability): sampling stops and y_j is the  */
+/* last sample kept.  Returns the number of samples kept, j (all nomega when */
+/* no check passes).  The projection is applied twice (classical Gram-       */
+/* Schmidt, two passes).  est_out[j-1] = s_j for the samples checked.        */
+/* ------------------------------------------------------------------------ */
+int64_t orc_residual_check(int64_t m, int64_t n, const double *A, int64_t lda, const double *Qt,
+                           int64_t ldq, int64_t r, const double *Om, int64_t ldom, int64_t nomega,
+                           double tau, double alpha, double *est_out)
+{
+    const int transposed = m > n;
+    const int64_t mh = transposed ? n : m;
+    const double pi = 3.14159265358979323846;
+    double *B = dalloc(mh * (r + nomega + 1));   /* the growing orthonormal basis */
+    double *y = dalloc(mh);
+    if (r > 0) mat_copy(mh, r, Qt, ldq, B, mh);
+    int64_t k = r, kept = nomega;
+    for (int64_t j = 0; j < nomega; ++j) {
+        const double *om = &AT(Om, ldom, 0, j);
+        if (transposed) mat_mul_tn(mh, 1, m, A, lda, om, m, y, mh);  /* y = A^T omega */
+        else mat_mul(mh, 1, n, A, lda, om, n, y, mh);                 /* y = A omega   */
+        for (int pass = 0; pass < 2; ++pass)
+            for (int64_t c = 0; c < k; ++c) {
+                const double d = col_dot(mh, &AT(B, mh, 0, c), y);
+                for (int64_t i = 0; i < mh; ++i) y[i] -= d * AT(B, mh, i, c);
+            }
+        const double nrm = col_norm(mh, y);
+        const double est = alpha * sqrt(2.0 / pi) * nrm;
+        if (est_out) est_out[j] = est;
+        if (est <= tau) {
+            kept = j + 1;
+            break;
+        }
+        if (nrm > 0.0) {
+            for (int64_t i = 0; i < mh; ++i) AT(B, mh, i, k) = y[i] / nrm;
+            ++k;
+        }
+    }
+    free(B);
+    free(y);
+    return kept;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Inexact augmented Lagrange multiplier RPCA (the iALM host of Sec. 4.1,    */
 /* "Robust PCA test"; lambda = 1/sqrt(max(m,n)) there).  The paper cites the */
 /* method without formulas; this is its standard form: an SVT step on L, a   */
@@ -704,6 +753,19 @@ int orc_rpca_ialm_ap(int64_t m, int64_t n, const double *O, int64_t ldo, double 
                      int64_t r_init, double *Qfinal, int64_t *r_final, double *L, int64_t ldl,
                      double *S, int64_t lds, int64_t *ranks, int64_t *widths, double *resid_est,
                      double *resid, int *iters)
+{
+    return orc_rpca_ialm_rc(m, n, O, ldo, lambda, svt_mode, p, q, seed, tol, max_iter, mu0, rho,
+                            mu_bar_factor, ap, ap_a, ap_rho, ap_gamma, keep, Qinit, r_init, Qfinal,
+                            r_final, 0, L, ldl, S, lds, ranks, widths, resid_est, resid, iters);
+}
+
+int orc_rpca_ialm_rc(int64_t m, int64_t n, const double *O, int64_t ldo, double lambda,
+                     int svt_mode, int64_t p, int q, uint64_t seed, double tol, int max_iter,
+                     double mu0, double rho, double mu_bar_factor, int ap, int64_t ap_a,
+                     double ap_rho, double ap_gamma, int64_t keep, const double *Qinit,
+                     int64_t r_init, double *Qfinal, int64_t *r_final, int resid_check, double *L,
+                     int64_t ldl, double *S, int64_t lds, int64_t *ranks, int64_t *widths,
+                     double *resid_est, double *resid, int *iters)
 {
     if (m < 1) return -1;
     if (n < 1) return -2;
@@ -787,11 +849,16 @@ int orc_rpca_ialm_ap(int64_t m, int64_t n, const double *O, int64_t ldo, double 
             }
             if (nomega < 1 && !Qprop) nomega = 1;
             if (nomega < 0) nomega = 0;
+            double *Om = dalloc(nh * (nomega > 0 ? nomega : 1));
+            if (nomega > 0) orc_gaussian_matrix(seed, (uint64_t)it, nh, nomega, Om, nh);
+            /* Sec. 3.2: stop sampling once the residual estimate is below
+             * this iteration's threshold */
+            if (resid_check && nomega > 0)
+                nomega = orc_residual_check(m, n, A, m, Qt, mh, Qprop ? r_prev : 0, Om, nh, nomega,
+                                            1.0 / mu, 20.0, NULL);
             const int64_t lw = (Qprop ? r_prev : 0) + nomega;
             l_prev = lw < mh ? lw : mh;
             if (widths) widths[it] = l_prev;
-            double *Om = dalloc(nh * (nomega > 0 ? nomega : 1));
-            if (nomega > 0) orc_gaussian_matrix(seed, (uint64_t)it, nh, nomega, Om, nh);
             /* Prop. 4 with the first new sample (alpha = 20); -1: no sample */
             if (resid_est)
                 resid_est[it] = nomega > 0 ? orc_residual_estimate(m, n, A, m, Qt, mh, Qprop ? r_prev : 0,

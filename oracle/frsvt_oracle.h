@@ -102,6 +102,23 @@ int orc_rpca_ialm(int64_t m, int64_t n, const double *O, int64_t ldo, double lam
  * them (no new sample once r_i = b).  p is unused then.  widths[] (length
  * max_iter, optional) receives l_i, resid_est[] the estimate below; returns -15 for a < 1, rho <= 0 or gamma
  * outside (0, 1]. */
+/* Sequential residual check of Sec. 3.2 (Prop. 4 with Lemma 3): number of
+ * the nomega samples Ahat Om(:, j) kept before (and including) the first
+ * whose residual estimate against the basis it extends is <= tau. */
+int64_t orc_residual_check(int64_t m, int64_t n, const double *A, int64_t lda, const double *Qt,
+                           int64_t ldq, int64_t r, const double *Om, int64_t ldom, int64_t nomega,
+                           double tau, double alpha, double *est_out);
+
+/* orc_rpca_ialm_ap with the residual check steering the number of new
+ * samples per iteration (resid_check != 0). */
+int orc_rpca_ialm_rc(int64_t m, int64_t n, const double *O, int64_t ldo, double lambda,
+                     int svt_mode, int64_t p, int q, uint64_t seed, double tol, int max_iter,
+                     double mu0, double rho, double mu_bar_factor, int ap, int64_t ap_a,
+                     double ap_rho, double ap_gamma, int64_t keep, const double *Qinit,
+                     int64_t r_init, double *Qfinal, int64_t *r_final, int resid_check, double *L,
+                     int64_t ldl, double *S, int64_t lds, int64_t *ranks, int64_t *widths,
+                     double *resid_est, double *resid, int *iters);
+
 int orc_rpca_ialm_ap(int64_t m, int64_t n, const double *O, int64_t ldo, double lambda,
                      int svt_mode, int64_t p, int q, uint64_t seed, double tol, int max_iter,
                      double mu0, double rho, double mu_bar_factor, int ap, int64_t ap_a,

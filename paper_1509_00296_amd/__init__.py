@@ -41,7 +41,7 @@ class RpcaOpts(ctypes.Structure):
                 ("mu_bar_factor", _dbl), ("use_frsvt", _i32), ("p", _i32), ("q", _i32),
                 ("l0", _i32), ("seed", _u64), ("ap", _i32), ("ap_a", _i32), ("ap_rho", _dbl),
                 ("ap_gamma", _dbl), ("keep", _i32), ("q_init", ctypes.c_void_p), ("r_init", _i32),
-                ("q_final", ctypes.c_void_p)]
+                ("q_final", ctypes.c_void_p), ("resid_check", _i32)]
 
 
 class LrrOpts(ctypes.Structure):
@@ -100,6 +100,16 @@ def library(path: str | None = None) -> ctypes.CDLL:
     lib.frsvt.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _i64, _dbl, _i32, _i32, _i32, _vp,
                           _i32, _i64, _u64, _u64, _vp, _i64, _vp, _i64, ctypes.POINTER(_i32)]
     lib.frsvt_noalloc.argtypes = lib.frsvt.argtypes
+    lib.rpca_unrolled_saved_bytes.argtypes = [ctypes.c_int, _i32, _i32, _i64, _i64, _i32, _i32]
+    lib.rpca_unrolled_saved_bytes.restype = _i64
+    lib.rpca_unrolled_schedule.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _i64, _dbl, _dbl, _dbl, _i32,
+                                           ctypes.POINTER(_dbl), ctypes.POINTER(_dbl)]
+    lib.rpca_unrolled_fwd.argtypes = [_vp, ctypes.c_int, _i32, _i32, _i64, _i64, _vp, _i64, _i64, _vp, _vp,
+                                      _dbl, _dbl, _dbl, _i32, _i32, _i32, _u64, _vp, _i64, _i64, _vp, _i64]
+    lib.rpca_unrolled_bwd.argtypes = [_vp, ctypes.c_int, _i32, _i32, _i64, _i64, _vp, _i64, _i64, _vp, _vp,
+                                      _i32, _i32, _i32, _u64, _vp, _i64, _vp, _i64, _i64, _vp, _vp]
+    lib.rpca_sliding.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _i64, _i32, _dbl, _i32, _i32, _i32,
+                                 _u64, _dbl, _i32, _dbl, _vp, _i64, _vp, _i64, _vp, _vp]
     lib.wsvt.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _i64, _vp, _vp, _i64,
                          ctypes.POINTER(_i32)]
     lib.wsvt_batched.argtypes = [_vp, _i64, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(WsvtRule), _vp]
@@ -366,14 +376,16 @@ def rpca_ialm(O, lam: float, *, use_frsvt: bool = True, tol: float = 1e-7, max_i
               mu0: float = 0.0, rho: float = 1.5, mu_bar_factor: float = 1e7, p: int = 5,
               q: int = 1, l0: int = 0, seed: int = 0, ap: bool = False, ap_a: int = 2,
               ap_rho: float = 0.05, ap_gamma: float = 1.0, keep: int = 0, q_init=None,
-              return_basis: bool = False) -> RpcaResult:
+              return_basis: bool = False, resid_check: bool = False) -> RpcaResult:
     """Inexact-ALM RPCA (the host of Sec. 4.1) with FRSVT + range propagation
     or exact SVT.  O is a GPU tensor (m x n).  With ap the sketch widths follow
     adaptive rank prediction (Sec. 2.3, Eq. 7: a, rho, gamma) instead of p
     new samples per iteration.  keep > 0 selects partial SVT (the keep largest
     singular values unshrunk: the truncated nuclear norm).  q_init (GPU, mhat x
     r, orthonormal columns) is the first call's propagated basis and
-    return_basis returns the last one in .Q (semi-online use)."""
+    return_basis returns the last one in .Q (semi-online use).  resid_check
+    stops each iteration's sampling at the first new sample whose residual
+    estimate (Prop. 4) is at most the threshold."""
     import torch
     h = handle(O.device.index)
     m, n, ldo, tr = _colmajor(O)
@@ -387,6 +399,7 @@ def rpca_ialm(O, lam: float, *, use_frsvt: bool = True, tol: float = 1e-7, max_i
     op.use_frsvt, op.p, op.q, op.l0, op.seed = int(use_frsvt), p, q, l0, seed
     op.ap, op.ap_a, op.ap_rho, op.ap_gamma = int(ap), ap_a, ap_rho, ap_gamma
     op.keep = keep
+    op.resid_check = int(resid_check)
     mh = min(m, n)
     qi = None
     if q_init is not None:
@@ -414,34 +427,39 @@ def rpca_ialm(O, lam: float, *, use_frsvt: bool = True, tol: float = 1e-7, max_i
 def rpca_sliding(frames, n: int, lam=None, *, keep: int = 1, l: int = 3, q: int = 2,
                  seed: int = 0, tol: float = 1e-7, max_iter: int = 60, rho: float = 1.5):
     """Semi-online low-rank + sparse decomposition of a frame sequence (Sec. 4,
-    Type B of Table 6): consecutive windows of n frames (the columns of
-    frames, m x F on the GPU), each by the partial-SVT iALM (the keep largest
-    singular values unshrunk) with FRSVT, the sketch width bounded by l
-    (adaptive prediction, a = l - keep, b = l) and q power iterations; each
-    window starts from the previous window's propagated basis.  lam defaults
-    to 1/sqrt(max(m, n)).  Frames past the last whole window are left out.
-    Returns L, S (m x F, zero past the last window) and the per-window
-    results."""
-    import numpy as np
+    Type B of Table 6) through rpca_sliding: consecutive windows of n frames
+    (the columns of frames, m x F on the GPU), each by the partial-SVT iALM
+    (the keep largest singular values unshrunk) with FRSVT, the sketch width
+    bounded by l and q power iterations; each window starts from the previous
+    window's propagated basis.  lam defaults to 1/sqrt(max(m, n)).  Frames
+    past the last whole window are left out (zero in L and S).  Returns L, S
+    and the per-window results."""
     import torch
-    m, F = frames.shape
-    if n < 2 or n > F:
-        raise ValueError("window length n must lie in [2, number of frames]")
-    if not 1 <= keep < l <= n:
-        raise ValueError("need 1 <= keep < l <= n")
-    lam = 1.0 / float(np.sqrt(max(m, n))) if lam is None else lam
-    L = torch.zeros_like(frames)
-    S = torch.zeros_like(frames)
-    runs, basis = [], None
-    for w in range(F // n):
-        Ow = frames[:, w * n:(w + 1) * n]
-        res = rpca_ialm(Ow, lam, use_frsvt=True, tol=tol, max_iter=max_iter, rho=rho, q=q,
-                        seed=seed + w, ap=True, ap_a=l - keep, ap_gamma=l / n, keep=keep,
-                        q_init=basis, return_basis=True)
-        L[:, w * n:(w + 1) * n] = res.L
-        S[:, w * n:(w + 1) * n] = res.S
-        basis = res.Q if (res.Q is not None and res.Q.shape[1] > 0) else None
-        runs.append(res)
+    h = handle(frames.device.index)
+    F = frames if (frames.stride(0) == 1) else frames.t().contiguous().t()
+    m, nf, ldf, tr = _colmajor(F)
+    if tr:
+        raise ValueError("frames must be a column-major (or contiguous-column) m x F tensor")
+    lam = 1.0 / float(max(m, n)) ** 0.5 if lam is None else lam
+    L = torch.zeros((nf, m), dtype=F.dtype, device=F.device).t()
+    S = torch.zeros((nf, m), dtype=F.dtype, device=F.device).t()
+    nw = nf // n if n >= 1 else 0
+    mh = min(m, n)
+    st = (RpcaStats * max(nw, 1))()
+    bases = torch.zeros((max(nw, 1), l, mh), dtype=F.dtype, device=F.device)
+    rc = h.lib.rpca_sliding(h.ptr, _prec(F), m, nf, F.data_ptr(), ldf, int(n), float(lam), int(keep), int(l),
+                            int(q), int(seed) & (2**64 - 1), float(tol), int(max_iter), float(rho), L.data_ptr(),
+                            m, S.data_ptr(), m, st, bases.data_ptr())
+    _check(h, rc, "rpca_sliding")
+    runs = []
+    for w in range(nw):
+        k = min(st[w].iters, 64)
+        r = st[w].ranks[k - 1] if k > 0 else 0
+        Qw = bases[w].t()[:, :r]                       # column-major mhat x r
+        runs.append(RpcaResult(L[:, w * n:(w + 1) * n], S[:, w * n:(w + 1) * n], st[w].iters,
+                               bool(st[w].converged), st[w].residual, st[w].norm2, st[w].seconds,
+                               list(st[w].ranks[:k]), list(st[w].residuals[:k]), list(st[w].widths[:k]),
+                               list(st[w].resid_est[:k]), Qw))
     return L, S, runs
 
 
@@ -602,103 +620,60 @@ def frsvt_ad(A, tau, k: int, p: int, q: int, *, seed: int = 0, counter: int = 0)
 
 
 class _UnrolledFn(_torch().autograd.Function):
-    """T unrolled inexact-ALM steps on a batch of instances, learnable
+    """T unrolled inexact-ALM steps on a batch of instances with learnable
     per-step SVT thresholds taus[t] and shrink thresholds lams[t] shared by
-    the batch:  L_{t+1} = FRSVT_{tau_t}(A_t);  (Y_{t+1}, A_{t+1}) = dual step
-    with lam_t, mu_t, mu_{t+1}.  Output L_T.  The backward runs the reverse
-    sweep with frsvt_vjp and dual_step_vjp; the threshold gradients are summed
-    on the device and read once."""
-
-    # Instances are independent: instance b runs on side stream b mod
-    # _STREAMS (its own library handle and workspace), and the caller's stream
-    # waits for all of them, so the GPU overlaps the instances' small kernels.
-    _STREAMS = 4
-
-    _side: dict = {}
+    the batch (rpca_unrolled_fwd / rpca_unrolled_bwd: the steps, the mu
+    schedule, the side streams and the batch sums all run in the library).
+    Output L_T, shape (B, m, n)."""
 
     @staticmethod
-    def _side_streams(dev, count):
-        """The caller's stream and `count` side streams of the device (made
-        once and reused, so each keeps its one library handle); the side
-        streams wait for the caller's."""
+    def forward(ctx, taus, lams, O, lam, rho, mu_bar_factor, k, p, q, seed):
         torch = _torch()
-        cur = torch.cuda.current_stream(dev)
-        key = dev.index if dev.index is not None else torch.cuda.current_device()
-        pool = _UnrolledFn._side.setdefault(key, [])
-        while len(pool) < count:
-            pool.append(torch.cuda.Stream(device=dev))
-        side = pool[:count]
-        for s in side:
-            s.wait_stream(cur)
-        return cur, side
-
-    @staticmethod
-    def forward(ctx, taus, lams, O, Y0, A0, mus, k, p, q, seeds):
-        torch = _torch()
-        T = taus.numel()
-        B = O.shape[0]
-        tv, lv = [float(x) for x in taus.tolist()], [float(x) for x in lams.tolist()]
-        As = [[None] * B for _ in range(T)]
-        Ys = [[None] * B for _ in range(T)]
-        Ls = [[None] * B for _ in range(T)]
-        Qs = [[None] * B for _ in range(T)]
-        Fs = [[None] * B for _ in range(T)]
-        cur, side = _UnrolledFn._side_streams(O.device, min(B, _UnrolledFn._STREAMS))
-        for b in range(B):
-            with torch.cuda.stream(side[b % len(side)]):
-                A_b, Y_b = A0[b], Y0[b]
-                for t in range(T):
-                    X, Q, fac = frsvt_fwd(A_b, tv[t], k, p, q, seed=seeds[b], counter=t)
-                    As[t][b], Ys[t][b], Ls[t][b], Qs[t][b], Fs[t][b] = A_b, Y_b, X, Q, fac
-                    if t + 1 < T:
-                        _, Y_b, A_b = dual_step(O[b], X, Y_b, lv[t], mus[b][t], mus[b][t + 1])
-        for s in side:
-            cur.wait_stream(s)
-        # tensors made on a side stream and used on the caller's stream
-        for b in range(B):
-            Ls[-1][b].record_stream(cur)
-        ctx.state = (As, Ys, Ls, Qs, Fs, O, mus, k, p, q, seeds, tv, lv, taus.device)
-        return torch.stack(Ls[-1])
+        h = handle(O.device.index)
+        Oc = O.contiguous()
+        B, m, n = Oc.shape
+        # instance b is row-major m x n: the column-major n x m matrix at b*m*n
+        td = taus.detach().to(device=O.device, dtype=torch.float64).contiguous()
+        ld = lams.detach().to(device=O.device, dtype=torch.float64).contiguous()
+        T = td.numel()
+        nbytes = h.lib.rpca_unrolled_saved_bytes(_prec(Oc), B, T, n, m, k, p)
+        if nbytes < 0:
+            raise ValueError("invalid unrolled RPCA sizes")
+        saved = torch.empty(nbytes, dtype=torch.uint8, device=O.device)
+        L = torch.empty_like(Oc)
+        rc = h.lib.rpca_unrolled_fwd(h.ptr, _prec(Oc), B, T, n, m, Oc.data_ptr(), n, m * n, td.data_ptr(),
+                                     ld.data_ptr(), float(lam), float(rho), float(mu_bar_factor), int(k), int(p),
+                                     int(q), int(seed) & (2**64 - 1), L.data_ptr(), n, m * n, saved.data_ptr(),
+                                     nbytes)
+        _check(h, rc, "rpca_unrolled_fwd")
+        ctx.state = (Oc, td, ld, saved, nbytes, k, p, q, seed, taus.device)
+        return L
 
     @staticmethod
     def backward(ctx, L_bar):
         torch = _torch()
-        As, Ys, Ls, Qs, Fs, O, mus, k, p, q, seeds, tv, lv, pdev = ctx.state
-        T, B = len(tv), len(seeds)
-        dev = L_bar.device
-        gt = torch.zeros((T, B), dtype=torch.float64, device=dev)
-        gl = torch.zeros((T, B), dtype=torch.float64, device=dev)
-        cur, side = _UnrolledFn._side_streams(dev, min(B, _UnrolledFn._STREAMS))
-        for b in range(B):
-            with torch.cuda.stream(side[b % len(side)]):
-                Ab_next, Yb_next = None, None
-                for t in range(T - 1, -1, -1):
-                    if t == T - 1:
-                        Lb = L_bar[b]
-                    else:
-                        Lb, Yb_t, _ = dual_step_vjp(O[b], Ls[t][b], Ys[t][b], lv[t], mus[b][t],
-                                                    mus[b][t + 1], None, Yb_next, Ab_next,
-                                                    lam_bar=gl[t, b])
-                        Yb_next = Yb_t
-                    Ab_t, tb = frsvt_vjp(As[t][b], tv[t], k, p, q, Qs[t][b], Fs[t][b], Lb,
-                                         seed=seeds[b], counter=t)
-                    gt[t, b].copy_(tb)
-                    Ab_next = Ab_t
-                    if t == T - 1:
-                        Yb_next = None
-        for s in side:
-            cur.wait_stream(s)
+        Oc, td, ld, saved, nbytes, k, p, q, seed, pdev = ctx.state
+        h = handle(Oc.device.index)
+        B, m, n = Oc.shape
+        T = td.numel()
+        Lb = L_bar.to(dtype=Oc.dtype).contiguous()
+        gt = torch.empty(T, dtype=torch.float64, device=Oc.device)
+        gl = torch.empty(T, dtype=torch.float64, device=Oc.device)
+        rc = h.lib.rpca_unrolled_bwd(h.ptr, _prec(Oc), B, T, n, m, Oc.data_ptr(), n, m * n, td.data_ptr(),
+                                     ld.data_ptr(), int(k), int(p), int(q), int(seed) & (2**64 - 1),
+                                     saved.data_ptr(), nbytes, Lb.data_ptr(), n, m * n, gt.data_ptr(),
+                                     gl.data_ptr())
+        _check(h, rc, "rpca_unrolled_bwd")
         ctx.state = None
-        gtau = gt.sum(dim=1).to(pdev)
-        glam = gl.sum(dim=1).to(pdev)
-        return gtau, glam, None, None, None, None, None, None, None, None
+        return gt.to(pdev), gl.to(pdev), None, None, None, None, None, None, None, None
 
 
 class UnrolledRPCA(_torch().nn.Module):
     """Differentiable unrolled inexact-ALM RPCA (FRSVT thresholding) with
     learnable per-step thresholds tau_t (SVT) and lam_t (shrink).  mu_t
     follows the iALM schedule of each instance: mu_0 = 1.25 / ||O||_2,
-    mu_{t+1} = rho mu_t (capped at mu_bar_factor mu_0)."""
+    mu_{t+1} = rho mu_t (capped at mu_bar_factor mu_0); instance b draws its
+    sketches with seed + b."""
 
     def __init__(self, taus, lams, *, k: int = 5, p: int = 5, q: int = 1, rho: float = 1.5,
                  mu_bar_factor: float = 1e7, seed: int = 0, lam_ialm: float | None = None):
@@ -711,28 +686,25 @@ class UnrolledRPCA(_torch().nn.Module):
         self.lam_ialm = lam_ialm
 
     @staticmethod
-    def default_schedule(O, steps: int = 10, rho: float = 1.5, lam: float | None = None):
-        """tau_t = 1/mu_t and lam_t = lam/mu_t of the plain iALM on instance O."""
-        m, n = O.shape
+    def default_schedule(O, steps: int = 10, rho: float = 1.5, lam: float | None = None,
+                         mu_bar_factor: float = 1e7):
+        """tau_t = 1/mu_t and lam_t = lam/mu_t of the plain iALM on instance O
+        (rpca_unrolled_schedule)."""
+        h = handle(O.device.index)
+        m, n, ldo, _ = _colmajor(O)
         lam = lam if lam is not None else 1.0 / max(m, n) ** 0.5
-        _, _, _, mu0, _ = rpca_init(O, lam)
-        mus = [mu0 * rho ** t for t in range(steps)]
-        return [1.0 / mu for mu in mus], [lam / mu for mu in mus]
+        tv, lv = (_dbl * steps)(), (_dbl * steps)()
+        rc = h.lib.rpca_unrolled_schedule(h.ptr, _prec(O), m, n, O.data_ptr(), ldo, float(lam), float(rho),
+                                          float(mu_bar_factor), int(steps), tv, lv)
+        _check(h, rc, "rpca_unrolled_schedule")
+        return list(tv), list(lv)
 
     def forward(self, O):
         """O: (B, m, n) GPU tensor.  Returns L_T, shape (B, m, n)."""
         B, m, n = O.shape
         lam = self.lam_ialm if self.lam_ialm is not None else 1.0 / max(m, n) ** 0.5
-        T = self.tau.numel()
-        Y0, A0, mus = [], [], []
-        for b in range(B):
-            y, a, _, mu0, _ = rpca_init(O[b], lam)
-            Y0.append(y)
-            A0.append(a)
-            mub = mu0 * self.mu_bar_factor
-            mus.append([min(mu0 * self.rho ** t, mub) for t in range(T + 1)])
-        seeds = [self.seed + b for b in range(B)]
-        return _UnrolledFn.apply(self.tau, self.lam, O, Y0, A0, mus, self.k, self.p, self.q, seeds)
+        return _UnrolledFn.apply(self.tau, self.lam, O, lam, self.rho, self.mu_bar_factor, self.k, self.p,
+                                 self.q, self.seed)
 
 
 @dataclass

@@ -31,6 +31,15 @@ struct frsvt_context {
     void *pinned = nullptr;      // host pinned status area
     void *scratch_dev = nullptr; // device address of this device's fixed scratch (frsvt_noalloc)
     char last_error[256] = {0};
+    // unrolled RPCA and other batch drivers: side contexts, each with its own
+    // stream, workspace and status words, that run instances concurrently;
+    // the fork/join events; a buffer for per-call state the drivers keep
+    frsvt_context *side[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool owns_stream = false;
+    hipEvent_t ev_fork = nullptr;
+    hipEvent_t ev_join = nullptr;
+    void *aux = nullptr;
+    size_t aux_bytes = 0;
     // batched weighted SVT: tuned group sizes per size bucket, the queue and
     // order buffers, and the captured graph of the last argument set
     int wb_gs[3] = {0, 0, 0};
@@ -99,6 +108,7 @@ constexpr size_t kStatusInts = 1024;
 constexpr int kGateSlot = 12;  // status word: null pivots of the large path's first null check
 constexpr int kResidSlot = 20; // status words 20-21: a double, Prop. 4's squared residual
 constexpr size_t kScalarDoubles = 8192;
+constexpr size_t kCheckSlot = 4096;  // device scalars 4096..4159: the residual check's squared norms
 
 int fail(frsvt_context *h, hipError_t e, const char *what)
 {
@@ -779,6 +789,11 @@ int frsvt_impl(frsvt_context *h, int64_t m, int64_t n, const T *A, int64_t lda, 
         CK(hipMemcpyAsync(h->pinned, h->dstatus, 8 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
         CK(hipStreamSynchronize(h->stream));
         *r_out = ((int *)h->pinned)[0];
+        if (((int *)h->pinned)[6] != 0) {
+            snprintf(h->last_error, sizeof(h->last_error),
+                     "the last orthonormalisation's Cholesky factor failed after the shifted fallback and refill");
+            return FRSVT_ERR_CHOLESKY;
+        }
         if (((int *)h->pinned)[2] == 0) return FRSVT_NOT_CONVERGED;
     }
     return FRSVT_OK;
@@ -1238,9 +1253,39 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
                 c.rp = 0;
                 c.cnew = r_prev < 0 ? l0 : (op.ap ? ap_width(0, l_prev) : std::min(op.p, mh));
             }
+            // Sec. 3.2: the planned samples in order, sampling stopped at
+            // the first whose residual estimate is at most 1/mu
+            bool checked = false;
+            if (op.resid_check && c.cnew > 0) {
+                if (!core_small<T>(c, c.rp + c.cnew) || !resid_seq_ok(mh, c.rp, c.cnew) || c.cnew > 64) {
+                    snprintf(h->last_error, sizeof(h->last_error),
+                             "the residual check runs on the one-workgroup path only (short side %d, width %d)",
+                             mh, c.rp + c.cnew);
+                    CK(hipStreamSynchronize(s));
+                    return FRSVT_ERR_UNSUPPORTED;
+                }
+                if (spec_cnew < c.cnew && (rc = sketch_stage<T>(h, c, b))) return rc;
+                double *est2 = h->dscalars + kCheckSlot;
+                CKT(FRSVT_K_ORTH, launch_resid_seq<T>(mh, c.Qt, c.ldqt, c.rp, b.Y, mh, c.cnew, est2, s));
+                CK(hipMemcpyAsync(h->pinned, est2, (size_t)c.cnew * sizeof(double), hipMemcpyDeviceToHost, s));
+                CK(hipStreamSynchronize(s));
+                const double tau_it = 1.0 / mu;
+                int kept = c.cnew;
+                for (int j = 0; j < c.cnew; ++j) {
+                    const double est = 20.0 * std::sqrt(2.0 / 3.14159265358979323846) *
+                                       std::sqrt(((const double *)h->pinned)[j]);
+                    if (est <= tau_it) {
+                        kept = j + 1;
+                        break;
+                    }
+                }
+                c.cnew = kept;
+                checked = true;
+            }
             l_prev = std::min(mh, c.rp + c.cnew);
             if (stats && it < 64) stats->widths[it] = l_prev;
-            c.sketch_ready = spec_cnew > 0 && spec_cnew == c.cnew && core_small<T>(c, c.rp + c.cnew);
+            // (the first c.cnew columns of a wider draw are the narrower draw)
+            c.sketch_ready = checked || (spec_cnew > 0 && spec_cnew == c.cnew && core_small<T>(c, c.rp + c.cnew));
             c.Qout = Qt;
             c.ldqo = mh;
             c.status = h->dstatus;
@@ -1340,6 +1385,12 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
         }
         CK(hipEventSynchronize(h->ev_iter));
         const int r = hst[0];
+        if (op.use_frsvt && hst[6] != 0) {
+            snprintf(h->last_error, sizeof(h->last_error),
+                     "iteration %d: the orthonormalisation's Cholesky factor failed after the shifted fallback", it);
+            CK(hipStreamSynchronize(s));
+            return FRSVT_ERR_CHOLESKY;
+        }
         double zz;
         const int zw[2] = {hst[8], hst[9]};
         memcpy(&zz, zw, sizeof(double));
@@ -1801,6 +1852,330 @@ int tensor_impl(frsvt_context *h, int64_t I1, int64_t I2, int64_t I3, const doub
     return converged ? FRSVT_OK : FRSVT_MAX_ITER;
 }
 
+
+// ---------------------------------------------------------------------------
+// Batch drivers: side contexts, fork/join, and the auxiliary buffer.
+// ---------------------------------------------------------------------------
+constexpr int kSides = 4;
+
+int ensure_aux(frsvt_context *h, size_t bytes)
+{
+    if (bytes <= h->aux_bytes) return FRSVT_OK;
+    if (h->aux) {
+        CK(hipStreamSynchronize(h->stream));
+        (void)hipFree(h->aux);
+        h->aux = nullptr;
+        h->aux_bytes = 0;
+    }
+    hipError_t e = hipMalloc(&h->aux, bytes);
+    if (e != hipSuccess) {
+        h->aux = nullptr;
+        return fail(h, e, "hipMalloc(aux)");
+    }
+    h->aux_bytes = bytes;
+    return FRSVT_OK;
+}
+
+// The side contexts of h (created on first use, each on a stream of its own
+// at the default priority).
+int ensure_sides(frsvt_context *h)
+{
+    if (h->side[0]) return FRSVT_OK;
+    int dev_prev = 0;
+    (void)hipGetDevice(&dev_prev);
+    CK(hipSetDevice(h->device));
+    int rc = FRSVT_OK;
+    if (!h->ev_fork && hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess)
+        rc = FRSVT_ERR_HIP;
+    for (int i = 0; i < kSides && rc == FRSVT_OK; ++i) {
+        hipStream_t st = nullptr;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            rc = FRSVT_ERR_HIP;
+            break;
+        }
+        frsvt_context *k = nullptr;
+        rc = frsvt_create(&k, h->device, st);
+        if (rc != FRSVT_OK) {
+            (void)hipStreamDestroy(st);
+            break;
+        }
+        k->owns_stream = true;
+        if (hipEventCreateWithFlags(&k->ev_join, hipEventDisableTiming) != hipSuccess) rc = FRSVT_ERR_HIP;
+        h->side[i] = k;
+    }
+    (void)hipSetDevice(dev_prev);
+    if (rc != FRSVT_OK) snprintf(h->last_error, sizeof(h->last_error), "creating the side streams failed");
+    return rc;
+}
+
+// The side streams wait for the work enqueued so far on h's stream.
+int fork_sides(frsvt_context *h)
+{
+    CK(hipEventRecord(h->ev_fork, h->stream));
+    for (int i = 0; i < kSides; ++i) CK(hipStreamWaitEvent(h->side[i]->stream, h->ev_fork, 0));
+    return FRSVT_OK;
+}
+
+// h's stream waits for everything enqueued on the side streams.
+int join_sides(frsvt_context *h)
+{
+    for (int i = 0; i < kSides; ++i) {
+        CK(hipEventRecord(h->side[i]->ev_join, h->side[i]->stream));
+        CK(hipStreamWaitEvent(h->stream, h->side[i]->ev_join, 0));
+    }
+    return FRSVT_OK;
+}
+
+// A side context's error text is copied to the caller's handle.
+int side_rc(frsvt_context *h, frsvt_context *k, int rc)
+{
+    if (rc != FRSVT_OK && rc != FRSVT_NOT_CONVERGED) memcpy(h->last_error, k->last_error, sizeof(h->last_error));
+    return rc;
+}
+
+// Reads n doubles of device memory (ordered on h's stream; waits).
+int read_doubles(frsvt_context *h, const double *src, size_t n, std::vector<double> &dst)
+{
+    dst.resize(n);
+    if (n == 0) return FRSVT_OK;
+    if (n * sizeof(double) > (1u << 20)) return FRSVT_ERR_UNSUPPORTED;
+    CK(hipMemcpyAsync(h->pinned, src, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    CK(hipStreamSynchronize(h->stream));
+    memcpy(dst.data(), h->pinned, n * sizeof(double));
+    return FRSVT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Unrolled inexact-ALM RPCA (differentiation form): T steps of
+//   L_{t+1} = FRSVT_{tau_t}(A_t)  (fresh sketch, counter t, seed + b),
+//   (Y_{t+1}, A_{t+1}) = dual step with lam_t, mu_t, mu_{t+1},
+// from the iALM starting point of each instance; mu_t = min(mu_0 rho^t,
+// mu_bar_factor mu_0), mu_0 = 1.25 / ||O_b||_2.  The forward keeps, per
+// instance, mu, every A_t, Y_t, L_t (t < T - 1), the bases Q_t and the small
+// factors in the caller's `saved` buffer; the reverse sweep reads them.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct UnrolledLayout {
+    double *mus;
+    std::vector<T *> A, Y, Lx, Q;
+    std::vector<double *> fac;
+};
+
+template <typename T>
+size_t carve_unrolled(Carver &cv, int steps, int64_t m, int64_t n, int l, UnrolledLayout<T> &u)
+{
+    const int64_t mh = std::min(m, n);
+    u.A.assign(steps, nullptr);
+    u.Y.assign(steps, nullptr);
+    u.Lx.assign(std::max(steps - 1, 0), nullptr);
+    u.Q.assign(steps, nullptr);
+    u.fac.assign(steps, nullptr);
+    u.mus = cv.take<double>((size_t)steps + 1);
+    for (int t = 0; t < steps; ++t) {
+        u.A[t] = cv.take<T>((size_t)m * n);
+        u.Y[t] = cv.take<T>((size_t)m * n);
+        if (t + 1 < steps) u.Lx[t] = cv.take<T>((size_t)m * n);
+        u.Q[t] = cv.take<T>((size_t)mh * l);
+        u.fac[t] = cv.take<double>((size_t)l + (size_t)l * l);
+    }
+    cv.off = (cv.off + 255) & ~(size_t)255;
+    return cv.off;
+}
+
+template <typename T>
+size_t unrolled_instance_bytes(int steps, int64_t m, int64_t n, int l)
+{
+    Carver dry(nullptr);
+    UnrolledLayout<T> u;
+    return carve_unrolled<T>(dry, steps, m, n, l, u);
+}
+
+// mu_t of the iALM schedule (capped at mu_bar_factor mu_0), t = 0..steps.
+std::vector<double> mu_schedule(double mu0, double rho, double mu_bar_factor, int steps)
+{
+    std::vector<double> mus((size_t)steps + 1);
+    double mu = mu0;
+    const double mub = mu0 * mu_bar_factor;
+    for (int t = 0; t <= steps; ++t) {
+        mus[t] = std::min(mu, mub);
+        mu *= rho;
+    }
+    return mus;
+}
+
+template <typename T>
+int unrolled_fwd_impl(frsvt_context *h, int B, int steps, int64_t m, int64_t n, const T *O, int64_t ldo,
+                      int64_t sO, const double *taus_d, const double *lams_d, double lambda, double rho,
+                      double mu_bar_factor, int k, int p, int q, uint64_t seed, T *L, int64_t ldl,
+                      int64_t sL, void *saved)
+{
+    const int64_t mh = std::min(m, n);
+    const int l = (int)std::min<int64_t>(mh, (int64_t)k + p);
+    std::vector<double> tv, lv;
+    int rc;
+    if ((rc = read_doubles(h, taus_d, steps, tv))) return rc;
+    if ((rc = read_doubles(h, lams_d, steps, lv))) return rc;
+    for (int t = 0; t < steps; ++t)
+        if (!(tv[t] >= 0.0) || !std::isfinite(tv[t]) || !(lv[t] >= 0.0) || !std::isfinite(lv[t])) return -10;
+    if ((rc = ensure_sides(h))) return rc;
+    const size_t per = unrolled_instance_bytes<T>(steps, m, n, l);
+    std::vector<UnrolledLayout<T>> lay(B);
+    std::vector<std::vector<double>> mus(B);
+    if ((rc = fork_sides(h))) return rc;
+    // starting points (each waits for its side stream: ||O_b||_2 sets mu_0)
+    for (int b = 0; b < B; ++b) {
+        frsvt_context *k2 = h->side[b % kSides];
+        Carver cv((char *)saved + (size_t)b * per);
+        carve_unrolled<T>(cv, steps, m, n, l, lay[b]);
+        double out[3];
+        rc = rpca_init_impl<T>(k2, m, n, O + (size_t)b * sO, ldo, lambda, 0.0, lay[b].Y[0], m, lay[b].A[0], m, out);
+        if (rc) return side_rc(h, k2, rc);
+        mus[b] = mu_schedule(out[1], rho, mu_bar_factor, steps);
+        CK(hipMemcpyAsync(lay[b].mus, mus[b].data(), mus[b].size() * sizeof(double), hipMemcpyHostToDevice,
+                          k2->stream));
+        CK(hipStreamSynchronize(k2->stream));
+    }
+    for (int b = 0; b < B; ++b) {
+        frsvt_context *k2 = h->side[b % kSides];
+        const UnrolledLayout<T> &u = lay[b];
+        const T *Ob = O + (size_t)b * sO;
+        for (int t = 0; t < steps; ++t) {
+            const bool last = t + 1 == steps;
+            T *X = last ? L + (size_t)b * sL : u.Lx[t];
+            const int64_t ldx = last ? ldl : m;
+            rc = frsvt_impl<T>(k2, m, n, u.A[t], m, tv[t], k, p, q, nullptr, 0, mh, seed + (uint64_t)b,
+                               (uint64_t)t, X, ldx, nullptr, mh, nullptr, false, u.Q[t], mh, u.fac[t]);
+            if (rc) return side_rc(h, k2, rc);
+            if (!last) {
+                rc = dual_step_impl<T>(k2, m, n, Ob, ldo, X, m, u.Y[t], m, lv[t], mus[b][t], mus[b][t + 1],
+                                       nullptr, m, u.Y[t + 1], m, u.A[t + 1], m);
+                if (rc) return side_rc(h, k2, rc);
+            }
+        }
+    }
+    return join_sides(h);
+}
+
+template <typename T>
+int unrolled_bwd_impl(frsvt_context *h, int B, int steps, int64_t m, int64_t n, const T *O, int64_t ldo,
+                      int64_t sO, const double *taus_d, const double *lams_d, int k, int p, int q,
+                      uint64_t seed, const void *saved, const T *Lbar, int64_t ldlb, int64_t sLb,
+                      double *tau_bar, double *lam_bar)
+{
+    const int64_t mh = std::min(m, n);
+    const int l = (int)std::min<int64_t>(mh, (int64_t)k + p);
+    std::vector<double> tv, lv;
+    int rc;
+    if ((rc = read_doubles(h, taus_d, steps, tv))) return rc;
+    if ((rc = read_doubles(h, lams_d, steps, lv))) return rc;
+    if ((rc = ensure_sides(h))) return rc;
+    const size_t per = unrolled_instance_bytes<T>(steps, m, n, l);
+    std::vector<UnrolledLayout<T>> lay(B);
+    std::vector<std::vector<double>> mus(B);
+    for (int b = 0; b < B; ++b) {
+        Carver cv((char *)saved + (size_t)b * per);
+        carve_unrolled<T>(cv, steps, m, n, l, lay[b]);
+        if ((rc = read_doubles(h, lay[b].mus, (size_t)steps + 1, mus[b]))) return rc;
+    }
+    // per-(instance, step) threshold gradients, summed over the batch at the end
+    const size_t gbytes = ((2 * (size_t)B * steps * sizeof(double)) + 255) & ~(size_t)255;
+    if ((rc = ensure_aux(h, gbytes))) return rc;
+    double *gt = (double *)h->aux;
+    double *gl = gt + (size_t)B * steps;
+    CK(hipMemsetAsync(gt, 0, 2 * (size_t)B * steps * sizeof(double), h->stream));
+    // reverse-sweep buffers of each side context: A_bar, L_bar, Y_bar (two)
+    const size_t mn = (size_t)m * n;
+    for (int i = 0; i < kSides; ++i)
+        if ((rc = ensure_aux(h->side[i], 4 * mn * sizeof(T) + 256))) return side_rc(h, h->side[i], rc);
+    if ((rc = fork_sides(h))) return rc;
+    for (int b = 0; b < B; ++b) {
+        frsvt_context *k2 = h->side[b % kSides];
+        const UnrolledLayout<T> &u = lay[b];
+        const T *Ob = O + (size_t)b * sO;
+        T *Ab = (T *)k2->aux, *Lb = Ab + mn, *Yb[2] = {Lb + mn, Lb + 2 * mn};
+        int cur = 0;  // Yb[cur]: gradient of Y_{t+1}
+        for (int t = steps - 1; t >= 0; --t) {
+            const T *Lin;
+            int64_t ldin;
+            if (t == steps - 1) {
+                Lin = Lbar + (size_t)b * sLb;
+                ldin = ldlb;
+            } else {
+                // Y_{T-1} feeds no later step: its gradient is zero
+                const T *Ynb = t == steps - 2 ? nullptr : Yb[cur];
+                rc = dual_step_vjp_impl<T>(k2, m, n, Ob, ldo, u.Lx[t], m, u.Y[t], m, lv[t], mus[b][t],
+                                           mus[b][t + 1], nullptr, m, Ynb, m, Ab, m, Lb, m, Yb[cur ^ 1], m,
+                                           gl + (size_t)b * steps + t);
+                if (rc) return side_rc(h, k2, rc);
+                cur ^= 1;
+                Lin = Lb;
+                ldin = m;
+            }
+            rc = frsvt_vjp_impl<T>(k2, m, n, u.A[t], m, tv[t], l, q, seed + (uint64_t)b, (uint64_t)t, u.Q[t],
+                                   mh, u.fac[t], Lin, ldin, Ab, m, gt + (size_t)b * steps + t);
+            if (rc) return side_rc(h, k2, rc);
+        }
+    }
+    if ((rc = join_sides(h))) return rc;
+    // sums over the batch in a fixed order
+    CKT(FRSVT_K_REDUCE, launch_reduce<double>(gt, steps, B, tau_bar, h->stream));
+    CKT(FRSVT_K_REDUCE, launch_reduce<double>(gl, steps, B, lam_bar, h->stream));
+    return FRSVT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Semi-online decomposition (Type B of Table 6, Sec. 4): consecutive windows
+// of `window` frames, each by the partial-SVT iALM with FRSVT (the keep
+// largest singular values unshrunk), sketch widths by adaptive prediction
+// bounded by l (a = l - keep, b = ceil((l / window) mhat)), q power
+// iterations; window w draws with seed + w and starts from window w - 1's
+// last propagated basis.
+// ---------------------------------------------------------------------------
+template <typename T>
+int sliding_impl(frsvt_context *h, int64_t m, int64_t frames, const T *F, int64_t ldf, int window,
+                 double lambda, int keep, int l, int q, uint64_t seed, double tol, int max_iter, double rho,
+                 T *L, int64_t ldl, T *S, int64_t lds, frsvt_rpca_stats *stats, T *bases)
+{
+    const int64_t nw = frames / window;
+    const int64_t mh = std::min<int64_t>(m, window);
+    int rc;
+    // two propagated-basis buffers (handed over from window to window)
+    if ((rc = ensure_aux(h, 2 * (size_t)mh * mh * sizeof(T) + 512))) return rc;
+    T *Qb[2] = {(T *)h->aux, (T *)((char *)h->aux + (((size_t)mh * mh * sizeof(T) + 255) & ~(size_t)255))};
+    int r = 0, cur = 0;
+    for (int64_t w = 0; w < nw; ++w) {
+        frsvt_rpca_opts op;
+        frsvt_rpca_default_opts(&op);
+        op.tol = tol;
+        op.max_iter = max_iter;
+        op.rho = rho;
+        op.use_frsvt = 1;
+        op.q = q;
+        op.seed = seed + (uint64_t)w;
+        op.ap = 1;
+        op.ap_a = l - keep;
+        op.ap_gamma = (double)l / (double)window;
+        op.keep = keep;
+        op.q_init = r > 0 ? Qb[cur] : nullptr;
+        op.r_init = r;
+        op.q_final = Qb[cur ^ 1];
+        frsvt_rpca_stats st;
+        memset(&st, 0, sizeof(st));
+        const int64_t c0 = w * window;
+        rc = rpca_impl<T>(h, m, window, F + c0 * ldf, ldf, lambda, op, L + c0 * ldl, ldl, S + c0 * lds, lds, &st);
+        if (rc != FRSVT_OK && rc != FRSVT_MAX_ITER) return rc;
+        if (stats) stats[w] = st;
+        // the last iteration's rank is the width of the basis handed over
+        r = st.iters > 0 ? st.ranks[std::min(st.iters, 64) - 1] : 0;
+        if (bases && r > 0)
+            CK(hipMemcpyAsync(bases + (size_t)w * mh * l, Qb[cur ^ 1], (size_t)mh * r * sizeof(T),
+                              hipMemcpyDeviceToDevice, h->stream));
+        cur ^= 1;
+    }
+    CK(hipStreamSynchronize(h->stream));
+    return FRSVT_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1846,6 +2221,14 @@ int frsvt_destroy(frsvt_handle h)
 {
     if (!h) return -1;
     (void)hipStreamSynchronize(h->stream);
+    for (auto &k : h->side)
+        if (k) {
+            (void)frsvt_destroy(k);
+            k = nullptr;
+        }
+    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+    if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+    if (h->aux) (void)hipFree(h->aux);
     for (auto &r : h->recs) {
         (void)hipEventDestroy(r.second.first);
         (void)hipEventDestroy(r.second.second);
@@ -1862,6 +2245,7 @@ int frsvt_destroy(frsvt_handle h)
     if (h->dstatus) (void)hipFree(h->dstatus);
     if (h->dscalars) (void)hipFree(h->dscalars);
     if (h->pinned) (void)hipHostFree(h->pinned);
+    if (h->owns_stream && h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
     return FRSVT_OK;
 }
@@ -1882,6 +2266,7 @@ const char *frsvt_status_string(int status)
     case FRSVT_ERR_HIP: return "HIP runtime error";
     case FRSVT_ERR_OOM: return "out of device memory";
     case FRSVT_ERR_NONFINITE: return "non-finite input";
+    case FRSVT_ERR_CHOLESKY: return "Cholesky factorisation failed after the shifted fallback";
     case FRSVT_ERR_UNSUPPORTED: return "unsupported device or configuration";
     case FRSVT_ERR_HANDLE: return "invalid handle";
     case FRSVT_ERR_SCRATCH: return "problem too large for the fixed scratch of frsvt_noalloc";
@@ -1978,6 +2363,7 @@ void frsvt_rpca_default_opts(frsvt_rpca_opts *op)
     op->q_init = nullptr;
     op->r_init = 0;
     op->q_final = nullptr;
+    op->resid_check = 0;
 }
 
 int svt(frsvt_handle h, frsvt_precision prec, int64_t m, int64_t n, const void *A, int64_t lda,
@@ -2093,6 +2479,7 @@ int rpca_ialm(frsvt_handle h, frsvt_precision prec, int64_t m, int64_t n, const 
         !(op.mu_bar_factor >= 1.0))
         return -8;
     if (op.ap != 0 && op.ap != 1) return -8;
+    if (op.resid_check != 0 && op.resid_check != 1) return -8;
     if (op.keep < 0 || op.r_init < 0 || op.r_init > std::min(m, n) || (op.r_init > 0 && bad_ptr(op.q_init)))
         return -8;
     if (op.ap && (op.ap_a < 1 || !(op.ap_rho > 0.0) || !(op.ap_rho <= 1.0) || !(op.ap_gamma > 0.0) ||
@@ -2291,6 +2678,148 @@ int rpca_init(frsvt_handle h, frsvt_precision prec, int64_t m, int64_t n, const 
                                       (double *)A0, lda0, out);
     return rpca_init_impl<float>(h, m, n, (const float *)O, ldo, lambda, mu0, (float *)Y0, ldy,
                                  (float *)A0, lda0, out);
+}
+
+
+int64_t rpca_unrolled_saved_bytes(frsvt_precision prec, int32_t batch, int32_t steps, int64_t m, int64_t n,
+                                  int32_t k, int32_t p)
+{
+    if (prec != FRSVT_F64 && prec != FRSVT_F32) return -1;
+    if (batch < 1 || steps < 1 || m < 1 || n < 1 || k < 0 || p < 0 || k + p < 1) return -1;
+    const int l = (int)std::min<int64_t>(std::min(m, n), (int64_t)k + p);
+    const size_t per = prec == FRSVT_F64 ? unrolled_instance_bytes<double>(steps, m, n, l)
+                                         : unrolled_instance_bytes<float>(steps, m, n, l);
+    return (int64_t)(per * (size_t)batch);
+}
+
+int rpca_unrolled_schedule(frsvt_handle h, frsvt_precision prec, int64_t m, int64_t n, const void *O,
+                           int64_t ldo, double lambda, double rho, double mu_bar_factor, int32_t steps,
+                           double *taus, double *lams)
+{
+    if (!h) return -1;
+    if (prec != FRSVT_F64 && prec != FRSVT_F32) return -2;
+    if (m < 1) return -3;
+    if (n < 1) return -4;
+    if (bad_ptr(O)) return -5;
+    if (ldo < m) return -6;
+    if (!(lambda > 0.0) || !std::isfinite(lambda)) return -7;
+    if (!(rho >= 1.0) || !std::isfinite(rho)) return -8;
+    if (!(mu_bar_factor >= 1.0)) return -9;
+    if (steps < 1) return -10;
+    if (bad_ptr(taus)) return -11;
+    if (bad_ptr(lams)) return -12;
+    if (std::min(m, n) > 1024) return FRSVT_ERR_UNSUPPORTED;
+    double normF = 0.0, mx = 0.0, norm2 = 0.0;
+    const Orient o = orient(m, n, ldo);
+    int rc = prec == FRSVT_F64 ? input_norms<double>(h, m, n, (const double *)O, ldo, &normF, &mx)
+                               : input_norms<float>(h, m, n, (const float *)O, ldo, &normF, &mx);
+    if (rc) return rc;
+    rc = prec == FRSVT_F64 ? spectral_norm<double>(h, (const double *)O, ldo, o, &norm2)
+                           : spectral_norm<float>(h, (const float *)O, ldo, o, &norm2);
+    if (rc) return rc;
+    const double mu0 = norm2 > 0.0 ? 1.25 / norm2 : 1.0;
+    const std::vector<double> mus = mu_schedule(mu0, rho, mu_bar_factor, steps);
+    for (int t = 0; t < steps; ++t) {
+        taus[t] = 1.0 / mus[t];
+        lams[t] = lambda / mus[t];
+    }
+    return FRSVT_OK;
+}
+
+static int unrolled_check(frsvt_handle h, frsvt_precision prec, int32_t batch, int32_t steps, int64_t m,
+                          int64_t n, const void *O, int64_t ldo, int64_t strideO, const double *taus,
+                          const double *lams, int32_t k, int32_t p, int32_t q, int kpos)
+{
+    if (!h) return -1;
+    if (prec != FRSVT_F64 && prec != FRSVT_F32) return -2;
+    if (batch < 1) return -3;
+    if (steps < 1) return -4;
+    if (m < 1) return -5;
+    if (n < 1) return -6;
+    if (bad_ptr(O)) return -7;
+    if (ldo < m) return -8;
+    if (batch > 1 && strideO < ldo * n) return -9;
+    if (bad_ptr(taus)) return -10;
+    if (bad_ptr(lams)) return -11;
+    if (k < 0 || k + p < 1) return -kpos;
+    if (p < 0) return -(kpos + 1);
+    if (q < 0 || q > 64) return -(kpos + 2);
+    if (std::min<int64_t>(std::min(m, n), (int64_t)k + p) > 64) return FRSVT_ERR_UNSUPPORTED;
+    if (std::min(m, n) > 1024) return FRSVT_ERR_UNSUPPORTED;
+    return FRSVT_OK;
+}
+
+int rpca_unrolled_fwd(frsvt_handle h, frsvt_precision prec, int32_t batch, int32_t steps, int64_t m, int64_t n,
+                      const void *O, int64_t ldo, int64_t strideO, const double *taus, const double *lams,
+                      double lambda, double rho, double mu_bar_factor, int32_t k, int32_t p, int32_t q,
+                      uint64_t seed, void *L, int64_t ldl, int64_t strideL, void *saved, int64_t saved_bytes)
+{
+    int rc = unrolled_check(h, prec, batch, steps, m, n, O, ldo, strideO, taus, lams, k, p, q, 15);
+    if (rc) return rc;
+    if (!(lambda > 0.0) || !std::isfinite(lambda)) return -12;
+    if (!(rho >= 1.0) || !std::isfinite(rho)) return -13;
+    if (!(mu_bar_factor >= 1.0)) return -14;
+    if (bad_ptr(L)) return -19;
+    if (ldl < m) return -20;
+    if (batch > 1 && strideL < ldl * n) return -21;
+    if (bad_ptr(saved)) return -22;
+    if (saved_bytes < rpca_unrolled_saved_bytes(prec, batch, steps, m, n, k, p)) return -23;
+    if (prec == FRSVT_F64)
+        return unrolled_fwd_impl<double>(h, batch, steps, m, n, (const double *)O, ldo, strideO, taus, lams, lambda,
+                                         rho, mu_bar_factor, k, p, q, seed, (double *)L, ldl, strideL, saved);
+    return unrolled_fwd_impl<float>(h, batch, steps, m, n, (const float *)O, ldo, strideO, taus, lams, lambda, rho,
+                                    mu_bar_factor, k, p, q, seed, (float *)L, ldl, strideL, saved);
+}
+
+int rpca_unrolled_bwd(frsvt_handle h, frsvt_precision prec, int32_t batch, int32_t steps, int64_t m, int64_t n,
+                      const void *O, int64_t ldo, int64_t strideO, const double *taus, const double *lams,
+                      int32_t k, int32_t p, int32_t q, uint64_t seed, const void *saved, int64_t saved_bytes,
+                      const void *L_bar, int64_t ldlb, int64_t strideLb, double *tau_bar, double *lam_bar)
+{
+    int rc = unrolled_check(h, prec, batch, steps, m, n, O, ldo, strideO, taus, lams, k, p, q, 12);
+    if (rc) return rc;
+    if (bad_ptr(saved)) return -16;
+    if (saved_bytes < rpca_unrolled_saved_bytes(prec, batch, steps, m, n, k, p)) return -17;
+    if (bad_ptr(L_bar)) return -18;
+    if (ldlb < m) return -19;
+    if (batch > 1 && strideLb < ldlb * n) return -20;
+    if (bad_ptr(tau_bar)) return -21;
+    if (bad_ptr(lam_bar)) return -22;
+    if (prec == FRSVT_F64)
+        return unrolled_bwd_impl<double>(h, batch, steps, m, n, (const double *)O, ldo, strideO, taus, lams, k, p,
+                                         q, seed, saved, (const double *)L_bar, ldlb, strideLb, tau_bar, lam_bar);
+    return unrolled_bwd_impl<float>(h, batch, steps, m, n, (const float *)O, ldo, strideO, taus, lams, k, p, q,
+                                    seed, saved, (const float *)L_bar, ldlb, strideLb, tau_bar, lam_bar);
+}
+
+int rpca_sliding(frsvt_handle h, frsvt_precision prec, int64_t m, int64_t frames, const void *F, int64_t ldf,
+                 int32_t window, double lambda, int32_t keep, int32_t l, int32_t q, uint64_t seed, double tol,
+                 int32_t max_iter, double rho, void *L, int64_t ldl, void *S, int64_t lds,
+                 frsvt_rpca_stats *stats, void *bases)
+{
+    if (!h) return -1;
+    if (prec != FRSVT_F64 && prec != FRSVT_F32) return -2;
+    if (m < 1) return -3;
+    if (frames < 1) return -4;
+    if (bad_ptr(F)) return -5;
+    if (ldf < m) return -6;
+    if (window < 2 || window > frames) return -7;
+    if (!(lambda > 0.0) || !std::isfinite(lambda)) return -8;
+    if (keep < 1) return -9;
+    if (l <= keep || l > window || l > m) return -10;
+    if (q < 0 || q > 64) return -11;
+    if (!(tol > 0.0)) return -13;
+    if (max_iter < 1 || max_iter > 64) return -14;
+    if (!(rho >= 1.0) || !std::isfinite(rho)) return -15;
+    if (bad_ptr(L)) return -16;
+    if (ldl < m) return -17;
+    if (bad_ptr(S)) return -18;
+    if (lds < m) return -19;
+    if (prec == FRSVT_F64)
+        return sliding_impl<double>(h, m, frames, (const double *)F, ldf, window, lambda, keep, l, q, seed, tol,
+                                    max_iter, rho, (double *)L, ldl, (double *)S, lds, stats, (double *)bases);
+    return sliding_impl<float>(h, m, frames, (const float *)F, ldf, window, lambda, keep, l, q, seed, tol, max_iter,
+                               rho, (float *)L, ldl, (float *)S, lds, stats, (float *)bases);
 }
 
 }  // extern "C"

@@ -248,8 +248,10 @@ __global__ void __launch_bounds__(kCholThreads) k_chol(int l, const double *G, d
     const int nn = chol_blk4<kCholThreads>(M, l, tolabs, 1.0, rowbuf, sh_d, null_cols);
     for (int idx = tid; idx < l * l; idx += kCholThreads) R[idx] = M[idx];
     if (tid == 0 && flags) {
-        flags[1] = nn;
-        if (null_tol <= 0.0 && nn > 0) flags[2] |= 1;
+        // null checks report the columns they flag; the final pass (no shift,
+        // no null tolerance) records whether its factor still failed
+        if (null_tol > 0.0) flags[1] = nn;
+        if (null_tol <= 0.0 && shift_factor == 0.0) flags[2] = nn > 0 ? 1 : 0;
     }
     if (tid == 0 && nn_out) *nn_out = nn;
 }

@@ -79,6 +79,14 @@ hipError_t launch_small_orth(int mh, const T *Qt, int64_t ldqt, int rp, const T 
 // first rp columns); -1 when c = 0.  (mh + rp) doubles of LDS, at most 64 KB.
 template <typename T>
 hipError_t launch_resid_est(int mh, const T *Q, int64_t ldq, int rp, int c, double *out, hipStream_t s);
+// Sequential residual check: out[j] = squared norm of column j of Y after
+// classical Gram-Schmidt (two passes) against [Qt (rp columns), the
+// normalised residuals of columns 0..j-1].  mh (c + 1) + rp + c + 1 doubles
+// of LDS, at most 64 KiB.
+template <typename T>
+hipError_t launch_resid_seq(int mh, const T *Qt, int64_t ldqt, int rp, const T *Y, int64_t ldy, int c,
+                            double *out, hipStream_t s);
+bool resid_seq_ok(int mh, int rp, int c);
 
 // ------------------------------------------------------------- small SVD
 // From the l x l Gram G = B B^T (double): semidefinite Cholesky G = R^T R,

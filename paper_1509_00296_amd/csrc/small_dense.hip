@@ -325,6 +325,86 @@ template hipError_t launch_resid_est<double>(int, const double *, int64_t, int, 
 template hipError_t launch_resid_est<float>(int, const float *, int64_t, int, int, double *, hipStream_t);
 
 // ===========================================================================
+// Sequential residual check (Sec. 3.2 after Prop. 4): the new samples
+// y_1..y_c (columns of Y) taken in order, each projected off the basis it
+// would extend, [Qt, q_1, ..., q_{j-1}] (Qt: rp orthonormal columns; q_i the
+// normalised residuals of the earlier samples), by classical Gram-Schmidt
+// applied twice.  out[j] = ||residual of y_{j+1}||^2; a zero residual adds
+// no basis column.  One workgroup; the new basis columns stay in LDS.
+// ===========================================================================
+template <typename T>
+__global__ void __launch_bounds__(256) k_resid_seq(int mh, const T *Qt, int64_t ldqt, int rp, const T *Y,
+                                                   int64_t ldy, int c, double *out)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double *y = reinterpret_cast<double *>(smem_raw);
+    double *B = y + mh;                       // mh x c new basis columns
+    double *d = B + (size_t)mh * c;           // rp + c coefficients
+    __shared__ double red[4];
+    __shared__ int nb_sh;
+    const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+    if (tid == 0) nb_sh = 0;
+    for (int j = 0; j < c; ++j) {
+        __syncthreads();
+        const int nb = nb_sh;
+        for (int i = tid; i < mh; i += 256) y[i] = (double)Y[i + (int64_t)j * ldy];
+        __syncthreads();
+        for (int pass = 0; pass < 2; ++pass) {
+            // all coefficients of this pass from the same y (classical Gram-Schmidt)
+            for (int t = wave; t < rp + nb; t += 4) {
+                double s = 0.0;
+                if (t < rp)
+                    for (int i = lane; i < mh; i += kWave) s += (double)Qt[i + (int64_t)t * ldqt] * y[i];
+                else
+                    for (int i = lane; i < mh; i += kWave) s += B[(size_t)(t - rp) * mh + i] * y[i];
+                s = wave_sum(s);
+                if (lane == 0) d[t] = s;
+            }
+            __syncthreads();
+            for (int i = tid; i < mh; i += 256) {
+                double v = y[i];
+                for (int t = 0; t < rp; ++t) v -= (double)Qt[i + (int64_t)t * ldqt] * d[t];
+                for (int t = 0; t < nb; ++t) v -= B[(size_t)t * mh + i] * d[rp + t];
+                y[i] = v;
+            }
+            __syncthreads();
+        }
+        double s = 0.0;
+        for (int i = tid; i < mh; i += 256) s += y[i] * y[i];
+        s = wave_sum(s);
+        if (lane == 0) red[wave] = s;
+        __syncthreads();
+        const double nrm2 = ((red[0] + red[1]) + red[2]) + red[3];
+        if (tid == 0) out[j] = nrm2;
+        if (nrm2 > 0.0) {
+            const double inv = 1.0 / sqrt(nrm2);
+            for (int i = tid; i < mh; i += 256) B[(size_t)nb * mh + i] = y[i] * inv;
+            if (tid == 0) nb_sh = nb + 1;
+        }
+    }
+}
+
+bool resid_seq_ok(int mh, int rp, int c)
+{
+    return mh >= 1 && rp >= 0 && c >= 1 &&
+           ((size_t)mh * (c + 1) + (size_t)(rp + c + 1)) * sizeof(double) <= 64 * 1024;
+}
+
+template <typename T>
+hipError_t launch_resid_seq(int mh, const T *Qt, int64_t ldqt, int rp, const T *Y, int64_t ldy, int c,
+                            double *out, hipStream_t s)
+{
+    const size_t lds = ((size_t)mh * (c + 1) + (size_t)(rp + c + 1)) * sizeof(double);
+    if (!resid_seq_ok(mh, rp, c) || ldy < mh || (rp > 0 && ldqt < mh)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_resid_seq<T>), dim3(1), dim3(256), lds, s, mh, Qt, ldqt, rp, Y, ldy, c, out);
+    return hipGetLastError();
+}
+template hipError_t launch_resid_seq<double>(int, const double *, int64_t, int, const double *, int64_t, int,
+                                             double *, hipStream_t);
+template hipError_t launch_resid_seq<float>(int, const float *, int64_t, int, const float *, int64_t, int,
+                                            double *, hipStream_t);
+
+// ===========================================================================
 // Small SVD of B from G = B B^T (Alg. 1's QR of A^T Q, polar and eigen steps reformulated):
 //   G = R^T R (semidefinite Cholesky), one-sided Jacobi on M = R^T: M V = W S.
 //   B = R^T H^T has left singular vectors U_B = W S^{-1} (the normalised

@@ -325,3 +325,25 @@ def test_frsvt_near_degenerate_pair_full_basis(fr, orc, q):
     sig = fac.cpu().numpy()[:n]
     assert np.abs(sig - s).max() <= 1e-13 * s[0]
     assert np.linalg.norm(X.cpu().numpy() - Xo) <= 1e-10 * np.linalg.norm(Xo)
+
+
+@pytest.mark.parametrize("m,n,frac,ap", [(2000, 200, 0.0005, False), (60, 3000, 0.0, False),
+                                         (3000, 60, 0.0, True), (3000, 60, 0.10, False)])
+def test_rpca_residual_check_matches_oracle(fr, orc, m, n, frac, ap):
+    """The residual check steering the sampling (Sec. 3.2 after Prop. 4):
+    the same (pruned) width sequence as the oracle, ranks, L and S within
+    1e-10.  2000 x 200 with 0.05 % outliers prunes the first sketch from 20
+    to 6 samples; exactly low-rank inputs prune every iteration to r + 1
+    (also under adaptive prediction); with 10 % outliers nothing is pruned."""
+    from paper_1509_00296_amd import synth
+    _say(f"case rpca residual check {m}x{n} frac={frac} ap={ap}")
+    O, Lgt, _ = synth.rpca(seed=3, m=m, n=n, rank=3, frac=frac)
+    lam = 1.0 / np.sqrt(max(m, n))
+    res = fr.rpca_ialm(_gpu(O), lam, use_frsvt=True, seed=17, ap=ap, resid_check=True)
+    out = orc.rpca_ialm(O, lam, mode="frsvt", p=5, q=1, seed=17, ap=ap, resid_check=True)
+    assert res.iters == out["iters"]
+    assert res.widths == list(out["widths"][:64])
+    assert res.ranks == list(out["ranks"][:64])
+    assert _rel(res.L.cpu().numpy(), out["L"]) <= 1e-10
+    assert _rel(res.S.cpu().numpy(), out["S"]) <= 1e-10
+    assert res.converged

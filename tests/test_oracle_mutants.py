@@ -10,9 +10,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "frsvt_oracle.c")
 PIN_FILES = ["tests/test_oracle_rng.py", "tests/test_oracle_linalg.py",
              "tests/test_oracle_svt.py", "tests/test_oracle_frsvt.py",
-             "tests/test_oracle_rpca_grad.py", "tests/test_oracle_ap.py", "tests/test_oracle_lrr.py"]
+             "tests/test_oracle_rpca_grad.py", "tests/test_oracle_ap.py", "tests/test_oracle_lrr.py",
+             "tests/test_oracle_resid_check.py"]
 
-# (name, original text, planted mistake)
+# (name, original text, planted mistake[, the pin file that should reject it
+# first: run ahead of the others so that the -x run stops early])
 MUTANTS = [
     ("philox_multiplier", "0xD2511F53u * (uint64_t)c0", "0xD2511F55u * (uint64_t)c0"),
     ("philox_key_bump", "k1 += 0xBB67AE85u;", "k1 += 0xBB67AE84u;"),
@@ -42,6 +44,12 @@ MUTANTS = [
     ("lrr_rhs_without_multiplier", "R[i] += J[i] - Y2[i] / mu;", "R[i] += J[i];"),
     ("residual_one_pass", "    for (int pass = 0; pass < 2; ++pass)\n        for (int64_t c = 0; c < r; ++c) {",
      "    for (int pass = 0; pass < 2; ++pass)\n        for (int64_t c = 0; c < r - 1; ++c) {"),
+    ("check_keeps_one_less", "            kept = j + 1;\n            break;", "            kept = j;\n            break;",
+     "tests/test_oracle_resid_check.py"),
+    ("check_basis_not_extended", "AT(B, mh, i, k) = y[i] / nrm;\n            ++k;",
+     "AT(B, mh, i, k) = y[i] / nrm;", "tests/test_oracle_resid_check.py"),
+    ("check_threshold_squared", "if (est <= tau) {", "if (est <= tau * tau) {",
+     "tests/test_oracle_resid_check.py"),
     ("ialm_dual_sign", "AT(Y, m, i, j) += mu * z;", "AT(Y, m, i, j) -= mu * z;"),
     ("ialm_shrink_lambda", "lambda / mu);", "lambda * mu);"),
     ("vjp_antisymmetric_term", "(f[i] + f[j]) / (sg[i] + sg[j])", "(f[i] - f[j]) / (sg[i] + sg[j])"),
@@ -51,8 +59,9 @@ MUTANTS = [
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("name,orig,bad", MUTANTS, ids=[m[0] for m in MUTANTS])
-def test_pins_reject_planted_mistake(tmp_path, name, orig, bad):
+@pytest.mark.parametrize("name,orig,bad,first", [m if len(m) == 4 else (*m, None) for m in MUTANTS],
+                         ids=[m[0] for m in MUTANTS])
+def test_pins_reject_planted_mistake(tmp_path, name, orig, bad, first):
     src = open(SRC).read()
     assert src.count(orig) == 1, f"mutation anchor for {name} not unique"
     mutated = tmp_path / "frsvt_oracle.c"
@@ -63,7 +72,8 @@ def test_pins_reject_planted_mistake(tmp_path, name, orig, bad):
                            str(mutated), "-lm"])
     env = dict(os.environ, FRSVT_ORACLE_LIB=str(lib))
     proc = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                           "--timeout", "120", *PIN_FILES], cwd=ROOT, env=env,
+                           "--timeout", "120", *([first] if first else []),
+                           *[f for f in PIN_FILES if f != first]], cwd=ROOT, env=env,
                           capture_output=True, text=True, timeout=900)
     assert proc.returncode != 0, f"mutant {name} survived the pin tests:\n{proc.stdout[-2000:]}"
 
