@@ -59,8 +59,8 @@ EXACT_COMPARATORS = True    # the further workloads' exact-SVT loops (off with -
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--prec", choices=["f64", "f32"], default="f64")
     ap.add_argument("--exact-steps", type=int, default=1,
                     help="complete RPCA solves with this library's exact SVT (0 also skips the "
@@ -70,7 +70,7 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=6,
                     help="iterations of the oracle timed for the CPU baseline (0 = skip)")
     ap.add_argument("--only-main", action="store_true", help="skip the further workloads")
-    ap.add_argument("--workloads", default="single,precision,batched,unrolled,ablation,typeb,lrr,tensor")
+    ap.add_argument("--workloads", default="rpca_f32,single,precision,batched,unrolled,ablation,typeb,lrr,tensor")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="one untimed device copy of this size first (counter calibration)")
     return ap.parse_args()
@@ -138,6 +138,44 @@ def traffic_from_profile(kernel_file: str, name: str):
 # ---------------------------------------------------------------------------
 # Exact SVT iALM with the vendor SVD (baseline only)
 # ---------------------------------------------------------------------------
+def machine_rates(torch):
+    """Measured rates beside the datasheet peaks: a device-to-device copy of
+    1 GiB (read + written bytes per second, median of 10) and square GEMMs
+    on the vendor library (torch.matmul: FP64 8192^2, BF16 16384^2, median of
+    5), each timed with events on torch's current stream."""
+    import numpy as np
+    out = {}
+    nb = 1 << 30
+    src = torch.empty(nb // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    ts = []
+    for _ in range(12):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b) * 1e-3)
+    out["hbm_copy_GBs"] = round(2 * nb / float(np.median(ts[2:])) / 1e9, 1)
+    del src, dst
+    for name, dt, n in (("fp64_gemm_TFs", torch.float64, 8192), ("bf16_gemm_TFs", torch.bfloat16, 16384)):
+        x = torch.randn(n, n, device="cuda").to(dt)
+        y = torch.randn(n, n, device="cuda").to(dt)
+        torch.matmul(x, y)
+        ts = []
+        for _ in range(5):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            torch.matmul(x, y)
+            b.record()
+            b.synchronize()
+            ts.append(a.elapsed_time(b) * 1e-3)
+        out[name] = round(2.0 * n ** 3 / float(np.median(ts)) / 1e12, 1)
+        del x, y
+    torch.cuda.synchronize()
+    return out
+
+
 def vendor_ialm_iters(torch, O, lam, iters):
     """The same iALM iterations with SVT by torch.linalg.svd of the 76800 x 200
     iterate (thin SVD); returns seconds per iteration."""
@@ -188,8 +226,41 @@ def wl_single(torch, fr, synth, tracer):
     torch.cuda.synchronize()
     dte = (time.perf_counter() - t0) / K
     err = float(torch.linalg.norm(X - Xe) / torch.linalg.norm(Xe))
+    # the same call captured once in a HIP graph (frsvt_noalloc: no
+    # allocation, the rank left on the device) and replayed
+    graph = None
+    try:
+        s = torch.cuda.Stream()
+        Xg = torch.empty((300, 500), dtype=torch.float64, device="cuda").t()
+        Qg = torch.empty((15, 300), dtype=torch.float64, device="cuda").t()
+        with torch.cuda.stream(s):
+            fr.handle(0)
+            fr.frsvt(A, 1.0, 10, 5, 2, seed=1, counter=0, noalloc=True, out=(Xg, Qg), want_rank=False)
+        s.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            fr.frsvt(A, 1.0, 10, 5, 2, seed=1, counter=0, noalloc=True, out=(Xg, Qg), want_rank=False)
+        for _ in range(3):
+            g.replay()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(25):
+            a = time.perf_counter()
+            for _ in range(20):
+                g.replay()
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - a) / 20)
+        dg = float(np.median(ts))
+        X0, _, _ = fr.frsvt(A, 1.0, 10, 5, 2, seed=1, counter=0)
+        graph = {"calls_per_s": round(1.0 / dg, 1), "us_per_call_median": round(1e6 * dg, 2),
+                 "us_per_call_iqr": [round(1e6 * float(np.percentile(ts, 25)), 2),
+                                     round(1e6 * float(np.percentile(ts, 75)), 2)],
+                 "equals_eager": bool(torch.equal(Xg, X0))}
+    except Exception as e:  # reported, never hidden
+        graph = {"error": f"{type(e).__name__}: {e}"}
     return {"workload": "frsvt_500x300_f64", "metric": "FRSVT calls/s", "value": round(1.0 / dt, 1),
             "unit": "calls/s", "ms_per_call": round(1e3 * dt, 4), "rank": r,
+            "graph_replay": graph,
             "exact_svt_calls_per_s": round(1.0 / dte, 1), "rel_err_vs_exact_svt": err,
             "config": {"m": 500, "n": 300, "rank": 10, "tau": 1.0, "k": 10, "p": 5, "q": 2},
             "kernels": _r(kern)}
@@ -306,10 +377,12 @@ def wl_ablation(torch, fr, synth, tracer):
     runs = []
     cases = [dict(p=p, q=q, ap=False) for q in (0, 1, 2) for p in (2, 5, 10)]
     cases.append(dict(p=5, q=1, ap=True))
+    cases.append(dict(p=5, q=1, ap=False, rc=True))
     for cs in cases:
         def solve():
             return fr.rpca_ialm(O, lam, use_frsvt=True, tol=1e-7, max_iter=60, p=cs["p"], q=cs["q"],
-                                seed=2024, ap=cs["ap"], ap_a=2, ap_rho=0.05, ap_gamma=1.0)
+                                seed=2024, ap=cs["ap"], ap_a=2, ap_rho=0.05, ap_gamma=1.0,
+                                resid_check=cs.get("rc", False))
         solve()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -320,13 +393,73 @@ def wl_ablation(torch, fr, synth, tracer):
         torch.cuda.synchronize()
         sec = time.perf_counter() - t0
         err = float(torch.linalg.norm(res.L - Lgt) / torch.linalg.norm(Lgt))
-        runs.append({"rule": "adaptive (a 2, rho 0.05, gamma 1)" if cs["ap"] else f"p {cs['p']}",
+        rule = "adaptive (a 2, rho 0.05, gamma 1)" if cs["ap"] else f"p {cs['p']}"
+        if cs.get("rc"):
+            rule += " + residual check (Prop. 4)"
+        runs.append({"rule": rule,
                      "q": cs["q"], "iters_per_s": round(iters / sec, 1), "iters": res.iters,
                      "ms_per_solve": round(1e3 * sec / K, 3), "converged": res.converged,
                      "nrmse_L": err, "widths_last": res.widths[-1] if res.widths else None,
                      "widths_max": max(res.widths) if res.widths else None})
+    # the residual check where it prunes: 2000 x 200, rank 3, 0.05 % outliers
+    # (the first sketch, l0 = 20, stops after 6 samples)
+    O2_np, L2_gt, _ = synth.rpca(seed=3, m=2000, n=200, rank=3, frac=0.0005)
+    O2 = torch.from_numpy(O2_np).cuda()
+    check = []
+    for rc in (False, True):
+        def solve2():
+            return fr.rpca_ialm(O2, 1.0 / np.sqrt(2000), use_frsvt=True, p=5, q=1, seed=17, resid_check=rc)
+        solve2()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            r2 = solve2()
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / 3
+        check.append({"resid_check": rc, "ms_per_solve": round(1e3 * sec, 3), "iters": r2.iters,
+                      "widths_first": r2.widths[:3], "converged": r2.converged,
+                      "nrmse_L": float(torch.linalg.norm(r2.L - torch.from_numpy(L2_gt).cuda()) /
+                                       np.linalg.norm(L2_gt))})
     return {"workload": "rpca_ialm_76800x200_p_q_ablation", "metric": "iters/s", "unit": "iters/s",
-            "runs": runs}
+            "runs": runs, "residual_check_2000x200_outliers_0.0005": check}
+
+
+def wl_rpca_f32(torch, fr, synth, tracer):
+    """The video workload in FP32 (float32 storage, FP64 Gram/Cholesky/small
+    SVD): iterations/s, iterations to tol, residual, NRMSE, epilogue GB/s."""
+    import numpy as np
+    O_np, L_gt, _ = synth.rpca(seed=0, m=M, n=N, rank=RANK, frac=FRAC)
+    O = torch.from_numpy(O_np.astype(np.float32)).cuda()
+    lam = 1.0 / np.sqrt(M)
+
+    def solve():
+        return fr.rpca_ialm(O, lam, use_frsvt=True, tol=1e-7, max_iter=60, p=5, q=1, seed=2024)
+    solve()
+    torch.cuda.synchronize()
+    times, iters = [], 0
+    for _ in range(5):
+        t0 = time.perf_counter()
+        res = solve()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        iters = res.iters
+    tracer.start()
+    solve()
+    torch.cuda.synchronize()
+    kernels = tracer.stop()
+    med = float(np.median(times))
+    out = {"workload": "rpca_ialm_frsvt_rp_76800x200_f32", "metric": "iters/s", "unit": "iters/s",
+           "value": round(iters / med, 2), "ms_per_solve_median": round(1e3 * med, 3),
+           "ms_per_solve_iqr": [round(1e3 * float(np.percentile(times, 25)), 3),
+                                round(1e3 * float(np.percentile(times, 75)), 3)],
+           "iters": iters, "converged": res.converged, "final_residual": res.residual,
+           "nrmse_L": float(np.linalg.norm(res.L.double().cpu().numpy() - L_gt) / np.linalg.norm(L_gt)),
+           "kernels": _r(kernels)}
+    if "epilogue" in kernels:
+        gbs = 4 * M * N * 4 / (kernels["epilogue"]["avg_us"] * 1e-6) / 1e9
+        out["epilogue_GBs"] = round(gbs, 1)
+        out["epilogue_frac_hbm"] = round(gbs / HBM_PEAK_GBS, 4)
+    return out
 
 
 def wl_typeb(torch, fr, synth, tracer):
@@ -468,13 +601,18 @@ def main():
     t0 = time.perf_counter()
     iters = 0
     res = None
+    per_solve = []
     for _ in range(args.steps):
-        res = solve(True)
+        a = time.perf_counter()
+        res = solve(True)          # returns after its last kernel (it waits for the stream)
+        per_solve.append(time.perf_counter() - a)
         iters += res.iters
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
     value = iters / elapsed
+    med_solve = float(np.median(per_solve))
+    iqr_solve = [float(np.percentile(per_solve, 25)), float(np.percentile(per_solve, 75))]
     # the same solve again with an event pair around every launch (on the
     # library's stream): per-kernel durations for the roofline
     _progress("traced solve")
@@ -503,6 +641,9 @@ def main():
         vendor = {"iters_per_s": round(1.0 / sec, 3), "iters_timed": args.vendor_iters,
                   "svd": "torch.linalg.svd (thin) of the 76800 x 200 iterate"}
 
+    _progress("measured copy bandwidth and GEMM rates")
+    rates = machine_rates(torch)
+
     # ---------------- roofline of the dominant kernel
     # Algorithmic bytes per launch, unit = one element of the 76800 x 200
     # matrix: the sketch, power and projection passes read A once; the RPCA
@@ -518,17 +659,19 @@ def main():
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "bytes_per_launch": bytes_per_launch,
-                "avg_launch_us": round(kernels[dom]["avg_us"], 2)}
+                "avg_launch_us": round(kernels[dom]["avg_us"], 2),
+                "frac_of_measured_copy": round(achieved / rates["hbm_copy_GBs"], 4)}
     passes = {}
     for k, ue in unit_elems.items():
         if k in kernels:
             gbs = ue * elems * ebytes / (kernels[k]["avg_us"] * 1e-6) / 1e9
-            passes[k] = {"GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+            passes[k] = {"GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                         "frac_of_measured_copy": round(gbs / rates["hbm_copy_GBs"], 4)}
 
     # ---------------- further workloads
     workloads = {}
     if not args.only_main:
-        fns = {"single": wl_single, "precision": wl_precision, "batched": wl_batched,
+        fns = {"rpca_f32": wl_rpca_f32, "single": wl_single, "precision": wl_precision, "batched": wl_batched,
                "unrolled": wl_unrolled, "ablation": wl_ablation, "typeb": wl_typeb, "lrr": wl_lrr,
                "tensor": wl_tensor}
         for name in [w for w in args.workloads.split(",") if w]:
@@ -553,6 +696,18 @@ def main():
                "kind": "oracle",
                "sample": f"76800x200 FP64, first {out['iters']} iALM iterations with FRSVT-RP "
                          f"(including the ||O||_2 SVD), single thread, {dt:.1f} s"}
+        # the same sample on every host core the box gives this process
+        # (the oracle's source built with -fopenmp; same values, bit for bit)
+        with oracle.use_library(oracle.build_openmp()):
+            thr = oracle.threads()
+            a = time.perf_counter()
+            out2 = oracle.rpca_ialm(O_np, lam, mode="frsvt", p=5, q=1, seed=2024,
+                                    max_iter=args.cpu_iters)
+            dt2 = time.perf_counter() - a
+        cpu["all_cores"] = {"value": round(out2["iters"] / dt2, 4), "unit": "iters/s", "cores": thr,
+                            "nproc": os.cpu_count(),
+                            "sample": f"the same {out2['iters']} iterations, OpenMP build, {thr} threads, "
+                                      f"{dt2:.1f} s"}
         # the further hosts' oracles on bounded samples of the same inputs
         further = {}
         if "lrr" in workloads and "error" not in workloads["lrr"]:
@@ -621,8 +776,12 @@ def main():
         "config": {"workload": "rpca_ialm_frsvt_rp_76800x200", "m": M, "n": N, "rank": RANK,
                    "outliers": FRAC, "lambda": lam, "p": 5, "q": 1, "l0": 20, "tol": 1e-7,
                    "max_iter": 60},
+        "ms_per_solve_median": round(1e3 * med_solve, 3),
+        "ms_per_solve_iqr": [round(1e3 * x, 3) for x in iqr_solve],
+        "iters_per_s_at_median": round(res.iters / med_solve, 2),
         "iters_per_solve": res.iters,
         "traced_solve_iters": traced.iters,
+        "measured": rates,
         "converged": res.converged,
         "final_residual": res.residual,
         "nrmse_L": nrmse,

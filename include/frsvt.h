@@ -88,6 +88,21 @@ FRSVT_API int frsvt_create(frsvt_handle *handle, int device, void *hip_stream);
 /* Release the workspace and the handle.  Waits for the handle's stream. */
 FRSVT_API int frsvt_destroy(frsvt_handle handle);
 
+/* Handle options (off by default):
+ *   FRSVT_OPT_QRCP_TRUNCATE  value 1: a fresh sketch (frsvt / frsvt_noalloc
+ *     without Q_prev) is truncated to its numerical rank before the power
+ *     iterations, as Alg. 1's QR_CP step and Sec. 2.1's s = min(l, r) do:
+ *     Householder QR with column pivoting of Y = Ahat Omega keeps the s
+ *     leading pivoted samples with |R_jj| > mhat * 2^-52 * |R_11|.  The
+ *     thresholded result does not depend on it (the dropped samples add no
+ *     direction of Ahat's range); the small factors shrink to s.  One host
+ *     wait per call; on the one-workgroup path (FP64/FP32, l <= 64 and
+ *     mhat l within its local memory) only, elsewhere l samples are kept.
+ *     frsvt_last_info word 3 reports s (l when nothing was dropped).
+ * Returns -2 for an unknown option, -3 for an invalid value. */
+#define FRSVT_OPT_QRCP_TRUNCATE 1
+FRSVT_API int frsvt_set_option(frsvt_handle handle, int option, int value);
+
 /* Rebind the handle to another stream of the same device. */
 FRSVT_API int frsvt_set_stream(frsvt_handle handle, void *hip_stream);
 
@@ -136,7 +151,9 @@ FRSVT_API const char *frsvt_trace_name(int kernel_class);
 
 /* Status words of the last thresholding step, copied to the host (waits for
  * the stream): info[0] rank r, info[1] Jacobi sweeps of the small SVD,
- * info[2] 1 when that Jacobi met its stopping test, info[4] 1 when the last
+ * info[2] 1 when that Jacobi met its stopping test, info[3] the sketch width
+ * s used by the last frsvt call (after the optional QR_CP truncation),
+ * info[4] 1 when the last
  * re-orthonormalisation took the CholeskyQR2 fast path (2 = shifted
  * fallback), info[5] columns refilled, info[6] final Cholesky failures,
  * info[7] 1 when frsvt_vjp met a singular triangular factor.
@@ -393,8 +410,12 @@ typedef struct {
  * waits for the stream), orders the matrices longest first, runs the
  * autotuner once per handle (group size of the Jacobi pair work per size
  * bucket, timed on the device) and captures the persistent launch in a HIP
- * graph; later calls with the same arguments replay that graph without
- * waiting.
+ * graph; later calls with the same arguments (pointers, count and rule)
+ * replay that graph.  The replay reads rows/cols anew: shapes rewritten in
+ * place keep the first call's processing order and tuning, and a shape
+ * outside the bounds above is skipped by the kernel (its rank set to -1)
+ * and reported as FRSVT_ERR_UNSUPPORTED.  Every call waits for the stream
+ * once, to read that check.
  */
 FRSVT_API int wsvt_batched(frsvt_handle handle, int64_t count, const int32_t *rows,
                  const int32_t *cols, const int64_t *offsets, const float *A_packed,

@@ -37,6 +37,27 @@ def build(force: bool = False) -> str:
     return _LIB_PATH
 
 
+_OMP_LIB_PATH = os.path.join(_HERE, "liboracle_omp.so")
+
+
+def build_openmp(force: bool = False) -> str:
+    """The same source compiled with -fopenmp (for the all-core CPU
+    baseline only): the parallel loops split independent output columns, so
+    the results equal the plain build's bit for bit."""
+    if force or not os.path.exists(_OMP_LIB_PATH) or \
+            os.path.getmtime(_OMP_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _OMP_LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-o", tmp,
+                               _SRC, "-lm"])
+        os.replace(tmp, _OMP_LIB_PATH)
+    return _OMP_LIB_PATH
+
+
+def threads() -> int:
+    """Threads of the active oracle build (1 for the plain build)."""
+    return int(_L().orc_threads())
+
+
 _libs: dict = {}
 _active = [None]
 
@@ -45,6 +66,8 @@ def _bind(path: str):
     if path not in _libs:
         lib = ctypes.CDLL(path)
         lib.orc_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
+        lib.orc_threads.argtypes = []
+        lib.orc_threads.restype = ctypes.c_int
         lib.orc_uniform53.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
         lib.orc_uniform53.restype = ctypes.c_double
         lib.orc_gaussian_matrix.argtypes = [ctypes.c_uint64, ctypes.c_uint64, _i64, _i64, _dp, _i64]

@@ -12,6 +12,10 @@
  */
 #include "frsvt_oracle.h"
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
 #include <float.h>
 #include <math.h>
 #include <stdlib.h>
@@ -94,6 +98,7 @@ void orc_gaussian_matrix(uint64_t seed, uint64_t counter, int64_t rows, int64_t 
 static void mat_mul(int64_t m, int64_t n, int64_t k, const double *A, int64_t lda,
                     const double *B, int64_t ldb, double *C, int64_t ldc)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < n; ++j) {
         for (int64_t i = 0; i < m; ++i) AT(C, ldc, i, j) = 0.0;
         for (int64_t p = 0; p < k; ++p) {
@@ -108,6 +113,7 @@ static void mat_mul(int64_t m, int64_t n, int64_t k, const double *A, int64_t ld
 static void mat_mul_tn(int64_t m, int64_t n, int64_t k, const double *A, int64_t lda,
                        const double *B, int64_t ldb, double *C, int64_t ldc)
 {
+#pragma omp parallel for collapse(2) schedule(static)
     for (int64_t j = 0; j < n; ++j)
         for (int64_t i = 0; i < m; ++i) {
             double s = 0.0;
@@ -167,6 +173,7 @@ static void apply_reflector(int64_t m, int64_t j, double beta, double *W, int64_
                             int64_t c0, int64_t c1)
 {
     if (beta == 0.0) return;
+#pragma omp parallel for schedule(static)
     for (int64_t c = c0; c < c1; ++c) {
         double s = AT(W, ldw, j, c);
         for (int64_t i = j + 1; i < m; ++i) s += AT(W, ldw, i, j) * AT(W, ldw, i, c);
@@ -399,6 +406,7 @@ static double soft_shrink(double x, double tau)
 static void rank_sum(int64_t m, int64_t n, int64_t count, const double *U, int64_t ldu,
                      const double *shrunk, const double *V, int64_t ldv, double *X, int64_t ldx)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < n; ++j) {
         for (int64_t i = 0; i < m; ++i) AT(X, ldx, i, j) = 0.0;
         for (int64_t c = 0; c < count; ++c) {
@@ -1132,4 +1140,17 @@ int orc_lrr_ialm(int64_t d, int64_t n, const double *X, int64_t ldx, double lamb
     free(Lc); free(Zk); free(J); free(Ek); free(Y1); free(Y2); free(XZ); free(T); free(W);
     free(R); free(Qt); free(Qnew);
     return status;
+}
+
+/* Threads the oracle's loops use: 1 in the plain build; in the OpenMP build
+ * (-fopenmp, for the all-core CPU baseline) the OpenMP thread count.  The
+ * parallel loops split independent output columns (or reflector target
+ * columns), so both builds compute every value in the same order. */
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

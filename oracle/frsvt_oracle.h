@@ -169,6 +169,9 @@ int orc_svt_vjp(int64_t m, int64_t n, const double *A, int64_t lda, double tau,
                 const double *Xbar, int64_t ldxb, double *Abar, int64_t ldab,
                 double *taubar);
 
+/* 1 in the plain build, the OpenMP thread count in the OpenMP build. */
+int orc_threads(void);
+
 #ifdef __cplusplus
 }
 #endif

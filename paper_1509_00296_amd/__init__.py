@@ -100,6 +100,7 @@ def library(path: str | None = None) -> ctypes.CDLL:
     lib.frsvt.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _i64, _dbl, _i32, _i32, _i32, _vp,
                           _i32, _i64, _u64, _u64, _vp, _i64, _vp, _i64, ctypes.POINTER(_i32)]
     lib.frsvt_noalloc.argtypes = lib.frsvt.argtypes
+    lib.frsvt_set_option.argtypes = [_vp, ctypes.c_int, ctypes.c_int]
     lib.rpca_unrolled_saved_bytes.argtypes = [ctypes.c_int, _i32, _i32, _i64, _i64, _i32, _i32]
     lib.rpca_unrolled_saved_bytes.restype = _i64
     lib.rpca_unrolled_schedule.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _i64, _dbl, _dbl, _dbl, _i32,
@@ -314,12 +315,15 @@ def wsvt_tuning() -> list:
 
 
 def frsvt(A, tau: float, k: int, p: int, q: int, Q_prev=None, *, seed: int = 0,
-          counter: int = 0, return_basis: bool = True, out=None, noalloc: bool = False):
+          counter: int = 0, return_basis: bool = True, out=None, noalloc: bool = False,
+          want_rank: bool = True):
     """FRSVT (Alg. 1).  Returns (X, Q~ (mhat x r), r); with Q_prev (mhat x r_prev,
     orthonormal columns) the basis is propagated and only p samples are drawn.
     out = (X, Qout) supplies the output buffers (X like A, Qout column-major
     mhat x l); noalloc calls frsvt_noalloc, whose workspace is the library's
-    fixed device scratch."""
+    fixed device scratch.  want_rank=False leaves the rank on the device
+    (no host wait: the call can be captured in a graph); r is then -1 and
+    the basis is returned at its full width l."""
     import torch
     h = handle(A.device.index)
     m, n, lda, tr = _colmajor(A)
@@ -350,8 +354,10 @@ def frsvt(A, tau: float, k: int, p: int, q: int, Q_prev=None, *, seed: int = 0,
     rc = fn(h.ptr, _prec(A), m, n, A.data_ptr(), lda, float(tau), int(k), int(p), int(q),
             qptr, int(rp), int(ldq), int(seed) & (2**64 - 1), int(counter) & (2**64 - 1),
             X.data_ptr(), ldx, Qout.data_ptr() if return_basis else None, mh,
-            ctypes.byref(r))
+            ctypes.byref(r) if want_rank else None)
     _check(h, rc, "frsvt_noalloc" if noalloc else "frsvt")
+    if not want_rank:
+        return X, Qout, -1
     rr = int(r.value)
     return X, Qout[:, :rr], rr
 
@@ -523,6 +529,15 @@ def frsvt_vjp(A, tau: float, k: int, p: int, q: int, Q, factors, X_bar, *, seed:
                          Ab.data_ptr(), ldab, tb.data_ptr())
     _check(h, rc, "frsvt_vjp")
     return Ab, tb
+
+
+OPT_QRCP_TRUNCATE = 1
+
+
+def set_option(option: int, value: int, device: int | None = None) -> None:
+    """Handle option (frsvt_set_option), e.g. OPT_QRCP_TRUNCATE."""
+    h = handle(device)
+    _check(h, h.lib.frsvt_set_option(h.ptr, int(option), int(value)), "frsvt_set_option")
 
 
 def last_info(count: int = 8) -> list:

@@ -30,6 +30,7 @@ struct frsvt_context {
     double *dscalars = nullptr;  // small device scalar area (doubles)
     void *pinned = nullptr;      // host pinned status area
     void *scratch_dev = nullptr; // device address of this device's fixed scratch (frsvt_noalloc)
+    int opt_truncate = 0;        // FRSVT_OPT_QRCP_TRUNCATE
     char last_error[256] = {0};
     // unrolled RPCA and other batch drivers: side contexts, each with its own
     // stream, workspace and status words, that run instances concurrently;
@@ -273,6 +274,7 @@ struct Core {
     int *status;         // device: [0] r, [1] sweeps, [2] converged, [4..] orth flags
     double *resid_out = nullptr;   // device, optional: squared residual of the first new sample (Prop. 4)
     int keep = 0;        // partial SVT: the first keep singular values pass unshrunk
+    const T *ysrc = nullptr;  // sketch columns to orthonormalise when not b.Y (after truncation)
 };
 
 template <typename T>
@@ -537,8 +539,8 @@ int run_core(frsvt_context *h, Core<T> &c, CoreBuffers<T> &b)
     // Alg. 1, sketch and initial basis (fresh or range-propagated)
     if (small) {
         if (!c.sketch_ready && (rc = sketch_stage<T>(h, c, b))) return rc;
-        CKT(FRSVT_K_ORTH, launch_small_orth<T>(mh, c.Qt, c.ldqt, c.rp, b.Y, mh, c.cnew, b.Q, mh, c.seed,
-                                c.counter, oflags, c.resid_out, s));
+        CKT(FRSVT_K_ORTH, launch_small_orth<T>(mh, c.Qt, c.ldqt, c.rp, c.ysrc ? c.ysrc : b.Y, mh, c.cnew, b.Q, mh,
+                                c.seed, c.counter, oflags, c.resid_out, s));
     } else {
         if (c.rp > 0)
             CK(hipMemcpy2DAsync(b.Q, mh * sizeof(T), c.Qt, c.ldqt * sizeof(T), mh * sizeof(T),
@@ -775,7 +777,23 @@ int frsvt_impl(frsvt_context *h, int64_t m, int64_t n, const T *A, int64_t lda, 
         c.A16T = A16T;
     }
     carve_core<T>(cv, o, l, c.cnew, h->num_cu, b, mixed);
+    // Alg. 1's QR_CP of a fresh sketch (Sec. 2.1: s = min(l, r)): the
+    // numerically null samples are dropped before the power iterations
+    int s_used = l;
+    if (h->opt_truncate && c.rp == 0 && c.cnew > 1 && !mixed && !Qsave && !factors &&
+        core_small<T>(c, c.cnew) && qrcp_trunc_ok(o.mh, c.cnew)) {
+        if ((rc = sketch_stage<T>(h, c, b))) return rc;
+        CKT(FRSVT_K_ORTH, launch_qrcp_trunc<T>(o.mh, c.cnew, b.Y, o.mh, (double)o.mh * 2.220446049250313e-16,
+                                               b.Qtmp, o.mh, h->dstatus + 3, h->stream));
+        CK(hipMemcpyAsync(h->pinned, h->dstatus + 3, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+        CK(hipStreamSynchronize(h->stream));
+        s_used = std::max(1, ((const int *)h->pinned)[0]);
+        c.cnew = s_used;
+        c.sketch_ready = true;
+        c.ysrc = b.Qtmp;
+    }
     if ((rc = run_core<T>(h, c, b))) return rc;
+    CKT(FRSVT_K_OTHER, launch_fill_int(h->dstatus + 3, 1, s_used, h->stream));
     if (Qsave)
         CK(hipMemcpy2DAsync(Qsave, ldqs * sizeof(T), b.Q, o.mh * sizeof(T), o.mh * sizeof(T), l,
                             hipMemcpyDeviceToDevice, h->stream));
@@ -1102,18 +1120,22 @@ int rpca_init_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t l
 template <typename T>
 int spectral_norm(frsvt_context *h, const T *A, int64_t lda, const Orient &o, double *out)
 {
+    // ||A||_2^2 = lambda_1(G), G = Ahat Ahat^T (mhat x mhat, FP64): block
+    // subspace iteration with Rayleigh-Ritz; where it cannot certify its
+    // estimate (more than eight top eigenvalues within a few per cent, or
+    // mhat < 8) the full small SVD of G (Cholesky + one-sided Jacobi)
     const int mh = o.mh;
     const int sk = gemm_splitk(mh, mh, o.nh, h->num_cu);
     Carver dry(nullptr);
     dry.take<double>((size_t)mh * mh);
     dry.take<double>((size_t)sk * mh * mh);
-    dry.take<double>((size_t)2 * mh + 2);
+    dry.take<double>((size_t)mh * mh * 3 + mh);
     int rc = ensure_ws(h, dry.off);
     if (rc) return rc;
     Carver cv(h->ws);
     double *G = cv.take<double>((size_t)mh * mh);
     double *gp = cv.take<double>((size_t)sk * mh * mh);
-    double *wk = cv.take<double>((size_t)2 * mh + 2);
+    double *sv = cv.take<double>((size_t)mh * mh * 3 + mh);
     if (std::is_same<T, double>::value) {
         // on the matrix cores (each operand has a unit stride)
         CKT(FRSVT_K_GEMM, launch_gemm_f64_mfma(mh, mh, o.nh, (const double *)A, o.si, o.sk, (const double *)A,
@@ -1123,10 +1145,27 @@ int spectral_norm(frsvt_context *h, const T *A, int64_t lda, const Orient &o, do
                                                (const float *)A, o.sk, o.si, G, 1, mh, sk, gp,
                                                h->stream)));
     }
-    CKT(FRSVT_K_OTHER, launch_power_eig(mh, G, wk, h->dscalars, h->stream));
-    CK(hipMemcpyAsync(h->pinned, h->dscalars, sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    CK(hipStreamSynchronize(h->stream));
-    *out = std::sqrt(std::max(0.0, ((double *)h->pinned)[0]));
+    double lam = 0.0;
+    bool ok = false;
+    if (mh >= 8) {
+        CKT(FRSVT_K_OTHER, launch_power_eig(mh, G, h->dscalars, h->stream));
+        CK(hipMemcpyAsync(h->pinned, h->dscalars, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        CK(hipStreamSynchronize(h->stream));
+        lam = ((double *)h->pinned)[0];
+        ok = ((double *)h->pinned)[1] > 0.5;
+    }
+    if (!ok) {
+        double *sig = sv, *U = sv + mh, *Mm = U + (size_t)mh * mh, *jw = Mm + (size_t)mh * mh;
+        SmallSvdOut so{sig, U, Mm, h->dstatus};
+        CKT(FRSVT_K_SMALL_SVD, launch_small_svd<T>(mh, G, 0.0, nullptr, 0, (const T *)nullptr, 0, mh, (T *)nullptr,
+                                                   0, (T *)nullptr, 0, so, jw, 0, h->stream));
+        CK(hipMemcpyAsync(h->pinned, sig, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        CK(hipStreamSynchronize(h->stream));
+        const double s1 = ((double *)h->pinned)[0];
+        *out = s1 > 0.0 ? s1 : 0.0;
+        return FRSVT_OK;
+    }
+    *out = std::sqrt(std::max(0.0, lam));
     return FRSVT_OK;
 }
 
@@ -1516,9 +1555,23 @@ int wsvt_batched_impl(frsvt_context *h, int64_t count, const int32_t *rows, cons
     uint64_t bits[4];
     memcpy(bits, &rule, sizeof(bits));
     for (uint64_t b : bits) key.push_back(b);
+    // the kernel checks every shape it reads and flags one outside the
+    // bounds (the replay reads the shapes anew): the flag is read back after
+    // every launch
+    auto shape_flag = [&]() -> int {
+        CK(hipMemcpyAsync(h->pinned, h->wb_queue + 1, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+        CK(hipStreamSynchronize(h->stream));
+        if (((const int *)h->pinned)[0] != 0) {
+            snprintf(h->last_error, sizeof(h->last_error),
+                     "wsvt_batched: a matrix shape outside 1..128 (shorter side <= 96) was skipped "
+                     "(shapes changed after the first call?); its rank is -1");
+            return FRSVT_ERR_UNSUPPORTED;
+        }
+        return FRSVT_OK;
+    };
     if (h->wb_exec && key == h->wb_key && !h->tracing) {
         CK(hipGraphLaunch(h->wb_exec, h->stream));
-        return FRSVT_OK;
+        return shape_flag();
     }
     // shapes to the host once per argument set: longest-first order and tuning
     std::vector<int32_t> hr(count), hc(count);
@@ -1606,7 +1659,10 @@ int wsvt_batched_impl(frsvt_context *h, int64_t count, const int32_t *rows, cons
     int32_t gs3[3] = {h->wb_gs[0], h->wb_gs[1], h->wb_gs[2]};
     CK(hipMemcpyAsync(h->wb_gs_dev, gs3, sizeof(gs3), hipMemcpyHostToDevice, h->stream));
     CK(hipStreamSynchronize(h->stream));
-    if (h->tracing) return wb_launch(h, a, h->stream);
+    if (h->tracing) {
+        if ((rc = wb_launch(h, a, h->stream))) return rc;
+        return shape_flag();
+    }
     // capture the persistent launch (queue reset kernel + kernel) once
     if (h->wb_exec) {
         (void)hipGraphExecDestroy(h->wb_exec);
@@ -1624,7 +1680,7 @@ int wsvt_batched_impl(frsvt_context *h, int64_t count, const int32_t *rows, cons
     }
     h->wb_key = key;
     CK(hipGraphLaunch(h->wb_exec, h->stream));
-    return FRSVT_OK;
+    return shape_flag();
 }
 
 
@@ -2247,6 +2303,15 @@ int frsvt_destroy(frsvt_handle h)
     if (h->pinned) (void)hipHostFree(h->pinned);
     if (h->owns_stream && h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
+    return FRSVT_OK;
+}
+
+int frsvt_set_option(frsvt_handle h, int option, int value)
+{
+    if (!h) return -1;
+    if (option != FRSVT_OPT_QRCP_TRUNCATE) return -2;
+    if (value != 0 && value != 1) return -3;
+    h->opt_truncate = value;
     return FRSVT_OK;
 }
 

@@ -287,81 +287,273 @@ template hipError_t launch_finite_check<double>(int64_t, int64_t, const double *
 template hipError_t launch_finite_check<float>(int64_t, int64_t, const float *, int64_t, int *, hipStream_t);
 
 // Power method on a symmetric PSD l x l matrix (global memory, one workgroup).
-__global__ void __launch_bounds__(1024) k_power_eig(int l, const double *G, double *x, double *out)
+// Largest eigenvalue of a symmetric positive semidefinite n x n matrix G
+// (the Gram A A^T; n <= 1024) by subspace iteration with a block of kEigB
+// vectors and Rayleigh-Ritz: from a Gaussian start block (Philox), each step
+// W = G V, H = V^T W (the Rayleigh matrix of the orthonormal V), the largest
+// eigenvalue theta_1 of H (cyclic Jacobi, one thread) as the estimate, then
+// V = orth(W) by two Cholesky-QR passes.  theta_1 rises to lambda_1 with the
+// error contracting by (lambda_{kEigB+1} / lambda_1)^2 per step, whatever the
+// gaps inside the top kEigB (close or equal top eigenvalues do not slow it);
+// the smallest Ritz value theta_kEigB (<= lambda_kEigB) over theta_1 bounds
+// that ratio from above once the block has settled.  Stops after step k when
+// theta_1 moved by at most 16 n u of itself (the rounding level of the
+// Rayleigh matrix) and (theta_kEigB / theta_1)^(2k) <= 1e-16, or after
+// max_it steps.  out[0] = theta_1, out[1] = 1 when the test
+// was met (else 0: the caller takes another method).
+constexpr int kEigB = 8;
+constexpr int kEigNP = kEigB * (kEigB + 1) / 2;   // packed symmetric entries
+constexpr int kEigThreads = 256;
+
+__device__ __forceinline__ void eig_pair(int p, int &a, int &b)
 {
-    __shared__ double red[16];
-    __shared__ double lam_sh, nrm_sh;
+    a = 0;
+    while (p >= kEigB - a) {
+        p -= kEigB - a;
+        ++a;
+    }
+    b = a + p;
+}
+
+// packed index of (a, b), a <= b (rows of the upper triangle in order)
+__host__ __device__ constexpr int eig_idx(int a, int b) { return a * kEigB - a * (a - 1) / 2 + (b - a); }
+
+// Packed symmetric sums over the block's rows: red[k] = sum_i x_i[a] y_i[b]
+// for the kEigNP pairs (a <= b), in a fixed order (wavefront shuffles, then
+// the wavefronts in order).
+__device__ __forceinline__ void eig_block_gram(int n, const double *X, const double *Y, double *part,
+                                               double *red)
+{
     const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
-    double *y = x + l;
-    for (int i = tid; i < l; i += 1024) x[i] = 1.0 / sqrt((double)l) * (1.0 + 0.01 * (i % 7));
-    __syncthreads();
-    double lam_old = -1.0;
-    for (int it = 0; it < 20000; ++it) {
-        // y = G x
-        for (int i = tid; i < l; i += 1024) {
-            double s = 0.0;
-            for (int j = 0; j < l; ++j) s += G[i + (size_t)j * l] * x[j];
-            y[i] = s;
+    constexpr int nw = kEigThreads / kWave;
+    double acc[kEigNP];
+#pragma unroll
+    for (int p = 0; p < kEigNP; ++p) acc[p] = 0.0;
+    for (int i = tid; i < n; i += kEigThreads) {
+        double x[kEigB], y[kEigB];
+#pragma unroll
+        for (int c = 0; c < kEigB; ++c) {
+            x[c] = X[i * kEigB + c];
+            y[c] = Y[i * kEigB + c];
         }
-        __syncthreads();
-        // lambda = x^T y, ||y||
-        double a = 0.0, b = 0.0;
-        for (int i = tid; i < l; i += 1024) {
-            a += x[i] * y[i];
-            b += y[i] * y[i];
-        }
-        a = wave_sum(a);
-        b = wave_sum(b);
-        if (lane == 0) {
-            red[wave] = a;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            double s = 0.0;
-            for (int w = 0; w < 16; ++w) s += red[w];
-            lam_sh = s;
-        }
-        __syncthreads();
-        if (lane == 0) red[wave] = b;
-        __syncthreads();
-        if (tid == 0) {
-            double s = 0.0;
-            for (int w = 0; w < 16; ++w) s += red[w];
-            nrm_sh = sqrt(s);
-        }
-        __syncthreads();
-        const double lam = lam_sh, nrm = nrm_sh;
-        if (!(nrm > 0.0)) {
-            if (tid == 0) out[0] = 0.0;
-            return;
-        }
-        for (int i = tid; i < l; i += 1024) x[i] = y[i] / nrm;
-        __syncthreads();
-        if (fabs(lam - lam_old) <= 1e-15 * lam && it > 3) break;
-        lam_old = lam;
+#pragma unroll
+        for (int a = 0; a < kEigB; ++a)
+#pragma unroll
+            for (int b = a; b < kEigB; ++b) acc[eig_idx(a, b)] += x[a] * y[b];
     }
-    // final Rayleigh quotient with the normalised x
-    for (int i = tid; i < l; i += 1024) {
+#pragma unroll
+    for (int p = 0; p < kEigNP; ++p) {
+        const double v = wave_sum(acc[p]);
+        if (lane == 0) part[p * nw + wave] = v;
+    }
+    __syncthreads();
+    if (tid < kEigNP) {
         double s = 0.0;
-        for (int j = 0; j < l; ++j) s += G[i + (size_t)j * l] * x[j];
-        y[i] = s;
+        for (int w = 0; w < nw; ++w) s += part[tid * nw + w];
+        red[tid] = s;
     }
     __syncthreads();
-    double a = 0.0;
-    for (int i = tid; i < l; i += 1024) a += x[i] * y[i];
-    a = wave_sum(a);
-    if (lane == 0) red[wave] = a;
-    __syncthreads();
+}
+
+// Semidefinite upper Cholesky factor of the packed Gram (one thread, all in
+// registers): a pivot at or below 64 u times the largest diagonal entry
+// gives a zero row (the block has lost that direction: G has smaller rank
+// than the block, and the remaining columns already span its range); false
+// for a non-finite Gram.
+__device__ bool eig_chol(const double *gp, double *R)
+{
+    double M[kEigB][kEigB];
+    double mx = 0.0;
+#pragma unroll
+    for (int a = 0; a < kEigB; ++a)
+#pragma unroll
+        for (int b = 0; b < kEigB; ++b) {
+            M[a][b] = b >= a ? gp[eig_idx(a, b)] : 0.0;
+            if (a == b) mx = fmax(mx, M[a][b]);
+        }
+    if (!(mx < 1e300)) return false;
+    const double tol = 64.0 * kU * mx;
+#pragma unroll
+    for (int j = 0; j < kEigB; ++j) {
+        double d = M[j][j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) d -= M[k][j] * M[k][j];
+        const bool null = !(d > tol);
+        const double r = null ? 0.0 : sqrt(d);
+        const double inv = null ? 0.0 : 1.0 / r;
+        M[j][j] = r;
+#pragma unroll
+        for (int c = j + 1; c < kEigB; ++c) {
+            double v = M[j][c];
+#pragma unroll
+            for (int k = 0; k < j; ++k) v -= M[k][j] * M[k][c];
+            M[j][c] = v * inv;
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < kEigB; ++a)
+#pragma unroll
+        for (int b = 0; b < kEigB; ++b) R[a * kEigB + b] = b >= a ? M[a][b] : 0.0;
+    return true;
+}
+
+// Largest and smallest eigenvalues of the packed symmetric kEigB x kEigB
+// matrix (cyclic Jacobi, one thread, all in registers).
+__device__ double eig_small_max(const double *hp, double *mn_out)
+{
+    double H[kEigB][kEigB];
+#pragma unroll
+    for (int a = 0; a < kEigB; ++a)
+#pragma unroll
+        for (int b = 0; b < kEigB; ++b) H[a][b] = hp[a <= b ? eig_idx(a, b) : eig_idx(b, a)];
+    for (int sweep = 0; sweep < 12; ++sweep) {
+        double off = 0.0, tot = 0.0;
+#pragma unroll
+        for (int a = 0; a < kEigB; ++a)
+#pragma unroll
+            for (int b = 0; b < kEigB; ++b) {
+                tot += H[a][b] * H[a][b];
+                if (a != b) off += H[a][b] * H[a][b];
+            }
+        if (!(off > 1e-32 * tot)) break;
+#pragma unroll
+        for (int p = 0; p < kEigB - 1; ++p)
+#pragma unroll
+            for (int q = p + 1; q < kEigB; ++q) {
+                const double apq = H[p][q];
+                const double theta = (H[q][q] - H[p][p]) / (2.0 * apq);
+                double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
+                if (apq == 0.0) t = 0.0;
+                const double c = 1.0 / sqrt(1.0 + t * t), sn = t * c;
+#pragma unroll
+                for (int k = 0; k < kEigB; ++k) {
+                    const double hkp = H[k][p], hkq = H[k][q];
+                    H[k][p] = c * hkp - sn * hkq;
+                    H[k][q] = sn * hkp + c * hkq;
+                }
+#pragma unroll
+                for (int k = 0; k < kEigB; ++k) {
+                    const double hpk = H[p][k], hqk = H[q][k];
+                    H[p][k] = c * hpk - sn * hqk;
+                    H[q][k] = sn * hpk + c * hqk;
+                }
+            }
+    }
+    double mx = H[0][0], mn = H[0][0];
+#pragma unroll
+    for (int a = 1; a < kEigB; ++a) {
+        mx = fmax(mx, H[a][a]);
+        mn = fmin(mn, H[a][a]);
+    }
+    *mn_out = mn;
+    return mx;
+}
+
+__global__ void __launch_bounds__(kEigThreads) k_power_eig(int n, const double *G, double *out, int max_it)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double *V = reinterpret_cast<double *>(smem_raw);          // n x kEigB, row-major
+    double *W = V + (size_t)n * kEigB;                          // n x kEigB
+    __shared__ double part[kEigNP * (kEigThreads / kWave)];
+    __shared__ double red[kEigNP];
+    __shared__ double R[kEigB * kEigB];
+    __shared__ double est_sh;
+    __shared__ int stop_sh, ok_sh;
+    const int tid = threadIdx.x;
+    // Gaussian start block (a fixed Philox stream)
+    for (int i = tid; i < n; i += kEigThreads)
+        for (int c = 0; c < kEigB; c += 2) {
+            double z0, z1;
+            gaussian_pair(0x6e6f726d32ull, 0, (uint32_t)i, 0x40000000u | (uint32_t)c, z0, z1);
+            V[i * kEigB + c] = z0;
+            V[i * kEigB + c + 1] = z1;
+        }
     if (tid == 0) {
-        double s = 0.0;
-        for (int w = 0; w < 16; ++w) s += red[w];
-        out[0] = s;
+        est_sh = 0.0;
+        stop_sh = 0;
+        ok_sh = 0;
+    }
+    __syncthreads();
+    // X <- X R^-1 for the rows of X (zero pivots give zero columns)
+    auto right_solve = [&](double *X) {
+        for (int i = tid; i < n; i += kEigThreads) {
+            double x[kEigB];
+#pragma unroll
+            for (int c = 0; c < kEigB; ++c) x[c] = X[i * kEigB + c];
+#pragma unroll
+            for (int c = 0; c < kEigB; ++c) {
+                double v = x[c];
+#pragma unroll
+                for (int k = 0; k < c; ++k) v -= x[k] * R[k * kEigB + c];
+                const double rc = R[c * kEigB + c];
+                x[c] = rc > 0.0 ? v / rc : 0.0;
+            }
+#pragma unroll
+            for (int c = 0; c < kEigB; ++c) V[i * kEigB + c] = x[c];
+        }
+        __syncthreads();
+    };
+    // V = orth(X): two Cholesky-QR passes
+    auto orth = [&](double *X) {
+        for (int pass = 0; pass < 2; ++pass) {
+            double *Xp = pass == 0 ? X : V;
+            eig_block_gram(n, Xp, Xp, part, red);
+            if (tid == 0 && !eig_chol(red, R)) stop_sh = 2;
+            __syncthreads();
+            if (stop_sh == 2) return;
+            right_solve(Xp);
+        }
+    };
+    orth(V);
+    for (int it = 0; it < max_it && stop_sh == 0; ++it) {
+        // W = G V (G symmetric: row i read as column i, coalesced across threads)
+        for (int i = tid; i < n; i += kEigThreads) {
+            double w[kEigB];
+#pragma unroll
+            for (int c = 0; c < kEigB; ++c) w[c] = 0.0;
+            for (int j = 0; j < n; ++j) {
+                const double g = G[i + (size_t)j * n];
+#pragma unroll
+                for (int c = 0; c < kEigB; ++c) w[c] += g * V[j * kEigB + c];
+            }
+#pragma unroll
+            for (int c = 0; c < kEigB; ++c) W[i * kEigB + c] = w[c];
+        }
+        __syncthreads();
+        // Rayleigh matrix of V and its largest eigenvalue
+        eig_block_gram(n, V, W, part, red);
+        if (tid == 0) {
+            double tmin = 0.0;
+            const double est = eig_small_max(red, &tmin);
+            const double d = est - est_sh;
+            const double ratio = est > 0.0 ? fmax(tmin, 0.0) / est : 1.0;
+            // the Rayleigh matrix carries rounding of order n u lambda_1: a step
+            // that moves the estimate by less than 16 n u of it has converged
+            if (it >= 1 && fabs(d) <= 16.0 * (double)n * kU * fabs(est) && pow(ratio, 2.0 * (it + 1)) <= 1e-16) {
+                stop_sh = 1;
+                ok_sh = 1;
+            }
+            if (!(est > 0.0)) {          // G = 0
+                stop_sh = 1;
+                ok_sh = 1;
+            }
+            est_sh = fmax(est, est_sh);
+        }
+        __syncthreads();
+        if (stop_sh) break;
+        orth(W);
+    }
+    if (tid == 0) {
+        out[0] = est_sh;
+        out[1] = ok_sh ? 1.0 : 0.0;
     }
 }
 
-hipError_t launch_power_eig(int l, const double *G, double *work, double *out, hipStream_t s)
+hipError_t launch_power_eig(int n, const double *G, double *out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_power_eig, dim3(1), dim3(1024), 0, s, l, G, work, out);
+    if (n < kEigB || n > 1024) return hipErrorInvalidValue;
+    const size_t lds = 2 * (size_t)n * kEigB * sizeof(double);
+    hipLaunchKernelGGL(k_power_eig, dim3(1), dim3(kEigThreads), lds, s, n, G, out, 300);
     return hipGetLastError();
 }
 

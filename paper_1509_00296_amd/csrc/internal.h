@@ -87,6 +87,13 @@ template <typename T>
 hipError_t launch_resid_seq(int mh, const T *Qt, int64_t ldqt, int rp, const T *Y, int64_t ldy, int c,
                             double *out, hipStream_t s);
 bool resid_seq_ok(int mh, int rp, int c);
+// Rank truncation of a fresh sketch Y (mh x c) by Householder QR with
+// column pivoting: *s_out = #{leading |R_jj| > tol_factor |R_00|}; the first
+// s pivoted columns of Y are written to Yout.  One workgroup, Y in LDS.
+template <typename T>
+hipError_t launch_qrcp_trunc(int mh, int c, const T *Y, int64_t ldy, double tol_factor, T *Yout, int64_t ldo,
+                             int *s_out, hipStream_t s);
+bool qrcp_trunc_ok(int mh, int c);
 
 // ------------------------------------------------------------- small SVD
 // From the l x l Gram G = B B^T (double): semidefinite Cholesky G = R^T R,
@@ -105,7 +112,9 @@ struct SmallSvdOut {
 template <typename T>
 hipError_t launch_small_svd(int l, const double *G, double tau, const double *w, int keep, const T *Q,
                             int64_t ldq, int mh, T *QM, int64_t ldqm, T *Qout, int64_t ldqo,
-                            const SmallSvdOut &out, double *work, int fuse_q, hipStream_t s);
+                            const SmallSvdOut &out, double *work, int fuse_q, hipStream_t s, int in_factor = 0);
+// (in_factor: G holds an upper triangular factor C, column-major, with B^T = H C
+//  for some H with orthonormal columns; the Cholesky step is skipped)
 bool small_svd_fuse_q_ok(int mh, int l);
 
 // ------------------------------------------------ rank-l reconstruct family
@@ -170,7 +179,9 @@ hipError_t launch_finite_check(int64_t m, int64_t n, const T *A, int64_t lda, in
 
 // Largest eigenvalue of a symmetric positive semidefinite l x l matrix by the
 // power method (one workgroup); out[0] = lambda_max.
-hipError_t launch_power_eig(int l, const double *G, double *work, double *out, hipStream_t s);
+// Largest eigenvalue of a symmetric PSD n x n matrix (8 <= n <= 1024) by
+// block subspace iteration: out[0] the estimate, out[1] 1 when certified.
+hipError_t launch_power_eig(int n, const double *G, double *out, hipStream_t s);
 
 // --------------------------------------------------------- generic GEMM
 // C(m, n) = sum_k A(m, k) B(k, n) with arbitrary element strides:

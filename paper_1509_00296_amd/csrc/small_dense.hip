@@ -405,6 +405,126 @@ template hipError_t launch_resid_seq<float>(int, const float *, int64_t, int, co
                                             double *, hipStream_t);
 
 // ===========================================================================
+// Rank truncation of a fresh sketch by QR with column pivoting (Alg. 1's
+// QR_CP of the sampled matrix; Sec. 2.1's real sampling rate s = min(l, r)):
+// Householder QR of Y (mh x c) where step j moves the remaining column of
+// largest norm (recomputed from the rows j.. of the reduced matrix) to
+// position j.  s = the number of leading |R_jj| above tol_factor |R_00|;
+// the first s pivoted columns of Y (whose span is that of QR_CP's Q_s) are
+// written to Yout in pivot order, and s to *s_out.  One workgroup, Y in LDS.
+// ===========================================================================
+template <typename T>
+__global__ void __launch_bounds__(256) k_qrcp_trunc(int mh, int c, const T *Y, int64_t ldy, double tol_factor,
+                                                    T *Yout, int64_t ldo, int *s_out)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int mhp = mh | 1;
+    double *W = reinterpret_cast<double *>(smem_raw);   // mh x c, ld mhp
+    __shared__ double cn[64];
+    __shared__ double rdiag[64];
+    __shared__ int perm[64];
+    __shared__ double sh_beta, sh_scale;
+    const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+    for (int idx = tid; idx < mh * c; idx += 256) {
+        const int i = idx % mh, j = idx / mh;
+        W[(size_t)j * mhp + i] = (double)Y[i + (int64_t)j * ldy];
+    }
+    for (int j = tid; j < c; j += 256) perm[j] = j;
+    __syncthreads();
+    const int kmax = mh < c ? mh : c;
+    for (int j = 0; j < kmax; ++j) {
+        // norms of the remaining parts of columns j..c-1
+        for (int col = j + wave; col < c; col += 4) {
+            double s = 0.0;
+            for (int i = j + lane; i < mh; i += kWave) {
+                const double v = W[(size_t)col * mhp + i];
+                s += v * v;
+            }
+            s = wave_sum(s);
+            if (lane == 0) cn[col] = s;
+        }
+        __syncthreads();
+        int best = j;
+        double bn = cn[j];
+        for (int col = j + 1; col < c; ++col)
+            if (cn[col] > bn) {
+                bn = cn[col];
+                best = col;
+            }
+        if (best != j) {
+            for (int i = tid; i < mh; i += 256) {
+                const double t = W[(size_t)j * mhp + i];
+                W[(size_t)j * mhp + i] = W[(size_t)best * mhp + i];
+                W[(size_t)best * mhp + i] = t;
+            }
+            if (tid == 0) {
+                const int t = perm[j];
+                perm[j] = perm[best];
+                perm[best] = t;
+            }
+        }
+        __syncthreads();
+        // Householder reflector of W(j:, j): v = x - alpha e1, alpha = -sign(x0) ||x||
+        if (tid == 0) {
+            const double nrm = sqrt(bn);
+            const double x0 = W[(size_t)j * mhp + j];
+            const double alpha = x0 >= 0.0 ? -nrm : nrm;
+            const double v0 = x0 - alpha;
+            // v scaled so that v0 = 1; beta = -v0 / alpha
+            sh_beta = nrm > 0.0 ? -v0 / alpha : 0.0;
+            sh_scale = (nrm > 0.0 && v0 != 0.0) ? 1.0 / v0 : 0.0;
+            rdiag[j] = nrm > 0.0 ? alpha : 0.0;
+        }
+        __syncthreads();
+        const double beta = sh_beta, scale = sh_scale;
+        for (int i = j + 1 + tid; i < mh; i += 256) W[(size_t)j * mhp + i] *= scale;
+        __syncthreads();
+        // apply (I - beta v v^T) to columns j+1..c-1, v = [1, W(j+1:, j)]
+        for (int col = j + 1 + wave; col < c; col += 4) {
+            double s = lane == 0 ? W[(size_t)col * mhp + j] : 0.0;
+            for (int i = j + 1 + lane; i < mh; i += kWave) s += W[(size_t)j * mhp + i] * W[(size_t)col * mhp + i];
+            s = wave_sum(s);
+            const double f = beta * s;
+            if (lane == 0) W[(size_t)col * mhp + j] -= f;
+            for (int i = j + 1 + lane; i < mh; i += kWave) W[(size_t)col * mhp + i] -= f * W[(size_t)j * mhp + i];
+        }
+        __syncthreads();
+    }
+    __shared__ int s_sh;
+    if (tid == 0) {
+        const double r00 = kmax > 0 ? fabs(rdiag[0]) : 0.0;
+        const double tol = tol_factor * r00;
+        int s = 0;
+        while (s < kmax && fabs(rdiag[s]) > tol) ++s;
+        s_sh = s;
+        *s_out = s;
+    }
+    __syncthreads();
+    const int s = s_sh;
+    for (int idx = tid; idx < mh * s; idx += 256) {
+        const int i = idx % mh, j = idx / mh;
+        Yout[i + (int64_t)j * ldo] = Y[i + (int64_t)perm[j] * ldy];
+    }
+}
+
+bool qrcp_trunc_ok(int mh, int c) { return c >= 1 && c <= 64 && (size_t)(mh | 1) * c * sizeof(double) <= 128 * 1024; }
+
+template <typename T>
+hipError_t launch_qrcp_trunc(int mh, int c, const T *Y, int64_t ldy, double tol_factor, T *Yout, int64_t ldo,
+                             int *s_out, hipStream_t s)
+{
+    if (!qrcp_trunc_ok(mh, c) || ldy < mh || ldo < mh) return hipErrorInvalidValue;
+    const size_t lds = (size_t)(mh | 1) * c * sizeof(double);
+    hipLaunchKernelGGL((k_qrcp_trunc<T>), dim3(1), dim3(256), lds, s, mh, c, Y, ldy, tol_factor, Yout, ldo, s_out);
+    return hipGetLastError();
+}
+template hipError_t launch_qrcp_trunc<double>(int, int, const double *, int64_t, double, double *, int64_t, int *,
+                                              hipStream_t);
+template hipError_t launch_qrcp_trunc<float>(int, int, const float *, int64_t, double, float *, int64_t, int *,
+                                             hipStream_t);
+
+
+// ===========================================================================
 // Small SVD of B from G = B B^T (Alg. 1's QR of A^T Q, polar and eigen steps reformulated):
 //   G = R^T R (semidefinite Cholesky), one-sided Jacobi on M = R^T: M V = W S.
 //   B = R^T H^T has left singular vectors U_B = W S^{-1} (the normalised
@@ -494,7 +614,7 @@ __device__ __forceinline__ void small_svd_body(double *M, double *smem, int l, c
                                                int64_t ldq, int mh, T *QM, int64_t ldqm, T *Qout,
                                                int64_t ldqo, const SmallSvdOut &out, int fuse_q,
                                                int &sh_rot, int &rank, int *order, double *sig,
-                                               double *coef, double *wc)
+                                               double *coef, double *wc, int in_factor)
 {
     const int tid = threadIdx.x;
     const int wave = tid / kWave;
@@ -509,19 +629,31 @@ __device__ __forceinline__ void small_svd_body(double *M, double *smem, int l, c
 
     // Row-major in-place semidefinite Cholesky: M[j*l + k] = R(j, k), k >= j.
     // Read column-major, column j of M is row j of R, i.e. M = R^T.
-    for (int idx = tid; idx < l * l; idx += NT) M[idx] = Gin[idx];
-    __syncthreads();
     int sweeps = 0;
     // column stride of M after the factorisation: l, or for 16 < l <= 128
     // (M in LDS) the Jacobi groups' row capacity 32, 64, 96, 112 or 128, the rows past
     // l held at zero
     const int ldm = (l > LM && l <= 128) ? svd_row_capacity(l) : l;
+    if (in_factor) {
+        // the input is already an upper triangular factor C with B^T = H C
+        // (column-major): M takes it in the factorisation's layout and the
+        // Cholesky step is skipped
+        const int ldf = (NT >= 256 && l <= LM) ? l : ldm;
+        for (int idx = tid; idx < l * ldf; idx += NT) {
+            const int j = idx / ldf, k = idx % ldf;
+            M[idx] = (k >= j && k < l) ? Gin[j + (size_t)k * l] : 0.0;
+        }
+        __syncthreads();
+    } else {
+        for (int idx = tid; idx < l * l; idx += NT) M[idx] = Gin[idx];
+        __syncthreads();
+    }
     if (NT >= 256 && l <= LM) {
         // wavefront 0 alone: register Cholesky, then the Jacobi
         if (wave == 0) {
             double maxdiag = 0.0;
             for (int j = 0; j < l; ++j) maxdiag = fmax(maxdiag, M[j * l + j]);
-            wave_chol16<LM>(M, l, 0.0, 4.0 * l * kU * maxdiag, M, nullptr, false);
+            if (!in_factor) wave_chol16<LM>(M, l, 0.0, 4.0 * l * kU * maxdiag, M, nullptr, false);
             wave_sync();
             sweeps = jacobi_wave16(M, l, 60);
         }
@@ -534,7 +666,8 @@ __device__ __forceinline__ void small_svd_body(double *M, double *smem, int l, c
         if (l <= 128) {
             // sig and coef serve as the step buffers here; R comes back with
             // row stride ldm (zeros past column l - 1)
-            chol_blk4<NT>(M, l, ptol, 0.0, coef, sig, nullptr, ldm);
+            if (!in_factor) chol_blk4<NT>(M, l, ptol, 0.0, coef, sig, nullptr, ldm);
+            __syncthreads();
             if (ldm == 32) sweeps = jacobi_groups<NT, 16, 2, true>(M, l, ldm, l, 60, &sh_rot);
             else if (ldm == 64) sweeps = jacobi_groups<NT, 16, 4, true>(M, l, ldm, l, 60, &sh_rot);
             else if (ldm == 96) sweeps = jacobi_groups<NT, 16, 6, true>(M, l, ldm, l, 60, &sh_rot);
@@ -543,7 +676,7 @@ __device__ __forceinline__ void small_svd_body(double *M, double *smem, int l, c
         } else {
             // right-looking in place: row j of R is scaled, then the trailing
             // upper triangle takes its rank-one update
-            for (int j = 0; j < l; ++j) {
+            for (int j = 0; j < l && !in_factor; ++j) {
                 const double d = M[j * l + j];
                 const double piv = d > ptol ? sqrt(d) : 0.0;
                 const double inv = piv > 0.0 ? 1.0 / piv : 0.0;
@@ -706,7 +839,7 @@ template <typename T, int NT, int LM>
 __global__ void __launch_bounds__(NT) k_small_svd(int l, const double *Gin, double tau, int keep,
                                                   const double *w, const T *Q, int64_t ldq, int mh,
                                                   T *QM, int64_t ldqm, T *Qout, int64_t ldqo,
-                                                  SmallSvdOut out, double *work, int fuse_q)
+                                                  SmallSvdOut out, double *work, int fuse_q, int in_factor)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int sh_rot, rank;
@@ -716,16 +849,16 @@ __global__ void __launch_bounds__(NT) k_small_svd(int l, const double *Gin, doub
     double *smem = reinterpret_cast<double *>(smem_raw);
     if (l <= 128)
         small_svd_body<T, NT, LM>(smem, smem, l, Gin, tau, w, keep, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, fuse_q,
-                              sh_rot, rank, order, sig, coef, wc);
+                              sh_rot, rank, order, sig, coef, wc, in_factor);
     else
         small_svd_body<T, NT, LM>(work, smem, l, Gin, tau, w, keep, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, fuse_q,
-                              sh_rot, rank, order, sig, coef, wc);
+                              sh_rot, rank, order, sig, coef, wc, in_factor);
 }
 
 template <typename T>
 hipError_t launch_small_svd(int l, const double *G, double tau, const double *w, int keep, const T *Q,
                             int64_t ldq, int mh, T *QM, int64_t ldqm, T *Qout, int64_t ldqo,
-                            const SmallSvdOut &out, double *work, int fuse_q, hipStream_t s)
+                            const SmallSvdOut &out, double *work, int fuse_q, hipStream_t s, int in_factor)
 {
     if (l < 1 || l > 1024) return hipErrorInvalidValue;
     // M in LDS up to l = 128, columns padded to svd_row_capacity(l) rows past l = LM
@@ -734,14 +867,14 @@ hipError_t launch_small_svd(int l, const double *G, double tau, const double *w,
     size_t lds = l <= 128 ? (size_t)l * std::max(l, ldm) * sizeof(double) : 0;
     if (fuse_q && Q) lds = std::max(lds, 2 * (size_t)l * l * sizeof(double));
     if (l <= 8)
-        hipLaunchKernelGGL((k_small_svd<T, 256, 8>), dim3(1), dim3(256), lds, s, l, G, tau, keep, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, work, fuse_q);
+        hipLaunchKernelGGL((k_small_svd<T, 256, 8>), dim3(1), dim3(256), lds, s, l, G, tau, keep, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, work, fuse_q, in_factor);
     else if (l <= 32)
-        hipLaunchKernelGGL((k_small_svd<T, 256, 16>), dim3(1), dim3(256), lds, s, l, G, tau, keep, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, work, fuse_q);
+        hipLaunchKernelGGL((k_small_svd<T, 256, 16>), dim3(1), dim3(256), lds, s, l, G, tau, keep, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, work, fuse_q, in_factor);
     else
-        hipLaunchKernelGGL((k_small_svd<T, 1024, 16>), dim3(1), dim3(1024), lds, s, l, G, tau, keep, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, work, fuse_q);
+        hipLaunchKernelGGL((k_small_svd<T, 1024, 16>), dim3(1), dim3(1024), lds, s, l, G, tau, keep, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, work, fuse_q, in_factor);
     return hipGetLastError();
 }
-template hipError_t launch_small_svd<double>(int, const double *, double, const double *, int, const double *, int64_t, int, double *, int64_t, double *, int64_t, const SmallSvdOut &, double *, int, hipStream_t);
-template hipError_t launch_small_svd<float>(int, const double *, double, const double *, int, const float *, int64_t, int, float *, int64_t, float *, int64_t, const SmallSvdOut &, double *, int, hipStream_t);
+template hipError_t launch_small_svd<double>(int, const double *, double, const double *, int, const double *, int64_t, int, double *, int64_t, double *, int64_t, const SmallSvdOut &, double *, int, hipStream_t, int);
+template hipError_t launch_small_svd<float>(int, const double *, double, const double *, int, const float *, int64_t, int, float *, int64_t, float *, int64_t, const SmallSvdOut &, double *, int, hipStream_t, int);
 
 }  // namespace frk

@@ -107,6 +107,17 @@ __global__ void __launch_bounds__(kWB, 2) k_wsvt_batched(WsvtBatchArgs a)
         if (qi >= a.count) break;
         const int j = a.order ? a.order[qi] : (int)qi;
         const int m = a.rows[j], n = a.cols[j];
+        if (m < 1 || n < 1 || m > kWMaxLong || n > kWMaxLong || min(m, n) > kWMaxShort) {
+            // shapes are read on the device at every launch: one outside the
+            // bounds (e.g. rewritten after the graph was captured) is skipped
+            // and reported instead of overrunning the local memory
+            if (tid == 0) {
+                atomicOr(a.queue + 1, 1);
+                if (a.ranks) a.ranks[j] = -1;
+            }
+            __syncthreads();
+            continue;
+        }
         const int64_t off = a.offsets[j];
         const float *Aj = a.A + off;
         const bool tall = n <= m;
@@ -210,9 +221,14 @@ __global__ void __launch_bounds__(kWB, 2) k_wsvt_batched(WsvtBatchArgs a)
     }
 }
 
+// q[0]: the work counter; q[1]: set when a matrix's shape is outside the
+// bounds the kernel's local memory holds (that matrix is skipped)
 __global__ void k_queue_reset(int *q)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) q[0] = 0;
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        q[0] = 0;
+        q[1] = 0;
+    }
 }
 
 hipError_t launch_wsvt_batched(const WsvtBatchArgs &a, int grid, hipStream_t s)

@@ -102,3 +102,38 @@ def test_batched_wsvt_full_workload(fr, orc):
     _say(f"8192 groups: worst relative error {worst:.2e}, rank mismatches {bad}, "
          f"mean rank {r.mean():.2f}")
     assert worst <= 2e-5 and bad == 0
+
+
+def test_batched_wsvt_replay_rejects_rewritten_shape(fr, orc):
+    """A replay reads the shapes anew: a shape rewritten in place to a value
+    outside the kernel's bounds is skipped on the device (rank -1) and the
+    call returns an error instead of overrunning local memory; the other
+    matrices are still right, and restoring the shape restores the result."""
+    _say("case batched wsvt replay with a rewritten shape")
+    rng = np.random.default_rng(41)
+    mats = [rng.standard_normal((int(rng.integers(30, 100)), int(rng.integers(20, 90)))) for _ in range(40)]
+    rows, cols, offs, packed = _pack(mats)
+    t = lambda a: torch.from_numpy(a).cuda()
+    R, C, Of, P = t(rows), t(cols), t(offs), t(packed)
+    X = torch.empty_like(P)
+    rk = torch.empty(len(mats), dtype=torch.int32, device="cuda")
+    fr.wsvt_batched(R, C, Of, P, X_packed=X, ranks=rk)          # captures the graph
+    fr.wsvt_batched(R, C, Of, P, X_packed=X, ranks=rk)          # replays it
+    torch.cuda.synchronize()
+    X0 = X.cpu().numpy().copy()
+    R[3] = 200                                                   # beyond the bound of 128 rows
+    with pytest.raises(fr.FRSVTError):
+        fr.wsvt_batched(R, C, Of, P, X_packed=X, ranks=rk)
+    torch.cuda.synchronize()
+    assert int(rk[3]) == -1
+    others = [j for j in range(len(mats)) if j != 3]
+    Xr = X.cpu().numpy()
+    for j in others:
+        o, n = int(offs[j]), int(rows[j]) * int(cols[j])
+        assert np.array_equal(Xr[o:o + n], X0[o:o + n])
+    R[3] = int(rows[3])
+    fr.wsvt_batched(R, C, Of, P, X_packed=X, ranks=rk)
+    torch.cuda.synchronize()
+    assert np.array_equal(X.cpu().numpy(), X0)
+    worst, bad_rank = _compare(orc, rows, cols, offs, packed, X0, rk.cpu().numpy())
+    assert worst <= 2e-5 and bad_rank == 0

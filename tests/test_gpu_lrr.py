@@ -1,11 +1,23 @@
 """Low-rank representation (Type A of Table 6) on the GPU against the oracle:
-the same iteration count and final rank, Z and E within 1e-8.  The tolerance
-is looser than the single-call 1e-10: the GPU applies (I + X^T X)^{-1} formed
-once by Newton-Schulz iterations where the oracle solves with a Cholesky
-factor each time, and some 150-300 iterations carry that rounding
-difference forward (each step is a contraction, so it does not grow).
-The final J-step rank is compared up to singular values at rounding level;
-on corrupted data Z and E are compared at 1e-7 for the reason given below."""
+the same iteration count and final rank, Z and E within 1e-10 (clean data,
+both J-step modes; corrupted data with FRSVT in the J step, the method of
+the paper).
+
+One case keeps a looser bar, for a reason that lies in the exact-SVT
+comparator, not in the LRR loop: the library's exact SVT takes the singular
+values from the Gram matrix A A^T (Cholesky, then one-sided Jacobi on the
+factor), which resolves them down to about sqrt(4 l u) sigma_1 (1.5e-7
+sigma_1 at l = 60; smaller pivots of the semidefinite Cholesky are zero).
+On corrupted data the late J inputs of the exact loop hold a singular value
+between the threshold 1/mu (down to 1e-10) and that resolution: the oracle's
+Jacobi SVD of the matrix itself keeps it (final rank 14), the Gram route
+drops it (13), and Z moves by about its size (measured 2.1e-8), hence 1e-7
+there.  The FRSVT J step meets the same data at 4.9e-12 (its small SVD
+works on the l x l core, whose spectrum stays above the resolution).
+Measured (GPU vs oracle, relative Frobenius): clean 1.4e-14 (exact) and
+2.6e-14 (FRSVT); corrupted 4.9e-12 (FRSVT).  The LRR loop itself is well
+conditioned: the oracle's own Z moves by 1e-14 (clean) and 2e-12
+(corrupted) under a 1e-15 relative perturbation of X."""
 import numpy as np
 import pytest
 
@@ -62,11 +74,8 @@ def test_lrr_matches_oracle(fr, orc, mode, corrupt):
     assert res.iters == out["iters"]
     Zg = res.Z.cpu().numpy()
     Eg = res.E.cpu().numpy()
-    # Clean data: J's spectrum has a wide gap at the threshold and the runs
-    # agree to 1e-8.  Corrupted data: the late J inputs keep singular values
-    # at the 1e-8 scale of the stopping tolerance, which rounding puts either
-    # side of 1/mu; each such flip moves Z by about that much, hence 1e-7.
-    tol = 1e-7 if corrupt else 1e-8
+    # the exact-SVT comparator on corrupted data: see the module docstring
+    tol = 1e-7 if (corrupt and mode == "exact") else 1e-10
     assert _rel(Zg, out["Z"]) <= tol
     assert _rel(Eg, out["E"]) <= tol or np.abs(out["E"]).max() < 1e-12
     # the GPU's own result meets the equality constraint X = XZ + E to the
@@ -97,8 +106,8 @@ def test_lrr_iteration_limit(fr, orc):
     out = orc.lrr_ialm(X, 0.1, mode="frsvt", p=5, q=1, seed=3, max_iter=200)
     assert not res.converged and not out["converged"] and res.iters == out["iters"] == 200
     assert res.rank == out["ranks"][-1] == 11
-    assert _rel(res.Z.cpu().numpy(), out["Z"]) <= 1e-8
-    assert _rel(res.E.cpu().numpy(), out["E"]) <= 1e-8
+    assert _rel(res.Z.cpu().numpy(), out["Z"]) <= 1e-10
+    assert _rel(res.E.cpu().numpy(), out["E"]) <= 1e-10
 
 
 def test_lrr_zero_data(fr):
@@ -108,3 +117,35 @@ def test_lrr_zero_data(fr):
     res = fr.lrr_ialm(X, 0.1)
     assert res.converged and res.iters == 1 and res.rank == 0
     assert float(res.Z.abs().max()) == 0.0 and float(res.E.abs().max()) == 0.0
+
+
+def test_lrr_full_workload_matches_oracle_summary(fr):
+    """The 2016 x 640 workload bench.py times (10 nine-dimensional subspaces,
+    64 corrupted columns, lambda = 0.1, FRSVT J step, p = 5, q = 1, seed 11)
+    against the oracle's full run, stored as a summary by
+    tests/golden/make_lrr_golden.py (the oracle takes minutes): the same
+    iteration count and rank sequence, the Frobenius norms and the top 100
+    singular values of Z within 1e-10, and 400 fixed entries of Z and of E
+    within 1e-10 of the respective Frobenius norm."""
+    import json
+    import os
+    from paper_1509_00296_amd import synth
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "lrr_2016x640_seed0.json")
+    g = json.load(open(path))
+    _say("case lrr 2016x640 full workload")
+    X, _, _ = synth.subspaces(seed=0)
+    res = fr.lrr_ialm(torch.from_numpy(X).cuda(), 0.1, use_frsvt=True, p=5, q=1, seed=11)
+    assert res.converged == g["converged"] and res.iters == g["iters"]
+    assert res.rank == g["ranks"][-1]
+    Z = res.Z.cpu().numpy()
+    E = res.E.cpu().numpy()
+    assert abs(np.linalg.norm(Z) - g["Z_fro"]) <= 1e-10 * g["Z_fro"]
+    assert abs(np.linalg.norm(E) - g["E_fro"]) <= 1e-10 * g["E_fro"]
+    sz = np.linalg.svd(Z, compute_uv=False)[:100]
+    so = np.array(g["Z_sigma_top100"])
+    assert np.abs(sz - so).max() <= 1e-10 * so[0]
+    dz = max(abs(Z[i, j] - v) for i, j, v in g["Z_samples"])
+    de = max(abs(E[i, j] - v) for i, j, v in g["E_samples"])
+    _say(f"  max sample deviation Z {dz:.2e}, E {de:.2e}")
+    assert dz <= 1e-10 * g["Z_fro"]
+    assert de <= 1e-10 * g["E_fro"]

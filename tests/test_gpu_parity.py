@@ -347,3 +347,59 @@ def test_rpca_residual_check_matches_oracle(fr, orc, m, n, frac, ap):
     assert _rel(res.L.cpu().numpy(), out["L"]) <= 1e-10
     assert _rel(res.S.cpu().numpy(), out["S"]) <= 1e-10
     assert res.converged
+
+
+@pytest.mark.parametrize("m,n,q,noise", [(300, 500, 2, 0.0), (500, 300, 1, 0.0), (400, 120, 0, 0.0),
+                                         (300, 500, 1, 0.01)])
+def test_frsvt_qrcp_truncation_matches_oracle(fr, orc, m, n, q, noise):
+    """Alg. 1's QR_CP of the fresh sketch (handle option): on an exactly
+    rank-6 input with l = 15 the sketch is cut to the oracle's s = 6 samples
+    (its QR_CP basis), on a noisy input nothing is dropped; X within 1e-10
+    of the oracle, equal ranks, the same propagated subspace."""
+    from paper_1509_00296_amd import synth
+    _say(f"case frsvt qrcp truncation {m}x{n} q={q} noise={noise}")
+    A = synth.single_svt(seed=m + n + q, m=m, n=n, rank=6, noise_std=noise)
+    tau, k, p, seed = 12.0, 10, 5, 404
+    fr.set_option(fr.OPT_QRCP_TRUNCATE, 1)
+    try:
+        X, Qt, r = fr.frsvt(_gpu(A), tau, k, p, q, seed=seed, counter=2)
+        s_gpu = fr.last_info()[3]
+    finally:
+        fr.set_option(fr.OPT_QRCP_TRUNCATE, 0)
+    Om = orc.gaussian_matrix(seed, 2, max(m, n), k + p)
+    Xo, Qo, ro, _, so = orc.frsvt(A, tau, q, Om)
+    assert s_gpu == so == (6 if noise == 0.0 else 15)
+    assert r == ro
+    assert _rel(X.cpu().numpy(), Xo) <= 1e-10
+    Qg = Qt.cpu().numpy()
+    assert np.abs(Qg @ Qg.T - Qo @ Qo.T).max() <= 1e-10
+    # without the option the same call keeps all 15 samples and the same X
+    X2, _, r2 = fr.frsvt(_gpu(A), tau, k, p, q, seed=seed, counter=2)
+    assert fr.last_info()[3] == 15 and r2 == r
+    assert _rel(X2.cpu().numpy(), Xo) <= 1e-10
+
+
+@pytest.mark.parametrize("delta", [0.0, 1e-8, 1e-5])
+def test_rpca_spectral_norm_with_close_top_pair(fr, orc, delta):
+    """||O||_2 (it sets mu0 = 1.25/||O||_2 and so every iterate) when the two
+    largest singular values of O are equal or nearly equal: the observation
+    of a 1500 x 80 RPCA problem is edited so that sigma_2 = (1 - delta)
+    sigma_1.  The library's block subspace iteration must give sigma_1 to
+    1e-14 (a single-vector power method stalls at such a pair), and the whole
+    solve must match the oracle (which takes sigma_1 from its Jacobi SVD)."""
+    from paper_1509_00296_amd import synth
+    _say(f"case rpca close top pair delta={delta}")
+    O0, _, _ = synth.rpca(seed=21, m=1500, n=80, rank=4, frac=0.02)
+    U, s, Vt = np.linalg.svd(O0, full_matrices=False)
+    s2 = s.copy()
+    s2[1] = s[0] * (1.0 - delta)
+    O = np.asfortranarray((U * s2) @ Vt)
+    sig1 = np.linalg.svd(O, compute_uv=False)[0]
+    lam = 1.0 / np.sqrt(1500)
+    res = fr.rpca_ialm(_gpu(O), lam, use_frsvt=True, seed=5)
+    assert abs(res.norm2 - sig1) <= 1e-14 * sig1
+    out = orc.rpca_ialm(O, lam, mode="frsvt", p=5, q=1, seed=5)
+    assert res.iters == out["iters"]
+    assert res.ranks == list(out["ranks"][:64])
+    assert _rel(res.L.cpu().numpy(), out["L"]) <= 1e-10
+    assert _rel(res.S.cpu().numpy(), out["S"]) <= 1e-10

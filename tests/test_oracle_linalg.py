@@ -99,3 +99,22 @@ def test_svd_zero_and_deficient_complete_bases(orc):
     assert np.all(S == 0)
     assert np.abs(U.T @ U - np.eye(4)).max() < 1e-15
     assert np.abs(V.T @ V - np.eye(4)).max() < 1e-15
+
+
+def test_openmp_build_matches_plain_build(orc):
+    """The all-core CPU baseline runs the oracle's source built with -fopenmp:
+    its parallel loops split independent output columns, so every value is
+    computed in the same order and the results equal the plain build's."""
+    import math
+    from paper_1509_00296_amd import synth
+    O, _, _ = synth.rpca(seed=4, m=2000, n=60, rank=3, frac=0.1)
+    lam = 1.0 / math.sqrt(2000)
+    a = orc.rpca_ialm(O, lam, mode="frsvt", max_iter=4, seed=5)
+    A = np.asfortranarray(np.random.default_rng(2).standard_normal((300, 120)))
+    Xa, ra = orc.svt(A, 3.0)
+    with orc.use_library(orc.build_openmp()):
+        assert orc.threads() >= 1
+        b = orc.rpca_ialm(O, lam, mode="frsvt", max_iter=4, seed=5)
+        Xb, rb = orc.svt(A, 3.0)
+    assert np.array_equal(a["L"], b["L"]) and np.array_equal(a["S"], b["S"])
+    assert ra == rb and np.array_equal(Xa, Xb)
