@@ -51,6 +51,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6       # MI355X FP64 (vector and matrix cores), dense
 M, N, RANK, FRAC = 76800, 200, 3, 0.10
 N_CLASSES = 13
 EXACT_COMPARATORS = True    # the further workloads' exact-SVT loops (off with --exact-steps 0)
@@ -322,10 +323,28 @@ def wl_batched(torch, fr, synth, tracer):
     torch.cuda.synchronize()
     kern = tracer.stop()
     elems = int(packed.size)
+    # FP64 work of one batch: the Gram's upper half (s (s + 1) L), the
+    # Cholesky (s^3 / 3), the Jacobi sweeps as counted on the device (6 column
+    # lengths per examined pair, 6 more per rotation; angles and tests not
+    # counted) and the rank-r reconstruction (Z = A m_c: 2 L s r, X += coef Z
+    # m_c^T: 3 L s r)
+    import numpy as np
+    pair_rows, rot_rows, nrot = fr.wsvt_work()
+    s_ = np.minimum(rows, cols).astype(np.float64)
+    L_ = np.maximum(rows, cols).astype(np.float64)
+    r_ = rk.cpu().numpy().astype(np.float64)
+    fl = {"gram": float(np.sum(s_ * (s_ + 1) * L_)), "cholesky": float(np.sum(s_ ** 3) / 3.0),
+          "jacobi": 6.0 * (pair_rows + rot_rows), "reconstruction": float(np.sum(5.0 * L_ * s_ * r_))}
+    tot = sum(fl.values())
+    fp64 = {"flops_per_batch": {k: round(v, 0) for k, v in fl.items()},
+            "jacobi_rotations": int(nrot), "jacobi_pairs_examined_rows": int(pair_rows),
+            "achieved_TFLOPs": round(tot / sec / 1e12, 4),
+            "peak_TFLOPs_fp64": PEAK_FP64_TFLOPS, "frac": round(tot / sec / 1e12 / PEAK_FP64_TFLOPS, 5),
+            "jacobi_share_of_flops": round(fl["jacobi"] / tot, 4)}
     return {"workload": "wsvt_batched_8192_patch_groups", "metric": "matrices/s",
             "value": round(8192 / sec, 1), "unit": "matrices/s", "ms_per_batch": round(1e3 * sec, 4),
             "hbm_GBs": round(2 * 4 * elems / sec / 1e9, 1), "tuned_group_size": fr.wsvt_tuning(),
-            "mean_rank": float(rk.double().mean()),
+            "mean_rank": float(rk.double().mean()), "fp64_counted": fp64,
             "config": {"count": 8192, "rows": [49, 64, 81, 100], "cols": [30, 90], "rank": 4,
                        "noise_std": 0.1, "c": 2.8},
             "kernels": _r(kern)}

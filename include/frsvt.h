@@ -426,6 +426,15 @@ FRSVT_API int wsvt_batched(frsvt_handle handle, int64_t count, const int32_t *ro
  * batched call. */
 FRSVT_API int frsvt_wsvt_tuning(frsvt_handle handle, int32_t group_size[3]);
 
+/* The one-sided Jacobi work of the last wsvt_batched call on this handle
+ * (waits for the handle's stream): work[0] = sum over examined pairs of the
+ * column length, work[1] = the same sum over applied rotations, work[2] =
+ * the number of applied rotations.  Each examined pair costs 6 column
+ * lengths of floating-point operations (three inner products), each
+ * rotation 6 more (the update) plus its angle.  Zeros before the first
+ * batched call. */
+FRSVT_API int frsvt_wsvt_work(frsvt_handle handle, int64_t work[3]);
+
 /* ---------------------------------------------------------- RPCA host */
 
 typedef struct {

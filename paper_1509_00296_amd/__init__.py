@@ -139,6 +139,7 @@ def library(path: str | None = None) -> ctypes.CDLL:
     lib.rpca_init.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _i64, _dbl, _dbl, _vp, _i64, _vp,
                               _i64, ctypes.POINTER(_dbl)]
     lib.frsvt_wsvt_tuning.argtypes = [_vp, _vp]
+    lib.frsvt_wsvt_work.argtypes = [_vp, _vp]
     lib.frsvt_last_info.argtypes = [_vp, ctypes.POINTER(_i32), ctypes.c_int]
     lib.frsvt_trace_enable.argtypes = [_vp, ctypes.c_int]
     lib.frsvt_trace_read.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(_dbl), ctypes.POINTER(_i64)]
@@ -312,6 +313,15 @@ def wsvt_tuning() -> list:
     g = (_i32 * 3)()
     h.lib.frsvt_wsvt_tuning(h.ptr, g)
     return list(g)
+
+
+def wsvt_work() -> list:
+    """Jacobi work of the last batched WSVT call: [sum of the column length
+    over examined pairs, the same over applied rotations, rotations]."""
+    h = handle()
+    w = (ctypes.c_int64 * 3)()
+    _check(h, h.lib.frsvt_wsvt_work(h.ptr, w), "frsvt_wsvt_work")
+    return list(w)
 
 
 def frsvt(A, tau: float, k: int, p: int, q: int, Q_prev=None, *, seed: int = 0,

@@ -267,6 +267,7 @@ struct Core {
     T *Qout;             // mh x l (ld ldqo); may alias Qt
     int64_t ldqo;
     bool sketch_ready;   // the sketch of this call is already in the buffers
+    bool orth_ready = false;  // its orthonormalised basis [Qt, Y] too (b.Q, one-workgroup path)
     // results (workspace)
     int l;
     T *Q, *Bt, *QM;
@@ -539,8 +540,9 @@ int run_core(frsvt_context *h, Core<T> &c, CoreBuffers<T> &b)
     // Alg. 1, sketch and initial basis (fresh or range-propagated)
     if (small) {
         if (!c.sketch_ready && (rc = sketch_stage<T>(h, c, b))) return rc;
-        CKT(FRSVT_K_ORTH, launch_small_orth<T>(mh, c.Qt, c.ldqt, c.rp, c.ysrc ? c.ysrc : b.Y, mh, c.cnew, b.Q, mh,
-                                c.seed, c.counter, oflags, c.resid_out, s));
+        if (!c.orth_ready)
+            CKT(FRSVT_K_ORTH, launch_small_orth<T>(mh, c.Qt, c.ldqt, c.rp, c.ysrc ? c.ysrc : b.Y, mh, c.cnew, b.Q,
+                                                   mh, c.seed, c.counter, oflags, c.resid_out, s));
     } else {
         if (c.rp > 0)
             CK(hipMemcpy2DAsync(b.Q, mh * sizeof(T), c.Qt, c.ldqt * sizeof(T), mh * sizeof(T),
@@ -1126,17 +1128,25 @@ int spectral_norm(frsvt_context *h, const T *A, int64_t lda, const Orient &o, do
     // mhat < 8) the full small SVD of G (Cholesky + one-sided Jacobi)
     const int mh = o.mh;
     const int sk = gemm_splitk(mh, mh, o.nh, h->num_cu);
+    // the transposed orientation with mh <= 256 takes the dedicated Gram
+    // kernel (one pass over A, upper blocks only)
+    const bool gtr = o.trans && gram_tr_ok(mh, o.nh, lda, (int)sizeof(T));
+    const size_t gpn = gtr ? gram_tr_part_doubles(mh, h->num_cu) + gram_tr_part_doubles(mh, 1)
+                           : (size_t)sk * mh * mh;
     Carver dry(nullptr);
     dry.take<double>((size_t)mh * mh);
-    dry.take<double>((size_t)sk * mh * mh);
+    dry.take<double>(gpn);
     dry.take<double>((size_t)mh * mh * 3 + mh);
     int rc = ensure_ws(h, dry.off);
     if (rc) return rc;
     Carver cv(h->ws);
     double *G = cv.take<double>((size_t)mh * mh);
-    double *gp = cv.take<double>((size_t)sk * mh * mh);
+    double *gp = cv.take<double>(gpn);
     double *sv = cv.take<double>((size_t)mh * mh * 3 + mh);
-    if (std::is_same<T, double>::value) {
+    if (gtr) {
+        CKT(FRSVT_K_GEMM, launch_gram_tr<T>(A, lda, mh, o.nh, h->num_cu, gp,
+                                            gp + gram_tr_part_doubles(mh, h->num_cu), G, h->stream));
+    } else if (std::is_same<T, double>::value) {
         // on the matrix cores (each operand has a unit stride)
         CKT(FRSVT_K_GEMM, launch_gemm_f64_mfma(mh, mh, o.nh, (const double *)A, o.si, o.sk, (const double *)A,
                                                o.sk, o.si, G, 1, mh, sk, gp, h->stream));
@@ -1147,7 +1157,15 @@ int spectral_norm(frsvt_context *h, const T *A, int64_t lda, const Orient &o, do
     }
     double lam = 0.0;
     bool ok = false;
-    if (mh >= 8) {
+    if (mh <= 256) {
+        // a dominant top eigenvalue is certified by a few single-vector steps
+        CKT(FRSVT_K_OTHER, launch_power_dom(mh, G, h->dscalars, h->stream));
+        CK(hipMemcpyAsync(h->pinned, h->dscalars, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        CK(hipStreamSynchronize(h->stream));
+        lam = ((double *)h->pinned)[0];
+        ok = ((double *)h->pinned)[1] > 0.5;
+    }
+    if (!ok && mh >= 8) {
         CKT(FRSVT_K_OTHER, launch_power_eig(mh, G, h->dscalars, h->stream));
         CK(hipMemcpyAsync(h->pinned, h->dscalars, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
         CK(hipStreamSynchronize(h->stream));
@@ -1241,6 +1259,9 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
     auto t0 = std::chrono::steady_clock::now();
     int r_prev = -1, l_prev = 0;
     int spec_cnew = 0;
+    // the next iteration's orthonormalisation enqueued before this
+    // iteration's rank is read, for the rank of the previous one (-1: none)
+    int spec_orth_rp = -1, spec_orth_cnew = 0;
     // semi-online: the caller's basis is the first call's propagated basis
     if (op.use_frsvt && op.r_init > 0) {
         if (op.r_init > mh) return -8;
@@ -1325,6 +1346,8 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
             if (stats && it < 64) stats->widths[it] = l_prev;
             // (the first c.cnew columns of a wider draw are the narrower draw)
             c.sketch_ready = checked || (spec_cnew > 0 && spec_cnew == c.cnew && core_small<T>(c, c.rp + c.cnew));
+            c.orth_ready = !checked && c.sketch_ready && spec_orth_rp > 0 && spec_orth_rp == c.rp &&
+                           spec_orth_cnew == c.cnew;
             c.Qout = Qt;
             c.ldqo = mh;
             c.status = h->dstatus;
@@ -1421,6 +1444,24 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
         } else if (next_sketch) {
             if ((rc = sketch_stage<T>(h, cn, b))) return rc;
             spec_cnew = cn.cnew;
+        }
+        // and, for the rank of this iteration's own propagated basis (the
+        // common case once the rank has settled), the next iteration's
+        // orthonormalisation of [Qt, Y]; it is used only if the rank read
+        // below matches (b.Q is free: this iteration is done with it)
+        spec_orth_rp = -1;
+        if (spec_cnew > 0 && !op.ap && !op.resid_check && r_prev > 0 &&
+            spec_cnew == std::max(0, std::min(op.p, mh - r_prev))) {
+            Core<T> cs = c;
+            cs.rp = r_prev;
+            cs.cnew = spec_cnew;
+            if (core_small<T>(cs, r_prev + spec_cnew)) {
+                CKT(FRSVT_K_ORTH, launch_small_orth<T>(mh, Qt, mh, r_prev, b.Y, mh, spec_cnew, b.Q, mh, op.seed,
+                                                       (uint64_t)(it + 1), h->dstatus + 4,
+                                                       reinterpret_cast<double *>(h->dstatus + kResidSlot), s));
+                spec_orth_rp = r_prev;
+                spec_orth_cnew = spec_cnew;
+            }
         }
         CK(hipEventSynchronize(h->ev_iter));
         const int r = hst[0];
@@ -1606,6 +1647,7 @@ int wsvt_batched_impl(frsvt_context *h, int64_t count, const int32_t *rows, cons
     a.sweeps = nullptr;
     a.order = h->wb_order;
     a.queue = h->wb_queue;
+    a.work = reinterpret_cast<unsigned long long *>(h->wb_queue + 16);
     a.group_size = h->wb_gs_dev;
 
     if (!h->wb_tuned) {
@@ -2568,6 +2610,20 @@ int frsvt_wsvt_tuning(frsvt_handle h, int32_t group_size[3])
     if (!h) return -1;
     if (!group_size) return -2;
     for (int b = 0; b < 3; ++b) group_size[b] = h->wb_tuned ? h->wb_gs[b] : 0;
+    return FRSVT_OK;
+}
+
+int frsvt_wsvt_work(frsvt_handle h, int64_t work[3])
+{
+    if (!h) return -1;
+    if (!work) return -2;
+    for (int b = 0; b < 3; ++b) work[b] = 0;
+    if (!h->wb_queue) return FRSVT_OK;
+    CK(hipSetDevice(h->device));
+    CK(hipMemcpyAsync(h->pinned, h->wb_queue + 16, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                      h->stream));
+    CK(hipStreamSynchronize(h->stream));
+    for (int b = 0; b < 3; ++b) work[b] = (int64_t)((const unsigned long long *)h->pinned)[b];
     return FRSVT_OK;
 }
 

@@ -207,6 +207,65 @@ __device__ __forceinline__ CholInfo wave_chol16(const double *G, int l, double s
     return info;
 }
 
+// 1/sqrt(x) for x > 0: the lean form where x is normal, the library's
+// below (a denormal x).
+__device__ __forceinline__ double rsqrt_pos(double x) { return x >= 1e-300 ? rsqrt_nr(x) : rsqrt(x); }
+
+// Cholesky of the upper triangle of g (l <= N), done by the calling thread on
+// its own copy in registers: every thread that calls it with the same g gets
+// the same R, so a workgroup needs no broadcast of the factor.  Row j of R
+// overwrites row j of g (entries past column l - 1 set to zero); pivots <=
+// null_tol are numerically null: R_jj = null_piv and a zero row.  min_ratio
+// is 0 when a non-null pivot fell below ratio_tol times its original
+// diagonal entry, else 1 (a comparison, no division).
+// rinv (optional) receives 1 / R_jj from the same reciprocal square root
+// (0 for a null pivot).
+template <int N>
+__device__ __forceinline__ CholInfo reg_chol(double (&g)[N][N], int l, double null_tol, double null_piv,
+                                             double ratio_tol = 0.0, double *rinv = nullptr)
+{
+    CholInfo info{0, 1.0};
+    double od[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) od[j] = g[j][j];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        if (j < l) {
+            const double d = g[j][j];
+            const bool isnull = !(d > null_tol);
+            const double rs = rsqrt_pos(isnull ? 1.0 : d);
+            if (isnull) ++info.nnull;
+            else if (d < ratio_tol * od[j]) info.min_ratio = 0.0;
+            g[j][j] = isnull ? null_piv : d * rs;
+            const double inv = isnull ? 0.0 : rs;
+            if (rinv) rinv[j] = inv;
+#pragma unroll
+            for (int k = j + 1; k < N; ++k) g[j][k] = k < l ? g[j][k] * inv : 0.0;
+#pragma unroll
+            for (int i = j + 1; i < N; ++i)
+#pragma unroll
+                for (int k = i; k < N; ++k) g[i][k] -= g[j][i] * g[j][k];
+        }
+    }
+    return info;
+}
+
+// w <- w R^{-1} for one row w (length l <= N) and R upper in registers (the
+// reciprocals of the diagonal formed once).
+template <int N>
+__device__ __forceinline__ void reg_trsm_row(double (&w)[N], const double (&R)[N][N], const double (&rinv)[N], int l)
+{
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        if (j < l) {
+            double v = w[j];
+#pragma unroll
+            for (int t = 0; t < j; ++t) v -= w[t] * R[t][j];
+            w[j] = v * rinv[j];
+        }
+    }
+}
+
 // Cholesky of the symmetric l x l matrix M (row-major; the upper triangle
 // is read) by NT threads: thread t owns the 4 x 4 blocks t, t + NT, ...
 // (BPT of them; blocks bi <= bj dealt in row-major order over the block
@@ -372,11 +431,13 @@ __device__ __forceinline__ void jacobi_rotation(double al, double be, double ga,
     const double d = be - al, g2 = 2.0 * ga;
     const double h2 = d * d + g2 * g2;
     if (h2 > 1e-290 && h2 < 1e290) {
-        const double rh = rsqrt(h2);
+        // both arguments normal (hc lies in [1/2, 1]): the lean reciprocal
+        // square root
+        const double rh = rsqrt_nr(h2);
         const double c2 = fabs(d) * rh;
         const double s2 = (d >= 0.0 ? g2 : -g2) * rh;
         const double hc = 0.5 * (1.0 + c2);
-        const double rc = rsqrt(hc);
+        const double rc = rsqrt_nr(hc);
         cs = hc * rc;
         sn = 0.5 * s2 * rc;
     } else {
@@ -395,6 +456,72 @@ __device__ __forceinline__ bool jacobi_needed(double al, double be, double ga, d
     return ab < 1e300 ? ga * ga > (tol * tol) * ab : fabs(ga) > tol * sqrt(ab);
 }
 
+// ---------------------------------------------------------------------------
+// One wavefront, l <= 8: the lane grid (r, c) = (lane % 8, lane / 8), lane
+// (r, c) holding element (r, c) of an 8 x 8 matrix M (zeros past l), so that
+// a column of M is one 8-lane DPP segment.
+// ---------------------------------------------------------------------------
+// M = R^T for the semidefinite upper Cholesky factor R of the symmetric g
+// (upper triangle read; pivots at or below 4 l u max_j g_jj give zero rows).
+// Every lane factors g itself (reg_chol) and keeps its element.
+__device__ __forceinline__ double wave8_factor(double (&g)[8][8], int l)
+{
+    const int lane = threadIdx.x % kWave, r = lane & 7, c = lane >> 3;
+    double maxdiag = 0.0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        if (j < l) maxdiag = fmax(maxdiag, g[j][j]);
+    reg_chol<8>(g, l, 4.0 * l * kU * maxdiag, 0.0);
+    double x = 0.0;
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = a; b < 8; ++b)
+            if (a == c && b == r) x = g[a][b];
+    return x;
+}
+
+// One-sided Jacobi on the columns of M in the lane grid.  Round rd of the
+// circle ordering pairs column c with d = 2 rd - c mod (n2 - 1) (column rd
+// with the fixed column n2 - 1); the partner's element arrives through one
+// lane permute, and the three inner products are segment sums that both
+// columns of a pair form over the same values in the same order, so both
+// lanes compute the same rotation.  No LDS access or barrier.  Returns the
+// sweeps taken (max_sweeps + 1 when the limit was hit).
+__device__ __forceinline__ int wave8_jacobi(double &x, int l, int max_sweeps)
+{
+    const int lane = threadIdx.x % kWave, r = lane & 7, c = lane >> 3;
+    const int n2 = l + (l & 1);
+    const double tol = (double)l * 2.0 * kU;
+    const bool live = c < n2;
+    int sweeps;
+    for (sweeps = 1; sweeps <= max_sweeps; ++sweeps) {
+        int rot = 0;
+        for (int rd = 0; rd < n2 - 1; ++rd) {
+            // the partner, without branches
+            int d2 = 2 * rd - c;
+            d2 += d2 < 0 ? n2 - 1 : 0;
+            d2 -= d2 >= n2 - 1 ? n2 - 1 : 0;
+            int d = c == n2 - 1 ? rd : (c == rd ? n2 - 1 : d2);
+            d = live ? d : c;
+            const double y = __shfl(x, (d << 3) | r, kWave);
+            double o2 = x * x, p2 = y * y, cr = x * y;
+            seg8_sum3(o2, p2, cr);
+            const bool isp = c < d;
+            const double al = isp ? o2 : p2, be = isp ? p2 : o2;
+            const bool doit = live && d != c && jacobi_needed(al, be, cr, tol);
+            if (doit) {
+                double cs, sn;
+                jacobi_rotation(al, be, cr, cs, sn);
+                x = isp ? cs * x - sn * y : sn * y + cs * x;
+            }
+            rot |= __any(doit) ? 1 : 0;
+        }
+        if (!rot) break;
+    }
+    return sweeps;
+}
+
 // One-sided Jacobi on the n columns (length rows, stride ld) of M by groups
 // of G lanes (G = 8, 16, 32 or 64): a group rotates one pair of the round,
 // lane i of the group holding rows i, i + G, ..., i + (E - 1) G in
@@ -402,9 +529,17 @@ __device__ __forceinline__ bool jacobi_needed(double al, double be, double ga, d
 // [rows, G E) of every column, so loads and stores need no bounds.  Rounds
 // with more pairs than groups take several passes (their pairs are
 // disjoint); one block barrier per round.  M may be in LDS or global memory.
+//
+// work (optional, LDS): the group leaders add the pairs they examined times
+// rows to work[0], the rotations they applied times rows to work[1] and the
+// rotations to work[2] (the floating-point work of the sweeps: 6 rows per
+// examined pair for the three inner products, 6 rows per rotation for the
+// update, and the rotation's angle).
 template <int NT, int G, int E, bool PAD = false>
-__device__ __forceinline__ int jacobi_groups(double *M, int rows, int ld, int n, int max_sweeps, int *sh_rot)
+__device__ __forceinline__ int jacobi_groups(double *M, int rows, int ld, int n, int max_sweeps, int *sh_rot,
+                                             unsigned long long *work = nullptr)
 {
+    unsigned npair = 0, nrot = 0;
     constexpr int ngroups = NT / G;
     const int gl = threadIdx.x % G, gid = threadIdx.x / G;
     const int n2 = n + (n & 1), npairs = n2 / 2;
@@ -490,12 +625,19 @@ __device__ __forceinline__ int jacobi_groups(double *M, int rows, int ld, int n,
                     }
                     if (gl == 0) *sh_rot = 1;
                 }
+                npair += live ? 1u : 0u;
+                nrot += doit ? 1u : 0u;
             }
             __syncthreads();
         }
         const int rot = *sh_rot;
         __syncthreads();
         if (!rot) break;
+    }
+    if (work && gl == 0 && npair) {
+        atomicAdd(&work[0], (unsigned long long)npair * (unsigned)rows);
+        atomicAdd(&work[1], (unsigned long long)nrot * (unsigned)rows);
+        atomicAdd(&work[2], (unsigned long long)nrot);
     }
     return sweep;
 }

@@ -81,7 +81,16 @@ constexpr uint32_t kRefillTag = 0x80000000u;
 template <int CTRL, typename T>
 __device__ __forceinline__ T dpp_mov(T v)
 {
-    return __builtin_amdgcn_update_dpp(T(0), v, CTRL, 0xF, 0xF, false);
+    // every lane's source is inside its row for the patterns used here, so
+    // the old value is never kept (bound_ctrl set, no initialised old)
+    if constexpr (sizeof(T) == 8) {
+        const long long b = __builtin_bit_cast(long long, v);
+        const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, true);
+        const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
+        return __builtin_bit_cast(T, ((long long)hi << 32) | (unsigned)lo);
+    } else {
+        return __builtin_bit_cast(T, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
+    }
 }
 constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
 
@@ -93,6 +102,30 @@ __device__ __forceinline__ T seg8_sum(T v)
     v += dpp_mov<kDppXor2>(v);
     v += dpp_mov<kDppHalfMirror>(v);
     return v;
+}
+// Three independent 8-lane sums stepped together, so that the latency of
+// one chain's DPP move and add passes while the others issue.  Each result
+// is bit-identical to seg8_sum of the same input.
+template <typename T>
+__device__ __forceinline__ void seg8_sum3(T &a, T &b, T &c)
+{
+#pragma clang fp contract(off)
+    T ta = dpp_mov<kDppXor1>(a), tb = dpp_mov<kDppXor1>(b), tc = dpp_mov<kDppXor1>(c);
+    a += ta;
+    b += tb;
+    c += tc;
+    ta = dpp_mov<kDppXor2>(a);
+    tb = dpp_mov<kDppXor2>(b);
+    tc = dpp_mov<kDppXor2>(c);
+    a += ta;
+    b += tb;
+    c += tc;
+    ta = dpp_mov<kDppHalfMirror>(a);
+    tb = dpp_mov<kDppHalfMirror>(b);
+    tc = dpp_mov<kDppHalfMirror>(c);
+    a += ta;
+    b += tb;
+    c += tc;
 }
 template <typename T>
 __device__ __forceinline__ T seg16_sum(T v)
@@ -140,6 +173,18 @@ __device__ __forceinline__ double wave_max(double v)
     v = fmax(v, dpp_mov<kDppHalfMirror>(v));
     v = fmax(v, dpp_mov<kDppMirror>(v));
     return fmax(fmax(read_lane(v, 0), read_lane(v, 16)), fmax(read_lane(v, 32), read_lane(v, 48)));
+}
+
+// 1/sqrt(x) for a normal, finite x > 0 (no denormal or overflow handling):
+// the hardware estimate refined by two Newton steps y (3/2 - x y^2 / 2), each
+// doubling the correct bits, to within a few units in the last place.
+__device__ __forceinline__ double rsqrt_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    y = y * fma(-hx, y * y, 1.5);
+    y = y * fma(-hx, y * y, 1.5);
+    return y;
 }
 
 __device__ __forceinline__ double soft_shrink(double x, double t)

@@ -1,4 +1,5 @@
 // elementwise.hip -- rank-l shrink-and-reconstruct, the RPCA epilogue and elementwise helpers (Alg. 1's thresholded reconstruction and the iALM updates).
+#include "block_dense.h"
 #include "device_common.h"
 #include "internal.h"
 
@@ -286,24 +287,27 @@ hipError_t launch_finite_check(int64_t m, int64_t n, const T *A, int64_t lda, in
 template hipError_t launch_finite_check<double>(int64_t, int64_t, const double *, int64_t, int *, hipStream_t);
 template hipError_t launch_finite_check<float>(int64_t, int64_t, const float *, int64_t, int *, hipStream_t);
 
-// Power method on a symmetric PSD l x l matrix (global memory, one workgroup).
 // Largest eigenvalue of a symmetric positive semidefinite n x n matrix G
-// (the Gram A A^T; n <= 1024) by subspace iteration with a block of kEigB
-// vectors and Rayleigh-Ritz: from a Gaussian start block (Philox), each step
-// W = G V, H = V^T W (the Rayleigh matrix of the orthonormal V), the largest
-// eigenvalue theta_1 of H (cyclic Jacobi, one thread) as the estimate, then
-// V = orth(W) by two Cholesky-QR passes.  theta_1 rises to lambda_1 with the
-// error contracting by (lambda_{kEigB+1} / lambda_1)^2 per step, whatever the
-// gaps inside the top kEigB (close or equal top eigenvalues do not slow it);
-// the smallest Ritz value theta_kEigB (<= lambda_kEigB) over theta_1 bounds
-// that ratio from above once the block has settled.  Stops after step k when
-// theta_1 moved by at most 16 n u of itself (the rounding level of the
-// Rayleigh matrix) and (theta_kEigB / theta_1)^(2k) <= 1e-16, or after
-// max_it steps.  out[0] = theta_1, out[1] = 1 when the test
-// was met (else 0: the caller takes another method).
+// (the Gram A A^T; 8 <= n <= 1024, global memory, one workgroup) by subspace
+// iteration with a block of kEigB vectors and Rayleigh-Ritz: from a Gaussian
+// start block (Philox), each outer step forms W = G V and the Rayleigh matrix
+// H = V^T W of the orthonormal V; its eigenvalues are the squared singular
+// values of the Cholesky factor of H, found by the lane-grid one-sided Jacobi
+// of one wavefront; theta_1 is the estimate.  V then advances by kEigQ
+// products with G (scaled by 1 / theta_1) and two Cholesky-QR passes.  The
+// error of theta_1 contracts by (lambda_{kEigB+1} / lambda_1)^2 per product,
+// whatever the gaps inside the top kEigB (close or equal top eigenvalues do
+// not slow it); the smallest Ritz value theta_kEigB (<= lambda_kEigB) over
+// theta_1 bounds that ratio from above once the block has settled.  Stops
+// when theta_1 moved by at most 16 n u of itself (the rounding level of the
+// Rayleigh matrix) and (theta_kEigB / theta_1)^(2 m) <= 1e-16, m the
+// products behind the current V plus one, or after max_it outer steps.
+// out[0] = theta_1, out[1] = 1 when the test was met (else 0: the caller
+// takes another method), out[2] = the outer steps taken.
 constexpr int kEigB = 8;
 constexpr int kEigNP = kEigB * (kEigB + 1) / 2;   // packed symmetric entries
 constexpr int kEigThreads = 256;
+constexpr int kEigQ = 4;   // products with G per outer step
 
 __device__ __forceinline__ void eig_pair(int p, int &a, int &b)
 {
@@ -397,58 +401,6 @@ __device__ bool eig_chol(const double *gp, double *R)
     return true;
 }
 
-// Largest and smallest eigenvalues of the packed symmetric kEigB x kEigB
-// matrix (cyclic Jacobi, one thread, all in registers).
-__device__ double eig_small_max(const double *hp, double *mn_out)
-{
-    double H[kEigB][kEigB];
-#pragma unroll
-    for (int a = 0; a < kEigB; ++a)
-#pragma unroll
-        for (int b = 0; b < kEigB; ++b) H[a][b] = hp[a <= b ? eig_idx(a, b) : eig_idx(b, a)];
-    for (int sweep = 0; sweep < 12; ++sweep) {
-        double off = 0.0, tot = 0.0;
-#pragma unroll
-        for (int a = 0; a < kEigB; ++a)
-#pragma unroll
-            for (int b = 0; b < kEigB; ++b) {
-                tot += H[a][b] * H[a][b];
-                if (a != b) off += H[a][b] * H[a][b];
-            }
-        if (!(off > 1e-32 * tot)) break;
-#pragma unroll
-        for (int p = 0; p < kEigB - 1; ++p)
-#pragma unroll
-            for (int q = p + 1; q < kEigB; ++q) {
-                const double apq = H[p][q];
-                const double theta = (H[q][q] - H[p][p]) / (2.0 * apq);
-                double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
-                if (apq == 0.0) t = 0.0;
-                const double c = 1.0 / sqrt(1.0 + t * t), sn = t * c;
-#pragma unroll
-                for (int k = 0; k < kEigB; ++k) {
-                    const double hkp = H[k][p], hkq = H[k][q];
-                    H[k][p] = c * hkp - sn * hkq;
-                    H[k][q] = sn * hkp + c * hkq;
-                }
-#pragma unroll
-                for (int k = 0; k < kEigB; ++k) {
-                    const double hpk = H[p][k], hqk = H[q][k];
-                    H[p][k] = c * hpk - sn * hqk;
-                    H[q][k] = sn * hpk + c * hqk;
-                }
-            }
-    }
-    double mx = H[0][0], mn = H[0][0];
-#pragma unroll
-    for (int a = 1; a < kEigB; ++a) {
-        mx = fmax(mx, H[a][a]);
-        mn = fmin(mn, H[a][a]);
-    }
-    *mn_out = mn;
-    return mx;
-}
-
 __global__ void __launch_bounds__(kEigThreads) k_power_eig(int n, const double *G, double *out, int max_it)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -504,56 +456,219 @@ __global__ void __launch_bounds__(kEigThreads) k_power_eig(int n, const double *
             right_solve(Xp);
         }
     };
-    orth(V);
-    for (int it = 0; it < max_it && stop_sh == 0; ++it) {
-        // W = G V (G symmetric: row i read as column i, coalesced across threads)
+    // Y = scale G X (G symmetric: row i read as column i, coalesced across
+    // threads; 32 loads in flight per thread)
+    auto matvec = [&](const double *X, double *Y, double scale) {
         for (int i = tid; i < n; i += kEigThreads) {
             double w[kEigB];
 #pragma unroll
             for (int c = 0; c < kEigB; ++c) w[c] = 0.0;
-            for (int j = 0; j < n; ++j) {
-                const double g = G[i + (size_t)j * n];
+            for (int j0 = 0; j0 < n; j0 += 32) {
+                double gv[32];
 #pragma unroll
-                for (int c = 0; c < kEigB; ++c) w[c] += g * V[j * kEigB + c];
+                for (int u = 0; u < 32; ++u) gv[u] = j0 + u < n ? G[i + (size_t)(j0 + u) * n] : 0.0;
+#pragma unroll
+                for (int u = 0; u < 32; ++u) {
+                    if (j0 + u < n) {
+#pragma unroll
+                        for (int c = 0; c < kEigB; ++c) w[c] += gv[u] * X[(j0 + u) * kEigB + c];
+                    }
+                }
             }
 #pragma unroll
-            for (int c = 0; c < kEigB; ++c) W[i * kEigB + c] = w[c];
+            for (int c = 0; c < kEigB; ++c) Y[i * kEigB + c] = w[c] * scale;
         }
         __syncthreads();
-        // Rayleigh matrix of V and its largest eigenvalue
+    };
+    orth(V);
+    int m = 0, it = 0;
+    for (it = 0; it < max_it && stop_sh == 0; ++it) {
+        matvec(V, W, 1.0);
+        // Rayleigh matrix of V; its extreme eigenvalues from wavefront 0
         eig_block_gram(n, V, W, part, red);
-        if (tid == 0) {
-            double tmin = 0.0;
-            const double est = eig_small_max(red, &tmin);
-            const double d = est - est_sh;
-            const double ratio = est > 0.0 ? fmax(tmin, 0.0) / est : 1.0;
-            // the Rayleigh matrix carries rounding of order n u lambda_1: a step
-            // that moves the estimate by less than 16 n u of it has converged
-            if (it >= 1 && fabs(d) <= 16.0 * (double)n * kU * fabs(est) && pow(ratio, 2.0 * (it + 1)) <= 1e-16) {
-                stop_sh = 1;
-                ok_sh = 1;
+        if (tid < kWave) {
+            double g[8][8];
+#pragma unroll
+            for (int a = 0; a < 8; ++a)
+#pragma unroll
+                for (int b = 0; b < 8; ++b) g[a][b] = b >= a ? red[eig_idx(a, b)] : 0.0;
+            double x = wave8_factor(g, kEigB);
+            wave8_jacobi(x, kEigB, 60);
+            const double s2 = seg8_sum(x * x);
+            double est = 0.0, tmin = 0.0;
+#pragma unroll
+            for (int b = 0; b < kEigB; ++b) {
+                const double t = read_lane(s2, b * 8);
+                est = b ? fmax(est, t) : t;
+                tmin = b ? fmin(tmin, t) : t;
             }
-            if (!(est > 0.0)) {          // G = 0
-                stop_sh = 1;
-                ok_sh = 1;
+            if (tid == 0) {
+                const double d = est - est_sh;
+                const double ratio = est > 0.0 ? fmax(tmin, 0.0) / est : 1.0;
+                // the Rayleigh matrix carries rounding of order n u lambda_1: a
+                // step that moves the estimate by less than 16 n u of it has
+                // converged
+                if (it >= 1 && fabs(d) <= 16.0 * (double)n * kU * fabs(est) && pow(ratio, 2.0 * (m + 1)) <= 1e-16) {
+                    stop_sh = 1;
+                    ok_sh = 1;
+                }
+                if (!(est > 0.0)) {  // G = 0
+                    stop_sh = 1;
+                    ok_sh = 1;
+                }
+                est_sh = fmax(est, est_sh);
             }
-            est_sh = fmax(est, est_sh);
         }
         __syncthreads();
         if (stop_sh) break;
-        orth(W);
+        // V <- orth(G^kEigQ V), the products scaled by 1 / theta_1
+        const double sc = 1.0 / est_sh;
+        for (int q = 1; q < kEigQ; ++q) {
+            if (q & 1) matvec(W, V, sc);
+            else matvec(V, W, sc);
+        }
+        orth((kEigQ - 1) & 1 ? V : W);
+        m += kEigQ;
     }
     if (tid == 0) {
         out[0] = est_sh;
         out[1] = ok_sh ? 1.0 : 0.0;
+        out[2] = (double)it;
     }
+}
+
+// Largest eigenvalue of a symmetric positive semidefinite n x n matrix G
+// (n <= 256, one workgroup, thread i owns row i) when it dominates: single
+// vector power iteration y = G x (x unit, from a fixed Philox start) with
+// the Rayleigh quotient theta = x^T y and the residual eps^2 = ||y||^2 -
+// theta^2 = ||G x - theta x||^2.  All eigenvalues are >= 0, so lambda_2 <=
+// trace(G) - lambda_1 <= trace(G) - theta; once theta > trace(G) / 2 that
+// leaves lambda_1 as the only eigenvalue above trace(G) - theta, and the
+// Kato-Temple inequality bounds lambda_1 - theta <= eps^2 / (2 theta -
+// trace(G)).  eps^2 is formed with an absolute rounding error below 4 u
+// ||y||^2, which the test adds.  Stops when that bound is at most 1e-15
+// theta: out[0] = theta, out[1] = 1; after max_it steps (no dominant
+// eigenvalue, or too slow) out[1] = 0 and the caller takes the block method.
+// NG > 0: n <= NG and thread i keeps row i of G in registers for the whole
+// iteration (one read of G); NG = 0: each product streams G again.
+template <int NG>
+__global__ void __launch_bounds__(kEigThreads) k_power_dom(int n, const double *G, double *out, int max_it)
+{
+    __shared__ double sx[256];
+    __shared__ double part[2 * (kEigThreads / kWave)];
+    __shared__ double tr_sh;
+    const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+    constexpr int nw = kEigThreads / kWave;
+    // start vector and trace
+    double xi = 0.0, gii = 0.0;
+    if (tid < n) {
+        double z0, z1;
+        gaussian_pair(0x646f6d6e74ull, 0, (uint32_t)tid, 0x40000000u, z0, z1);
+        xi = z0;
+        gii = G[tid + (size_t)tid * n];
+    }
+    {
+        const double a = wave_sum(xi * xi), t = wave_sum(gii);
+        if (lane == 0) {
+            part[wave] = a;
+            part[nw + wave] = t;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double s2 = 0.0, tr = 0.0;
+            for (int w = 0; w < nw; ++w) {
+                s2 += part[w];
+                tr += part[nw + w];
+            }
+            part[0] = s2;
+            tr_sh = tr;
+        }
+        __syncthreads();
+        const double inv = part[0] > 0.0 ? 1.0 / sqrt(part[0]) : 0.0;
+        sx[tid] = tid < n ? xi * inv : 0.0;   // zeros past n (read by the register form)
+        __syncthreads();
+    }
+    const double tr = tr_sh;
+    double grow[NG > 0 ? NG : 1];
+    if constexpr (NG > 0) {
+        // row i of G (= column i: G is symmetric), all loads issued at once
+#pragma unroll
+        for (int j = 0; j < NG; ++j) grow[j] = (tid < n && j < n) ? G[(size_t)tid * n + j] : 0.0;
+    }
+    double theta = 0.0;
+    int ok = 0;
+    if (!(tr > 0.0)) {
+        // G = 0 (a PSD matrix with zero trace)
+        ok = 1;
+    } else {
+        for (int it = 0; it < max_it; ++it) {
+            // y_i = sum_j G(i, j) x_j (column j read across the threads)
+            double yi = 0.0, xo = 0.0;
+            if (NG > 0 && tid < n) {
+                xo = sx[tid];
+                // two chains, x read from LDS two entries at a time
+                double y0 = 0.0, y1 = 0.0;
+#pragma unroll
+                for (int j = 0; j < (NG > 0 ? NG : 2); j += 2) {
+                    y0 += grow[j] * sx[j];
+                    y1 += grow[j + 1] * sx[j + 1];
+                }
+                yi = y0 + y1;
+            } else if (tid < n) {
+                xo = sx[tid];
+                for (int j0 = 0; j0 < n; j0 += 32) {
+                    double gv[32];
+#pragma unroll
+                    for (int u = 0; u < 32; ++u) gv[u] = j0 + u < n ? G[tid + (size_t)(j0 + u) * n] : 0.0;
+#pragma unroll
+                    for (int u = 0; u < 32; ++u)
+                        if (j0 + u < n) yi += gv[u] * sx[j0 + u];
+                }
+            }
+            const double a = wave_sum(xo * yi), b = wave_sum(yi * yi);
+            if (lane == 0) {
+                part[wave] = a;
+                part[nw + wave] = b;
+            }
+            __syncthreads();
+            double th = 0.0, yy = 0.0;
+            for (int w = 0; w < nw; ++w) {
+                th += part[w];
+                yy += part[nw + w];
+            }
+            theta = th;
+            const double eps2 = fmax(yy - th * th, 0.0) + 4.0 * kU * yy;
+            const double gap = 2.0 * th - tr;
+            if (gap > 0.0 && eps2 <= 1e-15 * th * gap) {
+                ok = 1;
+                break;
+            }
+            __syncthreads();  // every read of sx and part is done
+            if (tid < n) sx[tid] = yy > 0.0 ? yi / sqrt(yy) : 0.0;
+            __syncthreads();
+        }
+    }
+    if (tid == 0) {
+        out[0] = theta;
+        out[1] = ok ? 1.0 : 0.0;
+    }
+}
+
+hipError_t launch_power_dom(int n, const double *G, double *out, hipStream_t s)
+{
+    if (n < 1 || n > 256) return hipErrorInvalidValue;
+    if (n <= 208)
+        hipLaunchKernelGGL(k_power_dom<208>, dim3(1), dim3(kEigThreads), 0, s, n, G, out, 60);
+    else
+        hipLaunchKernelGGL(k_power_dom<0>, dim3(1), dim3(kEigThreads), 0, s, n, G, out, 60);
+    return hipGetLastError();
 }
 
 hipError_t launch_power_eig(int n, const double *G, double *out, hipStream_t s)
 {
     if (n < kEigB || n > 1024) return hipErrorInvalidValue;
     const size_t lds = 2 * (size_t)n * kEigB * sizeof(double);
-    hipLaunchKernelGGL(k_power_eig, dim3(1), dim3(kEigThreads), lds, s, n, G, out, 300);
+    hipLaunchKernelGGL(k_power_eig, dim3(1), dim3(kEigThreads), lds, s, n, G, out, 100);
     return hipGetLastError();
 }
 

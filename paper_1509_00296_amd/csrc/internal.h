@@ -55,6 +55,14 @@ hipError_t launch_long(const LongPlan &plan, int mode, const LongArgs<T> &args, 
 // out[j] = sum_{g < nparts} part[g * count + j], fixed order.
 template <typename T>
 hipError_t launch_reduce(const T *part, int64_t count, int nparts, T *out, hipStream_t s);
+// G = Ahat Ahat^T (mh x mh, double, column-major) for the transposed
+// orientation (Ahat(i, k) = A[k + i lda]), mh <= 256, on `grid` workgroups;
+// part: gram_tr_part_doubles(mh, grid) doubles, sum: the same for grid = 1.
+bool gram_tr_ok(int mh, int64_t nh, int64_t lda, int elem_bytes);
+size_t gram_tr_part_doubles(int mh, int grid);
+template <typename T>
+hipError_t launch_gram_tr(const T *A, int64_t lda, int mh, int64_t nh, int grid, double *part, double *sum,
+                          double *G, hipStream_t s);
 // sum of nparts doubles (the order of launch_reduce with count 1), the
 // first nstatus status words and the double *res (-1 when res is null),
 // written to mapped host memory (device pointers host_status, host_z,
@@ -181,6 +189,10 @@ hipError_t launch_finite_check(int64_t m, int64_t n, const T *A, int64_t lda, in
 // power method (one workgroup); out[0] = lambda_max.
 // Largest eigenvalue of a symmetric PSD n x n matrix (8 <= n <= 1024) by
 // block subspace iteration: out[0] the estimate, out[1] 1 when certified.
+// Largest eigenvalue of the PSD n x n G (n <= 256) by a single-vector power
+// iteration certified through the Kato-Temple bound when it exceeds half the
+// trace: out[0] the estimate, out[1] 1 when certified (else 0).
+hipError_t launch_power_dom(int n, const double *G, double *out, hipStream_t s);
 hipError_t launch_power_eig(int n, const double *G, double *out, hipStream_t s);
 
 // --------------------------------------------------------- generic GEMM
@@ -290,6 +302,7 @@ struct WsvtBatchArgs {
     int32_t *sweeps;         // optional, Jacobi sweeps per matrix
     const int32_t *order;    // processing order or nullptr
     int *queue;              // work counter
+    unsigned long long *work;   // optional: Jacobi work counters (pair rows, rotation rows, rotations)
     const int32_t *group_size;  // lanes per Jacobi pair group, per size bucket (3)
 };
 size_t wsvt_batched_lds();

@@ -745,10 +745,13 @@ static hipError_t launch_long_cm(const LongPlan &p, const LongArgs<T> &a, hipStr
 template <typename T, int MODE>
 static hipError_t launch_long_tr(const LongPlan &p, const LongArgs<T> &a, uint32_t span, hipStream_t s)
 {
-    // NJ row groups of 16 per thread: 8 for mhp <= 128, else 16
+    // NJ row groups of 16 per thread: 8 for mhp <= 128, 13 for mhp <= 208
+    // (no phase-1 products of empty row groups), else 16
     const bool nj8 = p.mhp <= 128;
     if (p.cm == 16 && nj8)
         hipLaunchKernelGGL((k_long_tr<T, MODE, 1, 2, 8>), dim3(p.grid), dim3(kThreads), p.ldst, s, a, span);
+    else if (p.cm == 16 && p.mhp <= 208)
+        hipLaunchKernelGGL((k_long_tr<T, MODE, 1, 2, 13>), dim3(p.grid), dim3(kThreads), p.ldst, s, a, span);
     else if (p.cm == 16)
         hipLaunchKernelGGL((k_long_tr<T, MODE, 1, 2, 16>), dim3(p.grid), dim3(kThreads), p.ldst, s, a, span);
     else if (nj8)
@@ -800,6 +803,153 @@ hipError_t launch_long(const LongPlan &p, int mode, const LongArgs<T> &a0, hipSt
 }
 template hipError_t launch_long<double>(const LongPlan &, int, const LongArgs<double> &, hipStream_t);
 template hipError_t launch_long<float>(const LongPlan &, int, const LongArgs<float> &, hipStream_t);
+
+// ===========================================================================
+// Gram G = Ahat Ahat^T (mh x mh, double) in the transposed orientation (the
+// long dimension contiguous), mh <= 16 NRB <= 256: the Gram behind ||O||_2.
+// One workgroup per compute unit streams tiles of 16 long indices x mh rows
+// with buffer loads (the next tile in registers while the current one is
+// used; rows past mh and indices past nh read as zero), stores the tile to
+// LDS and accumulates the upper 16 x 16 blocks (I <= J) on the matrix cores:
+// wavefront w owns the blocks w, w + 4, ... for the whole pass, four
+// 16x16x4 steps per tile (K = the tile's long indices).  Each workgroup
+// writes its blocks as one partial (block b, MFMA register r, lane l at
+// (b * 4 + r) * 64 + l); the fixed-order reduction adds the partials and
+// k_gram_scatter places the sum in both triangles of G.
+// ===========================================================================
+__host__ __device__ constexpr int gram_nblk(int nrb) { return nrb * (nrb + 1) / 2; }
+
+template <typename T, int NRB>
+__global__ void __launch_bounds__(kThreads) k_gram_tr(const T *A, int64_t lda, int mh, int64_t nh, int ntiles,
+                                                      uint32_t span_bytes, double *part)
+{
+    constexpr int NBLK = gram_nblk(NRB);
+    constexpr int NPW = (NBLK + 3) / 4;
+    constexpr int LD = 17;  // LDS row stride in doubles (odd: operand reads spread over the banks)
+    constexpr uint32_t ESZ = sizeof(T);
+    typedef __attribute__((__vector_size__(4 * sizeof(double)))) double d4;
+    __shared__ double sT[16 * NRB * LD];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const __amdgpu_buffer_rsrc_t rsrc =
+        __builtin_amdgcn_make_buffer_rsrc((void *)A, (short)0, (int)span_bytes, 0x00020000);
+    const int kk_l = tid & 15, r0 = tid >> 4;
+    const uint32_t v0 = ((uint32_t)kk_l + (uint32_t)r0 * (uint32_t)lda) * ESZ;
+    const uint32_t rowstep = 16u * (uint32_t)lda * ESZ;
+    // this wavefront's blocks (I, J), I <= J, in row-major order of the
+    // upper block triangle
+    int bi[NPW], bj[NPW];
+#pragma unroll
+    for (int q = 0; q < NPW; ++q) {
+        int b = wave + 4 * q, I = 0;
+        if (b >= NBLK) b = 0;
+        while (b >= NRB - I) {
+            b -= NRB - I;
+            ++I;
+        }
+        bi[q] = I;
+        bj[q] = I + b;
+    }
+    d4 acc[NPW];
+#pragma unroll
+    for (int q = 0; q < NPW; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+    T pre[NRB];
+    auto load_tile = [&](int tile) {
+        const int64_t k0 = (int64_t)tile * kKT;
+        const uint32_t vt = (k0 + kk_l < nh) ? v0 + (uint32_t)k0 * ESZ : kOob;
+#pragma unroll
+        for (int j = 0; j < NRB; ++j) pre[j] = buf_load<T>(rsrc, (r0 + 16 * j < mh) ? vt : kOob, (uint32_t)j * rowstep);
+    };
+    if ((int)blockIdx.x < ntiles) load_tile(blockIdx.x);
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+#pragma unroll
+        for (int j = 0; j < NRB; ++j) sT[(r0 + 16 * j) * LD + kk_l] = (double)pre[j];
+        __syncthreads();
+        if (tile + (int)gridDim.x < ntiles) load_tile(tile + gridDim.x);
+#pragma unroll
+        for (int q = 0; q < NPW; ++q) {
+            if (wave + 4 * q < NBLK) {
+                const double *ra = sT + (bi[q] * 16 + (lane & 15)) * LD + (lane >> 4);
+                const double *rb = sT + (bj[q] * 16 + (lane & 15)) * LD + (lane >> 4);
+#pragma unroll
+                for (int k4 = 0; k4 < kKT; k4 += 4)
+                    acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ra[k4], rb[k4], acc[q], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    double *pp = part + (size_t)blockIdx.x * NBLK * 256;
+#pragma unroll
+    for (int q = 0; q < NPW; ++q) {
+        const int b = wave + 4 * q;
+        if (b < NBLK)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) pp[(size_t)(b * 4 + r) * 64 + lane] = acc[q][r];
+    }
+}
+
+// G (mh x mh, column-major) from the summed blocks of k_gram_tr: entry
+// (b, r, l) is row 16 I + (l >> 4) + 4 r, column 16 J + (l & 15) of block
+// b = (I, J), and its mirror.
+__global__ void k_gram_scatter(const double *sum, int nrb, int mh, double *G)
+{
+    const int nblk = gram_nblk(nrb);
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nblk * 256) return;
+    int b = idx / 256, I = 0;
+    const int r = (idx / 64) % 4, l = idx % 64;
+    while (b >= nrb - I) {
+        b -= nrb - I;
+        ++I;
+    }
+    const int J = I + b;
+    const int row = 16 * I + (l >> 4) + 4 * r, col = 16 * J + (l & 15);
+    if (row < mh && col < mh) {
+        const double v = sum[idx];
+        G[row + (size_t)col * mh] = v;
+        G[col + (size_t)row * mh] = v;
+    }
+}
+
+bool gram_tr_ok(int mh, int64_t nh, int64_t lda, int elem_bytes)
+{
+    if (mh < 1 || mh > 256 || nh < 1 || lda < nh) return false;
+    const uint64_t span = ((uint64_t)(nh - 1) + (uint64_t)(mh - 1) * (uint64_t)lda + 1) * (uint64_t)elem_bytes;
+    const uint64_t rows = (uint64_t)16 * (uint64_t)lda * (uint64_t)elem_bytes * 16;
+    return span < kOob && rows < kOob;
+}
+
+size_t gram_tr_part_doubles(int mh, int grid) { return (size_t)grid * gram_nblk((mh + 15) / 16) * 256; }
+
+template <typename T, int NRB>
+static hipError_t launch_gram_tr_nrb(const T *A, int64_t lda, int mh, int64_t nh, int grid, double *part,
+                                     double *sum, double *G, hipStream_t s)
+{
+    const int ntiles = (int)((nh + kKT - 1) / kKT);
+    const uint32_t span = (uint32_t)(((uint64_t)(nh - 1) + (uint64_t)(mh - 1) * (uint64_t)lda + 1) * sizeof(T));
+    hipLaunchKernelGGL((k_gram_tr<T, NRB>), dim3(grid), dim3(kThreads), 0, s, A, lda, mh, nh, ntiles, span, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int count = gram_nblk(NRB) * 256;
+    if ((e = launch_reduce<double>(part, count, grid, sum, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gram_scatter, dim3((count + 255) / 256), dim3(256), 0, s, sum, NRB, mh, G);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gram_tr(const T *A, int64_t lda, int mh, int64_t nh, int grid, double *part, double *sum,
+                          double *G, hipStream_t s)
+{
+    if (!gram_tr_ok(mh, nh, lda, sizeof(T)) || grid < 1) return hipErrorInvalidValue;
+    const int nrb = (mh + 15) / 16;
+    if (nrb <= 4) return launch_gram_tr_nrb<T, 4>(A, lda, mh, nh, grid, part, sum, G, s);
+    if (nrb <= 8) return launch_gram_tr_nrb<T, 8>(A, lda, mh, nh, grid, part, sum, G, s);
+    if (nrb <= 13) return launch_gram_tr_nrb<T, 13>(A, lda, mh, nh, grid, part, sum, G, s);
+    return launch_gram_tr_nrb<T, 16>(A, lda, mh, nh, grid, part, sum, G, s);
+}
+template hipError_t launch_gram_tr<double>(const double *, int64_t, int, int64_t, int, double *, double *, double *,
+                                           hipStream_t);
+template hipError_t launch_gram_tr<float>(const float *, int64_t, int, int64_t, int, double *, double *, double *,
+                                          hipStream_t);
 
 // ===========================================================================
 // Fixed-order reductions: out[j] = sum_g part[g * count + j].

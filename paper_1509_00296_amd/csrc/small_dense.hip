@@ -33,6 +33,55 @@ bool small_orth_ok(int mh, int l)
     return l >= 1 && l <= 64 && (size_t)(mh | 1) * l * 16 + (size_t)l * l * 16 + 8192 <= 96 * 1024;
 }
 
+// Step 4 of the orthonormalisation, from the equilibrated basis in W (LDS,
+// all NT threads): shifted CholeskyQR, refill of numerically null columns,
+// and a final CholeskyQR pass.  Ends with a barrier.
+__device__ __forceinline__ void orth_fallback(double *W, double *G, double *R, int *null_flags, int mh, int mhp,
+                                              int l, uint64_t seed, uint64_t counter, int &refilled,
+                                              int &final_fail)
+{
+    const int tid = threadIdx.x, NT = blockDim.x;
+    const int lane = tid % kWave, wave = tid / kWave, nw = NT / kWave;
+    block_gram(W, mh, mhp, l, G);
+    double tr = 0.0;
+    for (int j = 0; j < l; ++j) tr += G[j * l + j];
+    double shift = 11.0 * ((double)mh * l + (double)l * (l + 1)) * kU * tr;
+    if (!(shift > 0.0)) shift = kU;
+    block_chol(G, l, shift, 0.0, R, nullptr);
+    block_trsm(W, mh, mhp, l, R);
+    for (int attempt = 0; attempt < 4; ++attempt) {
+        block_gram(W, mh, mhp, l, G);
+        double mxd = 0.0;
+        for (int j = 0; j < l; ++j) mxd = fmax(mxd, G[j * l + j]);
+        const CholInfo ci = block_chol(G, l, 0.0, 16.0 * l * kU * fmax(mxd, 1e-300), R, null_flags);
+        if (ci.nnull == 0 || attempt == 3) break;
+        for (int j = 0; j < l; ++j) {
+            if (!null_flags[j]) continue;
+            for (int i = tid; i < mh; i += NT) {
+                double z0, z1;
+                gaussian_pair(seed, counter, (uint32_t)i, kRefillTag | (uint32_t)(attempt * 64 + j), z0, z1);
+                W[(size_t)j * mhp + i] = z0;
+            }
+        }
+        __syncthreads();
+        for (int j = wave; j < l; j += nw) {
+            if (!null_flags[j]) continue;
+            double *wj = W + (size_t)j * mhp;
+            double s = 0.0;
+            for (int i = lane; i < mh; i += kWave) s += wj[i] * wj[i];
+            s = wave_sum(s);
+            const double inv = 1.0 / sqrt(s);
+            for (int i = lane; i < mh; i += kWave) wj[i] *= inv;
+        }
+        __syncthreads();
+        refilled += ci.nnull;
+    }
+    block_trsm(W, mh, mhp, l, R);
+    block_gram(W, mh, mhp, l, G);
+    final_fail = block_chol(G, l, 0.0, 0.0, R, nullptr).nnull;
+    block_trsm(W, mh, mhp, l, R);
+}
+
 template <typename T, int NT, int LM>
 __global__ void __launch_bounds__(NT) k_small_orth(int mh, const T *Qt, int64_t ldqt, int rp,
                                                    const T *Y, int64_t ldy, int c, T *Q,
@@ -198,49 +247,172 @@ __global__ void __launch_bounds__(NT) k_small_orth(int mh, const T *Qt, int64_t 
             W[(size_t)j * mhp + i] = W0[(size_t)j * mhp + i];
         }
         __syncthreads();
-        block_gram(W, mh, mhp, l, G);
-        double tr = 0.0;
-        for (int j = 0; j < l; ++j) tr += G[j * l + j];
-        double shift = 11.0 * ((double)mh * l + (double)l * (l + 1)) * kU * tr;
-        if (!(shift > 0.0)) shift = kU;
-        block_chol(G, l, shift, 0.0, R, nullptr);
-        block_trsm(W, mh, mhp, l, R);
-        for (int attempt = 0; attempt < 4; ++attempt) {
-            block_gram(W, mh, mhp, l, G);
-            double mxd = 0.0;
-            for (int j = 0; j < l; ++j) mxd = fmax(mxd, G[j * l + j]);
-            const CholInfo ci = block_chol(G, l, 0.0, 16.0 * l * kU * fmax(mxd, 1e-300), R, null_flags);
-            if (ci.nnull == 0 || attempt == 3) break;
-            for (int j = 0; j < l; ++j) {
-                if (!null_flags[j]) continue;
-                for (int i = tid; i < mh; i += NT) {
-                    double z0, z1;
-                    gaussian_pair(seed, counter, (uint32_t)i, kRefillTag | (uint32_t)(attempt * 64 + j), z0, z1);
-                    W[(size_t)j * mhp + i] = z0;
-                }
-            }
-            __syncthreads();
-            for (int j = wave; j < l; j += nw) {
-                if (!null_flags[j]) continue;
-                double *wj = W + (size_t)j * mhp;
-                double s = 0.0;
-                for (int i = lane; i < mh; i += kWave) s += wj[i] * wj[i];
-                s = wave_sum(s);
-                const double inv = 1.0 / sqrt(s);
-                for (int i = lane; i < mh; i += kWave) wj[i] *= inv;
-            }
-            __syncthreads();
-            refilled += ci.nnull;
-        }
-        block_trsm(W, mh, mhp, l, R);
-        block_gram(W, mh, mhp, l, G);
-        final_fail = block_chol(G, l, 0.0, 0.0, R, nullptr).nnull;
-        block_trsm(W, mh, mhp, l, R);
+        orth_fallback(W, G, R, null_flags, mh, mhp, l, seed, counter, refilled, final_fail);
     }
 
     for (int idx = tid; idx < mh * l; idx += NT) {
         const int i = idx % mh, j = idx / mh;
         Q[i + (int64_t)j * ldq] = (T)W[(size_t)j * mhp + i];
+    }
+    if (tid == 0 && flags) {
+        flags[0] = fast ? 1 : 2;
+        flags[1] = refilled;
+        flags[2] = final_fail;
+    }
+}
+
+// l <= 8 and mh <= 256 RPT: the same steps with the rows of W in registers
+// (thread t owns rows t + 256 k, k < RPT).  The Grams run on the matrix cores
+// from an LDS copy of W (gram16_mfma); every thread then reads the l x l Gram
+// and factors it itself (reg_chol: the same arithmetic in every thread, so
+// no broadcast step and no barrier for the factor), and solves its own rows
+// with the reciprocal pivots.  The fallback (step 4) runs from LDS.
+template <typename T, int RPT>
+__global__ void __launch_bounds__(256) k_small_orth8(int mh, const T *Qt, int64_t ldqt, int rp, const T *Y,
+                                                     int64_t ldy, int c, T *Q, int64_t ldq, uint64_t seed,
+                                                     uint64_t counter, int *flags, double *resid2)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int l = rp + c;
+    const int mhp = mh | 1;
+    double *W = reinterpret_cast<double *>(smem_raw);
+    double *W0 = W + (size_t)l * mhp;
+    double *G = W0 + (size_t)l * mhp;
+    double *R = G + (size_t)l * l;
+    double *part = R + (size_t)l * l;
+    __shared__ int null_flags[64];
+    const int tid = threadIdx.x;
+
+    // every load of the thread's rows issued before the first use
+    double w[RPT][8];
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        const int i = tid + 256 * k;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            double v = 0.0;
+            if (i < mh && j < l) v = j < rp ? (double)Qt[i + (int64_t)j * ldqt] : (double)Y[i + (int64_t)(j - rp) * ldy];
+            w[k][j] = v;
+        }
+    }
+    auto put = [&](int j0) {
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const int i = tid + 256 * k;
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (i < mh && j >= j0 && j < l) W[(size_t)j * mhp + i] = w[k][j];
+        }
+    };
+    put(0);
+    __syncthreads();
+
+    // 1. CGS2 against the propagated basis: Y <- Y - Qt C, C = Qt^T Y (the
+    //    Qt-Y block of the Gram of [Qt, Y])
+    if (rp > 0 && c > 0) {
+        for (int pass = 0; pass < 2; ++pass) {
+            gram16_mfma(W, mh, mhp, l, G, part);
+            double cf[8][8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+#pragma unroll
+                for (int j = 0; j < 8; ++j) cf[t][j] = (t < rp && j >= rp && j < l) ? G[t * l + j] : 0.0;
+#pragma unroll
+            for (int k = 0; k < RPT; ++k)
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    if (j >= rp && j < l) {
+                        double v = w[k][j];
+#pragma unroll
+                        for (int t = 0; t < 8; ++t)
+                            if (t < rp) v -= w[k][t] * cf[t][j];
+                        w[k][j] = v;
+                    }
+                }
+            put(rp);
+            __syncthreads();
+        }
+    }
+    // 2. equilibration from the Gram's diagonal; the Gram of the scaled basis
+    //    is the scaled Gram
+    gram16_mfma(W, mh, mhp, l, G, part);
+    if (resid2 && tid == 0) *resid2 = c > 0 ? G[rp * l + rp] : -1.0;
+    double sc[8], g[8][8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const double d = j < l ? G[j * l + j] : 0.0;
+        sc[j] = d > 0.0 ? rsqrt_pos(d) : 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = 0; b < 8; ++b) g[a][b] = (b >= a && b < l) ? G[a * l + b] * (sc[a] * sc[b]) : 0.0;
+    double w0[RPT][8];
+#pragma unroll
+    for (int k = 0; k < RPT; ++k)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            w[k][j] *= sc[j];
+            w0[k][j] = w[k][j];
+        }
+    // 3. CholeskyQR2
+    double mx = 0.0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        if (j < l) mx = fmax(mx, g[j][j]);
+    double rinv[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) rinv[j] = 0.0;
+    const CholInfo c1 = reg_chol<8>(g, l, 16.0 * l * kU * fmax(mx, 1e-300), 1.0, 1e-8, rinv);
+    bool fast = c1.nnull == 0 && c1.min_ratio > 0.0;
+    if (fast) {
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) reg_trsm_row<8>(w[k], g, rinv, l);
+        put(0);
+        __syncthreads();
+        gram16_mfma(W, mh, mhp, l, G, part);
+#pragma unroll
+        for (int a = 0; a < 8; ++a)
+#pragma unroll
+            for (int b = 0; b < 8; ++b) g[a][b] = (b >= a && b < l) ? G[a * l + b] : 0.0;
+        const CholInfo c2 = reg_chol<8>(g, l, 0.5, 1.0, 0.0, rinv);
+        bool near_one = c2.nnull == 0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (j < l) near_one = near_one && fabs(g[j][j] - 1.0) <= 1e-6;
+        if (near_one) {
+#pragma unroll
+            for (int k = 0; k < RPT; ++k) reg_trsm_row<8>(w[k], g, rinv, l);
+        } else {
+            fast = false;
+        }
+    }
+    int refilled = 0, final_fail = 0;
+    if (!fast) {
+        // 4. fallback from the saved equilibrated basis, in LDS
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const int i = tid + 256 * k;
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (i < mh && j < l) W[(size_t)j * mhp + i] = w0[k][j];
+        }
+        __syncthreads();
+        orth_fallback(W, G, R, null_flags, mh, mhp, l, seed, counter, refilled, final_fail);
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const int i = tid + 256 * k;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) w[k][j] = (i < mh && j < l) ? W[(size_t)j * mhp + i] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        const int i = tid + 256 * k;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (i < mh && j < l) Q[i + (int64_t)j * ldq] = (T)w[k][j];
     }
     if (tid == 0 && flags) {
         flags[0] = fast ? 1 : 2;
@@ -257,7 +429,13 @@ hipError_t launch_small_orth(int mh, const T *Qt, int64_t ldqt, int rp, const T 
     const int l = rp + c;
     if (!small_orth_ok(mh, l)) return hipErrorInvalidValue;
     const size_t lds = (2 * (size_t)l * (mh | 1) + 2 * (size_t)l * l + 4 * 256) * sizeof(double);
-    if (l <= 8)
+    if (l <= 8 && mh <= 256)
+        hipLaunchKernelGGL((k_small_orth8<T, 1>), dim3(1), dim3(256), lds, s, mh, Qt, ldqt, rp, Y, ldy, c, Q,
+                           ldq, seed, counter, flags, resid2);
+    else if (l <= 8 && mh <= 512)
+        hipLaunchKernelGGL((k_small_orth8<T, 2>), dim3(1), dim3(256), lds, s, mh, Qt, ldqt, rp, Y, ldy, c, Q,
+                           ldq, seed, counter, flags, resid2);
+    else if (l <= 8)
         hipLaunchKernelGGL((k_small_orth<T, 256, 8>), dim3(1), dim3(256), lds, s, mh, Qt, ldqt, rp, Y,
                            ldy, c, Q, ldq, seed, counter, flags, resid2);
     else
@@ -855,6 +1033,111 @@ __global__ void __launch_bounds__(NT) k_small_svd(int l, const double *Gin, doub
                               sh_rot, rank, order, sig, coef, wc, in_factor);
 }
 
+// l <= 8: the whole small SVD in one wavefront's registers.  Every lane of
+// wavefront 0 factors G = R^T R itself (reg_chol), then lane (r, c) =
+// (lane % 8, lane / 8) keeps element (r, c) of M = R^T, so that a column of
+// M is one 8-lane DPP segment.  Round `rd` of the circle ordering pairs column
+// c with d = 2 rd - c mod (n2 - 1) (column rd with the fixed column n2 - 1);
+// the partner's element arrives through one lane permute, and the three
+// inner products are segment sums that both columns of a pair form over the
+// same values in the same order, so both lanes compute the same rotation.
+// No LDS access or barrier inside the sweeps.  The other wavefronts load
+// their rows of Q meanwhile and join for the products with Q.
+template <typename T>
+__global__ void __launch_bounds__(256) k_small_svd8(int l, const double *Gin, double tau, int keep,
+                                                    const double *w, const T *Q, int64_t ldq, int mh, T *QM,
+                                                    int64_t ldqm, T *Qout, int64_t ldqo, SmallSvdOut out,
+                                                    int fuse_q, int in_factor)
+{
+    __shared__ double sM[64], sU[64], sMm[64], swc[8];
+    __shared__ int sh_rank;
+    const int tid = threadIdx.x;
+    const bool fq = fuse_q && Q;
+    double qpre[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) qpre[t] = (fq && tid < mh && t < l) ? (double)Q[tid + (int64_t)t * ldq] : 0.0;
+
+    if (tid < kWave) {
+        const int lane = tid, r = lane & 7, c = lane >> 3;
+        double x = 0.0;
+        if (in_factor) {
+            // the input is already the upper triangular factor C (column-major)
+            if (r < l && c < l && r >= c) x = Gin[c + (size_t)r * l];
+        } else {
+            double g[8][8];
+#pragma unroll
+            for (int a = 0; a < 8; ++a)
+#pragma unroll
+                for (int b = 0; b < 8; ++b) g[a][b] = (b >= a && b < l) ? Gin[a * l + b] : 0.0;
+            x = wave8_factor(g, l);
+        }
+        const int sweeps = wave8_jacobi(x, l, 60);
+        // singular values (column norms), their descending order by counting
+        // (ties by column index), thresholds and the factors
+        const double sg = sqrt(seg8_sum(x * x));
+        int pos = 0;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const double sb = read_lane(sg, b * 8);
+            pos += (b < l && (sb > sg || (sb == sg && b < c))) ? 1 : 0;
+        }
+        const bool col = c < l;
+        double coef = 0.0, f = -1.0;
+        if (col) {
+            const double th = w ? w[pos] : (pos < keep ? 0.0 : tau);
+            f = sg - th;
+            coef = (f > 0.0 && sg > 0.0) ? f / sg : 0.0;
+        }
+        const int rank = __popcll(__ballot(col && r == 0 && f > 0.0));
+        const double u = sg > 0.0 ? x / sg : 0.0;
+        if (col && r < l) {
+            out.U[r + (size_t)pos * l] = u;
+            sU[r + pos * 8] = u;
+        }
+        if (col && r == 0) {
+            out.sigma[pos] = sg;
+            swc[c] = sg > 0.0 ? coef / (sg * sg) : 0.0;
+        }
+        sM[lane] = x;
+        wave_sync();
+        // Mm(r, c) = sum_b wc_b M(r, b) M(c, b)
+        double acc = 0.0;
+        for (int b = 0; b < l; ++b) acc += sM[b * 8 + r] * (swc[b] * sM[b * 8 + c]);
+        if (r < l && c < l) out.Mm[r + (size_t)c * l] = acc;
+        sMm[r + c * 8] = acc;
+        if (lane == 0) {
+            out.status[0] = rank;
+            out.status[1] = sweeps;
+            out.status[2] = sweeps <= 60 ? 1 : 0;
+            sh_rank = rank;
+        }
+    }
+    __syncthreads();
+    if (fq) {
+        // QM = Q Mm and Qout = Q U(:, 1:r), one row of Q per thread
+        const int rk = sh_rank;
+        for (int i = tid; i < mh; i += 256) {
+            double q[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) q[t] = (i == tid) ? qpre[t] : (t < l ? (double)Q[i + (int64_t)t * ldq] : 0.0);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if (j < l) {
+                    double v = 0.0, uu = 0.0;
+#pragma unroll
+                    for (int t = 0; t < 8; ++t)
+                        if (t < l) {
+                            v += q[t] * sMm[t + j * 8];
+                            uu += q[t] * sU[t + j * 8];
+                        }
+                    QM[i + (int64_t)j * ldqm] = (T)v;
+                    if (Qout && j < rk) Qout[i + (int64_t)j * ldqo] = (T)uu;
+                }
+            }
+        }
+    }
+}
+
 template <typename T>
 hipError_t launch_small_svd(int l, const double *G, double tau, const double *w, int keep, const T *Q,
                             int64_t ldq, int mh, T *QM, int64_t ldqm, T *Qout, int64_t ldqo,
@@ -867,6 +1150,9 @@ hipError_t launch_small_svd(int l, const double *G, double tau, const double *w,
     size_t lds = l <= 128 ? (size_t)l * std::max(l, ldm) * sizeof(double) : 0;
     if (fuse_q && Q) lds = std::max(lds, 2 * (size_t)l * l * sizeof(double));
     if (l <= 8)
+        hipLaunchKernelGGL((k_small_svd8<T>), dim3(1), dim3(256), 0, s, l, G, tau, keep, w, Q, ldq, mh, QM, ldqm,
+                           Qout, ldqo, out, fuse_q, in_factor);
+    else if (l <= 8)
         hipLaunchKernelGGL((k_small_svd<T, 256, 8>), dim3(1), dim3(256), lds, s, l, G, tau, keep, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, work, fuse_q, in_factor);
     else if (l <= 32)
         hipLaunchKernelGGL((k_small_svd<T, 256, 16>), dim3(1), dim3(256), lds, s, l, G, tau, keep, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, work, fuse_q, in_factor);

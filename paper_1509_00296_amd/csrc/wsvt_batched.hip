@@ -96,10 +96,14 @@ __global__ void __launch_bounds__(kWB, 2) k_wsvt_batched(WsvtBatchArgs a)
     double *M = reinterpret_cast<double *>(smem_raw);
     double *Z = M + kWMaxShort * kWMaxShort;  // [kWZ][kWMaxLong]
     __shared__ int sh_idx, sh_rot, sh_rank, sh_nz;
+    // the workgroup's count of the Jacobi work (added to a.work at the end)
+    __shared__ unsigned long long sh_work[3];
+    unsigned long long *const wk = a.work ? sh_work : nullptr;
     __shared__ __align__(16) double coef[kWMaxShort];
     __shared__ double sig[kWMaxShort];
     __shared__ int nzc[kWMaxShort];
     const int tid = threadIdx.x;
+    if (tid < 3) sh_work[tid] = 0;
     for (;;) {
         if (tid == 0) sh_idx = atomicAdd(a.queue, 1);
         __syncthreads();
@@ -140,17 +144,17 @@ __global__ void __launch_bounds__(kWB, 2) k_wsvt_batched(WsvtBatchArgs a)
         //    its bucket)
         int sweeps;
         if (bucket == 0) {
-            if (gs == 8) sweeps = jacobi_groups<kWB, 8, 6, true>(M, s, ldm, s, 40, &sh_rot);
-            else if (gs == 32) sweeps = jacobi_groups<kWB, 32, 2, true>(M, s, ldm, s, 40, &sh_rot);
-            else sweeps = jacobi_groups<kWB, 16, 3, true>(M, s, ldm, s, 40, &sh_rot);
+            if (gs == 8) sweeps = jacobi_groups<kWB, 8, 6, true>(M, s, ldm, s, 40, &sh_rot, wk);
+            else if (gs == 32) sweeps = jacobi_groups<kWB, 32, 2, true>(M, s, ldm, s, 40, &sh_rot, wk);
+            else sweeps = jacobi_groups<kWB, 16, 3, true>(M, s, ldm, s, 40, &sh_rot, wk);
         } else if (bucket == 1) {
-            if (gs == 8) sweeps = jacobi_groups<kWB, 8, 8, true>(M, s, ldm, s, 40, &sh_rot);
-            else if (gs == 32) sweeps = jacobi_groups<kWB, 32, 2, true>(M, s, ldm, s, 40, &sh_rot);
-            else sweeps = jacobi_groups<kWB, 16, 4, true>(M, s, ldm, s, 40, &sh_rot);
+            if (gs == 8) sweeps = jacobi_groups<kWB, 8, 8, true>(M, s, ldm, s, 40, &sh_rot, wk);
+            else if (gs == 32) sweeps = jacobi_groups<kWB, 32, 2, true>(M, s, ldm, s, 40, &sh_rot, wk);
+            else sweeps = jacobi_groups<kWB, 16, 4, true>(M, s, ldm, s, 40, &sh_rot, wk);
         } else {
-            if (gs == 8) sweeps = jacobi_groups<kWB, 8, 12, true>(M, s, ldm, s, 40, &sh_rot);
-            else if (gs == 32) sweeps = jacobi_groups<kWB, 32, 3, true>(M, s, ldm, s, 40, &sh_rot);
-            else sweeps = jacobi_groups<kWB, 16, 6, true>(M, s, ldm, s, 40, &sh_rot);
+            if (gs == 8) sweeps = jacobi_groups<kWB, 8, 12, true>(M, s, ldm, s, 40, &sh_rot, wk);
+            else if (gs == 32) sweeps = jacobi_groups<kWB, 32, 3, true>(M, s, ldm, s, 40, &sh_rot, wk);
+            else sweeps = jacobi_groups<kWB, 16, 6, true>(M, s, ldm, s, 40, &sh_rot, wk);
         }
         // 4. singular values, thresholds: P = sum_c (f_c / s_c) v_c v_c^T with
         //    v_c = m_c / s_c, i.e. coef_c = f_c / s_c^3 on the columns m_c
@@ -219,15 +223,21 @@ __global__ void __launch_bounds__(kWB, 2) k_wsvt_batched(WsvtBatchArgs a)
         }
         __syncthreads();
     }
+    if (a.work && tid < 3 && sh_work[tid]) atomicAdd(&a.work[tid], sh_work[tid]);
 }
 
 // q[0]: the work counter; q[1]: set when a matrix's shape is outside the
-// bounds the kernel's local memory holds (that matrix is skipped)
+// bounds the kernel's local memory holds (that matrix is skipped); the Jacobi
+// work counters (three 64-bit words at byte 64 of the queue block)
 __global__ void k_queue_reset(int *q)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         q[0] = 0;
         q[1] = 0;
+        unsigned long long *w = reinterpret_cast<unsigned long long *>(q + 16);
+        w[0] = 0;
+        w[1] = 0;
+        w[2] = 0;
     }
 }
 

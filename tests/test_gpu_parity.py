@@ -403,3 +403,21 @@ def test_rpca_spectral_norm_with_close_top_pair(fr, orc, delta):
     assert res.ranks == list(out["ranks"][:64])
     assert _rel(res.L.cpu().numpy(), out["L"]) <= 1e-10
     assert _rel(res.S.cpu().numpy(), out["S"]) <= 1e-10
+
+@pytest.mark.parametrize("m,n,dt", [(3000, 50, "f64"), (2000, 100, "f64"), (5000, 200, "f64"),
+                                    (4000, 256, "f64"), (1001, 255, "f64"), (6000, 200, "f32"),
+                                    (60, 3000, "f64")])
+def test_rpca_norm2_matches_svd(fr, m, n, dt):
+    """||O||_2 of the iALM start (the Gram of the short side on the matrix
+    cores, then its largest eigenvalue) against LAPACK's largest singular
+    value of the same (float32-widened) data, over short sides that fill one
+    to sixteen 16-row blocks, ragged and full, and the wide orientation."""
+    from paper_1509_00296_amd import synth
+    _say(f"case rpca norm2 {m}x{n} {dt}")
+    O, _, _ = synth.rpca(seed=m + n, m=m, n=n, rank=5, frac=0.05)
+    if dt == "f32":
+        O = np.asfortranarray(O.astype(np.float32))
+    sig1 = np.linalg.svd(O.astype(np.float64), compute_uv=False)[0]
+    res = fr.rpca_ialm(torch.from_numpy(np.asfortranarray(O)).cuda(), 1.0 / np.sqrt(max(m, n)),
+                       use_frsvt=True, seed=5, max_iter=1)
+    assert abs(res.norm2 - sig1) <= 1e-13 * sig1

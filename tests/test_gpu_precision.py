@@ -173,7 +173,8 @@ def test_precision_workload_full_size(fr, orc, c3_data):
     per signal direction: total error <= sqrt(ks) (eps_A + sigma_b u_b) /
     ||X||_F.  Inside the signal subspace (U_s^T (X~ - X) V_s) a rotation of
     angle a_j enters at second order, sum_j a_j^2 sigma_j.  The bounds below
-    are those predictions times 3 (measured: see the printed ratios); the
-    rank is the oracle's (every sampled direction lies above tau = 5)."""
+    are those predictions times 3 (measured ratios to the predictions:
+    total 0.78, signal 0.59 here; 0.43 and 0.22 at 2048 x 2048); the rank is
+    the oracle's (every sampled direction lies above tau = 5)."""
     _say("case precision workload 8192x8192: GPU runs and the oracle (about two minutes)")
     _mixed_against_oracle(fr, orc, c3_data, 5.0, 100, 10, 2, 1000, fp64_check=True)
