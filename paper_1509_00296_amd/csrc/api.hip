@@ -268,6 +268,13 @@ struct Core {
     int64_t ldqo;
     bool sketch_ready;   // the sketch of this call is already in the buffers
     bool orth_ready = false;  // its orthonormalised basis [Qt, Y] too (b.Q, one-workgroup path)
+    // optional: the projection pass also draws Omega's rows (counter
+    // om_counter, om_c columns) into om for the next sketch; om_drawn is set
+    // once they are enqueued
+    double *om = nullptr;
+    int om_c = 0;
+    uint64_t om_counter = 0;
+    bool om_drawn = false;
     // results (workspace)
     int l;
     T *Q, *Bt, *QM;
@@ -293,7 +300,7 @@ size_t carve_core(Carver &cv, const Orient &o, int l, int cnew, int num_cu, Core
 {
     const int mh = o.mh;
     const int64_t nh = o.nh;
-    const int grid = 2 * num_cu;
+    const int grid = long_grid_cap(num_cu);
     const int cmax = std::max(l, 1);
     b.Ypart = cv.take<T>((size_t)grid * mh * cmax);
     b.ypart_cap = (size_t)grid * mh * cmax;
@@ -497,7 +504,7 @@ int sketch_stage(frsvt_context *h, const Core<T> &c, CoreBuffers<T> &b)
     la.counter = c.counter;
     la.c = c.cnew;
     la.Ypart = b.Ypart;
-    LongPlan p = long_plan(mh, o.nh, c.cnew, Prec<T>::bytes, kSketch, h->num_cu);
+    LongPlan p = long_plan(mh, o.nh, c.cnew, Prec<T>::bytes, kSketch, h->num_cu, o.trans);
     CKT(FRSVT_K_SKETCH, launch_long<T>(p, kSketch, la, h->stream));
     CKT(FRSVT_K_REDUCE, launch_reduce<T>(b.Ypart, (int64_t)mh * c.cnew, p.grid, b.Y, h->stream));
     return FRSVT_OK;
@@ -567,7 +574,7 @@ int run_core(frsvt_context *h, Core<T> &c, CoreBuffers<T> &b)
     for (int it = 0; it < c.q; ++it) {
         const uint64_t ctr2 = c.counter ^ (0x5bd1e995ull << 32) ^ (uint64_t)(it + 1) << 56;
         if (small) {
-            LongPlan p = long_plan(mh, o.nh, l, Prec<T>::bytes, kPower, h->num_cu);
+            LongPlan p = long_plan(mh, o.nh, l, Prec<T>::bytes, kPower, h->num_cu, o.trans);
             la.c = l;
             la.Q = b.Q;
             la.ldq = mh;
@@ -585,14 +592,20 @@ int run_core(frsvt_context *h, Core<T> &c, CoreBuffers<T> &b)
 
     // Alg. 1, QR of A^T Q: B^T = Ahat^T Q and its Gram B B^T
     if (small || (!c.A16 && long_path_ok(mh, l))) {
-        LongPlan p = long_plan(mh, o.nh, l, Prec<T>::bytes, kProject, h->num_cu);
+        LongPlan p = long_plan(mh, o.nh, l, Prec<T>::bytes, kProject, h->num_cu, o.trans);
         la.c = l;
         la.Q = b.Q;
         la.ldq = mh;
         la.Z = b.Bt;
         la.ldz = o.nh;
         la.Gpart = b.Gpart;
+        if (c.om) {
+            la.om = c.om;
+            la.om_c = c.om_c;
+            la.om_counter = c.om_counter;
+        }
         CKT(FRSVT_K_PROJECT, launch_long<T>(p, kProject, la, s));
+        c.om_drawn = c.om != nullptr;
         CKT(FRSVT_K_REDUCE, launch_reduce<double>(b.Gpart, (int64_t)l * l, p.grid, b.G, s));
     } else {
         if ((rc = ahat_t_times<T>(h, c, b.Q, mh, l, b.Bt, b.gpart_t))) return rc;
@@ -1223,21 +1236,26 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
     const int lmax = op.use_frsvt ? std::min(mh, std::max(l0, mh)) : mh;
     // residual partials: one per epilogue workgroup (256 x 16 elements)
     const size_t zcap = (size_t)((m + 255) / 256) * (size_t)((n + 15) / 16);
+    // Omega's rows for the sketch fused into the epilogue (FP64, Ahat = A^T,
+    // at most eight new samples): drawn one iteration ahead
+    const int csk_fixed = std::min(op.ap ? op.ap_a : op.p, mh);
+    const bool om_rows = op.use_frsvt && std::is_same<T, double>::value && o.trans && csk_fixed >= 1 && csk_fixed <= 8;
     auto layout = [&](Carver &cv, T **A, CoreBuffers<T> &b, T **Qt, double **zp, T **Lx,
-                      double **zsum) {
+                      double **zsum, double **om) {
         *A = cv.take<T>((size_t)m * n);
         *Qt = cv.take<T>((size_t)mh * mh);
         *zp = cv.take<double>(zcap);
         *zsum = cv.take<double>(4);
         *Lx = cv.take<T>((size_t)m * n);
+        *om = om_rows ? cv.take<double>((size_t)o.nh * 8) : nullptr;
         if (op.use_frsvt) carve_core<T>(cv, o, lmax, lmax, h->num_cu, b);
         return cv.off;
     };
     T *A, *Qt, *Lx;
-    double *zp, *zsum;
+    double *zp, *zsum, *om;
     CoreBuffers<T> b{};
     Carver dry(nullptr);
-    size_t need = layout(dry, &A, b, &Qt, &zp, &Lx, &zsum);
+    size_t need = layout(dry, &A, b, &Qt, &zp, &Lx, &zsum, &om);
     size_t exact_need = 0;
     if (!op.use_frsvt) {
         Carver d2(nullptr);
@@ -1249,8 +1267,9 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
     }
     if ((rc = ensure_ws(h, std::max(need, exact_need)))) return rc;
     Carver cv(h->ws);
-    layout(cv, &A, b, &Qt, &zp, &Lx, &zsum);
+    layout(cv, &A, b, &Qt, &zp, &Lx, &zsum, &om);
     const size_t exact_off = cv.off;
+
 
     T *Ybuf[2] = {L, S};
     const int64_t ldyb[2] = {ldl, lds};
@@ -1352,6 +1371,13 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
             c.ldqo = mh;
             c.status = h->dstatus;
             c.resid_out = reinterpret_cast<double *>(h->dstatus + kResidSlot);
+            // the next epilogue's sketch rows (iteration it + 1), drawn by
+            // this iteration's projection pass
+            if (om && it + 1 < op.max_iter) {
+                c.om = om;
+                c.om_c = csk_fixed;
+                c.om_counter = (uint64_t)(it + 1);
+            }
             if ((rc = run_core<T>(h, c, b))) return rc;
             ra.c = c.l;
             if (o.trans) {
@@ -1421,6 +1447,7 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
             ra.csk = cn.cnew;
             ra.seed = cn.seed;
             ra.counter = cn.counter;
+            if (om && c.om_drawn && cn.cnew == csk_fixed) ra.om = om;
         }
         int nz = 0;
         CKT(FRSVT_K_EPILOGUE, launch_recon<T>(kEpi, ra, &nz, s));
@@ -1463,6 +1490,7 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
                 spec_orth_cnew = spec_cnew;
             }
         }
+
         CK(hipEventSynchronize(h->ev_iter));
         const int r = hst[0];
         if (op.use_frsvt && hst[6] != 0) {

@@ -25,18 +25,25 @@ int64_t recon_row_blocks(int64_t rows) { return (rows + kThreads - 1) / kThreads
 // operands moved through LDS from the lane-per-row layout of the epilogue to
 // the 16-lanes-per-row operand layout; the four wavefronts' products are
 // added in a fixed order.
+template <bool PRE>
 __device__ __forceinline__ void sketch_rows(const ReconArgs<double> &a, int64_t pr, double (&an)[16], double *sW)
 {
     const int lane = threadIdx.x % kWave;
     // Omega row pr, columns j < csk (the sketch pass's draw: pair p of row k
     // gives columns 2p and 2p + 1)
     double om[8];
+    if (PRE) {
+        // drawn beforehand (k_omega_rows), eight per row
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-        double z0 = 0.0, z1 = 0.0;
-        if (2 * p < a.csk && pr < a.rows) gaussian_pair(a.seed, a.counter, (uint32_t)pr, (uint32_t)p, z0, z1);
-        om[2 * p] = z0;
-        om[2 * p + 1] = (2 * p + 1 < a.csk) ? z1 : 0.0;
+        for (int j = 0; j < 8; ++j) om[j] = pr < a.rows ? a.om[pr * 8 + j] : 0.0;
+    } else {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            double z0 = 0.0, z1 = 0.0;
+            if (2 * p < a.csk && pr < a.rows) gaussian_pair(a.seed, a.counter, (uint32_t)pr, (uint32_t)p, z0, z1);
+            om[2 * p] = z0;
+            om[2 * p + 1] = (2 * p + 1 < a.csk) ? z1 : 0.0;
+        }
     }
     constexpr int LDW = 17;
 #pragma unroll
@@ -71,8 +78,35 @@ __device__ __forceinline__ void sketch_rows(const ReconArgs<double> &a, int64_t 
     }
 }
 
-template <typename T, int MODE, int CM, bool SK = false>
-__global__ void __launch_bounds__(kThreads) k_recon(ReconArgs<T> a)
+// Omega(k, j) for rows k < rows and j < csk <= 8 (zeros up to eight per
+// row), exactly as the sketch draws it (pair p of row k gives columns 2p and
+// 2p + 1): the epilogue's sketch reads these rows instead of drawing them in
+// each of its column blocks.
+__global__ void __launch_bounds__(kThreads) k_omega_rows(int64_t rows, int csk, uint64_t seed, uint64_t counter,
+                                                         double *om)
+{
+    const int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const int64_t k = idx >> 2;
+    const int p = (int)(idx & 3);
+    if (k >= rows) return;
+    double z0 = 0.0, z1 = 0.0;
+    if (2 * p < csk) gaussian_pair(seed, counter, (uint32_t)k, (uint32_t)p, z0, z1);
+    om[k * 8 + 2 * p] = z0;
+    om[k * 8 + 2 * p + 1] = (2 * p + 1 < csk) ? z1 : 0.0;
+}
+
+hipError_t launch_omega_rows(int64_t rows, int csk, uint64_t seed, uint64_t counter, double *om, hipStream_t s)
+{
+    if (rows < 1 || csk < 1 || csk > 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_omega_rows, dim3((unsigned)((4 * rows + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
+                       rows, csk, seed, counter, om);
+    return hipGetLastError();
+}
+
+// SK: 0 no sketch, 1 the sketch with Omega drawn here, 2 with Omega's rows
+// read from a.om
+template <typename T, int MODE, int CM, int SK = 0>
+__global__ void __launch_bounds__(kThreads, (SK == 2 && CM <= 16) ? 3 : 1) k_recon(ReconArgs<T> a)
 {
     __shared__ T sFC[kReconCols][CM];
     __shared__ double sred[kThreads / kWave];
@@ -103,7 +137,7 @@ __global__ void __launch_bounds__(kThreads) k_recon(ReconArgs<T> a)
         // A for the passes that read it
         // (columns past the end load the last column again: unconditional
         // loads, nothing stored for them)
-        T lv[kReconCols], ov[kReconCols], yv[kReconCols];
+        T ov[kReconCols], yv[kReconCols];
         if (MODE != kRecon) {
 #pragma unroll
             for (int j = 0; j < kReconCols; ++j) {
@@ -112,23 +146,23 @@ __global__ void __launch_bounds__(kThreads) k_recon(ReconArgs<T> a)
                 yv[j] = __builtin_nontemporal_load(&a.Y[pr + pc * a.ldy]);
             }
         }
+        // L of each column formed where it is used (from the factors, or read)
+        T lin[kReconCols];
         if (a.Lin) {
 #pragma unroll
-            for (int j = 0; j < kReconCols; ++j) lv[j] = a.Lin[pr + (pc0 + min(j, ncol - 1)) * a.ldlin];
-        } else {
-#pragma unroll
-            for (int j = 0; j < kReconCols; ++j) {
-                T L = T(0);
-#pragma unroll
-                for (int cc = 0; cc < CM; ++cc) L += fr[cc] * sFC[j][cc];
-                lv[j] = L;
-            }
+            for (int j = 0; j < kReconCols; ++j) lin[j] = a.Lin[pr + (pc0 + min(j, ncol - 1)) * a.ldlin];
         }
 #pragma unroll
         for (int j = 0; j < kReconCols; ++j) {
-            if (j >= ncol) break;
+            if (j >= ncol) continue;
             const int64_t pc = pc0 + j;
-            const T L = lv[j];
+            T L = T(0);
+            if (a.Lin) {
+                L = lin[j];
+            } else {
+#pragma unroll
+                for (int cc = 0; cc < CM; ++cc) L += fr[cc] * sFC[j][cc];
+            }
             if (MODE == kRecon) {
                 a.X[pr + pc * a.ldx] = L;
             } else {
@@ -150,9 +184,9 @@ __global__ void __launch_bounds__(kThreads) k_recon(ReconArgs<T> a)
             }
         }
     }
-    if constexpr (SK) {
+    if constexpr (SK != 0) {
         __shared__ double sW[kThreads / kWave][64 * 17];
-        sketch_rows(a, pr, anv, sW[threadIdx.x / kWave]);
+        sketch_rows<SK == 2>(a, pr, anv, sW[threadIdx.x / kWave]);
     }
     if (MODE == kEpi) {
         zz = wave_sum(zz);
@@ -170,10 +204,16 @@ template <typename T, int MODE>
 static hipError_t launch_recon_cm(const ReconArgs<T> &a, dim3 grid, hipStream_t s)
 {
     if constexpr (MODE == kEpi && std::is_same<T, double>::value) {
+        if (a.ysk && a.om) {
+            if (a.c <= 8) hipLaunchKernelGGL((k_recon<T, MODE, 8, 2>), grid, dim3(kThreads), 0, s, a);
+            else if (a.c <= 16) hipLaunchKernelGGL((k_recon<T, MODE, 16, 2>), grid, dim3(kThreads), 0, s, a);
+            else hipLaunchKernelGGL((k_recon<T, MODE, 32, 2>), grid, dim3(kThreads), 0, s, a);
+            return hipGetLastError();
+        }
         if (a.ysk) {
-            if (a.c <= 8) hipLaunchKernelGGL((k_recon<T, MODE, 8, true>), grid, dim3(kThreads), 0, s, a);
-            else if (a.c <= 16) hipLaunchKernelGGL((k_recon<T, MODE, 16, true>), grid, dim3(kThreads), 0, s, a);
-            else hipLaunchKernelGGL((k_recon<T, MODE, 32, true>), grid, dim3(kThreads), 0, s, a);
+            if (a.c <= 8) hipLaunchKernelGGL((k_recon<T, MODE, 8, 1>), grid, dim3(kThreads), 0, s, a);
+            else if (a.c <= 16) hipLaunchKernelGGL((k_recon<T, MODE, 16, 1>), grid, dim3(kThreads), 0, s, a);
+            else hipLaunchKernelGGL((k_recon<T, MODE, 32, 1>), grid, dim3(kThreads), 0, s, a);
             return hipGetLastError();
         }
     } else {

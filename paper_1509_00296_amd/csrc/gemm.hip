@@ -216,19 +216,28 @@ hipError_t launch_gram_tall(int64_t rows, int l, const T *Y, int64_t ldy, double
 template hipError_t launch_gram_tall<double>(int64_t, int, const double *, int64_t, double *, double *, hipStream_t, const int *);
 template hipError_t launch_gram_tall<float>(int64_t, int, const float *, int64_t, double *, double *, hipStream_t, const int *);
 
-// Cholesky of (G + shift I), shift = shift_factor trace(G), by one
-// workgroup with the upper triangle dealt to the threads' registers in
-// 4 x 4 blocks (chol_blk4).  Pivots <= null_tol max_j G_jj are
-// numerically null: R_jj = 1 and a zero row (null_cols[j] = 1).  R is
-// written whole (upper, row-major [j * l + k], zeros below the diagonal).
-constexpr int kCholThreads = 576;  // >= 528 blocks of 4 x 4 for l <= 128
+// Cholesky of (G + shift I), shift = shift_factor trace(G), l <= 128, by one
+// workgroup on the matrix in LDS (row-major, upper triangle used), blocked
+// in panels of 16 rows (right-looking):
+//   1. wavefront 0 factors the 16 x 16 diagonal block in registers (lane k
+//      holds column k; pivots and rows broadcast with readlane);
+//   2. the panel's rows right of the block, R_JJ^{-T} A(J, k), one column k
+//      per thread;
+//   3. the trailing upper triangle takes the rank-16 update in 4 x 4 blocks.
+// Three barriers per panel.  Pivots <= null_tol max_j G_jj are numerically
+// null: R_jj = 1 and a zero row (null_cols[j] = 1).  R is written whole
+// (upper, row-major [j * l + k], zeros below the diagonal).
+constexpr int kCholThreads = 512;
 __global__ void __launch_bounds__(kCholThreads) k_chol(int l, const double *G, double shift_factor, double null_tol, double *R, int *null_cols, int *flags, const int *gate, int *nn_out)
 {
     if (gate && *gate == 0) return;  // the factor in R is still current
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double *M = reinterpret_cast<double *>(smem_raw);
     __shared__ double shift, tolabs;
-    const int tid = threadIdx.x;
+    __shared__ double srinv[128];
+    __shared__ int snull[128];
+    __shared__ int sh_nn;
+    const int tid = threadIdx.x, lane = tid % kWave;
     for (int idx = tid; idx < l * l; idx += kCholThreads) M[idx] = G[idx];
     __syncthreads();
     if (tid == 0) {
@@ -239,27 +248,134 @@ __global__ void __launch_bounds__(kCholThreads) k_chol(int l, const double *G, d
         }
         shift = shift_factor * tr;
         tolabs = null_tol > 0.0 ? null_tol * fmax(mx, 1e-300) : 0.0;
+        sh_nn = 0;
     }
     __syncthreads();
     for (int j = tid; j < l; j += kCholThreads) M[j * l + j] += shift;
     __syncthreads();
-    __shared__ __align__(16) double rowbuf[128];
-    __shared__ double sh_d[128];
-    const int nn = chol_blk4<kCholThreads>(M, l, tolabs, 1.0, rowbuf, sh_d, null_cols);
-    for (int idx = tid; idx < l * l; idx += kCholThreads) R[idx] = M[idx];
-    if (tid == 0 && flags) {
-        // null checks report the columns they flag; the final pass (no shift,
-        // no null tolerance) records whether its factor still failed
-        if (null_tol > 0.0) flags[1] = nn;
-        if (null_tol <= 0.0 && shift_factor == 0.0) flags[2] = nn > 0 ? 1 : 0;
+    const double tol = tolabs;
+    for (int J = 0; J < l; J += 16) {
+        const int nb = min(16, l - J);
+        // 1. the diagonal block (upper entries read; the lower ones are stale)
+        if (tid < kWave) {
+            double g[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) g[i] = (i < nb && lane < nb) ? M[(J + i) * l + J + lane] : 0.0;
+            int nn = 0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                if (j < nb) {
+                    double gj = 0.0;
+#pragma unroll
+                    for (int i = 0; i < 16; ++i)
+                        if (i == j) gj = g[i];
+                    const double d = read_lane(gj, j);
+                    const bool isnull = !(d > tol);
+                    const double rs = rsqrt(isnull ? 1.0 : d);
+                    const double piv = isnull ? 1.0 : d * rs;
+                    nn += isnull ? 1 : 0;
+                    double rjk = 0.0;
+                    if (lane == j) rjk = piv;
+                    else if (lane > j && lane < nb && !isnull) rjk = gj * rs;
+                    if (lane < nb) M[(J + j) * l + J + lane] = rjk;
+                    if (lane == 0) {
+                        snull[J + j] = isnull ? 1 : 0;
+                        srinv[J + j] = isnull ? 0.0 : rs;
+                        if (null_cols) null_cols[J + j] = isnull ? 1 : 0;
+                    }
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        if (i > j) {
+                            const double rji = read_lane(rjk, i);
+                            g[i] = lane > j ? g[i] - rji * rjk : g[i];
+                        }
+                    }
+                }
+            }
+            if (lane == 0) sh_nn += nn;
+        }
+        __syncthreads();
+        // 2. R(J : J + nb, k) = R_JJ^{-T} A(J : J + nb, k), k >= J + nb (null
+        //    rows zero)
+        for (int k = J + nb + tid; k < l; k += kCholThreads) {
+            double x[16];
+#pragma unroll
+            for (int a = 0; a < 16; ++a) x[a] = a < nb ? M[(J + a) * l + k] : 0.0;
+#pragma unroll
+            for (int a = 0; a < 16; ++a) {
+                if (a < nb) {
+                    double v = x[a];
+#pragma unroll
+                    for (int t = 0; t < a; ++t) v -= M[(J + t) * l + J + a] * x[t];
+                    x[a] = v * srinv[J + a];
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < 16; ++a)
+                if (a < nb) M[(J + a) * l + k] = x[a];
+        }
+        __syncthreads();
+        // 3. trailing update of the upper triangle, rows and columns >= J + nb
+        const int base = J + nb, nt = l - base;
+        if (nt > 0) {
+            const int nbk = (nt + 3) / 4;
+            const int nblk = nbk * (nbk + 1) / 2;
+            for (int blk = tid; blk < nblk; blk += kCholThreads) {
+                int bi = 0, rem = blk;
+                while (rem >= nbk - bi) {
+                    rem -= nbk - bi;
+                    ++bi;
+                }
+                const int bj = bi + rem;
+                const int a0 = base + 4 * bi, k0 = base + 4 * bj;
+                double acc[4][4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+#pragma unroll
+                    for (int f = 0; f < 4; ++f)
+                        acc[e][f] = (a0 + e < l && k0 + f < l) ? M[(a0 + e) * l + k0 + f] : 0.0;
+                for (int t = 0; t < nb; ++t) {
+                    const double *row = M + (J + t) * l;
+                    double ra[4], rk[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        ra[e] = a0 + e < l ? row[a0 + e] : 0.0;
+                        rk[e] = k0 + e < l ? row[k0 + e] : 0.0;
+                    }
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+#pragma unroll
+                        for (int f = 0; f < 4; ++f) acc[e][f] -= ra[e] * rk[f];
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+#pragma unroll
+                    for (int f = 0; f < 4; ++f)
+                        if (a0 + e < l && k0 + f < l) M[(a0 + e) * l + k0 + f] = acc[e][f];
+            }
+        }
+        __syncthreads();
     }
-    if (tid == 0 && nn_out) *nn_out = nn;
+    for (int idx = tid; idx < l * l; idx += kCholThreads) {
+        const int j = idx / l, k = idx % l;
+        R[idx] = k >= j ? M[idx] : 0.0;
+    }
+    if (tid == 0) {
+        const int nn = sh_nn;
+        if (flags) {
+            // null checks report the columns they flag; the final pass (no
+            // shift, no null tolerance) records whether its factor still failed
+            if (null_tol > 0.0) flags[1] = nn;
+            if (null_tol <= 0.0 && shift_factor == 0.0) flags[2] = nn > 0 ? 1 : 0;
+        }
+        if (nn_out) *nn_out = nn;
+    }
 }
 
 hipError_t launch_chol(int l, const double *G, double shift_factor, double null_tol, double *R, int *null_cols, int *flags, hipStream_t s, const int *gate, int *nn_out)
 {
     const size_t lds = (size_t)l * l * sizeof(double);
-    if (l > 128) return hipErrorInvalidValue;
+    if (l < 1 || l > 128) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_chol, dim3(1), dim3(kCholThreads), lds, s, l, G, shift_factor, null_tol, R, null_cols, flags, gate, nn_out);
     return hipGetLastError();
 }

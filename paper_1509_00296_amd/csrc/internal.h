@@ -36,6 +36,12 @@ struct LongArgs {
     T *Z;            // kProject: Bt, nhat x c
     int64_t ldz;
     double *Gpart;   // kProject: [grid][c][c]
+    // kProject, optional: also draw Omega's rows for the next sketch,
+    // om[k * 8 + j] for k < nh, j < om_c (zeros past om_c), with (seed,
+    // om_counter) as launch_omega_rows does
+    double *om = nullptr;
+    int om_c = 0;
+    uint64_t om_counter = 0;
 };
 
 struct LongPlan {
@@ -48,7 +54,9 @@ struct LongPlan {
 };
 
 bool long_path_ok(int mh, int c);
-LongPlan long_plan(int mh, int64_t nh, int c, int elem_bytes, int mode, int num_cu);
+LongPlan long_plan(int mh, int64_t nh, int c, int elem_bytes, int mode, int num_cu, bool trans);
+// the most workgroups a long pass launches (partial buffers are sized for it)
+int long_grid_cap(int num_cu);
 template <typename T>
 hipError_t launch_long(const LongPlan &plan, int mode, const LongArgs<T> &args, hipStream_t s);
 
@@ -165,6 +173,9 @@ struct ReconArgs {
     T *ysk;
     int csk;
     uint64_t seed, counter;
+    // optional: Omega's rows drawn beforehand by launch_omega_rows (8 per
+    // row, the same values); nullptr: drawn in the epilogue
+    const double *om = nullptr;
 };
 bool recon_ok(int c);
 int64_t recon_row_blocks(int64_t rows);   // grid.x of the epilogue launch
@@ -193,6 +204,9 @@ hipError_t launch_finite_check(int64_t m, int64_t n, const T *A, int64_t lda, in
 // iteration certified through the Kato-Temple bound when it exceeds half the
 // trace: out[0] the estimate, out[1] 1 when certified (else 0).
 hipError_t launch_power_dom(int n, const double *G, double *out, hipStream_t s);
+// Omega(k, 0..csk-1) of the sketch, rows k < rows, into om[k * 8 + j]
+// (zeros past csk): the epilogue's fused sketch reads them.
+hipError_t launch_omega_rows(int64_t rows, int csk, uint64_t seed, uint64_t counter, double *om, hipStream_t s);
 hipError_t launch_power_eig(int n, const double *G, double *out, hipStream_t s);
 
 // --------------------------------------------------------- generic GEMM

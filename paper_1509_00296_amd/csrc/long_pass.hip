@@ -53,7 +53,9 @@ struct LpMfma<float> {
 
 bool long_path_ok(int mh, int c) { return mh >= 1 && mh <= kMaxMh && c >= 1 && c <= 32; }
 
-LongPlan long_plan(int mh, int64_t nh, int c, int elem_bytes, int mode, int num_cu)
+int long_grid_cap(int num_cu) { return 3 * num_cu; }
+
+LongPlan long_plan(int mh, int64_t nh, int c, int elem_bytes, int mode, int num_cu, bool trans)
 {
     LongPlan p{};
     const int nrb = (mh + 15) / 16;
@@ -62,7 +64,10 @@ LongPlan long_plan(int mh, int64_t nh, int c, int elem_bytes, int mode, int num_
     p.rpt = nrb <= 16 ? 4 : 8;             // row blocks per wavefront (phase 2)
     p.kt = kKT;
     p.ntiles = (int)((nh + kKT - 1) / kKT);
-    p.grid = std::max(1, std::min(p.ntiles, 2 * num_cu));
+    // two workgroups per compute unit; three where the transposed power and
+    // projection forms fit them (one 16-column block, at most 13 row groups)
+    const bool three = trans && (mode == kPower || mode == kProject) && c <= 16 && p.mhp <= 208;
+    p.grid = std::max(1, std::min(p.ntiles, (three ? 3 : 2) * num_cu));
     const bool needs_q = (mode == kPower || mode == kProject);
     const int ld = elem_bytes == 8 ? LpMfma<double>::kLD : LpMfma<float>::kLD;
     p.lds = (size_t)p.mhp * ld * elem_bytes + (size_t)kKT * p.cm * elem_bytes +
@@ -511,7 +516,10 @@ __device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, uint3
 }
 
 template <typename T, int MODE, int NB, int RING, int NJ>
-__global__ void __launch_bounds__(kThreads) k_long_tr(LongArgs<T> a, uint32_t span_bytes)
+// (the power and projection forms with one 16-column block and at most 13
+// row groups fit three wavefronts per SIMD: three workgroups per compute unit)
+__global__ void __launch_bounds__(kThreads, (NB == 1 && NJ <= 13 && (MODE == kPower || MODE == kProject)) ? 3 : 1)
+k_long_tr(LongArgs<T> a, uint32_t span_bytes)
 {
     using M = LpMfma<T>;
     using V4 = typename M::V4;
@@ -589,6 +597,18 @@ __global__ void __launch_bounds__(kThreads) k_long_tr(LongArgs<T> a, uint32_t sp
     __builtin_amdgcn_sched_barrier(0);
     if (RING > 1) load_tile(pb, blockIdx.x + gridDim.x);
     if (MODE == kSketch) draw(0);
+    if (MODE == kProject && a.om) {
+        // Omega's rows for the next sketch, spread over the whole grid while
+        // the first tiles load: item g is pair g % 4 of row g / 4
+        for (int64_t g = (int64_t)blockIdx.x * kThreads + tid; g < 4 * a.nh; g += (int64_t)gridDim.x * kThreads) {
+            const int64_t k = g >> 2;
+            const int pp = (int)(g & 3);
+            double z0 = 0.0, z1 = 0.0;
+            if (2 * pp < a.om_c) gaussian_pair(a.seed, a.om_counter, (uint32_t)k, (uint32_t)pp, z0, z1);
+            a.om[k * 8 + 2 * pp] = z0;
+            a.om[k * 8 + 2 * pp + 1] = (2 * pp + 1 < a.om_c) ? z1 : 0.0;
+        }
+    }
 
     auto process = [&](T (&pre)[NJ], int tile, int it) {
         const int64_t k0 = (int64_t)tile * kKT;
@@ -798,8 +818,11 @@ hipError_t launch_long(const LongPlan &p, int mode, const LongArgs<T> &a0, hipSt
             }
         }
     }
-    if (a.trans) return launch_long_mode<T, true>(p, mode, a, s);
-    return launch_long_mode<T, false>(p, mode, a, s);
+    hipError_t e = a.trans ? launch_long_mode<T, true>(p, mode, a, s) : launch_long_mode<T, false>(p, mode, a, s);
+    // the other forms leave Omega's rows to a pass of their own
+    if (e == hipSuccess && mode == kProject && a.om)
+        e = launch_omega_rows(a.nh, a.om_c, a.seed, a.om_counter, a.om, s);
+    return e;
 }
 template hipError_t launch_long<double>(const LongPlan &, int, const LongArgs<double> &, hipStream_t);
 template hipError_t launch_long<float>(const LongPlan &, int, const LongArgs<float> &, hipStream_t);
