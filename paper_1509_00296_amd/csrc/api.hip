@@ -459,6 +459,45 @@ int big_orth(frsvt_context *h, int64_t rows, int l, T *Y, int64_t ldy, CoreBuffe
              uint64_t seed, uint64_t counter, int *flags)
 {
     int rc;
+    // Fast path (not under graph capture: it reads two status words on the
+    // host): equilibration, then CholeskyQR2 in double precision with the
+    // checks of the one-workgroup path (no pivot at or below 1e-8 of the
+    // equilibrated diagonal in the first factor, every pivot of the second
+    // within 1e-6 of 1).  A float basis is orthonormalised on a double copy
+    // (written back at the end); a double one in place, its equilibrated
+    // copy kept.  On a failed check the robust sequence below runs from the
+    // basis as it came (float) or from the equilibrated copy (double).
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    CK(hipStreamIsCapturing(h->stream, &cap));
+    const bool dbl = std::is_same<T, double>::value;
+    const size_t need_f = 2 * (size_t)rows * l * sizeof(double);   // float: double copy + spare
+    if (cap == hipStreamCaptureStatusNone && l <= 128 && b.jwork && ldy == rows &&
+        (dbl ? b.Qtmp != nullptr : (b.gpart_t != nullptr && (size_t)128 * rows * l * sizeof(T) >= need_f))) {
+        int *nn = h->dstatus + kGateSlot + 1;  // two words
+        double *Yd = dbl ? reinterpret_cast<double *>(Y) : reinterpret_cast<double *>(b.gpart_t);
+        if (!dbl) CKT(FRSVT_K_ORTH, launch_cast<double>(rows, l, Y, 0, ldy, Yd, rows, h->stream));
+        if ((rc = gram<double>(h, rows, l, Yd, rows, b.G, b.gpart_d))) return rc;
+        CKT(FRSVT_K_ORTH, launch_col_scale<double>(rows, l, Yd, rows, b.G, h->stream));
+        CKT(FRSVT_K_ORTH, launch_scale_gram(l, b.G, b.jwork, h->stream));
+        if (dbl) CK(hipMemcpyAsync(b.Qtmp, Yd, (size_t)rows * l * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+        CKT(FRSVT_K_ORTH, launch_chol(l, b.jwork, 0.0, 1e-8, b.R, b.nullc, nullptr, h->stream, nullptr, nn));
+        CKT(FRSVT_K_ORTH, launch_trsm<double>(rows, l, Yd, rows, b.R, h->stream));
+        if ((rc = gram<double>(h, rows, l, Yd, rows, b.G, b.gpart_d))) return rc;
+        CKT(FRSVT_K_ORTH, launch_chol(l, b.G, 0.0, 0.5, b.R, b.nullc, nullptr, h->stream, nullptr, nn + 1, 1e-6));
+        CKT(FRSVT_K_ORTH, launch_trsm<double>(rows, l, Yd, rows, b.R, h->stream));
+        CK(hipMemcpyAsync(h->pinned, nn, 2 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+        CK(hipStreamSynchronize(h->stream));
+        const int *hn = (const int *)h->pinned;
+        if (hn[0] == 0 && hn[1] == 0) {
+            if (!dbl) CKT(FRSVT_K_ORTH, launch_cast<T>(rows, l, Yd, 1, rows, Y, ldy, h->stream));
+            if (flags) {
+                CKT(FRSVT_K_OTHER, launch_fill_int(flags, 3, 0, h->stream));
+                CKT(FRSVT_K_OTHER, launch_fill_int(flags, 1, 1, h->stream));
+            }
+            return FRSVT_OK;
+        }
+        if (dbl) CK(hipMemcpyAsync(Y, b.Qtmp, (size_t)rows * l * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    }
     if ((rc = gram(h, rows, l, Y, ldy, b.G, b.gpart_d))) return rc;
     CKT(FRSVT_K_ORTH, launch_col_scale<T>(rows, l, Y, ldy, b.G, h->stream));
     const double shift = 11.0 * ((double)rows * l + (double)l * (l + 1)) * kU;

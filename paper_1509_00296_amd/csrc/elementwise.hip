@@ -25,8 +25,10 @@ int64_t recon_row_blocks(int64_t rows) { return (rows + kThreads - 1) / kThreads
 // operands moved through LDS from the lane-per-row layout of the epilogue to
 // the 16-lanes-per-row operand layout; the four wavefronts' products are
 // added in a fixed order.
+// (ncol_blk: the workgroup's column count, 8 or 16; an[] holds zeros past it)
 template <bool PRE>
-__device__ __forceinline__ void sketch_rows(const ReconArgs<double> &a, int64_t pr, double (&an)[16], double *sW)
+__device__ __forceinline__ void sketch_rows(const ReconArgs<double> &a, int64_t pr, int rb, int cb, int ncol_blk,
+                                            double (&an)[16], double *sW)
 {
     const int lane = threadIdx.x % kWave;
     // Omega row pr, columns j < csk (the sketch pass's draw: pair p of row k
@@ -71,10 +73,10 @@ __device__ __forceinline__ void sketch_rows(const ReconArgs<double> &a, int64_t 
     __syncthreads();
     if (threadIdx.x < 128) {
         const int j = threadIdx.x >> 4, i = threadIdx.x & 15;
-        const int64_t pc = (int64_t)blockIdx.y * kReconCols + i;
+        const int64_t pc = (int64_t)cb * ncol_blk + i;
         const double t = ((sC[(0 * 8 + j) * 16 + i] + sC[(1 * 8 + j) * 16 + i]) + sC[(2 * 8 + j) * 16 + i]) +
                          sC[(3 * 8 + j) * 16 + i];
-        if (j < a.csk && pc < a.cols) a.ysk[(int64_t)blockIdx.x * a.cols * a.csk + pc + (int64_t)j * a.cols] = t;
+        if (j < a.csk && i < ncol_blk && pc < a.cols) a.ysk[(int64_t)rb * a.cols * a.csk + pc + (int64_t)j * a.cols] = t;
     }
 }
 
@@ -105,13 +107,22 @@ hipError_t launch_omega_rows(int64_t rows, int csk, uint64_t seed, uint64_t coun
 
 // SK: 0 no sketch, 1 the sketch with Omega drawn here, 2 with Omega's rows
 // read from a.om
-template <typename T, int MODE, int CM, int SK = 0>
+template <typename T, int MODE, int CM, int SK = 0, int NC = kReconCols>
 __global__ void __launch_bounds__(kThreads, (SK == 2 && CM <= 16) ? 3 : 1) k_recon(ReconArgs<T> a)
 {
+    constexpr int kReconCols = NC;   // this instantiation's columns per workgroup
     __shared__ T sFC[kReconCols][CM];
     __shared__ double sred[kThreads / kWave];
-    const int64_t pr = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    const int64_t pc0 = (int64_t)blockIdx.y * kReconCols;
+    // XCD-aware tile order: workgroups are dealt to the eight XCDs in turn
+    // (w mod 8), so workgroup w takes row block 8 (i / nb) + w mod 8 and
+    // column block i mod nb, i = w / 8, nb column blocks: every column block
+    // of a row block runs on one XCD, one after the other, and the row
+    // factors (and the sketch's Omega rows) they all read stay in its L2
+    const int xcd = (int)(blockIdx.x & 7), wi = (int)(blockIdx.x >> 3);
+    const int rb = (wi / a.ncb) * 8 + xcd, cb = wi % a.ncb;
+    if (rb >= a.nrb) return;
+    const int64_t pr = (int64_t)rb * kThreads + threadIdx.x;
+    const int64_t pc0 = (int64_t)cb * kReconCols;
     const int c = a.c;
     for (int idx = threadIdx.x; idx < kReconCols * CM; idx += kThreads) {
         const int j = idx / CM, cc = idx % CM;
@@ -123,9 +134,9 @@ __global__ void __launch_bounds__(kThreads, (SK == 2 && CM <= 16) ? 3 : 1) k_rec
     for (int cc = 0; cc < CM; ++cc) fr[cc] = (cc < c && pr < a.rows && a.FR) ? a.FR[pr + (int64_t)cc * a.ldfr] : T(0);
     __syncthreads();
     double zz = 0.0;
-    T anv[SK ? kReconCols : 1];
+    T anv[SK ? 16 : 1];
 #pragma unroll
-    for (int j = 0; j < (SK ? kReconCols : 1); ++j) anv[j] = T(0);
+    for (int j = 0; j < (SK ? 16 : 1); ++j) anv[j] = T(0);
     if (pr < a.rows) {
         const T mu = (T)a.mu, inv_mu = (T)(1.0 / a.mu), inv_mu_next = (T)(1.0 / a.mu_next);
         const T thr = (T)(a.lam / a.mu);
@@ -186,7 +197,7 @@ __global__ void __launch_bounds__(kThreads, (SK == 2 && CM <= 16) ? 3 : 1) k_rec
     }
     if constexpr (SK != 0) {
         __shared__ double sW[kThreads / kWave][64 * 17];
-        sketch_rows<SK == 2>(a, pr, anv, sW[threadIdx.x / kWave]);
+        sketch_rows<SK == 2>(a, pr, rb, cb, kReconCols, anv, sW[threadIdx.x / kWave]);
     }
     if (MODE == kEpi) {
         zz = wave_sum(zz);
@@ -195,7 +206,7 @@ __global__ void __launch_bounds__(kThreads, (SK == 2 && CM <= 16) ? 3 : 1) k_rec
         if (threadIdx.x == 0) {
             double s = 0.0;
             for (int w = 0; w < kThreads / kWave; ++w) s += sred[w];
-            a.zpart[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+            a.zpart[(int64_t)cb * a.nrb + rb] = s;
         }
     }
 }
@@ -203,6 +214,7 @@ __global__ void __launch_bounds__(kThreads, (SK == 2 && CM <= 16) ? 3 : 1) k_rec
 template <typename T, int MODE>
 static hipError_t launch_recon_cm(const ReconArgs<T> &a, dim3 grid, hipStream_t s)
 {
+    // (a carries nrb, ncb; the grid is 8 ceil(nrb / 8) ncb workgroups)
     if constexpr (MODE == kEpi && std::is_same<T, double>::value) {
         if (a.ysk && a.om) {
             if (a.c <= 8) hipLaunchKernelGGL((k_recon<T, MODE, 8, 2>), grid, dim3(kThreads), 0, s, a);
@@ -230,11 +242,17 @@ hipError_t launch_recon(int mode, const ReconArgs<T> &a, int *nparts, hipStream_
 {
     if (!recon_ok(a.c)) return hipErrorInvalidValue;
     if (a.ysk && (mode != kEpi || a.csk < 1 || a.csk > 8)) return hipErrorInvalidValue;
-    dim3 grid((unsigned)((a.rows + kThreads - 1) / kThreads), (unsigned)((a.cols + kReconCols - 1) / kReconCols));
-    if (nparts) *nparts = (int)(grid.x * grid.y);
-    if (mode == kRecon) return launch_recon_cm<T, kRecon>(a, grid, s);
-    if (mode == kEpi) return launch_recon_cm<T, kEpi>(a, grid, s);
-    return launch_recon_cm<T, kFinal>(a, grid, s);
+    ReconArgs<T> b = a;
+    const int ncol = kReconCols;
+    const int64_t nrb = (a.rows + kThreads - 1) / kThreads, ncb = (a.cols + ncol - 1) / ncol;
+    if (nrb < 1 || ncb < 1 || 8 * ((nrb + 7) / 8) * ncb > (int64_t)0x7fffffff) return hipErrorInvalidValue;
+    b.nrb = (int)nrb;
+    b.ncb = (int)ncb;
+    dim3 grid((unsigned)(8 * ((nrb + 7) / 8) * ncb));
+    if (nparts) *nparts = (int)(nrb * ncb);
+    if (mode == kRecon) return launch_recon_cm<T, kRecon>(b, grid, s);
+    if (mode == kEpi) return launch_recon_cm<T, kEpi>(b, grid, s);
+    return launch_recon_cm<T, kFinal>(b, grid, s);
 }
 template hipError_t launch_recon<double>(int, const ReconArgs<double> &, int *, hipStream_t);
 template hipError_t launch_recon<float>(int, const ReconArgs<float> &, int *, hipStream_t);

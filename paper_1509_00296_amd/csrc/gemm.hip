@@ -228,7 +228,10 @@ template hipError_t launch_gram_tall<float>(int64_t, int, const float *, int64_t
 // null: R_jj = 1 and a zero row (null_cols[j] = 1).  R is written whole
 // (upper, row-major [j * l + k], zeros below the diagonal).
 constexpr int kCholThreads = 512;
-__global__ void __launch_bounds__(kCholThreads) k_chol(int l, const double *G, double shift_factor, double null_tol, double *R, int *null_cols, int *flags, const int *gate, int *nn_out)
+// near_one > 0: a pivot further than near_one from 1 is also counted (and
+// treated) as null (the second CholeskyQR pass's check that the Gram is
+// near the identity).
+__global__ void __launch_bounds__(kCholThreads) k_chol(int l, const double *G, double shift_factor, double null_tol, double *R, int *null_cols, int *flags, const int *gate, int *nn_out, double near_one)
 {
     if (gate && *gate == 0) return;  // the factor in R is still current
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -270,7 +273,8 @@ __global__ void __launch_bounds__(kCholThreads) k_chol(int l, const double *G, d
                     for (int i = 0; i < 16; ++i)
                         if (i == j) gj = g[i];
                     const double d = read_lane(gj, j);
-                    const bool isnull = !(d > tol);
+                    bool isnull = !(d > tol);
+                    if (near_one > 0.0 && !isnull) isnull = !(fabs(sqrt(d) - 1.0) <= near_one);
                     const double rs = rsqrt(isnull ? 1.0 : d);
                     const double piv = isnull ? 1.0 : d * rs;
                     nn += isnull ? 1 : 0;
@@ -372,11 +376,29 @@ __global__ void __launch_bounds__(kCholThreads) k_chol(int l, const double *G, d
     }
 }
 
-hipError_t launch_chol(int l, const double *G, double shift_factor, double null_tol, double *R, int *null_cols, int *flags, hipStream_t s, const int *gate, int *nn_out)
+hipError_t launch_chol(int l, const double *G, double shift_factor, double null_tol, double *R, int *null_cols, int *flags, hipStream_t s, const int *gate, int *nn_out, double near_one)
 {
     const size_t lds = (size_t)l * l * sizeof(double);
     if (l < 1 || l > 128) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_chol, dim3(1), dim3(kCholThreads), lds, s, l, G, shift_factor, null_tol, R, null_cols, flags, gate, nn_out);
+    hipLaunchKernelGGL(k_chol, dim3(1), dim3(kCholThreads), lds, s, l, G, shift_factor, null_tol, R, null_cols, flags, gate, nn_out, near_one);
+    return hipGetLastError();
+}
+
+// G_out(a, b) = G(a, b) / sqrt(G(a, a) G(b, b)) (zero where a diagonal entry
+// is not positive): the Gram of the columns scaled as k_col_scale scales them.
+__global__ void __launch_bounds__(kThreads) k_scale_gram(int l, const double *G, double *Gout)
+{
+    for (int idx = blockIdx.x * kThreads + threadIdx.x; idx < l * l; idx += gridDim.x * kThreads) {
+        const int a = idx / l, b = idx % l;
+        const double ga = G[a * l + a], gb = G[b * l + b];
+        const double sa = ga > 0.0 ? 1.0 / sqrt(ga) : 0.0, sb = gb > 0.0 ? 1.0 / sqrt(gb) : 0.0;
+        Gout[idx] = G[idx] * (sa * sb);
+    }
+}
+
+hipError_t launch_scale_gram(int l, const double *G, double *Gout, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scale_gram, dim3((unsigned)((l * l + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, l, G, Gout);
     return hipGetLastError();
 }
 

@@ -176,6 +176,8 @@ struct ReconArgs {
     // optional: Omega's rows drawn beforehand by launch_omega_rows (8 per
     // row, the same values); nullptr: drawn in the epilogue
     const double *om = nullptr;
+    // row and column block counts (set by launch_recon)
+    int nrb = 0, ncb = 0;
 };
 bool recon_ok(int c);
 int64_t recon_row_blocks(int64_t rows);   // grid.x of the epilogue launch
@@ -242,7 +244,9 @@ hipError_t launch_gram_tall(int64_t rows, int l, const T *Y, int64_t ldy, double
 // number of null pivots.
 hipError_t launch_chol(int l, const double *G, double shift_factor, double null_tol, double *R,
                        int *null_cols, int *flags, hipStream_t s, const int *gate = nullptr,
-                       int *nn_out = nullptr);
+                       int *nn_out = nullptr, double near_one = 0.0);
+// G_out(a, b) = G(a, b) / sqrt(G(a, a) G(b, b)): the Gram after k_col_scale.
+hipError_t launch_scale_gram(int l, const double *G, double *Gout, hipStream_t s);
 // Y (rows x l) <- Y R^{-1} in place (R upper, double), one lane per row.
 template <typename T>
 hipError_t launch_trsm(int64_t rows, int l, T *Y, int64_t ldy, const double *R, hipStream_t s);

@@ -64,10 +64,10 @@ LongPlan long_plan(int mh, int64_t nh, int c, int elem_bytes, int mode, int num_
     p.rpt = nrb <= 16 ? 4 : 8;             // row blocks per wavefront (phase 2)
     p.kt = kKT;
     p.ntiles = (int)((nh + kKT - 1) / kKT);
-    // two workgroups per compute unit; three where the transposed power and
-    // projection forms fit them (one 16-column block, at most 13 row groups)
-    const bool three = trans && (mode == kPower || mode == kProject) && c <= 16 && p.mhp <= 208;
-    p.grid = std::max(1, std::min(p.ntiles, (three ? 3 : 2) * num_cu));
+    // two workgroups per compute unit (three, where the registers allow it,
+    // measured no faster on the transposed power and projection passes)
+    (void)trans;
+    p.grid = std::max(1, std::min(p.ntiles, 2 * num_cu));
     const bool needs_q = (mode == kPower || mode == kProject);
     const int ld = elem_bytes == 8 ? LpMfma<double>::kLD : LpMfma<float>::kLD;
     p.lds = (size_t)p.mhp * ld * elem_bytes + (size_t)kKT * p.cm * elem_bytes +
@@ -516,10 +516,7 @@ __device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, uint3
 }
 
 template <typename T, int MODE, int NB, int RING, int NJ>
-// (the power and projection forms with one 16-column block and at most 13
-// row groups fit three wavefronts per SIMD: three workgroups per compute unit)
-__global__ void __launch_bounds__(kThreads, (NB == 1 && NJ <= 13 && (MODE == kPower || MODE == kProject)) ? 3 : 1)
-k_long_tr(LongArgs<T> a, uint32_t span_bytes)
+__global__ void __launch_bounds__(kThreads) k_long_tr(LongArgs<T> a, uint32_t span_bytes)
 {
     using M = LpMfma<T>;
     using V4 = typename M::V4;
