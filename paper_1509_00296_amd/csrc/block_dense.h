@@ -456,6 +456,15 @@ __device__ __forceinline__ bool jacobi_needed(double al, double be, double ga, d
     return ab < 1e300 ? ga * ga > (tol * tol) * ab : fabs(ga) > tol * sqrt(ab);
 }
 
+// Stopping rule of the cyclic Jacobi sweeps: a pair is rotated while its
+// cosine |m_p.m_q| / (|m_p| |m_q|) exceeds rows 2u, and the sweeps stop after
+// one in which no applied rotation had a cosine above kJacobiQuadStop.  Near
+// convergence each sweep squares the largest cosine (the quadratic
+// convergence of cyclic Jacobi), so the sweep that would follow would find
+// cosines near 1e-16, below the rotation threshold: stopping here saves that
+// confirming sweep and leaves the columns orthogonal to working precision.
+constexpr double kJacobiQuadStop = 1e-8;
+
 // ---------------------------------------------------------------------------
 // One wavefront, l <= 8: the lane grid (r, c) = (lane % 8, lane / 8), lane
 // (r, c) holding element (r, c) of an 8 x 8 matrix M (zeros past l), so that
@@ -515,7 +524,7 @@ __device__ __forceinline__ int wave8_jacobi(double &x, int l, int max_sweeps)
                 jacobi_rotation(al, be, cr, cs, sn);
                 x = isp ? cs * x - sn * y : sn * y + cs * x;
             }
-            rot |= __any(doit) ? 1 : 0;
+            rot |= __any(doit && jacobi_needed(al, be, cr, kJacobiQuadStop)) ? 1 : 0;
         }
         if (!rot) break;
     }
@@ -623,7 +632,7 @@ __device__ __forceinline__ int jacobi_groups(double *M, int rows, int ld, int n,
                             mq[i] = sn * x[e] + cs * y[e];
                         }
                     }
-                    if (gl == 0) *sh_rot = 1;
+                    if (gl == 0 && jacobi_needed(al, be, ga, kJacobiQuadStop)) *sh_rot = 1;
                 }
                 npair += live ? 1u : 0u;
                 nrot += doit ? 1u : 0u;

@@ -767,7 +767,7 @@ __device__ __forceinline__ int jacobi_wave16(double *M, int l, int max_sweeps)
                         M[q * l + row] = sn * x + cs * y;
                     }
                 }
-                rot |= __any(doit) ? 1 : 0;
+                rot |= __any(doit && jacobi_needed(al, be, ga, kJacobiQuadStop)) ? 1 : 0;
                 wave_sync();
             }
         }
