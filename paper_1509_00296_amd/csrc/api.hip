@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -53,7 +54,7 @@ struct frsvt_context {
     hipGraphExec_t wb_exec = nullptr;
     std::vector<uint64_t> wb_key;
     // per-iteration status event of the RPCA host loop
-    hipEvent_t ev_iter = nullptr;
+    int iter_seq = 0;                // last sequence number of an RPCA iteration
     void *host_iter = nullptr;       // coherent mapped host words of the RPCA loop
     void *host_iter_dev = nullptr;   // its device address
     // tracing: event pairs around launches, aggregated per kernel class
@@ -290,6 +291,7 @@ struct CoreBuffers {
     uint16_t *V16;   // bfloat16 scratch (nh x l) for the precision form
     T *Ypart, *Y, *Q, *Bt, *QM, *Om, *Z, *gpart_t, *Qtmp;
     double *Gpart, *G, *U, *Mm, *sigma, *R, *gpart_d, *jwork;
+    double *dinv;    // inverses of R's 16 x 16 diagonal blocks (large path)
     int *nullc;
     size_t ypart_cap;   // elements of Ypart
 };
@@ -317,6 +319,7 @@ size_t carve_core(Carver &cv, const Orient &o, int l, int cnew, int num_cu, Core
     b.R = cv.take<double>((size_t)cmax * cmax);
     b.nullc = cv.take<int>((size_t)cmax);
     b.jwork = cv.take<double>((size_t)cmax * cmax);
+    b.dinv = cv.take<double>((size_t)256 * ((cmax + 15) / 16));
     const bool big = force_big || !(long_path_ok(mh, std::max(l, 1)) && small_orth_ok(mh, l));
     b.V16 = nullptr;
     if (big) {
@@ -451,40 +454,50 @@ int gram(frsvt_context *h, int64_t rows, int l, const T *Y, int64_t ldy, double 
     return FRSVT_OK;
 }
 
-// Large-path orthonormalisation of Y (rows x l) in place: column
-// equilibration, shifted CholeskyQR, CholeskyQR with null refill, a final
-// CholeskyQR pass.  No host synchronisation.
+// Large-path orthonormalisation of Y (rows x l) in place.  The fast path
+// below (CholeskyQR2, one host read of its checks); where a check fails, or
+// under graph capture, the robust sequence: column equilibration, shifted
+// CholeskyQR, CholeskyQR with null refill, a final CholeskyQR pass (no host
+// synchronisation).
 template <typename T>
 int big_orth(frsvt_context *h, int64_t rows, int l, T *Y, int64_t ldy, CoreBuffers<T> &b,
              uint64_t seed, uint64_t counter, int *flags)
 {
     int rc;
     // Fast path (not under graph capture: it reads two status words on the
-    // host): equilibration, then CholeskyQR2 in double precision with the
-    // checks of the one-workgroup path (no pivot at or below 1e-8 of the
-    // equilibrated diagonal in the first factor, every pivot of the second
-    // within 1e-6 of 1).  A float basis is orthonormalised on a double copy
-    // (written back at the end); a double one in place, its equilibrated
-    // copy kept.  On a failed check the robust sequence below runs from the
-    // basis as it came (float) or from the equilibrated copy (double).
+    // host): equilibration, one CholeskyQR pass in double precision, then
+    // the second pass.  The first factor must have no pivot at or below
+    // 1e-8 of the equilibrated diagonal.  The second Gram is I + E: while
+    // ||E||_F <= 1e-8 its inverse Cholesky factor is I - S to working
+    // precision (S the upper triangle of E, half diagonal), applied as a
+    // triangular product on the matrix cores; otherwise the second factor is
+    // computed (every pivot within 1e-6 of 1).  Both solves use the matrix
+    // cores with the inverses of the factor's diagonal blocks.  A float
+    // basis is orthonormalised on a double copy (written back at the end); a
+    // double one in place, its equilibrated copy kept.  On a failed check
+    // the robust sequence below runs from the basis as it came (float) or
+    // from the equilibrated copy (double).
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     CK(hipStreamIsCapturing(h->stream, &cap));
     const bool dbl = std::is_same<T, double>::value;
     const size_t need_f = 2 * (size_t)rows * l * sizeof(double);   // float: double copy + spare
-    if (cap == hipStreamCaptureStatusNone && l <= 128 && b.jwork && ldy == rows &&
+    if (cap == hipStreamCaptureStatusNone && l <= 128 && b.jwork && b.dinv && ldy == rows &&
         (dbl ? b.Qtmp != nullptr : (b.gpart_t != nullptr && (size_t)128 * rows * l * sizeof(T) >= need_f))) {
-        int *nn = h->dstatus + kGateSlot + 1;  // two words
+        int *nn = h->dstatus + kGateSlot + 1;   // two words: null pivots of each pass
+        int *full = h->dstatus + kGateSlot + 3;  // 1: the second pass needs its own factor
         double *Yd = dbl ? reinterpret_cast<double *>(Y) : reinterpret_cast<double *>(b.gpart_t);
         if (!dbl) CKT(FRSVT_K_ORTH, launch_cast<double>(rows, l, Y, 0, ldy, Yd, rows, h->stream));
         if ((rc = gram<double>(h, rows, l, Yd, rows, b.G, b.gpart_d))) return rc;
         CKT(FRSVT_K_ORTH, launch_col_scale<double>(rows, l, Yd, rows, b.G, h->stream));
         CKT(FRSVT_K_ORTH, launch_scale_gram(l, b.G, b.jwork, h->stream));
         if (dbl) CK(hipMemcpyAsync(b.Qtmp, Yd, (size_t)rows * l * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
-        CKT(FRSVT_K_ORTH, launch_chol(l, b.jwork, 0.0, 1e-8, b.R, b.nullc, nullptr, h->stream, nullptr, nn));
-        CKT(FRSVT_K_ORTH, launch_trsm<double>(rows, l, Yd, rows, b.R, h->stream));
+        CKT(FRSVT_K_ORTH, launch_chol(l, b.jwork, 0.0, 1e-8, b.R, b.nullc, nullptr, h->stream, nullptr, nn, 0.0, b.dinv));
+        CKT(FRSVT_K_ORTH, launch_trsm<double>(rows, l, Yd, rows, b.R, h->stream, b.dinv));
         if ((rc = gram<double>(h, rows, l, Yd, rows, b.G, b.gpart_d))) return rc;
-        CKT(FRSVT_K_ORTH, launch_chol(l, b.G, 0.0, 0.5, b.R, b.nullc, nullptr, h->stream, nullptr, nn + 1, 1e-6));
-        CKT(FRSVT_K_ORTH, launch_trsm<double>(rows, l, Yd, rows, b.R, h->stream));
+        CKT(FRSVT_K_ORTH, launch_near_identity(l, b.G, b.jwork, full, nn + 1, 1e-8, h->stream));
+        CKT(FRSVT_K_ORTH, launch_trmm<double>(rows, l, Yd, rows, b.jwork, h->stream, full));
+        CKT(FRSVT_K_ORTH, launch_chol(l, b.G, 0.0, 0.5, b.R, b.nullc, nullptr, h->stream, full, nn + 1, 1e-6, b.dinv));
+        CKT(FRSVT_K_ORTH, launch_trsm<double>(rows, l, Yd, rows, b.R, h->stream, b.dinv, full));
         CK(hipMemcpyAsync(h->pinned, nn, 2 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
         CK(hipStreamSynchronize(h->stream));
         const int *hn = (const int *)h->pinned;
@@ -502,8 +515,8 @@ int big_orth(frsvt_context *h, int64_t rows, int l, T *Y, int64_t ldy, CoreBuffe
     CKT(FRSVT_K_ORTH, launch_col_scale<T>(rows, l, Y, ldy, b.G, h->stream));
     const double shift = 11.0 * ((double)rows * l + (double)l * (l + 1)) * kU;
     if ((rc = gram(h, rows, l, Y, ldy, b.G, b.gpart_d))) return rc;
-    CKT(FRSVT_K_ORTH, launch_chol(l, b.G, shift, 0.0, b.R, nullptr, flags, h->stream));
-    CKT(FRSVT_K_ORTH, launch_trsm<T>(rows, l, Y, ldy, b.R, h->stream));
+    CKT(FRSVT_K_ORTH, launch_chol(l, b.G, shift, 0.0, b.R, nullptr, flags, h->stream, nullptr, nullptr, 0.0, b.dinv));
+    CKT(FRSVT_K_ORTH, launch_trsm<T>(rows, l, Y, ldy, b.R, h->stream, b.dinv));
     // The first null check records its count in *gate; when it found no
     // null column nothing was refilled, so the Gram and factor of the second
     // check and of the next pass would repeat it: those launches return at
@@ -513,15 +526,16 @@ int big_orth(frsvt_context *h, int64_t rows, int l, T *Y, int64_t ldy, CoreBuffe
         const int *g = attempt ? gate : nullptr;
         if ((rc = gram(h, rows, l, Y, ldy, b.G, b.gpart_d, g))) return rc;
         CKT(FRSVT_K_ORTH, launch_chol(l, b.G, 0.0, 16.0 * l * kU, b.R, b.nullc, flags, h->stream, g,
-                                      attempt ? nullptr : gate));
+                                      attempt ? nullptr : gate, 0.0, b.dinv));
         CKT(FRSVT_K_ORTH, launch_refill<T>(rows, l, Y, ldy, b.nullc, seed, counter, attempt, h->stream));
     }
     if ((rc = gram(h, rows, l, Y, ldy, b.G, b.gpart_d, gate))) return rc;
-    CKT(FRSVT_K_ORTH, launch_chol(l, b.G, 0.0, 16.0 * l * kU, b.R, b.nullc, flags, h->stream, gate));
-    CKT(FRSVT_K_ORTH, launch_trsm<T>(rows, l, Y, ldy, b.R, h->stream));
+    CKT(FRSVT_K_ORTH, launch_chol(l, b.G, 0.0, 16.0 * l * kU, b.R, b.nullc, flags, h->stream, gate, nullptr, 0.0,
+                                  b.dinv));
+    CKT(FRSVT_K_ORTH, launch_trsm<T>(rows, l, Y, ldy, b.R, h->stream, b.dinv));
     if ((rc = gram(h, rows, l, Y, ldy, b.G, b.gpart_d))) return rc;
-    CKT(FRSVT_K_ORTH, launch_chol(l, b.G, 0.0, 0.0, b.R, nullptr, flags, h->stream));
-    CKT(FRSVT_K_ORTH, launch_trsm<T>(rows, l, Y, ldy, b.R, h->stream));
+    CKT(FRSVT_K_ORTH, launch_chol(l, b.G, 0.0, 0.0, b.R, nullptr, flags, h->stream, nullptr, nullptr, 0.0, b.dinv));
+    CKT(FRSVT_K_ORTH, launch_trsm<T>(rows, l, Y, ldy, b.R, h->stream, b.dinv));
     return FRSVT_OK;
 }
 
@@ -1239,6 +1253,39 @@ int spectral_norm(frsvt_context *h, const T *A, int64_t lda, const Orient &o, do
     return FRSVT_OK;
 }
 
+// Int word of the mapped host block that carries an RPCA iteration's
+// sequence number (after the status words 0-7, the residual sum 8-9 and the
+// residual estimate 10-11).
+constexpr int kIterSeqWord = 16;
+
+// Waits for the last kernel of an RPCA iteration to have written its status
+// words to mapped host memory: polls the sequence number it writes after
+// them (an event on the stream would hold the next kernel back by a few
+// microseconds), querying the stream now and then so that an error on it
+// ends the wait.
+int wait_iter_words(frsvt_context *h, hipStream_t s, volatile int *word, int seq)
+{
+    for (unsigned spin = 1;; ++spin) {
+        if (*word == seq) {
+            std::atomic_thread_fence(std::memory_order_acquire);
+            return FRSVT_OK;
+        }
+        if ((spin & 1023u) == 0) {
+            const hipError_t e = hipStreamQuery(s);
+            if (e == hipSuccess) {
+                // the stream has drained: the word is there or never comes
+                std::atomic_thread_fence(std::memory_order_acquire);
+                if (*word == seq) return FRSVT_OK;
+                snprintf(h->last_error, sizeof(h->last_error),
+                         "the RPCA iteration's status words did not reach mapped host memory");
+                return FRSVT_ERR_HIP;
+            }
+            if (e != hipErrorNotReady) return fail(h, e, "hipStreamQuery (RPCA iteration)");
+        }
+        __builtin_ia32_pause();
+    }
+}
+
 template <typename T>
 int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, double lambda,
               const frsvt_rpca_opts &op, T *L, int64_t ldl, T *S, int64_t lds,
@@ -1491,16 +1538,15 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
         int nz = 0;
         CKT(FRSVT_K_EPILOGUE, launch_recon<T>(kEpi, ra, &nz, s));
         // status words (rank, residual) written by the last kernel straight
-        // to mapped host memory, marked by an event; the host waits for that
-        // event only, so the GPU keeps working on the speculative sketch
-        // below while the host reads them and enqueues the next iteration.
+        // to mapped host memory, then a sequence number; the host polls that
+        // word only, so the GPU keeps working on the speculative sketch below
+        // while the host reads them and enqueues the next iteration.
         int *hdev = (int *)h->host_iter_dev;
+        const int seq = h->iter_seq = (h->iter_seq % 0x3fffffff) + 1;
         CKT(FRSVT_K_REDUCE, launch_finish_iter(zp, nz, h->dstatus, 8, hdev, (double *)(hdev + 8),
                                                op.use_frsvt ? reinterpret_cast<const double *>(h->dstatus + kResidSlot)
                                                             : nullptr,
-                                               (double *)(hdev + 10), s));
-        if (!h->ev_iter) CK(hipEventCreateWithFlags(&h->ev_iter, hipEventDisableTiming));
-        CK(hipEventRecord(h->ev_iter, s));
+                                               (double *)(hdev + 10), s, hdev + kIterSeqWord, seq));
         // the next sketch is completed (or run) before the host waits for
         // this iteration's rank
         spec_cnew = 0;
@@ -1530,7 +1576,7 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
             }
         }
 
-        CK(hipEventSynchronize(h->ev_iter));
+        if ((rc = wait_iter_words(h, s, hst + kIterSeqWord, seq))) return rc;
         const int r = hst[0];
         if (op.use_frsvt && hst[6] != 0) {
             snprintf(h->last_error, sizeof(h->last_error),
@@ -2399,7 +2445,6 @@ int frsvt_destroy(frsvt_handle h)
         (void)hipEventDestroy(r.second.second);
     }
     for (auto e : h->pool) (void)hipEventDestroy(e);
-    if (h->ev_iter) (void)hipEventDestroy(h->ev_iter);
     if (h->host_iter) (void)hipHostFree(h->host_iter);
     if (h->wb_exec) (void)hipGraphExecDestroy(h->wb_exec);
     if (h->wb_capture) (void)hipStreamDestroy(h->wb_capture);

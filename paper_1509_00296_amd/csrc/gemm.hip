@@ -217,158 +217,151 @@ template hipError_t launch_gram_tall<double>(int64_t, int, const double *, int64
 template hipError_t launch_gram_tall<float>(int64_t, int, const float *, int64_t, double *, double *, hipStream_t, const int *);
 
 // Cholesky of (G + shift I), shift = shift_factor trace(G), l <= 128, by one
-// workgroup on the matrix in LDS (row-major, upper triangle used), blocked
-// in panels of 16 rows (right-looking):
+// workgroup of four wavefronts on the matrix in LDS (row-major, rows and
+// columns padded to a multiple of 16 with zeros; upper triangle used),
+// blocked in panels of 16 rows (right-looking):
 //   1. wavefront 0 factors the 16 x 16 diagonal block in registers (lane k
-//      holds column k; pivots and rows broadcast with readlane);
+//      holds column k; pivots and rows broadcast with readlane; one lean
+//      reciprocal square root per pivot);
 //   2. the panel's rows right of the block, R_JJ^{-T} A(J, k), one column k
-//      per thread;
-//   3. the trailing upper triangle takes the rank-16 update in 4 x 4 blocks.
+//      per thread; meanwhile wavefront 3 inverts the diagonal block (dinv,
+//      when requested: the operand of the matrix-core triangular solve);
+//   3. the trailing upper triangle takes the rank-16 update as 16 x 16 tiles
+//      on the matrix cores (four 16x16x4 FP64 products per tile).
 // Three barriers per panel.  Pivots <= null_tol max_j G_jj are numerically
-// null: R_jj = 1 and a zero row (null_cols[j] = 1).  R is written whole
-// (upper, row-major [j * l + k], zeros below the diagonal).
-constexpr int kCholThreads = 512;
-// near_one > 0: a pivot further than near_one from 1 is also counted (and
-// treated) as null (the second CholeskyQR pass's check that the Gram is
-// near the identity).
-__global__ void __launch_bounds__(kCholThreads) k_chol(int l, const double *G, double shift_factor, double null_tol, double *R, int *null_cols, int *flags, const int *gate, int *nn_out, double near_one)
+// null, and with near_one > 0 so is a pivot further than near_one from 1
+// (the second CholeskyQR pass's check that the Gram is near the identity):
+// R_jj = 1 and a zero row (null_cols[j] = 1).  R is written whole (upper,
+// row-major [j * l + k], zeros below the diagonal).
+constexpr int kCholThreads = 256;
+__global__ void __launch_bounds__(kCholThreads) k_chol(int l, const double *G, double shift_factor, double null_tol, double *R, int *null_cols, int *flags, const int *gate, int *nn_out, double near_one, double *dinv)
 {
-    if (gate && *gate == 0) return;  // the factor in R is still current
+    if (gate && *gate == 0) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    double *M = reinterpret_cast<double *>(smem_raw);
-    __shared__ double shift, tolabs;
-    __shared__ double srinv[128];
-    __shared__ int snull[128];
-    __shared__ int sh_nn;
-    const int tid = threadIdx.x, lane = tid % kWave;
-    for (int idx = tid; idx < l * l; idx += kCholThreads) M[idx] = G[idx];
-    __syncthreads();
-    if (tid == 0) {
-        double tr = 0.0, mx = 0.0;
-        for (int j = 0; j < l; ++j) {
-            tr += M[j * l + j];
-            mx = fmax(mx, M[j * l + j]);
-        }
-        shift = shift_factor * tr;
-        tolabs = null_tol > 0.0 ? null_tol * fmax(mx, 1e-300) : 0.0;
-        sh_nn = 0;
+    double *M = reinterpret_cast<double *>(smem_raw);   // lp x lp, row-major
+    __shared__ double sRd[16 * 16];
+    __shared__ double srinv[16];
+    __shared__ double sdiag[2];
+    const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+    const int lp = (l + 15) & ~15;
+    for (int idx = tid; idx < lp * lp; idx += kCholThreads) {
+        const int j = idx / lp, k = idx - j * lp;
+        M[idx] = (j < l && k < l) ? G[(size_t)j * l + k] : 0.0;
     }
     __syncthreads();
-    for (int j = tid; j < l; j += kCholThreads) M[j * l + j] += shift;
+    if (wave == 0) {
+        double tr = 0.0, mx = 0.0;
+        for (int j = lane; j < l; j += kWave) {
+            const double d = M[j * lp + j];
+            tr += d;
+            mx = fmax(mx, d);
+        }
+        tr = wave_sum(tr);
+        mx = wave_max(mx);
+        if (lane == 0) {
+            sdiag[0] = shift_factor * tr;
+            sdiag[1] = null_tol > 0.0 ? null_tol * fmax(mx, 1e-300) : 0.0;
+        }
+    }
     __syncthreads();
-    const double tol = tolabs;
+    const double shift = sdiag[0], tol = sdiag[1];
+    if (shift != 0.0) {
+        for (int j = tid; j < l; j += kCholThreads) M[j * lp + j] += shift;
+        __syncthreads();
+    }
+    int nn = 0;
     for (int J = 0; J < l; J += 16) {
         const int nb = min(16, l - J);
-        // 1. the diagonal block (upper entries read; the lower ones are stale)
-        if (tid < kWave) {
+        if (wave == 0) {
             double g[16];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) g[i] = (i < nb && lane < nb) ? M[(J + i) * l + J + lane] : 0.0;
-            int nn = 0;
+            for (int i = 0; i < 16; ++i) g[i] = (lane < nb && i <= lane) ? M[(J + i) * lp + J + lane] : 0.0;
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
+                double r = 0.0, rs = 0.0;
                 if (j < nb) {
-                    double gj = 0.0;
-#pragma unroll
-                    for (int i = 0; i < 16; ++i)
-                        if (i == j) gj = g[i];
-                    const double d = read_lane(gj, j);
+                    const double d = read_lane(g[j], j);
                     bool isnull = !(d > tol);
-                    if (near_one > 0.0 && !isnull) isnull = !(fabs(sqrt(d) - 1.0) <= near_one);
-                    const double rs = rsqrt(isnull ? 1.0 : d);
-                    const double piv = isnull ? 1.0 : d * rs;
+                    const double rq = rsqrt_pos(isnull ? 1.0 : d);
+                    const double piv = d * rq;
+                    if (near_one > 0.0 && !isnull) isnull = !(fabs(piv - 1.0) <= near_one);
+                    rs = isnull ? 0.0 : rq;
                     nn += isnull ? 1 : 0;
-                    double rjk = 0.0;
-                    if (lane == j) rjk = piv;
-                    else if (lane > j && lane < nb && !isnull) rjk = gj * rs;
-                    if (lane < nb) M[(J + j) * l + J + lane] = rjk;
-                    if (lane == 0) {
-                        snull[J + j] = isnull ? 1 : 0;
-                        srinv[J + j] = isnull ? 0.0 : rs;
-                        if (null_cols) null_cols[J + j] = isnull ? 1 : 0;
-                    }
+                    if (lane == j) r = isnull ? 1.0 : piv;
+                    else if (lane > j && lane < nb) r = g[j] * rs;
+                    if (lane == 0 && null_cols) null_cols[J + j] = isnull ? 1 : 0;
+                    // every lane updates (lanes below i change entries below
+                    // the diagonal, which are never read)
 #pragma unroll
-                    for (int i = 0; i < 16; ++i) {
-                        if (i > j) {
-                            const double rji = read_lane(rjk, i);
-                            g[i] = lane > j ? g[i] - rji * rjk : g[i];
-                        }
-                    }
+                    for (int i = j + 1; i < 16; ++i) g[i] -= read_lane(r, i) * r;
                 }
+                if (lane < 16) sRd[j * 16 + lane] = r;
+                if (lane == 0) srinv[j] = rs;
             }
-            if (lane == 0) sh_nn += nn;
         }
         __syncthreads();
-        // 2. R(J : J + nb, k) = R_JJ^{-T} A(J : J + nb, k), k >= J + nb (null
-        //    rows zero)
-        for (int k = J + nb + tid; k < l; k += kCholThreads) {
+        if (dinv && wave == kCholThreads / kWave - 1) {
+            // the inverse of this 16 x 16 diagonal block (identity past l):
+            // lane c forms column c by back substitution
+            const int c = lane & 15;
             double x[16];
 #pragma unroll
-            for (int a = 0; a < 16; ++a) x[a] = a < nb ? M[(J + a) * l + k] : 0.0;
+            for (int i = 15; i >= 0; --i) {
+                double v = (i == c) ? 1.0 : 0.0;
+                if (i < nb) {
 #pragma unroll
-            for (int a = 0; a < 16; ++a) {
-                if (a < nb) {
-                    double v = x[a];
-#pragma unroll
-                    for (int t = 0; t < a; ++t) v -= M[(J + t) * l + J + a] * x[t];
-                    x[a] = v * srinv[J + a];
+                    for (int t = i + 1; t < 16; ++t) v -= sRd[i * 16 + t] * x[t];
+                    v /= sRd[i * 16 + i];
                 }
+                x[i] = v;
             }
+            if (lane < 16)
 #pragma unroll
-            for (int a = 0; a < 16; ++a)
-                if (a < nb) M[(J + a) * l + k] = x[a];
+                for (int i = 0; i < 16; ++i) dinv[(J >> 4) * 256 + i * 16 + c] = x[i];
         }
-        __syncthreads();
-        // 3. trailing update of the upper triangle, rows and columns >= J + nb
-        const int base = J + nb, nt = l - base;
-        if (nt > 0) {
-            const int nbk = (nt + 3) / 4;
-            const int nblk = nbk * (nbk + 1) / 2;
-            for (int blk = tid; blk < nblk; blk += kCholThreads) {
-                int bi = 0, rem = blk;
-                while (rem >= nbk - bi) {
-                    rem -= nbk - bi;
-                    ++bi;
-                }
-                const int bj = bi + rem;
-                const int a0 = base + 4 * bi, k0 = base + 4 * bj;
-                double acc[4][4];
+        for (int k = J + 16 + tid; k < l; k += kCholThreads) {
+            double x[16];
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
+            for (int a = 0; a < 16; ++a) x[a] = M[(J + a) * lp + k];
 #pragma unroll
-                    for (int f = 0; f < 4; ++f)
-                        acc[e][f] = (a0 + e < l && k0 + f < l) ? M[(a0 + e) * l + k0 + f] : 0.0;
-                for (int t = 0; t < nb; ++t) {
-                    const double *row = M + (J + t) * l;
-                    double ra[4], rk[4];
+            for (int t = 0; t < 16; ++t) {
+                x[t] *= srinv[t];
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        ra[e] = a0 + e < l ? row[a0 + e] : 0.0;
-                        rk[e] = k0 + e < l ? row[k0 + e] : 0.0;
-                    }
-#pragma unroll
-                    for (int e = 0; e < 4; ++e)
-#pragma unroll
-                        for (int f = 0; f < 4; ++f) acc[e][f] -= ra[e] * rk[f];
-                }
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-#pragma unroll
-                    for (int f = 0; f < 4; ++f)
-                        if (a0 + e < l && k0 + f < l) M[(a0 + e) * l + k0 + f] = acc[e][f];
+                for (int a = t + 1; a < 16; ++a) x[a] -= sRd[t * 16 + a] * x[t];
             }
+#pragma unroll
+            for (int a = 0; a < 16; ++a) M[(J + a) * lp + k] = x[a];
+        }
+        for (int e = tid; e < 256; e += kCholThreads) M[(J + e / 16) * lp + J + e % 16] = sRd[e];
+        __syncthreads();
+        const int K0 = J + 16;
+        const int nrem = (lp - K0) / 16;
+        const int ntiles = nrem * (nrem + 1) / 2;
+        for (int tile = wave; tile < ntiles; tile += kCholThreads / kWave) {
+            int bi = 0, rem = tile;
+            while (rem >= nrem - bi) {
+                rem -= nrem - bi;
+                ++bi;
+            }
+            const int K = K0 + 16 * bi, L = K0 + 16 * (bi + rem);
+            bd_doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int t = J + 4 * s + (lane >> 4);
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(M[t * lp + K + (lane & 15)], M[t * lp + L + (lane & 15)],
+                                                           acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) M[(K + (lane >> 4) + 4 * r) * lp + L + (lane & 15)] -= acc[r];
         }
         __syncthreads();
     }
     for (int idx = tid; idx < l * l; idx += kCholThreads) {
-        const int j = idx / l, k = idx % l;
-        R[idx] = k >= j ? M[idx] : 0.0;
+        const int j = idx / l, k = idx - j * l;
+        R[idx] = k >= j ? M[j * lp + k] : 0.0;
     }
     if (tid == 0) {
-        const int nn = sh_nn;
         if (flags) {
-            // null checks report the columns they flag; the final pass (no
-            // shift, no null tolerance) records whether its factor still failed
             if (null_tol > 0.0) flags[1] = nn;
             if (null_tol <= 0.0 && shift_factor == 0.0) flags[2] = nn > 0 ? 1 : 0;
         }
@@ -376,11 +369,12 @@ __global__ void __launch_bounds__(kCholThreads) k_chol(int l, const double *G, d
     }
 }
 
-hipError_t launch_chol(int l, const double *G, double shift_factor, double null_tol, double *R, int *null_cols, int *flags, hipStream_t s, const int *gate, int *nn_out, double near_one)
+hipError_t launch_chol(int l, const double *G, double shift_factor, double null_tol, double *R, int *null_cols, int *flags, hipStream_t s, const int *gate, int *nn_out, double near_one, double *dinv)
 {
-    const size_t lds = (size_t)l * l * sizeof(double);
     if (l < 1 || l > 128) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_chol, dim3(1), dim3(kCholThreads), lds, s, l, G, shift_factor, null_tol, R, null_cols, flags, gate, nn_out, near_one);
+    const int lp = (l + 15) & ~15;
+    const size_t lds = (size_t)lp * lp * sizeof(double);
+    hipLaunchKernelGGL(k_chol, dim3(1), dim3(kCholThreads), lds, s, l, G, shift_factor, null_tol, R, null_cols, flags, gate, nn_out, near_one, dinv);
     return hipGetLastError();
 }
 
@@ -481,15 +475,187 @@ __global__ void __launch_bounds__(kTrsmThreads) k_trsm(int64_t rows, int l, T *Y
     }
 }
 
-template <typename T>
-hipError_t launch_trsm(int64_t rows, int l, T *Y, int64_t ldy, const double *R, hipStream_t s)
+// Orders one wavefront's LDS accesses around a point (its DS instructions
+// execute in order); for kernels whose workgroup is a single wavefront.
+__device__ __forceinline__ void wave_lds_sync()
 {
-    if (l > 128) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_trsm<T>), dim3((unsigned)((rows + kWave - 1) / kWave)), dim3(kTrsmThreads), 0, s, rows, l, Y, ldy, R);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_wave_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// Y <- Y R^{-1} on the matrix cores, given the inverses Dinv of R's 16 x 16
+// diagonal blocks (k_chol writes them; identity past l).  One wavefront per
+// 16 rows of Y; for column block J:
+//   X_J = (Y_J - sum_{K < J} X_K R_KJ) Dinv_J,
+// the sum as 16x16x4 FP64 products in two interleaved accumulation chains
+// (A operand: the solved blocks X_K from LDS; B operand: R from memory,
+// shared by every wavefront through the caches), the block Y_J - sum moved
+// to operand layout through LDS and multiplied by Dinv_J.
+template <typename T>
+__global__ void __launch_bounds__(kWave) k_trsm_mfma(int64_t rows, int l, T *Y, int64_t ldy,
+                                                     const double *__restrict__ R, const double *__restrict__ Dinv,
+                                                     const int *gate)
+{
+    if (gate && *gate == 0) return;   // the solve is not wanted this time
+    constexpr int LDX = 129;   // odd stride: the operand reads of 16 rows hit distinct banks
+    __shared__ double sX[16 * LDX];
+    __shared__ double sT[16 * 17];
+    const int lane = threadIdx.x;
+    const int nb = (l + 15) >> 4;
+    const int64_t i0 = (int64_t)blockIdx.x * 16;
+    const int ar = lane & 15, ak = lane >> 4;   // operand row / column within 16 and k within 4
+    for (int J = 0; J < nb; ++J) {
+        const int cj = J * 16 + ar;
+        double y[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t i = i0 + ak + 4 * r;
+            y[r] = (i < rows && cj < l) ? (double)Y[i + (int64_t)cj * ldy] : 0.0;
+        }
+        bd_doublex4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+        for (int K = 0; K < J; ++K) {
+            double b[4], a[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int t = K * 16 + 4 * q + ak;   // < J * 16 < l
+                b[q] = cj < l ? R[(int64_t)t * l + cj] : 0.0;
+                a[q] = sX[ar * LDX + t];
+            }
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1], b[1], acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[2], b[2], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[3], b[3], acc1, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sT[(ak + 4 * r) * 17 + ar] = y[r] - (acc0[r] + acc1[r]);
+        wave_lds_sync();
+        bd_doublex4 x = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            x = __builtin_amdgcn_mfma_f64_16x16x4f64(sT[ar * 17 + 4 * q + ak], Dinv[J * 256 + (4 * q + ak) * 16 + ar], x,
+                                                     0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = ak + 4 * r;
+            sX[row * LDX + cj] = x[r];
+            const int64_t i = i0 + row;
+            if (i < rows && cj < l) Y[i + (int64_t)cj * ldy] = (T)x[r];
+        }
+        wave_lds_sync();
+    }
+}
+
+template <typename T>
+hipError_t launch_trsm(int64_t rows, int l, T *Y, int64_t ldy, const double *R, hipStream_t s, const double *dinv,
+                       const int *gate)
+{
+    if (l > 128 || (gate && !dinv)) return hipErrorInvalidValue;
+    if (dinv)
+        hipLaunchKernelGGL((k_trsm_mfma<T>), dim3((unsigned)((rows + 15) / 16)), dim3(kWave), 0, s, rows, l, Y, ldy, R,
+                           dinv, gate);
+    else
+        hipLaunchKernelGGL((k_trsm<T>), dim3((unsigned)((rows + kWave - 1) / kWave)), dim3(kTrsmThreads), 0, s, rows, l,
+                           Y, ldy, R);
     return hipGetLastError();
 }
-template hipError_t launch_trsm<double>(int64_t, int, double *, int64_t, const double *, hipStream_t);
-template hipError_t launch_trsm<float>(int64_t, int, float *, int64_t, const double *, hipStream_t);
+template hipError_t launch_trsm<double>(int64_t, int, double *, int64_t, const double *, hipStream_t, const double *,
+                                        const int *);
+template hipError_t launch_trsm<float>(int64_t, int, float *, int64_t, const double *, hipStream_t, const double *,
+                                       const int *);
+
+// Y <- Y U for an upper triangular U (row-major, l <= 128) on the matrix
+// cores: one wavefront per 16 rows, the rows of Y staged in LDS first, then
+// every column block Y_J' = sum_{K <= J} Y_K U_KJ.
+template <typename T>
+__global__ void __launch_bounds__(kWave) k_trmm_mfma(int64_t rows, int l, T *Y, int64_t ldy, const double *__restrict__ U,
+                                                     const int *skip)
+{
+    if (skip && *skip != 0) return;   // the product is not wanted this time
+    constexpr int LDX = 129;
+    __shared__ double sX[16 * LDX];
+    const int lane = threadIdx.x;
+    const int nb = (l + 15) >> 4;
+    const int64_t i0 = (int64_t)blockIdx.x * 16;
+    const int ar = lane & 15, ak = lane >> 4;
+    for (int J = 0; J < nb; ++J) {
+        const int cj = J * 16 + ar;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t i = i0 + ak + 4 * r;
+            sX[(ak + 4 * r) * LDX + cj] = (i < rows && cj < l) ? (double)Y[i + (int64_t)cj * ldy] : 0.0;
+        }
+    }
+    wave_lds_sync();
+    for (int J = 0; J < nb; ++J) {
+        const int cj = J * 16 + ar;
+        bd_doublex4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+        for (int K = 0; K <= J; ++K) {
+            double b[4], a[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int t = K * 16 + 4 * q + ak;
+                b[q] = (t < l && cj < l) ? U[(int64_t)t * l + cj] : 0.0;
+                a[q] = sX[ar * LDX + t];
+            }
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1], b[1], acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[2], b[2], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[3], b[3], acc1, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t i = i0 + ak + 4 * r;
+            if (i < rows && cj < l) Y[i + (int64_t)cj * ldy] = (T)(acc0[r] + acc1[r]);
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_trmm(int64_t rows, int l, T *Y, int64_t ldy, const double *U, hipStream_t s, const int *skip)
+{
+    if (l < 1 || l > 128) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_trmm_mfma<T>), dim3((unsigned)((rows + 15) / 16)), dim3(kWave), 0, s, rows, l, Y, ldy, U,
+                       skip);
+    return hipGetLastError();
+}
+template hipError_t launch_trmm<double>(int64_t, int, double *, int64_t, const double *, hipStream_t, const int *);
+template hipError_t launch_trmm<float>(int64_t, int, float *, int64_t, const double *, hipStream_t, const int *);
+
+// The second CholeskyQR pass when the Gram G = I + E of the once
+// orthonormalised basis is close to the identity: its Cholesky factor is
+// R = I + S + O(|E|^2), S the upper triangle of E with half its diagonal
+// (so that S + S^T = E), and R^{-1} = I - S + O(|E|^2).  Writes U = I - S
+// (upper, row-major), *full = 1 when ||E||_F exceeds tol (the first-order
+// factor would not be accurate to working precision: the full Cholesky
+// pass is wanted) else 0, and clears *nn (the null count of that pass).
+__global__ void __launch_bounds__(kThreads) k_near_identity(int l, const double *G, double *U, int *full, int *nn,
+                                                            double tol)
+{
+    __shared__ double sred[kThreads / kWave];
+    double ss = 0.0;
+    for (int idx = threadIdx.x; idx < l * l; idx += kThreads) {
+        const int i = idx / l, j = idx - i * l;
+        const double e = G[idx] - (i == j ? 1.0 : 0.0);
+        ss += e * e;
+        U[idx] = j > i ? -e : (j == i ? 1.0 - 0.5 * e : 0.0);
+    }
+    ss = wave_sum(ss);
+    if (threadIdx.x % kWave == 0) sred[threadIdx.x / kWave] = ss;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kThreads / kWave; ++w) t += sred[w];
+        *full = !(sqrt(t) <= tol) ? 1 : 0;
+        *nn = 0;
+    }
+}
+
+hipError_t launch_near_identity(int l, const double *G, double *U, int *full, int *nn, double tol, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_near_identity, dim3(1), dim3(kThreads), 0, s, l, G, U, full, nn, tol);
+    return hipGetLastError();
+}
 
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_refill(int64_t rows, int l, T *Y, int64_t ldy, const int *null_cols, uint64_t seed, uint64_t counter, int attempt)

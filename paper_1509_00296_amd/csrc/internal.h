@@ -74,10 +74,11 @@ hipError_t launch_gram_tr(const T *A, int64_t lda, int mh, int64_t nh, int grid,
 // sum of nparts doubles (the order of launch_reduce with count 1), the
 // first nstatus status words and the double *res (-1 when res is null),
 // written to mapped host memory (device pointers host_status, host_z,
-// host_res)
+// host_res); then, if host_seq is set, seq to *host_seq (after the words,
+// so that a host polling that word sees them)
 hipError_t launch_finish_iter(const double *part, int nparts, const int *status, int nstatus,
                               int *host_status, double *host_z, const double *res, double *host_res,
-                              hipStream_t s);
+                              hipStream_t s, int *host_seq = nullptr, int seq = 0);
 
 // ------------------------------------------------------ one-workgroup CholeskyQR
 // Q = orth([Qt, Y]) with Qt (mh x rp) orthonormal and Y (mh x c):
@@ -241,15 +242,30 @@ template <typename T>
 hipError_t launch_gram_tall(int64_t rows, int l, const T *Y, int64_t ldy, double *part, double *G,
                             hipStream_t s, const int *gate = nullptr);
 // gate: as for launch_gram_tall (R is still current); nn_out receives the
-// number of null pivots.
+// number of null pivots; near_one > 0 also treats a pivot further than
+// near_one from 1 as null; dinv (optional, 256 ceil(l / 16) doubles)
+// receives the inverses of R's 16 x 16 diagonal blocks (identity past l).
 hipError_t launch_chol(int l, const double *G, double shift_factor, double null_tol, double *R,
                        int *null_cols, int *flags, hipStream_t s, const int *gate = nullptr,
-                       int *nn_out = nullptr, double near_one = 0.0);
+                       int *nn_out = nullptr, double near_one = 0.0, double *dinv = nullptr);
 // G_out(a, b) = G(a, b) / sqrt(G(a, a) G(b, b)): the Gram after k_col_scale.
 hipError_t launch_scale_gram(int l, const double *G, double *Gout, hipStream_t s);
-// Y (rows x l) <- Y R^{-1} in place (R upper, double), one lane per row.
+// Y (rows x l) <- Y R^{-1} in place (R upper, double): with dinv (the
+// inverses of R's 16 x 16 diagonal blocks, 256 doubles each, as launch_chol
+// writes them) on the matrix cores, one wavefront per 16 rows; else one lane
+// per row.
 template <typename T>
-hipError_t launch_trsm(int64_t rows, int l, T *Y, int64_t ldy, const double *R, hipStream_t s);
+hipError_t launch_trsm(int64_t rows, int l, T *Y, int64_t ldy, const double *R, hipStream_t s,
+                       const double *dinv = nullptr, const int *gate = nullptr);
+// Y (rows x l) <- Y U in place, U upper triangular (row-major, double),
+// l <= 128; nothing when skip is set and *skip != 0.
+template <typename T>
+hipError_t launch_trmm(int64_t rows, int l, T *Y, int64_t ldy, const double *U, hipStream_t s,
+                       const int *skip = nullptr);
+// U = I - S, S the upper triangle of E = G - I with half its diagonal (the
+// inverse of G's Cholesky factor to first order in E); *full = 1 when
+// ||E||_F > tol, else 0; *nn = 0.
+hipError_t launch_near_identity(int l, const double *G, double *U, int *full, int *nn, double tol, hipStream_t s);
 // Y(:, j) <- Gaussian(refill stream) for null_cols[j] = 1; also scales
 // columns to unit norm when normalize != 0 (norms from the Gram diagonal).
 template <typename T>

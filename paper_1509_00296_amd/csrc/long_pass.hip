@@ -1039,7 +1039,8 @@ __global__ void __launch_bounds__(1024) k_reduce_scalar(const T *part, int64_t c
 // reads them after an event without a copy on the stream.
 __global__ void __launch_bounds__(1024) k_finish_iter(const double *part, int nparts, const int *status,
                                                       int nstatus, int *host_status, double *host_z,
-                                                      const double *res, double *host_res)
+                                                      const double *res, double *host_res, int *host_seq,
+                                                      int seq)
 {
     __shared__ double red[16];
     double s = 0.0;
@@ -1054,15 +1055,20 @@ __global__ void __launch_bounds__(1024) k_finish_iter(const double *part, int np
         *host_z = t;
         if (host_res) *host_res = res ? *res : -1.0;
         __threadfence_system();
+        // the sequence number last: a host that sees it sees the words above
+        if (host_seq) {
+            *(volatile int *)host_seq = seq;
+            __threadfence_system();
+        }
     }
 }
 
 hipError_t launch_finish_iter(const double *part, int nparts, const int *status, int nstatus,
                               int *host_status, double *host_z, const double *res, double *host_res,
-                              hipStream_t s)
+                              hipStream_t s, int *host_seq, int seq)
 {
     hipLaunchKernelGGL(k_finish_iter, dim3(1), dim3(1024), 0, s, part, nparts, status, nstatus, host_status, host_z,
-                       res, host_res);
+                       res, host_res, host_seq, seq);
     return hipGetLastError();
 }
 
