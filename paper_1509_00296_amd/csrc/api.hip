@@ -1140,9 +1140,8 @@ int input_norms(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo,
 {
     hipStream_t s = h->stream;
     CKT(FRSVT_K_OTHER, launch_fill_int(h->dstatus + 16, 1, 0, s));
-    CKT(FRSVT_K_OTHER, launch_finite_check<T>(m, n, O, ldo, h->dstatus + 16, s));
     int nparts = 0;
-    CKT(FRSVT_K_OTHER, launch_norms<T>(m, n, O, ldo, h->dscalars + 16, &nparts, s));
+    CKT(FRSVT_K_OTHER, launch_norms<T>(m, n, O, ldo, h->dscalars + 16, &nparts, s, h->dstatus + 16));
     CK(hipMemcpyAsync(h->pinned, h->dstatus + 16, sizeof(int), hipMemcpyDeviceToHost, s));
     CK(hipMemcpyAsync((char *)h->pinned + 64, h->dscalars + 16, 2 * nparts * sizeof(double),
                       hipMemcpyDeviceToHost, s));

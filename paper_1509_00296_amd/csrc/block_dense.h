@@ -152,6 +152,54 @@ __device__ __forceinline__ void gram16_mfma(const double *W, int mh, int mhp, in
     __syncthreads();
 }
 
+// G = W^T W for 16 < l <= 32 on the matrix cores: the three distinct 16 x 16
+// blocks (columns 0-15 with 0-15, 0-15 with 16-31, 16-31 with 16-31), each
+// wavefront over the 4-row steps 4 w, 4 w + 16, ... as gram16_mfma; the four
+// wavefronts' partial blocks added in a fixed order.  part: 4 * 768 doubles
+// of LDS.  Ends with a barrier.
+__device__ __forceinline__ void gram32_mfma(const double *W, int mh, int mhp, int l, double *G, double *part)
+{
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    const int a = lane & 15, ko = lane >> 4;
+    bd_doublex4 z00 = {0, 0, 0, 0}, z01 = {0, 0, 0, 0}, z11 = {0, 0, 0, 0};
+    const double *w0 = W + (size_t)a * mhp;
+    const double *w1 = W + (size_t)(16 + a < l ? 16 + a : 0) * mhp;
+    for (int i0 = 4 * wave; i0 < mh; i0 += 16) {
+        const int i = i0 + ko;
+        const double x0 = i < mh ? w0[i] : 0.0;
+        const double x1 = (i < mh && 16 + a < l) ? w1[i] : 0.0;
+        z00 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, x0, z00, 0, 0, 0);
+        z01 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, x1, z01, 0, 0, 0);
+        z11 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, x1, z11, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int e = ((lane >> 4) + 4 * r) * 16 + a;
+        part[wave * 768 + e] = z00[r];
+        part[wave * 768 + 256 + e] = z01[r];
+        part[wave * 768 + 512 + e] = z11[r];
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < l * l; idx += blockDim.x) {
+        const int x = idx / l, y = idx % l;
+        int e;
+        if (x < 16 && y < 16) e = x * 16 + y;
+        else if (x < 16) e = 256 + x * 16 + (y - 16);
+        else if (y < 16) e = 256 + y * 16 + (x - 16);
+        else e = 512 + (x - 16) * 16 + (y - 16);
+        G[idx] = ((part[e] + part[768 + e]) + part[1536 + e]) + part[2304 + e];
+    }
+    __syncthreads();
+}
+
+// The Gram of an l <= LM column basis in LDS on the matrix cores.
+template <int LM>
+__device__ __forceinline__ void gram_mfma(const double *W, int mh, int mhp, int l, double *G, double *part)
+{
+    if (LM <= 16) gram16_mfma(W, mh, mhp, l, G, part);
+    else gram32_mfma(W, mh, mhp, l, G, part);
+}
+
 // Cholesky of (G + shift I), l <= LM <= 16 (LM a compile-time bound), by
 // ONE wavefront: lane k holds column
 // k of the trailing matrix in registers; each pivot and each row of R is
@@ -647,6 +695,117 @@ __device__ __forceinline__ int jacobi_groups(double *M, int rows, int ld, int n,
         atomicAdd(&work[0], (unsigned long long)npair * (unsigned)rows);
         atomicAdd(&work[1], (unsigned long long)nrot * (unsigned)rows);
         atomicAdd(&work[2], (unsigned long long)nrot);
+    }
+    return sweep;
+}
+
+// Groups of G lanes a cyclic sweep of one-sided Jacobi needs with the
+// nested ordering below (n columns): 2^L ceil(n / 2^(L+1)) at its widest
+// level, at most n rounded up to a power of two, halved.
+__host__ __device__ __forceinline__ int jacobi_nested_groups(int n)
+{
+    int need = 1, s = n, lv = 0;
+    while (s >= 2) {
+        const int h = (s + 1) / 2;
+        need = (1 << lv) * h > need ? (1 << lv) * h : need;
+        s = h;
+        ++lv;
+    }
+    return need;
+}
+
+// One-sided Jacobi as jacobi_groups (PAD layout: ld >= G E, zeros in rows
+// [rows, G E)), with a nested ordering in which each group keeps one column
+// of its pair in registers for many steps, so that a step moves one column
+// per group through LDS instead of two.  Level 0 pairs every column of the
+// first half of [0, n) (padded to even length; the pad is a column that
+// never exists) with every column of the second half: group q keeps column
+// q and meets second-half column hs + (q + st) mod hs at step st.  Each half
+// is then split the same way (level 1, its pairs all disjoint from the
+// other half's), and so on down to halves of one column: every pair exactly
+// once per sweep, in sum_l ceil(s_l / 2) steps (s_0 = n, s_{l+1} =
+// ceil(s_l / 2); 111 steps for n = 110, against 109 rounds of the circle
+// ordering).  The moving column of a step was written back by the
+// neighbouring group in the step before; one block barrier per step.
+// Requires NT / G >= jacobi_nested_groups(n); returns the sweeps as
+// jacobi_groups does (the same rotation test and stopping rule).
+template <int NT, int G, int E>
+__device__ __forceinline__ int jacobi_nested(double *M, int rows, int ld, int n, int max_sweeps, int *sh_rot)
+{
+    const int gl = threadIdx.x % G, gid = threadIdx.x / G;
+    const double tol = (double)(rows > 1 ? rows : 1) * 2.0 * kU;
+    int sweep;
+    for (sweep = 1; sweep <= max_sweeps; ++sweep) {
+        if (threadIdx.x == 0) *sh_rot = 0;
+        __syncthreads();
+        for (int lv = 0, s = n; s >= 2; ++lv, s = (s + 1) / 2) {
+            const int h = (s + 1) / 2;
+            const int k = gid / h, q = gid % h;
+            // this group's set [a, b): node k of depth lv of the halving tree
+            int a = 0, b = n;
+            for (int d = lv - 1; d >= 0; --d) {
+                const int m = b - a, mid = a + (m + 1) / 2;
+                if ((k >> d) & 1) a = mid;
+                else b = mid;
+            }
+            const int hs = (b - a + 1) / 2;
+            const bool grp = k < (1 << lv) && q < hs && b - a >= 2;
+            const int f = a + q;
+            double xf[E], ym[E];
+            double *mf = M + (size_t)(grp ? f : 0) * ld;
+#pragma unroll
+            for (int e = 0; e < E; ++e) xf[e] = mf[gl + G * e];
+            for (int st = 0; st < h; ++st) {
+                const int c = a + hs + (q + st) % (hs > 0 ? hs : 1);
+                const bool live = grp && st < hs && c < b;
+                double *mc = M + (size_t)(live ? c : 0) * ld;
+                double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    ym[e] = mc[gl + G * e];
+                    al += xf[e] * xf[e];
+                    be += ym[e] * ym[e];
+                    ga += xf[e] * ym[e];
+                }
+                if (G == 8) {
+                    al = seg8_sum(al);
+                    be = seg8_sum(be);
+                    ga = seg8_sum(ga);
+                } else if (G == 16) {
+                    al = seg16_sum(al);
+                    be = seg16_sum(be);
+                    ga = seg16_sum(ga);
+                } else if (G == 32) {
+                    al = seg32_sum(al);
+                    be = seg32_sum(be);
+                    ga = seg32_sum(ga);
+                } else {
+                    al = wave_sum(al);
+                    be = wave_sum(be);
+                    ga = wave_sum(ga);
+                }
+                if (live && jacobi_needed(al, be, ga, tol)) {
+                    double cs, sn;
+                    jacobi_rotation(al, be, ga, cs, sn);
+#pragma unroll
+                    for (int e = 0; e < E; ++e) {
+                        const double x = xf[e], y = ym[e];
+                        xf[e] = cs * x - sn * y;
+                        mc[gl + G * e] = sn * x + cs * y;
+                    }
+                    if (gl == 0 && jacobi_needed(al, be, ga, kJacobiQuadStop)) *sh_rot = 1;
+                }
+                __syncthreads();
+            }
+            if (grp) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) mf[gl + G * e] = xf[e];
+            }
+            __syncthreads();
+        }
+        const int rot = *sh_rot;
+        __syncthreads();
+        if (!rot) break;
     }
     return sweep;
 }

@@ -260,18 +260,35 @@ template hipError_t launch_recon<float>(int, const ReconArgs<float> &, int *, hi
 // ===========================================================================
 // Elementwise helpers.
 // ===========================================================================
+// Per-workgroup sum of squares and largest magnitude of A (m x n, ld lda),
+// and, when flag is set, *flag |= 1 for a NaN or infinite entry (the same
+// pass).  A dense A (lda == m) is read as one flat array.
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_norms(int64_t m, int64_t n, const T *A, int64_t lda, double *parts)
+__global__ void __launch_bounds__(kThreads) k_norms(int64_t m, int64_t n, const T *A, int64_t lda, double *parts,
+                                                    int *flag)
 {
     __shared__ double s1[kThreads / kWave], s2[kThreads / kWave];
     double ss = 0.0, mx = 0.0;
+    int bad = 0;
     const int64_t total = m * n;
-    for (int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * kThreads) {
-        const int64_t i = idx % m, j = idx / m;
-        const double v = (double)A[i + j * lda];
-        ss += v * v;
-        mx = fmax(mx, fabs(v));
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    if (lda == m) {
+        for (int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x; idx < total; idx += stride) {
+            const double v = (double)A[idx];
+            ss += v * v;
+            mx = fmax(mx, fabs(v));
+            bad |= !isfinite(v);
+        }
+    } else {
+        for (int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x; idx < total; idx += stride) {
+            const int64_t i = idx % m, j = idx / m;
+            const double v = (double)A[i + j * lda];
+            ss += v * v;
+            mx = fmax(mx, fabs(v));
+            bad |= !isfinite(v);
+        }
     }
+    if (flag && __any(bad) && threadIdx.x % kWave == 0) atomicOr(flag, 1);
     ss = wave_sum(ss);
     mx = wave_max(mx);
     if (threadIdx.x % kWave == 0) {
@@ -291,21 +308,34 @@ __global__ void __launch_bounds__(kThreads) k_norms(int64_t m, int64_t n, const 
 }
 
 template <typename T>
-hipError_t launch_norms(int64_t m, int64_t n, const T *A, int64_t lda, double *parts, int *nparts, hipStream_t s)
+hipError_t launch_norms(int64_t m, int64_t n, const T *A, int64_t lda, double *parts, int *nparts, hipStream_t s,
+                        int *flag)
 {
     const int grid = 1024;
     *nparts = grid;
-    hipLaunchKernelGGL((k_norms<T>), dim3(grid), dim3(kThreads), 0, s, m, n, A, lda, parts);
+    hipLaunchKernelGGL((k_norms<T>), dim3(grid), dim3(kThreads), 0, s, m, n, A, lda, parts, flag);
     return hipGetLastError();
 }
-template hipError_t launch_norms<double>(int64_t, int64_t, const double *, int64_t, double *, int *, hipStream_t);
-template hipError_t launch_norms<float>(int64_t, int64_t, const float *, int64_t, double *, int *, hipStream_t);
+template hipError_t launch_norms<double>(int64_t, int64_t, const double *, int64_t, double *, int *, hipStream_t,
+                                         int *);
+template hipError_t launch_norms<float>(int64_t, int64_t, const float *, int64_t, double *, int *, hipStream_t, int *);
 
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_rpca_init(int64_t m, int64_t n, const T *O, int64_t ldo, double invJ, double inv_mu, T *Y, int64_t ldy, T *A, int64_t lda)
 {
     const int64_t total = m * n;
-    for (int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * kThreads) {
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    if (ldo == m && ldy == m && lda == m) {
+        // dense: one flat index (no division per element)
+        for (int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x; idx < total; idx += stride) {
+            const T o = O[idx];
+            const T y = o * (T)invJ;
+            Y[idx] = y;
+            A[idx] = o + y * (T)inv_mu;
+        }
+        return;
+    }
+    for (int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x; idx < total; idx += stride) {
         const int64_t i = idx % m, j = idx / m;
         const T o = O[i + j * ldo];
         const T y = o * (T)invJ;
@@ -323,27 +353,6 @@ hipError_t launch_rpca_init(int64_t m, int64_t n, const T *O, int64_t ldo, doubl
 template hipError_t launch_rpca_init<double>(int64_t, int64_t, const double *, int64_t, double, double, double *, int64_t, double *, int64_t, hipStream_t);
 template hipError_t launch_rpca_init<float>(int64_t, int64_t, const float *, int64_t, double, double, float *, int64_t, float *, int64_t, hipStream_t);
 
-template <typename T>
-__global__ void __launch_bounds__(kThreads) k_finite(int64_t m, int64_t n, const T *A, int64_t lda, int *flag)
-{
-    int bad = 0;
-    const int64_t total = m * n;
-    for (int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * kThreads) {
-        const int64_t i = idx % m, j = idx / m;
-        const double v = (double)A[i + j * lda];
-        bad |= !isfinite(v);
-    }
-    if (__any(bad) && threadIdx.x % kWave == 0) atomicOr(flag, 1);
-}
-
-template <typename T>
-hipError_t launch_finite_check(int64_t m, int64_t n, const T *A, int64_t lda, int *flag, hipStream_t s)
-{
-    hipLaunchKernelGGL((k_finite<T>), dim3(1024), dim3(kThreads), 0, s, m, n, A, lda, flag);
-    return hipGetLastError();
-}
-template hipError_t launch_finite_check<double>(int64_t, int64_t, const double *, int64_t, int *, hipStream_t);
-template hipError_t launch_finite_check<float>(int64_t, int64_t, const float *, int64_t, int *, hipStream_t);
 
 // Largest eigenvalue of a symmetric positive semidefinite n x n matrix G
 // (the Gram A A^T; 8 <= n <= 1024, global memory, one workgroup) by subspace

@@ -186,18 +186,15 @@ template <typename T>
 hipError_t launch_recon(int mode, const ReconArgs<T> &a, int *nparts, hipStream_t s);
 
 // ------------------------------------------------------------ elementwise
-// Sum of squares and max |.| of an m x n matrix: parts[2*g] = sum, parts[2*g+1] = max.
+// Sum of squares and max |.| of an m x n matrix: parts[2*g] = sum, parts[2*g+1] = max;
+// with flag, *flag |= 1 in the same pass when an entry is NaN or infinite.
 template <typename T>
 hipError_t launch_norms(int64_t m, int64_t n, const T *A, int64_t lda, double *parts,
-                        int *nparts, hipStream_t s);
+                        int *nparts, hipStream_t s, int *flag = nullptr);
 // Y = O / J ;  A = O + Y / mu
 template <typename T>
 hipError_t launch_rpca_init(int64_t m, int64_t n, const T *O, int64_t ldo, double invJ,
                             double inv_mu, T *Y, int64_t ldy, T *A, int64_t lda, hipStream_t s);
-// non-finite check: flag[0] |= 1 when any entry is NaN or Inf
-template <typename T>
-hipError_t launch_finite_check(int64_t m, int64_t n, const T *A, int64_t lda, int *flag,
-                               hipStream_t s);
 
 // Largest eigenvalue of a symmetric positive semidefinite l x l matrix by the
 // power method (one workgroup); out[0] = lambda_max.

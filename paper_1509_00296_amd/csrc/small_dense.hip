@@ -30,7 +30,10 @@ namespace frk {
 // ===========================================================================
 bool small_orth_ok(int mh, int l)
 {
-    return l >= 1 && l <= 64 && (size_t)(mh | 1) * l * 16 + (size_t)l * l * 16 + 8192 <= 96 * 1024;
+    // W, its saved copy, G, R and the matrix-core Gram partials (4 x 256
+    // doubles, 4 x 768 for 16 < l <= 32)
+    return l >= 1 && l <= 64 &&
+           (size_t)(mh | 1) * l * 16 + (size_t)l * l * 16 + (l > 16 && l <= 32 ? 24576 : 8192) <= 96 * 1024;
 }
 
 // Step 4 of the orthonormalisation, from the equilibrated basis in W (LDS,
@@ -115,12 +118,12 @@ __global__ void __launch_bounds__(NT) k_small_orth(int mh, const T *Qt, int64_t 
     __shared__ double sh_ratio[2];
     bool fast = true;
     if (l <= LM && NT == 256) {
-        // ---- l <= LM (8 or 16): Grams on the matrix cores, Cholesky in one wavefront
+        // ---- l <= LM (8, 16 or 32): Grams on the matrix cores, Cholesky in one wavefront
         double *part = R + (size_t)l * l;
         // 1. CGS2: coefficients from the Qt-Y block of the Gram of [Qt, Y]
         if (rp > 0 && c > 0) {
             for (int pass = 0; pass < 2; ++pass) {
-                gram16_mfma(W, mh, mhp, l, G, part);
+                gram_mfma<LM>(W, mh, mhp, l, G, part);
                 for (int i = tid; i < mh; i += NT) {
                     double qt[LM];
 #pragma unroll
@@ -138,7 +141,7 @@ __global__ void __launch_bounds__(NT) k_small_orth(int mh, const T *Qt, int64_t 
         }
         // 2. equilibration from the Gram's diagonal; the Gram of the scaled
         //    basis is the scaled Gram
-        gram16_mfma(W, mh, mhp, l, G, part);
+        gram_mfma<LM>(W, mh, mhp, l, G, part);
         // the first new column's squared residual against Qt (its norm when
         // nothing is propagated): Prop. 4's by-product
         if (resid2 && tid == 0) *resid2 = c > 0 ? G[rp * l + rp] : -1.0;
@@ -169,7 +172,7 @@ __global__ void __launch_bounds__(NT) k_small_orth(int mh, const T *Qt, int64_t 
         if (sh_info[0] > 0 || sh_ratio[0] < 1e-8) fast = false;
         if (fast) {
             block_trsm<LM>(W, mh, mhp, l, R);
-            gram16_mfma(W, mh, mhp, l, G, part);
+            gram_mfma<LM>(W, mh, mhp, l, G, part);
             if (wave == 0) {
                 const CholInfo c2 = wave_chol16<LM>(G, l, 0.0, 0.5, R, nullptr);
                 if (lane == 0) sh_info[1] = c2.nnull;
@@ -428,7 +431,8 @@ hipError_t launch_small_orth(int mh, const T *Qt, int64_t ldqt, int rp, const T 
 {
     const int l = rp + c;
     if (!small_orth_ok(mh, l)) return hipErrorInvalidValue;
-    const size_t lds = (2 * (size_t)l * (mh | 1) + 2 * (size_t)l * l + 4 * 256) * sizeof(double);
+    const size_t lds =
+        (2 * (size_t)l * (mh | 1) + 2 * (size_t)l * l + (l > 16 && l <= 32 ? 4 * 768 : 4 * 256)) * sizeof(double);
     if (l <= 8 && mh <= 256)
         hipLaunchKernelGGL((k_small_orth8<T, 1>), dim3(1), dim3(256), lds, s, mh, Qt, ldqt, rp, Y, ldy, c, Q,
                            ldq, seed, counter, flags, resid2);
@@ -438,8 +442,11 @@ hipError_t launch_small_orth(int mh, const T *Qt, int64_t ldqt, int rp, const T 
     else if (l <= 8)
         hipLaunchKernelGGL((k_small_orth<T, 256, 8>), dim3(1), dim3(256), lds, s, mh, Qt, ldqt, rp, Y,
                            ldy, c, Q, ldq, seed, counter, flags, resid2);
-    else
+    else if (l <= 16)
         hipLaunchKernelGGL((k_small_orth<T, 256, 16>), dim3(1), dim3(256), lds, s, mh, Qt, ldqt, rp, Y,
+                           ldy, c, Q, ldq, seed, counter, flags, resid2);
+    else
+        hipLaunchKernelGGL((k_small_orth<T, 256, 32>), dim3(1), dim3(256), lds, s, mh, Qt, ldqt, rp, Y,
                            ldy, c, Q, ldq, seed, counter, flags, resid2);
     return hipGetLastError();
 }
@@ -846,7 +853,15 @@ __device__ __forceinline__ void small_svd_body(double *M, double *smem, int l, c
             // row stride ldm (zeros past column l - 1)
             if (!in_factor) chol_blk4<NT>(M, l, ptol, 0.0, coef, sig, nullptr, ldm);
             __syncthreads();
-            if (ldm == 32) sweeps = jacobi_groups<NT, 16, 2, true>(M, l, ldm, l, 60, &sh_rot);
+            // the nested ordering (one LDS column move per group and step)
+            // where the workgroup has the groups for it, else the circle
+            if (NT / 16 >= jacobi_nested_groups(l)) {
+                if (ldm == 32) sweeps = jacobi_nested<NT, 16, 2>(M, l, ldm, l, 60, &sh_rot);
+                else if (ldm == 64) sweeps = jacobi_nested<NT, 16, 4>(M, l, ldm, l, 60, &sh_rot);
+                else if (ldm == 96) sweeps = jacobi_nested<NT, 16, 6>(M, l, ldm, l, 60, &sh_rot);
+                else if (ldm == 112) sweeps = jacobi_nested<NT, 16, 7>(M, l, ldm, l, 60, &sh_rot);
+                else sweeps = jacobi_nested<NT, 16, 8>(M, l, ldm, l, 60, &sh_rot);
+            } else if (ldm == 32) sweeps = jacobi_groups<NT, 16, 2, true>(M, l, ldm, l, 60, &sh_rot);
             else if (ldm == 64) sweeps = jacobi_groups<NT, 16, 4, true>(M, l, ldm, l, 60, &sh_rot);
             else if (ldm == 96) sweeps = jacobi_groups<NT, 16, 6, true>(M, l, ldm, l, 60, &sh_rot);
             else if (ldm == 112) sweeps = jacobi_groups<NT, 16, 7, true>(M, l, ldm, l, 60, &sh_rot);
