@@ -199,7 +199,9 @@ FRSVT_API int svt(frsvt_handle handle, frsvt_precision prec, int64_t m, int64_t 
  *                alias Q_prev (it is written after Q_prev is consumed).
  *   r_out        [out, HOST, optional] r = #{sigma_i > tau}; non-NULL makes
  *                the call wait for the stream.
- * l is clamped to mhat; at l = mhat the result equals exact SVT.
+ * l is clamped to mhat; at l = mhat the result equals exact SVT.  A width
+ * min(l, mhat) above 256 returns FRSVT_ERR_UNSUPPORTED (the
+ * orthonormalisation's factor is formed for at most 256 columns).
  */
 FRSVT_API int frsvt(frsvt_handle handle, frsvt_precision prec, int64_t m, int64_t n, const void *A,
           int64_t lda, double tau, int32_t k, int32_t p, int32_t q, const void *Q_prev,
@@ -520,6 +522,11 @@ FRSVT_API void frsvt_rpca_default_opts(frsvt_rpca_opts *opts);
  * to size the next sketch and test convergence; the call returns after the
  * last iteration has finished.  Returns FRSVT_MAX_ITER when max_iter was
  * reached before tol.
+ * Sizes: min(m, n) <= 1024 with exact SVT; <= 8192 with FRSVT, whose sketch
+ * widths are capped at 256 (fewer new samples beside a wider propagated
+ * basis).  Beyond a short side of 1024, ||O||_2 for the
+ * starting point is the top Ritz value of 40 steps of 16-vector block
+ * power iteration on O O^T (relative error below (s_17 / s_1)^160).
  */
 FRSVT_API int rpca_ialm(frsvt_handle handle, frsvt_precision prec, int64_t m, int64_t n, const void *O,
               int64_t ldo, double lambda, const frsvt_rpca_opts *opts, void *L, int64_t ldl,

@@ -292,6 +292,7 @@ struct CoreBuffers {
     T *Ypart, *Y, *Q, *Bt, *QM, *Om, *Z, *gpart_t, *Qtmp;
     double *Gpart, *G, *U, *Mm, *sigma, *R, *gpart_d, *jwork;
     double *dinv;    // inverses of R's 16 x 16 diagonal blocks (large path)
+    double *cholw;   // the Cholesky's workspace beyond l = 128 (lp^2 doubles), else null
     int *nullc;
     size_t ypart_cap;   // elements of Ypart
 };
@@ -304,14 +305,18 @@ size_t carve_core(Carver &cv, const Orient &o, int l, int cnew, int num_cu, Core
     const int64_t nh = o.nh;
     const int grid = long_grid_cap(num_cu);
     const int cmax = std::max(l, 1);
-    b.Ypart = cv.take<T>((size_t)grid * mh * cmax);
-    b.ypart_cap = (size_t)grid * mh * cmax;
+    // the long passes' partials (they take at most 32 columns, and only
+    // where the short side fits them)
+    const size_t ypc = long_path_ok(mh, 1) ? (size_t)grid * mh * std::min(cmax, 32) : (size_t)mh;
+    b.Ypart = cv.take<T>(ypc);
+    b.ypart_cap = ypc;
     b.Y = cv.take<T>((size_t)mh * cmax);
     b.Q = cv.take<T>((size_t)mh * cmax);
     b.Qtmp = cv.take<T>((size_t)mh * cmax);
     b.Bt = cv.take<T>((size_t)nh * cmax);
     b.QM = cv.take<T>((size_t)mh * cmax);
-    b.Gpart = cv.take<double>((size_t)grid * cmax * cmax);
+    b.Gpart = cv.take<double>(long_path_ok(mh, 1) ? (size_t)grid * std::min(cmax, 32) * std::min(cmax, 32)
+                                                  : (size_t)cmax * cmax);
     b.G = cv.take<double>((size_t)cmax * cmax);
     b.U = cv.take<double>((size_t)cmax * cmax);
     b.Mm = cv.take<double>((size_t)cmax * cmax);
@@ -320,6 +325,7 @@ size_t carve_core(Carver &cv, const Orient &o, int l, int cnew, int num_cu, Core
     b.nullc = cv.take<int>((size_t)cmax);
     b.jwork = cv.take<double>((size_t)cmax * cmax);
     b.dinv = cv.take<double>((size_t)256 * ((cmax + 15) / 16));
+    b.cholw = cmax > 128 ? cv.take<double>((size_t)((cmax + 15) / 16) * 256 * ((cmax + 15) / 16)) : nullptr;
     const bool big = force_big || !(long_path_ok(mh, std::max(l, 1)) && small_orth_ok(mh, l));
     b.V16 = nullptr;
     if (big) {
@@ -481,7 +487,7 @@ int big_orth(frsvt_context *h, int64_t rows, int l, T *Y, int64_t ldy, CoreBuffe
     CK(hipStreamIsCapturing(h->stream, &cap));
     const bool dbl = std::is_same<T, double>::value;
     const size_t need_f = 2 * (size_t)rows * l * sizeof(double);   // float: double copy + spare
-    if (cap == hipStreamCaptureStatusNone && l <= 128 && b.jwork && b.dinv && ldy == rows &&
+    if (cap == hipStreamCaptureStatusNone && (l <= 128 || (l <= 256 && b.cholw)) && b.jwork && b.dinv && ldy == rows &&
         (dbl ? b.Qtmp != nullptr : (b.gpart_t != nullptr && (size_t)128 * rows * l * sizeof(T) >= need_f))) {
         int *nn = h->dstatus + kGateSlot + 1;   // two words: null pivots of each pass
         int *full = h->dstatus + kGateSlot + 3;  // 1: the second pass needs its own factor
@@ -491,12 +497,14 @@ int big_orth(frsvt_context *h, int64_t rows, int l, T *Y, int64_t ldy, CoreBuffe
         CKT(FRSVT_K_ORTH, launch_col_scale<double>(rows, l, Yd, rows, b.G, h->stream));
         CKT(FRSVT_K_ORTH, launch_scale_gram(l, b.G, b.jwork, h->stream));
         if (dbl) CK(hipMemcpyAsync(b.Qtmp, Yd, (size_t)rows * l * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
-        CKT(FRSVT_K_ORTH, launch_chol(l, b.jwork, 0.0, 1e-8, b.R, b.nullc, nullptr, h->stream, nullptr, nn, 0.0, b.dinv));
+        CKT(FRSVT_K_ORTH, launch_chol(l, b.jwork, 0.0, 1e-8, b.R, b.nullc, nullptr, h->stream, nullptr, nn, 0.0, b.dinv,
+                                      b.cholw));
         CKT(FRSVT_K_ORTH, launch_trsm<double>(rows, l, Yd, rows, b.R, h->stream, b.dinv));
         if ((rc = gram<double>(h, rows, l, Yd, rows, b.G, b.gpart_d))) return rc;
         CKT(FRSVT_K_ORTH, launch_near_identity(l, b.G, b.jwork, full, nn + 1, 1e-8, h->stream));
         CKT(FRSVT_K_ORTH, launch_trmm<double>(rows, l, Yd, rows, b.jwork, h->stream, full));
-        CKT(FRSVT_K_ORTH, launch_chol(l, b.G, 0.0, 0.5, b.R, b.nullc, nullptr, h->stream, full, nn + 1, 1e-6, b.dinv));
+        CKT(FRSVT_K_ORTH, launch_chol(l, b.G, 0.0, 0.5, b.R, b.nullc, nullptr, h->stream, full, nn + 1, 1e-6, b.dinv,
+                                      b.cholw));
         CKT(FRSVT_K_ORTH, launch_trsm<double>(rows, l, Yd, rows, b.R, h->stream, b.dinv, full));
         CK(hipMemcpyAsync(h->pinned, nn, 2 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
         CK(hipStreamSynchronize(h->stream));
@@ -515,7 +523,8 @@ int big_orth(frsvt_context *h, int64_t rows, int l, T *Y, int64_t ldy, CoreBuffe
     CKT(FRSVT_K_ORTH, launch_col_scale<T>(rows, l, Y, ldy, b.G, h->stream));
     const double shift = 11.0 * ((double)rows * l + (double)l * (l + 1)) * kU;
     if ((rc = gram(h, rows, l, Y, ldy, b.G, b.gpart_d))) return rc;
-    CKT(FRSVT_K_ORTH, launch_chol(l, b.G, shift, 0.0, b.R, nullptr, flags, h->stream, nullptr, nullptr, 0.0, b.dinv));
+    CKT(FRSVT_K_ORTH, launch_chol(l, b.G, shift, 0.0, b.R, nullptr, flags, h->stream, nullptr, nullptr, 0.0, b.dinv,
+                                  b.cholw));
     CKT(FRSVT_K_ORTH, launch_trsm<T>(rows, l, Y, ldy, b.R, h->stream, b.dinv));
     // The first null check records its count in *gate; when it found no
     // null column nothing was refilled, so the Gram and factor of the second
@@ -526,15 +535,16 @@ int big_orth(frsvt_context *h, int64_t rows, int l, T *Y, int64_t ldy, CoreBuffe
         const int *g = attempt ? gate : nullptr;
         if ((rc = gram(h, rows, l, Y, ldy, b.G, b.gpart_d, g))) return rc;
         CKT(FRSVT_K_ORTH, launch_chol(l, b.G, 0.0, 16.0 * l * kU, b.R, b.nullc, flags, h->stream, g,
-                                      attempt ? nullptr : gate, 0.0, b.dinv));
+                                      attempt ? nullptr : gate, 0.0, b.dinv, b.cholw));
         CKT(FRSVT_K_ORTH, launch_refill<T>(rows, l, Y, ldy, b.nullc, seed, counter, attempt, h->stream));
     }
     if ((rc = gram(h, rows, l, Y, ldy, b.G, b.gpart_d, gate))) return rc;
     CKT(FRSVT_K_ORTH, launch_chol(l, b.G, 0.0, 16.0 * l * kU, b.R, b.nullc, flags, h->stream, gate, nullptr, 0.0,
-                                  b.dinv));
+                                  b.dinv, b.cholw));
     CKT(FRSVT_K_ORTH, launch_trsm<T>(rows, l, Y, ldy, b.R, h->stream, b.dinv));
     if ((rc = gram(h, rows, l, Y, ldy, b.G, b.gpart_d))) return rc;
-    CKT(FRSVT_K_ORTH, launch_chol(l, b.G, 0.0, 0.0, b.R, nullptr, flags, h->stream, nullptr, nullptr, 0.0, b.dinv));
+    CKT(FRSVT_K_ORTH, launch_chol(l, b.G, 0.0, 0.0, b.R, nullptr, flags, h->stream, nullptr, nullptr, 0.0, b.dinv,
+                                  b.cholw));
     CKT(FRSVT_K_ORTH, launch_trsm<T>(rows, l, Y, ldy, b.R, h->stream, b.dinv));
     return FRSVT_OK;
 }
@@ -1198,16 +1208,22 @@ int spectral_norm(frsvt_context *h, const T *A, int64_t lda, const Orient &o, do
     const bool gtr = o.trans && gram_tr_ok(mh, o.nh, lda, (int)sizeof(T));
     const size_t gpn = gtr ? gram_tr_part_doubles(mh, h->num_cu) + gram_tr_part_doubles(mh, 1)
                            : (size_t)sk * mh * mh;
+    // (beyond mh = 1024: block power vectors and their small factors instead
+    // of the small SVD's buffers)
+    constexpr int kB = 16;
+    const bool large = mh > 1024;
+    const size_t svn = large ? (size_t)mh * kB * 2 + (size_t)64 * kB * kB + 4 * kB * kB + 512
+                             : (size_t)mh * mh * 3 + mh;
     Carver dry(nullptr);
     dry.take<double>((size_t)mh * mh);
     dry.take<double>(gpn);
-    dry.take<double>((size_t)mh * mh * 3 + mh);
+    dry.take<double>(svn);
     int rc = ensure_ws(h, dry.off);
     if (rc) return rc;
     Carver cv(h->ws);
     double *G = cv.take<double>((size_t)mh * mh);
     double *gp = cv.take<double>(gpn);
-    double *sv = cv.take<double>((size_t)mh * mh * 3 + mh);
+    double *sv = cv.take<double>(svn);
     if (gtr) {
         CKT(FRSVT_K_GEMM, launch_gram_tr<T>(A, lda, mh, o.nh, h->num_cu, gp,
                                             gp + gram_tr_part_doubles(mh, h->num_cu), G, h->stream));
@@ -1219,6 +1235,40 @@ int spectral_norm(frsvt_context *h, const T *A, int64_t lda, const Orient &o, do
         CKT(FRSVT_K_GEMM, (launch_gemm<float, double, double>(mh, mh, o.nh, (const float *)A, o.si, o.sk,
                                                (const float *)A, o.sk, o.si, G, 1, mh, sk, gp,
                                                h->stream)));
+    }
+    if (large) {
+        // beyond the one-workgroup eigen kernels: block power iteration on G
+        // (16 vectors, 40 products, each block re-orthonormalised by
+        // CholeskyQR), then the top Ritz value of V^T G V.  Its relative
+        // error decays as (lambda_17 / lambda_1)^80; the RPCA host uses the
+        // value only for its starting point (mu_0 and the dual scaling J).
+        constexpr int kSteps = 40;
+        double *V = sv, *W = V + (size_t)mh * kB, *pt = W + (size_t)mh * kB;
+        double *H = pt + (size_t)64 * kB * kB, *R = H + kB * kB, *Ud = R + kB * kB, *Mmd = Ud + kB * kB;
+        double *dv = Mmd + kB * kB, *sg = dv + 256;
+        CKT(FRSVT_K_OTHER, launch_omega<double>(mh, kB, 0x5eed5eedull, 0x0c0ffee0ull, V, mh, h->stream));
+        for (int t = 0; t < kSteps; ++t) {
+            if ((rc = mm<double>(h, mh, kB, mh, G, 1, mh, V, 1, mh, W, 1, mh, 1, nullptr))) return rc;
+            if ((rc = gram<double>(h, mh, kB, W, mh, H, pt))) return rc;
+            CKT(FRSVT_K_ORTH, launch_col_scale<double>(mh, kB, W, mh, H, h->stream));
+            if ((rc = gram<double>(h, mh, kB, W, mh, H, pt))) return rc;
+            CKT(FRSVT_K_ORTH, launch_chol(kB, H, 0.0, 1e-14, R, nullptr, nullptr, h->stream, nullptr, nullptr, 0.0, dv));
+            CKT(FRSVT_K_ORTH, launch_trsm<double>(mh, kB, W, mh, R, h->stream, dv));
+            std::swap(V, W);
+        }
+        // H = V^T (G V)
+        if ((rc = mm<double>(h, mh, kB, mh, G, 1, mh, V, 1, mh, W, 1, mh, 1, nullptr))) return rc;
+        if ((rc = mm<double>(h, kB, kB, mh, V, mh, 1, W, 1, mh, H, 1, kB, 1, nullptr))) return rc;
+        SmallSvdOut so{sg, Ud, Mmd, h->dstatus};
+        CKT(FRSVT_K_SMALL_SVD, launch_small_svd<double>(kB, H, 0.0, nullptr, 0, (const double *)nullptr, 0, kB,
+                                                        (double *)nullptr, 0, (double *)nullptr, 0, so, nullptr, 0,
+                                                        h->stream));
+        CK(hipMemcpyAsync(h->pinned, sg, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        CK(hipStreamSynchronize(h->stream));
+        // the small SVD takes H as a Gram: its singular values are sqrt(eig H)
+        const double s1 = ((double *)h->pinned)[0];
+        *out = s1 > 0.0 ? s1 : 0.0;
+        return FRSVT_OK;
     }
     double lam = 0.0;
     bool ok = false;
@@ -1318,7 +1368,8 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
     const int l0 = op.l0 > 0 ? std::min(op.l0, bmax) : std::max(1, std::min(bmax, (int)std::ceil(0.1 * bmax)));
 
     // workspace: A, the FRSVT core at its largest width, exact factors, z partials
-    const int lmax = op.use_frsvt ? std::min(mh, std::max(l0, mh)) : mh;
+    // (the large path's orthonormalisation takes at most 256 columns)
+    const int lmax = op.use_frsvt ? std::min(mh, 256) : mh;
     // residual partials: one per epilogue workgroup (256 x 16 elements)
     const size_t zcap = (size_t)((m + 255) / 256) * (size_t)((n + 15) / 16);
     // Omega's rows for the sketch fused into the epilogue (FP64, Ahat = A^T,
@@ -1417,6 +1468,10 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
                 c.rp = 0;
                 c.cnew = r_prev < 0 ? l0 : (op.ap ? ap_width(0, l_prev) : std::min(op.p, mh));
             }
+            // widths stay within the 256 columns the large path's
+            // orthonormalisation takes: fewer new samples beside a wide
+            // propagated basis (r_prev <= the previous width <= 256)
+            if (c.rp + c.cnew > lmax) c.cnew = std::max(0, lmax - c.rp);
             // Sec. 3.2: the planned samples in order, sampling stopped at
             // the first whose residual estimate is at most 1/mu
             bool checked = false;
@@ -1479,8 +1534,8 @@ int rpca_impl(frsvt_context *h, int64_t m, int64_t n, const T *O, int64_t ldo, d
             if (!recon_ok(c.l)) {
                 // wide basis: materialise L = (QM) B, then the epilogue reads it
                 const int64_t scm = o.trans ? m : 1, scn = o.trans ? 1 : m;
-                CKT(FRSVT_K_GEMM, (launch_gemm<T, T, T>(o.mh, o.nh, c.l, c.QM, 1, o.mh, c.Bt, o.nh, 1, Lx, scm,
-                                         scn, 1, (T *)nullptr, s)));
+                if ((rc = mm<T>(h, o.mh, o.nh, c.l, c.QM, 1, o.mh, c.Bt, o.nh, 1, Lx, scm, scn, 1, (T *)nullptr)))
+                    return rc;
                 ra.c = 0;
                 ra.Lin = Lx;
                 ra.ldlin = m;
@@ -2642,7 +2697,8 @@ static int frsvt_entry(frsvt_handle h, frsvt_precision prec, int64_t m, int64_t 
     if (bad_ptr(X)) return -16;
     if (ldx < m) return -17;
     if (Q_out && ldq_out < mh) return -19;
-    if (std::min<int64_t>(mh, (int64_t)(Q_prev && r_prev > 0 ? r_prev + p : k + p)) > 128 && mh > 1024)
+    // the large path's orthonormalisation takes at most 256 columns
+    if (std::min<int64_t>(mh, (int64_t)(Q_prev && r_prev > 0 ? r_prev + p : k + p)) > 256)
         return FRSVT_ERR_UNSUPPORTED;
     if (prec == FRSVT_MIXED_BF16)
         return frsvt_impl<float>(h, m, n, (const float *)A, lda, tau, k, p, q, (const float *)Q_prev,
@@ -2707,7 +2763,9 @@ int rpca_ialm(frsvt_handle h, frsvt_precision prec, int64_t m, int64_t n, const 
     if (ldl < m) return -10;
     if (bad_ptr(S)) return -11;
     if (lds < m) return -12;
-    if (std::min(m, n) > 1024) return FRSVT_ERR_UNSUPPORTED;
+    // exact SVT: the one-workgroup small SVD of the short side (<= 1024);
+    // FRSVT: up to 8192 (the propagated basis is kept as a short-side square)
+    if (std::min(m, n) > (op.use_frsvt ? 8192 : 1024)) return FRSVT_ERR_UNSUPPORTED;
     if (prec == FRSVT_MIXED_BF16) return FRSVT_ERR_UNSUPPORTED;
     if (prec == FRSVT_F64)
         return rpca_impl<double>(h, m, n, (const double *)O, ldo, lambda, op, (double *)L, ldl,

@@ -216,9 +216,11 @@ hipError_t launch_gram_tall(int64_t rows, int l, const T *Y, int64_t ldy, double
 template hipError_t launch_gram_tall<double>(int64_t, int, const double *, int64_t, double *, double *, hipStream_t, const int *);
 template hipError_t launch_gram_tall<float>(int64_t, int, const float *, int64_t, double *, double *, hipStream_t, const int *);
 
-// Cholesky of (G + shift I), shift = shift_factor trace(G), l <= 128, by one
-// workgroup of four wavefronts on the matrix in LDS (row-major, rows and
-// columns padded to a multiple of 16 with zeros; upper triangle used),
+// Cholesky of (G + shift I), shift = shift_factor trace(G), l <= 256, by one
+// workgroup of four wavefronts on the matrix in LDS (l <= 128; beyond, by
+// sixteen wavefronts on a global workspace gwork of lp x lp doubles, which
+// stays in the caches) (row-major, rows and columns padded to a multiple of
+// 16 with zeros; upper triangle used),
 // blocked in panels of 16 rows (right-looking):
 //   1. wavefront 0 factors the 16 x 16 diagonal block in registers (lane k
 //      holds column k; pivots and rows broadcast with readlane; one lean
@@ -233,12 +235,16 @@ template hipError_t launch_gram_tall<float>(int64_t, int, const float *, int64_t
 // (the second CholeskyQR pass's check that the Gram is near the identity):
 // R_jj = 1 and a zero row (null_cols[j] = 1).  R is written whole (upper,
 // row-major [j * l + k], zeros below the diagonal).
-constexpr int kCholThreads = 256;
-__global__ void __launch_bounds__(kCholThreads) k_chol(int l, const double *G, double shift_factor, double null_tol, double *R, int *null_cols, int *flags, const int *gate, int *nn_out, double near_one, double *dinv)
+// GM: the matrix in a global workspace (l > 128, where it does not fit in
+// LDS) instead of LDS, NT threads (1024 there: more wavefronts for the
+// trailing tiles, whose operands then come from the caches).
+template <bool GM, int NT>
+__global__ void __launch_bounds__(NT) k_chol(int l, const double *G, double shift_factor, double null_tol, double *R, int *null_cols, int *flags, const int *gate, int *nn_out, double near_one, double *dinv, double *gwork)
 {
+    constexpr int kCholThreads = NT;
     if (gate && *gate == 0) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    double *M = reinterpret_cast<double *>(smem_raw);   // lp x lp, row-major
+    double *M = GM ? gwork : reinterpret_cast<double *>(smem_raw);   // lp x lp, row-major
     __shared__ double sRd[16 * 16];
     __shared__ double srinv[16];
     __shared__ double sdiag[2];
@@ -369,12 +375,18 @@ __global__ void __launch_bounds__(kCholThreads) k_chol(int l, const double *G, d
     }
 }
 
-hipError_t launch_chol(int l, const double *G, double shift_factor, double null_tol, double *R, int *null_cols, int *flags, hipStream_t s, const int *gate, int *nn_out, double near_one, double *dinv)
+hipError_t launch_chol(int l, const double *G, double shift_factor, double null_tol, double *R, int *null_cols, int *flags, hipStream_t s, const int *gate, int *nn_out, double near_one, double *dinv, double *gwork)
 {
-    if (l < 1 || l > 128) return hipErrorInvalidValue;
+    if (l < 1 || l > 256 || (l > 128 && !gwork)) return hipErrorInvalidValue;
     const int lp = (l + 15) & ~15;
-    const size_t lds = (size_t)lp * lp * sizeof(double);
-    hipLaunchKernelGGL(k_chol, dim3(1), dim3(kCholThreads), lds, s, l, G, shift_factor, null_tol, R, null_cols, flags, gate, nn_out, near_one, dinv);
+    if (l > 128) {
+        hipLaunchKernelGGL((k_chol<true, 1024>), dim3(1), dim3(1024), 0, s, l, G, shift_factor, null_tol, R, null_cols,
+                           flags, gate, nn_out, near_one, dinv, gwork);
+    } else {
+        const size_t lds = (size_t)lp * lp * sizeof(double);
+        hipLaunchKernelGGL((k_chol<false, 256>), dim3(1), dim3(256), lds, s, l, G, shift_factor, null_tol, R, null_cols,
+                           flags, gate, nn_out, near_one, dinv, gwork);
+    }
     return hipGetLastError();
 }
 
@@ -492,13 +504,14 @@ __device__ __forceinline__ void wave_lds_sync()
 // (A operand: the solved blocks X_K from LDS; B operand: R from memory,
 // shared by every wavefront through the caches), the block Y_J - sum moved
 // to operand layout through LDS and multiplied by Dinv_J.
-template <typename T>
+// LDX: the row stride of the solved block in LDS, odd (the operand reads of
+// 16 rows hit distinct banks) and above l: 129 for l <= 128, 257 for l <= 256.
+template <typename T, int LDX>
 __global__ void __launch_bounds__(kWave) k_trsm_mfma(int64_t rows, int l, T *Y, int64_t ldy,
                                                      const double *__restrict__ R, const double *__restrict__ Dinv,
                                                      const int *gate)
 {
     if (gate && *gate == 0) return;   // the solve is not wanted this time
-    constexpr int LDX = 129;   // odd stride: the operand reads of 16 rows hit distinct banks
     __shared__ double sX[16 * LDX];
     __shared__ double sT[16 * 17];
     const int lane = threadIdx.x;
@@ -550,10 +563,13 @@ template <typename T>
 hipError_t launch_trsm(int64_t rows, int l, T *Y, int64_t ldy, const double *R, hipStream_t s, const double *dinv,
                        const int *gate)
 {
-    if (l > 128 || (gate && !dinv)) return hipErrorInvalidValue;
-    if (dinv)
-        hipLaunchKernelGGL((k_trsm_mfma<T>), dim3((unsigned)((rows + 15) / 16)), dim3(kWave), 0, s, rows, l, Y, ldy, R,
-                           dinv, gate);
+    if (l > 256 || (l > 128 && !dinv) || (gate && !dinv)) return hipErrorInvalidValue;
+    if (dinv && l > 128)
+        hipLaunchKernelGGL((k_trsm_mfma<T, 257>), dim3((unsigned)((rows + 15) / 16)), dim3(kWave), 0, s, rows, l, Y, ldy,
+                           R, dinv, gate);
+    else if (dinv)
+        hipLaunchKernelGGL((k_trsm_mfma<T, 129>), dim3((unsigned)((rows + 15) / 16)), dim3(kWave), 0, s, rows, l, Y, ldy,
+                           R, dinv, gate);
     else
         hipLaunchKernelGGL((k_trsm<T>), dim3((unsigned)((rows + kWave - 1) / kWave)), dim3(kTrsmThreads), 0, s, rows, l,
                            Y, ldy, R);
@@ -567,12 +583,11 @@ template hipError_t launch_trsm<float>(int64_t, int, float *, int64_t, const dou
 // Y <- Y U for an upper triangular U (row-major, l <= 128) on the matrix
 // cores: one wavefront per 16 rows, the rows of Y staged in LDS first, then
 // every column block Y_J' = sum_{K <= J} Y_K U_KJ.
-template <typename T>
+template <typename T, int LDX>
 __global__ void __launch_bounds__(kWave) k_trmm_mfma(int64_t rows, int l, T *Y, int64_t ldy, const double *__restrict__ U,
                                                      const int *skip)
 {
     if (skip && *skip != 0) return;   // the product is not wanted this time
-    constexpr int LDX = 129;
     __shared__ double sX[16 * LDX];
     const int lane = threadIdx.x;
     const int nb = (l + 15) >> 4;
@@ -614,9 +629,13 @@ __global__ void __launch_bounds__(kWave) k_trmm_mfma(int64_t rows, int l, T *Y, 
 template <typename T>
 hipError_t launch_trmm(int64_t rows, int l, T *Y, int64_t ldy, const double *U, hipStream_t s, const int *skip)
 {
-    if (l < 1 || l > 128) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_trmm_mfma<T>), dim3((unsigned)((rows + 15) / 16)), dim3(kWave), 0, s, rows, l, Y, ldy, U,
-                       skip);
+    if (l < 1 || l > 256) return hipErrorInvalidValue;
+    if (l > 128)
+        hipLaunchKernelGGL((k_trmm_mfma<T, 257>), dim3((unsigned)((rows + 15) / 16)), dim3(kWave), 0, s, rows, l, Y, ldy,
+                           U, skip);
+    else
+        hipLaunchKernelGGL((k_trmm_mfma<T, 129>), dim3((unsigned)((rows + 15) / 16)), dim3(kWave), 0, s, rows, l, Y, ldy,
+                           U, skip);
     return hipGetLastError();
 }
 template hipError_t launch_trmm<double>(int64_t, int, double *, int64_t, const double *, hipStream_t, const int *);

@@ -241,21 +241,24 @@ hipError_t launch_gram_tall(int64_t rows, int l, const T *Y, int64_t ldy, double
 // gate: as for launch_gram_tall (R is still current); nn_out receives the
 // number of null pivots; near_one > 0 also treats a pivot further than
 // near_one from 1 as null; dinv (optional, 256 ceil(l / 16) doubles)
-// receives the inverses of R's 16 x 16 diagonal blocks (identity past l).
+// receives the inverses of R's 16 x 16 diagonal blocks (identity past l);
+// l <= 128, or l <= 256 with gwork (a workspace of lp^2 doubles, lp = l
+// rounded up to 16).
 hipError_t launch_chol(int l, const double *G, double shift_factor, double null_tol, double *R,
                        int *null_cols, int *flags, hipStream_t s, const int *gate = nullptr,
-                       int *nn_out = nullptr, double near_one = 0.0, double *dinv = nullptr);
+                       int *nn_out = nullptr, double near_one = 0.0, double *dinv = nullptr,
+                       double *gwork = nullptr);
 // G_out(a, b) = G(a, b) / sqrt(G(a, a) G(b, b)): the Gram after k_col_scale.
 hipError_t launch_scale_gram(int l, const double *G, double *Gout, hipStream_t s);
 // Y (rows x l) <- Y R^{-1} in place (R upper, double): with dinv (the
 // inverses of R's 16 x 16 diagonal blocks, 256 doubles each, as launch_chol
-// writes them) on the matrix cores, one wavefront per 16 rows; else one lane
-// per row.
+// writes them) on the matrix cores, one wavefront per 16 rows (l <= 256);
+// else one lane per row (l <= 128).
 template <typename T>
 hipError_t launch_trsm(int64_t rows, int l, T *Y, int64_t ldy, const double *R, hipStream_t s,
                        const double *dinv = nullptr, const int *gate = nullptr);
 // Y (rows x l) <- Y U in place, U upper triangular (row-major, double),
-// l <= 128; nothing when skip is set and *skip != 0.
+// l <= 256; nothing when skip is set and *skip != 0.
 template <typename T>
 hipError_t launch_trmm(int64_t rows, int l, T *Y, int64_t ldy, const double *U, hipStream_t s,
                        const int *skip = nullptr);

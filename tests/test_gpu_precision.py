@@ -178,3 +178,28 @@ def test_precision_workload_full_size(fr, orc, c3_data):
     the oracle's (every sampled direction lies above tau = 5)."""
     _say("case precision workload 8192x8192: GPU runs and the oracle (about two minutes)")
     _mixed_against_oracle(fr, orc, c3_data, 5.0, 100, 10, 2, 1000, fp64_check=True)
+
+
+@pytest.mark.parametrize("m,n,k,p,q", [(1500, 900, 190, 10, 1), (900, 1400, 150, 6, 0)])
+def test_frsvt_f64_wide_sketch(fr, orc, m, n, k, p, q):
+    """Sketch widths between 128 and 256 columns: the Cholesky on its global
+    workspace (sixteen wavefronts), the triangular solve and product with the
+    wider LDS stride, against the oracle at <= 1e-10."""
+    from paper_1509_00296_amd import synth
+    _say(f"case frsvt f64 wide sketch {m}x{n} l={k + p} q={q}")
+    A = synth.single_svt(seed=m + 3 * n, m=m, n=n, rank=k - 20, noise_std=0.05, smax=200.0, smin=5.0)
+    X, Qt, r = fr.frsvt(torch.from_numpy(A).cuda(), 2.0, k, p, q, seed=11, counter=3)
+    Om = orc.gaussian_matrix(11, 3, max(m, n), k + p)
+    Xo, Qo, ro, _, _ = orc.frsvt(A, 2.0, q, Om)
+    assert r == ro
+    assert _rel(X.cpu().numpy(), Xo) <= 1e-10
+    Qg = Qt.cpu().numpy()
+    assert np.abs(Qg.T @ Qg - np.eye(r)).max() < 1e-12
+
+
+def test_frsvt_width_above_256_rejected(fr):
+    """A sketch wider than 256 columns (below the short side) is refused
+    before any launch."""
+    A = torch.zeros((1200, 600), dtype=torch.float64, device="cuda")
+    with pytest.raises(fr.FRSVTError):
+        fr.frsvt(A, 1.0, 290, 10, 1, seed=1)
