@@ -1319,7 +1319,7 @@ int wait_iter_words(frsvt_context *h, hipStream_t s, volatile int *word, int seq
             std::atomic_thread_fence(std::memory_order_acquire);
             return FRSVT_OK;
         }
-        if ((spin & 1023u) == 0) {
+        if ((spin & 65535u) == 0) {
             const hipError_t e = hipStreamQuery(s);
             if (e == hipSuccess) {
                 // the stream has drained: the word is there or never comes
