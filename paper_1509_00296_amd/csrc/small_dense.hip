@@ -269,14 +269,17 @@ __global__ void __launch_bounds__(NT) k_small_orth(int mh, const T *Qt, int64_t 
 // from an LDS copy of W (gram16_mfma); every thread then reads the l x l Gram
 // and factors it itself (reg_chol: the same arithmetic in every thread, so
 // no broadcast step and no barrier for the factor), and solves its own rows
-// with the reciprocal pivots.  The fallback (step 4) runs from LDS.
-template <typename T, int RPT>
+// with the reciprocal pivots.  The fallback (step 4) runs from LDS.  LC > 0
+// fixes the width l = rp + c at compile time: the kernel runs once per launch
+// from a cold instruction cache, and a fixed width removes the guards and
+// address arithmetic of the unrolled loops from the straight-line code.
+template <typename T, int RPT, int LC = 0>
 __global__ void __launch_bounds__(256) k_small_orth8(int mh, const T *Qt, int64_t ldqt, int rp, const T *Y,
                                                      int64_t ldy, int c, T *Q, int64_t ldq, uint64_t seed,
                                                      uint64_t counter, int *flags, double *resid2)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int l = rp + c;
+    const int l = LC > 0 ? LC : rp + c;
     const int mhp = mh | 1;
     double *W = reinterpret_cast<double *>(smem_raw);
     double *W0 = W + (size_t)l * mhp;
@@ -433,10 +436,19 @@ hipError_t launch_small_orth(int mh, const T *Qt, int64_t ldqt, int rp, const T 
     if (!small_orth_ok(mh, l)) return hipErrorInvalidValue;
     const size_t lds =
         (2 * (size_t)l * (mh | 1) + 2 * (size_t)l * l + (l > 16 && l <= 32 ? 4 * 768 : 4 * 256)) * sizeof(double);
-    if (l <= 8 && mh <= 256)
-        hipLaunchKernelGGL((k_small_orth8<T, 1>), dim3(1), dim3(256), lds, s, mh, Qt, ldqt, rp, Y, ldy, c, Q,
-                           ldq, seed, counter, flags, resid2);
-    else if (l <= 8 && mh <= 512)
+    if (l <= 8 && mh <= 256) {
+        switch (l) {
+#define FRK_ORTH8_CASE(L)                                                                                    \
+    case L:                                                                                                  \
+        hipLaunchKernelGGL((k_small_orth8<T, 1, L>), dim3(1), dim3(256), lds, s, mh, Qt, ldqt, rp, Y, ldy, c, \
+                           Q, ldq, seed, counter, flags, resid2);                                            \
+        break;
+            FRK_ORTH8_CASE(1) FRK_ORTH8_CASE(2) FRK_ORTH8_CASE(3) FRK_ORTH8_CASE(4)
+            FRK_ORTH8_CASE(5) FRK_ORTH8_CASE(6) FRK_ORTH8_CASE(7) FRK_ORTH8_CASE(8)
+#undef FRK_ORTH8_CASE
+        default: return hipErrorInvalidValue;
+        }
+    } else if (l <= 8 && mh <= 512)
         hipLaunchKernelGGL((k_small_orth8<T, 2>), dim3(1), dim3(256), lds, s, mh, Qt, ldqt, rp, Y, ldy, c, Q,
                            ldq, seed, counter, flags, resid2);
     else if (l <= 8)
@@ -1058,12 +1070,14 @@ __global__ void __launch_bounds__(NT) k_small_svd(int l, const double *Gin, doub
 // same values in the same order, so both lanes compute the same rotation.
 // No LDS access or barrier inside the sweeps.  The other wavefronts load
 // their rows of Q meanwhile and join for the products with Q.
-template <typename T>
-__global__ void __launch_bounds__(256) k_small_svd8(int l, const double *Gin, double tau, int keep,
+// LC > 0 fixes l at compile time (as for k_small_orth8).
+template <typename T, int LC>
+__global__ void __launch_bounds__(256) k_small_svd8(int l_in, const double *Gin, double tau, int keep,
                                                     const double *w, const T *Q, int64_t ldq, int mh, T *QM,
                                                     int64_t ldqm, T *Qout, int64_t ldqo, SmallSvdOut out,
                                                     int fuse_q, int in_factor)
 {
+    const int l = LC > 0 ? LC : l_in;
     __shared__ double sM[64], sU[64], sMm[64], swc[8];
     __shared__ int sh_rank;
     const int tid = threadIdx.x;
@@ -1164,12 +1178,18 @@ hipError_t launch_small_svd(int l, const double *G, double tau, const double *w,
     const int ldm = (l > lm && l <= 128) ? svd_row_capacity(l) : l;
     size_t lds = l <= 128 ? (size_t)l * std::max(l, ldm) * sizeof(double) : 0;
     if (fuse_q && Q) lds = std::max(lds, 2 * (size_t)l * l * sizeof(double));
-    if (l <= 8)
-        hipLaunchKernelGGL((k_small_svd8<T>), dim3(1), dim3(256), 0, s, l, G, tau, keep, w, Q, ldq, mh, QM, ldqm,
-                           Qout, ldqo, out, fuse_q, in_factor);
-    else if (l <= 8)
-        hipLaunchKernelGGL((k_small_svd<T, 256, 8>), dim3(1), dim3(256), lds, s, l, G, tau, keep, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, work, fuse_q, in_factor);
-    else if (l <= 32)
+    if (l <= 8) {
+        switch (l) {
+#define FRK_SVD8_CASE(L)                                                                                      \
+    case L:                                                                                                   \
+        hipLaunchKernelGGL((k_small_svd8<T, L>), dim3(1), dim3(256), 0, s, l, G, tau, keep, w, Q, ldq, mh, QM, \
+                           ldqm, Qout, ldqo, out, fuse_q, in_factor);                                         \
+        break;
+            FRK_SVD8_CASE(1) FRK_SVD8_CASE(2) FRK_SVD8_CASE(3) FRK_SVD8_CASE(4)
+            FRK_SVD8_CASE(5) FRK_SVD8_CASE(6) FRK_SVD8_CASE(7) FRK_SVD8_CASE(8)
+#undef FRK_SVD8_CASE
+        }
+    } else if (l <= 32)
         hipLaunchKernelGGL((k_small_svd<T, 256, 16>), dim3(1), dim3(256), lds, s, l, G, tau, keep, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, work, fuse_q, in_factor);
     else
         hipLaunchKernelGGL((k_small_svd<T, 1024, 16>), dim3(1), dim3(1024), lds, s, l, G, tau, keep, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, work, fuse_q, in_factor);
