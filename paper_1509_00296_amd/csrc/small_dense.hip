@@ -85,14 +85,15 @@ __device__ __forceinline__ void orth_fallback(double *W, double *G, double *R, i
     block_trsm(W, mh, mhp, l, R);
 }
 
-template <typename T, int NT, int LM>
+// LC > 0 fixes the width l = rp + c at compile time (see k_small_orth8).
+template <typename T, int NT, int LM, int LC = 0>
 __global__ void __launch_bounds__(NT) k_small_orth(int mh, const T *Qt, int64_t ldqt, int rp,
                                                    const T *Y, int64_t ldy, int c, T *Q,
                                                    int64_t ldq, uint64_t seed, uint64_t counter,
                                                    int *flags, double *resid2)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int l = rp + c;
+    const int l = LC > 0 ? LC : rp + c;
     const int mhp = mh | 1;
     double *W = reinterpret_cast<double *>(smem_raw);
     double *W0 = W + (size_t)l * mhp;
@@ -454,9 +455,18 @@ hipError_t launch_small_orth(int mh, const T *Qt, int64_t ldqt, int rp, const T 
     else if (l <= 8)
         hipLaunchKernelGGL((k_small_orth<T, 256, 8>), dim3(1), dim3(256), lds, s, mh, Qt, ldqt, rp, Y,
                            ldy, c, Q, ldq, seed, counter, flags, resid2);
-    else if (l <= 16)
-        hipLaunchKernelGGL((k_small_orth<T, 256, 16>), dim3(1), dim3(256), lds, s, mh, Qt, ldqt, rp, Y,
-                           ldy, c, Q, ldq, seed, counter, flags, resid2);
+    else if (l <= 16) {
+        switch (l) {
+#define FRK_ORTH16_CASE(L)                                                                                    \
+    case L:                                                                                                   \
+        hipLaunchKernelGGL((k_small_orth<T, 256, 16, L>), dim3(1), dim3(256), lds, s, mh, Qt, ldqt, rp, Y, ldy, \
+                           c, Q, ldq, seed, counter, flags, resid2);                                          \
+        break;
+            FRK_ORTH16_CASE(9) FRK_ORTH16_CASE(10) FRK_ORTH16_CASE(11) FRK_ORTH16_CASE(12)
+            FRK_ORTH16_CASE(13) FRK_ORTH16_CASE(14) FRK_ORTH16_CASE(15) FRK_ORTH16_CASE(16)
+#undef FRK_ORTH16_CASE
+        }
+    }
     else
         hipLaunchKernelGGL((k_small_orth<T, 256, 32>), dim3(1), dim3(256), lds, s, mh, Qt, ldqt, rp, Y,
                            ldy, c, Q, ldq, seed, counter, flags, resid2);
@@ -1040,12 +1050,14 @@ __device__ __forceinline__ void small_svd_body(double *M, double *smem, int l, c
     }
 }
 
-template <typename T, int NT, int LM>
-__global__ void __launch_bounds__(NT) k_small_svd(int l, const double *Gin, double tau, int keep,
+// LC > 0 fixes l at compile time (see k_small_orth8).
+template <typename T, int NT, int LM, int LC = 0>
+__global__ void __launch_bounds__(NT) k_small_svd(int l_in, const double *Gin, double tau, int keep,
                                                   const double *w, const T *Q, int64_t ldq, int mh,
                                                   T *QM, int64_t ldqm, T *Qout, int64_t ldqo,
                                                   SmallSvdOut out, double *work, int fuse_q, int in_factor)
 {
+    const int l = LC > 0 ? LC : l_in;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int sh_rot, rank;
     __shared__ int order[1024];
@@ -1188,6 +1200,17 @@ hipError_t launch_small_svd(int l, const double *G, double tau, const double *w,
             FRK_SVD8_CASE(1) FRK_SVD8_CASE(2) FRK_SVD8_CASE(3) FRK_SVD8_CASE(4)
             FRK_SVD8_CASE(5) FRK_SVD8_CASE(6) FRK_SVD8_CASE(7) FRK_SVD8_CASE(8)
 #undef FRK_SVD8_CASE
+        }
+    } else if (l <= 16) {
+        switch (l) {
+#define FRK_SVD16_CASE(L)                                                                                     \
+    case L:                                                                                                   \
+        hipLaunchKernelGGL((k_small_svd<T, 256, 16, L>), dim3(1), dim3(256), lds, s, l, G, tau, keep, w, Q, ldq, \
+                           mh, QM, ldqm, Qout, ldqo, out, work, fuse_q, in_factor);                           \
+        break;
+            FRK_SVD16_CASE(9) FRK_SVD16_CASE(10) FRK_SVD16_CASE(11) FRK_SVD16_CASE(12)
+            FRK_SVD16_CASE(13) FRK_SVD16_CASE(14) FRK_SVD16_CASE(15) FRK_SVD16_CASE(16)
+#undef FRK_SVD16_CASE
         }
     } else if (l <= 32)
         hipLaunchKernelGGL((k_small_svd<T, 256, 16>), dim3(1), dim3(256), lds, s, l, G, tau, keep, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, work, fuse_q, in_factor);
