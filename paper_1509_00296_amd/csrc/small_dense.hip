@@ -467,9 +467,21 @@ hipError_t launch_small_orth(int mh, const T *Qt, int64_t ldqt, int rp, const T 
 #undef FRK_ORTH16_CASE
         }
     }
-    else
-        hipLaunchKernelGGL((k_small_orth<T, 256, 32>), dim3(1), dim3(256), lds, s, mh, Qt, ldqt, rp, Y,
-                           ldy, c, Q, ldq, seed, counter, flags, resid2);
+    else {
+        switch (l) {
+#define FRK_ORTH32_CASE(L)                                                                                    \
+    case L:                                                                                                   \
+        hipLaunchKernelGGL((k_small_orth<T, 256, 32, L>), dim3(1), dim3(256), lds, s, mh, Qt, ldqt, rp, Y, ldy, \
+                           c, Q, ldq, seed, counter, flags, resid2);                                          \
+        break;
+            FRK_ORTH32_CASE(17) FRK_ORTH32_CASE(18) FRK_ORTH32_CASE(19) FRK_ORTH32_CASE(20)
+            FRK_ORTH32_CASE(21) FRK_ORTH32_CASE(22) FRK_ORTH32_CASE(23) FRK_ORTH32_CASE(24)
+            FRK_ORTH32_CASE(25) FRK_ORTH32_CASE(26) FRK_ORTH32_CASE(27) FRK_ORTH32_CASE(28)
+            FRK_ORTH32_CASE(29) FRK_ORTH32_CASE(30) FRK_ORTH32_CASE(31) FRK_ORTH32_CASE(32)
+#undef FRK_ORTH32_CASE
+        default: return hipErrorInvalidValue;
+        }
+    }
     return hipGetLastError();
 }
 template hipError_t launch_small_orth<double>(int, const double *, int64_t, int, const double *, int64_t, int, double *, int64_t, uint64_t, uint64_t, int *, double *, hipStream_t);
@@ -1201,7 +1213,7 @@ hipError_t launch_small_svd(int l, const double *G, double tau, const double *w,
             FRK_SVD8_CASE(5) FRK_SVD8_CASE(6) FRK_SVD8_CASE(7) FRK_SVD8_CASE(8)
 #undef FRK_SVD8_CASE
         }
-    } else if (l <= 16) {
+    } else if (l <= 32) {
         switch (l) {
 #define FRK_SVD16_CASE(L)                                                                                     \
     case L:                                                                                                   \
@@ -1210,10 +1222,13 @@ hipError_t launch_small_svd(int l, const double *G, double tau, const double *w,
         break;
             FRK_SVD16_CASE(9) FRK_SVD16_CASE(10) FRK_SVD16_CASE(11) FRK_SVD16_CASE(12)
             FRK_SVD16_CASE(13) FRK_SVD16_CASE(14) FRK_SVD16_CASE(15) FRK_SVD16_CASE(16)
+            FRK_SVD16_CASE(17) FRK_SVD16_CASE(18) FRK_SVD16_CASE(19) FRK_SVD16_CASE(20)
+            FRK_SVD16_CASE(21) FRK_SVD16_CASE(22) FRK_SVD16_CASE(23) FRK_SVD16_CASE(24)
+            FRK_SVD16_CASE(25) FRK_SVD16_CASE(26) FRK_SVD16_CASE(27) FRK_SVD16_CASE(28)
+            FRK_SVD16_CASE(29) FRK_SVD16_CASE(30) FRK_SVD16_CASE(31) FRK_SVD16_CASE(32)
 #undef FRK_SVD16_CASE
         }
-    } else if (l <= 32)
-        hipLaunchKernelGGL((k_small_svd<T, 256, 16>), dim3(1), dim3(256), lds, s, l, G, tau, keep, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, work, fuse_q, in_factor);
+    }
     else
         hipLaunchKernelGGL((k_small_svd<T, 1024, 16>), dim3(1), dim3(1024), lds, s, l, G, tau, keep, w, Q, ldq, mh, QM, ldqm, Qout, ldqo, out, work, fuse_q, in_factor);
     return hipGetLastError();
